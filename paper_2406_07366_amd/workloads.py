@@ -1,0 +1,196 @@
+"""Seeded synthetic filament sets (inputs only; no Biot-Savart arithmetic here).
+
+This module is shared by the oracle, the tests and the benchmark.  It builds
+closed vortex filaments as ordered node lists with unwrapped coordinates and
+per-filament circulation (paper Sec. 2.1, "Filaments as oriented curves";
+Sec. 2.2, eq:BS allows a circulation per curve).  Nothing here evaluates the
+method: it only samples the parametric curves at their nodes.
+
+Workloads (all in a cubic periodic box of side L = 2*pi, core a = 1e-6):
+
+  ring     one circular ring, R = pi/3, centred in the box, axis z, 64 nodes
+           equispaced in angle, Gamma = 1.                     (grid 32^3, tol 1e-6)
+  ellipses 40 ellipses: centres U[0,L)^3, semi-axes U[pi/8, pi/3] each, Haar
+           orientation, Gamma = +-1 with p = 1/2, 64 nodes each.
+           Same generator as the paper's random-ellipse case (Sec. 5.1, test
+           case 3) with its radii range and node count changed. (grid 64^3, tol 1e-6)
+  tangle   1000 random Fourier curves x(t) = c + sum_{m=1..4} A_m cos(mt) +
+           B_m sin(mt), A_m, B_m ~ N(0, (0.3/m)^2) per component, c U[0,L)^3,
+           100 nodes each, Gamma = 1.                         (grid 256^3, tol 1e-5)
+  ringpairs 5000 coaxial antiparallel ring pairs (R U[0.05, 0.2], axial gap d
+           log-uniform in [1e-3, 1e-1], Haar orientation, 16 nodes per ring,
+           Gamma = +1 / -1) plus 400 tangle-style curves of 100 nodes.
+                                                              (grid 256^3, tol 1e-5)
+  bigtangle tangle generator with 10000 curves (N = 1e6).      (grid 512^3, tol 1e-5)
+
+Nodes are equispaced in each curve's own parameter (angle or t).  Draw order
+within one seed: centres, shape parameters, orientations, circulation signs.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+@dataclasses.dataclass
+class FilamentSet:
+    """Closed filaments in CSR form.
+
+    offsets: int64 [nfil+1], filament l owns nodes offsets[l]:offsets[l+1].
+    xyz:     float64 [N, 3], unwrapped node positions (consecutive nodes are
+             close; the curve closes on itself, node N_l == node 0).
+    gamma:   float64 [nfil], circulation of each filament.
+    """
+
+    name: str
+    L: float
+    a: float
+    offsets: np.ndarray
+    xyz: np.ndarray
+    gamma: np.ndarray
+    grid_n: int
+    tol: float
+    delta: float = 0.25
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def n_fil(self) -> int:
+        return int(len(self.offsets) - 1)
+
+    def subset(self, nfil: int) -> "FilamentSet":
+        """The first nfil filaments, standalone in the same box."""
+        off = self.offsets[: nfil + 1].copy()
+        return dataclasses.replace(
+            self,
+            name=f"{self.name}[:{nfil}]",
+            offsets=off,
+            xyz=self.xyz[: off[-1]].copy(),
+            gamma=self.gamma[:nfil].copy(),
+        )
+
+
+def _csr(counts):
+    off = np.zeros(len(counts) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    return off
+
+
+def haar_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniform random rotation matrices from normalised Gaussian quaternions."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    R = np.empty((n, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - w * z)
+    R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y)
+    R[:, 2, 1] = 2 * (y * z + w * x)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def ring(n_nodes: int = 64, R: float = math.pi / 3, L: float = TWO_PI,
+         centre=None, gamma: float = 1.0, a: float = 1e-6,
+         grid_n: int = 32, tol: float = 1e-6) -> FilamentSet:
+    """One circular ring in the plane z = const, positively oriented about +z."""
+    c = np.full(3, L / 2) if centre is None else np.asarray(centre, float)
+    th = TWO_PI * np.arange(n_nodes) / n_nodes
+    xyz = np.stack([c[0] + R * np.cos(th), c[1] + R * np.sin(th),
+                    np.full_like(th, c[2])], axis=1)
+    return FilamentSet("ring", L, a, _csr([n_nodes]), xyz,
+                       np.array([gamma]), grid_n, tol)
+
+
+def ellipses(nfil: int = 40, n_per: int = 64, seed: int = 1002,
+             L: float = TWO_PI, rmin: float = math.pi / 8, rmax: float = math.pi / 3,
+             a: float = 1e-6, grid_n: int = 64, tol: float = 1e-6) -> FilamentSet:
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, L, size=(nfil, 3))
+    axes = rng.uniform(rmin, rmax, size=(nfil, 2))
+    rot = haar_rotations(rng, nfil)
+    gamma = np.where(rng.uniform(size=nfil) < 0.5, -1.0, 1.0)
+    th = TWO_PI * np.arange(n_per) / n_per
+    local = np.zeros((nfil, n_per, 3))
+    local[:, :, 0] = axes[:, 0:1] * np.cos(th)[None, :]
+    local[:, :, 1] = axes[:, 1:2] * np.sin(th)[None, :]
+    xyz = centres[:, None, :] + np.einsum("fij,fnj->fni", rot, local)
+    return FilamentSet("ellipses", L, a, _csr([n_per] * nfil),
+                       xyz.reshape(-1, 3), gamma, grid_n, tol)
+
+
+def _fourier_curves(rng, nfil, n_per, L, amp=0.3, nharm=4):
+    centres = rng.uniform(0.0, L, size=(nfil, 3))
+    sd = amp / np.arange(1, nharm + 1)
+    A = rng.standard_normal((nfil, nharm, 3)) * sd[None, :, None]
+    B = rng.standard_normal((nfil, nharm, 3)) * sd[None, :, None]
+    t = TWO_PI * np.arange(n_per) / n_per
+    m = np.arange(1, nharm + 1)
+    cos_mt = np.cos(np.outer(m, t))  # [nharm, n_per]
+    sin_mt = np.sin(np.outer(m, t))
+    xyz = (centres[:, None, :]
+           + np.einsum("fmc,mn->fnc", A, cos_mt)
+           + np.einsum("fmc,mn->fnc", B, sin_mt))
+    return xyz.reshape(-1, 3)
+
+
+def tangle(nfil: int = 1000, n_per: int = 100, seed: int = 1003,
+           L: float = TWO_PI, a: float = 1e-6, grid_n: int = 256,
+           tol: float = 1e-5, name: str = "tangle") -> FilamentSet:
+    rng = np.random.default_rng(seed)
+    xyz = _fourier_curves(rng, nfil, n_per, L)
+    return FilamentSet(name, L, a, _csr([n_per] * nfil), xyz,
+                       np.ones(nfil), grid_n, tol)
+
+
+def ringpairs(npairs: int = 5000, n_ring: int = 16, nbg: int = 400,
+              n_bg: int = 100, seed: int = 1004, L: float = TWO_PI,
+              a: float = 1e-6, grid_n: int = 256, tol: float = 1e-5) -> FilamentSet:
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, L, size=(npairs, 3))
+    radius = rng.uniform(0.05, 0.2, size=npairs)
+    gap = np.exp(rng.uniform(math.log(1e-3), math.log(1e-1), size=npairs))
+    rot = haar_rotations(rng, npairs)
+    th = TWO_PI * np.arange(n_ring) / n_ring
+    circ = np.stack([np.cos(th), np.sin(th), np.zeros_like(th)], axis=1)  # [n,3]
+    rings = []
+    for sgn in (-0.5, 0.5):
+        local = radius[:, None, None] * circ[None]
+        local[:, :, 2] += sgn * gap[:, None]
+        rings.append(centres[:, None, :] + np.einsum("fij,fnj->fni", rot, local))
+    # interleave: pair p -> filaments 2p (Gamma=+1, z=-d/2) and 2p+1 (Gamma=-1)
+    pair_xyz = np.stack(rings, axis=1).reshape(2 * npairs * n_ring, 3)
+    pair_gamma = np.tile([1.0, -1.0], npairs)
+    bg = _fourier_curves(rng, nbg, n_bg, L)
+    xyz = np.concatenate([pair_xyz, bg], axis=0)
+    gamma = np.concatenate([pair_gamma, np.ones(nbg)])
+    counts = [n_ring] * (2 * npairs) + [n_bg] * nbg
+    return FilamentSet("ringpairs", L, a, _csr(counts), xyz, gamma, grid_n, tol)
+
+
+def bigtangle(nfil: int = 10000, seed: int = 1005) -> FilamentSet:
+    return tangle(nfil=nfil, n_per=100, seed=seed, grid_n=512, tol=1e-5,
+                  name="bigtangle")
+
+
+WORKLOADS = {
+    "ring": ring,
+    "ellipses": ellipses,
+    "tangle": tangle,
+    "ringpairs": ringpairs,
+    "bigtangle": bigtangle,
+}
+
+
+def make(name: str, **kw) -> FilamentSet:
+    return WORKLOADS[name](**kw)

@@ -1,0 +1,347 @@
+"""Pins of the FP64 oracle to facts outside itself (CPU only).
+
+Each test checks the oracle against something it does not compute itself:
+library routines (numpy, scipy, mpmath), closed forms printed in the paper,
+brute-force image sums, invariants of the exact problem, or the paper's own
+error estimates.  A plausible slip in any oracle routine (a dropped term, a
+wrong sign or index, a transposed operand) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.interpolate
+
+from oracle import oracle as O
+from paper_2406_07366_amd import workloads as W
+
+mpmath = pytest.importorskip("mpmath")
+
+
+def rel_l2(a, b):
+    """Relative l2 error of paper Sec. 5.1, eq:def_relative_errors."""
+    return math.sqrt(((a - b) ** 2).sum(1).mean() / (b ** 2).sum(1).mean())
+
+
+# ---------------------------------------------------------------- geometry
+@pytest.mark.parametrize("Q", [1, 2, 3, 4])
+def test_gauss_legendre_rule_matches_numpy(Q):
+    h, w = O.gl_rule(Q)
+    x, ww = np.polynomial.legendre.leggauss(Q)
+    np.testing.assert_allclose(h, 0.5 * (x + 1), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w, 0.5 * ww, rtol=0, atol=1e-15)
+    assert abs(w.sum() - 1) < 1e-15
+
+
+@pytest.mark.parametrize("n", [3, 4, 9, 64])
+def test_cyclic_tridiagonal_matches_dense_solve(n):
+    rng = np.random.default_rng(n)
+    a = rng.uniform(0.1, 1, n); c = rng.uniform(0.1, 1, n)
+    b = a + c + rng.uniform(0.5, 2, n)
+    r = rng.standard_normal(n)
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, i] = b[i]
+        A[i, (i - 1) % n] += a[i]
+        A[i, (i + 1) % n] += c[i]
+    np.testing.assert_allclose(O.cyclic_tridiag(a, b, c, r), np.linalg.solve(A, r),
+                               rtol=1e-12, atol=1e-13)
+
+
+def _wobbly_loop(n=23, seed=3):
+    rng = np.random.default_rng(seed)
+    th = 2 * np.pi * (np.arange(n) + 0.3 * rng.uniform(size=n)) / n
+    xyz = np.stack([1.3 * np.cos(th), 0.7 * np.sin(th), 0.2 * np.sin(3 * th)], 1) + 2.0
+    return W.FilamentSet("wobbly", 2 * np.pi, 1e-6, np.array([0, n]), xyz,
+                         np.array([1.7]), 32, 1e-6)
+
+
+def test_spline_matches_scipy_periodic_cubic():
+    """App. B: chord-length knots + periodic interpolating cubic spline.  The
+    oracle's moments form must coincide with scipy's periodic CubicSpline."""
+    fs = _wobbly_loop()
+    Q = 3
+    o = O.Oracle(fs, Q=Q)
+    nd = o.nodes()
+    x = fs.xyz
+    seg = np.linalg.norm(np.roll(x, -1, 0) - x, axis=1)
+    tau = np.concatenate([[0], np.cumsum(seg)])           # closes at T
+    np.testing.assert_allclose(nd["tau"], tau[:-1], rtol=0, atol=1e-14)
+    sp = scipy.interpolate.CubicSpline(tau, np.vstack([x, x[:1]]), bc_type="periodic")
+    np.testing.assert_allclose(nd["sdot"], sp(tau[:-1], 1), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(nd["sddot"], sp(tau[:-1], 2), rtol=0, atol=1e-10)
+    h, w = np.polynomial.legendre.leggauss(Q)
+    h = 0.5 * (h + 1); w = 0.5 * w
+    tq = (tau[:-1, None] + h[None, :] * seg[:, None]).reshape(-1)
+    pos, der, chg = o.quad()
+    np.testing.assert_allclose(pos, sp(tq), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(der, sp(tq, 1), rtol=0, atol=1e-11)
+    # vector charges of eq:vorticity_fourier_coefs: Gamma w_i dtau_j s'_ij
+    wq = (w[None, :] * seg[:, None]).reshape(-1)
+    np.testing.assert_allclose(chg, 1.7 * wq[:, None] * sp(tq, 1), rtol=0, atol=1e-12)
+    # segment lengths: the same Q-point rule applied to |s'|
+    ell = (wq * np.linalg.norm(sp(tq, 1), axis=1)).reshape(-1, Q).sum(1)
+    np.testing.assert_allclose(nd["ell"], ell, rtol=1e-13)
+
+
+# ----------------------------------------------------- Ewald weight functions
+@pytest.mark.parametrize("x", [1e-4, 1e-2, 0.2, 0.49, 0.51, 1.0, 2.5, 5.0])
+def test_ewald_weights_match_mpmath(x):
+    """eq:ewald_derivative_weight_functions evaluated in 50-digit arithmetic."""
+    mpmath.mp.dps = 50
+    X = mpmath.mpf(x)
+    e = 2 * X / mpmath.sqrt(mpmath.pi) * mpmath.exp(-X * X)
+    glr = float(mpmath.erf(X) - e)
+    gsr = float(mpmath.erfc(X) + e)
+    assert abs(O.g_lr(x) - glr) <= 1e-13 * abs(glr)
+    assert abs(O.g_sr(x) - gsr) <= 1e-13 * abs(gsr)
+    assert abs(O.g_lr(x) + O.g_sr(x) - 1.0) < 1e-15
+
+
+def test_long_range_kernel_small_r_limit():
+    """Sec. 3.1: grad G_lr ~ -alpha^3 r / (3 pi^{3/2}) near r = 0, i.e.
+    g_lr(x)/x^3 -> 4/(3 sqrt(pi))."""
+    for x in [1e-3, 1e-5]:
+        assert abs(O.g_lr(x) / x ** 3 - 4 / (3 * math.sqrt(math.pi))) < 1e-5
+
+
+# ---------------------------------------------------------- invariants
+def test_total_is_independent_of_alpha():
+    """Sec. 3.1: the physical fields do not depend on the splitting parameter
+    when both parts are converged (same quadrature points for spread and self
+    term make this exact at the discrete level)."""
+    fs = W.ellipses(nfil=8, n_per=32, seed=11)
+    o = O.Oracle(fs)
+    L = fs.L
+    vs, ps = [], []
+    for beta, rc in [(6.5, L), (6.5, L / 2), (7.0, 1.9)]:
+        prm = O.reference_params(L, beta, rc)
+        v, p = o.ewald(prm["alpha"], prm["rc"], prm["K"])
+        vs.append(v); ps.append(p)
+    for v, p in zip(vs[1:], ps[1:]):
+        assert rel_l2(v, vs[0]) < 1e-12
+        assert rel_l2(p, ps[0]) < 1e-12
+
+
+def test_brute_force_image_sum_equals_ewald_plus_uniform_dipole_term():
+    """Unsplit discrete sum over cubic shells of images |n|_inf <= K,
+    Richardson-extrapolated in 1/K^2, minus the Ewald result must be the same
+    vector at every node, namely (2/3) p with p the impulse per unit density
+    (the uniform field that the k = 0 removal takes out)."""
+    fs = W.ellipses(nfil=3, n_per=12, seed=7)
+    o = O.Oracle(fs)
+    v, _ = o.reference(psi=False)
+    vl, _ = o.local()
+    b16 = o.brute_images(16) + vl
+    b32 = o.brute_images(32) + vl
+    rich = (32 ** 2 * b32 - 16 ** 2 * b16) / (32 ** 2 - 16 ** 2)
+    d = rich - v
+    p = o.impulse()
+    assert np.abs(d - d.mean(0)).max() < 5e-8          # uniform over nodes
+    np.testing.assert_allclose(d.mean(0), (2.0 / 3.0) * p, rtol=0, atol=5e-8)
+    # and the unextrapolated sums do approach it
+    assert np.abs(b32 - v - (2 / 3) * p).max() < np.abs(b16 - v - (2 / 3) * p).max()
+
+
+def _kelvin(R, a, delta=0.25):
+    return (math.log(8 * R / a) - delta) / (4 * math.pi * R)
+
+
+def test_kelvin_ring_speed_in_large_box():
+    """eq:vortex_ring_velocity.  In a box of side L the Ewald velocity is the
+    isolated one minus the uniform (2/3) kappa pi R^2 / L^3 term; the
+    remaining error is the O(N^-2) curvature error of the cubic spline, removed
+    by Richardson extrapolation between N = 256 and 512 (Q = 4)."""
+    R, a = 1.0, 1e-6
+    L = 16 * math.pi
+    V = {}
+    for N in (256, 512):
+        fs = W.ring(n_nodes=N, R=R, L=L, a=a)
+        o = O.Oracle(fs, Q=4)
+        v, _ = o.reference(targets=[0, N // 3], psi=False)
+        # in-plane components vanish; nodes differ only by the box's cubic anisotropy
+        assert np.abs(v[:, :2]).max() < 1e-10 and abs(v[0, 2] - v[1, 2]) < 1e-9
+        V[N] = v[0, 2] + (2 / 3) * math.pi * R ** 2 / L ** 3
+    vk = _kelvin(R, a)
+    rich = V[512] + (V[512] - V[256]) / 3
+    assert abs(V[256] - vk) / vk < 6e-5
+    assert abs(rich - vk) / vk < 2e-6
+
+
+def test_kelvin_ring_speed_small_workload():
+    """The 64-node ring workload (R = pi/3, L = 2 pi, Q = 2) sits within the
+    cubic-spline discretisation error of the corrected closed form."""
+    fs = W.ring()
+    o = O.Oracle(fs, Q=2)
+    v, _ = o.reference(targets=[0], psi=False)
+    R = math.pi / 3
+    vk = _kelvin(R, fs.a) - (2 / 3) * math.pi * R ** 2 / fs.L ** 3
+    assert abs(v[0, 2] - vk) / vk < 1.5e-3
+
+
+def test_ring_energy_and_impulse_closed_forms():
+    """eq:vortex_ring_energy: E = kappa^2 R/(2V) [ln(8R/a) - (Delta + 1)],
+    from eq:kinetic_energy_streamfunction with psi on the nodes; the periodic
+    correction decays like L^-3 and the discretisation error like N^-2 (both
+    removed by Richardson extrapolation).  Impulse p = kappa pi R^2 / V."""
+    R, a = 1.0, 1e-6
+    EV = {}
+    for N in (256, 512):
+        for L in (8 * math.pi, 16 * math.pi):
+            fs = W.ring(n_nodes=N, R=R, L=L, a=a)
+            o = O.Oracle(fs, Q=4)
+            _, p = o.reference()
+            EV[N, L] = o.energy(p) * L ** 3
+            if N == 512:
+                pV = o.impulse() * L ** 3
+                np.testing.assert_allclose(pV, [0, 0, math.pi * R ** 2], rtol=0, atol=1e-8)
+    def ext_L(N):
+        return EV[N, 16 * math.pi] + (EV[N, 16 * math.pi] - EV[N, 8 * math.pi]) / 7
+    e = ext_L(512) + (ext_L(512) - ext_L(256)) / 3
+    ek = R / 2 * (math.log(8 * R / a) - 1.25)
+    assert abs(e - ek) / ek < 3e-6
+    # the line-form energy (non-periodic expression) would give Delta instead
+    # of Delta + 1: a relative shift of 1/(ln(8R/a) - 1.25) ~ 7 %, far outside.
+    assert abs(e - R / 2 * (math.log(8 * R / a) - 0.25)) / ek > 0.05
+
+
+def test_truncation_estimate_bounds_measured_error():
+    """Sec. 4, eq:error_trunc_velocity: the rms truncation error estimate is an
+    upper bound of the measured relative error (Sec. 5.1, Fig. 2), and the
+    error decays like exp(-beta^2).  Parameters at fixed grid as the GPU plan
+    picks them: K = 20, alpha = K (2 pi / L) / (2 beta), r_c = beta / alpha."""
+    fs = W.ellipses()
+    o = O.Oracle(fs)
+    vr, _ = o.reference(psi=False)
+    L = fs.L; V = L ** 3; Lt = o.length(); K = 20
+    vrms = math.sqrt((vr ** 2).sum(1).mean())
+    errs = []
+    for beta in (2.5, 3.0, 3.5, 4.0):
+        alpha = K * (2 * math.pi / L) / (2 * beta)
+        v, _ = o.ewald(alpha, beta / alpha, K, psi=False)
+        est = (Lt / (math.sqrt(math.pi) * alpha * V)
+               + math.sqrt(Lt / (8 * math.pi * V)) / beta) * math.exp(-beta ** 2) / vrms
+        err = rel_l2(v, vr)
+        assert err < est
+        errs.append(err)
+    assert errs[2] < 1e-6          # beta = 3.5 meets the 1e-6 tolerance
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 < e0 / 10
+
+
+def test_symmetries():
+    """Translation invariance, linearity in Gamma, orientation reversal and a
+    90-degree rotation of the box about z (Sec. 2.2, eq:BS)."""
+    fs = W.ellipses(nfil=6, n_per=24, seed=5)
+    L = fs.L
+    prm = dict(alpha=3.0, rc=1.3, K=12)
+    base, _ = O.Oracle(fs).ewald(**prm, psi=False)
+    c = np.array([0.37, -2.9, 5.1])
+    t, _ = O.Oracle(W.FilamentSet(**{**fs.__dict__, "xyz": fs.xyz + c})).ewald(**prm, psi=False)
+    np.testing.assert_allclose(t, base, rtol=0, atol=1e-13 * np.abs(base).max())
+    g, _ = O.Oracle(W.FilamentSet(**{**fs.__dict__, "gamma": -2.5 * fs.gamma})).ewald(**prm, psi=False)
+    np.testing.assert_allclose(g, -2.5 * base, rtol=0, atol=1e-13 * np.abs(base).max())
+    # reverse node order of every filament, keeping node 0 first
+    idx = np.concatenate([np.r_[s, np.arange(e - 1, s, -1)]
+                          for s, e in zip(fs.offsets[:-1], fs.offsets[1:])])
+    r, _ = O.Oracle(W.FilamentSet(**{**fs.__dict__, "xyz": fs.xyz[idx]})).ewald(**prm, psi=False)
+    np.testing.assert_allclose(r, -base[idx], rtol=0, atol=1e-12 * np.abs(base).max())
+    # (x, y, z) -> (-y, x, z)
+    rot = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1.0]])
+    q, _ = O.Oracle(W.FilamentSet(**{**fs.__dict__, "xyz": fs.xyz @ rot.T})).ewald(**prm, psi=False)
+    np.testing.assert_allclose(q, base @ rot.T, rtol=0, atol=1e-12 * np.abs(base).max())
+
+
+# ------------------------------------------------------------ near-singular
+def _bs_segment_numeric(A, B, x):
+    e = B - A
+    out = []
+    for k in range(3):
+        def f(t):
+            r = A + t * e - x
+            c = np.cross(r, e)
+            return c[k] / np.linalg.norm(r) ** 3
+        out.append(scipy.integrate.quad(f, 0, 1, epsabs=0, epsrel=1e-13, limit=200)[0])
+    return np.array(out) / (4 * math.pi)
+
+
+def test_straight_segment_closed_form_matches_quadrature():
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        A, B = rng.standard_normal(3), rng.standard_normal(3)
+        x = 0.5 * (A + B) + 1e-2 * rng.standard_normal(3)
+        np.testing.assert_allclose(O.chord_integral(A, B, x), _bs_segment_numeric(A, B, x),
+                                   rtol=1e-9)
+    # infinite-line limit: Gamma/(2 pi d) about the line
+    d, Z = 0.3, 1e6
+    v = O.chord_integral([0, 0, -Z], [0, 0, Z], [d, 0, 0])
+    exact = Z / math.hypot(Z, d) / (2 * math.pi * d)
+    np.testing.assert_allclose(v, [0, exact, 0], rtol=1e-13, atol=1e-14)
+
+
+def test_adaptive_segment_integral_matches_scipy_quad_on_scipy_spline():
+    """Exact integral of the full kernel over one spline segment at a target
+    very close to it: the oracle's adaptive Gauss-Kronrod against scipy.quad
+    on scipy's own periodic spline of the same nodes."""
+    fs = _wobbly_loop(n=17, seed=9)
+    o = O.Oracle(fs, Q=2)
+    x = fs.xyz
+    seg = np.linalg.norm(np.roll(x, -1, 0) - x, axis=1)
+    tau = np.concatenate([[0], np.cumsum(seg)])
+    sp = scipy.interpolate.CubicSpline(tau, np.vstack([x, x[:1]]), bc_type="periodic")
+    j = 5
+    mid = sp(tau[j] + 0.41 * seg[j])
+    nrm = np.cross(sp(tau[j] + 0.41 * seg[j], 1), [0.3, 0.2, 1.0])
+    nrm /= np.linalg.norm(nrm)
+    for d in (1e-1, 1e-2, 1e-3):
+        tgt = mid + d * seg[j] * nrm
+        got, npieces = o.segment_integral(j, tgt, tol=1e-13)
+        assert npieces > 0
+        ref = []
+        for k in range(3):
+            def f(t):
+                r = sp(t) - tgt
+                return np.cross(r, sp(t, 1))[k] / np.linalg.norm(r) ** 3
+            ref.append(scipy.integrate.quad(f, tau[j], tau[j + 1], epsabs=0, epsrel=1e-12,
+                                            limit=400, points=[tau[j] + 0.41 * seg[j]])[0])
+        ref = np.array(ref) * 1.7 / (4 * math.pi)
+        np.testing.assert_allclose(got, ref, rtol=1e-9)
+        # the Q-point rule is badly off this close, which is why it is replaced
+        qs = o.segment_qsum(j, tgt)
+        if d <= 1e-2:
+            assert np.linalg.norm(qs - ref) > 0.1 * np.linalg.norm(ref)
+
+
+def test_near_singular_correction_flags_and_limits():
+    fs = W.ringpairs(npairs=3, nbg=0, seed=4)
+    o = O.Oracle(fs)
+    dv0, c0 = o.ns_correction(eta=0.0)
+    assert c0.sum() == 0 and np.abs(dv0).max() == 0.0
+    dv, c = o.ns_correction(eta=1.0)
+    # every node sees its partner ring closer than one segment length
+    gaps = np.linalg.norm(fs.xyz[0:16] - fs.xyz[16:32], axis=1)
+    assert c.min() >= 1 and np.abs(dv).max() > 0
+    # correction grows as the gap shrinks (pair 0 vs pair 1 vs pair 2)
+    del gaps
+
+
+# --------------------------------------------------------------------- MLP
+def test_mlp_gradient_matches_central_differences():
+    n = O.mlp_nparams()
+    assert n == 8 * 64 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3
+    rng = np.random.default_rng(0)
+    P = rng.standard_normal(n) * 0.3
+    X = rng.standard_normal((5, 8))
+    T = rng.standard_normal((5, 3))
+    loss, G = O.mlp_loss_grad(P, X, T)
+    idx = rng.choice(n, 60, replace=False)
+    for i in idx:
+        h = 1e-6
+        Pp = P.copy(); Pp[i] += h
+        Pm = P.copy(); Pm[i] -= h
+        fd = (O.mlp_loss_grad(Pp, X, T)[0] - O.mlp_loss_grad(Pm, X, T)[0]) / (2 * h)
+        assert abs(fd - G[i]) <= 1e-7 + 1e-5 * abs(fd)
+    # forward of a zero network is its output bias
+    Z = np.zeros(n); Z[-3:] = [1, 2, 3]
+    np.testing.assert_array_equal(O.mlp_forward(Z, X), np.tile([1.0, 2, 3], (5, 1)))
