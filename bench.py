@@ -1,0 +1,237 @@
+"""Benchmark: filament nodes per second per Biot-Savart velocity evaluation.
+
+One step = bs_set_filaments (device-resident positions in: chord lengths,
+spline fit, quadrature points, binning) + bs_velocity (local, self,
+short-range pairs, spread, FFT, spectral operator, inverse FFT,
+interpolation), i.e. the whole hot path from node positions to node
+velocities, on one MI355X.
+
+Default workload: 40 random ellipses x 64 nodes (N = 2560), grid 64^3,
+tolerance 1e-6, FP64 path (the accuracy bar of the metric: rel. l2 error
+<= 1e-6 against the converged FP64 CPU oracle).  The FP32-mixed path is timed
+on the same workload and reported beside it.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_TFLOPS = 157.3     # MI355X dense fp32 vector
+FP64_VECTOR_TFLOPS = 78.6
+PAIR_FLOP = 60.0               # per interacting pair (erfc, exp, sqrt, div, cross, fma)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    return math.sqrt(((a - b) ** 2).sum(1).mean() / (b ** 2).sum(1).mean())
+
+
+def count_pairs(fs, Q, rc):
+    """Interacting (node, quadrature point) pairs within r_c, minimum image,
+    minus the 2Q excluded points of each node's adjacent segments."""
+    from scipy.spatial import cKDTree
+    from oracle import oracle as O   # geometry only, for the pair count
+    o = O.Oracle(fs, Q=Q)
+    qp, _, _ = o.quad()
+    L = fs.L
+    tree = cKDTree(np.mod(qp, L) % L, boxsize=L)
+    cnt = tree.query_ball_point(np.mod(fs.xyz, L) % L, rc, return_length=True)
+    return int(cnt.sum()) - 2 * Q * fs.n_nodes
+
+
+def stage_bytes(prm, N, Nq, fp32):
+    """Algorithmic HBM bytes per launch of each stage (minimum traffic)."""
+    s = 4 if fp32 else 8
+    n = prm.grid_n
+    n3 = n ** 3
+    nc = n * n * (n // 2 + 1)
+    w = prm.w
+    return {
+        "spread": 3 * n3 * s + Nq * (16 + (3 * w + 4) * s),
+        "fft_fwd": 3 * n3 * s + 3 * nc * 2 * s,
+        "spectral": 2 * 3 * nc * 2 * s,
+        "fft_inv": 3 * nc * 2 * s + 3 * n3 * s,
+        "interp": 3 * n3 * s + N * (24 + 48),
+    }
+
+
+def time_steps(torch, plan, fs, xyz, gamma, out, steps, warmup):
+    for _ in range(warmup):
+        plan.set_filaments(fs.offsets, xyz, gamma)
+        plan.velocity(out)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        plan.set_filaments(fs.offsets, xyz, gamma)
+        plan.velocity(out)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, ev0.elapsed_time(ev1) / steps
+
+
+def stage_profile(torch, plan, fs, xyz, gamma, out, steps):
+    plan.set_profiling(True)
+    plan.stage_times(reset=True)
+    for _ in range(steps):
+        plan.set_filaments(fs.offsets, xyz, gamma)
+        plan.velocity(out)
+    torch.cuda.synchronize()
+    st = plan.stage_times(reset=True)
+    plan.set_profiling(False)
+    return {k: (ms / c if c else 0.0) for k, (ms, c) in st.items()}
+
+
+def cpu_baseline(fs, prm, budget_s=10.0):
+    """The oracle as it stands (direct Fourier sums, brute-force pairs) at the
+    plan's own alpha, r_c, K on the whole workload, repeated for ~budget_s."""
+    from oracle import oracle as O
+    o = O.Oracle(fs, Q=prm.Q)
+    t0 = time.perf_counter()
+    runs = 0
+    while True:
+        oo = O.Oracle(fs, Q=prm.Q)          # geometry is part of the step
+        oo.ewald(prm.alpha, prm.rcut, prm.K, psi=False)
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    del o
+    return {"value": fs.n_nodes * runs / dt, "unit": "nodes/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{runs} full evaluations of the {fs.name} workload (N={fs.n_nodes}) "
+                      f"at the GPU plan's alpha, r_c, K with direct Fourier sums, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ellipses")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from oracle import oracle as O
+    from paper_2406_07366_amd import binding as B
+    from paper_2406_07366_amd import workloads as W
+
+    fs = W.make(args.workload)
+    N = fs.n_nodes
+    log(f"[bench] workload {fs.name} N={N} grid={fs.grid_n}^3 tol={fs.tol}")
+    xyz, gamma = B.load_workload(fs)
+    out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+
+    # reference solution (converged oracle), sampled on large workloads
+    if N <= 20000:
+        idx = np.arange(N)
+    else:
+        idx = np.sort(np.random.default_rng(0).choice(N, 256, replace=False))
+    t0 = time.perf_counter()
+    ref, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False)
+    log(f"[bench] reference ({len(idx)} nodes) in {time.perf_counter() - t0:.1f} s")
+
+    results = {}
+    for prec_name in ("fp64", "mixed"):
+        prec = B.BS_FP64 if prec_name == "fp64" else B.BS_FP32_MIXED
+        plan = B.Plan(B.params_for(fs, precision=prec))
+        prm = plan.params()
+        plan.set_filaments(fs.offsets, xyz, gamma)
+        plan.velocity(out)
+        plan.status()
+        err = rel_l2(out.cpu().numpy()[idx], ref)
+        ms_host, ms_ev = time_steps(torch, plan, fs, xyz, gamma, out, args.steps, args.warmup)
+        st = stage_profile(torch, plan, fs, xyz, gamma, out, max(20, args.steps // 4))
+        log(f"[bench] {prec_name}: {ms_host:.4f} ms/step (events {ms_ev:.4f}), "
+            f"rel_l2 {err:.3e}, {N / ms_host * 1e3:.4g} nodes/s")
+        log("[bench]   stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in st.items()))
+        results[prec_name] = dict(ms=ms_host, ms_events=ms_ev, err=err, stages=st,
+                                  prm=prm.as_dict(), plan=plan)
+
+    primary = results[args.precision]
+    prm = primary["prm"]
+    fp32 = args.precision == "mixed"
+    Nq = N * prm["Q"]
+    npairs = count_pairs(fs, prm["Q"], prm["rcut"])
+    sb = stage_bytes(B.resolve_params(B.params_for(fs, precision=int(fp32))), N, Nq, fp32)
+    st = primary["stages"]
+    roof_all = {}
+    for k, b in sb.items():
+        if st.get(k, 0) > 0:
+            roof_all[k] = dict(bound="hbm", achieved=b / (st[k] * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                               unit="GB/s", bytes=b, ms=st[k])
+    if st.get("pairs", 0) > 0:
+        peak = FP32_VECTOR_TFLOPS if fp32 else FP64_VECTOR_TFLOPS
+        fl = npairs * PAIR_FLOP
+        roof_all["pairs"] = dict(bound="alu", achieved=fl / (st["pairs"] * 1e-3) / 1e12,
+                                 peak=peak, unit="TFLOP/s", flops=fl, pairs=npairs,
+                                 ms=st["pairs"])
+    dom = max((k for k in roof_all), key=lambda k: roof_all[k]["ms"])
+    d = roof_all[dom]
+    roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"],
+                "peak": d["peak"], "unit": d["unit"], "frac": d["achieved"] / d["peak"],
+                "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle baseline ...")
+        cpu = cpu_baseline(fs, B.resolve_params(B.params_for(fs)))
+        log(f"[bench] cpu baseline {cpu['value']:.4g} nodes/s on {cpu['cores']} threads")
+
+    value = N / (primary["ms"] * 1e-3)
+    other = "mixed" if args.precision == "fp64" else "fp64"
+    line = {
+        "metric": "filament nodes/s per velocity eval at rel. L2 err <= 1e-6 vs FP64 oracle",
+        "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": primary["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{fs.name}: {fs.n_fil} filaments, N={N}, grid {fs.grid_n}^3, "
+                               f"tol {fs.tol:g}, Q={prm['Q']}, w={prm['w']}, "
+                               f"beta={prm['beta']}",
+                   "rel_l2_err": primary["err"],
+                   "other_precision": {"name": other, "nodes_per_s": N / (results[other]["ms"] * 1e-3),
+                                       "rel_l2_err": results[other]["err"]}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    os.makedirs(os.path.dirname(args.detail), exist_ok=True)
+    with open(args.detail, "w") as f:
+        json.dump({"line": line, "roofline_all": roof_all,
+                   "stages": {k: v["stages"] for k, v in results.items()},
+                   "params": {k: v["prm"] for k, v in results.items()},
+                   "pairs": npairs}, f, indent=1, default=float)
+    for r in results.values():
+        r["plan"].close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

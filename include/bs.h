@@ -1,0 +1,208 @@
+/*
+ * bs.h -- C ABI of libbs.so: Ewald-split Biot-Savart velocity (and
+ * streamfunction / energy) at the nodes of closed vortex filaments in a
+ * triply periodic cubic box, on one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: J. I. Polanco, "Fast and accurate evaluation of Biot-Savart
+ * integrals over spatial curves in periodic domains", arXiv 2406.07366.
+ *
+ * Problem statement followed by the calls:
+ *   - filaments are closed oriented curves given by ordered nodes
+ *     (Sec. 2.1) carrying one circulation each (Sec. 2.2, eq:BS);
+ *   - the curve through the nodes is the periodic cubic spline on
+ *     chord-length knots (App. B); line integrals use Q Gauss-Legendre
+ *     points per segment (Sec. 2.7, eq:line_integral_quadrature);
+ *   - v = v_local + v_short + v_long - v_self (Sec. 3,
+ *     eq:ewald_velocity_splitting), psi likewise
+ *     (eq:ewald_streamfunction_splitting), with the local terms
+ *     eq:BS_local / eq:streamfunction_local, the short-range sums
+ *     eq:velocity_shortrange / eq:streamfunction_shortrange cut at r_c,
+ *     the long-range part by a type-1 NUFFT, the Gaussian-filtered symbol
+ *     i k x / k^2 (eq:velocity_longrange_physical) and a type-2 NUFFT
+ *     (Sec. 3.3, App. A, backward Kaiser-Bessel kernel eq:kaiser_bessel_bw),
+ *     and the self corrections eq:velocity_longrange_self /
+ *     eq:streamfunction_longrange_self;
+ *   - E = (1/2V) sum_l Gamma_l oint psi . ds
+ *     (eq:kinetic_energy_streamfunction).
+ *
+ * Conventions shared by every call:
+ *   - all floating-point arrays are float64; node arrays are [N][3]
+ *     row-major (x, y, z of node 0, then node 1, ...);
+ *   - "device" pointers are HIP device memory on the plan's device; the
+ *     caller owns every array it passes; the plan owns its internal buffers;
+ *   - calls are asynchronous on the plan's stream unless stated otherwise;
+ *     results are ready once that stream has been synchronised;
+ *   - return value: 0 (BS_OK) or a negative BS_E* code; bs_last_error()
+ *     then holds a message.  A failed call leaves the plan usable.
+ *   - one plan must not be used from two host threads at once.
+ */
+#ifndef BS_H
+#define BS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BS_OK        0
+#define BS_EINVAL   -1   /* bad argument, size, or filament geometry            */
+#define BS_EMINIMG  -2   /* r_c > L/2: violates the minimum-image convention
+                            (Sec. 5.2, footnote on r_c <= L/2)                 */
+#define BS_ETOL     -3   /* tolerance unreachable on this grid (would need
+                            r_c > L/2)                                        */
+#define BS_EKB      -4   /* retained modes outside the kernel's band (|k|
+                            scaled beyond the Kaiser-Bessel shape parameter)  */
+#define BS_ENOMEM   -5   /* device allocation failed                          */
+#define BS_EDEVICE  -6   /* HIP / hipFFT runtime error                        */
+#define BS_ESTATE   -7   /* call out of order (e.g. velocity before filaments)*/
+
+/* precision */
+#define BS_FP64        0  /* every step in float64                            */
+#define BS_FP32_MIXED  1  /* spread, FFT, interpolation and short-range pairs
+                             in float32 with float32 accumulation; positions,
+                             grid offsets and pair separations formed in
+                             float64; local, self, k = 0 and reductions in
+                             float64                                          */
+
+/* near-singular treatment of (node, segment) pairs closer than
+ * ns_eta * segment length (not part of the paper; see bs_velocity) */
+#define BS_NS_OFF       0
+#define BS_NS_ADAPTIVE  1  /* adaptive Gauss-Kronrod on the spline segment    */
+#define BS_NS_MLP       2  /* learned correction with adaptive fallback       */
+
+typedef struct bs_plan_s *bs_plan_t;
+
+/* Parameters.  Zero in a derived field means "derive it":
+ *   beta   from tol: the beta of the most accurate-enough row of the paper's
+ *          Table 1 (tol 1e-3..1e-14 -> beta 2.0..5.5), i.e. the row with the
+ *          largest tolerance <= tol;
+ *   w      from tol: ceil(-log10(tol)/0.9) + 1 (NUFFT error ~10^(-0.9 w) at
+ *          sigma = 1.5, App. A, Fig. accuracy_nufft), clamped to [4, 16];
+ *   alpha  from the grid: M = floor(grid_n / sigma) resolved modes per
+ *          axis, K = floor((M-1)/2), k_max = 2 pi K / L = 2 beta alpha
+ *          (Sec. 4: k_max = 2 beta alpha, r_c = beta / alpha);
+ *   rcut   = beta / alpha.
+ * If alpha is given, rcut defaults to beta/alpha; if both are given they
+ * are used as is. */
+typedef struct {
+    double L;            /* box period (cubic)                                 */
+    double a;            /* vortex core radius                                 */
+    double delta;        /* core-profile constant Delta (1/4: uniform core)    */
+    double tol;          /* nominal relative tolerance                         */
+    double beta;         /* cut-off coefficient (0: from tol)                  */
+    double alpha;        /* Ewald splitting parameter (0: from grid and beta)  */
+    double rcut;         /* short-range cut-off (0: beta/alpha)                */
+    int    grid_n;       /* spread/FFT grid points per axis (multiple of 4)    */
+    double sigma;        /* oversampling factor (0: 1.5)                       */
+    int    w;            /* kernel width in grid points (0: from tol)          */
+    int    Q;            /* Gauss-Legendre points per segment, 1..4 (0: 2)     */
+    int    spline_order; /* 4 = cubic (the only order built; 0: 4)             */
+    int    precision;    /* BS_FP64 or BS_FP32_MIXED                           */
+    int    ns_mode;      /* BS_NS_OFF, BS_NS_ADAPTIVE or BS_NS_MLP             */
+    double ns_eta;       /* flag pairs with chord distance < ns_eta * ell (0: 1) */
+    const void *mlp_weights; /* host pointer to the packed float32 MLP
+                                parameters (see bs_mlp_nparams); needed for
+                                BS_NS_MLP; copied by bs_plan                   */
+    /* resolved values, written by bs_resolve_params / bs_get_params */
+    int    K;            /* retained modes |m_i| <= K per axis                 */
+    int    ncell;        /* cells per axis of the short-range cell list        */
+    double zeta;         /* Kaiser-Bessel shape parameter                      */
+} bs_params;
+
+/* Pure host call (no device needed): validate p and fill every derived
+ * field into *out.  Errors: BS_EINVAL (L, a, tol, grid_n, sigma, w, Q,
+ * spline_order out of range), BS_EMINIMG (rcut > L/2), BS_ETOL (derived
+ * rcut would exceed L/2), BS_EKB. */
+int bs_resolve_params(const bs_params *p, bs_params *out);
+
+/* Create a plan on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL = the null stream); every later call enqueues on it.  Allocates
+ * the grids and builds the FFT plans.  *out receives the handle (NULL on
+ * error).  Errors as bs_resolve_params, plus BS_ENOMEM, BS_EDEVICE. */
+int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out);
+
+/* Load a filament set.
+ *   nfil     number of closed filaments (>= 1);
+ *   offsets  HOST int64 [nfil+1], offsets[0] = 0, filament l owns nodes
+ *            offsets[l] .. offsets[l+1]-1, each filament has >= 3 nodes;
+ *   xyz      DEVICE float64 [N][3], N = offsets[nfil], unwrapped positions
+ *            (consecutive nodes close; the node after the last one is the
+ *            first one at the same unwrapped position);
+ *   gamma    DEVICE float64 [nfil], circulation of each filament.
+ * The spline fit and quadrature geometry are computed here, asynchronously;
+ * xyz and gamma are read before the call's work completes and are not kept.
+ * Host-side errors: BS_EINVAL (sizes), BS_ENOMEM.  Non-finite positions or
+ * zero-length segments are detected on the device and reported by the next
+ * bs_status() (outputs computed from such input are meaningless). */
+int bs_set_filaments(bs_plan_t plan, int64_t nfil, const int64_t *offsets,
+                     const double *xyz, const double *gamma);
+
+/* Velocity at every node: v_out DEVICE float64 [N][3] (overwritten).
+ * v = v_local + v_short + v_long - v_self, plus, when ns_mode is not
+ * BS_NS_OFF, the near-singular correction: for every non-adjacent segment
+ * whose chord lies closer than ns_eta * (segment length) to the node, the
+ * Q-point sum of that segment is replaced by its exact integral of the full
+ * Biot-Savart kernel.  BS_ESTATE if no filaments were set. */
+int bs_velocity(bs_plan_t plan, double *v_out);
+
+/* Velocity split into its terms, each a DEVICE float64 [N][3] array or
+ * NULL: local, short-range, long-range, self correction (to be subtracted)
+ * and near-singular correction.  For tests and diagnostics. */
+int bs_velocity_terms(bs_plan_t plan, double *v_local, double *v_short,
+                      double *v_long, double *v_self, double *v_ns);
+
+/* Streamfunction at every node (psi_out DEVICE [N][3], or NULL) and the
+ * kinetic energy per unit density E (HOST double).  Synchronises the plan
+ * stream.  BS_ESTATE if no filaments were set. */
+int bs_energy(bs_plan_t plan, double *E_out, double *psi_out);
+
+/* Fourier coefficients of the vorticity recovered from the spread grid
+ * (type-1 NUFFT of the vector charges, eq:vorticity_fourier_coefs), for
+ * the half space of modes: out DEVICE float64 complex as (re, im) pairs,
+ * shape [K+1][2K+1][2K+1][3] indexed [mz][my+K][mx+K][component]; entries
+ * outside the half space (mz = 0 and (my < 0 or my = 0 and mx <= 0)) are 0.
+ * For tests of the spreading step. */
+int bs_vorticity_modes(bs_plan_t plan, double *out);
+
+/* Geometry of the loaded filaments, DEVICE float64 arrays or NULL:
+ * quadrature point positions [N*Q][3] (unwrapped), vector charges
+ * Gamma w_i dtau_j s'_ij [N*Q][3], node tangents ds/dtau [N][3], node
+ * second derivatives d2s/dtau2 [N][3], segment lengths [N].  Point q =
+ * j*Q + i lies on segment j (node j to its successor). */
+int bs_geometry(bs_plan_t plan, double *qpos, double *qcharge, double *sdot,
+                double *sddot, double *ell);
+
+/* Synchronise the plan stream and report device-side input errors seen
+ * since the last call (BS_EINVAL with a message), else BS_OK. */
+int bs_status(bs_plan_t plan);
+
+/* Per-stage timing, for measurement.  While enabled, bs_set_filaments and
+ * bs_velocity record HIP events before and after each stage on the plan
+ * stream and synchronise at their end; bs_stage_times returns the summed
+ * milliseconds and the number of timed launches of each stage (arrays of
+ * BS_NSTAGES, either may be NULL) and optionally resets them.  Stages:
+ *   0 geometry (chord lengths, spline solve, quadrature points)
+ *   1 binning (counting sorts and sorted copies)
+ *   2 local and self terms      3 spread        4 forward FFT
+ *   5 spectral operator         6 inverse FFT   7 interpolation
+ *   8 short-range pairs         9 near-singular correction              */
+#define BS_NSTAGES 10
+int bs_set_profiling(bs_plan_t plan, int enable);
+int bs_stage_times(bs_plan_t plan, double *ms, int64_t *counts, int reset);
+
+/* Parameters actually used (all derived fields filled). */
+int bs_get_params(bs_plan_t plan, bs_params *resolved);
+
+/* Release every device buffer and FFT plan; synchronises first. */
+int bs_destroy(bs_plan_t plan);
+
+/* Message of the last failed call on this plan (or of the last failed
+ * bs_plan / bs_resolve_params when plan is NULL).  Never NULL. */
+const char *bs_last_error(bs_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BS_H */

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libbs.so (argument marshalling only).
+
+Every step of the velocity / energy evaluation runs in the HIP kernels of
+libbs.so; this module only converts torch tensors and numpy arrays into the
+pointers and sizes of the C ABI declared in include/bs.h.  PyTorch provides
+device memory and the HIP stream.  There is no fallback: if libbs.so is not
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbs.so")
+
+BS_OK, BS_EINVAL, BS_EMINIMG, BS_ETOL, BS_EKB, BS_ENOMEM, BS_EDEVICE, BS_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+BS_FP64, BS_FP32_MIXED = 0, 1
+BS_NS_OFF, BS_NS_ADAPTIVE, BS_NS_MLP = 0, 1, 2
+
+_CODES = {0: "BS_OK", -1: "BS_EINVAL", -2: "BS_EMINIMG", -3: "BS_ETOL", -4: "BS_EKB",
+          -5: "BS_ENOMEM", -6: "BS_EDEVICE", -7: "BS_ESTATE"}
+
+EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_velocity",
+            "bs_velocity_terms", "bs_energy", "bs_vorticity_modes", "bs_geometry",
+            "bs_status", "bs_set_profiling", "bs_stage_times", "bs_get_params",
+            "bs_destroy", "bs_last_error"]
+
+NSTAGES = 10
+STAGES = ["geometry", "binning", "local_self", "spread", "fft_fwd", "spectral", "fft_inv",
+          "interp", "pairs", "ns"]
+
+
+class BsParams(C.Structure):
+    _fields_ = [("L", C.c_double), ("a", C.c_double), ("delta", C.c_double),
+                ("tol", C.c_double), ("beta", C.c_double), ("alpha", C.c_double),
+                ("rcut", C.c_double), ("grid_n", C.c_int), ("sigma", C.c_double),
+                ("w", C.c_int), ("Q", C.c_int), ("spline_order", C.c_int),
+                ("precision", C.c_int), ("ns_mode", C.c_int), ("ns_eta", C.c_double),
+                ("mlp_weights", C.c_void_p), ("K", C.c_int), ("ncell", C.c_int),
+                ("zeta", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "mlp_weights"}
+
+
+class BsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(hipcc --offload-arch=gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+_vp = C.c_void_p
+_lib.bs_resolve_params.argtypes = [C.POINTER(BsParams), C.POINTER(BsParams)]
+_lib.bs_plan.argtypes = [C.POINTER(BsParams), _vp, C.POINTER(_vp)]
+_lib.bs_set_filaments.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int64), _vp, _vp]
+_lib.bs_velocity.argtypes = [_vp, _vp]
+_lib.bs_velocity_terms.argtypes = [_vp] + [_vp] * 5
+_lib.bs_energy.argtypes = [_vp, C.POINTER(C.c_double), _vp]
+_lib.bs_vorticity_modes.argtypes = [_vp, _vp]
+_lib.bs_geometry.argtypes = [_vp] + [_vp] * 5
+_lib.bs_status.argtypes = [_vp]
+_lib.bs_get_params.argtypes = [_vp, C.POINTER(BsParams)]
+_lib.bs_set_profiling.argtypes = [_vp, C.c_int]
+_lib.bs_stage_times.argtypes = [_vp, _vp, _vp, C.c_int]
+_lib.bs_destroy.argtypes = [_vp]
+_lib.bs_last_error.argtypes = [_vp]
+_lib.bs_last_error.restype = C.c_char_p
+
+
+def lib():
+    return _lib
+
+
+def _check(code, plan=None):
+    if code != BS_OK:
+        msg = _lib.bs_last_error(plan).decode()
+        raise BsError(code, msg)
+
+
+def make_params(L, a, tol, grid_n, delta=0.25, beta=0.0, alpha=0.0, rcut=0.0, sigma=0.0,
+                w=0, Q=0, precision=BS_FP64, ns_mode=BS_NS_OFF, ns_eta=0.0) -> BsParams:
+    p = BsParams()
+    p.L, p.a, p.delta, p.tol = L, a, delta, tol
+    p.beta, p.alpha, p.rcut = beta, alpha, rcut
+    p.grid_n, p.sigma, p.w, p.Q = grid_n, sigma, w, Q
+    p.spline_order = 4
+    p.precision, p.ns_mode, p.ns_eta = precision, ns_mode, ns_eta
+    p.mlp_weights = None
+    return p
+
+
+def resolve_params(p: BsParams) -> BsParams:
+    """Host-only parameter derivation (no device needed)."""
+    out = BsParams()
+    _check(_lib.bs_resolve_params(C.byref(p), C.byref(out)))
+    return out
+
+
+def params_for(fs, precision=BS_FP64, **kw) -> BsParams:
+    """Parameters of a workloads.FilamentSet (box, core, grid and tolerance)."""
+    return make_params(L=fs.L, a=fs.a, delta=fs.delta, tol=fs.tol, grid_n=fs.grid_n,
+                       precision=precision, **kw)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One evaluation plan on the current HIP device and torch stream."""
+
+    def __init__(self, params: BsParams, stream=None):
+        import torch
+        self._torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _vp()
+        _check(_lib.bs_plan(C.byref(params), _vp(stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.N = 0
+        self.nfil = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> BsParams:
+        out = BsParams()
+        _check(_lib.bs_get_params(self._h, C.byref(out)), self._h)
+        return out
+
+    def set_filaments(self, offsets, xyz, gamma):
+        torch = self._torch
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.is_contiguous()
+        assert gamma.is_cuda and gamma.dtype == torch.float64 and gamma.is_contiguous()
+        assert xyz.shape == (int(off[-1]), 3) and gamma.shape == (len(off) - 1,)
+        self._off = off
+        _check(_lib.bs_set_filaments(self._h, len(off) - 1,
+                                     off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     _ptr(xyz), _ptr(gamma)), self._h)
+        self.N = int(off[-1])
+        self.nfil = len(off) - 1
+
+    def _out(self, out):
+        if out is None:
+            out = self._torch.empty((self.N, 3), dtype=self._torch.float64, device="cuda")
+        return out
+
+    def velocity(self, out=None):
+        out = self._out(out)
+        _check(_lib.bs_velocity(self._h, _ptr(out)), self._h)
+        return out
+
+    def velocity_terms(self):
+        t = [self._out(None) for _ in range(5)]
+        _check(_lib.bs_velocity_terms(self._h, *[_ptr(x) for x in t]), self._h)
+        return dict(zip(["local", "short", "long", "self", "ns"], t))
+
+    def energy(self, psi_out=None, want_psi=True):
+        E = C.c_double(0.0)
+        psi = self._out(psi_out) if (want_psi or psi_out is not None) else None
+        _check(_lib.bs_energy(self._h, C.byref(E), _ptr(psi)), self._h)
+        return E.value, psi
+
+    def vorticity_modes(self):
+        K = self.params().K
+        W = 2 * K + 1
+        out = self._torch.empty((K + 1, W, W, 3, 2), dtype=self._torch.float64, device="cuda")
+        _check(_lib.bs_vorticity_modes(self._h, _ptr(out)), self._h)
+        return out
+
+    def geometry(self):
+        torch = self._torch
+        Nq = self.N * self.params().Q
+        qp = torch.empty((Nq, 3), dtype=torch.float64, device="cuda")
+        qc = torch.empty_like(qp)
+        sd = self._out(None); sdd = self._out(None)
+        ell = torch.empty((self.N,), dtype=torch.float64, device="cuda")
+        _check(_lib.bs_geometry(self._h, *[_ptr(x) for x in (qp, qc, sd, sdd, ell)]), self._h)
+        return dict(qpos=qp, qcharge=qc, sdot=sd, sddot=sdd, ell=ell)
+
+    def status(self):
+        _check(_lib.bs_status(self._h), self._h)
+
+    def set_profiling(self, on: bool):
+        _check(_lib.bs_set_profiling(self._h, int(bool(on))), self._h)
+
+    def stage_times(self, reset=False):
+        ms = np.zeros(NSTAGES)
+        cnt = np.zeros(NSTAGES, dtype=np.int64)
+        _check(_lib.bs_stage_times(self._h, ms.ctypes.data_as(C.c_void_p),
+                                   cnt.ctypes.data_as(C.c_void_p), int(reset)), self._h)
+        return {name: (ms[i], int(cnt[i])) for i, name in enumerate(STAGES)}
+
+
+def load_workload(fs, device="cuda"):
+    """Device tensors (xyz, gamma) of a workloads.FilamentSet."""
+    import torch
+    xyz = torch.from_numpy(np.ascontiguousarray(fs.xyz)).to(device)
+    gamma = torch.from_numpy(np.ascontiguousarray(fs.gamma)).to(device)
+    return xyz, gamma

@@ -1,0 +1,524 @@
+// C ABI of libbs.so: parameter resolution, plan and buffer management, and
+// the order of the steps of one velocity / energy evaluation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "bs_internal.h"
+
+namespace bs {
+
+static thread_local std::string g_err = "no error";
+
+int set_error(bs_plan_t p, int code, const std::string &msg) {
+    if (p) p->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+int check_hip(bs_plan_t p, hipError_t e, const char *what) {
+    if (e == hipSuccess) return BS_OK;
+    return set_error(p, e == hipErrorOutOfMemory ? BS_ENOMEM : BS_EDEVICE,
+                     std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Gauss-Legendre rule on [-1, 1] by Newton iteration on the three-term
+// recurrence of the Legendre polynomials; nodes ascending.
+static void legendre_rule(int n, double *x, double *w) {
+    for (int i = 0; i < n; i++) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        // recompute derivative at the converged node
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; k++) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1; p1 = p2;
+        }
+        if (n == 1) { p1 = z; p0 = 1.0; }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+GLRule gl_rule(int Q) {
+    GLRule r{};
+    double x[kMaxQ], w[kMaxQ];
+    if (Q == 1) { x[0] = 0.0; w[0] = 2.0; }
+    else legendre_rule(Q, x, w);
+    for (int i = 0; i < Q; i++) { r.h[i] = 0.5 * (x[i] + 1.0); r.w[i] = 0.5 * w[i]; }
+    return r;
+}
+
+// Host copy of the normalised kernel phi(z) = sinh(zeta s)/(sinh(zeta) s),
+// s = sqrt(1 - z^2) (same normalisation as the device kernel).
+static double kb_phi_host(double z, double zeta) {
+    double s2 = 1.0 - z * z;
+    double den = -std::expm1(-2.0 * zeta);
+    if (s2 <= 0.0) return 2.0 * zeta * std::exp(-zeta) / den;
+    double s = std::sqrt(s2);
+    return std::exp(zeta * (s - 1.0)) * (-std::expm1(-2.0 * zeta * s)) / s / den;
+}
+
+// F(m) = (w/2) int_{-1}^{1} phi(z) cos(pi m w z / n) dz, the transform of the
+// spreading kernel per axis (Poisson summation of the grid sum; App. A).
+// The integrand is analytic on [-1,1], so a 256-point Gauss-Legendre rule is
+// exact to rounding.  (The closed form I0(sqrt(zeta^2 - kappa^2)) of
+// eq:kaiser_bessel_bw is the transform of the kernel continued beyond
+// |z| = 1 and differs from the truncated kernel's by ~e^{-zeta}.)
+static void kernel_ft_table(int K, int w, int n, double zeta, double *F) {
+    const int nq = 256;
+    std::vector<double> x(nq), wt(nq), ph(nq);
+    legendre_rule(nq, x.data(), wt.data());
+    for (int i = 0; i < nq; i++) ph[i] = kb_phi_host(x[i], zeta);
+    for (int m = 0; m <= K; m++) {
+        double kap = kPi * m * w / n, s = 0.0;
+        for (int i = 0; i < nq; i++) s += wt[i] * ph[i] * std::cos(kap * x[i]);
+        F[m] = 0.5 * w * s;
+    }
+}
+
+template <typename T>
+static int ensure(bs_plan_t p, DBuf &b, size_t count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (b.bytes >= bytes) return BS_OK;
+    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) { b.p = nullptr; return check_hip(p, e, "hipMalloc"); }
+    b.bytes = bytes;
+    return BS_OK;
+}
+
+static void release(DBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+__global__ void k_fill_f64(double *p, size_t n, double v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static void fill_f64(bs_plan_t p, double *ptr, size_t n, double v) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p->stream, ptr,
+                       n, v);
+}
+
+static int launch_status(bs_plan_t p, const char *what) {
+    return check_hip(p, hipGetLastError(), what);
+}
+
+// Table 1 of the paper: nominal tolerance -> beta.
+static const double kTabTol[7] = {1e-3, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12, 1e-14};
+static const double kTabBeta[7] = {2.0, 2.5, 3.5, 4.0, 4.5, 5.0, 5.5};
+
+static double beta_from_tol(double tol) {
+    for (int i = 0; i < 7; i++)
+        if (kTabTol[i] <= tol * (1.0 + 1e-9)) return kTabBeta[i];
+    return kTabBeta[6];
+}
+
+static int width_from_tol(double tol) {
+    double pe = -std::log10(tol);
+    int w = (int)std::ceil(pe / 0.9 - 1e-9) + 1;
+    return std::min(kMaxW, std::max(kMinW, w));
+}
+
+int resolve(const bs_params *in, bs_params *out) {
+    if (!in || !out) return set_error(nullptr, BS_EINVAL, "null parameter pointer");
+    bs_params r = *in;
+    auto bad = [](const char *m) { return set_error(nullptr, BS_EINVAL, m); };
+    if (!(std::isfinite(r.L) && r.L > 0)) return bad("L must be positive");
+    if (!(std::isfinite(r.a) && r.a > 0 && r.a < r.L)) return bad("a must be in (0, L)");
+    if (!std::isfinite(r.delta)) return bad("delta must be finite");
+    if (!(r.tol > 0 && r.tol <= 0.5)) return bad("tol must be in (0, 0.5]");
+    if (r.grid_n < 16 || r.grid_n % 4 != 0 || r.grid_n > 1024)
+        return bad("grid_n must be a multiple of 4 in [16, 1024]");
+    if (r.sigma == 0) r.sigma = 1.5;
+    if (!(r.sigma > 1.0 && r.sigma <= 4.0)) return bad("sigma must be in (1, 4]");
+    if (r.Q == 0) r.Q = 2;
+    if (r.Q < 1 || r.Q > kMaxQ) return bad("Q must be in 1..4");
+    if (r.spline_order == 0) r.spline_order = 4;
+    if (r.spline_order != 4) return bad("only cubic splines (spline_order 4) are built");
+    if (r.precision != BS_FP64 && r.precision != BS_FP32_MIXED) return bad("unknown precision");
+    if (r.ns_mode < BS_NS_OFF || r.ns_mode > BS_NS_MLP) return bad("unknown ns_mode");
+    if (r.ns_eta == 0) r.ns_eta = 1.0;
+    if (!(r.ns_eta > 0)) return bad("ns_eta must be positive");
+    if (r.beta == 0) r.beta = beta_from_tol(r.tol);
+    if (!(r.beta > 0)) return bad("beta must be positive");
+    if (r.w == 0) r.w = width_from_tol(r.tol);
+    if (r.w < kMinW || r.w > kMaxW) return bad("w must be in 4..16");
+    if (r.w > r.grid_n) return bad("w must not exceed grid_n");
+    int M = (int)std::floor(r.grid_n / r.sigma + 1e-9);
+    r.K = (M - 1) / 2;
+    if (r.K < 1) return bad("grid too small for one retained mode");
+    bool derived = (in->alpha == 0 && in->rcut == 0);
+    if (r.alpha == 0) r.alpha = r.K * (2.0 * kPi / r.L) / (2.0 * r.beta);
+    if (!(r.alpha > 0)) return bad("alpha must be positive");
+    if (r.rcut == 0) r.rcut = r.beta / r.alpha;
+    if (!(r.rcut > 0)) return bad("rcut must be positive");
+    if (r.rcut > 0.5 * r.L * (1.0 + 1e-12)) {
+        if (derived)
+            return set_error(nullptr, BS_ETOL,
+                             "tolerance needs r_c = beta/alpha > L/2 on this grid; use a larger "
+                             "grid_n");
+        return set_error(nullptr, BS_EMINIMG, "rcut > L/2 violates the minimum-image convention");
+    }
+    r.zeta = 0.995 * r.w * kPi * (1.0 - 1.0 / (2.0 * r.sigma));
+    double kap_max = kPi * r.K * r.w / r.grid_n;
+    if (kap_max >= r.zeta)
+        return set_error(nullptr, BS_EKB, "retained modes beyond the kernel's band (raise sigma)");
+    int nc = (int)std::floor(r.L / r.rcut);
+    if (nc < 3) nc = 1;
+    if (nc > 128) nc = 128;
+    r.ncell = nc;
+    *out = r;
+    return BS_OK;
+}
+
+void stage_collect(bs_plan_t p) {
+    if (!p->prof) return;
+    (void)hipStreamSynchronize(p->stream);
+    for (int s = 0; s < BS_NSTAGES; s++) {
+        if (!p->ev_used[s]) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p->ev_beg[s], p->ev_end[s]) == hipSuccess) {
+            p->stage_ms[s] += ms;
+            p->stage_cnt[s] += 1;
+        }
+        p->ev_used[s] = false;
+    }
+}
+
+}  // namespace bs
+
+using namespace bs;
+
+extern "C" {
+
+int bs_set_profiling(bs_plan_t P, int enable) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (enable && !P->ev_beg[0]) {
+        for (int s = 0; s < BS_NSTAGES; s++) {
+            int rc = check_hip(P, hipEventCreate(&P->ev_beg[s]), "hipEventCreate");
+            if (!rc) rc = check_hip(P, hipEventCreate(&P->ev_end[s]), "hipEventCreate");
+            if (rc) return rc;
+        }
+    }
+    P->prof = enable != 0;
+    return BS_OK;
+}
+
+int bs_stage_times(bs_plan_t P, double *ms, int64_t *counts, int reset) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    for (int s = 0; s < BS_NSTAGES; s++) {
+        if (ms) ms[s] = P->stage_ms[s];
+        if (counts) counts[s] = P->stage_cnt[s];
+        if (reset) { P->stage_ms[s] = 0.0; P->stage_cnt[s] = 0; }
+    }
+    return BS_OK;
+}
+
+int bs_resolve_params(const bs_params *p, bs_params *out) { return resolve(p, out); }
+
+const char *bs_last_error(bs_plan_t plan) { return plan ? plan->err.c_str() : g_err.c_str(); }
+
+int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
+    if (!out) return set_error(nullptr, BS_EINVAL, "null output handle");
+    *out = nullptr;
+    bs_params r;
+    int rc = resolve(p, &r);
+    if (rc) return rc;
+    if (r.ns_mode == BS_NS_MLP)
+        return set_error(nullptr, BS_EINVAL, "BS_NS_MLP is not available in this build");
+    bs_plan_t P = new bs_plan_s();
+    P->prm = r;
+    P->stream = (hipStream_t)hip_stream;
+    P->fp32 = (r.precision == BS_FP32_MIXED);
+    P->real_size = P->fp32 ? 4 : 8;
+    P->n = r.grid_n;
+    P->T = (P->n % 8 == 0) ? 8 : 4;
+    P->NT = P->n / P->T;
+    P->nc = r.ncell;
+    P->Q = r.Q;
+    (void)hipGetDevice(&P->device);
+    const size_t n = (size_t)P->n, n3 = n * n * n, nc = n * n * (n / 2 + 1);
+    auto fail = [&](int code) {
+        g_err = P->err;
+        bs_destroy(P);
+        return code;
+    };
+    if ((rc = ensure<char>(P, P->grid, 3 * n3 * P->real_size))) return fail(rc);
+    if ((rc = ensure<char>(P, P->spec, 3 * nc * 2 * P->real_size))) return fail(rc);
+    if ((rc = ensure<double>(P, P->deconv, 2 * (r.K + 1)))) return fail(rc);
+    if ((rc = ensure<int>(P, P->d_status, 1))) return fail(rc);
+    if ((rc = ensure<int>(P, P->red_tmp, 8192))) return fail(rc);
+    if ((rc = check_hip(P, hipMemsetAsync(P->d_status.p, 0, sizeof(int), P->stream), "memset")))
+        return fail(rc);
+    // deconvolution table: [1/F(m)] then [1/F(m)^2], m = 0..K
+    std::vector<double> F(r.K + 1), tab(2 * (r.K + 1));
+    kernel_ft_table(r.K, r.w, P->n, r.zeta, F.data());
+    for (int m = 0; m <= r.K; m++) {
+        tab[m] = 1.0 / F[m];
+        tab[r.K + 1 + m] = 1.0 / (F[m] * F[m]);
+    }
+    if ((rc = check_hip(P, hipMemcpy(P->deconv.p, tab.data(), tab.size() * sizeof(double),
+                                     hipMemcpyHostToDevice), "copy table")))
+        return fail(rc);
+    // FFT plans: 3 transforms of n^3 (real) <-> n^2 (n/2+1) (complex)
+    int dims[3] = {P->n, P->n, P->n};
+    size_t ws = 0;
+    if (hipfftCreate(&P->fft_fwd) != HIPFFT_SUCCESS || hipfftCreate(&P->fft_inv) != HIPFFT_SUCCESS)
+        return fail(set_error(P, BS_EDEVICE, "hipfftCreate failed"));
+    hipfftType tf = P->fp32 ? HIPFFT_R2C : HIPFFT_D2Z, ti = P->fp32 ? HIPFFT_C2R : HIPFFT_Z2D;
+    if (hipfftMakePlanMany(P->fft_fwd, 3, dims, nullptr, 1, (int)n3, nullptr, 1, (int)nc, tf, 3,
+                           &ws) != HIPFFT_SUCCESS ||
+        hipfftMakePlanMany(P->fft_inv, 3, dims, nullptr, 1, (int)nc, nullptr, 1, (int)n3, ti, 3,
+                           &ws) != HIPFFT_SUCCESS)
+        return fail(set_error(P, BS_EDEVICE, "hipfftMakePlanMany failed"));
+    if (hipfftSetStream(P->fft_fwd, P->stream) != HIPFFT_SUCCESS ||
+        hipfftSetStream(P->fft_inv, P->stream) != HIPFFT_SUCCESS)
+        return fail(set_error(P, BS_EDEVICE, "hipfftSetStream failed"));
+    *out = P;
+    return BS_OK;
+}
+
+int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const double *xyz,
+                     const double *gamma) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (nfil < 1 || !offsets || !xyz || !gamma)
+        return set_error(P, BS_EINVAL, "need nfil >= 1 and non-null offsets, xyz, gamma");
+    if (offsets[0] != 0) return set_error(P, BS_EINVAL, "offsets[0] must be 0");
+    int64_t maxn = 0;
+    for (int64_t f = 0; f < nfil; f++) {
+        int64_t c = offsets[f + 1] - offsets[f];
+        if (c < 3) return set_error(P, BS_EINVAL, "every filament needs at least 3 nodes");
+        maxn = std::max(maxn, c);
+    }
+    const int64_t N = offsets[nfil], Nq = N * P->Q;
+    if (Nq >= ((int64_t)1 << 31) / 4) return set_error(P, BS_EINVAL, "too many nodes");
+    bool same = P->have_filaments && P->nfil == nfil &&
+                std::equal(offsets, offsets + nfil + 1, P->off_host.begin());
+    int rc;
+    const int ntiles = P->NT * P->NT * P->NT, nc3 = P->nc * P->nc * P->nc;
+    const size_t rs = P->real_size;
+    if (!same) {
+        P->have_filaments = false;
+        if ((rc = ensure<int>(P, P->d_off, nfil + 1)) || (rc = ensure<int>(P, P->d_fil, N)) ||
+            (rc = ensure<double>(P, P->d_gamma, nfil)) || (rc = ensure<double>(P, P->d_x, 3 * N)) ||
+            (rc = ensure<double>(P, P->d_dtau, N)) || (rc = ensure<double>(P, P->d_D, 3 * N)) ||
+            (rc = ensure<double>(P, P->d_sdd, 3 * N)) || (rc = ensure<double>(P, P->d_ell, N)) ||
+            (rc = ensure<double>(P, P->d_qpos, 3 * Nq)) ||
+            (rc = ensure<double>(P, P->d_qchg, 3 * Nq)) || (rc = ensure<double>(P, P->tmp3, 3 * N)) ||
+            (rc = ensure<int>(P, P->sp_key, Nq)) || (rc = ensure<int>(P, P->sp_cnt, ntiles + 1)) ||
+            (rc = ensure<int>(P, P->sp_start, ntiles + 1)) ||
+            (rc = ensure<int>(P, P->sp_fill, ntiles + 1)) || (rc = ensure<int>(P, P->sp_perm, Nq)) ||
+            (rc = ensure<int4>(P, P->sp_base, Nq)) ||
+            (rc = ensure<char>(P, P->sp_ker, Nq * 3 * P->prm.w * rs)) ||
+            (rc = ensure<char>(P, P->sp_q, Nq * 4 * rs)) || (rc = ensure<int>(P, P->pq_key, Nq)) ||
+            (rc = ensure<int>(P, P->pq_cnt, nc3 + 1)) || (rc = ensure<int>(P, P->pq_start, nc3 + 1)) ||
+            (rc = ensure<int>(P, P->pq_fill, nc3 + 1)) || (rc = ensure<int>(P, P->pq_perm, Nq)) ||
+            (rc = ensure<double4>(P, P->pq_pos, Nq)) || (rc = ensure<char>(P, P->pq_chg, Nq * 4 * rs)) ||
+            (rc = ensure<int>(P, P->pq_seg, Nq)) || (rc = ensure<int>(P, P->nd_key, N)) ||
+            (rc = ensure<int>(P, P->nd_cnt, nc3 + 1)) || (rc = ensure<int>(P, P->nd_start, nc3 + 1)) ||
+            (rc = ensure<int>(P, P->nd_fill, nc3 + 1)) || (rc = ensure<int>(P, P->nd_perm, N)))
+            return rc;
+        if (maxn > 512 && (rc = ensure<double>(P, P->spline_tmp, 12 * N))) return rc;
+        std::vector<int> off32(nfil + 1), fil32(N);
+        for (int64_t f = 0; f <= nfil; f++) off32[f] = (int)offsets[f];
+        for (int64_t f = 0; f < nfil; f++)
+            for (int64_t j = offsets[f]; j < offsets[f + 1]; j++) fil32[j] = (int)f;
+        if ((rc = check_hip(P, hipMemcpyAsync(P->d_off.p, off32.data(), sizeof(int) * (nfil + 1),
+                                              hipMemcpyHostToDevice, P->stream), "copy offsets")) ||
+            (rc = check_hip(P, hipMemcpyAsync(P->d_fil.p, fil32.data(), sizeof(int) * N,
+                                              hipMemcpyHostToDevice, P->stream), "copy fil")))
+            return rc;
+        // the host vectors die at return: wait for the copies
+        if ((rc = check_hip(P, hipStreamSynchronize(P->stream), "sync"))) return rc;
+        P->off_host.assign(offsets, offsets + nfil + 1);
+        P->nfil = nfil;
+        P->N = N;
+        P->Nq = Nq;
+        P->max_fil_nodes = maxn;
+    }
+    if ((rc = check_hip(P, hipMemcpyAsync(P->d_x.p, xyz, sizeof(double) * 3 * N,
+                                          hipMemcpyDeviceToDevice, P->stream), "copy xyz")) ||
+        (rc = check_hip(P, hipMemcpyAsync(P->d_gamma.p, gamma, sizeof(double) * nfil,
+                                          hipMemcpyDeviceToDevice, P->stream), "copy gamma")))
+        return rc;
+    stage_begin(P, 0);
+    launch_chord(P);
+    launch_spline(P);
+    launch_geometry(P);
+    stage_end(P, 0);
+    stage_begin(P, 1);
+    build_bins(P);
+    stage_end(P, 1);
+    if ((rc = launch_status(P, "geometry kernels"))) return rc;
+    P->have_filaments = true;
+    stage_collect(P);
+    return BS_OK;
+}
+
+static int long_range(bs_plan_t P, int psi, double *out) {
+    int rc;
+    stage_begin(P, 3);
+    launch_spread(P);
+    stage_end(P, 3);
+    stage_begin(P, 4);
+    if ((rc = fft_forward(P))) return rc;
+    stage_end(P, 4);
+    stage_begin(P, 5);
+    launch_spectral(P, psi);
+    stage_end(P, 5);
+    stage_begin(P, 6);
+    if ((rc = fft_inverse(P))) return rc;
+    stage_end(P, 6);
+    stage_begin(P, 7);
+    launch_interp(P, out);
+    stage_end(P, 7);
+    return launch_status(P, "long-range kernels");
+}
+
+int bs_velocity(bs_plan_t P, double *v_out) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
+    if (!v_out) return set_error(P, BS_EINVAL, "null output");
+    stage_begin(P, 2);
+    launch_local_self(P, LS_VLOCAL | LS_VSELF | LS_ASSIGN, 1.0, v_out);
+    stage_end(P, 2);
+    int rc = long_range(P, 0, v_out);
+    if (rc) return rc;
+    stage_begin(P, 8);
+    launch_pairs(P, 0, v_out);
+    stage_end(P, 8);
+    if ((rc = launch_status(P, "pair kernel"))) return rc;
+    stage_collect(P);
+    return BS_OK;
+}
+
+int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_long,
+                      double *v_self, double *v_ns) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
+    int rc;
+    const size_t n3 = 3 * (size_t)P->N;
+    if (v_local) launch_local_self(P, LS_VLOCAL | LS_ASSIGN, 1.0, v_local);
+    if (v_self) launch_local_self(P, LS_VSELF | LS_ASSIGN, 1.0, v_self);
+    if (v_long) {
+        fill_f64(P, v_long, n3, 0.0);
+        if ((rc = long_range(P, 0, v_long))) return rc;
+    }
+    if (v_short) {
+        fill_f64(P, v_short, n3, 0.0);
+        launch_pairs(P, 0, v_short);
+    }
+    if (v_ns) fill_f64(P, v_ns, n3, 0.0);
+    return launch_status(P, "velocity terms");
+}
+
+int bs_energy(bs_plan_t P, double *E_out, double *psi_out) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
+    double *psi = psi_out ? psi_out : (double *)P->tmp3.p;
+    launch_local_self(P, LS_VLOCAL | LS_VSELF | LS_PSI | LS_ASSIGN, 1.0, psi);
+    int rc = long_range(P, 1, psi);
+    if (rc) return rc;
+    launch_pairs(P, 1, psi);
+    const int nb = 512;
+    double *partial = (double *)P->red_tmp.p;   // nb + 1 doubles
+    launch_energy(P, psi, partial, nb);
+    if ((rc = launch_status(P, "energy kernels"))) return rc;
+    if (E_out) {
+        if ((rc = check_hip(P, hipMemcpyAsync(E_out, partial + nb, sizeof(double),
+                                              hipMemcpyDeviceToHost, P->stream), "copy E")))
+            return rc;
+    }
+    return check_hip(P, hipStreamSynchronize(P->stream), "sync");
+}
+
+int bs_vorticity_modes(bs_plan_t P, double *out) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
+    if (!out) return set_error(P, BS_EINVAL, "null output");
+    launch_spread(P);
+    int rc = fft_forward(P);
+    if (rc) return rc;
+    launch_modes(P, out);
+    return launch_status(P, "mode extraction");
+}
+
+int bs_geometry(bs_plan_t P, double *qpos, double *qcharge, double *sdot, double *sddot,
+                double *ell) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
+    const size_t N = P->N, Nq = P->Nq;
+    struct { void *dst; const void *src; size_t bytes; } cp[5] = {
+        {qpos, P->d_qpos.p, 3 * Nq * 8}, {qcharge, P->d_qchg.p, 3 * Nq * 8},
+        {sdot, P->d_D.p, 3 * N * 8}, {sddot, P->d_sdd.p, 3 * N * 8}, {ell, P->d_ell.p, N * 8}};
+    for (auto &c : cp) {
+        if (!c.dst) continue;
+        int rc = check_hip(P, hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice,
+                                             P->stream), "copy geometry");
+        if (rc) return rc;
+    }
+    return BS_OK;
+}
+
+int bs_status(bs_plan_t P) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    int st = 0, rc;
+    if ((rc = check_hip(P, hipMemcpyAsync(&st, P->d_status.p, sizeof(int), hipMemcpyDeviceToHost,
+                                          P->stream), "read status")) ||
+        (rc = check_hip(P, hipStreamSynchronize(P->stream), "sync")))
+        return rc;
+    if (st) {
+        (void)hipMemsetAsync(P->d_status.p, 0, sizeof(int), P->stream);
+        (void)hipStreamSynchronize(P->stream);
+        return set_error(P, BS_EINVAL, "non-finite node position or zero-length segment");
+    }
+    return BS_OK;
+}
+
+int bs_get_params(bs_plan_t P, bs_params *resolved) {
+    if (!P || !resolved) return set_error(P, BS_EINVAL, "null argument");
+    *resolved = P->prm;
+    return BS_OK;
+}
+
+int bs_destroy(bs_plan_t P) {
+    if (!P) return BS_OK;
+    (void)hipStreamSynchronize(P->stream);
+    for (int s = 0; s < BS_NSTAGES; s++) {
+        if (P->ev_beg[s]) (void)hipEventDestroy(P->ev_beg[s]);
+        if (P->ev_end[s]) (void)hipEventDestroy(P->ev_end[s]);
+    }
+    if (P->fft_fwd) hipfftDestroy(P->fft_fwd);
+    if (P->fft_inv) hipfftDestroy(P->fft_inv);
+    DBuf *all[] = {&P->grid, &P->spec, &P->deconv, &P->fftwork, &P->d_off, &P->d_fil,
+                   &P->d_gamma, &P->d_x, &P->d_dtau, &P->d_D, &P->d_sdd, &P->d_ell,
+                   &P->d_qpos, &P->d_qchg, &P->d_status, &P->sp_key, &P->sp_cnt, &P->sp_start,
+                   &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
+                   &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
+                   &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
+                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3};
+    for (DBuf *b : all) release(*b);
+    delete P;
+    return BS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Device helpers shared by the binning, NUFFT and pair kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace bs {
+
+// Position folded into [0, L).  Anything that does not land there (NaN,
+// infinities, magnitudes where the fold loses all digits) maps to 0, so that
+// every index derived from the result stays inside its array; such input is
+// reported through the plan's status word by the chord-length kernel.
+__device__ __forceinline__ double wrap_box(double v, double L) {
+    double r = v - L * floor(v / L);
+    if (r >= L) r -= L;
+    return (r >= 0.0 && r < L) ? r : 0.0;
+}
+
+// Stencil base per axis: i0 = floor(u - w/2) + 1 with u = x/h, x wrapped
+// to [0, L); the support is i0 .. i0 + w - 1 (mod n).
+__device__ __forceinline__ int stencil_base(double xw, double inv_h, int w, int n, double *frac) {
+    double u = xw * inv_h;
+    double i0 = floor(u - 0.5 * w) + 1.0;
+    *frac = u - i0;
+    int b = (int)i0 % n;
+    return b < 0 ? b + n : b;
+}
+
+// Backward Kaiser-Bessel kernel, normalised to 1 at the centre:
+//   phi(z) = sinh(zeta sqrt(1-z^2)) / (sinh(zeta) sqrt(1-z^2)),  |z| <= 1
+// (eq:kaiser_bessel_bw up to the constant pi/sinh(zeta), which the
+// deconvolution table carries).  Written as
+//   exp(zeta (s-1)) * (1 - exp(-2 zeta s)) / ((1 - exp(-2 zeta)) s)
+// with 1 - exp(-y) = -expm1(-y) to keep digits as s -> 0.
+__device__ __forceinline__ double kb_phi(double z, double zeta, double inv_den) {
+    double s2 = 1.0 - z * z;
+    if (s2 <= 0.0) return 2.0 * zeta * exp(-zeta) * inv_den;
+    double s = sqrt(s2);
+    return exp(zeta * (s - 1.0)) * (-expm1(-2.0 * zeta * s)) / s * inv_den;
+}
+
+
+__device__ __forceinline__ int next_node_d(const int *off, const int *fil, int j) {
+    int f = fil[j];
+    return (j + 1 < off[f + 1]) ? j + 1 : off[f];
+}
+__device__ __forceinline__ int prev_node_d(const int *off, const int *fil, int j) {
+    int f = fil[j];
+    return (j > off[f]) ? j - 1 : off[f + 1] - 1;
+}
+
+}  // namespace bs

@@ -1,0 +1,129 @@
+// Internal declarations of libbs.so (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bs.h"
+
+namespace bs {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kMaxQ = 4;
+constexpr int kMinW = 4, kMaxW = 16;
+
+// Gauss-Legendre nodes h_i in [0,1] and weights w_i (sum 1) for Q = 1..4.
+struct GLRule {
+    double h[kMaxQ];
+    double w[kMaxQ];
+};
+GLRule gl_rule(int Q);
+
+// Growable device buffer.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Geometry;  // device views, see geometry.hip
+
+}  // namespace bs
+
+struct bs_plan_s {
+    bs_params prm{};        // resolved parameters
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    int fp32 = 0;           // precision == BS_FP32_MIXED
+    size_t real_size = 8;   // bytes of a grid real
+
+    // grid and FFT
+    int n = 0;              // grid points per axis
+    int T = 8;              // spread tile edge (cells)
+    int NT = 0;             // tiles per axis
+    hipfftHandle fft_fwd = 0, fft_inv = 0;
+    bs::DBuf grid;          // [3][n][n][n] real
+    bs::DBuf spec;          // [3][n][n][n/2+1] complex
+    bs::DBuf deconv;        // [K+1] float64: 1 / F(m)^2 per axis
+    bs::DBuf fftwork;
+
+    // short-range cell list
+    int nc = 1;             // cells per axis
+
+    // filaments
+    int64_t nfil = 0, N = 0, Nq = 0;
+    int Q = 2;
+    std::vector<int64_t> off_host;
+    bool have_filaments = false;
+    bs::DBuf d_off, d_fil, d_gamma;            // int32 [nfil+1], int32 [N], f64 [nfil]
+    bs::DBuf d_x;                              // f64 [N][3] private copy of nodes
+    bs::DBuf d_dtau, d_D, d_sdd, d_ell;        // node geometry
+    bs::DBuf d_qpos, d_qchg;                   // f64 [Nq][3]
+    bs::DBuf d_status;                         // int32 device status word
+    // spread binning
+    bs::DBuf sp_key, sp_cnt, sp_start, sp_fill, sp_perm;
+    bs::DBuf sp_base, sp_ker, sp_q;
+    // pair binning
+    bs::DBuf pq_key, pq_cnt, pq_start, pq_fill, pq_perm;
+    bs::DBuf pq_pos, pq_chg, pq_seg;
+    bs::DBuf nd_key, nd_cnt, nd_start, nd_fill, nd_perm;
+    // scan scratch, reductions, spline scratch (filaments over 512 nodes)
+    bs::DBuf scan_tmp, red_tmp, spline_tmp;
+    int64_t max_fil_nodes = 0;
+    // terms (for velocity terms / energy)
+    bs::DBuf tmp3;                             // f64 [N][3]
+    // per-stage timing (diagnostics)
+    bool prof = false;
+    hipEvent_t ev_beg[BS_NSTAGES] = {}, ev_end[BS_NSTAGES] = {};
+    bool ev_used[BS_NSTAGES] = {};
+    double stage_ms[BS_NSTAGES] = {};
+    int64_t stage_cnt[BS_NSTAGES] = {};
+};
+
+namespace bs {
+
+int set_error(bs_plan_t p, int code, const std::string &msg);
+int check_hip(bs_plan_t p, hipError_t e, const char *what);
+
+// geometry.hip
+void launch_chord(bs_plan_t p);
+void launch_spline(bs_plan_t p);
+void launch_geometry(bs_plan_t p);
+// mode bits for launch_local_self
+enum { LS_VLOCAL = 1, LS_VSELF = 2, LS_PSI = 4, LS_ASSIGN = 8 };
+void launch_local_self(bs_plan_t p, int mode, double sign, double *out);
+
+// binning.hip
+void exclusive_scan(bs_plan_t p, const int *in, int *out, int n);
+void build_bins(bs_plan_t p);
+
+// nufft.hip
+void launch_spread(bs_plan_t p);
+void launch_spectral(bs_plan_t p, int psi);
+void launch_interp(bs_plan_t p, double *out);
+void launch_modes(bs_plan_t p, double *out);
+int fft_forward(bs_plan_t p);
+int fft_inverse(bs_plan_t p);
+
+// pairs.hip
+void launch_pairs(bs_plan_t p, int psi, double *out);
+
+// energy.hip
+void launch_energy(bs_plan_t p, const double *psi, double *partial, int nblocks);
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// stage timing: record begin/end events on the plan stream when profiling
+inline void stage_begin(bs_plan_t p, int s) {
+    if (p->prof) { (void)hipEventRecord(p->ev_beg[s], p->stream); p->ev_used[s] = true; }
+}
+inline void stage_end(bs_plan_t p, int s) {
+    if (p->prof) (void)hipEventRecord(p->ev_end[s], p->stream);
+}
+void stage_collect(bs_plan_t p);
+
+}  // namespace bs

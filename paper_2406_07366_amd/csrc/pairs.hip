@@ -1,0 +1,157 @@
+// Short-range part (Sec. 3.2, eq:velocity_shortrange and
+// eq:streamfunction_shortrange) as quadrature sums over cell lists, and the
+// energy reduction (eq:kinetic_energy_streamfunction).
+//
+// One thread per target node, nodes processed in cell order so that a
+// wavefront reads the same few cells.  For each quadrature point of the 27
+// surrounding cells (or of every cell when fewer than 3 fit along an axis):
+// r = s_q - s_i by minimum image (formed in float64), skip the 2Q points of
+// the two segments adjacent to the node, keep r < r_c, and add
+//   v:   g_sr(r) (r x q) / r^3,  g_sr = erfc(alpha r) + (2 alpha r/sqrt(pi)) e^{-alpha^2 r^2}
+//   psi: erfc(alpha r) q / r
+// times 1/(4 pi).  R = float in the mixed mode (float32 accumulation).
+#include "bs_internal.h"
+#include "bs_device.h"
+
+namespace bs {
+
+template <typename R, bool PSI>
+__global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double rc, double alpha,
+                                               const int *__restrict__ nperm,
+                                               const double *__restrict__ x,
+                                               const int *__restrict__ off,
+                                               const int *__restrict__ fil,
+                                               const int *__restrict__ cstart,
+                                               const double4 *__restrict__ spos,
+                                               const R *__restrict__ schg,
+                                               const int *__restrict__ sseg,
+                                               double *__restrict__ out) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const int o = nperm[t];
+    const int ip = prev_node_d(off, fil, o);
+    const double xi0 = x[3 * o], xi1 = x[3 * o + 1], xi2 = x[3 * o + 2];
+    const double invL = 1.0 / L;
+    int c[3];
+    {
+        double w0 = wrap_box(xi0, L), w1 = wrap_box(xi1, L), w2 = wrap_box(xi2, L);
+        double ws[3] = {w0, w1, w2};
+        for (int q = 0; q < 3; q++) {
+            int v = (int)(ws[q] * invL * nc);
+            c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+        }
+    }
+    const R rc2 = (R)(rc * rc), a = (R)alpha;
+    const R two_over_sqrtpi = (R)1.12837916709551257389615890312154517;
+    R acc0 = 0, acc1 = 0, acc2 = 0;
+    const int span = nc >= 3 ? 1 : 0;
+    for (int dz = -span; dz <= span; dz++) {
+        int cz = c[2] + dz; cz = cz < 0 ? cz + nc : (cz >= nc ? cz - nc : cz);
+        for (int dy = -span; dy <= span; dy++) {
+            int cy = c[1] + dy; cy = cy < 0 ? cy + nc : (cy >= nc ? cy - nc : cy);
+            for (int dx = -span; dx <= span; dx++) {
+                int cx = c[0] + dx; cx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
+                int cell = (cz * nc + cy) * nc + cx;
+                int s = cstart[cell], e = cstart[cell + 1];
+                for (int p = s; p < e; p++) {
+                    int sg = sseg[p];
+                    if (sg == o || sg == ip) continue;
+                    double4 sp = spos[p];
+                    double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
+                    rx -= L * rint(rx * invL);
+                    ry -= L * rint(ry * invL);
+                    rz -= L * rint(rz * invL);
+                    R fx = (R)rx, fy = (R)ry, fz = (R)rz;
+                    R r2 = fx * fx + fy * fy + fz * fz;
+                    if (!(r2 < rc2) || r2 == (R)0) continue;
+                    R rr = sqrt(r2);
+                    R ar = a * rr;
+                    R ec = erfc(ar);
+                    const R *qq = schg + 4 * (size_t)p;
+                    R q0 = qq[0], q1 = qq[1], q2 = qq[2];
+                    if (PSI) {
+                        R f = ec / rr;
+                        acc0 += f * q0; acc1 += f * q1; acc2 += f * q2;
+                    } else {
+                        R g = ec + two_over_sqrtpi * ar * exp(-ar * ar);
+                        R f = g / (r2 * rr);
+                        acc0 += f * (fy * q2 - fz * q1);
+                        acc1 += f * (fz * q0 - fx * q2);
+                        acc2 += f * (fx * q1 - fy * q0);
+                    }
+                }
+            }
+        }
+    }
+    const double inv4pi = 1.0 / (4.0 * kPi);
+    out[3 * o] += (double)acc0 * inv4pi;
+    out[3 * o + 1] += (double)acc1 * inv4pi;
+    out[3 * o + 2] += (double)acc2 * inv4pi;
+}
+
+void launch_pairs(bs_plan_t p, int psi, double *out) {
+    const int N = (int)p->N;
+    dim3 grid(ceil_div(N, 256)), block(256);
+    const double L = p->prm.L, rc = p->prm.rcut, alpha = p->prm.alpha;
+    const int *nperm = (const int *)p->nd_perm.p, *off = (const int *)p->d_off.p,
+              *fil = (const int *)p->d_fil.p, *cs = (const int *)p->pq_start.p,
+              *seg = (const int *)p->pq_seg.p;
+    const double *x = (const double *)p->d_x.p;
+    const double4 *sp = (const double4 *)p->pq_pos.p;
+    if (p->fp32) {
+        const float *q = (const float *)p->pq_chg.p;
+        if (psi) hipLaunchKernelGGL((k_pairs<float, true>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        else hipLaunchKernelGGL((k_pairs<float, false>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+    } else {
+        const double *q = (const double *)p->pq_chg.p;
+        if (psi) hipLaunchKernelGGL((k_pairs<double, true>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        else hipLaunchKernelGGL((k_pairs<double, false>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+    }
+}
+
+// ------------------------------------------------------------------ energy
+// Partial sums of Gamma_l psi_j . sdot_j (dtau_{j-1} + dtau_j) / 2 (nodal
+// trapezoid in tau); a second pass adds the block sums in a fixed order.
+constexpr int kRedBlock = 256;
+
+__global__ void k_energy_partial(int N, const double *__restrict__ psi,
+                                 const double *__restrict__ D, const double *__restrict__ dtau,
+                                 const int *__restrict__ off, const int *__restrict__ fil,
+                                 const double *__restrict__ gamma, double *__restrict__ partial) {
+    __shared__ double sh[kRedBlock];
+    double s = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+        int jp = prev_node_d(off, fil, j);
+        double w = 0.5 * (dtau[jp] + dtau[j]);
+        s += gamma[fil[j]] * w *
+             (psi[3 * j] * D[3 * j] + psi[3 * j + 1] * D[3 * j + 1] + psi[3 * j + 2] * D[3 * j + 2]);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_energy_final(int nb, double scale, const double *__restrict__ partial,
+                               double *__restrict__ e) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; b++) s += partial[b];
+        *e = s * scale;
+    }
+}
+
+void launch_energy(bs_plan_t p, const double *psi, double *partial, int nblocks) {
+    double L = p->prm.L;
+    hipLaunchKernelGGL(k_energy_partial, dim3(nblocks), dim3(kRedBlock), 0, p->stream, (int)p->N,
+                       psi, (const double *)p->d_D.p, (const double *)p->d_dtau.p,
+                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
+                       (const double *)p->d_gamma.p, partial);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, p->stream, nblocks,
+                       1.0 / (2.0 * L * L * L), partial, partial + nblocks);
+}
+
+}  // namespace bs

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol of include/bs.h, and derives its parameters as the header states."""
+import math
+import os
+import re
+import json
+
+import pytest
+
+from paper_2406_07366_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "bs.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(bs_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 10
+    lib = B.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTED) == sorted(names)
+
+
+def test_params_struct_matches_header_field_order():
+    src = open(os.path.join(ROOT, "include", "bs.h")).read()
+    body = src[src.index("typedef struct {"):src.index("} bs_params;")]
+    fields = re.findall(r"^\s*(?:double|int|const void \*)\s*(\w+)", body, re.M)
+    assert fields == [f for f, _ in B.BsParams._fields_]
+
+
+def _table1():
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "table1_parameters.json")))
+    return d["rows"]
+
+
+@pytest.mark.parametrize("row", _table1())
+def test_beta_and_width_follow_table1(row):
+    """Sec. 5.3, Table 1: beta and w per nominal tolerance (sigma = 1.5).
+    Width rule ceil(-log10(tol)/0.9)+1 reproduces the table for 1e-4..1e-8."""
+    tol, beta, _, sigma, w = row[:5]
+    r = B.resolve_params(B.make_params(L=2 * math.pi, a=1e-6, tol=tol, grid_n=512))
+    assert r.beta == beta
+    assert r.sigma == sigma
+    if 1e-8 <= tol <= 1e-4:
+        assert r.w == w
+
+
+def test_derived_parameters_of_the_workloads():
+    L = 2 * math.pi
+    # 64-node ring: n = 32 -> M = 21, K = 10, beta = 3.5 (tol 1e-6)
+    r = B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=32))
+    assert (r.K, r.w, r.beta) == (10, 8, 3.5)
+    assert math.isclose(r.alpha, 10 / 7, rel_tol=1e-14)          # K (2pi/L)/(2 beta)
+    assert math.isclose(r.rcut, r.beta / r.alpha, rel_tol=1e-14)
+    assert r.rcut <= L / 2
+    assert r.ncell == 1                                           # r_c > L/3
+    # 40 ellipses: n = 64 -> K = 20
+    r = B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64))
+    assert (r.K, r.w) == (20, 8) and math.isclose(r.alpha, 20 / 7, rel_tol=1e-14)
+    assert r.ncell == 5
+    # tangle: n = 256, tol 1e-5 -> beta 3.5 (next accurate-enough row), w = 7
+    r = B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-5, grid_n=256))
+    assert (r.K, r.w, r.beta) == (84, 7, 3.5)
+    # k_max = 2 beta alpha (Sec. 4)
+    assert math.isclose(2 * r.beta * r.alpha, r.K * 2 * math.pi / L, rel_tol=1e-14)
+    # Kaiser-Bessel shape parameter zeta = 0.995 w pi (1 - 1/(2 sigma)) (App. A)
+    assert math.isclose(r.zeta, 0.995 * 7 * math.pi * (1 - 1 / 3), rel_tol=1e-14)
+
+
+def test_parameter_errors():
+    L = 2 * math.pi
+    with pytest.raises(B.BsError) as e:
+        B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=16))
+    assert e.value.code == B.BS_ETOL                 # would need r_c > L/2
+    with pytest.raises(B.BsError) as e:
+        B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, alpha=1.0, rcut=4.0))
+    assert e.value.code == B.BS_EMINIMG
+    for bad in (dict(grid_n=30), dict(grid_n=64, Q=5), dict(grid_n=64, w=20),
+                dict(grid_n=64, sigma=0.9)):
+        with pytest.raises(B.BsError) as e:
+            B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, **bad))
+        assert e.value.code == B.BS_EINVAL
+    with pytest.raises(B.BsError) as e:
+        B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=1024, sigma=1.0001))
+    assert e.value.code == B.BS_EKB
+    p = B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64)
+    p.spline_order = 6
+    with pytest.raises(B.BsError) as e:
+        B.resolve_params(p)
+    assert e.value.code == B.BS_EINVAL

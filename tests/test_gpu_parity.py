@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Two kinds of comparison:
+  * step parity at identical parameters (same alpha, r_c, K, Q): geometry,
+    local and self terms, short-range sums to rounding; long-range part and
+    vorticity modes to the NUFFT error (made ~1e-12 with sigma = 2, w = 16);
+  * accuracy of the whole evaluation at the plan's tolerance against the
+    converged reference solution (beta = 6.5 in the oracle), the metric's
+    rel. l2 error (paper Sec. 5.1, eq:def_relative_errors).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2406_07366_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return math.sqrt(((a - b) ** 2).sum(1).mean() / (b ** 2).sum(1).mean())
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_07366_amd import binding
+    return binding
+
+
+def make_plan(B, fs, **kw):
+    print(f"\n[case] {fs.name} N={fs.n_nodes} params={kw}", flush=True)
+    plan = B.Plan(B.params_for(fs, **kw))
+    xyz, g = B.load_workload(fs)
+    plan.set_filaments(fs.offsets, xyz, g)
+    plan.status()
+    return plan
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def test_geometry_matches_oracle(B):
+    fs = W.ellipses()
+    for Q in (1, 2, 3, 4):
+        plan = make_plan(B, fs, Q=Q)
+        g = {k: np_(v) for k, v in plan.geometry().items()}
+        o = O.Oracle(fs, Q=Q)
+        qp, _, qc = o.quad()
+        nd = o.nodes()
+        scale = np.abs(fs.xyz).max()
+        assert np.abs(g["qpos"] - qp).max() < 1e-13 * scale
+        assert np.abs(g["qcharge"] - qc).max() < 1e-13 * np.abs(qc).max()
+        assert np.abs(g["sdot"] - nd["sdot"]).max() < 1e-12
+        assert np.abs(g["sddot"] - nd["sddot"]).max() < 1e-10 * np.abs(nd["sddot"]).max()
+        assert np.abs(g["ell"] - nd["ell"]).max() < 1e-14 * nd["ell"].max() * 10
+        plan.close()
+
+
+def test_terms_match_oracle_at_same_parameters(B):
+    fs = W.ellipses()
+    plan = make_plan(B, fs, sigma=2.0, w=16)
+    prm = plan.params()
+    t = {k: np_(v) for k, v in plan.velocity_terms().items()}
+    o = O.Oracle(fs)
+    vl, _ = o.local()
+    vs, _ = o.shortrange(prm.alpha, prm.rcut, psi=False)
+    vL, _ = o.longrange(prm.alpha, prm.K, psi=False)
+    vS, _ = o.selfcorr(prm.alpha)
+    for name, gpu, ref, tol in (("local", t["local"], vl, 1e-13), ("short", t["short"], vs, 1e-12),
+                                ("self", t["self"], vS, 1e-12), ("long", t["long"], vL, 1e-10)):
+        err = rel_l2(gpu, ref)
+        print(f"  term {name}: rel_l2 {err:.2e}")
+        assert err < tol, (name, err)
+    assert np.abs(t["ns"]).max() == 0.0
+    # the terms add up to bs_velocity
+    v = np_(plan.velocity())
+    np.testing.assert_allclose(v, t["local"] + t["short"] + t["long"] - t["self"],
+                               rtol=0, atol=1e-13 * np.abs(v).max())
+
+
+def test_vorticity_modes_match_direct_sums(B):
+    """Type-1 NUFFT (spread + FFT + deconvolution) against the direct sums
+    of eq:vorticity_fourier_coefs."""
+    fs = W.ellipses()
+    plan = make_plan(B, fs, sigma=2.0, w=16)
+    K = plan.params().K
+    m = np_(plan.vorticity_modes())
+    gpu = m[..., 0] + 1j * m[..., 1]
+    ref = O.Oracle(fs).omega_hat(K)
+    err = np.abs(gpu - ref).max() / np.abs(ref).max()
+    print(f"  K={K} max rel err {err:.2e}")
+    assert err < 1e-11
+    # at the tolerance's own width the error is the NUFFT error ~10^(-0.9 w)
+    plan = make_plan(B, fs)
+    K = plan.params().K
+    m = np_(plan.vorticity_modes())
+    gpu = m[..., 0] + 1j * m[..., 1]
+    ref = O.Oracle(fs).omega_hat(K)
+    err = np.abs(gpu - ref).max() / np.abs(ref).max()
+    print(f"  K={K} w={plan.params().w} max rel err {err:.2e}")
+    assert err < 10 ** (-0.9 * plan.params().w + 1)
+
+
+@pytest.mark.parametrize("name", ["ring", "ellipses"])
+def test_velocity_fp64_meets_1e6(B, name):
+    fs = W.make(name)
+    plan = make_plan(B, fs)
+    v = np_(plan.velocity())
+    ref, _ = O.Oracle(fs).reference(psi=False)
+    err = rel_l2(v, ref)
+    print(f"  {name} FP64 rel_l2 vs reference {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_velocity_mixed_precision_ellipses(B):
+    fs = W.ellipses()
+    plan = make_plan(B, fs, precision=B.BS_FP32_MIXED)
+    v = np_(plan.velocity())
+    ref, _ = O.Oracle(fs).reference(psi=False)
+    err = rel_l2(v, ref)
+    print(f"  ellipses FP32-mixed rel_l2 vs reference {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_streamfunction_and_energy(B, precision):
+    fs = W.ellipses()
+    plan = make_plan(B, fs, precision=precision)
+    E, psi = plan.energy()
+    psi = np_(psi)
+    o = O.Oracle(fs)
+    _, pref = o.reference()
+    Eref = o.energy(pref)
+    err = rel_l2(psi, pref)
+    print(f"  psi rel_l2 {err:.3e}  E {E:.12e} ref {Eref:.12e}")
+    tol = 1e-6 if precision == 0 else 1e-5
+    assert err <= tol
+    assert abs(E - Eref) <= tol * abs(Eref)
+
+
+def test_edge_cases_small_ragged_long_filaments(B):
+    """3-node filaments, ragged lengths, one 600-node filament (spline solve
+    outside LDS), grid 36 (4^3 spread tiles), odd width."""
+    rng = np.random.default_rng(5)
+    parts, counts = [], []
+    for nl in (3, 4, 7, 600, 31):
+        th = 2 * np.pi * np.arange(nl) / nl
+        R = rng.uniform(0.4, 1.0)
+        c = rng.uniform(0, 2 * np.pi, 3)
+        rot = W.haar_rotations(rng, 1)[0]
+        loc = np.stack([R * np.cos(th), 0.7 * R * np.sin(th), 0.1 * np.sin(2 * th)], 1)
+        parts.append(c + loc @ rot.T)
+        counts.append(nl)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    fs = W.FilamentSet("edge", 2 * np.pi, 1e-6, off, np.concatenate(parts),
+                       rng.choice([-1.0, 1.0], len(counts)), 36, 1e-6)
+    for kw in (dict(w=11, sigma=2.0, beta=3.0), dict(w=9, Q=3, sigma=2.0, beta=3.0)):
+        plan = make_plan(B, fs, **kw)
+        prm = plan.params()
+        assert plan.N == off[-1]
+        v = np_(plan.velocity())
+        o = O.Oracle(fs, Q=prm.Q)
+        ref, _ = o.ewald(prm.alpha, prm.rcut, prm.K, psi=False)
+        err = rel_l2(v, ref)
+        print(f"  edge w={prm.w} Q={prm.Q} n={prm.grid_n} K={prm.K} rel_l2 {err:.2e}")
+        assert err < 1e-8
+
+
+def test_bitwise_reproducible(B):
+    fs = W.ellipses()
+    for prec in (0, 1):
+        plan = make_plan(B, fs, precision=prec)
+        a = np_(plan.velocity())
+        xyz, g = B.load_workload(fs)
+        plan.set_filaments(fs.offsets, xyz, g)
+        b = np_(plan.velocity())
+        assert np.array_equal(a, b)
+
+
+def test_status_reports_bad_geometry(B):
+    import torch
+    fs = W.ellipses(nfil=2, n_per=16)
+    plan = make_plan(B, fs)
+    xyz, g = B.load_workload(fs)
+    bad = xyz.clone()
+    bad[5] = bad[4]                       # zero-length segment
+    plan.set_filaments(fs.offsets, bad, g)
+    with pytest.raises(B.BsError) as e:
+        plan.status()
+    assert e.value.code == B.BS_EINVAL
+    bad = xyz.clone()
+    bad[3, 1] = float("nan")
+    plan.set_filaments(fs.offsets, bad, g)
+    with pytest.raises(B.BsError):
+        plan.status()
+    plan.set_filaments(fs.offsets, xyz, g)   # recovers
+    plan.velocity()
+    plan.status()
+    with pytest.raises(B.BsError) as e:
+        plan.set_filaments(np.array([0, 2], dtype=np.int64), xyz[:2].contiguous(), g[:1].contiguous())
+    assert e.value.code == B.BS_EINVAL
+    fresh = B.Plan(B.params_for(fs))
+    with pytest.raises(B.BsError) as e:
+        fresh.velocity(torch.empty((4, 3), dtype=torch.float64, device="cuda"))
+    assert e.value.code == B.BS_ESTATE
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tangle_sampled(B, precision):
+    """Full-size random Fourier tangle (N = 1e5, grid 256^3, tol 1e-5):
+    256 sampled nodes against the reference."""
+    fs = W.tangle()
+    plan = make_plan(B, fs, precision=precision)
+    v = np_(plan.velocity())
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(fs.n_nodes, 256, replace=False))
+    ref, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False)
+    err = rel_l2(v[idx], ref)
+    print(f"  tangle prec={precision} sampled rel_l2 {err:.3e}")
+    assert err <= 1e-5
