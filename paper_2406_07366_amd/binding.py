@@ -57,6 +57,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "(hipcc --offload-arch=gfx950)")
 
+# torch ships its own HIP runtime (same soname as the system one).  Loading
+# torch first makes libbs.so bind to that already-loaded runtime instead of
+# pulling in a second copy, which would leave two runtimes fighting over the
+# device in one process.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 _vp = C.c_void_p
 _lib.bs_resolve_params.argtypes = [C.POINTER(BsParams), C.POINTER(BsParams)]

@@ -130,16 +130,38 @@ __global__ void k_scatter(int M, const int *__restrict__ key, const int *__restr
     perm[start[k] + atomicAdd(&fill[k], 1)] = i;
 }
 
-// order each bin by original index (insertion sort; bins are small)
-__global__ void k_sort_bins(int nbins, const int *__restrict__ start, int *__restrict__ perm) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
+// Order each bin by original index: one wavefront per bin computes every
+// entry's rank (number of smaller indices in the bin) and writes it to its
+// rank slot.  Bins of up to kSortLds entries are ranked in LDS and written
+// back in place; larger bins are ranked from global memory into `scratch`
+// (the key array, free once the scatter is done) and copied back.
+constexpr int kSortLds = 2048;
+
+__global__ __launch_bounds__(64) void k_sort_bins(int nbins, const int *__restrict__ start,
+                                                  int *__restrict__ perm,
+                                                  int *__restrict__ scratch) {
+    __shared__ int v[kSortLds];
+    int b = blockIdx.x;
     if (b >= nbins) return;
-    int s = start[b], e = start[b + 1];
-    for (int i = s + 1; i < e; i++) {
-        int v = perm[i], j = i - 1;
-        while (j >= s && perm[j] > v) { perm[j + 1] = perm[j]; j--; }
-        perm[j + 1] = v;
+    int s = start[b], n = start[b + 1] - s;
+    if (n <= 1) return;
+    if (n <= kSortLds) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = perm[s + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            int x = v[i], r = 0;
+            for (int j = 0; j < n; j++) r += (v[j] < x);
+            perm[s + r] = x;
+        }
+        return;
     }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int x = perm[s + i], r = 0;
+        for (int j = 0; j < n; j++) r += (perm[s + j] < x);
+        scratch[s + r] = x;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[s + i] = scratch[s + i];
 }
 
 __global__ void k_fill_int(int *p, int n, int v) {
@@ -212,8 +234,8 @@ void build_bins(bs_plan_t p) {
     exclusive_scan(p, cnt, start, ntiles);
     hipLaunchKernelGGL(k_scatter, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M, key, start,
                        fill, perm);
-    hipLaunchKernelGGL(k_sort_bins, dim3(ceil_div(ntiles, bs)), dim3(bs), 0, p->stream, ntiles,
-                       start, perm);
+    hipLaunchKernelGGL(k_sort_bins, dim3(ntiles), dim3(64), 0, p->stream, ntiles, start, perm,
+                       key);
     const double zeta = p->prm.zeta, inv_den = 1.0 / (-expm1(-2.0 * zeta));
     if (p->fp32)
         hipLaunchKernelGGL(k_gather_spread<float>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream,
@@ -236,8 +258,7 @@ void build_bins(bs_plan_t p) {
     exclusive_scan(p, cnt, start, nc3);
     hipLaunchKernelGGL(k_scatter, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M, key, start,
                        fill, perm);
-    hipLaunchKernelGGL(k_sort_bins, dim3(ceil_div(nc3, bs)), dim3(bs), 0, p->stream, nc3, start,
-                       perm);
+    hipLaunchKernelGGL(k_sort_bins, dim3(nc3), dim3(64), 0, p->stream, nc3, start, perm, key);
     if (p->fp32)
         hipLaunchKernelGGL(k_gather_pairs<float>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream,
                            M, p->Q, perm, (const double *)p->d_qpos.p,
@@ -258,8 +279,7 @@ void build_bins(bs_plan_t p) {
     exclusive_scan(p, cnt, start, nc3);
     hipLaunchKernelGGL(k_scatter, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, key, start,
                        fill, perm);
-    hipLaunchKernelGGL(k_sort_bins, dim3(ceil_div(nc3, bs)), dim3(bs), 0, p->stream, nc3, start,
-                       perm);
+    hipLaunchKernelGGL(k_sort_bins, dim3(nc3), dim3(64), 0, p->stream, nc3, start, perm, key);
 }
 
 }  // namespace bs

@@ -90,6 +90,18 @@ static void kernel_ft_table(int K, int w, int n, double zeta, double *F) {
     }
 }
 
+// 16-point Gauss-Legendre rule for the near-singular panels
+struct NsRule {
+    double x[16];
+    double w[16];
+};
+void ns_rule(NsRule *R) {
+    static NsRule cached;
+    static bool have = false;
+    if (!have) { legendre_rule(16, cached.x, cached.w); have = true; }
+    *R = cached;
+}
+
 template <typename T>
 static int ensure(bs_plan_t p, DBuf &b, size_t count) {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
@@ -338,6 +350,13 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             (rc = ensure<int>(P, P->nd_fill, nc3 + 1)) || (rc = ensure<int>(P, P->nd_perm, N)))
             return rc;
         if (maxn > 512 && (rc = ensure<double>(P, P->spline_tmp, 12 * N))) return rc;
+        if (P->prm.ns_mode != BS_NS_OFF) {
+            size_t mp = (size_t)N * P->ns_max_per_node;
+            if ((rc = ensure<double>(P, P->ns_maxell, 1)) || (rc = ensure<int>(P, P->ns_cnt, N + 1)) ||
+                (rc = ensure<int>(P, P->ns_start, N + 1)) || (rc = ensure<int2>(P, P->ns_pairs, mp)) ||
+                (rc = ensure<int>(P, P->ns_pnode, mp)) || (rc = ensure<double>(P, P->ns_pout, 3 * mp)))
+                return rc;
+        }
         std::vector<int> off32(nfil + 1), fil32(N);
         for (int64_t f = 0; f <= nfil; f++) off32[f] = (int)offsets[f];
         for (int64_t f = 0; f < nfil; f++)
@@ -367,6 +386,7 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     stage_end(P, 0);
     stage_begin(P, 1);
     build_bins(P);
+    if (P->prm.ns_mode != BS_NS_OFF) ns_build_pairs(P);
     stage_end(P, 1);
     if ((rc = launch_status(P, "geometry kernels"))) return rc;
     P->have_filaments = true;
@@ -406,6 +426,11 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     stage_begin(P, 8);
     launch_pairs(P, 0, v_out);
     stage_end(P, 8);
+    if (P->prm.ns_mode != BS_NS_OFF) {
+        stage_begin(P, 9);
+        launch_ns_adaptive(P, v_out);
+        stage_end(P, 9);
+    }
     if ((rc = launch_status(P, "pair kernel"))) return rc;
     stage_collect(P);
     return BS_OK;
@@ -427,7 +452,10 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
         fill_f64(P, v_short, n3, 0.0);
         launch_pairs(P, 0, v_short);
     }
-    if (v_ns) fill_f64(P, v_ns, n3, 0.0);
+    if (v_ns) {
+        fill_f64(P, v_ns, n3, 0.0);
+        if (P->prm.ns_mode != BS_NS_OFF) launch_ns_adaptive(P, v_ns);
+    }
     return launch_status(P, "velocity terms");
 }
 
@@ -489,7 +517,8 @@ int bs_status(bs_plan_t P) {
     if (st) {
         (void)hipMemsetAsync(P->d_status.p, 0, sizeof(int), P->stream);
         (void)hipStreamSynchronize(P->stream);
-        return set_error(P, BS_EINVAL, "non-finite node position or zero-length segment");
+        return set_error(P, BS_EINVAL, (st & 1) ? "non-finite node position or zero-length segment"
+                                                : "more than 32 near-singular segments at a node");
     }
     return BS_OK;
 }
@@ -515,7 +544,8 @@ int bs_destroy(bs_plan_t P) {
                    &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
                    &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
-                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3};
+                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->ns_maxell,
+                   &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout};
     for (DBuf *b : all) release(*b);
     delete P;
     return BS_OK;

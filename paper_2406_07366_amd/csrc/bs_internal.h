@@ -74,6 +74,9 @@ struct bs_plan_s {
     // scan scratch, reductions, spline scratch (filaments over 512 nodes)
     bs::DBuf scan_tmp, red_tmp, spline_tmp;
     int64_t max_fil_nodes = 0;
+    // near-singular pairs
+    int ns_max_per_node = 32;
+    bs::DBuf ns_maxell, ns_cnt, ns_start, ns_pairs, ns_pnode, ns_pout;
     // terms (for velocity terms / energy)
     bs::DBuf tmp3;                             // f64 [N][3]
     // per-stage timing (diagnostics)
@@ -111,6 +114,10 @@ int fft_inverse(bs_plan_t p);
 
 // pairs.hip
 void launch_pairs(bs_plan_t p, int psi, double *out);
+
+// ns.hip
+void ns_build_pairs(bs_plan_t p);
+void launch_ns_adaptive(bs_plan_t p, double *v);
 
 // energy.hip
 void launch_energy(bs_plan_t p, const double *psi, double *partial, int nblocks);

@@ -22,6 +22,13 @@
 namespace bs {
 
 // ----------------------------------------------------------------- spread
+// Candidates (points whose stencil base lies in one of the nbv^3 bins that
+// can reach this tile) are staged in LDS in batches of kSpreadBatch by all
+// threads at once; then each wavefront takes candidates in turn, its lanes
+// covering the (ky, kz) rows of the stencil, and adds the row's cells that
+// fall in the tile into the LDS tile with LDS atomics.
+constexpr int kSpreadBatch = 64;
+
 template <typename R, int W, int TT>
 __global__ __launch_bounds__(256) void k_spread(int n, int NT, int nbv,
                                                 const int *__restrict__ start,
@@ -29,53 +36,77 @@ __global__ __launch_bounds__(256) void k_spread(int n, int NT, int nbv,
                                                 const R *__restrict__ ker,
                                                 const R *__restrict__ q, R *__restrict__ grid) {
     constexpr int T3 = TT * TT * TT;
+    constexpr int CB = kSpreadBatch;
     __shared__ R acc[3 * T3];
+    __shared__ R sker[CB * 3 * W];
+    __shared__ R sq[CB * 3];
+    __shared__ int4 sb[CB];
+    __shared__ int bin_s[27], bin_o[28];
     const int tile = blockIdx.x;
     const int tx = tile % NT, ty = (tile / NT) % NT, tz = tile / (NT * NT);
     const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
     for (int i = threadIdx.x; i < 3 * T3; i += blockDim.x) acc[i] = (R)0;
+    const int nbins = nbv * nbv * nbv;
+    if (threadIdx.x < nbins) {
+        int i = threadIdx.x;
+        int dx = i % nbv, dy = (i / nbv) % nbv, dz = i / (nbv * nbv);
+        int bz = tz - dz; if (bz < 0) bz += NT;
+        int by = ty - dy; if (by < 0) by += NT;
+        int bx = tx - dx; if (bx < 0) bx += NT;
+        int bin = (bz * NT + by) * NT + bx;
+        bin_s[i] = start[bin];
+        bin_o[i + 1] = start[bin + 1] - start[bin];
+    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        bin_o[0] = 0;
+        for (int i = 0; i < nbins; i++) bin_o[i + 1] += bin_o[i];
+    }
+    __syncthreads();
+    const int total = bin_o[nbins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    for (int dz = 0; dz < nbv; dz++)
-        for (int dy = 0; dy < nbv; dy++)
-            for (int dx = 0; dx < nbv; dx++) {
-                int bz = tz - dz; if (bz < 0) bz += NT;
-                int by = ty - dy; if (by < 0) by += NT;
-                int bx = tx - dx; if (bx < 0) bx += NT;
-                int bin = (bz * NT + by) * NT + bx;
-                int s = start[bin], e = start[bin + 1];
-                for (int pidx = s + wave; pidx < e; pidx += nwaves) {
-                    int4 b = base[pidx];
-                    const R *kp = ker + (size_t)pidx * 3 * W;
-                    // local x index of stencil column 0 (same for every lane)
-                    int lx0 = b.x - t0x;
-                    if (lx0 < 0) lx0 += n;
-                    R qx = q[4 * (size_t)pidx], qy = q[4 * (size_t)pidx + 1],
-                      qz = q[4 * (size_t)pidx + 2];
-                    for (int l = lane; l < W * W; l += 64) {
-                        int ky = l % W, kz = l / W;
-                        int ly = b.y + ky - t0y;
-                        if (ly < 0) ly += n; else if (ly >= n) ly -= n;
-                        int lz = b.z + kz - t0z;
-                        if (lz < 0) lz += n; else if (lz >= n) lz -= n;
-                        if (ly >= TT || lz >= TT) continue;
-                        R cyz = kp[W + ky] * kp[2 * W + kz];
-                        R cx = qx * cyz, cy = qy * cyz, cz = qz * cyz;
-                        R *row = acc + (lz * TT + ly) * TT;
+    for (int c0 = 0; c0 < total; c0 += CB) {
+        const int cn = total - c0 < CB ? total - c0 : CB;
+        for (int i = threadIdx.x; i < cn * (3 * W + 4); i += blockDim.x) {
+            int c = i / (3 * W + 4), k = i % (3 * W + 4);
+            int ci = c0 + c, b = 0;
+            while (bin_o[b + 1] <= ci) b++;
+            int g = bin_s[b] + (ci - bin_o[b]);
+            if (k < 3 * W) sker[c * 3 * W + k] = ker[(size_t)g * 3 * W + k];
+            else if (k < 3 * W + 3) sq[c * 3 + (k - 3 * W)] = q[4 * (size_t)g + (k - 3 * W)];
+            else sb[c] = base[g];
+        }
+        __syncthreads();
+        for (int c = wave; c < cn; c += nwaves) {
+            int4 b = sb[c];
+            const R *kp = sker + c * 3 * W;
+            int lx0 = b.x - t0x;
+            if (lx0 < 0) lx0 += n;
+            R qx = sq[3 * c], qy = sq[3 * c + 1], qz = sq[3 * c + 2];
+            for (int l = lane; l < W * W; l += 64) {
+                int ky = l % W, kz = l / W;
+                int ly = b.y + ky - t0y;
+                if (ly < 0) ly += n; else if (ly >= n) ly -= n;
+                int lz = b.z + kz - t0z;
+                if (lz < 0) lz += n; else if (lz >= n) lz -= n;
+                if (ly >= TT || lz >= TT) continue;
+                R cyz = kp[W + ky] * kp[2 * W + kz];
+                R cx = qx * cyz, cy = qy * cyz, cz = qz * cyz;
+                R *row = acc + (lz * TT + ly) * TT;
 #pragma unroll
-                        for (int kx = 0; kx < W; kx++) {
-                            int lx = lx0 + kx;
-                            if (lx >= n) lx -= n;
-                            if (lx >= TT) continue;
-                            R ph = kp[kx];
-                            atomicAdd(row + lx, cx * ph);
-                            atomicAdd(row + T3 + lx, cy * ph);
-                            atomicAdd(row + 2 * T3 + lx, cz * ph);
-                        }
-                    }
+                for (int kx = 0; kx < W; kx++) {
+                    int lx = lx0 + kx;
+                    if (lx >= n) lx -= n;
+                    if (lx >= TT) continue;
+                    R ph = kp[kx];
+                    atomicAdd(row + lx, cx * ph);
+                    atomicAdd(row + T3 + lx, cy * ph);
+                    atomicAdd(row + 2 * T3 + lx, cz * ph);
                 }
             }
-    __syncthreads();
+        }
+        __syncthreads();
+    }
     const size_t n3 = (size_t)n * n * n;
     for (int i = threadIdx.x; i < T3; i += blockDim.x) {
         int lx = i % TT, ly = (i / TT) % TT, lz = i / (TT * TT);
@@ -229,71 +260,75 @@ void launch_modes(bs_plan_t p, double *out) {
 }
 
 // ---------------------------------------------------------- interpolation
-template <typename R, int W>
+// G lanes per node; lane l sums the x-rows (ky, kz) = (r % W, r / W) for
+// r = l, l + G, ...; partial sums combined by a fixed xor-shuffle tree.
+template <typename R, int W, int G>
 __global__ __launch_bounds__(256) void k_interp(int N, const int *__restrict__ perm,
                                                 const double *__restrict__ x, double L,
                                                 double inv_h, int n, double zeta, double inv_den,
                                                 const R *__restrict__ grid,
                                                 double *__restrict__ out) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gid / G, lane = gid % G;
     if (t >= N) return;
-    int o = perm[t];
+    const int o = perm[t];
     const double half = 0.5 * W;
-    int ix[W], iy[W];
-    R px[W], py[W];
     double fx, fy, fz;
     int bx = stencil_base(wrap_box(x[3 * o], L), inv_h, W, n, &fx);
     int by = stencil_base(wrap_box(x[3 * o + 1], L), inv_h, W, n, &fy);
     int bz = stencil_base(wrap_box(x[3 * o + 2], L), inv_h, W, n, &fz);
+    int ix[W];
+    R px[W];
 #pragma unroll
     for (int k = 0; k < W; k++) {
         int c = bx + k;
         ix[k] = c >= n ? c - n : c;
         px[k] = (R)kb_phi((k - fx) / half, zeta, inv_den);
-        c = by + k;
-        iy[k] = c >= n ? c - n : c;
-        py[k] = (R)kb_phi((k - fy) / half, zeta, inv_den);
     }
     const size_t n3 = (size_t)n * n * n;
     R a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll 1
-    for (int kz = 0; kz < W; kz++) {
-        R pz = (R)kb_phi((kz - fz) / half, zeta, inv_den);
-        int cz = bz + kz;
-        cz = cz >= n ? cz - n : cz;
-        const R *plane = grid + (size_t)cz * n * n;
-        R b0 = 0, b1 = 0, b2 = 0;
+    for (int r = lane; r < W * W; r += G) {
+        int ky = r % W, kz = r / W;
+        int cy = by + ky; cy = cy >= n ? cy - n : cy;
+        int cz = bz + kz; cz = cz >= n ? cz - n : cz;
+        R wyz = (R)(kb_phi((ky - fy) / half, zeta, inv_den) * kb_phi((kz - fz) / half, zeta, inv_den));
+        const R *row = grid + ((size_t)cz * n + cy) * n;
+        R s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
-        for (int ky = 0; ky < W; ky++) {
-            const R *row = plane + (size_t)iy[ky] * n;
-            R s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-            for (int kx = 0; kx < W; kx++) {
-                int c = ix[kx];
-                s0 += px[kx] * row[c];
-                s1 += px[kx] * row[n3 + c];
-                s2 += px[kx] * row[2 * n3 + c];
-            }
-            b0 += py[ky] * s0; b1 += py[ky] * s1; b2 += py[ky] * s2;
+        for (int kx = 0; kx < W; kx++) {
+            int c = ix[kx];
+            s0 += px[kx] * row[c];
+            s1 += px[kx] * row[n3 + c];
+            s2 += px[kx] * row[2 * n3 + c];
         }
-        a0 += pz * b0; a1 += pz * b1; a2 += pz * b2;
+        a0 += wyz * s0; a1 += wyz * s1; a2 += wyz * s2;
     }
-    out[3 * o] += (double)a0;
-    out[3 * o + 1] += (double)a1;
-    out[3 * o + 2] += (double)a2;
+#pragma unroll
+    for (int m = G / 2; m > 0; m >>= 1) {
+        a0 += __shfl_xor(a0, m, G);
+        a1 += __shfl_xor(a1, m, G);
+        a2 += __shfl_xor(a2, m, G);
+    }
+    if (lane == 0) {
+        out[3 * o] += (double)a0;
+        out[3 * o + 1] += (double)a1;
+        out[3 * o + 2] += (double)a2;
+    }
 }
+
+constexpr int kInterpLanes = 64;
 
 template <typename R>
 static void interp_r(bs_plan_t p, double *out) {
     const int N = (int)p->N;
-    dim3 grid(ceil_div(N, 256)), block(256);
+    dim3 grid(ceil_div((int64_t)N * kInterpLanes, 256)), block(256);
     const double L = p->prm.L, inv_h = p->n / L, zeta = p->prm.zeta;
     const double inv_den = 1.0 / (-expm1(-2.0 * zeta));
     const int *perm = (const int *)p->nd_perm.p;
     const double *x = (const double *)p->d_x.p;
     const R *g = (const R *)p->grid.p;
 #define INTERP_CASE(WW) \
-    case WW: hipLaunchKernelGGL((k_interp<R, WW>), grid, block, 0, p->stream, N, perm, x, L, inv_h, p->n, zeta, inv_den, g, out); break;
+    case WW: hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes>), grid, block, 0, p->stream, N, perm, x, L, inv_h, p->n, zeta, inv_den, g, out); break;
     switch (p->prm.w) {
         INTERP_CASE(4) INTERP_CASE(5) INTERP_CASE(6) INTERP_CASE(7) INTERP_CASE(8)
         INTERP_CASE(9) INTERP_CASE(10) INTERP_CASE(11) INTERP_CASE(12) INTERP_CASE(13)

@@ -2,8 +2,8 @@
 // eq:streamfunction_shortrange) as quadrature sums over cell lists, and the
 // energy reduction (eq:kinetic_energy_streamfunction).
 //
-// One thread per target node, nodes processed in cell order so that a
-// wavefront reads the same few cells.  For each quadrature point of the 27
+// A group of lanes per target node, nodes processed in cell order so that
+// consecutive groups read the same few cells.  For each quadrature point of the 27
 // surrounding cells (or of every cell when fewer than 3 fit along an axis):
 // r = s_q - s_i by minimum image (formed in float64), skip the 2Q points of
 // the two segments adjacent to the node, keep r < r_c, and add
@@ -15,7 +15,10 @@
 
 namespace bs {
 
-template <typename R, bool PSI>
+// G lanes cooperate on one target node: each lane takes every G-th candidate
+// of each cell, then the partial sums are combined by a fixed xor-shuffle
+// tree (deterministic order).
+template <typename R, bool PSI, int G>
 __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double rc, double alpha,
                                                const int *__restrict__ nperm,
                                                const double *__restrict__ x,
@@ -26,16 +29,16 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
                                                const R *__restrict__ schg,
                                                const int *__restrict__ sseg,
                                                double *__restrict__ out) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gid / G, lane = gid % G;
+    if (t >= N) return;   // whole groups exit together
     const int o = nperm[t];
     const int ip = prev_node_d(off, fil, o);
     const double xi0 = x[3 * o], xi1 = x[3 * o + 1], xi2 = x[3 * o + 2];
     const double invL = 1.0 / L;
     int c[3];
     {
-        double w0 = wrap_box(xi0, L), w1 = wrap_box(xi1, L), w2 = wrap_box(xi2, L);
-        double ws[3] = {w0, w1, w2};
+        double ws[3] = {wrap_box(xi0, L), wrap_box(xi1, L), wrap_box(xi2, L)};
         for (int q = 0; q < 3; q++) {
             int v = (int)(ws[q] * invL * nc);
             c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
                 int cx = c[0] + dx; cx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
                 int cell = (cz * nc + cy) * nc + cx;
                 int s = cstart[cell], e = cstart[cell + 1];
-                for (int p = s; p < e; p++) {
+                for (int p = s + lane; p < e; p += G) {
                     int sg = sseg[p];
                     if (sg == o || sg == ip) continue;
                     double4 sp = spos[p];
@@ -83,15 +86,25 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
             }
         }
     }
-    const double inv4pi = 1.0 / (4.0 * kPi);
-    out[3 * o] += (double)acc0 * inv4pi;
-    out[3 * o + 1] += (double)acc1 * inv4pi;
-    out[3 * o + 2] += (double)acc2 * inv4pi;
+#pragma unroll
+    for (int m = G / 2; m > 0; m >>= 1) {
+        acc0 += __shfl_xor(acc0, m, G);
+        acc1 += __shfl_xor(acc1, m, G);
+        acc2 += __shfl_xor(acc2, m, G);
+    }
+    if (lane == 0) {
+        const double inv4pi = 1.0 / (4.0 * kPi);
+        out[3 * o] += (double)acc0 * inv4pi;
+        out[3 * o + 1] += (double)acc1 * inv4pi;
+        out[3 * o + 2] += (double)acc2 * inv4pi;
+    }
 }
+
+constexpr int kPairLanes = 64;
 
 void launch_pairs(bs_plan_t p, int psi, double *out) {
     const int N = (int)p->N;
-    dim3 grid(ceil_div(N, 256)), block(256);
+    dim3 grid(ceil_div((int64_t)N * kPairLanes, 256)), block(256);
     const double L = p->prm.L, rc = p->prm.rcut, alpha = p->prm.alpha;
     const int *nperm = (const int *)p->nd_perm.p, *off = (const int *)p->d_off.p,
               *fil = (const int *)p->d_fil.p, *cs = (const int *)p->pq_start.p,
@@ -100,12 +113,12 @@ void launch_pairs(bs_plan_t p, int psi, double *out) {
     const double4 *sp = (const double4 *)p->pq_pos.p;
     if (p->fp32) {
         const float *q = (const float *)p->pq_chg.p;
-        if (psi) hipLaunchKernelGGL((k_pairs<float, true>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
-        else hipLaunchKernelGGL((k_pairs<float, false>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        if (psi) hipLaunchKernelGGL((k_pairs<float, true, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        else hipLaunchKernelGGL((k_pairs<float, false, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
     } else {
         const double *q = (const double *)p->pq_chg.p;
-        if (psi) hipLaunchKernelGGL((k_pairs<double, true>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
-        else hipLaunchKernelGGL((k_pairs<double, false>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        if (psi) hipLaunchKernelGGL((k_pairs<double, true, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        else hipLaunchKernelGGL((k_pairs<double, false, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
     }
 }
 

@@ -1,0 +1,86 @@
+"""Near-singular correction on the GPU against the oracle's adaptive
+Gauss-Kronrod integrals (the correction is defined in include/bs.h: the
+Q-point sum of every non-adjacent segment whose chord lies within
+ns_eta * ell of a node is replaced by the exact segment integral)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2406_07366_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return math.sqrt(((a - b) ** 2).sum(1).mean() / (b ** 2).sum(1).mean())
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_07366_amd import binding
+    return binding
+
+
+def make_plan(B, fs, **kw):
+    print(f"\n[case] {fs.name} N={fs.n_nodes} params={kw}", flush=True)
+    plan = B.Plan(B.params_for(fs, **kw))
+    xyz, g = B.load_workload(fs)
+    plan.set_filaments(fs.offsets, xyz, g)
+    plan.status()
+    return plan
+
+
+def small_ringpairs():
+    fs = W.ringpairs(npairs=150, nbg=20, seed=77)
+    fs.grid_n = 64
+    fs.tol = 1e-6
+    return fs
+
+
+def test_ns_term_matches_oracle(B):
+    fs = small_ringpairs()
+    plan = make_plan(B, fs, ns_mode=B.BS_NS_ADAPTIVE)
+    t = plan.velocity_terms()
+    dv = t["ns"].cpu().numpy()
+    ref, cnt = O.Oracle(fs).ns_correction(eta=1.0)
+    assert cnt.sum() > fs.n_nodes          # ring partners are flagged
+    err = rel_l2(dv, ref)
+    print(f"  ns term rel_l2 {err:.2e}, flagged pairs {cnt.sum()}")
+    assert err < 1e-10
+    # and the velocity including it equals the terms' sum
+    v = plan.velocity().cpu().numpy()
+    tot = sum(t[k].cpu().numpy() for k in ("local", "short", "long", "ns")) - t["self"].cpu().numpy()
+    np.testing.assert_allclose(v, tot, rtol=0, atol=1e-12 * np.abs(v).max())
+
+
+def test_ns_velocity_meets_reference(B):
+    fs = small_ringpairs()
+    plan = make_plan(B, fs, ns_mode=B.BS_NS_ADAPTIVE)
+    v = plan.velocity().cpu().numpy()
+    ref, _ = O.Oracle(fs).reference(psi=False, ns_eta=1.0)
+    err = rel_l2(v, ref)
+    plain = make_plan(B, fs)
+    v0 = plain.velocity().cpu().numpy()
+    err0 = rel_l2(v0, ref)
+    print(f"  with NS {err:.3e}   without NS {err0:.3e}")
+    assert err <= 1e-6
+    assert err0 > 100 * err
+
+
+def test_ns_ringpairs_full_sampled(B):
+    """Full ring-pair workload (N = 2e5, grid 256^3, tol 1e-5), 128 sampled
+    nodes of the ring pairs against the reference with exact near-singular
+    integrals."""
+    fs = W.ringpairs()
+    plan = make_plan(B, fs, ns_mode=B.BS_NS_ADAPTIVE)
+    v = plan.velocity().cpu().numpy()
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(160000, 128, replace=False))
+    ref, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False, ns_eta=1.0)
+    err = rel_l2(v[idx], ref)
+    print(f"  ringpairs sampled rel_l2 {err:.3e}")
+    assert err <= 1e-5
