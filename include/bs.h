@@ -174,6 +174,14 @@ int bs_vorticity_modes(bs_plan_t plan, double *out);
 int bs_geometry(bs_plan_t plan, double *qpos, double *qcharge, double *sdot,
                 double *sddot, double *ell);
 
+/* One classical fourth-order Runge-Kutta step of dx/dt = v(x) for every
+ * node (Sec. 5.2: each node moves with the Biot-Savart velocity; the spline
+ * is refitted at every stage).  xyz: DEVICE float64 [N][3], advanced in
+ * place; offsets (HOST) and gamma (DEVICE) as in bs_set_filaments; dt the
+ * time step.  Leaves the plan loaded with the last stage's filaments. */
+int bs_rk4_step(bs_plan_t plan, int64_t nfil, const int64_t *offsets, double *xyz,
+                const double *gamma, double dt);
+
 /* Synchronise the plan stream and report device-side input errors seen
  * since the last call (BS_EINVAL with a message), else BS_OK. */
 int bs_status(bs_plan_t plan);
@@ -191,6 +199,57 @@ int bs_status(bs_plan_t plan);
 #define BS_NSTAGES 10
 int bs_set_profiling(bs_plan_t plan, int enable);
 int bs_stage_times(bs_plan_t plan, double *ms, int64_t *counts, int reset);
+
+/* ---- learned near-singular correction --------------------------------
+ * A small network 8 -> 64 -> 64 -> 64 -> 3 with SiLU hidden activations,
+ * BF16 weights on MFMA with FP32 accumulation (not part of the paper).
+ * Parameters are FP32, packed W1[64][8] b1[64] W2[64][64] b2[64] W3[64][64]
+ * b3[64] W4[3][64] b4[3] (bs_mlp_nparams() values, W row-major [out][in]).
+ * X is float32 [B][8] (features), Y and T float32 [B][3], all DEVICE
+ * pointers; calls are asynchronous on the stream given at creation. */
+typedef struct bs_mlp_s *bs_mlp_t;
+int bs_mlp_nparams(void);
+/* copy params_host (FP32, bs_mlp_nparams() values) to the device; Adam
+ * moments start at zero */
+int bs_mlp_create(const float *params_host, void *hip_stream, bs_mlp_t *out);
+/* Y = network(X) */
+int bs_mlp_forward(bs_mlp_t m, int64_t B, const float *X, float *Y);
+/* loss = (1/2B) sum |network(X) - T|^2 and its gradient w.r.t. the packed
+ * parameters (loss_dev: 1 float, grad_dev: bs_mlp_nparams() floats; either
+ * may be NULL) */
+int bs_mlp_loss_grad(bs_mlp_t m, int64_t B, const float *X, const float *T,
+                     float *loss_dev, float *grad_dev);
+/* one Adam step on that loss (bias-corrected moments); loss_dev may be NULL */
+int bs_mlp_adam_step(bs_mlp_t m, int64_t B, const float *X, const float *T,
+                     float lr, float beta1, float beta2, float eps, float *loss_dev);
+/* synchronise and copy the current FP32 parameters to the host */
+int bs_mlp_get_params(bs_mlp_t m, float *params_host);
+int bs_mlp_destroy(bs_mlp_t m);
+
+/* Training samples for the learned near-singular correction, generated on
+ * the device by the plan's own graded Gauss-Legendre segment integrator
+ * (float64).  U: DEVICE float64 [n][8] uniforms in [0,1) supplied by the
+ * caller (they fix the segment tangents, the target's position class,
+ * distance and azimuth); X: DEVICE float32 [n][8] features; T: DEVICE float32
+ * [n][3] targets d_c * (I_seg - I_chord) in the chord frame; aux: DEVICE
+ * float64 [n][4] (d_c/h, exact raw integral in the frame) or NULL.  The
+ * sample box: tangent angles <= 0.6 rad, tangent lengths in [0.9, 1.1],
+ * d_c/h log-uniform in bs_ns_error_bins' range. */
+int bs_ns_samples(int64_t n, const double *U, float *X, float *T, double *aux,
+                  void *hip_stream);
+/* range [lo, hi] of d_c/h covered by the network and the number of
+ * log-spaced bins of its error table */
+int bs_ns_error_bins(double *lo, double *hi, int *nbins);
+/* Attach a trained network to a BS_NS_MLP plan.  err_table[nbins] is the
+ * largest relative error of the learned segment integral seen on held-out
+ * samples in each log10(d_c/h) bin; pairs in bins whose error exceeds the
+ * plan's tol, or outside the sample box, use the adaptive integrator.  The
+ * plan keeps the pointer: the network must outlive its use by the plan. */
+int bs_set_mlp(bs_plan_t plan, bs_mlp_t mlp, const float *err_table, int nbins);
+/* Synchronise; number of flagged near-singular pairs of the loaded
+ * filaments, and number of adaptive fallbacks of the learned path since the
+ * last call (which resets it). */
+int bs_ns_counts(bs_plan_t plan, int64_t *npairs, int64_t *nfallback);
 
 /* Parameters actually used (all derived fields filled). */
 int bs_get_params(bs_plan_t plan, bs_params *resolved);

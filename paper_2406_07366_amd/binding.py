@@ -27,7 +27,9 @@ _CODES = {0: "BS_OK", -1: "BS_EINVAL", -2: "BS_EMINIMG", -3: "BS_ETOL", -4: "BS_
 EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_velocity",
             "bs_velocity_terms", "bs_energy", "bs_vorticity_modes", "bs_geometry",
             "bs_status", "bs_set_profiling", "bs_stage_times", "bs_get_params",
-            "bs_destroy", "bs_last_error"]
+            "bs_destroy", "bs_last_error", "bs_mlp_nparams", "bs_mlp_create",
+            "bs_mlp_forward", "bs_mlp_loss_grad", "bs_mlp_adam_step", "bs_mlp_get_params",
+            "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_set_mlp", "bs_ns_counts", "bs_rk4_step"]
 
 NSTAGES = 10
 STAGES = ["geometry", "binning", "local_self", "spread", "fft_fwd", "spectral", "fft_inv",
@@ -80,6 +82,19 @@ _lib.bs_stage_times.argtypes = [_vp, _vp, _vp, C.c_int]
 _lib.bs_destroy.argtypes = [_vp]
 _lib.bs_last_error.argtypes = [_vp]
 _lib.bs_last_error.restype = C.c_char_p
+_lib.bs_mlp_nparams.restype = C.c_int
+_lib.bs_mlp_create.argtypes = [_vp, _vp, C.POINTER(_vp)]
+_lib.bs_mlp_forward.argtypes = [_vp, C.c_int64, _vp, _vp]
+_lib.bs_mlp_loss_grad.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp]
+_lib.bs_mlp_adam_step.argtypes = [_vp, C.c_int64, _vp, _vp, C.c_float, C.c_float, C.c_float,
+                                  C.c_float, _vp]
+_lib.bs_mlp_get_params.argtypes = [_vp, _vp]
+_lib.bs_mlp_destroy.argtypes = [_vp]
+_lib.bs_ns_samples.argtypes = [C.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.bs_ns_error_bins.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
+_lib.bs_set_mlp.argtypes = [_vp, _vp, _vp, C.c_int]
+_lib.bs_ns_counts.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+_lib.bs_rk4_step.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int64), _vp, _vp, C.c_double]
 
 
 def lib():
@@ -206,6 +221,24 @@ class Plan:
     def status(self):
         _check(_lib.bs_status(self._h), self._h)
 
+    def rk4_step(self, offsets, xyz, gamma, dt):
+        """Advance device positions xyz in place by one RK4 step."""
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        _check(_lib.bs_rk4_step(self._h, len(off) - 1, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                _ptr(xyz), _ptr(gamma), float(dt)), self._h)
+        self.N = int(off[-1])
+        self.nfil = len(off) - 1
+
+    def set_mlp(self, mlp, err_table):
+        tab = np.ascontiguousarray(err_table, dtype=np.float32)
+        self._mlp = mlp          # keep the network alive while the plan uses it
+        _check(_lib.bs_set_mlp(self._h, mlp._h, tab.ctypes.data_as(_vp), len(tab)), self._h)
+
+    def ns_counts(self):
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(_lib.bs_ns_counts(self._h, C.byref(a), C.byref(b)), self._h)
+        return a.value, b.value
+
     def set_profiling(self, on: bool):
         _check(_lib.bs_set_profiling(self._h, int(bool(on))), self._h)
 
@@ -223,3 +256,100 @@ def load_workload(fs, device="cuda"):
     xyz = torch.from_numpy(np.ascontiguousarray(fs.xyz)).to(device)
     gamma = torch.from_numpy(np.ascontiguousarray(fs.gamma)).to(device)
     return xyz, gamma
+
+
+class MLP:
+    """Device copy of the 8-64-64-64-3 network (BF16 MFMA kernels)."""
+
+    def __init__(self, params, stream=None):
+        import torch
+        self._torch = torch
+        self.nparams = _lib.bs_mlp_nparams()
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (self.nparams,)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _vp()
+        _check(_lib.bs_mlp_create(p.ctypes.data_as(_vp), _vp(stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bs_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _f32(t):
+        assert t.is_cuda and t.dtype.is_floating_point
+        return t.float().contiguous()
+
+    def forward(self, X):
+        torch = self._torch
+        X = self._f32(X)
+        Y = torch.empty((X.shape[0], 3), dtype=torch.float32, device="cuda")
+        _check(_lib.bs_mlp_forward(self._h, X.shape[0], _ptr(X), _ptr(Y)))
+        return Y
+
+    def loss_grad(self, X, T):
+        torch = self._torch
+        X, T = self._f32(X), self._f32(T)
+        loss = torch.empty((1,), dtype=torch.float32, device="cuda")
+        grad = torch.empty((self.nparams,), dtype=torch.float32, device="cuda")
+        _check(_lib.bs_mlp_loss_grad(self._h, X.shape[0], _ptr(X), _ptr(T), _ptr(loss),
+                                     _ptr(grad)))
+        return loss, grad
+
+    def adam_step(self, X, T, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
+        _check(_lib.bs_mlp_adam_step(self._h, X.shape[0], _ptr(X), _ptr(T), lr, beta1, beta2,
+                                     eps, _ptr(loss)))
+
+    def params(self):
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(_lib.bs_mlp_get_params(self._h, out.ctypes.data_as(_vp)))
+        return out
+
+
+def bf16_round(a):
+    """float32 -> nearest-even bfloat16, returned as float32 (host helper for
+    comparing against the device's BF16 weights)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def mlp_init(seed=0):
+    """He-style initial parameters of the 8-64-64-64-3 network."""
+    rng = np.random.default_rng(seed)
+    dims = [8, 64, 64, 64, 3]
+    parts = []
+    for i in range(4):
+        fan_in = dims[i]
+        parts.append(rng.standard_normal((dims[i + 1], fan_in)).ravel() * np.sqrt(2.0 / fan_in))
+        parts.append(np.zeros(dims[i + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def ns_error_bins():
+    lo, hi, nb = C.c_double(), C.c_double(), C.c_int()
+    _check(_lib.bs_ns_error_bins(C.byref(lo), C.byref(hi), C.byref(nb)))
+    return lo.value, hi.value, nb.value
+
+
+def ns_samples(U, aux=True):
+    """Features, targets (and aux) for uniforms U (device float64 [n][8])."""
+    import torch
+    assert U.is_cuda and U.dtype == torch.float64 and U.is_contiguous() and U.shape[1] == 8
+    n = U.shape[0]
+    X = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+    T = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    A = torch.empty((n, 4), dtype=torch.float64, device="cuda") if aux else None
+    _check(_lib.bs_ns_samples(n, _ptr(U), _ptr(X), _ptr(T), _ptr(A),
+                              _vp(torch.cuda.current_stream().cuda_stream)))
+    return X, T, A

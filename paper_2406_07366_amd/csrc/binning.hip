@@ -93,92 +93,138 @@ void exclusive_scan(bs_plan_t p, const int *in, int *out, int n) {
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanBlock), 0, p->stream, in, n, sums, out);
 }
 
-// ---------------------------------------------------------------- keys
-__global__ void k_keys_spread(int M, const double *__restrict__ pos, double L, double inv_h,
-                              int w, int n, int T, int NT, int *__restrict__ key,
-                              int *__restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    double f;
-    int bx = stencil_base(wrap_box(pos[3 * i], L), inv_h, w, n, &f);
-    int by = stencil_base(wrap_box(pos[3 * i + 1], L), inv_h, w, n, &f);
-    int bz = stencil_base(wrap_box(pos[3 * i + 2], L), inv_h, w, n, &f);
-    int k = ((bz / T) * NT + by / T) * NT + bx / T;
-    key[i] = k;
-    atomicAdd(&cnt[k], 1);
-}
-
-__global__ void k_keys_cell(int M, const double *__restrict__ pos, double L, int nc,
-                            int *__restrict__ key, int *__restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    int c[3];
-    for (int q = 0; q < 3; q++) {
-        int v = (int)(wrap_box(pos[3 * i + q], L) / L * nc);
-        c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
-    }
-    int k = (c[2] * nc + c[1]) * nc + c[0];
-    key[i] = k;
-    atomicAdd(&cnt[k], 1);
-}
-
-__global__ void k_scatter(int M, const int *__restrict__ key, const int *__restrict__ start,
-                          int *__restrict__ fill, int *__restrict__ perm) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    int k = key[i];
-    perm[start[k] + atomicAdd(&fill[k], 1)] = i;
-}
-
-// Order each bin by original index: one wavefront per bin computes every
+// Bins are ordered by original index: one wavefront per bin computes every
 // entry's rank (number of smaller indices in the bin) and writes it to its
 // rank slot.  Bins of up to kSortLds entries are ranked in LDS and written
-// back in place; larger bins are ranked from global memory into `scratch`
-// (the key array, free once the scatter is done) and copied back.
+// back in place; larger bins are ranked from global memory into the key array
+// (free once the scatter is done) and copied back.
 constexpr int kSortLds = 2048;
 
-__global__ __launch_bounds__(64) void k_sort_bins(int nbins, const int *__restrict__ start,
-                                                  int *__restrict__ perm,
-                                                  int *__restrict__ scratch) {
+// ------------------------------------------------------- fused bin passes
+// The three sorts (quadrature points by spread tile, quadrature points by pair
+// cell, nodes by pair cell) run side by side: each pass below is one launch
+// covering all three.
+struct SortSet {
+    int *key[3], *cnt[3], *start[3], *fill[3], *perm[3];
+    int nbins[3], nitems[3];
+};
+
+__global__ void k_zero_bins(SortSet S) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int a = 0; a < 3; a++)
+        if (i <= S.nbins[a]) { S.cnt[a][i] = 0; S.fill[a][i] = 0; }
+}
+
+__global__ void k_keys_all(SortSet S, const double *__restrict__ qpos,
+                           const double *__restrict__ x, double L, double inv_h, int w, int n,
+                           int T, int NT, int nc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Mq = S.nitems[0];
+    if (i < Mq) {
+        double f;
+        double w0 = wrap_box(qpos[3 * i], L), w1 = wrap_box(qpos[3 * i + 1], L),
+               w2 = wrap_box(qpos[3 * i + 2], L);
+        int bx = stencil_base(w0, inv_h, w, n, &f);
+        int by = stencil_base(w1, inv_h, w, n, &f);
+        int bz = stencil_base(w2, inv_h, w, n, &f);
+        int k = ((bz / T) * NT + by / T) * NT + bx / T;
+        S.key[0][i] = k;
+        atomicAdd(&S.cnt[0][k], 1);
+        double ws[3] = {w0, w1, w2};
+        int c[3];
+        for (int q = 0; q < 3; q++) {
+            int v = (int)(ws[q] / L * nc);
+            c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+        }
+        k = (c[2] * nc + c[1]) * nc + c[0];
+        S.key[1][i] = k;
+        atomicAdd(&S.cnt[1][k], 1);
+    } else if (i < Mq + S.nitems[2]) {
+        int j = i - Mq;
+        int c[3];
+        for (int q = 0; q < 3; q++) {
+            int v = (int)(wrap_box(x[3 * j + q], L) / L * nc);
+            c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+        }
+        int k = (c[2] * nc + c[1]) * nc + c[0];
+        S.key[2][j] = k;
+        atomicAdd(&S.cnt[2][k], 1);
+    }
+}
+
+// one workgroup per array: exclusive scan of cnt into start (start[n] = total)
+__global__ __launch_bounds__(1024) void k_scan_small(SortSet S) {
+    __shared__ int sh[1024];
+    const int a = blockIdx.x;
+    const int n = S.nbins[a];
+    const int *in = S.cnt[a];
+    int *out = S.start[a];
+    int carry = 0;
+    for (int c0 = 0; c0 < n; c0 += 1024 * 4) {
+        int base = c0 + threadIdx.x * 4, v[4], s = 0;
+        for (int k = 0; k < 4; k++) { v[k] = (base + k < n) ? in[base + k] : 0; s += v[k]; }
+        int tot;
+        int ex = block_exclusive_scan(s, sh, &tot) + carry;
+        for (int k = 0; k < 4; k++) {
+            if (base + k < n) out[base + k] = ex;
+            ex += v[k];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void k_scatter_all(SortSet S) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = 0;
+    if (i >= S.nitems[0]) { i -= S.nitems[0]; a = 1; }
+    if (a == 1 && i >= S.nitems[1]) { i -= S.nitems[1]; a = 2; }
+    if (a == 2 && i >= S.nitems[2]) return;
+    int k = S.key[a][i];
+    S.perm[a][S.start[a][k] + atomicAdd(&S.fill[a][k], 1)] = i;
+}
+
+__global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
+    int b = blockIdx.x, a = 0;
+    if (b >= S.nbins[0]) { b -= S.nbins[0]; a = 1; }
+    if (a == 1 && b >= S.nbins[1]) { b -= S.nbins[1]; a = 2; }
+    if (a == 2 && b >= S.nbins[2]) return;
+    // reuse the single-array body
     __shared__ int v[kSortLds];
-    int b = blockIdx.x;
-    if (b >= nbins) return;
-    int s = start[b], n = start[b + 1] - s;
+    int s = S.start[a][b], n = S.start[a][b + 1] - s;
+    int *perm = S.perm[a], *scratch = S.key[a];
     if (n <= 1) return;
     if (n <= kSortLds) {
         for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = perm[s + i];
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            int x = v[i], r = 0;
-            for (int j = 0; j < n; j++) r += (v[j] < x);
-            perm[s + r] = x;
+            int xv = v[i], r = 0;
+            for (int j = 0; j < n; j++) r += (v[j] < xv);
+            perm[s + r] = xv;
         }
         return;
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int x = perm[s + i], r = 0;
-        for (int j = 0; j < n; j++) r += (perm[s + j] < x);
-        scratch[s + r] = x;
+        int xv = perm[s + i], r = 0;
+        for (int j = 0; j < n; j++) r += (perm[s + j] < xv);
+        scratch[s + r] = xv;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) perm[s + i] = scratch[s + i];
 }
 
-__global__ void k_fill_int(int *p, int n, int v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-// -------------------------------------------------- sorted copies for spread
+// sorted copies for the spread (by tile) and the pairs (by cell), one pass
 template <typename R>
-__global__ void k_gather_spread(int M, int w, const int *__restrict__ perm,
-                                const double *__restrict__ pos, const double *__restrict__ chg,
-                                double L, double inv_h, int n, double zeta, double inv_den,
-                                int4 *__restrict__ base, R *__restrict__ ker,
-                                R *__restrict__ q) {
+__global__ void k_gather_all(int M, int w, int Q, const int *__restrict__ sperm,
+                             const int *__restrict__ pperm, const double *__restrict__ pos,
+                             const double *__restrict__ chg, double L, double inv_h, int n,
+                             double zeta, double inv_den, int4 *__restrict__ base,
+                             R *__restrict__ ker, R *__restrict__ q, double4 *__restrict__ spos,
+                             R *__restrict__ schg, int *__restrict__ sseg) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
-    int o = perm[p];
+    int o = sperm[p];
     int b[3];
     double half = 0.5 * w;
     for (int d = 0; d < 3; d++) {
@@ -188,35 +234,14 @@ __global__ void k_gather_spread(int M, int w, const int *__restrict__ perm,
             ker[((size_t)p * 3 + d) * w + k] = (R)kb_phi((k - f) / half, zeta, inv_den);
     }
     base[p] = make_int4(b[0], b[1], b[2], 0);
-    q[4 * (size_t)p + 0] = (R)chg[3 * o + 0];
-    q[4 * (size_t)p + 1] = (R)chg[3 * o + 1];
-    q[4 * (size_t)p + 2] = (R)chg[3 * o + 2];
+    for (int c = 0; c < 3; c++) q[4 * (size_t)p + c] = (R)chg[3 * o + c];
     q[4 * (size_t)p + 3] = (R)0;
-}
-
-// ---------------------------------------------------- sorted copies for pairs
-template <typename R>
-__global__ void k_gather_pairs(int M, int Q, const int *__restrict__ perm,
-                               const double *__restrict__ pos, const double *__restrict__ chg,
-                               double L, double4 *__restrict__ spos, R *__restrict__ schg,
-                               int *__restrict__ sseg) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
-    int o = perm[p];
+    o = pperm[p];
     spos[p] = make_double4(wrap_box(pos[3 * o], L), wrap_box(pos[3 * o + 1], L),
                            wrap_box(pos[3 * o + 2], L), 0.0);
-    schg[4 * (size_t)p + 0] = (R)chg[3 * o + 0];
-    schg[4 * (size_t)p + 1] = (R)chg[3 * o + 1];
-    schg[4 * (size_t)p + 2] = (R)chg[3 * o + 2];
+    for (int c = 0; c < 3; c++) schg[4 * (size_t)p + c] = (R)chg[3 * o + c];
     schg[4 * (size_t)p + 3] = (R)0;
     sseg[p] = o / Q;
-}
-
-// ---------------------------------------------------------------- driver
-static void zero_bins(bs_plan_t p, int nbins, int *cnt, int *fill) {
-    int bs = 256;
-    hipLaunchKernelGGL(k_fill_int, dim3(ceil_div(nbins, bs)), dim3(bs), 0, p->stream, cnt, nbins, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(ceil_div(nbins, bs)), dim3(bs), 0, p->stream, fill, nbins, 0);
 }
 
 void build_bins(bs_plan_t p) {
@@ -224,62 +249,41 @@ void build_bins(bs_plan_t p) {
     const int M = (int)p->Nq, N = (int)p->N;
     const double L = p->prm.L, inv_h = p->n / L;
     const int w = p->prm.w, n = p->n;
-    // --- spread tiles
-    int ntiles = p->NT * p->NT * p->NT;
-    int *key = (int *)p->sp_key.p, *cnt = (int *)p->sp_cnt.p, *start = (int *)p->sp_start.p,
-        *fill = (int *)p->sp_fill.p, *perm = (int *)p->sp_perm.p;
-    zero_bins(p, ntiles, cnt, fill);
-    hipLaunchKernelGGL(k_keys_spread, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M,
-                       (const double *)p->d_qpos.p, L, inv_h, w, n, p->T, p->NT, key, cnt);
-    exclusive_scan(p, cnt, start, ntiles);
-    hipLaunchKernelGGL(k_scatter, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M, key, start,
-                       fill, perm);
-    hipLaunchKernelGGL(k_sort_bins, dim3(ntiles), dim3(64), 0, p->stream, ntiles, start, perm,
-                       key);
+    const int ntiles = p->NT * p->NT * p->NT, nc3 = p->nc * p->nc * p->nc;
+    SortSet S;
+    S.key[0] = (int *)p->sp_key.p; S.cnt[0] = (int *)p->sp_cnt.p; S.start[0] = (int *)p->sp_start.p;
+    S.fill[0] = (int *)p->sp_fill.p; S.perm[0] = (int *)p->sp_perm.p;
+    S.key[1] = (int *)p->pq_key.p; S.cnt[1] = (int *)p->pq_cnt.p; S.start[1] = (int *)p->pq_start.p;
+    S.fill[1] = (int *)p->pq_fill.p; S.perm[1] = (int *)p->pq_perm.p;
+    S.key[2] = (int *)p->nd_key.p; S.cnt[2] = (int *)p->nd_cnt.p; S.start[2] = (int *)p->nd_start.p;
+    S.fill[2] = (int *)p->nd_fill.p; S.perm[2] = (int *)p->nd_perm.p;
+    S.nbins[0] = ntiles; S.nbins[1] = nc3; S.nbins[2] = nc3;
+    S.nitems[0] = M; S.nitems[1] = M; S.nitems[2] = N;
+    const int maxb = ntiles > nc3 ? ntiles : nc3;
+    hipLaunchKernelGGL(k_zero_bins, dim3(ceil_div(maxb + 1, bs)), dim3(bs), 0, p->stream, S);
+    hipLaunchKernelGGL(k_keys_all, dim3(ceil_div(M + N, bs)), dim3(bs), 0, p->stream, S,
+                       (const double *)p->d_qpos.p, (const double *)p->d_x.p, L, inv_h, w, n,
+                       p->T, p->NT, p->nc);
+    if (maxb <= (1 << 16)) {
+        hipLaunchKernelGGL(k_scan_small, dim3(3), dim3(1024), 0, p->stream, S);
+    } else {
+        for (int a = 0; a < 3; a++) exclusive_scan(p, S.cnt[a], S.start[a], S.nbins[a]);
+    }
+    hipLaunchKernelGGL(k_scatter_all, dim3(ceil_div(2 * M + N, bs)), dim3(bs), 0, p->stream, S);
+    hipLaunchKernelGGL(k_sort_all, dim3(ntiles + 2 * nc3), dim3(64), 0, p->stream, S);
     const double zeta = p->prm.zeta, inv_den = 1.0 / (-expm1(-2.0 * zeta));
     if (p->fp32)
-        hipLaunchKernelGGL(k_gather_spread<float>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream,
-                           M, w, perm, (const double *)p->d_qpos.p, (const double *)p->d_qchg.p,
-                           L, inv_h, n, zeta, inv_den, (int4 *)p->sp_base.p,
-                           (float *)p->sp_ker.p, (float *)p->sp_q.p);
-    else
-        hipLaunchKernelGGL(k_gather_spread<double>, dim3(ceil_div(M, bs)), dim3(bs), 0,
-                           p->stream, M, w, perm, (const double *)p->d_qpos.p,
+        hipLaunchKernelGGL(k_gather_all<float>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M,
+                           w, p->Q, S.perm[0], S.perm[1], (const double *)p->d_qpos.p,
                            (const double *)p->d_qchg.p, L, inv_h, n, zeta, inv_den,
-                           (int4 *)p->sp_base.p, (double *)p->sp_ker.p, (double *)p->sp_q.p);
-
-    // --- pair cells for quadrature points
-    int nc3 = p->nc * p->nc * p->nc;
-    key = (int *)p->pq_key.p; cnt = (int *)p->pq_cnt.p; start = (int *)p->pq_start.p;
-    fill = (int *)p->pq_fill.p; perm = (int *)p->pq_perm.p;
-    zero_bins(p, nc3, cnt, fill);
-    hipLaunchKernelGGL(k_keys_cell, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M,
-                       (const double *)p->d_qpos.p, L, p->nc, key, cnt);
-    exclusive_scan(p, cnt, start, nc3);
-    hipLaunchKernelGGL(k_scatter, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M, key, start,
-                       fill, perm);
-    hipLaunchKernelGGL(k_sort_bins, dim3(nc3), dim3(64), 0, p->stream, nc3, start, perm, key);
-    if (p->fp32)
-        hipLaunchKernelGGL(k_gather_pairs<float>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream,
-                           M, p->Q, perm, (const double *)p->d_qpos.p,
-                           (const double *)p->d_qchg.p, L, (double4 *)p->pq_pos.p,
-                           (float *)p->pq_chg.p, (int *)p->pq_seg.p);
+                           (int4 *)p->sp_base.p, (float *)p->sp_ker.p, (float *)p->sp_q.p,
+                           (double4 *)p->pq_pos.p, (float *)p->pq_chg.p, (int *)p->pq_seg.p);
     else
-        hipLaunchKernelGGL(k_gather_pairs<double>, dim3(ceil_div(M, bs)), dim3(bs), 0,
-                           p->stream, M, p->Q, perm, (const double *)p->d_qpos.p,
-                           (const double *)p->d_qchg.p, L, (double4 *)p->pq_pos.p,
-                           (double *)p->pq_chg.p, (int *)p->pq_seg.p);
-
-    // --- nodes by pair cell
-    key = (int *)p->nd_key.p; cnt = (int *)p->nd_cnt.p; start = (int *)p->nd_start.p;
-    fill = (int *)p->nd_fill.p; perm = (int *)p->nd_perm.p;
-    zero_bins(p, nc3, cnt, fill);
-    hipLaunchKernelGGL(k_keys_cell, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
-                       (const double *)p->d_x.p, L, p->nc, key, cnt);
-    exclusive_scan(p, cnt, start, nc3);
-    hipLaunchKernelGGL(k_scatter, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, key, start,
-                       fill, perm);
-    hipLaunchKernelGGL(k_sort_bins, dim3(nc3), dim3(64), 0, p->stream, nc3, start, perm, key);
+        hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream,
+                           M, w, p->Q, S.perm[0], S.perm[1], (const double *)p->d_qpos.p,
+                           (const double *)p->d_qchg.p, L, inv_h, n, zeta, inv_den,
+                           (int4 *)p->sp_base.p, (double *)p->sp_ker.p, (double *)p->sp_q.p,
+                           (double4 *)p->pq_pos.p, (double *)p->pq_chg.p, (int *)p->pq_seg.p);
 }
 
 }  // namespace bs

@@ -255,8 +255,6 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
     bs_params r;
     int rc = resolve(p, &r);
     if (rc) return rc;
-    if (r.ns_mode == BS_NS_MLP)
-        return set_error(nullptr, BS_EINVAL, "BS_NS_MLP is not available in this build");
     bs_plan_t P = new bs_plan_s();
     P->prm = r;
     P->stream = (hipStream_t)hip_stream;
@@ -356,6 +354,10 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
                 (rc = ensure<int>(P, P->ns_start, N + 1)) || (rc = ensure<int2>(P, P->ns_pairs, mp)) ||
                 (rc = ensure<int>(P, P->ns_pnode, mp)) || (rc = ensure<double>(P, P->ns_pout, 3 * mp)))
                 return rc;
+            if (P->prm.ns_mode == BS_NS_MLP &&
+                ((rc = ensure<float>(P, P->ns_X, 8 * mp)) || (rc = ensure<float>(P, P->ns_Y, 3 * mp)) ||
+                 (rc = ensure<int>(P, P->ns_fallback, 1))))
+                return rc;
         }
         std::vector<int> off32(nfil + 1), fil32(N);
         for (int64_t f = 0; f <= nfil; f++) off32[f] = (int)offsets[f];
@@ -394,6 +396,16 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     return BS_OK;
 }
 
+static int launch_ns(bs_plan_t P, double *out) {
+    if (P->prm.ns_mode == BS_NS_ADAPTIVE) {
+        launch_ns_adaptive(P, out);
+        return BS_OK;
+    }
+    if (!P->mlp) return set_error(P, BS_ESTATE, "BS_NS_MLP plan without bs_set_mlp");
+    launch_ns_mlp(P, out);
+    return BS_OK;
+}
+
 static int long_range(bs_plan_t P, int psi, double *out) {
     int rc;
     stage_begin(P, 3);
@@ -428,7 +440,7 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     stage_end(P, 8);
     if (P->prm.ns_mode != BS_NS_OFF) {
         stage_begin(P, 9);
-        launch_ns_adaptive(P, v_out);
+        if ((rc = launch_ns(P, v_out))) return rc;
         stage_end(P, 9);
     }
     if ((rc = launch_status(P, "pair kernel"))) return rc;
@@ -454,7 +466,7 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
     }
     if (v_ns) {
         fill_f64(P, v_ns, n3, 0.0);
-        if (P->prm.ns_mode != BS_NS_OFF) launch_ns_adaptive(P, v_ns);
+        if (P->prm.ns_mode != BS_NS_OFF && (rc = launch_ns(P, v_ns))) return rc;
     }
     return launch_status(P, "velocity terms");
 }
@@ -523,6 +535,76 @@ int bs_status(bs_plan_t P) {
     return BS_OK;
 }
 
+// classical RK4 stage helpers on [N][3] float64 arrays
+__global__ void k_axpy_stage(size_t n, const double *__restrict__ x, const double *__restrict__ k,
+                             double c, double *__restrict__ y) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] + c * k[i];
+}
+__global__ void k_rk4_final(size_t n, double *__restrict__ x, const double *__restrict__ k1,
+                            const double *__restrict__ k2, const double *__restrict__ k3,
+                            const double *__restrict__ k4, double dt) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+int bs_rk4_step(bs_plan_t P, int64_t nfil, const int64_t *offsets, double *xyz,
+                const double *gamma, double dt) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (!offsets || nfil < 1 || !xyz || !gamma || !std::isfinite(dt))
+        return set_error(P, BS_EINVAL, "bad arguments");
+    const int64_t N = offsets[nfil];
+    const size_t n3 = 3 * (size_t)N;
+    int rc;
+    if ((rc = ensure<double>(P, P->rk_k, 4 * n3)) || (rc = ensure<double>(P, P->rk_s, n3))) return rc;
+    double *k = (double *)P->rk_k.p, *s = (double *)P->rk_s.p;
+    const dim3 g((unsigned)((n3 + 255) / 256)), b(256);
+    const double c[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+    for (int st = 0; st < 4; st++) {
+        const double *pos = xyz;
+        if (st > 0) {
+            hipLaunchKernelGGL(k_axpy_stage, g, b, 0, P->stream, n3, xyz, k + (st - 1) * n3, c[st], s);
+            pos = s;
+        }
+        if ((rc = bs_set_filaments(P, nfil, offsets, pos, gamma))) return rc;
+        if ((rc = bs_velocity(P, k + st * n3))) return rc;
+    }
+    hipLaunchKernelGGL(k_rk4_final, g, b, 0, P->stream, n3, xyz, k, k + n3, k + 2 * n3, k + 3 * n3, dt);
+    return launch_status(P, "rk4 kernels");
+}
+
+int bs_set_mlp(bs_plan_t P, bs_mlp_t mlp, const float *err_table, int nbins) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    int want = 0;
+    bs_ns_error_bins(nullptr, nullptr, &want);
+    if (P->prm.ns_mode != BS_NS_MLP) return set_error(P, BS_ESTATE, "plan is not BS_NS_MLP");
+    if (!mlp || !err_table || nbins != want)
+        return set_error(P, BS_EINVAL, "need a network and an error table of bs_ns_error_bins bins");
+    P->mlp = mlp;
+    for (int b = 0; b < nbins; b++) P->ns_err[b] = err_table[b];
+    return BS_OK;
+}
+
+int bs_ns_counts(bs_plan_t P, int64_t *npairs, int64_t *nfallback) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    int np = 0, nf = 0, rc;
+    if (P->prm.ns_mode != BS_NS_OFF && P->have_filaments) {
+        if ((rc = check_hip(P, hipMemcpyAsync(&np, (int *)P->ns_start.p + P->N, sizeof(int),
+                                              hipMemcpyDeviceToHost, P->stream), "read count")))
+            return rc;
+        if (P->prm.ns_mode == BS_NS_MLP && P->ns_fallback.p &&
+            (rc = check_hip(P, hipMemcpyAsync(&nf, P->ns_fallback.p, sizeof(int),
+                                              hipMemcpyDeviceToHost, P->stream), "read count")))
+            return rc;
+        if ((rc = check_hip(P, hipStreamSynchronize(P->stream), "sync"))) return rc;
+        if (P->ns_fallback.p)
+            (void)hipMemsetAsync(P->ns_fallback.p, 0, sizeof(int), P->stream);
+    }
+    if (npairs) *npairs = np;
+    if (nfallback) *nfallback = nf;
+    return BS_OK;
+}
+
 int bs_get_params(bs_plan_t P, bs_params *resolved) {
     if (!P || !resolved) return set_error(P, BS_EINVAL, "null argument");
     *resolved = P->prm;
@@ -545,7 +627,8 @@ int bs_destroy(bs_plan_t P) {
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
                    &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
                    &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->ns_maxell,
-                   &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout};
+                   &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout,
+                   &P->ns_X, &P->ns_Y, &P->ns_fallback, &P->rk_k, &P->rk_s};
     for (DBuf *b : all) release(*b);
     delete P;
     return BS_OK;

@@ -77,6 +77,12 @@ struct bs_plan_s {
     // near-singular pairs
     int ns_max_per_node = 32;
     bs::DBuf ns_maxell, ns_cnt, ns_start, ns_pairs, ns_pnode, ns_pout;
+    // learned correction
+    bs_mlp_t mlp = nullptr;
+    float ns_err[16] = {};
+    bs::DBuf ns_X, ns_Y, ns_fallback;
+    // RK4 stage buffers
+    bs::DBuf rk_k, rk_s;
     // terms (for velocity terms / energy)
     bs::DBuf tmp3;                             // f64 [N][3]
     // per-stage timing (diagnostics)
@@ -118,6 +124,10 @@ void launch_pairs(bs_plan_t p, int psi, double *out);
 // ns.hip
 void ns_build_pairs(bs_plan_t p);
 void launch_ns_adaptive(bs_plan_t p, double *v);
+void launch_ns_mlp(bs_plan_t p, double *v);
+// mlp.hip: inference with the sample count read on the device
+void mlp_forward_device(bs_mlp_t m, const int *Bdev, int64_t Bmax, const float *X, float *Y,
+                        hipStream_t stream);
 
 // energy.hip
 void launch_energy(bs_plan_t p, const double *psi, double *partial, int nblocks);

@@ -204,16 +204,11 @@ __device__ void ns_panel(const Seg &s, const double *x, double a, double b, cons
     }
 }
 
-// Exact segment integral minus its Q-point sum, for one (node, segment) pair.
-__device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, const double *x,
-                        const double *D, const double *dtau, const double *gamma,
-                        const double *qpos, const double *qchg, int Q, double L,
-                        const NsRule &R, double *out) {
-    double xs[3];
-    int shv[3] = {((sh >> 20) & 1023) - 512, ((sh >> 10) & 1023) - 512, (sh & 1023) - 512};
-    for (int q = 0; q < 3; q++) xs[q] = x[3 * o + q] + shv[q] * L;
-    Seg s = load_seg(sg, off, fil, x, D, dtau);
-    // closest point: best of a coarse scan, then Newton on (s - x) . s' = 0
+// Integral over u in [0,1] of (s(u) - x) x s'(u) / |s(u) - x|^3 for one
+// cubic segment: closest point by a coarse scan and Newton steps on
+// (s - x) . s' = 0, then 16-point Gauss-Legendre panels graded geometrically
+// (ratio 3) away from it.
+__device__ void ns_seg_integral(const Seg &s, const double *xs, const NsRule &R, double *acc) {
     double ub = 0.0, best = 1e300;
     for (int k = 0; k <= 8; k++) {
         double u = k / 8.0, r2 = 0.0;
@@ -248,11 +243,9 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
     // than the singularity's width
     double delta = 0.5 * sqrt(r2 / sp2);
     delta = delta < 1e-13 ? 1e-13 : delta;
-    double acc[3] = {0.0, 0.0, 0.0};
-    // centre panel
+    acc[0] = acc[1] = acc[2] = 0.0;
     double a0 = ub - delta < 0.0 ? 0.0 : ub - delta, b0 = ub + delta > 1.0 ? 1.0 : ub + delta;
     if (b0 > a0) ns_panel(s, xs, a0, b0, R, acc);
-    // left panels
     double edge = a0, width = delta;
     while (edge > 0.0) {
         double nxt = ub - 3.0 * width;
@@ -269,9 +262,12 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
         edge = nxt;
         width *= 3.0;
     }
-    const double g4 = gamma[fil[sg]] / (4.0 * kPi);
-    // subtract the Q-point sum the method used for this segment and image
-    double qs[3] = {0.0, 0.0, 0.0};
+}
+
+// (s_q - x) x q / |s_q - x|^3 summed over the Q points of segment sg
+__device__ void ns_qsum(int sg, const double *xs, const double *qpos, const double *qchg, int Q,
+                        double *qs) {
+    qs[0] = qs[1] = qs[2] = 0.0;
     for (int i = 0; i < Q; i++) {
         const double *qp = qpos + 3 * ((size_t)sg * Q + i), *qc = qchg + 3 * ((size_t)sg * Q + i);
         double r[3] = {qp[0] - xs[0], qp[1] - xs[1], qp[2] - xs[2]};
@@ -281,6 +277,25 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
         qs[1] += f * (r[2] * qc[0] - r[0] * qc[2]);
         qs[2] += f * (r[0] * qc[1] - r[1] * qc[0]);
     }
+}
+
+__device__ __forceinline__ void unpack_shift(int sh, const double *x, double L, double *xs) {
+    int shv[3] = {((sh >> 20) & 1023) - 512, ((sh >> 10) & 1023) - 512, (sh & 1023) - 512};
+    for (int q = 0; q < 3; q++) xs[q] = x[q] + shv[q] * L;
+}
+
+// Exact segment integral minus its Q-point sum, for one (node, segment) pair.
+__device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, const double *x,
+                        const double *D, const double *dtau, const double *gamma,
+                        const double *qpos, const double *qchg, int Q, double L,
+                        const NsRule &R, double *out) {
+    double xs[3];
+    unpack_shift(sh, x + 3 * o, L, xs);
+    Seg s = load_seg(sg, off, fil, x, D, dtau);
+    double acc[3], qs[3];
+    ns_seg_integral(s, xs, R, acc);
+    ns_qsum(sg, xs, qpos, qchg, Q, qs);
+    const double g4 = gamma[fil[sg]] / (4.0 * kPi);
     for (int q = 0; q < 3; q++) out[q] = g4 * acc[q] - qs[q] / (4.0 * kPi);
 }
 
@@ -321,6 +336,213 @@ __global__ void k_ns_apply(int N, const int *__restrict__ pstart, const double *
     v[3 * o] += s0;
     v[3 * o + 1] += s1;
     v[3 * o + 2] += s2;
+}
+
+// ------------------------------------------------------ learned correction
+// Chord frame of a segment A -> B (node slopes D0, D1): e1 along the chord,
+// e2 along the part of D0 normal to it (else of D1, else any normal), e3 =
+// e1 x e2; lengths in units of the chord h.  Features (8, float32):
+//   (x - M).e_k / h (3),  D0.e1, D0.e2,  D1.e1, D1.e2, D1.e3
+// with M the chord midpoint.  The segment in this frame is the cubic from
+// (-1/2,0,0) to (1/2,0,0) with end derivatives D0, D1 (chord-length knots
+// make d tau = h), so the integral is a function of the 8 features alone
+// (times 1/h).  The network predicts z = d_c * (I_seg - I_chord) in frame
+// components, d_c the distance from the target to the chord over h.
+constexpr double kNsThetaMax = 0.6;     // max angle of D0, D1 to the chord
+constexpr double kNsDmin = 0.9, kNsDmax = 1.1;   // |D0|, |D1| range
+constexpr double kNsRlo = 1e-3, kNsRhi = 1.1;    // d_c / h range
+constexpr int kNsBins = 12;                      // log10(d_c/h) bins of the error table
+
+struct NsBox {
+    float err[kNsBins];   // max relative error of the learned integral per bin
+    double tol;           // fall back where err > tol
+};
+
+// raw straight-segment integral  int (s - x) x ds / |s - x|^3  over A -> B
+__device__ __forceinline__ void chord_raw(const double *A, const double *B, const double *x,
+                                          double *out) {
+    double r1[3] = {A[0] - x[0], A[1] - x[1], A[2] - x[2]};
+    double r2[3] = {B[0] - x[0], B[1] - x[1], B[2] - x[2]};
+    double p = sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+    double q = sqrt(r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
+    double c[3] = {r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2],
+                   r1[0] * r2[1] - r1[1] * r2[0]};
+    double dt = r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2];
+    // p q + r1.r2 cancels when the target lies beside the segment; there it
+    // equals |r1 x r2|^2 / (p q - r1.r2)
+    double den = dt >= 0.0 ? p * q + dt : (c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) / (p * q - dt);
+    double f = (p + q) / (p * q * den);
+    out[0] = c[0] * f; out[1] = c[1] * f; out[2] = c[2] * f;
+}
+
+struct NsFrame {
+    double e[3][3];
+    double h, dc;   // chord length, distance to the chord over h
+    float f[8];
+    bool inbox;
+};
+
+__device__ NsFrame ns_frame(const double *A, const double *B, const double *D0, const double *D1,
+                            const double *x) {
+    NsFrame F;
+    double d[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    F.h = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double *e1 = F.e[0], *e2 = F.e[1], *e3 = F.e[2];
+    for (int q = 0; q < 3; q++) e1[q] = d[q] / F.h;
+    double a0 = D0[0] * e1[0] + D0[1] * e1[1] + D0[2] * e1[2];
+    double a1 = D1[0] * e1[0] + D1[1] * e1[1] + D1[2] * e1[2];
+    double p0[3], p1[3];
+    for (int q = 0; q < 3; q++) { p0[q] = D0[q] - a0 * e1[q]; p1[q] = D1[q] - a1 * e1[q]; }
+    double n0 = sqrt(p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);
+    double n1 = sqrt(p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2]);
+    if (n0 > 1e-12) for (int q = 0; q < 3; q++) e2[q] = p0[q] / n0;
+    else if (n1 > 1e-12) for (int q = 0; q < 3; q++) e2[q] = p1[q] / n1;
+    else {
+        int k = (fabs(e1[0]) < fabs(e1[1])) ? (fabs(e1[0]) < fabs(e1[2]) ? 0 : 2)
+                                            : (fabs(e1[1]) < fabs(e1[2]) ? 1 : 2);
+        double u[3] = {0.0, 0.0, 0.0};
+        u[k] = 1.0;
+        double t = u[0] * e1[0] + u[1] * e1[1] + u[2] * e1[2];
+        for (int q = 0; q < 3; q++) u[q] -= t * e1[q];
+        double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        for (int q = 0; q < 3; q++) e2[q] = u[q] / nu;
+    }
+    e3[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    e3[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    e3[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    double xl[3];
+    for (int k = 0; k < 3; k++) {
+        double s = 0.0;
+        for (int q = 0; q < 3; q++) s += (x[q] - 0.5 * (A[q] + B[q])) * F.e[k][q];
+        xl[k] = s / F.h;
+    }
+    double b0 = D0[0] * e2[0] + D0[1] * e2[1] + D0[2] * e2[2];
+    double b1 = D1[0] * e2[0] + D1[1] * e2[1] + D1[2] * e2[2];
+    double c1 = D1[0] * e3[0] + D1[1] * e3[1] + D1[2] * e3[2];
+    F.f[0] = (float)xl[0]; F.f[1] = (float)xl[1]; F.f[2] = (float)xl[2];
+    F.f[3] = (float)a0; F.f[4] = (float)b0; F.f[5] = (float)a1; F.f[6] = (float)b1;
+    F.f[7] = (float)c1;
+    double tc = xl[0] + 0.5;
+    double tcl = tc < 0.0 ? 0.0 : (tc > 1.0 ? 1.0 : tc);
+    F.dc = sqrt((tc - tcl) * (tc - tcl) + xl[1] * xl[1] + xl[2] * xl[2]);
+    double m0 = sqrt(a0 * a0 + b0 * b0), m1 = sqrt(a1 * a1 + b1 * b1 + c1 * c1);
+    double th0 = atan2(b0, a0), th1 = atan2(sqrt(b1 * b1 + c1 * c1), a1);
+    F.inbox = F.dc >= kNsRlo && F.dc <= kNsRhi && m0 >= kNsDmin && m0 <= kNsDmax &&
+              m1 >= kNsDmin && m1 <= kNsDmax && th0 <= kNsThetaMax && th1 <= kNsThetaMax;
+    return F;
+}
+
+__device__ __forceinline__ int ns_bin(double dc) {
+    double t = (log10(dc) - log10(kNsRlo)) / (log10(kNsRhi) - log10(kNsRlo));
+    int b = (int)(t * kNsBins);
+    return b < 0 ? 0 : (b >= kNsBins ? kNsBins - 1 : b);
+}
+
+// Training samples from caller-supplied uniforms U[n][8]: tangent angles and
+// lengths (U0..U4), position class and parameter (U5), distance (U6,
+// log-uniform over [kNsRlo, kNsRhi]) and azimuth (U7).  70 % of targets lie
+// beside the chord, 30 % on the hemispherical caps beyond either end.
+__global__ void k_ns_samples(int64_t n, const double *__restrict__ U, NsRule R,
+                             float *__restrict__ X, float *__restrict__ T,
+                             double *__restrict__ aux) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *u = U + 8 * i;
+    double th0 = kNsThetaMax * u[0], m0 = kNsDmin + (kNsDmax - kNsDmin) * u[1];
+    double th1 = kNsThetaMax * u[2], ps1 = 2.0 * kPi * u[3], m1 = kNsDmin + (kNsDmax - kNsDmin) * u[4];
+    double D0[3] = {m0 * cos(th0), m0 * sin(th0), 0.0};
+    double D1[3] = {m1 * cos(th1), m1 * sin(th1) * cos(ps1), m1 * sin(th1) * sin(ps1)};
+    double dc = kNsRlo * pow(kNsRhi / kNsRlo, u[6]), ph = 2.0 * kPi * u[7];
+    double x[3];
+    if (u[5] < 0.7) {
+        double tc = u[5] / 0.7;
+        x[0] = tc - 0.5; x[1] = dc * cos(ph); x[2] = dc * sin(ph);
+    } else {
+        double v = (u[5] - 0.7) / 0.3;
+        double sg = v < 0.5 ? -1.0 : 1.0;
+        double ct = 2.0 * v - floor(2.0 * v), st = sqrt(1.0 - ct * ct);
+        x[0] = sg * (0.5 + dc * ct); x[1] = dc * st * cos(ph); x[2] = dc * st * sin(ph);
+    }
+    const double A[3] = {-0.5, 0.0, 0.0}, B[3] = {0.5, 0.0, 0.0};
+    Seg s;
+    for (int q = 0; q < 3; q++) {
+        s.c0[q] = A[q];
+        s.c1[q] = D0[q];
+        s.c2[q] = 3.0 * (B[q] - A[q]) - 2.0 * D0[q] - D1[q];
+        s.c3[q] = 2.0 * (A[q] - B[q]) + D0[q] + D1[q];
+    }
+    double I[3], Ic[3];
+    ns_seg_integral(s, x, R, I);
+    chord_raw(A, B, x, Ic);
+    NsFrame F = ns_frame(A, B, D0, D1, x);
+    for (int k = 0; k < 8; k++) X[8 * i + k] = F.f[k];
+    for (int q = 0; q < 3; q++) T[3 * i + q] = (float)(F.dc * (I[q] - Ic[q]));
+    if (aux) {
+        aux[4 * i] = F.dc;
+        aux[4 * i + 1] = I[0]; aux[4 * i + 2] = I[1]; aux[4 * i + 3] = I[2];
+    }
+}
+
+__device__ __forceinline__ void pair_geometry(int o, int sg, int sh, const int *off, const int *fil,
+                                              const double *x, const double *D, double L,
+                                              double *A, double *B, double *D0, double *D1,
+                                              double *xs) {
+    int jn = next_node_d(off, fil, sg);
+    for (int q = 0; q < 3; q++) {
+        A[q] = x[3 * sg + q]; B[q] = x[3 * jn + q];
+        D0[q] = D[3 * sg + q]; D1[q] = D[3 * jn + q];
+    }
+    unpack_shift(sh, x + 3 * o, L, xs);
+}
+
+__global__ __launch_bounds__(256) void k_ns_features(
+    const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
+    const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
+    const double *__restrict__ D, double L, float *__restrict__ X) {
+    const int P = *total;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        int2 pr = pairs[p];
+        double A[3], B[3], D0[3], D1[3], xs[3];
+        pair_geometry(pnode[p], pr.x, pr.y, off, fil, x, D, L, A, B, D0, D1, xs);
+        NsFrame F = ns_frame(A, B, D0, D1, xs);
+        for (int k = 0; k < 8; k++) X[8 * (size_t)p + k] = F.f[k];
+    }
+}
+
+// learned integral where the error table allows it, adaptive elsewhere
+__global__ __launch_bounds__(256) void k_ns_combine(
+    const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
+    const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
+    const double *__restrict__ D, const double *__restrict__ dtau,
+    const double *__restrict__ gamma, const double *__restrict__ qpos,
+    const double *__restrict__ qchg, int Q, double L, NsRule R, NsBox box,
+    const float *__restrict__ Y, double *__restrict__ pout, int *__restrict__ nfallback) {
+    const int P = *total;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        int2 pr = pairs[p];
+        const int o = pnode[p];
+        double A[3], B[3], D0[3], D1[3], xs[3];
+        pair_geometry(o, pr.x, pr.y, off, fil, x, D, L, A, B, D0, D1, xs);
+        NsFrame F = ns_frame(A, B, D0, D1, xs);
+        double out[3];
+        if (!F.inbox || (double)box.err[ns_bin(F.dc)] > box.tol) {
+            ns_pair(o, pr.x, pr.y, off, fil, x, D, dtau, gamma, qpos, qchg, Q, L, R, out);
+            atomicAdd(nfallback, 1);
+        } else {
+            double Ic[3], qs[3], y[3];
+            chord_raw(A, B, xs, Ic);
+            for (int k = 0; k < 3; k++) y[k] = (double)Y[3 * (size_t)p + k] / F.dc;
+            ns_qsum(pr.x, xs, qpos, qchg, Q, qs);
+            const double g4 = gamma[fil[pr.x]] / (4.0 * kPi);
+            for (int q = 0; q < 3; q++) {
+                double yw = F.e[0][q] * y[0] + F.e[1][q] * y[1] + F.e[2][q] * y[2];
+                out[q] = g4 * (Ic[q] + yw / F.h) - qs[q] / (4.0 * kPi);
+            }
+        }
+        pout[3 * (size_t)p] = out[0];
+        pout[3 * (size_t)p + 1] = out[1];
+        pout[3 * (size_t)p + 2] = out[2];
+    }
 }
 
 static NsArgs ns_args(bs_plan_t p) {
@@ -369,4 +591,50 @@ void launch_ns_adaptive(bs_plan_t p, double *v) {
                        (const double *)p->ns_pout.p, v);
 }
 
+void launch_ns_mlp(bs_plan_t p, double *v) {
+    const int N = (int)p->N;
+    NsRule R;
+    ns_rule(&R);
+    const int *start = (const int *)p->ns_start.p;
+    const int *total = start + N;
+    hipLaunchKernelGGL(k_ns_features, dim3(1024), dim3(256), 0, p->stream, total,
+                       (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
+                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
+                       (const double *)p->d_x.p, (const double *)p->d_D.p, p->prm.L,
+                       (float *)p->ns_X.p);
+    mlp_forward_device(p->mlp, total, (int64_t)N * p->ns_max_per_node, (const float *)p->ns_X.p,
+                       (float *)p->ns_Y.p, p->stream);
+    NsBox box;
+    for (int b = 0; b < kNsBins; b++) box.err[b] = p->ns_err[b];
+    box.tol = p->prm.tol;
+    hipLaunchKernelGGL(k_ns_combine, dim3(1024), dim3(256), 0, p->stream, total,
+                       (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
+                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
+                       (const double *)p->d_x.p, (const double *)p->d_D.p,
+                       (const double *)p->d_dtau.p, (const double *)p->d_gamma.p,
+                       (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q,
+                       p->prm.L, R, box, (const float *)p->ns_Y.p, (double *)p->ns_pout.p,
+                       (int *)p->ns_fallback.p);
+    hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(N, 256)), dim3(256), 0, p->stream, N, start,
+                       (const double *)p->ns_pout.p, v);
+}
+
 }  // namespace bs
+
+extern "C" int bs_ns_samples(int64_t n, const double *U, float *X, float *T, double *aux,
+                             void *hip_stream) {
+    if (n < 0 || (n > 0 && (!U || !X || !T))) return BS_EINVAL;
+    if (n == 0) return BS_OK;
+    bs::NsRule R;
+    bs::ns_rule(&R);
+    hipLaunchKernelGGL(bs::k_ns_samples, dim3((unsigned)((n + 127) / 128)), dim3(128), 0,
+                       (hipStream_t)hip_stream, n, U, R, X, T, aux);
+    return hipGetLastError() == hipSuccess ? BS_OK : BS_EDEVICE;
+}
+
+extern "C" int bs_ns_error_bins(double *lo, double *hi, int *nbins) {
+    if (lo) *lo = bs::kNsRlo;
+    if (hi) *hi = bs::kNsRhi;
+    if (nbins) *nbins = bs::kNsBins;
+    return BS_OK;
+}

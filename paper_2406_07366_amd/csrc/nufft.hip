@@ -24,29 +24,39 @@ namespace bs {
 // ----------------------------------------------------------------- spread
 // Candidates (points whose stencil base lies in one of the nbv^3 bins that
 // can reach this tile) are staged in LDS in batches of kSpreadBatch by all
-// threads at once; then each wavefront takes candidates in turn, its lanes
-// covering the (ky, kz) rows of the stencil, and adds the row's cells that
-// fall in the tile into the LDS tile with LDS atomics.
+// threads at once.  Each wavefront then takes candidates in turn; its lanes
+// cover the (kx, ky) columns of the stencil (so the 64 lanes of one LDS
+// instruction touch distinct, mostly consecutive words) and loop over kz.
+// Every wavefront accumulates into its own LDS copy of the tile with plain
+// adds (lanes never collide within an instruction), and the copies are summed
+// in wavefront order when the tile is written: no atomics, and the summation
+// order is fixed, so the grid is bitwise reproducible.
 constexpr int kSpreadBatch = 64;
+constexpr int kSpreadWaves = 4;
 
 template <typename R, int W, int TT>
-__global__ __launch_bounds__(256) void k_spread(int n, int NT, int nbv,
-                                                const int *__restrict__ start,
-                                                const int4 *__restrict__ base,
-                                                const R *__restrict__ ker,
-                                                const R *__restrict__ q, R *__restrict__ grid) {
+__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(int n, int NT, int nbv,
+                                                              const int *__restrict__ start,
+                                                              const int4 *__restrict__ base,
+                                                              const R *__restrict__ ker,
+                                                              const R *__restrict__ q,
+                                                              R *__restrict__ grid) {
     constexpr int T3 = TT * TT * TT;
     constexpr int CB = kSpreadBatch;
-    __shared__ R acc[3 * T3];
+    // stencil-base bins a tile can be reached from: nb per axis
+    constexpr int NBMAX = 1 + (W - 1 + TT - 1) / TT;
+    constexpr int NB3 = NBMAX * NBMAX * NBMAX;
+    static_assert(NB3 <= 64 * kSpreadWaves, "bin table must fit one thread per bin");
+    __shared__ R acc[kSpreadWaves][3 * T3];
     __shared__ R sker[CB * 3 * W];
     __shared__ R sq[CB * 3];
     __shared__ int4 sb[CB];
-    __shared__ int bin_s[27], bin_o[28];
+    __shared__ int bin_s[NB3], bin_o[NB3 + 1];
     const int tile = blockIdx.x;
     const int tx = tile % NT, ty = (tile / NT) % NT, tz = tile / (NT * NT);
     const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
-    for (int i = threadIdx.x; i < 3 * T3; i += blockDim.x) acc[i] = (R)0;
-    const int nbins = nbv * nbv * nbv;
+    for (int i = threadIdx.x; i < kSpreadWaves * 3 * T3; i += blockDim.x) (&acc[0][0])[i] = (R)0;
+    const int nbins = nbv * nbv * nbv;   // nbv <= NBMAX (checked by the launcher)
     if (threadIdx.x < nbins) {
         int i = threadIdx.x;
         int dx = i % nbv, dy = (i / nbv) % nbv, dz = i / (nbv * nbv);
@@ -64,7 +74,8 @@ __global__ __launch_bounds__(256) void k_spread(int n, int NT, int nbv,
     }
     __syncthreads();
     const int total = bin_o[nbins];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    R *my = acc[wave];
     for (int c0 = 0; c0 < total; c0 += CB) {
         const int cn = total - c0 < CB ? total - c0 : CB;
         for (int i = threadIdx.x; i < cn * (3 * W + 4); i += blockDim.x) {
@@ -77,31 +88,33 @@ __global__ __launch_bounds__(256) void k_spread(int n, int NT, int nbv,
             else sb[c] = base[g];
         }
         __syncthreads();
-        for (int c = wave; c < cn; c += nwaves) {
-            int4 b = sb[c];
+        for (int c = wave; c < cn; c += kSpreadWaves) {
+            const int4 b = sb[c];
             const R *kp = sker + c * 3 * W;
-            int lx0 = b.x - t0x;
-            if (lx0 < 0) lx0 += n;
-            R qx = sq[3 * c], qy = sq[3 * c + 1], qz = sq[3 * c + 2];
+            const R qx = sq[3 * c], qy = sq[3 * c + 1], qz = sq[3 * c + 2];
+            int lz0 = b.z - t0z;
+            if (lz0 < 0) lz0 += n;
             for (int l = lane; l < W * W; l += 64) {
-                int ky = l % W, kz = l / W;
+                const int kx = l % W, ky = l / W;
+                int lx = b.x + kx - t0x;
+                if (lx < 0) lx += n; else if (lx >= n) lx -= n;
                 int ly = b.y + ky - t0y;
                 if (ly < 0) ly += n; else if (ly >= n) ly -= n;
-                int lz = b.z + kz - t0z;
-                if (lz < 0) lz += n; else if (lz >= n) lz -= n;
-                if (ly >= TT || lz >= TT) continue;
-                R cyz = kp[W + ky] * kp[2 * W + kz];
-                R cx = qx * cyz, cy = qy * cyz, cz = qz * cyz;
-                R *row = acc + (lz * TT + ly) * TT;
+                const bool on = (lx < TT) && (ly < TT);
+                const R cxy = kp[kx] * kp[W + ky];
+                const R cx = qx * cxy, cy = qy * cxy, cz = qz * cxy;
+                R *col = my + ly * TT + lx;
 #pragma unroll
-                for (int kx = 0; kx < W; kx++) {
-                    int lx = lx0 + kx;
-                    if (lx >= n) lx -= n;
-                    if (lx >= TT) continue;
-                    R ph = kp[kx];
-                    atomicAdd(row + lx, cx * ph);
-                    atomicAdd(row + T3 + lx, cy * ph);
-                    atomicAdd(row + 2 * T3 + lx, cz * ph);
+                for (int kz = 0; kz < W; kz++) {
+                    int lz = lz0 + kz;
+                    if (lz >= n) lz -= n;
+                    if (lz >= TT) continue;          // same for every lane
+                    if (!on) continue;
+                    const R ph = kp[2 * W + kz];
+                    R *cell = col + lz * TT * TT;
+                    cell[0] += cx * ph;
+                    cell[T3] += cy * ph;
+                    cell[2 * T3] += cz * ph;
                 }
             }
         }
@@ -111,18 +124,24 @@ __global__ __launch_bounds__(256) void k_spread(int n, int NT, int nbv,
     for (int i = threadIdx.x; i < T3; i += blockDim.x) {
         int lx = i % TT, ly = (i / TT) % TT, lz = i / (TT * TT);
         size_t g = ((size_t)(t0z + lz) * n + (t0y + ly)) * n + (t0x + lx);
-        grid[g] = acc[i];
-        grid[n3 + g] = acc[T3 + i];
-        grid[2 * n3 + g] = acc[2 * T3 + i];
+        R s0 = acc[0][i], s1 = acc[0][T3 + i], s2 = acc[0][2 * T3 + i];
+#pragma unroll
+        for (int w2 = 1; w2 < kSpreadWaves; w2++) {
+            s0 += acc[w2][i]; s1 += acc[w2][T3 + i]; s2 += acc[w2][2 * T3 + i];
+        }
+        grid[g] = s0;
+        grid[n3 + g] = s1;
+        grid[2 * n3 + g] = s2;
     }
 }
 
 template <typename R, int TT>
 static void spread_tt(bs_plan_t p) {
     const int w = p->prm.w;
-    int nb = 1 + ceil_div(w - 1, TT);
+    int nb = 1 + ceil_div(w - 1, TT);   // equals the kernel's NBMAX for W = w
     int nbv = nb < p->NT ? nb : p->NT;
-    dim3 grid(p->NT * p->NT * p->NT), block(256);
+    if (nbv * nbv * nbv > 256) return;  // unreachable for w <= 16, TT >= 4
+    dim3 grid(p->NT * p->NT * p->NT), block(64 * kSpreadWaves);
     const int *start = (const int *)p->sp_start.p;
     const int4 *base = (const int4 *)p->sp_base.p;
     const R *ker = (const R *)p->sp_ker.p, *q = (const R *)p->sp_q.p;

@@ -1,0 +1,89 @@
+"""Training of the learned near-singular correction.
+
+Samples come from the library's own segment integrator (bs_ns_samples, the
+plain method in float64); the network is trained by the library's BF16-MFMA
+forward/backward kernels with Adam (bs_mlp_adam_step).  A held-out set gives
+the error table the plan uses to decide, per pair, between the network and
+the adaptive integrator.  This module only drives those calls.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import binding as B
+
+
+def _uniforms(n, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    return torch.from_numpy(rng.random((n, 8))).cuda()
+
+
+def make_dataset(n, seed):
+    U = _uniforms(n, seed)
+    X, T, A = B.ns_samples(U)
+    return X, T, A
+
+
+def error_table(mlp, X, T, A, nbins=None):
+    """Max relative error of the learned raw segment integral per
+    log10(d_c/h) bin: |y_pred - y| / |I_seg| with y = T / d_c."""
+    import torch
+    lo, hi, nb = B.ns_error_bins()
+    nbins = nbins or nb
+    Y = mlp.forward(X).double()
+    dc = A[:, 0:1]
+    err = ((Y - T.double()) / dc).norm(dim=1) / A[:, 1:4].norm(dim=1)
+    t = (torch.log10(A[:, 0]) - math.log10(lo)) / (math.log10(hi) - math.log10(lo))
+    b = (t * nbins).long().clamp(0, nbins - 1)
+    tab = np.zeros(nbins, dtype=np.float32)
+    med = np.zeros(nbins, dtype=np.float32)
+    e = err.cpu().numpy()
+    bb = b.cpu().numpy()
+    for k in range(nbins):
+        sel = e[bb == k]
+        if len(sel):
+            tab[k] = sel.max()
+            med[k] = np.median(sel)
+        else:
+            tab[k] = np.inf
+    return tab, med
+
+
+def train(n_train=1_000_000, n_val=100_000, epochs=60, batch=8192, lr=3e-3, seed=0,
+          log=print):
+    """Train a network on device-generated samples; returns (mlp, err_table,
+    info)."""
+    import torch
+    t0 = time.perf_counter()
+    X, T, A = make_dataset(n_train, seed)
+    Xv, Tv, Av = make_dataset(n_val, seed + 1)
+    torch.cuda.synchronize()
+    tgen = time.perf_counter() - t0
+    mlp = B.MLP(B.mlp_init(seed))
+    steps = epochs * (n_train // batch)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    t1 = time.perf_counter()
+    k = 0
+    for ep in range(epochs):
+        for i in range(n_train // batch):
+            sl = slice(i * batch, (i + 1) * batch)
+            lr_k = 1e-5 + 0.5 * (lr - 1e-5) * (1 + math.cos(math.pi * k / steps))
+            mlp.adam_step(X[sl], T[sl], lr_k, loss=loss)
+            k += 1
+        if log and (ep % 10 == 0 or ep == epochs - 1):
+            log(f"[ns-mlp] epoch {ep} loss {loss.item():.3e}")
+    torch.cuda.synchronize()
+    ttrain = time.perf_counter() - t1
+    tab, med = error_table(mlp, Xv, Tv, Av)
+    info = dict(n_train=n_train, n_val=n_val, epochs=epochs, batch=batch, gen_s=tgen,
+                train_s=ttrain, val_loss=mlp.loss_grad(Xv, Tv)[0].item(),
+                err_max=tab.tolist(), err_median=med.tolist())
+    if log:
+        log(f"[ns-mlp] trained {n_train} samples x {epochs} epochs in {ttrain:.1f} s; "
+            f"val loss {info['val_loss']:.3e}")
+        log("[ns-mlp] max rel err per d/h bin: " + " ".join(f"{v:.1e}" for v in tab))
+    return mlp, tab, info

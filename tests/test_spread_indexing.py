@@ -1,0 +1,63 @@
+"""CPU model of the spread's tile/bin bookkeeping (no GPU).
+
+The spread kernel bins points by the tile holding their stencil base and has
+each T^3 tile visit the nbv^3 bins that can reach it.  This test re-derives,
+for every grid size and kernel width the plan accepts, that
+
+  * every stencil cell of every point is added by exactly one tile visit,
+  * the number of bins a tile visits fits the kernel's bin table,
+  * all bin and cell indices stay inside their arrays.
+"""
+import math
+
+import numpy as np
+import pytest
+
+
+def stencil_base(u, w, n):
+    i0 = math.floor(u - 0.5 * w) + 1
+    return i0 % n, u - i0
+
+
+def tile_edge(n):
+    return 8 if n % 8 == 0 else 4
+
+
+def kernel_bin_table(W, TT):
+    nbmax = 1 + (W - 1 + TT - 1) // TT
+    return nbmax ** 3
+
+
+@pytest.mark.parametrize("n", [16, 20, 32, 36, 44, 64])
+@pytest.mark.parametrize("w", [4, 5, 7, 8, 11, 13, 16])
+def test_tiles_cover_each_stencil_cell_once(n, w):
+    if w > n:
+        pytest.skip("w > n is rejected by the plan")
+    T = tile_edge(n)
+    NT = n // T
+    nb = 1 + -(-(w - 1) // T)
+    nbv = min(nb, NT)
+    assert nbv ** 3 <= kernel_bin_table(w, T) <= 256
+    rng = np.random.default_rng(n * 100 + w)
+    us = np.concatenate([rng.uniform(0, n, 40), [0.0, n - 1e-9, 0.5 * w, n - 0.5 * w]])
+    for u in us:
+        b, f = stencil_base(u, w, n)
+        assert 0 <= b < n and 0.5 * w - 1 <= f < 0.5 * w + 1e-12
+        tile_of_base = b // T
+        assert 0 <= tile_of_base < NT
+        cells = [(b + k) % n for k in range(w)]
+        hits = {c: 0 for c in cells}
+        for t in range(NT):
+            # bins this tile visits along one axis
+            visited = [(t - d) % NT for d in range(nbv)]
+            if tile_of_base not in visited:
+                continue
+            t0 = t * T
+            lx0 = (b - t0) % n
+            for k in range(w):
+                lx = lx0 + k
+                if lx >= n:
+                    lx -= n
+                if lx < T:
+                    hits[(t0 + lx) % n] += 1
+        assert all(v == 1 for v in hits.values()), (n, w, u, hits)
