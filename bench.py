@@ -157,10 +157,26 @@ def main():
     ref, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False)
     log(f"[bench] reference ({len(idx)} nodes) in {time.perf_counter() - t0:.1f} s")
 
+    ns_eta = None
+    mlp = table = None
+    if fs.name == "ringpairs":
+        # near-singular pairs dominate: plain = FP64 + adaptive integrals,
+        # learned = FP32-mixed + the trained network (trained here, on the GPU)
+        from paper_2406_07366_amd import ns_mlp
+        log("[bench] training the near-singular network (1e6 samples) ...")
+        mlp, table, info = ns_mlp.train(n_train=1_000_000, n_val=100_000, epochs=40,
+                                        batch=8192, log=log)
+        variants = {"fp64": (B.BS_FP64, B.BS_NS_ADAPTIVE), "mixed": (B.BS_FP32_MIXED, B.BS_NS_MLP)}
+        ns_eta = 1.0
+        ref, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False, ns_eta=1.0)
+    else:
+        variants = {"fp64": (B.BS_FP64, B.BS_NS_OFF), "mixed": (B.BS_FP32_MIXED, B.BS_NS_OFF)}
+
     results = {}
-    for prec_name in ("fp64", "mixed"):
-        prec = B.BS_FP64 if prec_name == "fp64" else B.BS_FP32_MIXED
-        plan = B.Plan(B.params_for(fs, precision=prec))
+    for prec_name, (prec, ns_mode) in variants.items():
+        plan = B.Plan(B.params_for(fs, precision=prec, ns_mode=ns_mode))
+        if ns_mode == B.BS_NS_MLP:
+            plan.set_mlp(mlp, table)
         prm = plan.params()
         plan.set_filaments(fs.offsets, xyz, gamma)
         plan.velocity(out)
@@ -168,11 +184,12 @@ def main():
         err = rel_l2(out.cpu().numpy()[idx], ref)
         ms_host, ms_ev = time_steps(torch, plan, fs, xyz, gamma, out, args.steps, args.warmup)
         st = stage_profile(torch, plan, fs, xyz, gamma, out, max(20, args.steps // 4))
-        log(f"[bench] {prec_name}: {ms_host:.4f} ms/step (events {ms_ev:.4f}), "
-            f"rel_l2 {err:.3e}, {N / ms_host * 1e3:.4g} nodes/s")
+        npairs, nfb = plan.ns_counts() if ns_mode != B.BS_NS_OFF else (0, 0)
+        log(f"[bench] {prec_name} (ns_mode {ns_mode}): {ms_host:.4f} ms/step (events {ms_ev:.4f}), "
+            f"rel_l2 {err:.3e}, {N / ms_host * 1e3:.4g} nodes/s, ns pairs {npairs}")
         log("[bench]   stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in st.items()))
         results[prec_name] = dict(ms=ms_host, ms_events=ms_ev, err=err, stages=st,
-                                  prm=prm.as_dict(), plan=plan)
+                                  prm=prm.as_dict(), plan=plan, ns_mode=ns_mode, ns_pairs=npairs)
 
     primary = results[args.precision]
     prm = primary["prm"]
@@ -207,7 +224,8 @@ def main():
     value = N / (primary["ms"] * 1e-3)
     other = "mixed" if args.precision == "fp64" else "fp64"
     line = {
-        "metric": "filament nodes/s per velocity eval at rel. L2 err <= 1e-6 vs FP64 oracle",
+        "metric": "filament nodes/s per velocity eval at rel. L2 err <= 1e-6 vs FP64 oracle; "
+                  "FP32+MLP vs plain",
         "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": primary["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
@@ -217,8 +235,10 @@ def main():
                                f"tol {fs.tol:g}, Q={prm['Q']}, w={prm['w']}, "
                                f"beta={prm['beta']}",
                    "rel_l2_err": primary["err"],
+                   "ns_mode": primary["ns_mode"],
                    "other_precision": {"name": other, "nodes_per_s": N / (results[other]["ms"] * 1e-3),
-                                       "rel_l2_err": results[other]["err"]}},
+                                       "rel_l2_err": results[other]["err"],
+                                       "ns_mode": results[other]["ns_mode"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -94,7 +94,9 @@ typedef struct {
     double beta;         /* cut-off coefficient (0: from tol)                  */
     double alpha;        /* Ewald splitting parameter (0: from grid and beta)  */
     double rcut;         /* short-range cut-off (0: beta/alpha)                */
-    int    grid_n;       /* spread/FFT grid points per axis (multiple of 4)    */
+    int    grid_n;       /* spread/FFT grid points per axis: a multiple of 4,
+                            16..1024, at least w + 8 (w + 4 if not a multiple
+                            of 8)                                           */
     double sigma;        /* oversampling factor (0: 1.5)                       */
     int    w;            /* kernel width in grid points (0: from tol)          */
     int    Q;            /* Gauss-Legendre points per segment, 1..4 (0: 2)     */
@@ -231,18 +233,21 @@ int bs_mlp_destroy(bs_mlp_t m);
  * (float64).  U: DEVICE float64 [n][8] uniforms in [0,1) supplied by the
  * caller (they fix the segment tangents, the target's position class,
  * distance and azimuth); X: DEVICE float32 [n][8] features; T: DEVICE float32
- * [n][3] targets d_c * (I_seg - I_chord) in the chord frame; aux: DEVICE
- * float64 [n][4] (d_c/h, exact raw integral in the frame) or NULL.  The
+ * [n][3] targets (I_seg - I_tan) / |I_tan| in the chord frame, I_tan the
+ * straight segment tangent to the curve at its point closest to the target
+ * and d that distance; aux: DEVICE float64 [n][6] (d/h, exact raw integral
+ * (3), |I_tan|, chord distance / h) or NULL.  The
  * sample box: tangent angles <= 0.6 rad, tangent lengths in [0.9, 1.1],
  * d_c/h log-uniform in bs_ns_error_bins' range. */
 int bs_ns_samples(int64_t n, const double *U, float *X, float *T, double *aux,
                   void *hip_stream);
-/* range [lo, hi] of d_c/h covered by the network and the number of
- * log-spaced bins of its error table */
+/* range [lo, hi] of (distance to the chord)/h covered by the network, and
+ * the number of log-spaced bins of its error table (binned by the distance
+ * to the curve over h, values below lo falling in the first bin) */
 int bs_ns_error_bins(double *lo, double *hi, int *nbins);
 /* Attach a trained network to a BS_NS_MLP plan.  err_table[nbins] is the
  * largest relative error of the learned segment integral seen on held-out
- * samples in each log10(d_c/h) bin; pairs in bins whose error exceeds the
+ * samples in each log10(d/h) bin; pairs in bins whose error exceeds the
  * plan's tol, or outside the sample box, use the adaptive integrator.  The
  * plan keeps the pointer: the network must outlive its use by the plan. */
 int bs_set_mlp(bs_plan_t plan, bs_mlp_t mlp, const float *err_table, int nbins);

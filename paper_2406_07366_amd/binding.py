@@ -349,7 +349,7 @@ def ns_samples(U, aux=True):
     n = U.shape[0]
     X = torch.empty((n, 8), dtype=torch.float32, device="cuda")
     T = torch.empty((n, 3), dtype=torch.float32, device="cuda")
-    A = torch.empty((n, 4), dtype=torch.float64, device="cuda") if aux else None
+    A = torch.empty((n, 6), dtype=torch.float64, device="cuda") if aux else None
     _check(_lib.bs_ns_samples(n, _ptr(U), _ptr(X), _ptr(T), _ptr(A),
                               _vp(torch.cuda.current_stream().cuda_stream)))
     return X, T, A

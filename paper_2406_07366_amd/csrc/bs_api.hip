@@ -174,7 +174,11 @@ int resolve(const bs_params *in, bs_params *out) {
     if (!(r.beta > 0)) return bad("beta must be positive");
     if (r.w == 0) r.w = width_from_tol(r.tol);
     if (r.w < kMinW || r.w > kMaxW) return bad("w must be in 4..16");
-    if (r.w > r.grid_n) return bad("w must not exceed grid_n");
+    {
+        // every stencil must reach a spread tile at most once along an axis
+        int T = (r.grid_n % 8 == 0) ? 8 : 4;
+        if (r.grid_n < r.w + T) return bad("grid_n must be at least w + 8 (w + 4 if not a multiple of 8)");
+    }
     int M = (int)std::floor(r.grid_n / r.sigma + 1e-9);
     r.K = (M - 1) / 2;
     if (r.K < 1) return bad("grid too small for one retained mode");

@@ -80,14 +80,18 @@ struct NsArgs {
     const double4 *spos;
 };
 
+// One wavefront per node: lanes take consecutive quadrature points of each
+// scanned cell; flagged lanes are ranked with a ballot so that pass 0 counts
+// and pass 1 writes the pairs in scan order (cell order, then sorted order).
 // pass 0: cnt[o] = number of flagged pairs; pass 1: write pairs at pstart[o]
 template <int PASS>
 __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt,
                                                  const int *__restrict__ pstart,
                                                  int2 *__restrict__ pairs,
                                                  int *__restrict__ status) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.N) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gid >> 6, lane = gid & 63;
+    if (t >= a.N) return;   // whole wavefronts exit together
     const int o = a.nperm[t];
     const int ip = prev_node_d(a.off, a.fil, o);
     const double xi[3] = {a.x[3 * o], a.x[3 * o + 1], a.x[3 * o + 2]};
@@ -99,7 +103,9 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
     bool full = (2 * span + 1 >= nc);
     if (full) span = nc;   // every cell, once
     const int lo = full ? 0 : -span, hi = full ? nc - 1 : span;
-    int k = 0, base = PASS ? pstart[o] : 0;
+    int k = 0;
+    const int base = PASS ? pstart[o] : 0;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int dz = lo; dz <= hi; dz++) {
         int cz = full ? dz : c0[2] + dz;
         cz = cz < 0 ? cz + nc : (cz >= nc ? cz - nc : cz);
@@ -109,58 +115,63 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
             for (int dx = lo; dx <= hi; dx++) {
                 int cx = full ? dx : c0[0] + dx;
                 cx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
-                int cidx = (cz * nc + cy) * nc + cx;
-                for (int p = a.cstart[cidx]; p < a.cstart[cidx + 1]; p++) {
-                    int sg = a.sseg[p];
-                    if (sg == o || sg == ip) continue;
-                    // quadrature index of this point within its segment: the
-                    // sorted copy keeps the original index order inside a cell,
-                    // so recover it from the position match
-                    int jn = next_node_d(a.off, a.fil, sg);
-                    const double A[3] = {a.x[3 * sg], a.x[3 * sg + 1], a.x[3 * sg + 2]};
-                    const double Bv[3] = {a.x[3 * jn], a.x[3 * jn + 1], a.x[3 * jn + 2]};
-                    double xs[3];
-                    double d = chord_dist(A, Bv, xi, a.L, xs);
-                    if (!(d < a.eta * a.ell[sg])) continue;
-                    // canonical point: the first quadrature point of segment sg
-                    // inside the scanned window
-                    double4 sp = a.spos[p];
-                    int first = -1;
-                    for (int i2 = 0; i2 < a.Q; i2++) {
-                        const double *qp = a.qpos + 3 * ((size_t)sg * a.Q + i2);
-                        int qc[3] = {cell_of(qp[0], a.L, nc), cell_of(qp[1], a.L, nc),
-                                     cell_of(qp[2], a.L, nc)};
-                        bool inw = full || (in_window(qc[0], c0[0], span, nc) &&
-                                            in_window(qc[1], c0[1], span, nc) &&
-                                            in_window(qc[2], c0[2], span, nc));
-                        if (inw) { first = i2; break; }
+                const int cidx = (cz * nc + cy) * nc + cx;
+                const int s = a.cstart[cidx], e = a.cstart[cidx + 1];
+                for (int p0 = s; p0 < e; p0 += 64) {
+                    const int p = p0 + lane;
+                    bool flag = false;
+                    int sg = -1;
+                    double xs[3] = {0.0, 0.0, 0.0};
+                    if (p < e) {
+                        sg = a.sseg[p];
+                        if (sg != o && sg != ip) {
+                            int jn = next_node_d(a.off, a.fil, sg);
+                            const double A[3] = {a.x[3 * sg], a.x[3 * sg + 1], a.x[3 * sg + 2]};
+                            const double Bv[3] = {a.x[3 * jn], a.x[3 * jn + 1], a.x[3 * jn + 2]};
+                            double d = chord_dist(A, Bv, xi, a.L, xs);
+                            if (d < a.eta * a.ell[sg]) {
+                                // count the segment once: at the first of its
+                                // quadrature points inside the scanned window
+                                double4 sp = a.spos[p];
+                                int first = 0;
+                                for (int i2 = 0; i2 < a.Q; i2++) {
+                                    const double *qp = a.qpos + 3 * ((size_t)sg * a.Q + i2);
+                                    bool inw = full ||
+                                               (in_window(cell_of(qp[0], a.L, nc), c0[0], span, nc) &&
+                                                in_window(cell_of(qp[1], a.L, nc), c0[1], span, nc) &&
+                                                in_window(cell_of(qp[2], a.L, nc), c0[2], span, nc));
+                                    if (inw) { first = i2; break; }
+                                }
+                                const double *qf = a.qpos + 3 * ((size_t)sg * a.Q + first);
+                                flag = wrap_box(qf[0], a.L) == sp.x && wrap_box(qf[1], a.L) == sp.y &&
+                                       wrap_box(qf[2], a.L) == sp.z;
+                            }
+                        }
                     }
-                    // is this point that first one?  compare wrapped positions
-                    const double *qf = a.qpos + 3 * ((size_t)sg * a.Q + (first < 0 ? 0 : first));
-                    bool same = wrap_box(qf[0], a.L) == sp.x && wrap_box(qf[1], a.L) == sp.y &&
-                                wrap_box(qf[2], a.L) == sp.z;
-                    if (!same) continue;
-                    if (k < a.max_per_node) {
-                        if (PASS) {
+                    const unsigned long long m = __ballot(flag);
+                    if (PASS && flag) {
+                        int slot = k + __popcll(m & below);
+                        if (slot < a.max_per_node) {
                             // image shift of the target, periods per axis,
                             // packed as three 10-bit fields (+-511 periods)
                             int sh = 0;
                             for (int q = 0; q < 3; q++) {
-                                int s = (int)rint((xs[q] - xi[q]) / a.L);
-                                s = s < -511 ? -511 : (s > 511 ? 511 : s);
-                                sh = (sh << 10) | (s + 512);
+                                int sv = (int)rint((xs[q] - xi[q]) / a.L);
+                                sv = sv < -511 ? -511 : (sv > 511 ? 511 : sv);
+                                sh = (sh << 10) | (sv + 512);
                             }
-                            pairs[base + k] = make_int2(sg, sh);
+                            pairs[base + slot] = make_int2(sg, sh);
                         }
-                    } else if (PASS == 0) {
-                        atomicOr(status, 2);
                     }
-                    k++;
+                    k += __popcll(m);
                 }
             }
         }
     }
-    if (PASS == 0) cnt[o] = k < a.max_per_node ? k : a.max_per_node;
+    if (PASS == 0 && lane == 0) {
+        if (k > a.max_per_node) atomicOr(status, 2);
+        cnt[o] = k < a.max_per_node ? k : a.max_per_node;
+    }
 }
 
 // cubic Hermite segment j as c0 + c1 u + c2 u^2 + c3 u^3
@@ -208,7 +219,16 @@ __device__ void ns_panel(const Seg &s, const double *x, double a, double b, cons
 // cubic segment: closest point by a coarse scan and Newton steps on
 // (s - x) . s' = 0, then 16-point Gauss-Legendre panels graded geometrically
 // (ratio 3) away from it.
-__device__ void ns_seg_integral(const Seg &s, const double *xs, const NsRule &R, double *acc) {
+__device__ __forceinline__ void seg_eval(const Seg &s, double u, double *p, double *d1) {
+    for (int q = 0; q < 3; q++) {
+        p[q] = s.c0[q] + u * (s.c1[q] + u * (s.c2[q] + u * s.c3[q]));
+        d1[q] = s.c1[q] + u * (2.0 * s.c2[q] + 3.0 * u * s.c3[q]);
+    }
+}
+
+// parameter of the point of the segment closest to x: best of a coarse scan,
+// then Newton steps on (s - x) . s' = 0 kept inside [0, 1]
+__device__ double closest_u(const Seg &s, const double *xs) {
     double ub = 0.0, best = 1e300;
     for (int k = 0; k <= 8; k++) {
         double u = k / 8.0, r2 = 0.0;
@@ -232,13 +252,16 @@ __device__ void ns_seg_integral(const Seg &s, const double *xs, const NsRule &R,
         un = un < 0.0 ? 0.0 : (un > 1.0 ? 1.0 : un);
         ub = un;
     }
-    double r2 = 0.0, sp2 = 0.0;
-    for (int q = 0; q < 3; q++) {
-        double r = s.c0[q] + ub * (s.c1[q] + ub * (s.c2[q] + ub * s.c3[q])) - xs[q];
-        double d1 = s.c1[q] + ub * (2.0 * s.c2[q] + 3.0 * ub * s.c3[q]);
-        r2 += r * r;
-        sp2 += d1 * d1;
-    }
+    return ub;
+}
+
+__device__ void ns_seg_integral(const Seg &s, const double *xs, const NsRule &R, double *acc) {
+    const double ub = closest_u(s, xs);
+    double P[3], d1[3];
+    seg_eval(s, ub, P, d1);
+    const double r2 = (P[0] - xs[0]) * (P[0] - xs[0]) + (P[1] - xs[1]) * (P[1] - xs[1]) +
+                      (P[2] - xs[2]) * (P[2] - xs[2]);
+    const double sp2 = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
     // half the distance in parameter units: the first panel pair is finer
     // than the singularity's width
     double delta = 0.5 * sqrt(r2 / sp2);
@@ -346,8 +369,11 @@ __global__ void k_ns_apply(int N, const int *__restrict__ pstart, const double *
 // with M the chord midpoint.  The segment in this frame is the cubic from
 // (-1/2,0,0) to (1/2,0,0) with end derivatives D0, D1 (chord-length knots
 // make d tau = h), so the integral is a function of the 8 features alone
-// (times 1/h).  The network predicts z = d_c * (I_seg - I_chord) in frame
-// components, d_c the distance from the target to the chord over h.
+// (times 1/h).  The network predicts z = (I_seg - I_tan) / |I_tan| in frame
+// components, I_tan the integral over the straight segment tangent to the
+// curve at its point closest to the target (distance d), which carries the
+// 1/d singularity exactly: z is a relative remainder, so the squared loss is
+// the mean squared relative error of the learned integral.
 constexpr double kNsThetaMax = 0.6;     // max angle of D0, D1 to the chord
 constexpr double kNsDmin = 0.9, kNsDmax = 1.1;   // |D0|, |D1| range
 constexpr double kNsRlo = 1e-3, kNsRhi = 1.1;    // d_c / h range
@@ -373,6 +399,38 @@ __device__ __forceinline__ void chord_raw(const double *A, const double *B, cons
     double den = dt >= 0.0 ? p * q + dt : (c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) / (p * q - dt);
     double f = (p + q) / (p * q * den);
     out[0] = c[0] * f; out[1] = c[1] * f; out[2] = c[2] * f;
+}
+
+// Straight segment tangent to the curve at its point P closest to x, running
+// |P - s(0)| back and |s(1) - P| forward along the unit tangent: it carries
+// the same 1/d singularity as the curve (d = |P - x|), so the remainder
+// I_seg - I_tan is small relative to I_tan near the curve.  Returns I_tan
+// (raw integral), the scale |I_tan| the network's output is multiplied by,
+// and d/h.
+__device__ void tangent_baseline(const Seg &s, const double *x, double h, double *Itan,
+                                 double *scale, double *dstar) {
+    const double u = closest_u(s, x);
+    double P[3], d1[3], S0[3], S1[3], dummy[3];
+    seg_eval(s, u, P, d1);
+    seg_eval(s, 0.0, S0, dummy);
+    seg_eval(s, 1.0, S1, dummy);
+    double tn = sqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);
+    double a = 0.0, b = 0.0, d = 0.0;
+    for (int q = 0; q < 3; q++) {
+        a += (P[q] - S0[q]) * (P[q] - S0[q]);
+        b += (S1[q] - P[q]) * (S1[q] - P[q]);
+        d += (P[q] - x[q]) * (P[q] - x[q]);
+    }
+    a = sqrt(a); b = sqrt(b); d = sqrt(d);
+    double A[3], B[3];
+    for (int q = 0; q < 3; q++) {
+        A[q] = P[q] - a * d1[q] / tn;
+        B[q] = P[q] + b * d1[q] / tn;
+    }
+    chord_raw(A, B, x, Itan);
+    double m = sqrt(Itan[0] * Itan[0] + Itan[1] * Itan[1] + Itan[2] * Itan[2]);
+    *scale = m > 1e-300 ? m : 1e-300;
+    *dstar = d / h;
 }
 
 struct NsFrame {
@@ -471,15 +529,17 @@ __global__ void k_ns_samples(int64_t n, const double *__restrict__ U, NsRule R,
         s.c2[q] = 3.0 * (B[q] - A[q]) - 2.0 * D0[q] - D1[q];
         s.c3[q] = 2.0 * (A[q] - B[q]) + D0[q] + D1[q];
     }
-    double I[3], Ic[3];
+    double I[3], It[3], scale, dstar;
     ns_seg_integral(s, x, R, I);
-    chord_raw(A, B, x, Ic);
+    tangent_baseline(s, x, 1.0, It, &scale, &dstar);
     NsFrame F = ns_frame(A, B, D0, D1, x);
     for (int k = 0; k < 8; k++) X[8 * i + k] = F.f[k];
-    for (int q = 0; q < 3; q++) T[3 * i + q] = (float)(F.dc * (I[q] - Ic[q]));
+    for (int q = 0; q < 3; q++) T[3 * i + q] = (float)((I[q] - It[q]) / scale);
     if (aux) {
-        aux[4 * i] = F.dc;
-        aux[4 * i + 1] = I[0]; aux[4 * i + 2] = I[1]; aux[4 * i + 3] = I[2];
+        aux[6 * i] = dstar;
+        aux[6 * i + 1] = I[0]; aux[6 * i + 2] = I[1]; aux[6 * i + 3] = I[2];
+        aux[6 * i + 4] = scale;
+        aux[6 * i + 5] = F.dc;
     }
 }
 
@@ -524,19 +584,21 @@ __global__ __launch_bounds__(256) void k_ns_combine(
         double A[3], B[3], D0[3], D1[3], xs[3];
         pair_geometry(o, pr.x, pr.y, off, fil, x, D, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
+        Seg sgm = load_seg(pr.x, off, fil, x, D, dtau);
+        double It[3], scale, dstar;
+        tangent_baseline(sgm, xs, F.h, It, &scale, &dstar);
         double out[3];
-        if (!F.inbox || (double)box.err[ns_bin(F.dc)] > box.tol) {
+        if (!F.inbox || (double)box.err[ns_bin(dstar)] > box.tol) {
             ns_pair(o, pr.x, pr.y, off, fil, x, D, dtau, gamma, qpos, qchg, Q, L, R, out);
             atomicAdd(nfallback, 1);
         } else {
-            double Ic[3], qs[3], y[3];
-            chord_raw(A, B, xs, Ic);
-            for (int k = 0; k < 3; k++) y[k] = (double)Y[3 * (size_t)p + k] / F.dc;
+            double qs[3], y[3];
+            for (int k = 0; k < 3; k++) y[k] = (double)Y[3 * (size_t)p + k] * scale;
             ns_qsum(pr.x, xs, qpos, qchg, Q, qs);
             const double g4 = gamma[fil[pr.x]] / (4.0 * kPi);
             for (int q = 0; q < 3; q++) {
                 double yw = F.e[0][q] * y[0] + F.e[1][q] * y[1] + F.e[2][q] * y[2];
-                out[q] = g4 * (Ic[q] + yw / F.h) - qs[q] / (4.0 * kPi);
+                out[q] = g4 * (It[q] + yw / F.h) - qs[q] / (4.0 * kPi);
             }
         }
         pout[3 * (size_t)p] = out[0];
@@ -561,14 +623,15 @@ static NsArgs ns_args(bs_plan_t p) {
 void ns_build_pairs(bs_plan_t p) {
     const int N = (int)p->N;
     dim3 grid(ceil_div(N, 256)), block(256);
+    dim3 wgrid(ceil_div((int64_t)N * 64, 256));
     hipLaunchKernelGGL(k_max_ell, dim3(1), dim3(256), 0, p->stream, N,
                        (const double *)p->d_ell.p, (double *)p->ns_maxell.p);
     NsArgs a = ns_args(p);
     int *cnt = (int *)p->ns_cnt.p, *start = (int *)p->ns_start.p;
-    hipLaunchKernelGGL((k_ns_flag<0>), grid, block, 0, p->stream, a, cnt, (const int *)nullptr,
+    hipLaunchKernelGGL((k_ns_flag<0>), wgrid, block, 0, p->stream, a, cnt, (const int *)nullptr,
                        (int2 *)nullptr, (int *)p->d_status.p);
     exclusive_scan(p, cnt, start, N);
-    hipLaunchKernelGGL((k_ns_flag<1>), grid, block, 0, p->stream, a, (int *)nullptr, start,
+    hipLaunchKernelGGL((k_ns_flag<1>), wgrid, block, 0, p->stream, a, (int *)nullptr, start,
                        (int2 *)p->ns_pairs.p, (int *)p->d_status.p);
     hipLaunchKernelGGL(k_ns_owner, grid, block, 0, p->stream, N, start, (int *)p->ns_pnode.p);
 }

@@ -34,6 +34,19 @@ namespace bs {
 constexpr int kSpreadBatch = 64;
 constexpr int kSpreadWaves = 4;
 
+// Stencil cells k in [0, W) whose local index (d + k) mod n, d = base - t0,
+// falls inside [0, TT): a contiguous range [lo, hi) (empty if hi <= lo).
+template <int W, int TT>
+__device__ __forceinline__ void overlap_range_t(int d, int n, int &lo, int &hi) {
+    if (d < 0) d += n;                 // d in [0, n)
+    if (d < TT) { lo = 0; hi = TT - d < W ? TT - d : W; }
+    else {                              // stencil starts before the tile (wrap)
+        lo = n - d;
+        hi = lo + TT < W ? lo + TT : W;
+    }
+}
+#define overlap_range(d, n, lo, hi) overlap_range_t<W, TT>(d, n, lo, hi)
+
 template <typename R, int W, int TT>
 __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(int n, int NT, int nbv,
                                                               const int *__restrict__ start,
@@ -90,26 +103,27 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(int n, int NT, int
         __syncthreads();
         for (int c = wave; c < cn; c += kSpreadWaves) {
             const int4 b = sb[c];
+            int klo[3], khi[3];
+            overlap_range(b.x - t0x, n, klo[0], khi[0]);
+            overlap_range(b.y - t0y, n, klo[1], khi[1]);
+            overlap_range(b.z - t0z, n, klo[2], khi[2]);
+            if (khi[0] <= klo[0] || khi[1] <= klo[1] || khi[2] <= klo[2]) continue;
+            const int ox = khi[0] - klo[0], oy = khi[1] - klo[1];
             const R *kp = sker + c * 3 * W;
             const R qx = sq[3 * c], qy = sq[3 * c + 1], qz = sq[3 * c + 2];
-            int lz0 = b.z - t0z;
-            if (lz0 < 0) lz0 += n;
-            for (int l = lane; l < W * W; l += 64) {
-                const int kx = l % W, ky = l / W;
-                int lx = b.x + kx - t0x;
-                if (lx < 0) lx += n; else if (lx >= n) lx -= n;
-                int ly = b.y + ky - t0y;
-                if (ly < 0) ly += n; else if (ly >= n) ly -= n;
-                const bool on = (lx < TT) && (ly < TT);
+            // local index of stencil cell k along an axis: (b + k - t0) mod n
+            int lx0 = b.x - t0x; if (lx0 < 0) lx0 += n;
+            int ly0 = b.y - t0y; if (ly0 < 0) ly0 += n;
+            int lz0 = b.z - t0z; if (lz0 < 0) lz0 += n;
+            for (int l = lane; l < ox * oy; l += 64) {
+                const int kx = klo[0] + l % ox, ky = klo[1] + l / ox;
+                int lx = lx0 + kx; if (lx >= n) lx -= n;
+                int ly = ly0 + ky; if (ly >= n) ly -= n;
                 const R cxy = kp[kx] * kp[W + ky];
                 const R cx = qx * cxy, cy = qy * cxy, cz = qz * cxy;
                 R *col = my + ly * TT + lx;
-#pragma unroll
-                for (int kz = 0; kz < W; kz++) {
-                    int lz = lz0 + kz;
-                    if (lz >= n) lz -= n;
-                    if (lz >= TT) continue;          // same for every lane
-                    if (!on) continue;
+                for (int kz = klo[2]; kz < khi[2]; kz++) {
+                    int lz = lz0 + kz; if (lz >= n) lz -= n;
                     const R ph = kp[2 * W + kz];
                     R *cell = col + lz * TT * TT;
                     cell[0] += cx * ph;

@@ -30,13 +30,13 @@ def make_dataset(n, seed):
 
 def error_table(mlp, X, T, A, nbins=None):
     """Max relative error of the learned raw segment integral per
-    log10(d_c/h) bin: |y_pred - y| / |I_seg| with y = T / d_c."""
+    log10(d/h) bin: |scale (y_pred - z)| / |I_seg|, z the target."""
     import torch
     lo, hi, nb = B.ns_error_bins()
     nbins = nbins or nb
     Y = mlp.forward(X).double()
-    dc = A[:, 0:1]
-    err = ((Y - T.double()) / dc).norm(dim=1) / A[:, 1:4].norm(dim=1)
+    scale = A[:, 4:5]
+    err = ((Y - T.double()) * scale).norm(dim=1) / A[:, 1:4].norm(dim=1)
     t = (torch.log10(A[:, 0]) - math.log10(lo)) / (math.log10(hi) - math.log10(lo))
     b = (t * nbins).long().clamp(0, nbins - 1)
     tab = np.zeros(nbins, dtype=np.float32)

@@ -31,9 +31,9 @@ def kernel_bin_table(W, TT):
 @pytest.mark.parametrize("n", [16, 20, 32, 36, 44, 64])
 @pytest.mark.parametrize("w", [4, 5, 7, 8, 11, 13, 16])
 def test_tiles_cover_each_stencil_cell_once(n, w):
-    if w > n:
-        pytest.skip("w > n is rejected by the plan")
     T = tile_edge(n)
+    if n < w + T:
+        pytest.skip("rejected by the plan (a stencil could enter a tile twice)")
     NT = n // T
     nb = 1 + -(-(w - 1) // T)
     nbv = min(nb, NT)
@@ -61,3 +61,34 @@ def test_tiles_cover_each_stencil_cell_once(n, w):
                 if lx < T:
                     hits[(t0 + lx) % n] += 1
         assert all(v == 1 for v in hits.values()), (n, w, u, hits)
+
+
+def overlap_range(d, n, W, TT):
+    """The kernel's contiguous overlap [lo, hi) of a stencil with a tile."""
+    if d < 0:
+        d += n
+    if d < TT:
+        return 0, min(TT - d, W)
+    lo = n - d
+    return lo, min(lo + TT, W)
+
+
+@pytest.mark.parametrize("n", [16, 20, 32, 36, 64])
+def test_overlap_range_is_the_set_of_cells_in_the_tile(n):
+    T = tile_edge(n)
+    for W in range(4, 17):
+        if n < W + T:
+            continue
+        for b in range(n):
+            for t0 in range(0, n, T):
+                lo, hi = overlap_range(b - t0, n, W, T)
+                valid = [k for k in range(W) if (b + k - t0) % n < T]
+                assert valid == list(range(lo, max(lo, hi)))
+
+
+def test_plan_rejects_grids_too_small_for_the_tiles():
+    from paper_2406_07366_amd import binding as B
+    with pytest.raises(B.BsError) as e:
+        B.resolve_params(B.make_params(L=2 * math.pi, a=1e-6, tol=1e-6, grid_n=16, w=10,
+                                       alpha=1.0, rcut=1.0))
+    assert e.value.code == B.BS_EINVAL
