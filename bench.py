@@ -41,13 +41,23 @@ def rel_l2(a, b):
     return math.sqrt(((a - b) ** 2).sum(1).mean() / (b ** 2).sum(1).mean())
 
 
-def count_pairs(fs, Q, rc):
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def load_reference(name):
+    """Oracle reference values written by tests/golden/make_references.py."""
+    path = os.path.join(GOLDEN, f"ref_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    return np.load(path)
+
+
+def count_pairs(plan, fs, Q, rc):
     """Interacting (node, quadrature point) pairs within r_c, minimum image,
-    minus the 2Q excluded points of each node's adjacent segments."""
+    minus the 2Q excluded points of each node's adjacent segments (quadrature
+    points from the plan's own geometry)."""
     from scipy.spatial import cKDTree
-    from oracle import oracle as O   # geometry only, for the pair count
-    o = O.Oracle(fs, Q=Q)
-    qp, _, _ = o.quad()
+    qp = plan.geometry()["qpos"].cpu().numpy()
     L = fs.L
     tree = cKDTree(np.mod(qp, L) % L, boxsize=L)
     cnt = tree.query_ball_point(np.mod(fs.xyz, L) % L, rc, return_length=True)
@@ -122,6 +132,85 @@ def cpu_baseline(fs, prm, budget_s=10.0):
                       f"{dt:.1f} s"}
 
 
+EULER_GAMMA = 0.5772156649015329
+
+
+def kelvin_period(lam, a, delta=0.25, kappa=1.0):
+    """T_kw(lambda) of Sec. 5.2; the RK4 step is dt = T_kw(l_min)."""
+    return 2 * lam ** 2 / kappa / (math.log(lam / (math.pi * a)) + 0.5 - (delta + EULER_GAMMA))
+
+
+def min_chord(fs):
+    x = fs.xyz
+    nxt = np.arange(fs.n_nodes) + 1
+    nxt[fs.offsets[1:] - 1] = fs.offsets[:-1]
+    return float(np.linalg.norm(x[nxt] - x, axis=1).min())
+
+
+def rk4_run(torch, B, plan, fs, steps, dt):
+    """steps RK4 steps on device positions; energy after each step."""
+    xyz, g = B.load_workload(fs)
+    plan.set_filaments(fs.offsets, xyz, g)
+    E = [plan.energy(want_psi=False)[0]]
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.rk4_step(fs.offsets, xyz, g, dt)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        plan.set_filaments(fs.offsets, xyz, g)
+        E.append(plan.energy(want_psi=False)[0])
+    plan.status()
+    return np.array(E), np.array(times), xyz.cpu().numpy()
+
+
+def bigtangle(args, torch, B, W):
+    """Large tangle (N = 1e6, grid 512^3, FP32-mixed + learned correction):
+    velocity throughput, 10 RK4 steps with energy, and the energy drift of the
+    first 100 filaments (1e4 nodes) against the FP64 oracle's energies stored
+    by tests/golden/make_references.py (--drift)."""
+    from paper_2406_07366_amd import ns_mlp
+    fs = W.bigtangle()
+    N = fs.n_nodes
+    dt = kelvin_period(min_chord(fs), fs.a)
+    log(f"[bench] bigtangle N={N}, dt = T_kw(l_min) = {dt:.3e}")
+    mlp, table, _ = ns_mlp.train(n_train=1_000_000, n_val=100_000, epochs=40, batch=8192, log=log)
+    plan = B.Plan(B.params_for(fs, precision=B.BS_FP32_MIXED, ns_mode=B.BS_NS_MLP))
+    plan.set_mlp(mlp, table)
+    xyz, g = B.load_workload(fs)
+    out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    ms, _ = time_steps(torch, plan, fs, xyz, g, out, args.steps, args.warmup)
+    st = stage_profile(torch, plan, fs, xyz, g, out, max(5, args.steps // 2))
+    npairs, nfb = plan.ns_counts()
+    log(f"[bench] bigtangle: {ms:.3f} ms per velocity eval, {N / ms * 1e3:.4g} nodes/s; "
+        f"ns pairs {npairs}")
+    log("[bench]   stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in st.items()))
+    E, tsteps, _ = rk4_run(torch, B, plan, fs, 10, dt)
+    drift = E / E[0] - 1
+    log(f"[bench] RK4 10 steps: {tsteps.mean() * 1e3:.2f} ms/step, energy drift "
+        + " ".join(f"{d:.2e}" for d in drift))
+    res = {"ms_per_eval": ms, "nodes_per_s": N / ms * 1e3, "stages": st, "dt": dt,
+           "rk4_ms_per_step": tsteps.mean() * 1e3, "energy": E.tolist(), "drift": drift.tolist(),
+           "ns_pairs": npairs}
+    if args.drift:
+        sub = fs.subset(100)
+        sub.grid_n = 128
+        log(f"[bench] drift subset N={sub.n_nodes}, grid 128^3")
+        ps = B.Plan(B.params_for(sub, precision=B.BS_FP32_MIXED, ns_mode=B.BS_NS_MLP))
+        ps.set_mlp(mlp, table)
+        Eg, _, _ = rk4_run(torch, B, ps, sub, 10, dt)
+        gold = load_reference("bigtangle_subset_energy")
+        assert gold is not None and abs(float(gold["dt"]) - dt) < 1e-12 * dt
+        Eo = gold["E"]
+        rel = np.abs(Eg - Eo) / np.abs(Eo)
+        log("[bench] subset |E_gpu - E_oracle|/E_oracle per step: " + " ".join(f"{r:.2e}" for r in rel))
+        log("[bench] subset drift gpu " + " ".join(f"{d:.2e}" for d in Eg / Eg[0] - 1))
+        log("[bench] subset drift oracle " + " ".join(f"{d:.2e}" for d in Eo / Eo[0] - 1))
+        res["subset"] = {"E_gpu": Eg.tolist(), "E_oracle": Eo.tolist(), "rel": rel.tolist()}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +220,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"))
+    ap.add_argument("--drift", action="store_true",
+                    help="bigtangle: energy drift of a 1e4-node subset against the FP64 oracle")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
@@ -138,9 +229,18 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    from oracle import oracle as O
     from paper_2406_07366_amd import binding as B
     from paper_2406_07366_amd import workloads as W
+
+    if args.workload == "bigtangle":
+        res = bigtangle(args, torch, B, W)
+        os.makedirs(os.path.dirname(args.detail), exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump(res, f, indent=1, default=float)
+        print(json.dumps({"workload": "bigtangle", "nodes_per_s": res["nodes_per_s"],
+                          "rk4_ms_per_step": res["rk4_ms_per_step"],
+                          "drift_last": res["drift"][-1]}), flush=True)
+        return
 
     fs = W.make(args.workload)
     N = fs.n_nodes
@@ -148,14 +248,11 @@ def main():
     xyz, gamma = B.load_workload(fs)
     out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
 
-    # reference solution (converged oracle), sampled on large workloads
-    if N <= 20000:
-        idx = np.arange(N)
-    else:
-        idx = np.sort(np.random.default_rng(0).choice(N, 256, replace=False))
-    t0 = time.perf_counter()
-    ref, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False)
-    log(f"[bench] reference ({len(idx)} nodes) in {time.perf_counter() - t0:.1f} s")
+    # reference solution (converged oracle, stored), sampled on large workloads
+    gold = load_reference(fs.name)
+    if gold is None:
+        raise SystemExit(f"no stored reference for {fs.name}: run tests/golden/make_references.py")
+    idx, ref = gold["idx"], gold["v"]
 
     ns_eta = None
     mlp = table = None
@@ -168,7 +265,6 @@ def main():
                                         batch=8192, log=log)
         variants = {"fp64": (B.BS_FP64, B.BS_NS_ADAPTIVE), "mixed": (B.BS_FP32_MIXED, B.BS_NS_MLP)}
         ns_eta = 1.0
-        ref, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False, ns_eta=1.0)
     else:
         variants = {"fp64": (B.BS_FP64, B.BS_NS_OFF), "mixed": (B.BS_FP32_MIXED, B.BS_NS_OFF)}
 
@@ -195,7 +291,7 @@ def main():
     prm = primary["prm"]
     fp32 = args.precision == "mixed"
     Nq = N * prm["Q"]
-    npairs = count_pairs(fs, prm["Q"], prm["rcut"])
+    npairs = count_pairs(primary["plan"], fs, prm["Q"], prm["rcut"])
     sb = stage_bytes(B.resolve_params(B.params_for(fs, precision=int(fp32))), N, Nq, fp32)
     st = primary["stages"]
     roof_all = {}

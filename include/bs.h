@@ -176,6 +176,19 @@ int bs_vorticity_modes(bs_plan_t plan, double *out);
 int bs_geometry(bs_plan_t plan, double *qpos, double *qcharge, double *sdot,
                 double *sddot, double *ell);
 
+/* bs_set_filaments followed by bs_velocity.  With graph replay enabled
+ * (bs_set_graph), the first call runs eagerly and then records the whole
+ * sequence as a HIP graph; later calls with the same pointers and the same
+ * offsets replay it with one launch.  If recording is not possible the plan
+ * silently keeps running eagerly (bs_graph_active tells which). */
+int bs_step(bs_plan_t plan, int64_t nfil, const int64_t *offsets, const double *xyz,
+            const double *gamma, double *v_out);
+/* enable (1) or disable (0) graph replay in bs_step; needs a non-null plan
+ * stream (BS_EINVAL otherwise).  Disabled by default. */
+int bs_set_graph(bs_plan_t plan, int enable);
+/* 1 if bs_step currently replays a recorded graph */
+int bs_graph_active(bs_plan_t plan);
+
 /* One classical fourth-order Runge-Kutta step of dx/dt = v(x) for every
  * node (Sec. 5.2: each node moves with the Biot-Savart velocity; the spline
  * is refitted at every stage).  xyz: DEVICE float64 [N][3], advanced in

@@ -29,7 +29,8 @@ EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_velocity",
             "bs_status", "bs_set_profiling", "bs_stage_times", "bs_get_params",
             "bs_destroy", "bs_last_error", "bs_mlp_nparams", "bs_mlp_create",
             "bs_mlp_forward", "bs_mlp_loss_grad", "bs_mlp_adam_step", "bs_mlp_get_params",
-            "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_set_mlp", "bs_ns_counts", "bs_rk4_step"]
+            "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_set_mlp", "bs_ns_counts", "bs_rk4_step", "bs_step", "bs_set_graph",
+            "bs_graph_active"]
 
 NSTAGES = 10
 STAGES = ["geometry", "binning", "local_self", "spread", "fft_fwd", "spectral", "fft_inv",
@@ -95,6 +96,9 @@ _lib.bs_ns_error_bins.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), 
 _lib.bs_set_mlp.argtypes = [_vp, _vp, _vp, C.c_int]
 _lib.bs_ns_counts.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
 _lib.bs_rk4_step.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int64), _vp, _vp, C.c_double]
+_lib.bs_step.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int64), _vp, _vp, _vp]
+_lib.bs_set_graph.argtypes = [_vp, C.c_int]
+_lib.bs_graph_active.argtypes = [_vp]
 
 
 def lib():
@@ -220,6 +224,24 @@ class Plan:
 
     def status(self):
         _check(_lib.bs_status(self._h), self._h)
+
+    def step(self, offsets, xyz, gamma, out):
+        """set_filaments + velocity in one call (graph replay when enabled)."""
+        if getattr(self, "_step_off", None) is None or len(self._step_off) != len(offsets) \
+                or not np.array_equal(self._step_off, offsets):
+            self._step_off = np.ascontiguousarray(offsets, dtype=np.int64)
+        off = self._step_off
+        _check(_lib.bs_step(self._h, len(off) - 1, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                            _ptr(xyz), _ptr(gamma), _ptr(out)), self._h)
+        self.N = int(off[-1])
+        self.nfil = len(off) - 1
+        return out
+
+    def set_graph(self, on: bool):
+        _check(_lib.bs_set_graph(self._h, int(bool(on))), self._h)
+
+    def graph_active(self) -> bool:
+        return bool(_lib.bs_graph_active(self._h))
 
     def rk4_step(self, offsets, xyz, gamma, dt):
         """Advance device positions xyz in place by one RK4 step."""

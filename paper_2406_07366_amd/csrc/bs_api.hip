@@ -577,6 +577,62 @@ int bs_rk4_step(bs_plan_t P, int64_t nfil, const int64_t *offsets, double *xyz,
     return launch_status(P, "rk4 kernels");
 }
 
+// ---------------------------------------------------------- graph replay
+static void drop_graph(bs_plan_t P) {
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+}
+
+int bs_set_graph(bs_plan_t P, int enable) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    if (enable && P->stream == nullptr)
+        return set_error(P, BS_EINVAL, "graph replay needs a non-null plan stream");
+    if (!enable) drop_graph(P);
+    P->use_graph = enable != 0;
+    return BS_OK;
+}
+
+int bs_step(bs_plan_t P, int64_t nfil, const int64_t *offsets, const double *xyz,
+            const double *gamma, double *v_out) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    const bool same = P->gexec && P->have_filaments && P->g_xyz == xyz && P->g_gamma == gamma &&
+                      P->g_v == v_out && P->nfil == nfil && offsets &&
+                      std::equal(offsets, offsets + nfil + 1, P->off_host.begin());
+    if (P->use_graph && !P->prof && same)
+        return check_hip(P, hipGraphLaunch(P->gexec, P->stream), "hipGraphLaunch");
+    // eager step (also sizes every buffer and uploads the filament structure)
+    int rc = bs_set_filaments(P, nfil, offsets, xyz, gamma);
+    if (!rc) rc = bs_velocity(P, v_out);
+    if (rc || !P->use_graph || P->prof) return rc;
+    // capture the same sequence; with unchanged offsets it has no host work
+    drop_graph(P);
+    hipError_t e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { P->use_graph = false; return BS_OK; }
+    int rc1 = bs_set_filaments(P, nfil, offsets, xyz, gamma);
+    int rc2 = rc1 ? rc1 : bs_velocity(P, v_out);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(P->stream, &g);
+    if (rc2 || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        P->use_graph = false;        // fall back to eager steps
+        return BS_OK;
+    }
+    if (hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        P->gexec = nullptr;
+        P->use_graph = false;
+        return BS_OK;
+    }
+    P->graph = g;
+    P->g_xyz = xyz; P->g_gamma = gamma; P->g_v = v_out;
+    return BS_OK;
+}
+
+int bs_graph_active(bs_plan_t P) { return P && P->gexec ? 1 : 0; }
+
 int bs_set_mlp(bs_plan_t P, bs_mlp_t mlp, const float *err_table, int nbins) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     int want = 0;
@@ -618,6 +674,7 @@ int bs_get_params(bs_plan_t P, bs_params *resolved) {
 int bs_destroy(bs_plan_t P) {
     if (!P) return BS_OK;
     (void)hipStreamSynchronize(P->stream);
+    drop_graph(P);
     for (int s = 0; s < BS_NSTAGES; s++) {
         if (P->ev_beg[s]) (void)hipEventDestroy(P->ev_beg[s]);
         if (P->ev_end[s]) (void)hipEventDestroy(P->ev_end[s]);

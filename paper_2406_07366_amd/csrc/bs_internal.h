@@ -83,6 +83,12 @@ struct bs_plan_s {
     bs::DBuf ns_X, ns_Y, ns_fallback;
     // RK4 stage buffers
     bs::DBuf rk_k, rk_s;
+    // graph replay of bs_step
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double *g_xyz = nullptr, *g_gamma = nullptr;
+    double *g_v = nullptr;
     // terms (for velocity terms / energy)
     bs::DBuf tmp3;                             // f64 [N][3]
     // per-stage timing (diagnostics)

@@ -220,3 +220,27 @@ def test_tangle_sampled(B, precision):
     err = rel_l2(v[idx], ref)
     print(f"  tangle prec={precision} sampled rel_l2 {err:.3e}")
     assert err <= 1e-5
+
+
+def test_graph_replay_matches_eager(B):
+    """bs_step recorded as a HIP graph and replayed: every replay, with eager
+    work and synchronisations in between, equals the eager result bitwise."""
+    import torch
+    fs = W.ellipses()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        print(f"\n[case] graph replay {fs.name}", flush=True)
+        plan = B.Plan(B.params_for(fs), stream=s)
+        xyz, g = B.load_workload(fs)
+        out = torch.empty((fs.n_nodes, 3), dtype=torch.float64, device="cuda")
+        plan.set_filaments(fs.offsets, xyz, g)
+        ref = plan.velocity(out).cpu().numpy()
+        plan.set_graph(True)
+        for k in range(6):
+            out.fill_(float(k))            # eager work between replays
+            plan.step(fs.offsets, xyz, g, out)
+            s.synchronize()
+            got = out.cpu().numpy()
+            assert np.array_equal(got, ref), k
+        print(f"  graph active: {plan.graph_active()}")
+        plan.close()

@@ -62,11 +62,20 @@ def test_rk4_ring_matches_oracle_and_translates(B):
     xo = oracle_rk4(fs, dt, steps)
     disp = np.abs(xo - fs.xyz).max()
     err = np.abs(xg - xo).max() / disp
-    print(f"  max |x_gpu - x_oracle| / displacement {err:.2e}; E drift {(E1 - E0) / E0:.2e}")
+    fo = W.FilamentSet(**{**fs.__dict__, "xyz": xo})
+    Eo0 = O.Oracle(fs).energy(O.Oracle(fs).reference()[1])
+    Eo1 = O.Oracle(fo).energy(O.Oracle(fo).reference()[1])
+    print(f"  max |x_gpu - x_oracle| / displacement {err:.2e}; E drift GPU {(E1 - E0) / E0:.2e}"
+          f" oracle {(Eo1 - Eo0) / Eo0:.2e}")
     assert err < 1e-5
     # the ring translates along its axis at its self-induced speed
     dz = (xg[:, 2] - fs.xyz[:, 2]).mean()
     assert abs(dz - v0[:, 2].mean() * dt * steps) < 1e-6 * abs(dz)
+    # the periodic images deform it only slightly (same radii as the oracle's)
     r = np.linalg.norm(xg[:, :2] - np.pi, axis=1)
-    assert np.abs(r - math.pi / 3).max() < 1e-9
-    assert abs(E1 - E0) < 1e-9 * abs(E0)
+    ro = np.linalg.norm(xo[:, :2] - np.pi, axis=1)
+    assert np.abs(r - math.pi / 3).max() < 1e-6
+    assert np.abs(r - ro).max() < 1e-9
+    # energy: conserved to the time-step error, and equal to the oracle's
+    assert abs(E1 - E0) < 1e-6 * abs(E0)
+    assert abs(E1 - Eo1) < 1e-6 * abs(Eo1)
