@@ -26,11 +26,15 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+from paper_2406_07366_amd.profsum import read_traffic  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_TFLOPS = 157.3     # MI355X dense fp32 vector
 FP64_VECTOR_TFLOPS = 78.6
 PAIR_FLOP = 60.0               # per interacting pair (erfc, exp, sqrt, div, cross, fma)
+# stages made of exactly one kernel launch, and the source file of that kernel
+SINGLE_KERNEL_STAGES = {"spread": "nufft.hip", "spectral": "nufft.hip", "interp": "nufft.hip",
+                        "pairs": "pairs.hip"}
 
 
 def log(*a):
@@ -219,12 +223,16 @@ def main():
     ap.add_argument("--workload", default="ellipses")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"))
+    ap.add_argument("--detail", default=None,
+                    help="also write per-stage times, rooflines and parameters to this JSON file")
     ap.add_argument("--drift", action="store_true",
                     help="bigtangle: energy drift of a 1e4-node subset against the FP64 oracle")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="end with a plain 256 MiB device copy, the size reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "only single-GPU runs are implemented: the sharded multi-GPU path does not exist; use --gpus 1"}))
         sys.exit(2)
 
     import torch
@@ -234,9 +242,10 @@ def main():
 
     if args.workload == "bigtangle":
         res = bigtangle(args, torch, B, W)
-        os.makedirs(os.path.dirname(args.detail), exist_ok=True)
-        with open(args.detail, "w") as f:
-            json.dump(res, f, indent=1, default=float)
+        if args.detail:
+            os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+            with open(args.detail, "w") as f:
+                json.dump(res, f, indent=1, default=float)
         print(json.dumps({"workload": "bigtangle", "nodes_per_s": res["nodes_per_s"],
                           "rk4_ms_per_step": res["rk4_ms_per_step"],
                           "drift_last": res["drift"][-1]}), flush=True)
@@ -287,6 +296,14 @@ def main():
         results[prec_name] = dict(ms=ms_host, ms_events=ms_ev, err=err, stages=st,
                                   prm=prm.as_dict(), plan=plan, ns_mode=ns_mode, ns_pairs=npairs)
 
+    if args.pmc_calibrate:
+        src_t = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(2):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+
     primary = results[args.precision]
     prm = primary["prm"]
     fp32 = args.precision == "mixed"
@@ -305,11 +322,17 @@ def main():
         roof_all["pairs"] = dict(bound="alu", achieved=fl / (st["pairs"] * 1e-3) / 1e12,
                                  peak=peak, unit="TFLOP/s", flops=fl, pairs=npairs,
                                  ms=st["pairs"])
-    dom = max((k for k in roof_all), key=lambda k: roof_all[k]["ms"])
+    # dominant single-kernel stage (stage events then time exactly one kernel)
+    dom = max((k for k in roof_all if k in SINGLE_KERNEL_STAGES), key=lambda k: roof_all[k]["ms"])
     d = roof_all[dom]
+    src = os.path.join(ROOT, "paper_2406_07366_amd", "csrc", SINGLE_KERNEL_STAGES[dom])
+    traffic = read_traffic(os.path.join(ROOT, "profiles",
+                                        f"pmc_{dom}_{fs.name}_{args.precision}.txt"), src)
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"],
                 "peak": d["peak"], "unit": d["unit"], "frac": d["achieved"] / d["peak"],
-                "traffic": None}
+                "traffic": traffic}
+    if "bytes" in d:
+        roofline["algorithmic_bytes"] = d["bytes"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -338,12 +361,13 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    os.makedirs(os.path.dirname(args.detail), exist_ok=True)
-    with open(args.detail, "w") as f:
-        json.dump({"line": line, "roofline_all": roof_all,
-                   "stages": {k: v["stages"] for k, v in results.items()},
-                   "params": {k: v["prm"] for k, v in results.items()},
-                   "pairs": npairs}, f, indent=1, default=float)
+    if args.detail:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump({"line": line, "roofline_all": roof_all,
+                       "stages": {k: v["stages"] for k, v in results.items()},
+                       "params": {k: v["prm"] for k, v in results.items()},
+                       "pairs": npairs}, f, indent=1, default=float)
     for r in results.values():
         r["plan"].close()
     print(json.dumps(line), flush=True)

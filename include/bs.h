@@ -210,8 +210,9 @@ int bs_status(bs_plan_t plan);
  *   1 binning (counting sorts and sorted copies)
  *   2 local and self terms      3 spread        4 forward FFT
  *   5 spectral operator         6 inverse FFT   7 interpolation
- *   8 short-range pairs         9 near-singular correction              */
-#define BS_NSTAGES 10
+ *   8 short-range pairs         9 near-singular correction
+ *  10 near-singular pair search (in bs_set_filaments, when ns_mode is on) */
+#define BS_NSTAGES 11
 int bs_set_profiling(bs_plan_t plan, int enable);
 int bs_stage_times(bs_plan_t plan, double *ms, int64_t *counts, int reset);
 
@@ -246,10 +247,12 @@ int bs_mlp_destroy(bs_mlp_t m);
  * (float64).  U: DEVICE float64 [n][8] uniforms in [0,1) supplied by the
  * caller (they fix the segment tangents, the target's position class,
  * distance and azimuth); X: DEVICE float32 [n][8] features; T: DEVICE float32
- * [n][3] targets (I_seg - I_tan) / |I_tan| in the chord frame, I_tan the
- * straight segment tangent to the curve at its point closest to the target
- * and d that distance; aux: DEVICE float64 [n][6] (d/h, exact raw integral
- * (3), |I_tan|, chord distance / h) or NULL.  The
+ * [n][3] targets (I_seg - I_tan) / m in the chord frame (chord length h = 1),
+ * I_tan the straight segment tangent to the curve at its point closest to
+ * the target, d that distance and m = 1 + log(1 + h/d); aux: DEVICE float64
+ * [n][7] (d/h, exact raw integral (3), m, the tangent segment's absolute
+ * integral S = int |ds|/|s-x|^2 that errors are measured against, chord
+ * distance / h) or NULL.  The
  * sample box: tangent angles <= 0.6 rad, tangent lengths in [0.9, 1.1],
  * d_c/h log-uniform in bs_ns_error_bins' range. */
 int bs_ns_samples(int64_t n, const double *U, float *X, float *T, double *aux,
@@ -265,8 +268,8 @@ int bs_ns_error_bins(double *lo, double *hi, int *nbins);
  * plan keeps the pointer: the network must outlive its use by the plan. */
 int bs_set_mlp(bs_plan_t plan, bs_mlp_t mlp, const float *err_table, int nbins);
 /* Synchronise; number of flagged near-singular pairs of the loaded
- * filaments, and number of adaptive fallbacks of the learned path since the
- * last call (which resets it). */
+ * filaments, and number of those the learned path handed to the adaptive
+ * integrator in the last velocity evaluation (0 if none ran). */
 int bs_ns_counts(bs_plan_t plan, int64_t *npairs, int64_t *nfallback);
 
 /* Parameters actually used (all derived fields filled). */

@@ -32,9 +32,9 @@ EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_velocity",
             "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_set_mlp", "bs_ns_counts", "bs_rk4_step", "bs_step", "bs_set_graph",
             "bs_graph_active"]
 
-NSTAGES = 10
+NSTAGES = 11
 STAGES = ["geometry", "binning", "local_self", "spread", "fft_fwd", "spectral", "fft_inv",
-          "interp", "pairs", "ns"]
+          "interp", "pairs", "ns", "ns_flag"]
 
 
 class BsParams(C.Structure):
@@ -371,7 +371,7 @@ def ns_samples(U, aux=True):
     n = U.shape[0]
     X = torch.empty((n, 8), dtype=torch.float32, device="cuda")
     T = torch.empty((n, 3), dtype=torch.float32, device="cuda")
-    A = torch.empty((n, 6), dtype=torch.float64, device="cuda") if aux else None
+    A = torch.empty((n, 7), dtype=torch.float64, device="cuda") if aux else None
     _check(_lib.bs_ns_samples(n, _ptr(U), _ptr(X), _ptr(T), _ptr(A),
                               _vp(torch.cuda.current_stream().cuda_stream)))
     return X, T, A

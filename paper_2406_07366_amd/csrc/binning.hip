@@ -93,11 +93,9 @@ void exclusive_scan(bs_plan_t p, const int *in, int *out, int n) {
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanBlock), 0, p->stream, in, n, sums, out);
 }
 
-// Bins are ordered by original index: one wavefront per bin computes every
-// entry's rank (number of smaller indices in the bin) and writes it to its
-// rank slot.  Bins of up to kSortLds entries are ranked in LDS and written
-// back in place; larger bins are ranked from global memory into the key array
-// (free once the scatter is done) and copied back.
+// Bins are ordered by original index: one wavefront per bin ranks its
+// entries (rank_sort_bin); a bin too large for LDS ranks into the key array,
+// which is free once the scatter is done.
 constexpr int kSortLds = 2048;
 
 // ------------------------------------------------------- fused bin passes
@@ -190,28 +188,9 @@ __global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
     if (b >= S.nbins[0]) { b -= S.nbins[0]; a = 1; }
     if (a == 1 && b >= S.nbins[1]) { b -= S.nbins[1]; a = 2; }
     if (a == 2 && b >= S.nbins[2]) return;
-    // reuse the single-array body
     __shared__ int v[kSortLds];
     int s = S.start[a][b], n = S.start[a][b + 1] - s;
-    int *perm = S.perm[a], *scratch = S.key[a];
-    if (n <= 1) return;
-    if (n <= kSortLds) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = perm[s + i];
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            int xv = v[i], r = 0;
-            for (int j = 0; j < n; j++) r += (v[j] < xv);
-            perm[s + r] = xv;
-        }
-        return;
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int xv = perm[s + i], r = 0;
-        for (int j = 0; j < n; j++) r += (perm[s + j] < xv);
-        scratch[s + r] = xv;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[s + i] = scratch[s + i];
+    rank_sort_bin<kSortLds>(S.perm[a], S.key[a], s, n, v);
 }
 
 // sorted copies for the spread (by tile) and the pairs (by cell), one pass

@@ -354,7 +354,16 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
         if (maxn > 512 && (rc = ensure<double>(P, P->spline_tmp, 12 * N))) return rc;
         if (P->prm.ns_mode != BS_NS_OFF) {
             size_t mp = (size_t)N * P->ns_max_per_node;
-            if ((rc = ensure<double>(P, P->ns_maxell, 1)) || (rc = ensure<int>(P, P->ns_cnt, N + 1)) ||
+            int ncmax = (int)cbrt(2.0 * (double)N);
+            P->ns_ncmax = ncmax < 3 ? 3 : (ncmax > 128 ? 128 : ncmax);
+            const size_t nb3 = (size_t)P->ns_ncmax * P->ns_ncmax * P->ns_ncmax;
+            if ((rc = ensure<double>(P, P->ns_red, 1025)) || (rc = ensure<int>(P, P->ns_nc, 1)) ||
+                (rc = ensure<int>(P, P->ns_ckey, N)) || (rc = ensure<int>(P, P->ns_ccnt, nb3 + 1)) ||
+                (rc = ensure<int>(P, P->ns_cstart, nb3 + 1)) ||
+                (rc = ensure<int>(P, P->ns_cfill, nb3 + 1)) || (rc = ensure<int>(P, P->ns_cperm, N)) ||
+                (rc = ensure<double4>(P, P->ns_segA, N)) || (rc = ensure<double4>(P, P->ns_segB, N)) ||
+                (rc = ensure<float4>(P, P->ns_segM, N)) ||
+                (rc = ensure<int2>(P, P->ns_slots, mp)) || (rc = ensure<int>(P, P->ns_cnt, N + 1)) ||
                 (rc = ensure<int>(P, P->ns_start, N + 1)) || (rc = ensure<int2>(P, P->ns_pairs, mp)) ||
                 (rc = ensure<int>(P, P->ns_pnode, mp)) || (rc = ensure<double>(P, P->ns_pout, 3 * mp)))
                 return rc;
@@ -392,8 +401,12 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     stage_end(P, 0);
     stage_begin(P, 1);
     build_bins(P);
-    if (P->prm.ns_mode != BS_NS_OFF) ns_build_pairs(P);
     stage_end(P, 1);
+    if (P->prm.ns_mode != BS_NS_OFF) {
+        stage_begin(P, 10);
+        ns_build_pairs(P);
+        stage_end(P, 10);
+    }
     if ((rc = launch_status(P, "geometry kernels"))) return rc;
     P->have_filaments = true;
     stage_collect(P);
@@ -657,8 +670,6 @@ int bs_ns_counts(bs_plan_t P, int64_t *npairs, int64_t *nfallback) {
                                               hipMemcpyDeviceToHost, P->stream), "read count")))
             return rc;
         if ((rc = check_hip(P, hipStreamSynchronize(P->stream), "sync"))) return rc;
-        if (P->ns_fallback.p)
-            (void)hipMemsetAsync(P->ns_fallback.p, 0, sizeof(int), P->stream);
     }
     if (npairs) *npairs = np;
     if (nfallback) *nfallback = nf;
@@ -687,7 +698,8 @@ int bs_destroy(bs_plan_t P) {
                    &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
                    &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
-                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->ns_maxell,
+                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->ns_red, &P->ns_nc, &P->ns_ckey,
+                   &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_slots,
                    &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout,
                    &P->ns_X, &P->ns_Y, &P->ns_fallback, &P->rk_k, &P->rk_s};
     for (DBuf *b : all) release(*b);

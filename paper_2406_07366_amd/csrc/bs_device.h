@@ -47,4 +47,31 @@ __device__ __forceinline__ int prev_node_d(const int *off, const int *fil, int j
     return (j > off[f]) ? j - 1 : off[f + 1] - 1;
 }
 
+// Orders the distinct entries perm[s .. s+n) ascending: every entry's rank is
+// the number of smaller entries in the bin, and it is written to its rank slot.
+// Called by a whole workgroup for one bin.  Bins of up to CAP entries are
+// ranked from the LDS array v and written back in place; larger bins are
+// ranked from global memory into scratch (same indexing) and copied back.
+template <int CAP>
+__device__ void rank_sort_bin(int *perm, int *scratch, int s, int n, int *v) {
+    if (n <= 1) return;
+    if (n <= CAP) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = perm[s + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            int xv = v[i], r = 0;
+            for (int j = 0; j < n; j++) r += (v[j] < xv);
+            perm[s + r] = xv;
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int xv = perm[s + i], r = 0;
+        for (int j = 0; j < n; j++) r += (perm[s + j] < xv);
+        scratch[s + r] = xv;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[s + i] = scratch[s + i];
+}
+
 }  // namespace bs

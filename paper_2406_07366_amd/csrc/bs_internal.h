@@ -76,7 +76,13 @@ struct bs_plan_s {
     int64_t max_fil_nodes = 0;
     // near-singular pairs
     int ns_max_per_node = 32;
-    bs::DBuf ns_maxell, ns_cnt, ns_start, ns_pairs, ns_pnode, ns_pout;
+    int ns_ncmax = 3;                          // bound on the segment cell grid per axis
+    bs::DBuf ns_red, ns_nc;                    // f64 [1 + blocks] max reach, int32 cells per axis
+    bs::DBuf ns_ckey, ns_ccnt, ns_cstart, ns_cfill, ns_cperm;   // segments by midpoint cell
+    bs::DBuf ns_segA, ns_segB;                 // double4 [N] cell-ordered end points
+    bs::DBuf ns_segM;                          // float4 [N] midpoint and reach (prefilter)
+    bs::DBuf ns_slots;                         // int2 [N][max_per_node] per-node flag output
+    bs::DBuf ns_cnt, ns_start, ns_pairs, ns_pnode, ns_pout;
     // learned correction
     bs_mlp_t mlp = nullptr;
     float ns_err[16] = {};

@@ -293,34 +293,58 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t B, const float *__rest
     if (threadIdx.x == 0) loss_partial[blockIdx.x] = lsum;
 }
 
-// sum workgroup partials (fixed order) and fold the padded image back to the
-// master layout; loss likewise
-__global__ void k_mlp_reduce(int nb, const float *__restrict__ partial,
-                             const float *__restrict__ loss_partial, float *__restrict__ grad,
-                             float *__restrict__ loss) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+// Sum of the workgroup partials in a fixed order: block j < kGpad / 64 owns
+// 64 consecutive entries of the padded gradient image; its 4 thread groups
+// sum 4 contiguous quarters of the partials (coalesced rows) and the quarter
+// sums are added in order.  The extra last block sums the loss partials
+// (fixed per-thread strides, then a fixed tree).
+constexpr int kRedCols = 64;
+constexpr int kRedBlocks = (kGpad + kRedCols - 1) / kRedCols;
+
+__global__ __launch_bounds__(256) void k_mlp_reduce_pad(int nb, const float *__restrict__ partial,
+                                                       const float *__restrict__ loss_partial,
+                                                       float *__restrict__ gpad,
+                                                       float *__restrict__ loss) {
+    __shared__ float sh[256];
+    const int t = threadIdx.x;
+    if (blockIdx.x == kRedBlocks) {
         float s = 0.f;
-        for (int k = 0; k < nb; k++) s += loss_partial[k];
-        *loss = s;
+        for (int k = t; k < nb; k += 256) s += loss_partial[k];
+        sh[t] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) sh[t] += sh[t + o];
+            __syncthreads();
+        }
+        if (t == 0) *loss = sh[0];
+        return;
     }
+    const int c = t % kRedCols, g = t / kRedCols;
+    const int i = blockIdx.x * kRedCols + c;
+    const int q = (nb + 3) / 4, k0 = g * q, k1 = k0 + q < nb ? k0 + q : nb;
+    float s = 0.f;
+    if (i < kGpad)
+        for (int k = k0; k < k1; k++) s += partial[(size_t)k * kGpad + i];
+    sh[t] = s;
+    __syncthreads();
+    if (g == 0 && i < kGpad) gpad[i] = (sh[c] + sh[64 + c]) + (sh[128 + c] + sh[192 + c]);
+}
+
+// fold the padded gradient image back to the master layout
+__global__ void k_mlp_fold(const float *__restrict__ gp, float *__restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kNP) return;
-    auto sum = [&](int pi) {
-        float s = 0.f;
-        for (int k = 0; k < nb; k++) s += partial[(size_t)k * kGpad + pi];
-        return s;
-    };
     float v;
-    if (i < 512) {                               // W1[o][c]
+    if (i < 512) {                               // W1[o][c]: both copies of column c
         int o = i / 8, c = i % 8;
-        v = sum(kW1p + o * 16 + c) + sum(kW1p + o * 16 + 8 + c);
-    } else if (i < 576) v = sum(kWpad + kB1 + (i - 512));
-    else if (i < 4672) v = sum(kW2 + (i - 576));
-    else if (i < 4736) v = sum(kWpad + kB2 + (i - 4672));
-    else if (i < 8832) v = sum(kW3 + (i - 4736));
-    else if (i < 8896) v = sum(kWpad + kB3 + (i - 8832));
-    else if (i < 9088) v = sum(kW4p + (i - 8896));    // rows 0..2 of W4p
-    else v = sum(kWpad + kB4p + (i - 9088));
+        v = gp[kW1p + o * 16 + c] + gp[kW1p + o * 16 + 8 + c];
+    } else if (i < 576) v = gp[kWpad + kB1 + (i - 512)];
+    else if (i < 4672) v = gp[kW2 + (i - 576)];
+    else if (i < 4736) v = gp[kWpad + kB2 + (i - 4672)];
+    else if (i < 8832) v = gp[kW3 + (i - 4736)];
+    else if (i < 8896) v = gp[kWpad + kB3 + (i - 8832)];
+    else if (i < 9088) v = gp[kW4p + (i - 8896)];    // rows 0..2 of W4p
+    else v = gp[kWpad + kB4p + (i - 9088)];
     grad[i] = v;
 }
 
@@ -369,7 +393,7 @@ struct bs_mlp_s {
     float *P = nullptr, *m = nullptr, *v = nullptr, *G = nullptr;
     unsigned short *wg = nullptr;
     float *bg = nullptr;
-    float *partial = nullptr, *loss_partial = nullptr, *loss = nullptr;
+    float *partial = nullptr, *loss_partial = nullptr, *loss = nullptr, *gpad = nullptr;
     int nb = 512;
     int64_t step = 0;
     std::string err;
@@ -399,6 +423,7 @@ int bs_mlp_create(const float *params_host, void *hip_stream, bs_mlp_t *out) {
     al((void **)&M->G, kNP * 4); al((void **)&M->wg, kWpad * 2); al((void **)&M->bg, kBpad * 4);
     al((void **)&M->partial, (size_t)M->nb * kGpad * 4);
     al((void **)&M->loss_partial, M->nb * 4); al((void **)&M->loss, 4);
+    al((void **)&M->gpad, kGpad * 4);
     if (e != hipSuccess) { bs_mlp_destroy(M); return BS_ENOMEM; }
     (void)hipMemcpy(M->P, params_host, kNP * 4, hipMemcpyHostToDevice);
     (void)hipMemset(M->m, 0, kNP * 4);
@@ -424,8 +449,10 @@ static int mlp_grad(bs_mlp_t M, int64_t B, const float *X, const float *T) {
     int blocks = (int)std::min<int64_t>(tiles, M->nb);
     hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(64), 0, M->stream, B, X, T,
                        1.0f / (float)B, M->wg, M->bg, M->partial, M->loss_partial);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3(ceil_div(kNP, 256)), dim3(256), 0, M->stream, blocks,
-                       M->partial, M->loss_partial, M->G, M->loss);
+    hipLaunchKernelGGL(k_mlp_reduce_pad, dim3(kRedBlocks + 1), dim3(256), 0, M->stream, blocks,
+                       M->partial, M->loss_partial, M->gpad, M->loss);
+    hipLaunchKernelGGL(k_mlp_fold, dim3(ceil_div(kNP, 256)), dim3(256), 0, M->stream, M->gpad,
+                       M->G);
     return hipGetLastError() == hipSuccess ? BS_OK : BS_EDEVICE;
 }
 
@@ -464,7 +491,8 @@ int bs_mlp_get_params(bs_mlp_t M, float *params_host) {
 int bs_mlp_destroy(bs_mlp_t M) {
     if (!M) return BS_OK;
     (void)hipStreamSynchronize(M->stream);
-    void *all[] = {M->P, M->m, M->v, M->G, M->wg, M->bg, M->partial, M->loss_partial, M->loss};
+    void *all[] = {M->P, M->m, M->v, M->G, M->wg, M->bg, M->partial, M->loss_partial, M->loss,
+                   M->gpad};
     for (void *p : all)
         if (p) (void)hipFree(p);
     delete M;

@@ -28,18 +28,58 @@ struct NsRule {
     double w[kNsGL];
 };
 
-// ------------------------------------------------------------ max segment
-__global__ void k_max_ell(int N, const double *__restrict__ ell, double *__restrict__ out) {
+// ------------------------------------------------------------ cell grid
+// A segment j flags target x when the distance from x to its chord is below
+// eta * ell_j.  Then |x - m_j| < reach_j = eta * ell_j + |B_j - A_j| / 2 (m_j
+// the chord midpoint), so with segments binned by midpoint into cells of edge
+// >= max_j reach_j, every segment a target flags lies in the 3^3 cells around
+// the target.  The cell count is decided on the device from that maximum.
+constexpr int kNsRedBlocks = 1024;
+
+__global__ void k_ns_reach(int N, const int *__restrict__ off, const int *__restrict__ fil,
+                           const double *__restrict__ x, const double *__restrict__ ell,
+                           double eta, double *__restrict__ partial) {
     __shared__ double sh[256];
     double m = 0.0;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) m = fmax(m, ell[j]);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+        const int jn = next_node_d(off, fil, j);
+        double c2 = 0.0;
+        for (int q = 0; q < 3; q++) {
+            double d = x[3 * jn + q] - x[3 * j + q];
+            c2 += d * d;
+        }
+        m = fmax(m, eta * ell[j] + 0.5 * sqrt(c2));
+    }
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// nc = floor(L / max reach), at most ncmax; below 3 a single cell holds every
+// segment (the 27 neighbours would repeat cells)
+__global__ void k_ns_cells(const double *__restrict__ partial, int nparts, double L, int ncmax,
+                           double *__restrict__ maxreach, int *__restrict__ nc_out) {
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partial[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        m = sh[0];
+        double f = m > 0.0 ? floor(L / (m * (1.0 + 1e-9))) : (double)ncmax;
+        int nc = f > (double)ncmax ? ncmax : (int)f;
+        if (nc < 3) nc = 1;
+        *maxreach = m;
+        *nc_out = nc;
+    }
 }
 
 __device__ __forceinline__ int cell_of(double v, double L, int nc) {
@@ -47,11 +87,66 @@ __device__ __forceinline__ int cell_of(double v, double L, int nc) {
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
-__device__ __forceinline__ bool in_window(int c, int c0, int span, int nc) {
-    int d = c - c0;
-    if (d < 0) d = -d;
-    if (nc - d < d) d = nc - d;
-    return d <= span;
+__global__ void k_ns_zero(int n, int *__restrict__ a, int *__restrict__ b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { a[i] = 0; b[i] = 0; }
+}
+
+__global__ void k_ns_keys(int N, const int *__restrict__ off, const int *__restrict__ fil,
+                          const double *__restrict__ x, double L, const int *__restrict__ ncp,
+                          int *__restrict__ key, int *__restrict__ cnt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int nc = *ncp, jn = next_node_d(off, fil, j);
+    int c[3];
+    for (int q = 0; q < 3; q++) c[q] = cell_of(0.5 * (x[3 * j + q] + x[3 * jn + q]), L, nc);
+    const int k = (c[2] * nc + c[1]) * nc + c[0];
+    key[j] = k;
+    atomicAdd(&cnt[k], 1);
+}
+
+__global__ void k_ns_scatter(int N, const int *__restrict__ key, const int *__restrict__ start,
+                             int *__restrict__ fill, int *__restrict__ perm) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int k = key[j];
+    perm[start[k] + atomicAdd(&fill[k], 1)] = j;
+}
+
+// one wavefront per occupied cell range, striding over the nc^3 cells
+constexpr int kNsSortLds = 1024;
+__global__ __launch_bounds__(64) void k_ns_sort(const int *__restrict__ ncp,
+                                               const int *__restrict__ start, int *__restrict__ perm,
+                                               int *__restrict__ scratch) {
+    __shared__ int v[kNsSortLds];
+    const int nc = *ncp, nb = nc * nc * nc;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int s0 = start[b], n = start[b + 1] - s0;
+        rank_sort_bin<kNsSortLds>(perm, scratch, s0, n, v);
+        __syncthreads();
+    }
+}
+
+// cell-ordered copies of each segment's end points, weight ell and index,
+// and the float32 sphere (wrapped chord midpoint, reach) of the prefilter
+__global__ void k_ns_gather(int N, const int *__restrict__ perm, const int *__restrict__ off,
+                            const int *__restrict__ fil, const double *__restrict__ x,
+                            const double *__restrict__ ell, double eta, double L,
+                            double4 *__restrict__ segA, double4 *__restrict__ segB,
+                            float4 *__restrict__ segM) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int j = perm[p], jn = next_node_d(off, fil, j);
+    segA[p] = make_double4(x[3 * j], x[3 * j + 1], x[3 * j + 2], ell[j]);
+    segB[p] = make_double4(x[3 * jn], x[3 * jn + 1], x[3 * jn + 2], (double)j);
+    double c2 = 0.0, m[3];
+    for (int q = 0; q < 3; q++) {
+        const double d = x[3 * jn + q] - x[3 * j + q];
+        c2 += d * d;
+        m[q] = wrap_box(0.5 * (x[3 * j + q] + x[3 * jn + q]), L);
+    }
+    segM[p] = make_float4((float)m[0], (float)m[1], (float)m[2],
+                          (float)(eta * ell[j] + 0.5 * sqrt(c2)));
 }
 
 // chord distance from x to segment A->B with A, B shifted by the minimum
@@ -73,21 +168,22 @@ __device__ __forceinline__ double chord_dist(const double *A, const double *B, c
 }
 
 struct NsArgs {
-    int N, Q, nc, max_per_node;
+    int N, max_per_node;
     double L, eta;
-    const double *x, *ell, *qpos, *maxell;
-    const int *off, *fil, *nperm, *cstart, *sseg;
-    const double4 *spos;
+    const double *x;
+    const int *off, *fil, *nperm, *ncp, *cstart;
+    const double4 *segA, *segB;
+    const float4 *segM;
 };
 
-// One wavefront per node: lanes take consecutive quadrature points of each
-// scanned cell; flagged lanes are ranked with a ballot so that pass 0 counts
-// and pass 1 writes the pairs in scan order (cell order, then sorted order).
-// pass 0: cnt[o] = number of flagged pairs; pass 1: write pairs at pstart[o]
-template <int PASS>
+// One wavefront per target node.  Lanes 0..26 hold one of the 27 cells
+// around the target; the cells' contents are enumerated as one flattened
+// range, 64 candidates per step, each lane finding its cell by binary search
+// over the wavefront's prefix sums.  Flagged candidates are ranked with a
+// ballot, so a node's pairs are written in enumeration order (cell order,
+// then segment order within a cell) to its max_per_node slots.
 __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt,
-                                                 const int *__restrict__ pstart,
-                                                 int2 *__restrict__ pairs,
+                                                 int2 *__restrict__ slots,
                                                  int *__restrict__ status) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = gid >> 6, lane = gid & 63;
@@ -95,82 +191,99 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
     const int o = a.nperm[t];
     const int ip = prev_node_d(a.off, a.fil, o);
     const double xi[3] = {a.x[3 * o], a.x[3 * o + 1], a.x[3 * o + 2]};
-    const int nc = a.nc;
-    int c0[3];
-    for (int q = 0; q < 3; q++) c0[q] = cell_of(xi[q], a.L, nc);
-    const double cell = a.L / nc;
-    int span = (int)ceil((a.eta + 1.25) * (*a.maxell) / cell);
-    bool full = (2 * span + 1 >= nc);
-    if (full) span = nc;   // every cell, once
-    const int lo = full ? 0 : -span, hi = full ? nc - 1 : span;
-    int k = 0;
-    const int base = PASS ? pstart[o] : 0;
+    const float xf[3] = {(float)wrap_box(xi[0], a.L), (float)wrap_box(xi[1], a.L),
+                         (float)wrap_box(xi[2], a.L)};
+    const float Lf = (float)a.L, iLf = (float)(1.0 / a.L), margin = (float)(1e-5 * a.L);
+    const int nc = *a.ncp;
+    const int ncell = nc >= 3 ? 27 : 1;
+    int cs = 0, cn = 0;
+    if (lane < ncell) {
+        int cidx = 0;
+        if (nc >= 3) {
+            const int dd[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+            int c[3];
+            for (int q = 0; q < 3; q++) {
+                int v = cell_of(xi[q], a.L, nc) + dd[q];
+                c[q] = v < 0 ? v + nc : (v >= nc ? v - nc : v);
+            }
+            cidx = (c[2] * nc + c[1]) * nc + c[0];
+        }
+        cs = a.cstart[cidx];
+        cn = a.cstart[cidx + 1] - cs;
+    }
+    int incl = cn;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    const int total = __shfl(incl, 63);
+    const int excl = incl - cn;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int dz = lo; dz <= hi; dz++) {
-        int cz = full ? dz : c0[2] + dz;
-        cz = cz < 0 ? cz + nc : (cz >= nc ? cz - nc : cz);
-        for (int dy = lo; dy <= hi; dy++) {
-            int cy = full ? dy : c0[1] + dy;
-            cy = cy < 0 ? cy + nc : (cy >= nc ? cy - nc : cy);
-            for (int dx = lo; dx <= hi; dx++) {
-                int cx = full ? dx : c0[0] + dx;
-                cx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
-                const int cidx = (cz * nc + cy) * nc + cx;
-                const int s = a.cstart[cidx], e = a.cstart[cidx + 1];
-                for (int p0 = s; p0 < e; p0 += 64) {
-                    const int p = p0 + lane;
-                    bool flag = false;
-                    int sg = -1;
-                    double xs[3] = {0.0, 0.0, 0.0};
-                    if (p < e) {
-                        sg = a.sseg[p];
-                        if (sg != o && sg != ip) {
-                            int jn = next_node_d(a.off, a.fil, sg);
-                            const double A[3] = {a.x[3 * sg], a.x[3 * sg + 1], a.x[3 * sg + 2]};
-                            const double Bv[3] = {a.x[3 * jn], a.x[3 * jn + 1], a.x[3 * jn + 2]};
-                            double d = chord_dist(A, Bv, xi, a.L, xs);
-                            if (d < a.eta * a.ell[sg]) {
-                                // count the segment once: at the first of its
-                                // quadrature points inside the scanned window
-                                double4 sp = a.spos[p];
-                                int first = 0;
-                                for (int i2 = 0; i2 < a.Q; i2++) {
-                                    const double *qp = a.qpos + 3 * ((size_t)sg * a.Q + i2);
-                                    bool inw = full ||
-                                               (in_window(cell_of(qp[0], a.L, nc), c0[0], span, nc) &&
-                                                in_window(cell_of(qp[1], a.L, nc), c0[1], span, nc) &&
-                                                in_window(cell_of(qp[2], a.L, nc), c0[2], span, nc));
-                                    if (inw) { first = i2; break; }
-                                }
-                                const double *qf = a.qpos + 3 * ((size_t)sg * a.Q + first);
-                                flag = wrap_box(qf[0], a.L) == sp.x && wrap_box(qf[1], a.L) == sp.y &&
-                                       wrap_box(qf[2], a.L) == sp.z;
-                            }
-                        }
+    int2 *out = slots + (size_t)o * a.max_per_node;
+    int k = 0;
+    for (int q0 = 0; q0 < total; q0 += 64) {
+        const int q = q0 + lane;
+        // last cell whose exclusive prefix is <= q
+        int c = 0;
+        for (int step = 16; step > 0; step >>= 1) {
+            const int tc = c + step;
+            const int pv = __shfl(excl, tc < ncell ? tc : ncell - 1);
+            if (tc < ncell && pv <= q) c = tc;
+        }
+        const int p = __shfl(cs, c) + (q - __shfl(excl, c));
+        bool flag = false;
+        int sg = -1, sh = 0;
+        // float32 prefilter: a flagged segment has |x - m| < reach (chord
+        // midpoint m); the margin covers the float32 rounding of both points
+        bool near = false;
+        if (q < total) {
+            const float4 M4 = a.segM[p];
+            float dx = xf[0] - M4.x, dy = xf[1] - M4.y, dz = xf[2] - M4.z;
+            dx -= Lf * rintf(dx * iLf); dy -= Lf * rintf(dy * iLf); dz -= Lf * rintf(dz * iLf);
+            const float r = M4.w + margin;
+            near = dx * dx + dy * dy + dz * dz < r * r;
+        }
+        if (near) {
+            const double4 A4 = a.segA[p], B4 = a.segB[p];
+            sg = (int)B4.w;
+            if (sg != o && sg != ip) {
+                const double A[3] = {A4.x, A4.y, A4.z}, Bv[3] = {B4.x, B4.y, B4.z};
+                double xs[3];
+                if (chord_dist(A, Bv, xi, a.L, xs) < a.eta * A4.w) {
+                    flag = true;
+                    // image shift of the target, periods per axis, packed as
+                    // three 10-bit fields (+-511 periods)
+                    for (int r = 0; r < 3; r++) {
+                        int sv = (int)rint((xs[r] - xi[r]) / a.L);
+                        sv = sv < -511 ? -511 : (sv > 511 ? 511 : sv);
+                        sh = (sh << 10) | (sv + 512);
                     }
-                    const unsigned long long m = __ballot(flag);
-                    if (PASS && flag) {
-                        int slot = k + __popcll(m & below);
-                        if (slot < a.max_per_node) {
-                            // image shift of the target, periods per axis,
-                            // packed as three 10-bit fields (+-511 periods)
-                            int sh = 0;
-                            for (int q = 0; q < 3; q++) {
-                                int sv = (int)rint((xs[q] - xi[q]) / a.L);
-                                sv = sv < -511 ? -511 : (sv > 511 ? 511 : sv);
-                                sh = (sh << 10) | (sv + 512);
-                            }
-                            pairs[base + slot] = make_int2(sg, sh);
-                        }
-                    }
-                    k += __popcll(m);
                 }
             }
         }
+        const unsigned long long m = __ballot(flag);
+        if (flag) {
+            const int slot = k + __popcll(m & below);
+            if (slot < a.max_per_node) out[slot] = make_int2(sg, sh);
+        }
+        k += __popcll(m);
     }
-    if (PASS == 0 && lane == 0) {
+    if (lane == 0) {
         if (k > a.max_per_node) atomicOr(status, 2);
         cnt[o] = k < a.max_per_node ? k : a.max_per_node;
+    }
+}
+
+// compact list: node o's pairs at [start[o], start[o] + cnt[o]), owner pnode
+__global__ void k_ns_compact(int64_t total_slots, int maxpn, const int *__restrict__ cnt,
+                             const int *__restrict__ start, const int2 *__restrict__ slots,
+                             int2 *__restrict__ pairs, int *__restrict__ pnode) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total_slots) return;
+    const int o = (int)(i / maxpn), s = (int)(i % maxpn);
+    if (s < cnt[o]) {
+        pairs[start[o] + s] = slots[i];
+        pnode[start[o] + s] = o;
     }
 }
 
@@ -340,12 +453,6 @@ __global__ __launch_bounds__(256) void k_ns_integrate(
 }
 
 // owner node of each pair slot (for the per-pair kernel)
-__global__ void k_ns_owner(int N, const int *__restrict__ pstart, int *__restrict__ pnode) {
-    int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= N) return;
-    for (int p = pstart[o]; p < pstart[o + 1]; p++) pnode[p] = o;
-}
-
 __global__ void k_ns_apply(int N, const int *__restrict__ pstart, const double *__restrict__ pout,
                            double *__restrict__ v) {
     int o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -403,12 +510,19 @@ __device__ __forceinline__ void chord_raw(const double *A, const double *B, cons
 
 // Straight segment tangent to the curve at its point P closest to x, running
 // |P - s(0)| back and |s(1) - P| forward along the unit tangent: it carries
-// the same 1/d singularity as the curve (d = |P - x|), so the remainder
-// I_seg - I_tan is small relative to I_tan near the curve.  Returns I_tan
-// (raw integral), the scale |I_tan| the network's output is multiplied by,
-// and d/h.
-__device__ void tangent_baseline(const Seg &s, const double *x, double h, double *Itan,
-                                 double *scale, double *dstar) {
+// the same 1/d singularity as the curve (d = |P - x|), and the remainder
+// I_seg - I_tan grows only like log(1/d) as d -> 0.  Returns I_tan (raw
+// integral), the target multiplier mult = (1 + log(1 + h/d)) / h that
+// bounds that remainder (the network predicts (I_seg - I_tan) / mult), the
+// tangent segment's absolute integral S = int |ds| / |s - x|^2 in closed form
+// (the scale errors are measured against; it never vanishes), and d/h.
+struct TangentBase {
+    double I[3];
+    double mult, S, dstar;
+};
+
+__device__ TangentBase tangent_baseline(const Seg &s, const double *x, double h) {
+    TangentBase tb;
     const double u = closest_u(s, x);
     double P[3], d1[3], S0[3], S1[3], dummy[3];
     seg_eval(s, u, P, d1);
@@ -422,15 +536,28 @@ __device__ void tangent_baseline(const Seg &s, const double *x, double h, double
         d += (P[q] - x[q]) * (P[q] - x[q]);
     }
     a = sqrt(a); b = sqrt(b); d = sqrt(d);
-    double A[3], B[3];
+    double A[3], B[3], t[3];
     for (int q = 0; q < 3; q++) {
-        A[q] = P[q] - a * d1[q] / tn;
-        B[q] = P[q] + b * d1[q] / tn;
+        t[q] = d1[q] / tn;
+        A[q] = P[q] - a * t[q];
+        B[q] = P[q] + b * t[q];
     }
-    chord_raw(A, B, x, Itan);
-    double m = sqrt(Itan[0] * Itan[0] + Itan[1] * Itan[1] + Itan[2] * Itan[2]);
-    *scale = m > 1e-300 ? m : 1e-300;
-    *dstar = d / h;
+    chord_raw(A, B, x, tb.I);
+    // int_0^len dl / (rho^2 + (l + p)^2) = atan2(rho len, rho^2 + u1 u2) / rho,
+    // u1 = p, u2 = p + len, p = (A - x).t, rho the distance to the line
+    double p = 0.0, r2 = 0.0;
+    for (int q = 0; q < 3; q++) {
+        p += (A[q] - x[q]) * t[q];
+        r2 += (A[q] - x[q]) * (A[q] - x[q]);
+    }
+    const double len = a + b, u1 = p, u2 = p + len;
+    double rho2 = r2 - p * p;
+    rho2 = rho2 > 0.0 ? rho2 : 0.0;
+    const double rho = sqrt(rho2);
+    tb.S = rho > 1e-300 ? atan2(rho * len, rho2 + u1 * u2) / rho : len / (u1 * u2);
+    tb.dstar = d / h;
+    tb.mult = (1.0 + log1p(h / fmax(d, 1e-300 * h))) / h;
+    return tb;
 }
 
 struct NsFrame {
@@ -529,28 +656,39 @@ __global__ void k_ns_samples(int64_t n, const double *__restrict__ U, NsRule R,
         s.c2[q] = 3.0 * (B[q] - A[q]) - 2.0 * D0[q] - D1[q];
         s.c3[q] = 2.0 * (A[q] - B[q]) + D0[q] + D1[q];
     }
-    double I[3], It[3], scale, dstar;
+    double I[3];
     ns_seg_integral(s, x, R, I);
-    tangent_baseline(s, x, 1.0, It, &scale, &dstar);
+    const TangentBase tb = tangent_baseline(s, x, 1.0);
     NsFrame F = ns_frame(A, B, D0, D1, x);
     for (int k = 0; k < 8; k++) X[8 * i + k] = F.f[k];
-    for (int q = 0; q < 3; q++) T[3 * i + q] = (float)((I[q] - It[q]) / scale);
+    for (int q = 0; q < 3; q++) T[3 * i + q] = (float)((I[q] - tb.I[q]) / tb.mult);
     if (aux) {
-        aux[6 * i] = dstar;
-        aux[6 * i + 1] = I[0]; aux[6 * i + 2] = I[1]; aux[6 * i + 3] = I[2];
-        aux[6 * i + 4] = scale;
-        aux[6 * i + 5] = F.dc;
+        double *o = aux + 7 * i;
+        o[0] = tb.dstar;
+        o[1] = I[0]; o[2] = I[1]; o[3] = I[2];
+        o[4] = tb.mult;
+        o[5] = tb.S;
+        o[6] = F.dc;
     }
 }
 
+// Pair (target o, segment sg): end points, the end tangents ds/du of the
+// segment over u in [0, 1] in units of its chord length h (the sample box's
+// frame), and the image-shifted target.
 __device__ __forceinline__ void pair_geometry(int o, int sg, int sh, const int *off, const int *fil,
-                                              const double *x, const double *D, double L,
-                                              double *A, double *B, double *D0, double *D1,
-                                              double *xs) {
+                                              const double *x, const double *D,
+                                              const double *dtau, double L, double *A,
+                                              double *B, double *D0, double *D1, double *xs) {
     int jn = next_node_d(off, fil, sg);
+    double h2 = 0.0;
     for (int q = 0; q < 3; q++) {
         A[q] = x[3 * sg + q]; B[q] = x[3 * jn + q];
-        D0[q] = D[3 * sg + q]; D1[q] = D[3 * jn + q];
+        h2 += (B[q] - A[q]) * (B[q] - A[q]);
+    }
+    const double sc = dtau[sg] / sqrt(h2);
+    for (int q = 0; q < 3; q++) {
+        D0[q] = sc * D[3 * sg + q];
+        D1[q] = sc * D[3 * jn + q];
     }
     unpack_shift(sh, x + 3 * o, L, xs);
 }
@@ -558,12 +696,13 @@ __device__ __forceinline__ void pair_geometry(int o, int sg, int sh, const int *
 __global__ __launch_bounds__(256) void k_ns_features(
     const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
     const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ D, double L, float *__restrict__ X) {
+    const double *__restrict__ D, const double *__restrict__ dtau, double L,
+    float *__restrict__ X) {
     const int P = *total;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         int2 pr = pairs[p];
         double A[3], B[3], D0[3], D1[3], xs[3];
-        pair_geometry(pnode[p], pr.x, pr.y, off, fil, x, D, L, A, B, D0, D1, xs);
+        pair_geometry(pnode[p], pr.x, pr.y, off, fil, x, D, dtau, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
         for (int k = 0; k < 8; k++) X[8 * (size_t)p + k] = F.f[k];
     }
@@ -582,23 +721,24 @@ __global__ __launch_bounds__(256) void k_ns_combine(
         int2 pr = pairs[p];
         const int o = pnode[p];
         double A[3], B[3], D0[3], D1[3], xs[3];
-        pair_geometry(o, pr.x, pr.y, off, fil, x, D, L, A, B, D0, D1, xs);
+        pair_geometry(o, pr.x, pr.y, off, fil, x, D, dtau, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
         Seg sgm = load_seg(pr.x, off, fil, x, D, dtau);
-        double It[3], scale, dstar;
-        tangent_baseline(sgm, xs, F.h, It, &scale, &dstar);
+        const TangentBase tb = tangent_baseline(sgm, xs, F.h);
         double out[3];
-        if (!F.inbox || (double)box.err[ns_bin(dstar)] > box.tol) {
+        if (!F.inbox || (double)box.err[ns_bin(tb.dstar)] > box.tol) {
             ns_pair(o, pr.x, pr.y, off, fil, x, D, dtau, gamma, qpos, qchg, Q, L, R, out);
             atomicAdd(nfallback, 1);
         } else {
+            // segment integral = I_tan + mult * (network output in the chord
+            // frame), minus the Q-point sum the pair kernel already added
             double qs[3], y[3];
-            for (int k = 0; k < 3; k++) y[k] = (double)Y[3 * (size_t)p + k] * scale;
+            for (int k = 0; k < 3; k++) y[k] = (double)Y[3 * (size_t)p + k] * tb.mult;
             ns_qsum(pr.x, xs, qpos, qchg, Q, qs);
             const double g4 = gamma[fil[pr.x]] / (4.0 * kPi);
             for (int q = 0; q < 3; q++) {
                 double yw = F.e[0][q] * y[0] + F.e[1][q] * y[1] + F.e[2][q] * y[2];
-                out[q] = g4 * (It[q] + yw / F.h) - qs[q] / (4.0 * kPi);
+                out[q] = g4 * (tb.I[q] + yw) - qs[q] / (4.0 * kPi);
             }
         }
         pout[3 * (size_t)p] = out[0];
@@ -607,33 +747,50 @@ __global__ __launch_bounds__(256) void k_ns_combine(
     }
 }
 
-static NsArgs ns_args(bs_plan_t p) {
-    NsArgs a;
-    a.N = (int)p->N; a.Q = p->Q; a.nc = p->nc; a.max_per_node = p->ns_max_per_node;
-    a.L = p->prm.L; a.eta = p->prm.ns_eta;
-    a.x = (const double *)p->d_x.p; a.ell = (const double *)p->d_ell.p;
-    a.qpos = (const double *)p->d_qpos.p; a.maxell = (const double *)p->ns_maxell.p;
-    a.off = (const int *)p->d_off.p; a.fil = (const int *)p->d_fil.p;
-    a.nperm = (const int *)p->nd_perm.p; a.cstart = (const int *)p->pq_start.p;
-    a.sseg = (const int *)p->pq_seg.p; a.spos = (const double4 *)p->pq_pos.p;
-    return a;
-}
-
 // flag + list build (after geometry and binning)
 void ns_build_pairs(bs_plan_t p) {
-    const int N = (int)p->N;
-    dim3 grid(ceil_div(N, 256)), block(256);
-    dim3 wgrid(ceil_div((int64_t)N * 64, 256));
-    hipLaunchKernelGGL(k_max_ell, dim3(1), dim3(256), 0, p->stream, N,
-                       (const double *)p->d_ell.p, (double *)p->ns_maxell.p);
-    NsArgs a = ns_args(p);
+    const int N = (int)p->N, bs = 256;
+    const int nb3 = p->ns_ncmax * p->ns_ncmax * p->ns_ncmax;
+    int *ncp = (int *)p->ns_nc.p;
+    int *ckey = (int *)p->ns_ckey.p, *ccnt = (int *)p->ns_ccnt.p, *cstart = (int *)p->ns_cstart.p;
+    int *cfill = (int *)p->ns_cfill.p, *cperm = (int *)p->ns_cperm.p;
+    const int *off = (const int *)p->d_off.p, *fil = (const int *)p->d_fil.p;
+    const double *x = (const double *)p->d_x.p, *ell = (const double *)p->d_ell.p;
+    double *red = (double *)p->ns_red.p;
+    const int nred = ceil_div(N, bs) < kNsRedBlocks ? ceil_div(N, bs) : kNsRedBlocks;
+    hipLaunchKernelGGL(k_ns_reach, dim3(nred), dim3(bs), 0, p->stream, N, off, fil, x, ell,
+                       p->prm.ns_eta, red + 1);
+    hipLaunchKernelGGL(k_ns_cells, dim3(1), dim3(bs), 0, p->stream, red + 1, nred, p->prm.L,
+                       p->ns_ncmax, red, ncp);
+    hipLaunchKernelGGL(k_ns_zero, dim3(ceil_div(nb3 + 1, bs)), dim3(bs), 0, p->stream, nb3 + 1,
+                       ccnt, cfill);
+    hipLaunchKernelGGL(k_ns_keys, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, off, fil, x,
+                       p->prm.L, (const int *)ncp, ckey, ccnt);
+    exclusive_scan(p, ccnt, cstart, nb3);
+    hipLaunchKernelGGL(k_ns_scatter, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
+                       (const int *)ckey, (const int *)cstart, cfill, cperm);
+    const int nsort = nb3 < 4096 ? nb3 : 4096;
+    hipLaunchKernelGGL(k_ns_sort, dim3(nsort), dim3(64), 0, p->stream, (const int *)ncp,
+                       (const int *)cstart, cperm, ckey);
+    hipLaunchKernelGGL(k_ns_gather, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
+                       (const int *)cperm, off, fil, x, ell, p->prm.ns_eta, p->prm.L,
+                       (double4 *)p->ns_segA.p, (double4 *)p->ns_segB.p,
+                       (float4 *)p->ns_segM.p);
+    NsArgs a;
+    a.N = N; a.max_per_node = p->ns_max_per_node;
+    a.L = p->prm.L; a.eta = p->prm.ns_eta;
+    a.x = x; a.off = off; a.fil = fil;
+    a.nperm = (const int *)p->nd_perm.p; a.ncp = ncp; a.cstart = cstart;
+    a.segA = (const double4 *)p->ns_segA.p; a.segB = (const double4 *)p->ns_segB.p;
+    a.segM = (const float4 *)p->ns_segM.p;
     int *cnt = (int *)p->ns_cnt.p, *start = (int *)p->ns_start.p;
-    hipLaunchKernelGGL((k_ns_flag<0>), wgrid, block, 0, p->stream, a, cnt, (const int *)nullptr,
-                       (int2 *)nullptr, (int *)p->d_status.p);
+    hipLaunchKernelGGL(k_ns_flag, dim3(ceil_div((int64_t)N * 64, bs)), dim3(bs), 0, p->stream, a,
+                       cnt, (int2 *)p->ns_slots.p, (int *)p->d_status.p);
     exclusive_scan(p, cnt, start, N);
-    hipLaunchKernelGGL((k_ns_flag<1>), wgrid, block, 0, p->stream, a, (int *)nullptr, start,
-                       (int2 *)p->ns_pairs.p, (int *)p->d_status.p);
-    hipLaunchKernelGGL(k_ns_owner, grid, block, 0, p->stream, N, start, (int *)p->ns_pnode.p);
+    const int64_t ns = (int64_t)N * p->ns_max_per_node;
+    hipLaunchKernelGGL(k_ns_compact, dim3(ceil_div(ns, bs)), dim3(bs), 0, p->stream, ns,
+                       p->ns_max_per_node, (const int *)cnt, (const int *)start,
+                       (const int2 *)p->ns_slots.p, (int2 *)p->ns_pairs.p, (int *)p->ns_pnode.p);
 }
 
 void ns_rule(NsRule *R);
@@ -663,13 +820,15 @@ void launch_ns_mlp(bs_plan_t p, double *v) {
     hipLaunchKernelGGL(k_ns_features, dim3(1024), dim3(256), 0, p->stream, total,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
-                       (const double *)p->d_x.p, (const double *)p->d_D.p, p->prm.L,
-                       (float *)p->ns_X.p);
+                       (const double *)p->d_x.p, (const double *)p->d_D.p,
+                       (const double *)p->d_dtau.p, p->prm.L, (float *)p->ns_X.p);
     mlp_forward_device(p->mlp, total, (int64_t)N * p->ns_max_per_node, (const float *)p->ns_X.p,
                        (float *)p->ns_Y.p, p->stream);
     NsBox box;
     for (int b = 0; b < kNsBins; b++) box.err[b] = p->ns_err[b];
     box.tol = p->prm.tol;
+    hipLaunchKernelGGL(k_ns_zero, dim3(1), dim3(64), 0, p->stream, 1, (int *)p->ns_fallback.p,
+                       (int *)p->ns_fallback.p);
     hipLaunchKernelGGL(k_ns_combine, dim3(1024), dim3(256), 0, p->stream, total,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,

@@ -2,12 +2,11 @@
 // operator, and type-2 NUFFT (inverse c2r FFT + interpolation), Sec. 3.3 and
 // App. A.
 //
-// Spread (tile-owned, atomic-free in global memory): one workgroup owns a
-// T^3 tile of the grid, accumulates every point whose w^3 stencil overlaps
-// it into an LDS copy of the tile (LDS atomics), and writes the tile once.
-// The grid is therefore written exactly once (no separate zeroing pass and
-// no global atomics), which is what matters at the low point densities of
-// filament tangles (~0.01-0.03 points per grid cell).
+// Spread (tile-owned, atomic-free): one wavefront owns a T^3 tile of the
+// grid, accumulates every point whose w^3 stencil overlaps it in registers,
+// and writes the tile once.  The grid is therefore written exactly once (no
+// zeroing pass, no atomics), which is what matters at the low point
+// densities of filament tangles (~0.01-0.03 points per grid cell).
 //
 // Spectral operator, per retained mode k = 2 pi m / L with |m_i| <= K, k != 0:
 //   v_hat = i k x G_hat exp(-k^2/(4 alpha^2)) / (k^2 L^3 F(m_x)^2 F(m_y)^2 F(m_z)^2)
@@ -22,146 +21,157 @@
 namespace bs {
 
 // ----------------------------------------------------------------- spread
-// Candidates (points whose stencil base lies in one of the nbv^3 bins that
-// can reach this tile) are staged in LDS in batches of kSpreadBatch by all
-// threads at once.  Each wavefront then takes candidates in turn; its lanes
-// cover the (kx, ky) columns of the stencil (so the 64 lanes of one LDS
-// instruction touch distinct, mostly consecutive words) and loop over kz.
-// Every wavefront accumulates into its own LDS copy of the tile with plain
-// adds (lanes never collide within an instruction), and the copies are summed
-// in wavefront order when the tile is written: no atomics, and the summation
-// order is fixed, so the grid is bitwise reproducible.
-constexpr int kSpreadBatch = 64;
-constexpr int kSpreadWaves = 4;
-
-// Stencil cells k in [0, W) whose local index (d + k) mod n, d = base - t0,
-// falls inside [0, TT): a contiguous range [lo, hi) (empty if hi <= lo).
-template <int W, int TT>
-__device__ __forceinline__ void overlap_range_t(int d, int n, int &lo, int &hi) {
-    if (d < 0) d += n;                 // d in [0, n)
-    if (d < TT) { lo = 0; hi = TT - d < W ? TT - d : W; }
-    else {                              // stencil starts before the tile (wrap)
-        lo = n - d;
-        hi = lo + TT < W ? lo + TT : W;
-    }
-}
-#define overlap_range(d, n, lo, hi) overlap_range_t<W, TT>(d, n, lo, hi)
-
+// One wavefront owns a T^3 tile of the grid.  Lane l owns the columns
+// (lx, ly) = (l % T, (l / T) % T) of the tile over ZL = T^3 / 64 z cells
+// starting at (l / T^2) ZL (T = 8: every lane a full column of 8 cells;
+// T = 4: one cell per lane) and accumulates them in registers.
+//
+// Candidates are the points whose stencil base lies in one of the nbv^3
+// bins that can reach the tile.  They are staged 64 at a time: lane c turns
+// candidate c's 3W kernel values into the tile's frame (T weights per axis,
+// zero where the stencil misses the tile), and the candidates that overlap
+// the tile are compacted into LDS with a ballot, in candidate order.  Every
+// lane then runs through the staged candidates in that order, adding
+// q wx[lx] wy[ly] wz[z] to its cells.  Each grid cell is written exactly once,
+// with no atomics and a fixed summation order (bitwise reproducible), and
+// the LDS holds only the staged candidates.
+//
+// Tiles are spread over the 8 XCDs in contiguous ranges (blocks b, b+8, ...
+// run on one XCD), so neighbouring tiles, which share candidate bins and the
+// cache lines of their grid rows, go through the same L2.
 template <typename R, int W, int TT>
-__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(int n, int NT, int nbv,
-                                                              const int *__restrict__ start,
-                                                              const int4 *__restrict__ base,
-                                                              const R *__restrict__ ker,
-                                                              const R *__restrict__ q,
-                                                              R *__restrict__ grid) {
-    constexpr int T3 = TT * TT * TT;
-    constexpr int CB = kSpreadBatch;
-    // stencil-base bins a tile can be reached from: nb per axis
-    constexpr int NBMAX = 1 + (W - 1 + TT - 1) / TT;
+__global__ __launch_bounds__(64) void k_spread(int n, int NT, int nbv, int per_xcd,
+                                               const int *__restrict__ start,
+                                               const int4 *__restrict__ base,
+                                               const R *__restrict__ ker,
+                                               const R *__restrict__ q,
+                                               R *__restrict__ grid) {
+    constexpr int ZL = TT * TT * TT / 64;
+    constexpr int SW = 3 * TT + 4;   // staged words: T weights per axis, q, pad
+    constexpr int NBMAX = 1 + (W - 1 + TT - 1) / TT;   // bins per axis that reach a tile
     constexpr int NB3 = NBMAX * NBMAX * NBMAX;
-    static_assert(NB3 <= 64 * kSpreadWaves, "bin table must fit one thread per bin");
-    __shared__ R acc[kSpreadWaves][3 * T3];
-    __shared__ R sker[CB * 3 * W];
-    __shared__ R sq[CB * 3];
-    __shared__ int4 sb[CB];
-    __shared__ int bin_s[NB3], bin_o[NB3 + 1];
-    const int tile = blockIdx.x;
+    __shared__ R st[64 * SW];
+    __shared__ int bin_s[NB3], bin_o[NB3];
+    const int ntiles = NT * NT * NT;
+    const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tile >= ntiles) return;
     const int tx = tile % NT, ty = (tile / NT) % NT, tz = tile / (NT * NT);
-    const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
-    for (int i = threadIdx.x; i < kSpreadWaves * 3 * T3; i += blockDim.x) (&acc[0][0])[i] = (R)0;
+    const int t0[3] = {tx * TT, ty * TT, tz * TT};
+    const int lane = threadIdx.x;
+    const int lx = lane % TT, ly = (lane / TT) % TT, lz0 = (lane / (TT * TT)) * ZL;
+    R acc[3][ZL];
+#pragma unroll
+    for (int z = 0; z < ZL; z++) acc[0][z] = acc[1][z] = acc[2][z] = (R)0;
+    // start of each bin and exclusive prefix of the bin sizes, in LDS
+    // (bins taken 64 at a time, prefix by wave shuffles)
     const int nbins = nbv * nbv * nbv;   // nbv <= NBMAX (checked by the launcher)
-    if (threadIdx.x < nbins) {
-        int i = threadIdx.x;
-        int dx = i % nbv, dy = (i / nbv) % nbv, dz = i / (nbv * nbv);
-        int bz = tz - dz; if (bz < 0) bz += NT;
-        int by = ty - dy; if (by < 0) by += NT;
-        int bx = tx - dx; if (bx < 0) bx += NT;
-        int bin = (bz * NT + by) * NT + bx;
-        bin_s[i] = start[bin];
-        bin_o[i + 1] = start[bin + 1] - start[bin];
+    int total = 0;
+    for (int i0 = 0; i0 < nbins; i0 += 64) {
+        const int i = i0 + lane;
+        int bstart = 0, bsize = 0;
+        if (i < nbins) {
+            const int dx = i % nbv, dy = (i / nbv) % nbv, dz = i / (nbv * nbv);
+            int bz = tz - dz; if (bz < 0) bz += NT;
+            int by = ty - dy; if (by < 0) by += NT;
+            int bx = tx - dx; if (bx < 0) bx += NT;
+            const int bin = (bz * NT + by) * NT + bx;
+            bstart = start[bin];
+            bsize = start[bin + 1] - bstart;
+        }
+        int incl = bsize;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (i < nbins) { bin_s[i] = bstart; bin_o[i] = total + incl - bsize; }
+        total += __shfl(incl, 63);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        bin_o[0] = 0;
-        for (int i = 0; i < nbins; i++) bin_o[i + 1] += bin_o[i];
-    }
-    __syncthreads();
-    const int total = bin_o[nbins];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    R *my = acc[wave];
-    for (int c0 = 0; c0 < total; c0 += CB) {
-        const int cn = total - c0 < CB ? total - c0 : CB;
-        for (int i = threadIdx.x; i < cn * (3 * W + 4); i += blockDim.x) {
-            int c = i / (3 * W + 4), k = i % (3 * W + 4);
-            int ci = c0 + c, b = 0;
-            while (bin_o[b + 1] <= ci) b++;
-            int g = bin_s[b] + (ci - bin_o[b]);
-            if (k < 3 * W) sker[c * 3 * W + k] = ker[(size_t)g * 3 * W + k];
-            else if (k < 3 * W + 3) sq[c * 3 + (k - 3 * W)] = q[4 * (size_t)g + (k - 3 * W)];
-            else sb[c] = base[g];
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int c0 = 0; c0 < total; c0 += 64) {
+        const int ci = c0 + lane;
+        // bin of candidate ci: the last bin whose exclusive prefix is <= ci
+        int b = 0;
+        for (int step = 64; step > 0; step >>= 1) {
+            const int tb = b + step;
+            if (tb < nbins && bin_o[tb] <= ci) b = tb;
+        }
+        const int g = bin_s[b] + (ci - bin_o[b]);
+        R wgt[3][TT];
+        bool act = false;
+        if (ci < total) {
+            const int4 bb = base[g];
+            const int bv[3] = {bb.x, bb.y, bb.z};
+            act = true;
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                // stencil index of the tile's first cell along axis a
+                int off = t0[a] - bv[a];
+                if (off < 0) off += n;
+                bool any = false;
+#pragma unroll
+                for (int l = 0; l < TT; l++) {
+                    int k = off + l;
+                    if (k >= n) k -= n;
+                    R wv = (R)0;
+                    if (k < W) { wv = ker[((size_t)g * 3 + a) * W + k]; any = true; }
+                    wgt[a][l] = wv;
+                }
+                act = act && any;
+            }
+        }
+        const unsigned long long m = __ballot(act);
+        if (act) {
+            R *s = st + __popcll(m & below) * SW;
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int l = 0; l < TT; l++) s[a * TT + l] = wgt[a][l];
+            s[3 * TT] = q[4 * (size_t)g];
+            s[3 * TT + 1] = q[4 * (size_t)g + 1];
+            s[3 * TT + 2] = q[4 * (size_t)g + 2];
         }
         __syncthreads();
-        for (int c = wave; c < cn; c += kSpreadWaves) {
-            const int4 b = sb[c];
-            int klo[3], khi[3];
-            overlap_range(b.x - t0x, n, klo[0], khi[0]);
-            overlap_range(b.y - t0y, n, klo[1], khi[1]);
-            overlap_range(b.z - t0z, n, klo[2], khi[2]);
-            if (khi[0] <= klo[0] || khi[1] <= klo[1] || khi[2] <= klo[2]) continue;
-            const int ox = khi[0] - klo[0], oy = khi[1] - klo[1];
-            const R *kp = sker + c * 3 * W;
-            const R qx = sq[3 * c], qy = sq[3 * c + 1], qz = sq[3 * c + 2];
-            // local index of stencil cell k along an axis: (b + k - t0) mod n
-            int lx0 = b.x - t0x; if (lx0 < 0) lx0 += n;
-            int ly0 = b.y - t0y; if (ly0 < 0) ly0 += n;
-            int lz0 = b.z - t0z; if (lz0 < 0) lz0 += n;
-            for (int l = lane; l < ox * oy; l += 64) {
-                const int kx = klo[0] + l % ox, ky = klo[1] + l / ox;
-                int lx = lx0 + kx; if (lx >= n) lx -= n;
-                int ly = ly0 + ky; if (ly >= n) ly -= n;
-                const R cxy = kp[kx] * kp[W + ky];
-                const R cx = qx * cxy, cy = qy * cxy, cz = qz * cxy;
-                R *col = my + ly * TT + lx;
-                for (int kz = klo[2]; kz < khi[2]; kz++) {
-                    int lz = lz0 + kz; if (lz >= n) lz -= n;
-                    const R ph = kp[2 * W + kz];
-                    R *cell = col + lz * TT * TT;
-                    cell[0] += cx * ph;
-                    cell[T3] += cy * ph;
-                    cell[2 * T3] += cz * ph;
-                }
+        const int na = __popcll(m);
+        for (int c = 0; c < na; c++) {
+            const R *s = st + c * SW;
+            const R wxy = s[lx] * s[TT + ly];
+            const R qx = s[3 * TT] * wxy, qy = s[3 * TT + 1] * wxy, qz = s[3 * TT + 2] * wxy;
+#pragma unroll
+            for (int z = 0; z < ZL; z++) {
+                const R wz = s[2 * TT + lz0 + z];
+                acc[0][z] += qx * wz;
+                acc[1][z] += qy * wz;
+                acc[2][z] += qz * wz;
             }
         }
         __syncthreads();
     }
     const size_t n3 = (size_t)n * n * n;
-    for (int i = threadIdx.x; i < T3; i += blockDim.x) {
-        int lx = i % TT, ly = (i / TT) % TT, lz = i / (TT * TT);
-        size_t g = ((size_t)(t0z + lz) * n + (t0y + ly)) * n + (t0x + lx);
-        R s0 = acc[0][i], s1 = acc[0][T3 + i], s2 = acc[0][2 * T3 + i];
 #pragma unroll
-        for (int w2 = 1; w2 < kSpreadWaves; w2++) {
-            s0 += acc[w2][i]; s1 += acc[w2][T3 + i]; s2 += acc[w2][2 * T3 + i];
-        }
-        grid[g] = s0;
-        grid[n3 + g] = s1;
-        grid[2 * n3 + g] = s2;
+    for (int z = 0; z < ZL; z++) {
+        const size_t gi = ((size_t)(t0[2] + lz0 + z) * n + (t0[1] + ly)) * n + (t0[0] + lx);
+        grid[gi] = acc[0][z];
+        grid[n3 + gi] = acc[1][z];
+        grid[2 * n3 + gi] = acc[2][z];
     }
 }
 
 template <typename R, int TT>
 static void spread_tt(bs_plan_t p) {
     const int w = p->prm.w;
-    int nb = 1 + ceil_div(w - 1, TT);   // equals the kernel's NBMAX for W = w
+    int nb = 1 + ceil_div(w - 1, TT);
     int nbv = nb < p->NT ? nb : p->NT;
-    if (nbv * nbv * nbv > 256) return;  // unreachable for w <= 16, TT >= 4
-    dim3 grid(p->NT * p->NT * p->NT), block(64 * kSpreadWaves);
+    if (nbv > nb) return;   // the kernel's bin table holds nb^3 bins
+    const int ntiles = p->NT * p->NT * p->NT;
+    const int per = ceil_div(ntiles, 8);
+    dim3 grid(8 * per), block(64);
     const int *start = (const int *)p->sp_start.p;
     const int4 *base = (const int4 *)p->sp_base.p;
     const R *ker = (const R *)p->sp_ker.p, *q = (const R *)p->sp_q.p;
     R *g = (R *)p->grid.p;
 #define SPREAD_CASE(WW) \
-    case WW: hipLaunchKernelGGL((k_spread<R, WW, TT>), grid, block, 0, p->stream, p->n, p->NT, nbv, start, base, ker, q, g); break;
+    case WW: hipLaunchKernelGGL((k_spread<R, WW, TT>), grid, block, 0, p->stream, p->n, p->NT, nbv, per, start, base, ker, q, g); break;
     switch (w) {
         SPREAD_CASE(4) SPREAD_CASE(5) SPREAD_CASE(6) SPREAD_CASE(7) SPREAD_CASE(8)
         SPREAD_CASE(9) SPREAD_CASE(10) SPREAD_CASE(11) SPREAD_CASE(12) SPREAD_CASE(13)
@@ -293,48 +303,73 @@ void launch_modes(bs_plan_t p, double *out) {
 }
 
 // ---------------------------------------------------------- interpolation
-// G lanes per node; lane l sums the x-rows (ky, kz) = (r % W, r / W) for
-// r = l, l + G, ...; partial sums combined by a fixed xor-shuffle tree.
+// G = 64 lanes per node.  Lane j < 3W evaluates the kernel value of stencil
+// cell j % W along axis j / W once; the others read them by shuffles.  Lane
+// l owns the stencil columns (kx, ky) = (r % W, r / W) for r = l, l + G, ...
+// and runs along z, so the lanes of one load instruction read W rows of W
+// consecutive grid values (a few cache lines, not one line per lane).  The
+// partial sums are combined by a fixed xor-shuffle tree.  Nodes come in
+// pair-cell order, and consecutive blocks of them stay on one XCD (blocks
+// b, b+8, ... run on one XCD), so the grid rows that neighbouring nodes share
+// are fetched into one L2.
 template <typename R, int W, int G>
-__global__ __launch_bounds__(256) void k_interp(int N, const int *__restrict__ perm,
+__global__ __launch_bounds__(256) void k_interp(int N, int per_xcd, const int *__restrict__ perm,
                                                 const double *__restrict__ x, double L,
                                                 double inv_h, int n, double zeta, double inv_den,
                                                 const R *__restrict__ grid,
                                                 double *__restrict__ out) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    static_assert(3 * W <= G, "one lane per kernel value");
+    constexpr int NR = (W * W + G - 1) / G;
+    const int blk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int gid = blk * blockDim.x + threadIdx.x;
     const int t = gid / G, lane = gid % G;
-    if (t >= N) return;
+    if (t >= N) return;   // whole wavefronts exit together
     const int o = perm[t];
     const double half = 0.5 * W;
-    double fx, fy, fz;
-    int bx = stencil_base(wrap_box(x[3 * o], L), inv_h, W, n, &fx);
-    int by = stencil_base(wrap_box(x[3 * o + 1], L), inv_h, W, n, &fy);
-    int bz = stencil_base(wrap_box(x[3 * o + 2], L), inv_h, W, n, &fz);
-    int ix[W];
-    R px[W];
+    double f[3];
+    int bb[3];
+    for (int a = 0; a < 3; a++) bb[a] = stencil_base(wrap_box(x[3 * o + a], L), inv_h, W, n, &f[a]);
+    R phi = (R)0;
+    if (lane < 3 * W) {
+        const int a = lane / W, k = lane % W;
+        phi = (R)kb_phi((k - f[a]) / half, zeta, inv_den);
+    }
+    R pz[W];
+    int iz[W];
 #pragma unroll
     for (int k = 0; k < W; k++) {
-        int c = bx + k;
-        ix[k] = c >= n ? c - n : c;
-        px[k] = (R)kb_phi((k - fx) / half, zeta, inv_den);
+        pz[k] = __shfl(phi, 2 * W + k, G);
+        const int c = bb[2] + k;
+        iz[k] = c >= n ? c - n : c;
     }
-    const size_t n3 = (size_t)n * n * n;
-    R a0 = 0, a1 = 0, a2 = 0;
-    for (int r = lane; r < W * W; r += G) {
-        int ky = r % W, kz = r / W;
-        int cy = by + ky; cy = cy >= n ? cy - n : cy;
-        int cz = bz + kz; cz = cz >= n ? cz - n : cz;
-        R wyz = (R)(kb_phi((ky - fy) / half, zeta, inv_den) * kb_phi((kz - fz) / half, zeta, inv_den));
-        const R *row = grid + ((size_t)cz * n + cy) * n;
-        R s0 = 0, s1 = 0, s2 = 0;
+    R wxy[NR];
+    size_t col[NR];
 #pragma unroll
-        for (int kx = 0; kx < W; kx++) {
-            int c = ix[kx];
-            s0 += px[kx] * row[c];
-            s1 += px[kx] * row[n3 + c];
-            s2 += px[kx] * row[2 * n3 + c];
+    for (int i = 0; i < NR; i++) {
+        const int r = lane + i * G, rc = r < W * W ? r : 0;
+        const int kx = rc % W, ky = rc / W;
+        const R wx = __shfl(phi, kx, G), wy = __shfl(phi, W + ky, G);
+        wxy[i] = r < W * W ? wx * wy : (R)0;
+        int cx = bb[0] + kx; cx = cx >= n ? cx - n : cx;
+        int cy = bb[1] + ky; cy = cy >= n ? cy - n : cy;
+        col[i] = (size_t)cy * n + cx;
+    }
+    const size_t n2 = (size_t)n * n, n3 = n2 * n;
+    R a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+    for (int i = 0; i < NR; i++) {
+        if (lane + i * G < W * W) {
+            const R *g = grid + col[i];
+            R s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+            for (int kz = 0; kz < W; kz++) {
+                const size_t c = (size_t)iz[kz] * n2;
+                s0 += pz[kz] * g[c];
+                s1 += pz[kz] * g[n3 + c];
+                s2 += pz[kz] * g[2 * n3 + c];
+            }
+            a0 += wxy[i] * s0; a1 += wxy[i] * s1; a2 += wxy[i] * s2;
         }
-        a0 += wyz * s0; a1 += wyz * s1; a2 += wyz * s2;
     }
 #pragma unroll
     for (int m = G / 2; m > 0; m >>= 1) {
@@ -354,14 +389,15 @@ constexpr int kInterpLanes = 64;
 template <typename R>
 static void interp_r(bs_plan_t p, double *out) {
     const int N = (int)p->N;
-    dim3 grid(ceil_div((int64_t)N * kInterpLanes, 256)), block(256);
+    const int nblk = ceil_div((int64_t)N * kInterpLanes, 256), per = ceil_div(nblk, 8);
+    dim3 grid(8 * per), block(256);
     const double L = p->prm.L, inv_h = p->n / L, zeta = p->prm.zeta;
     const double inv_den = 1.0 / (-expm1(-2.0 * zeta));
     const int *perm = (const int *)p->nd_perm.p;
     const double *x = (const double *)p->d_x.p;
     const R *g = (const R *)p->grid.p;
 #define INTERP_CASE(WW) \
-    case WW: hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes>), grid, block, 0, p->stream, N, perm, x, L, inv_h, p->n, zeta, inv_den, g, out); break;
+    case WW: hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes>), grid, block, 0, p->stream, N, per, perm, x, L, inv_h, p->n, zeta, inv_den, g, out); break;
     switch (p->prm.w) {
         INTERP_CASE(4) INTERP_CASE(5) INTERP_CASE(6) INTERP_CASE(7) INTERP_CASE(8)
         INTERP_CASE(9) INTERP_CASE(10) INTERP_CASE(11) INTERP_CASE(12) INTERP_CASE(13)

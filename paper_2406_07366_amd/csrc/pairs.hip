@@ -2,9 +2,10 @@
 // eq:streamfunction_shortrange) as quadrature sums over cell lists, and the
 // energy reduction (eq:kinetic_energy_streamfunction).
 //
-// A group of lanes per target node, nodes processed in cell order so that
-// consecutive groups read the same few cells.  For each quadrature point of the 27
-// surrounding cells (or of every cell when fewer than 3 fit along an axis):
+// A wavefront per target node, nodes processed in cell order so that
+// consecutive wavefronts read the same few cells.  For each quadrature point
+// of the 27 surrounding cells (or of every cell when fewer than 3 fit along
+// an axis):
 // r = s_q - s_i by minimum image (formed in float64), skip the 2Q points of
 // the two segments adjacent to the node, keep r < r_c, and add
 //   v:   g_sr(r) (r x q) / r^3,  g_sr = erfc(alpha r) + (2 alpha r/sqrt(pi)) e^{-alpha^2 r^2}
@@ -15,9 +16,12 @@
 
 namespace bs {
 
-// G lanes cooperate on one target node: each lane takes every G-th candidate
-// of each cell, then the partial sums are combined by a fixed xor-shuffle
-// tree (deterministic order).
+// One wavefront (G = 64 lanes) per target node.  Lanes 0..26 hold one of
+// the 27 cells around the target; the cells' contents are enumerated as one
+// flattened range, 64 candidates per step (every lane busy, independent
+// loads), each lane finding its cell by binary search over the wavefront's
+// prefix sums.  The partial sums are combined by a fixed xor-shuffle tree
+// (deterministic order).
 template <typename R, bool PSI, int G>
 __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double rc, double alpha,
                                                const int *__restrict__ nperm,
@@ -29,61 +33,76 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
                                                const R *__restrict__ schg,
                                                const int *__restrict__ sseg,
                                                double *__restrict__ out) {
+    static_assert(G == 64, "one wavefront per target");
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = gid / G, lane = gid % G;
-    if (t >= N) return;   // whole groups exit together
+    if (t >= N) return;   // whole wavefronts exit together
     const int o = nperm[t];
     const int ip = prev_node_d(off, fil, o);
     const double xi0 = x[3 * o], xi1 = x[3 * o + 1], xi2 = x[3 * o + 2];
     const double invL = 1.0 / L;
-    int c[3];
-    {
-        double ws[3] = {wrap_box(xi0, L), wrap_box(xi1, L), wrap_box(xi2, L)};
-        for (int q = 0; q < 3; q++) {
-            int v = (int)(ws[q] * invL * nc);
-            c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+    const int ncell = nc >= 3 ? 27 : 1;
+    int cs = 0, cn = 0;
+    if (lane < ncell) {
+        int cidx = 0;
+        if (nc >= 3) {
+            const double ws[3] = {wrap_box(xi0, L), wrap_box(xi1, L), wrap_box(xi2, L)};
+            const int dd[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+            int c[3];
+            for (int q = 0; q < 3; q++) {
+                int v = (int)(ws[q] * invL * nc);
+                v = (v < 0 ? 0 : (v >= nc ? nc - 1 : v)) + dd[q];
+                c[q] = v < 0 ? v + nc : (v >= nc ? v - nc : v);
+            }
+            cidx = (c[2] * nc + c[1]) * nc + c[0];
         }
+        cs = cstart[cidx];
+        cn = cstart[cidx + 1] - cs;
     }
+    int incl = cn;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    const int total = __shfl(incl, 63);
+    const int excl = incl - cn;
     const R rc2 = (R)(rc * rc), a = (R)alpha;
     const R two_over_sqrtpi = (R)1.12837916709551257389615890312154517;
     R acc0 = 0, acc1 = 0, acc2 = 0;
-    const int span = nc >= 3 ? 1 : 0;
-    for (int dz = -span; dz <= span; dz++) {
-        int cz = c[2] + dz; cz = cz < 0 ? cz + nc : (cz >= nc ? cz - nc : cz);
-        for (int dy = -span; dy <= span; dy++) {
-            int cy = c[1] + dy; cy = cy < 0 ? cy + nc : (cy >= nc ? cy - nc : cy);
-            for (int dx = -span; dx <= span; dx++) {
-                int cx = c[0] + dx; cx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
-                int cell = (cz * nc + cy) * nc + cx;
-                int s = cstart[cell], e = cstart[cell + 1];
-                for (int p = s + lane; p < e; p += G) {
-                    int sg = sseg[p];
-                    if (sg == o || sg == ip) continue;
-                    double4 sp = spos[p];
-                    double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
-                    rx -= L * rint(rx * invL);
-                    ry -= L * rint(ry * invL);
-                    rz -= L * rint(rz * invL);
-                    R fx = (R)rx, fy = (R)ry, fz = (R)rz;
-                    R r2 = fx * fx + fy * fy + fz * fz;
-                    if (!(r2 < rc2) || r2 == (R)0) continue;
-                    R rr = sqrt(r2);
-                    R ar = a * rr;
-                    R ec = erfc(ar);
-                    const R *qq = schg + 4 * (size_t)p;
-                    R q0 = qq[0], q1 = qq[1], q2 = qq[2];
-                    if (PSI) {
-                        R f = ec / rr;
-                        acc0 += f * q0; acc1 += f * q1; acc2 += f * q2;
-                    } else {
-                        R g = ec + two_over_sqrtpi * ar * exp(-ar * ar);
-                        R f = g / (r2 * rr);
-                        acc0 += f * (fy * q2 - fz * q1);
-                        acc1 += f * (fz * q0 - fx * q2);
-                        acc2 += f * (fx * q1 - fy * q0);
-                    }
-                }
-            }
+    for (int q0 = 0; q0 < total; q0 += 64) {
+        const int q = q0 + lane;
+        int c = 0;
+        for (int step = 16; step > 0; step >>= 1) {
+            const int tc = c + step;
+            const int pv = __shfl(excl, tc < ncell ? tc : ncell - 1);
+            if (tc < ncell && pv <= q) c = tc;
+        }
+        const int p = __shfl(cs, c) + (q - __shfl(excl, c));
+        if (q >= total) continue;
+        const int sg = sseg[p];
+        if (sg == o || sg == ip) continue;
+        const double4 sp = spos[p];
+        double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
+        rx -= L * rint(rx * invL);
+        ry -= L * rint(ry * invL);
+        rz -= L * rint(rz * invL);
+        const R fx = (R)rx, fy = (R)ry, fz = (R)rz;
+        const R r2 = fx * fx + fy * fy + fz * fz;
+        if (!(r2 < rc2) || r2 == (R)0) continue;
+        const R rr = sqrt(r2);
+        const R ar = a * rr;
+        const R ec = erfc(ar);
+        const R *qq = schg + 4 * (size_t)p;
+        const R q0v = qq[0], q1v = qq[1], q2v = qq[2];
+        if (PSI) {
+            const R f = ec / rr;
+            acc0 += f * q0v; acc1 += f * q1v; acc2 += f * q2v;
+        } else {
+            const R g = ec + two_over_sqrtpi * ar * exp(-ar * ar);
+            const R f = g / (r2 * rr);
+            acc0 += f * (fy * q2v - fz * q1v);
+            acc1 += f * (fz * q0v - fx * q2v);
+            acc2 += f * (fx * q1v - fy * q0v);
         }
     }
 #pragma unroll

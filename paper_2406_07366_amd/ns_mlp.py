@@ -29,14 +29,14 @@ def make_dataset(n, seed):
 
 
 def error_table(mlp, X, T, A, nbins=None):
-    """Max relative error of the learned raw segment integral per
-    log10(d/h) bin: |scale (y_pred - z)| / |I_seg|, z the target."""
+    """Max error of the learned raw segment integral per log10(d/h) bin,
+    relative to the tangent segment's absolute integral S:
+    |m (y_pred - z)| / S, z the target and m its multiplier."""
     import torch
     lo, hi, nb = B.ns_error_bins()
     nbins = nbins or nb
     Y = mlp.forward(X).double()
-    scale = A[:, 4:5]
-    err = ((Y - T.double()) * scale).norm(dim=1) / A[:, 1:4].norm(dim=1)
+    err = ((Y - T.double()) * A[:, 4:5]).norm(dim=1) / A[:, 5]
     t = (torch.log10(A[:, 0]) - math.log10(lo)) / (math.log10(hi) - math.log10(lo))
     b = (t * nbins).long().clamp(0, nbins - 1)
     tab = np.zeros(nbins, dtype=np.float32)
@@ -85,5 +85,6 @@ def train(n_train=1_000_000, n_val=100_000, epochs=60, batch=8192, lr=3e-3, seed
     if log:
         log(f"[ns-mlp] trained {n_train} samples x {epochs} epochs in {ttrain:.1f} s; "
             f"val loss {info['val_loss']:.3e}")
-        log("[ns-mlp] max rel err per d/h bin: " + " ".join(f"{v:.1e}" for v in tab))
+        log("[ns-mlp] max err / S per d/h bin: " + " ".join(f"{v:.1e}" for v in tab))
+        log("[ns-mlp] median err / S per d/h bin: " + " ".join(f"{v:.1e}" for v in med))
     return mlp, tab, info

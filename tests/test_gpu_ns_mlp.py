@@ -29,8 +29,9 @@ def rel_l2(a, b):
 
 def test_ns_samples_match_scipy_quadrature(B):
     """Each sample's exact integral (aux) is the segment integral of the cubic
-    the features describe; checked with scipy.quad, and the target against the
-    oracle's straight-chord closed form."""
+    the features describe; checked with scipy.quad, and the target, its
+    multiplier and error scale against the oracle's straight-chord closed form
+    and quadrature along the tangent segment."""
     import torch
     print("\n[case] ns samples n=24", flush=True)
     rng = np.random.default_rng(11)
@@ -60,10 +61,15 @@ def test_ns_samples_match_scipy_quadrature(B):
         d = np.linalg.norm(P - x)
         a_, b_ = np.linalg.norm(P - s(0)), np.linalg.norm(s(1) - P)
         tang = O.chord_integral(P - a_ * tan, P + b_ * tan, x) * 4 * math.pi
-        scale = np.linalg.norm(tang)
+        mult = 1 + math.log1p(1 / d)
+        # absolute integral of the tangent segment, by quadrature
+        Sabs = scipy.integrate.quad(
+            lambda l: 1.0 / np.linalg.norm(P + (l - a_) * tan - x) ** 2, 0, a_ + b_,
+            points=[a_], epsabs=0, epsrel=1e-12, limit=500)[0]
         np.testing.assert_allclose(A[i, 0], d, rtol=1e-3)
-        np.testing.assert_allclose(A[i, 4], scale, rtol=1e-3)
-        np.testing.assert_allclose(T[i] * scale, ref - tang, rtol=2e-2,
+        np.testing.assert_allclose(A[i, 4], mult, rtol=1e-3)
+        np.testing.assert_allclose(A[i, 5], Sabs, rtol=2e-3)
+        np.testing.assert_allclose(T[i] * mult, ref - tang, rtol=2e-2,
                                    atol=2e-3 * np.abs(ref).max())
 
 
@@ -72,8 +78,8 @@ def test_learned_correction_gain(B):
     integrals, for the plain Q-point rule, the network alone, the network with
     its error-table fallback, and the adaptive integrator."""
     from paper_2406_07366_amd import ns_mlp
-    print("\n[case] learned NS: train 2e5 samples, ring pairs N=6800", flush=True)
-    mlp, tab, info = ns_mlp.train(n_train=200_000, n_val=50_000, epochs=30, batch=4096)
+    print("\n[case] learned NS: train 5e5 samples, ring pairs N=6800", flush=True)
+    mlp, tab, info = ns_mlp.train(n_train=500_000, n_val=100_000, epochs=40, batch=4096)
     fs = W.ringpairs(npairs=150, nbg=20, seed=77)
     fs.grid_n = 64
     ref, _ = O.Oracle(fs).reference(psi=False, ns_eta=1.0)

@@ -1,0 +1,69 @@
+"""CPU model of the near-singular pair search's cell bookkeeping (no GPU).
+
+Segments are binned by chord midpoint into nc^3 cells with
+nc = floor(L / max_j reach_j), reach_j = eta*ell_j + |B_j - A_j|/2 (nc < 3:
+one cell).  The flag pass of a target scans the 27 cells around the target's
+cell.  This test re-derives, on random tangles with long and short segments
+and targets near the box faces, that every pair a brute-force search flags
+(chord distance below eta*ell_j, minimum image) has its segment inside that
+window, and that the 27 cells are distinct whenever nc >= 3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+
+def wrap(v, L):
+    return v - L * np.floor(v / L)
+
+
+def cell_of(v, L, nc):
+    return np.clip((wrap(v, L) / L * nc).astype(int), 0, nc - 1)
+
+
+def chord_dist(A, B, x, L):
+    m = 0.5 * (A + B)
+    xs = x - L * np.rint((x - m) / L)
+    e = B - A
+    t = np.clip(((xs - A) * e).sum(-1) / (e * e).sum(-1), 0, 1)
+    return np.linalg.norm(xs - A - t[..., None] * e, axis=-1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_flagged_segments_lie_in_the_27_cells(seed):
+    rng = np.random.default_rng(seed)
+    L = 2 * math.pi
+    eta = 1.0
+    nseg = 400
+    A = rng.uniform(-L, 2 * L, (nseg, 3))            # unwrapped end points
+    ln = np.exp(rng.uniform(np.log(0.01), np.log(0.6), nseg))
+    d = rng.normal(size=(nseg, 3))
+    B = A + ln[:, None] * d / np.linalg.norm(d, axis=1)[:, None]
+    ell = ln * rng.uniform(1.0, 1.2, nseg)           # arc length >= chord
+    reach = eta * ell + 0.5 * np.linalg.norm(B - A, axis=1)
+    nc = int(math.floor(L / (reach.max() * (1 + 1e-9))))
+    nc = 1 if nc < 3 else nc
+    mcell = cell_of(0.5 * (A + B), L, nc)
+    # targets: near the segments (the interesting case) and near box faces
+    x = np.concatenate([A + rng.normal(scale=0.05, size=A.shape),
+                        rng.choice([0.0, L - 1e-12], size=(100, 3)) + rng.normal(scale=1e-3, size=(100, 3))])
+    for xi in x:
+        dist = chord_dist(A, B, xi[None], L)
+        flagged = np.nonzero(dist < eta * ell)[0]
+        c0 = cell_of(xi, L, nc)
+        if nc >= 3:
+            window = {tuple((c0 + np.array([dx, dy, dz])) % nc)
+                      for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)}
+            assert len(window) == 27
+            for j in flagged:
+                assert tuple(mcell[j]) in window, (xi, j)
+        # single cell: every segment is scanned
+
+
+def test_cell_count_matches_the_reach_bound():
+    L = 2 * math.pi
+    for r in (0.1, 0.3, 1.0, 2.0, 3.0):
+        nc = int(math.floor(L / (r * (1 + 1e-9))))
+        nc = 1 if nc < 3 else nc
+        assert nc == 1 or L / nc >= r

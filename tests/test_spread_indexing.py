@@ -63,27 +63,37 @@ def test_tiles_cover_each_stencil_cell_once(n, w):
         assert all(v == 1 for v in hits.values()), (n, w, u, hits)
 
 
-def overlap_range(d, n, W, TT):
-    """The kernel's contiguous overlap [lo, hi) of a stencil with a tile."""
-    if d < 0:
-        d += n
-    if d < TT:
-        return 0, min(TT - d, W)
-    lo = n - d
-    return lo, min(lo + TT, W)
+def tile_weights_index(b, t0, n, W, TT):
+    """The kernel's per-axis mapping: tile cell l takes stencil value k =
+    (t0 + l - b) mod n when k < W, else weight 0."""
+    out = []
+    for l in range(TT):
+        k = (t0 + l - b) % n
+        out.append(k if k < W else None)
+    return out
 
 
 @pytest.mark.parametrize("n", [16, 20, 32, 36, 64])
-def test_overlap_range_is_the_set_of_cells_in_the_tile(n):
+def test_tile_frame_weights_cover_the_stencil_once(n):
     T = tile_edge(n)
+    NT = n // T
     for W in range(4, 17):
         if n < W + T:
             continue
+        nb = 1 + -(-(W - 1) // T)
+        nbv = min(nb, NT)
         for b in range(n):
-            for t0 in range(0, n, T):
-                lo, hi = overlap_range(b - t0, n, W, T)
-                valid = [k for k in range(W) if (b + k - t0) % n < T]
-                assert valid == list(range(lo, max(lo, hi)))
+            covered = {}
+            for t in range(NT):
+                if (b // T) not in [(t - d) % NT for d in range(nbv)]:
+                    continue
+                t0 = t * T
+                for l, k in enumerate(tile_weights_index(b, t0, n, W, T)):
+                    if k is not None:
+                        cell = t0 + l
+                        assert (b + k) % n == cell
+                        covered[k] = covered.get(k, 0) + 1
+            assert sorted(covered) == list(range(W)) and all(v == 1 for v in covered.values())
 
 
 def test_plan_rejects_grids_too_small_for_the_tiles():
