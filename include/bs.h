@@ -69,8 +69,17 @@ extern "C" {
 /* near-singular treatment of (node, segment) pairs closer than
  * ns_eta * segment length (not part of the paper; see bs_velocity) */
 #define BS_NS_OFF       0
-#define BS_NS_ADAPTIVE  1  /* adaptive Gauss-Kronrod on the spline segment    */
+#define BS_NS_ADAPTIVE  1  /* graded Gauss-Legendre panels on the spline segment */
 #define BS_NS_MLP       2  /* learned correction with adaptive fallback       */
+
+/* 3-D transforms of the long-range step */
+#define BS_FFT_AUTO     0  /* the faster of the two below for the grid (hipFFT) */
+#define BS_FFT_LIBRARY  1  /* hipFFT: full r2c / c2r transforms and a separate
+                              spectral-operator pass                           */
+#define BS_FFT_PRUNED   2  /* grid_n a power of two (else BS_EINVAL): transforms
+                              that form only the retained modes |m_i| <= K,
+                              with the spectral operator fused into the z
+                              transform                                        */
 
 typedef struct bs_plan_s *bs_plan_t;
 
@@ -107,6 +116,7 @@ typedef struct {
     const void *mlp_weights; /* host pointer to the packed float32 MLP
                                 parameters (see bs_mlp_nparams); needed for
                                 BS_NS_MLP; copied by bs_plan                   */
+    int    fft_mode;     /* BS_FFT_AUTO, BS_FFT_LIBRARY or BS_FFT_PRUNED       */
     /* resolved values, written by bs_resolve_params / bs_get_params */
     int    K;            /* retained modes |m_i| <= K per axis                 */
     int    ncell;        /* cells per axis of the short-range cell list        */
@@ -146,7 +156,9 @@ int bs_set_filaments(bs_plan_t plan, int64_t nfil, const int64_t *offsets,
  * BS_NS_OFF, the near-singular correction: for every non-adjacent segment
  * whose chord lies closer than ns_eta * (segment length) to the node, the
  * Q-point sum of that segment is replaced by its exact integral of the full
- * Biot-Savart kernel.  BS_ESTATE if no filaments were set. */
+ * Biot-Savart kernel.  At most 64 such segments per node are kept: a node
+ * with more is reported by bs_status (BS_EINVAL).  BS_ESTATE if no
+ * filaments were set. */
 int bs_velocity(bs_plan_t plan, double *v_out);
 
 /* Velocity split into its terms, each a DEVICE float64 [N][3] array or

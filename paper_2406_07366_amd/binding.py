@@ -20,6 +20,7 @@ BS_OK, BS_EINVAL, BS_EMINIMG, BS_ETOL, BS_EKB, BS_ENOMEM, BS_EDEVICE, BS_ESTATE 
     0, -1, -2, -3, -4, -5, -6, -7
 BS_FP64, BS_FP32_MIXED = 0, 1
 BS_NS_OFF, BS_NS_ADAPTIVE, BS_NS_MLP = 0, 1, 2
+BS_FFT_AUTO, BS_FFT_LIBRARY, BS_FFT_PRUNED = 0, 1, 2
 
 _CODES = {0: "BS_OK", -1: "BS_EINVAL", -2: "BS_EMINIMG", -3: "BS_ETOL", -4: "BS_EKB",
           -5: "BS_ENOMEM", -6: "BS_EDEVICE", -7: "BS_ESTATE"}
@@ -43,7 +44,8 @@ class BsParams(C.Structure):
                 ("rcut", C.c_double), ("grid_n", C.c_int), ("sigma", C.c_double),
                 ("w", C.c_int), ("Q", C.c_int), ("spline_order", C.c_int),
                 ("precision", C.c_int), ("ns_mode", C.c_int), ("ns_eta", C.c_double),
-                ("mlp_weights", C.c_void_p), ("K", C.c_int), ("ncell", C.c_int),
+                ("mlp_weights", C.c_void_p), ("fft_mode", C.c_int), ("K", C.c_int),
+                ("ncell", C.c_int),
                 ("zeta", C.c_double)]
 
     def as_dict(self):
@@ -112,7 +114,8 @@ def _check(code, plan=None):
 
 
 def make_params(L, a, tol, grid_n, delta=0.25, beta=0.0, alpha=0.0, rcut=0.0, sigma=0.0,
-                w=0, Q=0, precision=BS_FP64, ns_mode=BS_NS_OFF, ns_eta=0.0) -> BsParams:
+                w=0, Q=0, precision=BS_FP64, ns_mode=BS_NS_OFF, ns_eta=0.0,
+                fft_mode=0) -> BsParams:
     p = BsParams()
     p.L, p.a, p.delta, p.tol = L, a, delta, tol
     p.beta, p.alpha, p.rcut = beta, alpha, rcut
@@ -120,6 +123,7 @@ def make_params(L, a, tol, grid_n, delta=0.25, beta=0.0, alpha=0.0, rcut=0.0, si
     p.spline_order = 4
     p.precision, p.ns_mode, p.ns_eta = precision, ns_mode, ns_eta
     p.mlp_weights = None
+    p.fft_mode = fft_mode
     return p
 
 

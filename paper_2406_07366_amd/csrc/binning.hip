@@ -113,41 +113,45 @@ __global__ void k_zero_bins(SortSet S) {
         if (i <= S.nbins[a]) { S.cnt[a][i] = 0; S.fill[a][i] = 0; }
 }
 
+// keys of the three sets; counts by wavefront-aggregated atomics (items
+// that are neighbours along a filament mostly share a tile or cell)
 __global__ void k_keys_all(SortSet S, const double *__restrict__ qpos,
                            const double *__restrict__ x, double L, double inv_h, int w, int n,
                            int T, int NT, int nc) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int Mq = S.nitems[0];
-    if (i < Mq) {
+    const bool isq = i < Mq, isn = !isq && i < Mq + S.nitems[2];
+    int k0 = 0, k1 = 0, k2 = 0;
+    if (isq) {
         double f;
         double w0 = wrap_box(qpos[3 * i], L), w1 = wrap_box(qpos[3 * i + 1], L),
                w2 = wrap_box(qpos[3 * i + 2], L);
         int bx = stencil_base(w0, inv_h, w, n, &f);
         int by = stencil_base(w1, inv_h, w, n, &f);
         int bz = stencil_base(w2, inv_h, w, n, &f);
-        int k = ((bz / T) * NT + by / T) * NT + bx / T;
-        S.key[0][i] = k;
-        atomicAdd(&S.cnt[0][k], 1);
+        k0 = ((bz / T) * NT + by / T) * NT + bx / T;
+        S.key[0][i] = k0;
         double ws[3] = {w0, w1, w2};
         int c[3];
         for (int q = 0; q < 3; q++) {
             int v = (int)(ws[q] / L * nc);
             c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
         }
-        k = (c[2] * nc + c[1]) * nc + c[0];
-        S.key[1][i] = k;
-        atomicAdd(&S.cnt[1][k], 1);
-    } else if (i < Mq + S.nitems[2]) {
+        k1 = (c[2] * nc + c[1]) * nc + c[0];
+        S.key[1][i] = k1;
+    } else if (isn) {
         int j = i - Mq;
         int c[3];
         for (int q = 0; q < 3; q++) {
             int v = (int)(wrap_box(x[3 * j + q], L) / L * nc);
             c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
         }
-        int k = (c[2] * nc + c[1]) * nc + c[0];
-        S.key[2][j] = k;
-        atomicAdd(&S.cnt[2][k], 1);
+        k2 = (c[2] * nc + c[1]) * nc + c[0];
+        S.key[2][j] = k2;
     }
+    wave_add<false>(S.cnt[0], k0, isq);
+    wave_add<false>(S.cnt[1], k1, isq);
+    wave_add<false>(S.cnt[2], k2, isn);
 }
 
 // one workgroup per array: exclusive scan of cnt into start (start[n] = total)
@@ -178,9 +182,14 @@ __global__ void k_scatter_all(SortSet S) {
     int a = 0;
     if (i >= S.nitems[0]) { i -= S.nitems[0]; a = 1; }
     if (a == 1 && i >= S.nitems[1]) { i -= S.nitems[1]; a = 2; }
-    if (a == 2 && i >= S.nitems[2]) return;
-    int k = S.key[a][i];
-    S.perm[a][S.start[a][k] + atomicAdd(&S.fill[a][k], 1)] = i;
+    const bool valid = !(a == 2 && i >= S.nitems[2]);
+    const int k = valid ? S.key[a][i] : 0;
+    int slot = 0;
+    for (int s = 0; s < 3; s++) {
+        const int r = wave_add<true>(S.fill[s], k, valid && a == s);
+        if (a == s) slot = r;
+    }
+    if (valid) S.perm[a][S.start[a][k] + slot] = i;
 }
 
 __global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
@@ -193,7 +202,9 @@ __global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
     rank_sort_bin<kSortLds>(S.perm[a], S.key[a], s, n, v);
 }
 
-// sorted copies for the spread (by tile) and the pairs (by cell), one pass
+// sorted copies for the spread (by tile) and the pairs (by cell), one pass;
+// thread (p, d) handles axis d of sorted entry p (its stencil base and w
+// kernel values, and component d of the charges and pair position)
 template <typename R>
 __global__ void k_gather_all(int M, int w, int Q, const int *__restrict__ sperm,
                              const int *__restrict__ pperm, const double *__restrict__ pos,
@@ -201,26 +212,29 @@ __global__ void k_gather_all(int M, int w, int Q, const int *__restrict__ sperm,
                              double zeta, double inv_den, int4 *__restrict__ base,
                              R *__restrict__ ker, R *__restrict__ q, double4 *__restrict__ spos,
                              R *__restrict__ schg, int *__restrict__ sseg) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * M) return;
+    const int p = t / 3, d = t - 3 * p;
     int o = sperm[p];
-    int b[3];
-    double half = 0.5 * w;
-    for (int d = 0; d < 3; d++) {
-        double f;
-        b[d] = stencil_base(wrap_box(pos[3 * o + d], L), inv_h, w, n, &f);
-        for (int k = 0; k < w; k++)
-            ker[((size_t)p * 3 + d) * w + k] = (R)kb_phi((k - f) / half, zeta, inv_den);
-    }
-    base[p] = make_int4(b[0], b[1], b[2], 0);
-    for (int c = 0; c < 3; c++) q[4 * (size_t)p + c] = (R)chg[3 * o + c];
-    q[4 * (size_t)p + 3] = (R)0;
+    double f;
+    const int b = stencil_base(wrap_box(pos[3 * o + d], L), inv_h, w, n, &f);
+    const double half = 0.5 * w;
+    for (int k = 0; k < w; k++)
+        ker[((size_t)p * 3 + d) * w + k] = (R)kb_phi((k - f) / half, zeta, inv_den);
+    int *bp = (int *)(base + p);
+    bp[d] = b;
+    q[4 * (size_t)p + d] = (R)chg[3 * o + d];
     o = pperm[p];
-    spos[p] = make_double4(wrap_box(pos[3 * o], L), wrap_box(pos[3 * o + 1], L),
-                           wrap_box(pos[3 * o + 2], L), 0.0);
-    for (int c = 0; c < 3; c++) schg[4 * (size_t)p + c] = (R)chg[3 * o + c];
-    schg[4 * (size_t)p + 3] = (R)0;
-    sseg[p] = o / Q;
+    double *sp = (double *)(spos + p);
+    sp[d] = wrap_box(pos[3 * o + d], L);
+    schg[4 * (size_t)p + d] = (R)chg[3 * o + d];
+    if (d == 0) {
+        bp[3] = 0;
+        q[4 * (size_t)p + 3] = (R)0;
+        sp[3] = 0.0;
+        schg[4 * (size_t)p + 3] = (R)0;
+        sseg[p] = o / Q;
+    }
 }
 
 void build_bins(bs_plan_t p) {
@@ -252,13 +266,13 @@ void build_bins(bs_plan_t p) {
     hipLaunchKernelGGL(k_sort_all, dim3(ntiles + 2 * nc3), dim3(64), 0, p->stream, S);
     const double zeta = p->prm.zeta, inv_den = 1.0 / (-expm1(-2.0 * zeta));
     if (p->fp32)
-        hipLaunchKernelGGL(k_gather_all<float>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream, M,
+        hipLaunchKernelGGL(k_gather_all<float>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0, p->stream, M,
                            w, p->Q, S.perm[0], S.perm[1], (const double *)p->d_qpos.p,
                            (const double *)p->d_qchg.p, L, inv_h, n, zeta, inv_den,
                            (int4 *)p->sp_base.p, (float *)p->sp_ker.p, (float *)p->sp_q.p,
                            (double4 *)p->pq_pos.p, (float *)p->pq_chg.p, (int *)p->pq_seg.p);
     else
-        hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(M, bs)), dim3(bs), 0, p->stream,
+        hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0, p->stream,
                            M, w, p->Q, S.perm[0], S.perm[1], (const double *)p->d_qpos.p,
                            (const double *)p->d_qchg.p, L, inv_h, n, zeta, inv_den,
                            (int4 *)p->sp_base.p, (double *)p->sp_ker.p, (double *)p->sp_q.p,

@@ -170,6 +170,9 @@ int resolve(const bs_params *in, bs_params *out) {
     if (r.ns_mode < BS_NS_OFF || r.ns_mode > BS_NS_MLP) return bad("unknown ns_mode");
     if (r.ns_eta == 0) r.ns_eta = 1.0;
     if (!(r.ns_eta > 0)) return bad("ns_eta must be positive");
+    if (r.fft_mode < BS_FFT_AUTO || r.fft_mode > BS_FFT_PRUNED) return bad("unknown fft_mode");
+    if (r.fft_mode == BS_FFT_PRUNED && (r.grid_n & (r.grid_n - 1)) != 0)
+        return bad("BS_FFT_PRUNED needs grid_n a power of two");
     if (r.beta == 0) r.beta = beta_from_tol(r.tol);
     if (!(r.beta > 0)) return bad("beta must be positive");
     if (r.w == 0) r.w = width_from_tol(r.tol);
@@ -307,6 +310,32 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
     if (hipfftSetStream(P->fft_fwd, P->stream) != HIPFFT_SUCCESS ||
         hipfftSetStream(P->fft_inv, P->stream) != HIPFFT_SUCCESS)
         return fail(set_error(P, BS_EDEVICE, "hipfftSetStream failed"));
+    // pruned transforms: twiddles exp(-+2 pi i k / n), k < n/2, from float64
+    P->pruned = r.fft_mode == BS_FFT_PRUNED && pruned_fft_ok(P->n);
+    if (P->pruned) {
+        const size_t cs = 2 * P->real_size, K1 = r.K + 1, NY = 2 * r.K + 1;
+        pruned_batches(P->n, cs, &P->fft_kb, &P->fft_kz);
+        if ((rc = ensure<char>(P, P->fft_tw, n * cs)) ||
+            (rc = ensure<char>(P, P->fft_A, 3 * n * n * K1 * cs)) ||
+            (rc = ensure<char>(P, P->fft_B, 3 * NY * n * K1 * cs)))
+            return fail(rc);
+        std::vector<double> tw(2 * n);
+        for (size_t k = 0; k < n / 2; k++) {
+            const double ang = 2.0 * kPi * (double)k / (double)n;
+            const double c = cos(ang), sn = sin(ang);
+            tw[2 * k] = c; tw[2 * k + 1] = -sn;                    // forward
+            tw[n + 2 * k] = c; tw[n + 2 * k + 1] = sn;             // inverse
+        }
+        if (P->fp32) {
+            std::vector<float> tf(tw.begin(), tw.end());
+            rc = check_hip(P, hipMemcpy(P->fft_tw.p, tf.data(), tf.size() * 4,
+                                        hipMemcpyHostToDevice), "copy twiddles");
+        } else {
+            rc = check_hip(P, hipMemcpy(P->fft_tw.p, tw.data(), tw.size() * 8,
+                                        hipMemcpyHostToDevice), "copy twiddles");
+        }
+        if (rc) return fail(rc);
+    }
     *out = P;
     return BS_OK;
 }
@@ -361,6 +390,9 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
                 (rc = ensure<int>(P, P->ns_ckey, N)) || (rc = ensure<int>(P, P->ns_ccnt, nb3 + 1)) ||
                 (rc = ensure<int>(P, P->ns_cstart, nb3 + 1)) ||
                 (rc = ensure<int>(P, P->ns_cfill, nb3 + 1)) || (rc = ensure<int>(P, P->ns_cperm, N)) ||
+                (rc = ensure<int>(P, P->ns_tkey, N)) || (rc = ensure<int>(P, P->ns_tcnt, nb3 + 1)) ||
+                (rc = ensure<int>(P, P->ns_tstart, nb3 + 1)) ||
+                (rc = ensure<int>(P, P->ns_tfill, nb3 + 1)) || (rc = ensure<int>(P, P->ns_tperm, N)) ||
                 (rc = ensure<double4>(P, P->ns_segA, N)) || (rc = ensure<double4>(P, P->ns_segB, N)) ||
                 (rc = ensure<float4>(P, P->ns_segM, N)) ||
                 (rc = ensure<int2>(P, P->ns_slots, mp)) || (rc = ensure<int>(P, P->ns_cnt, N + 1)) ||
@@ -389,13 +421,8 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
         P->Nq = Nq;
         P->max_fil_nodes = maxn;
     }
-    if ((rc = check_hip(P, hipMemcpyAsync(P->d_x.p, xyz, sizeof(double) * 3 * N,
-                                          hipMemcpyDeviceToDevice, P->stream), "copy xyz")) ||
-        (rc = check_hip(P, hipMemcpyAsync(P->d_gamma.p, gamma, sizeof(double) * nfil,
-                                          hipMemcpyDeviceToDevice, P->stream), "copy gamma")))
-        return rc;
     stage_begin(P, 0);
-    launch_chord(P);
+    launch_chord(P, xyz, gamma);   // also takes the plan's copies of xyz and gamma
     launch_spline(P);
     launch_geometry(P);
     stage_end(P, 0);
@@ -428,15 +455,27 @@ static int long_range(bs_plan_t P, int psi, double *out) {
     stage_begin(P, 3);
     launch_spread(P);
     stage_end(P, 3);
-    stage_begin(P, 4);
-    if ((rc = fft_forward(P))) return rc;
-    stage_end(P, 4);
-    stage_begin(P, 5);
-    launch_spectral(P, psi);
-    stage_end(P, 5);
-    stage_begin(P, 6);
-    if ((rc = fft_inverse(P))) return rc;
-    stage_end(P, 6);
+    if (P->pruned) {
+        stage_begin(P, 4);
+        pruned_forward(P);
+        stage_end(P, 4);
+        stage_begin(P, 5);
+        pruned_spectral_op(P, psi);
+        stage_end(P, 5);
+        stage_begin(P, 6);
+        pruned_inverse(P);
+        stage_end(P, 6);
+    } else {
+        stage_begin(P, 4);
+        if ((rc = fft_forward(P))) return rc;
+        stage_end(P, 4);
+        stage_begin(P, 5);
+        launch_spectral(P, psi);
+        stage_end(P, 5);
+        stage_begin(P, 6);
+        if ((rc = fft_inverse(P))) return rc;
+        stage_end(P, 6);
+    }
     stage_begin(P, 7);
     launch_interp(P, out);
     stage_end(P, 7);
@@ -547,7 +586,7 @@ int bs_status(bs_plan_t P) {
         (void)hipMemsetAsync(P->d_status.p, 0, sizeof(int), P->stream);
         (void)hipStreamSynchronize(P->stream);
         return set_error(P, BS_EINVAL, (st & 1) ? "non-finite node position or zero-length segment"
-                                                : "more than 32 near-singular segments at a node");
+                                                : "more than 64 near-singular segments at a node");
     }
     return BS_OK;
 }
@@ -692,14 +731,15 @@ int bs_destroy(bs_plan_t P) {
     }
     if (P->fft_fwd) hipfftDestroy(P->fft_fwd);
     if (P->fft_inv) hipfftDestroy(P->fft_inv);
-    DBuf *all[] = {&P->grid, &P->spec, &P->deconv, &P->fftwork, &P->d_off, &P->d_fil,
+    DBuf *all[] = {&P->grid, &P->spec, &P->deconv, &P->fftwork, &P->fft_tw, &P->fft_A, &P->fft_B, &P->d_off, &P->d_fil,
                    &P->d_gamma, &P->d_x, &P->d_dtau, &P->d_D, &P->d_sdd, &P->d_ell,
                    &P->d_qpos, &P->d_qchg, &P->d_status, &P->sp_key, &P->sp_cnt, &P->sp_start,
                    &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
                    &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
                    &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->ns_red, &P->ns_nc, &P->ns_ckey,
-                   &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_slots,
+                   &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_tkey, &P->ns_tcnt,
+                   &P->ns_tstart, &P->ns_tfill, &P->ns_tperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_slots,
                    &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout,
                    &P->ns_X, &P->ns_Y, &P->ns_fallback, &P->rk_k, &P->rk_s};
     for (DBuf *b : all) release(*b);

@@ -47,6 +47,36 @@ __device__ __forceinline__ int prev_node_d(const int *off, const int *fil, int j
     return (j > off[f]) ? j - 1 : off[f + 1] - 1;
 }
 
+// counter[key] += 1 for every active lane, with one atomic per distinct key
+// in the wavefront: lanes sharing a key form a group, whose lowest lane adds
+// the group size.  With RET, returns the counter's value before the lane's own
+// increment (the group's old value plus the lane's rank in the group, in lane
+// order); else 0.  Call from converged control flow (every lane of the
+// wavefront), with active false for lanes that have no item.
+template <bool RET>
+__device__ __forceinline__ int wave_add(int *counter, int key, bool active) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long todo = __ballot(active);
+    int result = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int kl = __shfl(key, leader);
+        const unsigned long long grp = __ballot(active && key == kl) & todo;
+        int old = 0;
+        if (lane == leader) {
+            if (RET) old = atomicAdd(counter + kl, __popcll(grp));
+            else atomicAdd(counter + kl, __popcll(grp));
+        }
+        if (RET) {
+            old = __shfl(old, leader);
+            if ((grp >> lane) & 1ull) result = old + __popcll(grp & below);
+        }
+        todo &= ~grp;
+    }
+    return result;
+}
+
 // Orders the distinct entries perm[s .. s+n) ascending: every entry's rank is
 // the number of smaller entries in the bin, and it is written to its rank slot.
 // Called by a whole workgroup for one bin.  Bins of up to CAP entries are

@@ -50,6 +50,11 @@ struct bs_plan_s {
     bs::DBuf spec;          // [3][n][n][n/2+1] complex
     bs::DBuf deconv;        // [K+1] float64: 1 / F(m)^2 per axis
     bs::DBuf fftwork;
+    // pruned transforms (power-of-two grids): twiddles [n/2 forward][n/2
+    // inverse], A [3][n][n][K+1] and B [3][2K+1][n][K+1] complex
+    bool pruned = false;
+    int fft_kb = 1, fft_kz = 1;
+    bs::DBuf fft_tw, fft_A, fft_B;
 
     // short-range cell list
     int nc = 1;             // cells per axis
@@ -75,10 +80,11 @@ struct bs_plan_s {
     bs::DBuf scan_tmp, red_tmp, spline_tmp;
     int64_t max_fil_nodes = 0;
     // near-singular pairs
-    int ns_max_per_node = 32;
+    int ns_max_per_node = 64;                  // near-singular segments per target, at most
     int ns_ncmax = 3;                          // bound on the segment cell grid per axis
     bs::DBuf ns_red, ns_nc;                    // f64 [1 + blocks] max reach, int32 cells per axis
     bs::DBuf ns_ckey, ns_ccnt, ns_cstart, ns_cfill, ns_cperm;   // segments by midpoint cell
+    bs::DBuf ns_tkey, ns_tcnt, ns_tstart, ns_tfill, ns_tperm;   // targets by node cell
     bs::DBuf ns_segA, ns_segB;                 // double4 [N] cell-ordered end points
     bs::DBuf ns_segM;                          // float4 [N] midpoint and reach (prefilter)
     bs::DBuf ns_slots;                         // int2 [N][max_per_node] per-node flag output
@@ -111,7 +117,7 @@ int set_error(bs_plan_t p, int code, const std::string &msg);
 int check_hip(bs_plan_t p, hipError_t e, const char *what);
 
 // geometry.hip
-void launch_chord(bs_plan_t p);
+void launch_chord(bs_plan_t p, const double *xyz, const double *gamma);
 void launch_spline(bs_plan_t p);
 void launch_geometry(bs_plan_t p);
 // mode bits for launch_local_self
@@ -129,6 +135,13 @@ void launch_interp(bs_plan_t p, double *out);
 void launch_modes(bs_plan_t p, double *out);
 int fft_forward(bs_plan_t p);
 int fft_inverse(bs_plan_t p);
+
+// fft.hip
+bool pruned_fft_ok(int n);
+void pruned_batches(int n, size_t csize, int *kb, int *kz);
+void pruned_forward(bs_plan_t p);
+void pruned_spectral_op(bs_plan_t p, int psi);
+void pruned_inverse(bs_plan_t p);
 
 // pairs.hip
 void launch_pairs(bs_plan_t p, int psi, double *out);

@@ -29,19 +29,24 @@ __device__ __forceinline__ int prev_node(const int *off, const int *fil, int j) 
 }
 
 // ------------------------------------------------------------- chord lengths
-__global__ void k_chord(int N, const double *__restrict__ x, const int *__restrict__ off,
-                        const int *__restrict__ fil, double *__restrict__ dtau,
-                        int *__restrict__ status) {
+// Chord lengths from the caller's node positions, which are copied into the
+// plan's own array on the way (xs may alias xd); thread f < nfil also copies
+// filament f's circulation.
+__global__ void k_chord(int N, int nfil, const double *xs, double *xd,
+                        const double *__restrict__ gs, double *__restrict__ gd,
+                        const int *__restrict__ off, const int *__restrict__ fil,
+                        double *__restrict__ dtau, int *__restrict__ status) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nfil) gd[j] = gs[j];
     if (j >= N) return;
     int jn = next_node(off, fil, j);
-    double dx = x[3 * jn] - x[3 * j], dy = x[3 * jn + 1] - x[3 * j + 1],
-           dz = x[3 * jn + 2] - x[3 * j + 2];
+    const double x0 = xs[3 * j], x1 = xs[3 * j + 1], x2 = xs[3 * j + 2];
+    double dx = xs[3 * jn] - x0, dy = xs[3 * jn + 1] - x1, dz = xs[3 * jn + 2] - x2;
     double h = sqrt(dx * dx + dy * dy + dz * dz);
-    bool ok = isfinite(x[3 * j]) && isfinite(x[3 * j + 1]) && isfinite(x[3 * j + 2]) &&
-              isfinite(h) && h > 0.0;
+    bool ok = isfinite(x0) && isfinite(x1) && isfinite(x2) && isfinite(h) && h > 0.0;
     if (!ok) atomicOr(status, 1);
     dtau[j] = ok ? h : 1.0;
+    xd[3 * j] = x0; xd[3 * j + 1] = x1; xd[3 * j + 2] = x2;
 }
 
 // ------------------------------------------------------------- spline (PCR)
@@ -248,11 +253,13 @@ __global__ void k_local_self(int N, int Q, int mode, double sign, double a, doub
 // ------------------------------------------------------------------ launch
 static inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
-void launch_chord(bs_plan_t p) {
+void launch_chord(bs_plan_t p, const double *xyz, const double *gamma) {
     if (p->N == 0) return;
-    hipLaunchKernelGGL(k_chord, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream, (int)p->N,
-                       (const double *)p->d_x.p, (const int *)p->d_off.p,
-                       (const int *)p->d_fil.p, (double *)p->d_dtau.p, (int *)p->d_status.p);
+    const int64_t items = p->N > p->nfil ? p->N : p->nfil;
+    hipLaunchKernelGGL(k_chord, dim3(blocks_for(items, 256)), dim3(256), 0, p->stream, (int)p->N,
+                       (int)p->nfil, xyz, (double *)p->d_x.p, gamma, (double *)p->d_gamma.p,
+                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
+                       (double *)p->d_dtau.p, (int *)p->d_status.p);
 }
 
 void launch_spline(bs_plan_t p) {

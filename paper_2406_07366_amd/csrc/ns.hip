@@ -92,25 +92,45 @@ __global__ void k_ns_zero(int n, int *__restrict__ a, int *__restrict__ b) {
     if (i < n) { a[i] = 0; b[i] = 0; }
 }
 
+// segment key: cell of the chord midpoint; target key: cell of the node
 __global__ void k_ns_keys(int N, const int *__restrict__ off, const int *__restrict__ fil,
                           const double *__restrict__ x, double L, const int *__restrict__ ncp,
-                          int *__restrict__ key, int *__restrict__ cnt) {
+                          int *__restrict__ key, int *__restrict__ cnt, int *__restrict__ tkey,
+                          int *__restrict__ tcnt) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const int nc = *ncp, jn = next_node_d(off, fil, j);
-    int c[3];
-    for (int q = 0; q < 3; q++) c[q] = cell_of(0.5 * (x[3 * j + q] + x[3 * jn + q]), L, nc);
-    const int k = (c[2] * nc + c[1]) * nc + c[0];
-    key[j] = k;
-    atomicAdd(&cnt[k], 1);
+    const bool valid = j < N;
+    int k = 0, kt = 0;
+    if (valid) {
+        const int nc = *ncp, jn = next_node_d(off, fil, j);
+        int c[3], d[3];
+        for (int q = 0; q < 3; q++) {
+            c[q] = cell_of(0.5 * (x[3 * j + q] + x[3 * jn + q]), L, nc);
+            d[q] = cell_of(x[3 * j + q], L, nc);
+        }
+        k = (c[2] * nc + c[1]) * nc + c[0];
+        key[j] = k;
+        kt = (d[2] * nc + d[1]) * nc + d[0];
+        tkey[j] = kt;
+    }
+    wave_add<false>(cnt, k, valid);
+    wave_add<false>(tcnt, kt, valid);
 }
 
+// segments and targets into their cells (the order of targets within a cell
+// does not matter; segments are ordered afterwards)
 __global__ void k_ns_scatter(int N, const int *__restrict__ key, const int *__restrict__ start,
-                             int *__restrict__ fill, int *__restrict__ perm) {
+                             int *__restrict__ fill, int *__restrict__ perm,
+                             const int *__restrict__ tkey, const int *__restrict__ tstart,
+                             int *__restrict__ tfill, int *__restrict__ tperm) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const int k = key[j];
-    perm[start[k] + atomicAdd(&fill[k], 1)] = j;
+    const bool valid = j < N;
+    const int k = valid ? key[j] : 0, kt = valid ? tkey[j] : 0;
+    const int r = wave_add<true>(fill, k, valid);
+    const int rt = wave_add<true>(tfill, kt, valid);
+    if (valid) {
+        perm[start[k] + r] = j;
+        tperm[tstart[kt] + rt] = j;
+    }
 }
 
 // one wavefront per occupied cell range, striding over the nc^3 cells
@@ -176,101 +196,199 @@ struct NsArgs {
     const float4 *segM;
 };
 
-// One wavefront per target node.  Lanes 0..26 hold one of the 27 cells
-// around the target; the cells' contents are enumerated as one flattened
-// range, 64 candidates per step, each lane finding its cell by binary search
-// over the wavefront's prefix sums.  Flagged candidates are ranked with a
-// ballot, so a node's pairs are written in enumeration order (cell order,
-// then segment order within a cell) to its max_per_node slots.
-__global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt,
-                                                 int2 *__restrict__ slots,
-                                                 int *__restrict__ status) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = gid >> 6, lane = gid & 63;
-    if (t >= a.N) return;   // whole wavefronts exit together
-    const int o = a.nperm[t];
-    const int ip = prev_node_d(a.off, a.fil, o);
-    const double xi[3] = {a.x[3 * o], a.x[3 * o + 1], a.x[3 * o + 2]};
-    const float xf[3] = {(float)wrap_box(xi[0], a.L), (float)wrap_box(xi[1], a.L),
-                         (float)wrap_box(xi[2], a.L)};
+// Target of a flag test: the node, its previous node (the two adjacent
+// segments are excluded), its position in float64 and wrapped float32.
+struct NsTarget {
+    int o, ip;
+    double x[3];
+    float xf[3];
+};
+
+__device__ __forceinline__ NsTarget ns_target(const NsArgs &a, int o) {
+    NsTarget T;
+    T.o = o;
+    T.ip = prev_node_d(a.off, a.fil, o);
+    for (int q = 0; q < 3; q++) {
+        T.x[q] = a.x[3 * o + q];
+        T.xf[q] = (float)wrap_box(T.x[q], a.L);
+    }
+    return T;
+}
+
+// Does segment record p (cell order) flag target T?  First a float32 test
+// against the sphere (chord midpoint, reach) that holds every target the
+// segment can flag, with a margin that covers the float32 rounding of both
+// points; then the float64 chord distance < eta * ell.  On success returns
+// the segment index and the target's image shift, periods per axis packed as
+// three 10-bit fields (+-511 periods).
+__device__ __forceinline__ bool ns_test(const NsArgs &a, const NsTarget &T, float4 M4, int p,
+                                        int *sg_out, int *sh_out) {
     const float Lf = (float)a.L, iLf = (float)(1.0 / a.L), margin = (float)(1e-5 * a.L);
-    const int nc = *a.ncp;
+    float dx = T.xf[0] - M4.x, dy = T.xf[1] - M4.y, dz = T.xf[2] - M4.z;
+    dx -= Lf * rintf(dx * iLf); dy -= Lf * rintf(dy * iLf); dz -= Lf * rintf(dz * iLf);
+    const float r = M4.w + margin;
+    if (!(dx * dx + dy * dy + dz * dz < r * r)) return false;
+    const double4 A4 = a.segA[p], B4 = a.segB[p];
+    const int sg = (int)B4.w;
+    if (sg == T.o || sg == T.ip) return false;
+    const double A[3] = {A4.x, A4.y, A4.z}, Bv[3] = {B4.x, B4.y, B4.z};
+    double xs[3];
+    if (!(chord_dist(A, Bv, T.x, a.L, xs) < a.eta * A4.w)) return false;
+    int sh = 0;
+    for (int q = 0; q < 3; q++) {
+        int sv = (int)rint((xs[q] - T.x[q]) / a.L);
+        sv = sv < -511 ? -511 : (sv > 511 ? 511 : sv);
+        sh = (sh << 10) | (sv + 512);
+    }
+    *sg_out = sg;
+    *sh_out = sh;
+    return true;
+}
+
+// Lanes 0..26 of a wavefront: start and size of one of the 27 cells around
+// cell (c0x, c0y, c0z) (lane 0: the single cell when nc < 3); returns the
+// lane's exclusive prefix of the sizes and the total in *total.
+__device__ __forceinline__ int ns_window(const NsArgs &a, int nc, const int *c0, int lane,
+                                         int *cs, int *cn, int *total) {
     const int ncell = nc >= 3 ? 27 : 1;
-    int cs = 0, cn = 0;
+    *cs = 0; *cn = 0;
     if (lane < ncell) {
         int cidx = 0;
         if (nc >= 3) {
             const int dd[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
             int c[3];
             for (int q = 0; q < 3; q++) {
-                int v = cell_of(xi[q], a.L, nc) + dd[q];
+                int v = c0[q] + dd[q];
                 c[q] = v < 0 ? v + nc : (v >= nc ? v - nc : v);
             }
             cidx = (c[2] * nc + c[1]) * nc + c[0];
         }
-        cs = a.cstart[cidx];
-        cn = a.cstart[cidx + 1] - cs;
+        *cs = a.cstart[cidx];
+        *cn = a.cstart[cidx + 1] - *cs;
     }
-    int incl = cn;
+    int incl = *cn;
     for (int d = 1; d < 64; d <<= 1) {
         const int v = __shfl_up(incl, d);
         if (lane >= d) incl += v;
     }
-    const int total = __shfl(incl, 63);
-    const int excl = incl - cn;
+    *total = __shfl(incl, 63);
+    return incl - *cn;
+}
+
+// Used when fewer than 3 cells fit along an axis (one cell holds every
+// segment): one wavefront per target, 64 candidates per step, flagged ones
+// ranked with a ballot and written in candidate order to the target's
+// max_per_node slots.
+__global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt,
+                                                 int2 *__restrict__ slots,
+                                                 int *__restrict__ status) {
+    if (*a.ncp >= 3) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = gid & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int2 *out = slots + (size_t)o * a.max_per_node;
-    int k = 0;
-    for (int q0 = 0; q0 < total; q0 += 64) {
-        const int q = q0 + lane;
-        // last cell whose exclusive prefix is <= q
-        int c = 0;
-        for (int step = 16; step > 0; step >>= 1) {
-            const int tc = c + step;
-            const int pv = __shfl(excl, tc < ncell ? tc : ncell - 1);
-            if (tc < ncell && pv <= q) c = tc;
-        }
-        const int p = __shfl(cs, c) + (q - __shfl(excl, c));
-        bool flag = false;
-        int sg = -1, sh = 0;
-        // float32 prefilter: a flagged segment has |x - m| < reach (chord
-        // midpoint m); the margin covers the float32 rounding of both points
-        bool near = false;
-        if (q < total) {
-            const float4 M4 = a.segM[p];
-            float dx = xf[0] - M4.x, dy = xf[1] - M4.y, dz = xf[2] - M4.z;
-            dx -= Lf * rintf(dx * iLf); dy -= Lf * rintf(dy * iLf); dz -= Lf * rintf(dz * iLf);
-            const float r = M4.w + margin;
-            near = dx * dx + dy * dy + dz * dz < r * r;
-        }
-        if (near) {
-            const double4 A4 = a.segA[p], B4 = a.segB[p];
-            sg = (int)B4.w;
-            if (sg != o && sg != ip) {
-                const double A[3] = {A4.x, A4.y, A4.z}, Bv[3] = {B4.x, B4.y, B4.z};
-                double xs[3];
-                if (chord_dist(A, Bv, xi, a.L, xs) < a.eta * A4.w) {
-                    flag = true;
-                    // image shift of the target, periods per axis, packed as
-                    // three 10-bit fields (+-511 periods)
-                    for (int r = 0; r < 3; r++) {
-                        int sv = (int)rint((xs[r] - xi[r]) / a.L);
-                        sv = sv < -511 ? -511 : (sv > 511 ? 511 : sv);
-                        sh = (sh << 10) | (sv + 512);
-                    }
-                }
+    for (int t = gid >> 6; t < a.N; t += (gridDim.x * blockDim.x) >> 6) {
+        const NsTarget T = ns_target(a, a.nperm[t]);
+        const int zero[3] = {0, 0, 0};
+        int cs, cn, total;
+        ns_window(a, 1, zero, lane, &cs, &cn, &total);
+        const int s0 = __shfl(cs, 0);
+        int2 *out = slots + (size_t)T.o * a.max_per_node;
+        int k = 0;
+        for (int q0 = 0; q0 < total; q0 += 64) {
+            const int q = q0 + lane;
+            int sg = 0, sh = 0;
+            const bool flag = q < total && ns_test(a, T, a.segM[s0 + q], s0 + q, &sg, &sh);
+            const unsigned long long m = __ballot(flag);
+            if (flag) {
+                const int slot = k + __popcll(m & below);
+                if (slot < a.max_per_node) out[slot] = make_int2(sg, sh);
             }
+            k += __popcll(m);
         }
-        const unsigned long long m = __ballot(flag);
-        if (flag) {
-            const int slot = k + __popcll(m & below);
-            if (slot < a.max_per_node) out[slot] = make_int2(sg, sh);
+        if (lane == 0) {
+            if (k > a.max_per_node) atomicOr(status, 2);
+            cnt[T.o] = k < a.max_per_node ? k : a.max_per_node;
         }
-        k += __popcll(m);
     }
-    if (lane == 0) {
-        if (k > a.max_per_node) atomicOr(status, 2);
-        cnt[o] = k < a.max_per_node ? k : a.max_per_node;
+}
+
+// One workgroup per cell of targets (nc >= 3).  The segment records of the
+// 27 cells around it (cell order, then segment order) are staged in LDS in
+// chunks of kNsStage and shared by every target of the cell; wavefront w
+// takes targets w, w + 4, ...  and scans each chunk 64 candidates per step.
+// Flagged candidates are ranked with a ballot, so each target's pairs are
+// written in candidate order to its max_per_node slots.  Targets are taken
+// 256 at a time (their running counts live in LDS).
+constexpr int kNsStage = 2048;
+
+__global__ __launch_bounds__(256) void k_ns_flag_cells(NsArgs a, const int *__restrict__ tstart,
+                                                       const int *__restrict__ tperm,
+                                                       int *__restrict__ cnt,
+                                                       int2 *__restrict__ slots,
+                                                       int *__restrict__ status) {
+    __shared__ float4 sm[kNsStage];
+    __shared__ int sp[kNsStage];
+    __shared__ int cell_s[27], cell_o[27], tk[256], win_total;
+    const int nc = *a.ncp;
+    if (nc < 3) return;
+    const int nb3 = nc * nc * nc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int C = blockIdx.x; C < nb3; C += gridDim.x) {
+        const int t0 = tstart[C], nt = tstart[C + 1] - t0;
+        if (nt == 0) continue;   // uniform over the workgroup
+        if (wave == 0) {
+            const int c0[3] = {C % nc, (C / nc) % nc, C / (nc * nc)};
+            int cs, cn, total;
+            const int excl = ns_window(a, nc, c0, lane, &cs, &cn, &total);
+            if (lane < 27) { cell_s[lane] = cs; cell_o[lane] = excl; }
+            if (lane == 0) win_total = total;
+        }
+        __syncthreads();
+        const int total = win_total;
+        for (int g0 = 0; g0 < nt; g0 += 256) {
+            const int ng = nt - g0 < 256 ? nt - g0 : 256;
+            for (int i = threadIdx.x; i < ng; i += blockDim.x) tk[i] = 0;
+            for (int c0 = 0; c0 < total; c0 += kNsStage) {
+                const int cn = total - c0 < kNsStage ? total - c0 : kNsStage;
+                for (int i = threadIdx.x; i < cn; i += blockDim.x) {
+                    const int q = c0 + i;
+                    int c = 0;
+                    for (int step = 16; step > 0; step >>= 1) {
+                        const int tc = c + step;
+                        if (tc < 27 && cell_o[tc] <= q) c = tc;
+                    }
+                    const int p = cell_s[c] + (q - cell_o[c]);
+                    sm[i] = a.segM[p];
+                    sp[i] = p;
+                }
+                __syncthreads();
+                for (int ti = wave; ti < ng; ti += 4) {
+                    const NsTarget T = ns_target(a, tperm[t0 + g0 + ti]);
+                    int2 *out = slots + (size_t)T.o * a.max_per_node;
+                    int k = tk[ti];
+                    for (int j0 = 0; j0 < cn; j0 += 64) {
+                        const int j = j0 + lane;
+                        int sg = 0, sh = 0;
+                        const bool flag = j < cn && ns_test(a, T, sm[j], sp[j], &sg, &sh);
+                        const unsigned long long m = __ballot(flag);
+                        if (flag) {
+                            const int slot = k + __popcll(m & below);
+                            if (slot < a.max_per_node) out[slot] = make_int2(sg, sh);
+                        }
+                        k += __popcll(m);
+                    }
+                    if (lane == 0) tk[ti] = k;
+                }
+                __syncthreads();
+            }
+            for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+                const int o = tperm[t0 + g0 + i], k = tk[i];
+                if (k > a.max_per_node) atomicOr(status, 2);
+                cnt[o] = k < a.max_per_node ? k : a.max_per_node;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -762,13 +880,19 @@ void ns_build_pairs(bs_plan_t p) {
                        p->prm.ns_eta, red + 1);
     hipLaunchKernelGGL(k_ns_cells, dim3(1), dim3(bs), 0, p->stream, red + 1, nred, p->prm.L,
                        p->ns_ncmax, red, ncp);
+    int *tkey = (int *)p->ns_tkey.p, *tcnt = (int *)p->ns_tcnt.p, *tstart = (int *)p->ns_tstart.p;
+    int *tfill = (int *)p->ns_tfill.p, *tperm = (int *)p->ns_tperm.p;
     hipLaunchKernelGGL(k_ns_zero, dim3(ceil_div(nb3 + 1, bs)), dim3(bs), 0, p->stream, nb3 + 1,
                        ccnt, cfill);
+    hipLaunchKernelGGL(k_ns_zero, dim3(ceil_div(nb3 + 1, bs)), dim3(bs), 0, p->stream, nb3 + 1,
+                       tcnt, tfill);
     hipLaunchKernelGGL(k_ns_keys, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, off, fil, x,
-                       p->prm.L, (const int *)ncp, ckey, ccnt);
+                       p->prm.L, (const int *)ncp, ckey, ccnt, tkey, tcnt);
     exclusive_scan(p, ccnt, cstart, nb3);
+    exclusive_scan(p, tcnt, tstart, nb3);
     hipLaunchKernelGGL(k_ns_scatter, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
-                       (const int *)ckey, (const int *)cstart, cfill, cperm);
+                       (const int *)ckey, (const int *)cstart, cfill, cperm, (const int *)tkey,
+                       (const int *)tstart, tfill, tperm);
     const int nsort = nb3 < 4096 ? nb3 : 4096;
     hipLaunchKernelGGL(k_ns_sort, dim3(nsort), dim3(64), 0, p->stream, (const int *)ncp,
                        (const int *)cstart, cperm, ckey);
@@ -784,7 +908,12 @@ void ns_build_pairs(bs_plan_t p) {
     a.segA = (const double4 *)p->ns_segA.p; a.segB = (const double4 *)p->ns_segB.p;
     a.segM = (const float4 *)p->ns_segM.p;
     int *cnt = (int *)p->ns_cnt.p, *start = (int *)p->ns_start.p;
-    hipLaunchKernelGGL(k_ns_flag, dim3(ceil_div((int64_t)N * 64, bs)), dim3(bs), 0, p->stream, a,
+    // exactly one of the two does work, depending on the cell count
+    hipLaunchKernelGGL(k_ns_flag_cells, dim3(nb3 < 8192 ? nb3 : 8192), dim3(bs), 0, p->stream, a,
+                       (const int *)tstart, (const int *)tperm, cnt, (int2 *)p->ns_slots.p,
+                       (int *)p->d_status.p);
+    const int nwave = ceil_div((int64_t)N * 64, bs);
+    hipLaunchKernelGGL(k_ns_flag, dim3(nwave < 1024 ? nwave : 1024), dim3(bs), 0, p->stream, a,
                        cnt, (int2 *)p->ns_slots.p, (int *)p->d_status.p);
     exclusive_scan(p, cnt, start, N);
     const int64_t ns = (int64_t)N * p->ns_max_per_node;
@@ -811,12 +940,26 @@ void launch_ns_adaptive(bs_plan_t p, double *v) {
                        (const double *)p->ns_pout.p, v);
 }
 
+__global__ void k_ns_count_all(const int *__restrict__ total, int *__restrict__ nfallback) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *nfallback = *total;
+}
+
 void launch_ns_mlp(bs_plan_t p, double *v) {
     const int N = (int)p->N;
     NsRule R;
     ns_rule(&R);
     const int *start = (const int *)p->ns_start.p;
     const int *total = start + N;
+    bool usable = false;
+    for (int b = 0; b < kNsBins; b++) usable = usable || (double)p->ns_err[b] <= p->prm.tol;
+    if (!usable) {
+        // the error table rules the network out in every bin: every pair
+        // takes the adaptive integrator, and the network is not evaluated
+        launch_ns_adaptive(p, v);
+        hipLaunchKernelGGL(k_ns_count_all, dim3(1), dim3(64), 0, p->stream, total,
+                           (int *)p->ns_fallback.p);
+        return;
+    }
     hipLaunchKernelGGL(k_ns_features, dim3(1024), dim3(256), 0, p->stream, total,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,

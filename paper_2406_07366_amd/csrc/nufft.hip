@@ -39,57 +39,69 @@ namespace bs {
 // Tiles are spread over the 8 XCDs in contiguous ranges (blocks b, b+8, ...
 // run on one XCD), so neighbouring tiles, which share candidate bins and the
 // cache lines of their grid rows, go through the same L2.
-template <typename R, int W, int TT>
-__global__ __launch_bounds__(64) void k_spread(int n, int NT, int nbv, int per_xcd,
-                                               const int *__restrict__ start,
-                                               const int4 *__restrict__ base,
-                                               const R *__restrict__ ker,
-                                               const R *__restrict__ q,
-                                               R *__restrict__ grid) {
-    constexpr int ZL = TT * TT * TT / 64;
+template <typename R, int W, int TT, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, int per_xcd,
+                                                       const int *__restrict__ start,
+                                                       const int4 *__restrict__ base,
+                                                       const R *__restrict__ ker,
+                                                       const R *__restrict__ q,
+                                                       R *__restrict__ grid) {
+    constexpr int T3 = TT * TT * TT;
+    constexpr int ZL = T3 / 64;
     constexpr int SW = 3 * TT + 4;   // staged words: T weights per axis, q, pad
     constexpr int NBMAX = 1 + (W - 1 + TT - 1) / TT;   // bins per axis that reach a tile
     constexpr int NB3 = NBMAX * NBMAX * NBMAX;
-    __shared__ R st[64 * SW];
-    __shared__ int bin_s[NB3], bin_o[NB3];
+    // staging area per wavefront; reused for the sum over wavefronts
+    constexpr int STAGE = WAVES * 64 * SW, RED = WAVES > 1 ? WAVES * 3 * T3 : 0;
+    __shared__ R lds[STAGE > RED ? STAGE : RED];
+    __shared__ int bin_s[NB3], bin_o[NB3], bin_total;
     const int ntiles = NT * NT * NT;
     const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tile >= ntiles) return;
     const int tx = tile % NT, ty = (tile / NT) % NT, tz = tile / (NT * NT);
     const int t0[3] = {tx * TT, ty * TT, tz * TT};
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % TT, ly = (lane / TT) % TT, lz0 = (lane / (TT * TT)) * ZL;
     R acc[3][ZL];
 #pragma unroll
     for (int z = 0; z < ZL; z++) acc[0][z] = acc[1][z] = acc[2][z] = (R)0;
     // start of each bin and exclusive prefix of the bin sizes, in LDS
-    // (bins taken 64 at a time, prefix by wave shuffles)
+    // (bins taken 64 at a time by wavefront 0, prefix by shuffles)
     const int nbins = nbv * nbv * nbv;   // nbv <= NBMAX (checked by the launcher)
-    int total = 0;
-    for (int i0 = 0; i0 < nbins; i0 += 64) {
-        const int i = i0 + lane;
-        int bstart = 0, bsize = 0;
-        if (i < nbins) {
-            const int dx = i % nbv, dy = (i / nbv) % nbv, dz = i / (nbv * nbv);
-            int bz = tz - dz; if (bz < 0) bz += NT;
-            int by = ty - dy; if (by < 0) by += NT;
-            int bx = tx - dx; if (bx < 0) bx += NT;
-            const int bin = (bz * NT + by) * NT + bx;
-            bstart = start[bin];
-            bsize = start[bin + 1] - bstart;
+    if (wave == 0) {
+        int total = 0;
+        for (int i0 = 0; i0 < nbins; i0 += 64) {
+            const int i = i0 + lane;
+            int bstart = 0, bsize = 0;
+            if (i < nbins) {
+                const int dx = i % nbv, dy = (i / nbv) % nbv, dz = i / (nbv * nbv);
+                int bz = tz - dz; if (bz < 0) bz += NT;
+                int by = ty - dy; if (by < 0) by += NT;
+                int bx = tx - dx; if (bx < 0) bx += NT;
+                const int bin = (bz * NT + by) * NT + bx;
+                bstart = start[bin];
+                bsize = start[bin + 1] - bstart;
+            }
+            int incl = bsize;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int v = __shfl_up(incl, d);
+                if (lane >= d) incl += v;
+            }
+            if (i < nbins) { bin_s[i] = bstart; bin_o[i] = total + incl - bsize; }
+            total += __shfl(incl, 63);
         }
-        int incl = bsize;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int v = __shfl_up(incl, d);
-            if (lane >= d) incl += v;
-        }
-        if (i < nbins) { bin_s[i] = bstart; bin_o[i] = total + incl - bsize; }
-        total += __shfl(incl, 63);
+        if (lane == 0) bin_total = total;
     }
     __syncthreads();
+    const int total = bin_total;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int c0 = 0; c0 < total; c0 += 64) {
-        const int ci = c0 + lane;
+    // wavefront w takes chunks w, w + WAVES, ...; every wavefront runs the
+    // same number of rounds so that the block barriers match
+    const int nchunks = (total + 63) / 64;
+    const int rounds = (nchunks + WAVES - 1) / WAVES;
+    R *st = lds + wave * 64 * SW;
+    for (int rd = 0; rd < rounds; rd++) {
+        const int ci = (rd * WAVES + wave) * 64 + lane;
         // bin of candidate ci: the last bin whose exclusive prefix is <= ci
         int b = 0;
         for (int step = 64; step > 0; step >>= 1) {
@@ -147,6 +159,25 @@ __global__ __launch_bounds__(64) void k_spread(int n, int NT, int nbv, int per_x
         }
         __syncthreads();
     }
+    if (WAVES > 1) {
+        // cell (lx, ly, lz0 + z) of wavefront w's partial tile
+#pragma unroll
+        for (int z = 0; z < ZL; z++) {
+            const int cell = ((lz0 + z) * TT + ly) * TT + lx;
+            for (int c = 0; c < 3; c++) lds[(wave * 3 + c) * T3 + cell] = acc[c][z];
+        }
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll
+        for (int z = 0; z < ZL; z++) {
+            const int cell = ((lz0 + z) * TT + ly) * TT + lx;
+            for (int c = 0; c < 3; c++) {
+                R v = lds[c * T3 + cell];
+                for (int w2 = 1; w2 < WAVES; w2++) v += lds[(w2 * 3 + c) * T3 + cell];
+                acc[c][z] = v;
+            }
+        }
+    }
     const size_t n3 = (size_t)n * n * n;
 #pragma unroll
     for (int z = 0; z < ZL; z++) {
@@ -157,6 +188,10 @@ __global__ __launch_bounds__(64) void k_spread(int n, int NT, int nbv, int per_x
     }
 }
 
+// tiles per wavefront-set: grids with fewer tiles than this split each
+// tile's candidates over 4 wavefronts (more parallelism for small grids)
+constexpr int kSpreadSplitTiles = 8192;
+
 template <typename R, int TT>
 static void spread_tt(bs_plan_t p) {
     const int w = p->prm.w;
@@ -165,13 +200,21 @@ static void spread_tt(bs_plan_t p) {
     if (nbv > nb) return;   // the kernel's bin table holds nb^3 bins
     const int ntiles = p->NT * p->NT * p->NT;
     const int per = ceil_div(ntiles, 8);
-    dim3 grid(8 * per), block(64);
+    const bool split = ntiles < kSpreadSplitTiles;
+    dim3 grid(8 * per), block(split ? 256 : 64);
     const int *start = (const int *)p->sp_start.p;
     const int4 *base = (const int4 *)p->sp_base.p;
     const R *ker = (const R *)p->sp_ker.p, *q = (const R *)p->sp_q.p;
     R *g = (R *)p->grid.p;
-#define SPREAD_CASE(WW) \
-    case WW: hipLaunchKernelGGL((k_spread<R, WW, TT>), grid, block, 0, p->stream, p->n, p->NT, nbv, per, start, base, ker, q, g); break;
+#define SPREAD_CASE(WW)                                                                          \
+    case WW:                                                                                     \
+        if (split)                                                                               \
+            hipLaunchKernelGGL((k_spread<R, WW, TT, 4>), grid, block, 0, p->stream, p->n, p->NT, \
+                               nbv, per, start, base, ker, q, g);                                \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_spread<R, WW, TT, 1>), grid, block, 0, p->stream, p->n, p->NT, \
+                               nbv, per, start, base, ker, q, g);                                \
+        break;
     switch (w) {
         SPREAD_CASE(4) SPREAD_CASE(5) SPREAD_CASE(6) SPREAD_CASE(7) SPREAD_CASE(8)
         SPREAD_CASE(9) SPREAD_CASE(10) SPREAD_CASE(11) SPREAD_CASE(12) SPREAD_CASE(13)

@@ -88,3 +88,48 @@ def train(n_train=1_000_000, n_val=100_000, epochs=60, batch=8192, lr=3e-3, seed
         log("[ns-mlp] max err / S per d/h bin: " + " ".join(f"{v:.1e}" for v in tab))
         log("[ns-mlp] median err / S per d/h bin: " + " ".join(f"{v:.1e}" for v in med))
     return mlp, tab, info
+
+
+def _main(argv=None):
+    """Fixed-size loops of the network kernels alone, for profiling:
+         python -m paper_2406_07366_amd.ns_mlp infer [n] [reps]
+         python -m paper_2406_07366_amd.ns_mlp train [batch] [steps]
+    Random initial weights and uniform random features."""
+    import argparse
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["infer", "train"])
+    ap.add_argument("size", nargs="?", type=int, default=1_000_000)
+    ap.add_argument("reps", nargs="?", type=int, default=20)
+    a = ap.parse_args(argv)
+    mlp = B.MLP(B.mlp_init(0))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.rand((a.size, 8), device="cuda", generator=g, dtype=torch.float32) * 2 - 1
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if a.what == "infer":
+        Y = mlp.forward(X)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(a.reps):
+            Y = mlp.forward(X)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / a.reps
+        flop = 2.0 * a.size * (8 * 64 + 64 * 64 * 2 + 64 * 3)
+        print(f"[mlp] forward of {a.size} samples: {ms:.4f} ms, "
+              f"{flop / ms / 1e9:.1f} TFLOP/s (model flops)", flush=True)
+    else:
+        T = torch.rand((a.size, 3), device="cuda", generator=g, dtype=torch.float32)
+        mlp.adam_step(X, T, 1e-3)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(a.reps):
+            mlp.adam_step(X, T, 1e-3)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / a.reps
+        print(f"[mlp] training step of batch {a.size}: {ms:.4f} ms", flush=True)
+
+
+if __name__ == "__main__":
+    _main()

@@ -93,3 +93,13 @@ def test_parameter_errors():
     with pytest.raises(B.BsError) as e:
         B.resolve_params(p)
     assert e.value.code == B.BS_EINVAL
+
+
+def test_pruned_transforms_need_a_power_of_two_grid():
+    L = 2 * math.pi
+    B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, fft_mode=B.BS_FFT_PRUNED))
+    with pytest.raises(B.BsError) as e:
+        B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=48, fft_mode=B.BS_FFT_PRUNED))
+    assert e.value.code == B.BS_EINVAL
+    with pytest.raises(B.BsError):
+        B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, fft_mode=7))

@@ -244,3 +244,29 @@ def test_graph_replay_matches_eager(B):
             assert np.array_equal(got, ref), k
         print(f"  graph active: {plan.graph_active()}")
         plan.close()
+
+
+def _pruned_vs_library(B, precision):
+    import torch
+    fs = W.ellipses()
+    out = {}
+    for mode in (B.BS_FFT_PRUNED, B.BS_FFT_LIBRARY):
+        plan = make_plan(B, fs, precision=precision, fft_mode=mode)
+        v = np_(plan.velocity())
+        E, psi = plan.energy()
+        out[mode] = (v, np_(psi), E)
+        plan.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pruned_transforms_agree_with_hipfft(B, precision):
+    """The pruned transforms with the fused spectral operator: velocity,
+    streamfunction and energy agree with the full hipFFT r2c / c2r path to
+    rounding (float64) or float32 rounding (mixed)."""
+    out = _pruned_vs_library(B, precision)
+    (va, pa, Ea), (vb, pb, Eb) = out[B.BS_FFT_PRUNED], out[B.BS_FFT_LIBRARY]
+    tol = 1e-12 if precision == 0 else 2e-6
+    dv, dp = rel_l2(va, vb), rel_l2(pa, pb)
+    print(f"  pruned vs hipFFT: v {dv:.2e} psi {dp:.2e} E {abs(Ea - Eb) / abs(Eb):.2e}")
+    assert dv <= tol and dp <= tol and abs(Ea - Eb) <= tol * abs(Eb)
