@@ -68,20 +68,32 @@ def count_pairs(plan, fs, Q, rc):
     return int(cnt.sum()) - 2 * Q * fs.n_nodes
 
 
+def pruned_transforms(prm):
+    """The plan's choice for fft_mode 0: pruned transforms on power-of-two
+    grids from 128 up (float64 up to 512)."""
+    n = prm.grid_n
+    return n >= 128 and n & (n - 1) == 0 and n * 4 * (16 if prm.precision == 0 else 8) < 65536
+
+
 def stage_bytes(prm, N, Nq, fp32):
     """Algorithmic HBM bytes per launch of each stage (minimum traffic)."""
     s = 4 if fp32 else 8
     n = prm.grid_n
     n3 = n ** 3
-    nc = n * n * (n // 2 + 1)
     w = prm.w
-    return {
-        "spread": 3 * n3 * s + Nq * (16 + (3 * w + 4) * s),
-        "fft_fwd": 3 * n3 * s + 3 * nc * 2 * s,
-        "spectral": 2 * 3 * nc * 2 * s,
-        "fft_inv": 3 * nc * 2 * s + 3 * n3 * s,
-        "interp": 3 * n3 * s + N * (24 + 48),
-    }
+    out = {"spread": 3 * n3 * s + Nq * (16 + (3 * w + 4) * s),
+           "interp": 3 * n3 * s + N * (24 + 48)}
+    if pruned_transforms(prm):
+        K1, NY = prm.K + 1, 2 * prm.K + 1
+        a = 3 * n * n * K1 * 2 * s          # x-transformed grid, modes 0..K
+        b = 3 * NY * n * K1 * 2 * s         # after y, |my| <= K
+        out.update({"fft_fwd": 3 * n3 * s + a + a + b, "spectral": 2 * b,
+                    "fft_inv": b + a + a + 3 * n3 * s})
+    else:
+        nc = n * n * (n // 2 + 1)
+        out.update({"fft_fwd": 3 * n3 * s + 3 * nc * 2 * s, "spectral": 2 * 3 * nc * 2 * s,
+                    "fft_inv": 3 * nc * 2 * s + 3 * n3 * s})
+    return out
 
 
 def time_steps(torch, plan, fs, xyz, gamma, out, steps, warmup):
@@ -325,7 +337,10 @@ def main():
     # dominant single-kernel stage (stage events then time exactly one kernel)
     dom = max((k for k in roof_all if k in SINGLE_KERNEL_STAGES), key=lambda k: roof_all[k]["ms"])
     d = roof_all[dom]
-    src = os.path.join(ROOT, "paper_2406_07366_amd", "csrc", SINGLE_KERNEL_STAGES[dom])
+    srcname = SINGLE_KERNEL_STAGES[dom]
+    if dom == "spectral" and pruned_transforms(B.resolve_params(B.params_for(fs))):
+        srcname = "fft.hip"         # the spectral operator runs inside the z transform
+    src = os.path.join(ROOT, "paper_2406_07366_amd", "csrc", srcname)
     traffic = read_traffic(os.path.join(ROOT, "profiles",
                                         f"pmc_{dom}_{fs.name}_{args.precision}.txt"), src)
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"],

@@ -73,7 +73,8 @@ extern "C" {
 #define BS_NS_MLP       2  /* learned correction with adaptive fallback       */
 
 /* 3-D transforms of the long-range step */
-#define BS_FFT_AUTO     0  /* the faster of the two below for the grid (hipFFT) */
+#define BS_FFT_AUTO     0  /* BS_FFT_PRUNED for power-of-two grids from 128 up
+                              (where it is faster), else BS_FFT_LIBRARY         */
 #define BS_FFT_LIBRARY  1  /* hipFFT: full r2c / c2r transforms and a separate
                               spectral-operator pass                           */
 #define BS_FFT_PRUNED   2  /* grid_n a power of two (else BS_EINVAL): transforms
@@ -119,7 +120,8 @@ typedef struct {
     int    fft_mode;     /* BS_FFT_AUTO, BS_FFT_LIBRARY or BS_FFT_PRUNED       */
     /* resolved values, written by bs_resolve_params / bs_get_params */
     int    K;            /* retained modes |m_i| <= K per axis                 */
-    int    ncell;        /* cells per axis of the short-range cell list        */
+    int    ncell;        /* cells per axis of the short-range cell list (edge
+                            >= 2 rcut / 3; 1 if fewer than 4 fit)            */
     double zeta;         /* Kaiser-Bessel shape parameter                      */
 } bs_params;
 

@@ -4,9 +4,9 @@
 //
 //   spread bins : tile of T^3 grid cells containing a point's stencil base
 //                 (lowest grid index of its w-point support per axis);
-//   pair cells  : ncell^3 cells of edge L/ncell >= r_c (the cell-list idea of
-//                 Sec. 5.3, with cells no smaller than r_c so that the 27
-//                 surrounding cells hold every pair within r_c);
+//   pair cells  : ncell^3 cells of edge L/ncell >= 2 r_c / 3 (the cell-list
+//                 idea of Sec. 5.3), so that the 4 x 4 x 4 cells from the
+//                 cell of x - r_c on hold every point within r_c of x;
 //   node order  : nodes sorted by pair cell, so neighbouring threads share
 //                 cells in the pair and interpolation kernels.
 //

@@ -171,8 +171,9 @@ int resolve(const bs_params *in, bs_params *out) {
     if (r.ns_eta == 0) r.ns_eta = 1.0;
     if (!(r.ns_eta > 0)) return bad("ns_eta must be positive");
     if (r.fft_mode < BS_FFT_AUTO || r.fft_mode > BS_FFT_PRUNED) return bad("unknown fft_mode");
-    if (r.fft_mode == BS_FFT_PRUNED && (r.grid_n & (r.grid_n - 1)) != 0)
-        return bad("BS_FFT_PRUNED needs grid_n a power of two");
+    if (r.fft_mode == BS_FFT_PRUNED &&
+        !pruned_fft_ok(r.grid_n, r.precision == BS_FP32_MIXED ? 8 : 16))
+        return bad("BS_FFT_PRUNED needs grid_n a power of two (at most 512 in float64)");
     if (r.beta == 0) r.beta = beta_from_tol(r.tol);
     if (!(r.beta > 0)) return bad("beta must be positive");
     if (r.w == 0) r.w = width_from_tol(r.tol);
@@ -201,9 +202,12 @@ int resolve(const bs_params *in, bs_params *out) {
     double kap_max = kPi * r.K * r.w / r.grid_n;
     if (kap_max >= r.zeta)
         return set_error(nullptr, BS_EKB, "retained modes beyond the kernel's band (raise sigma)");
-    int nc = (int)std::floor(r.L / r.rcut);
-    if (nc < 3) nc = 1;
-    if (nc > 128) nc = 128;
+    // short-range cells of edge >= 2 r_c / 3: the points within r_c of any
+    // target lie in a 4 x 4 x 4 block of cells (one cell when fewer than 4
+    // fit along an axis)
+    int nc = (int)std::floor(3.0 * r.L / (2.0 * r.rcut * (1.0 + 1e-6)));
+    if (nc < 4) nc = 1;
+    if (nc > 160) nc = 160;
     r.ncell = nc;
     *out = r;
     return BS_OK;
@@ -311,20 +315,24 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
         hipfftSetStream(P->fft_inv, P->stream) != HIPFFT_SUCCESS)
         return fail(set_error(P, BS_EDEVICE, "hipfftSetStream failed"));
     // pruned transforms: twiddles exp(-+2 pi i k / n), k < n/2, from float64
-    P->pruned = r.fft_mode == BS_FFT_PRUNED && pruned_fft_ok(P->n);
+    // automatic choice: the pruned transforms win from 128^3 up (measured);
+    // hipFFT on smaller grids, where launch latency dominates
+    P->pruned = r.fft_mode == BS_FFT_PRUNED ||
+                (r.fft_mode == BS_FFT_AUTO && P->n >= 128 && pruned_fft_ok(P->n, 2 * P->real_size));
     if (P->pruned) {
         const size_t cs = 2 * P->real_size, K1 = r.K + 1, NY = 2 * r.K + 1;
-        pruned_batches(P->n, cs, &P->fft_kb, &P->fft_kz);
-        if ((rc = ensure<char>(P, P->fft_tw, n * cs)) ||
+        pruned_batches(P->n, cs, &P->fft_rb, &P->fft_kb, &P->fft_kz);
+        if ((rc = ensure<char>(P, P->fft_tw, 2 * n * cs)) ||
             (rc = ensure<char>(P, P->fft_A, 3 * n * n * K1 * cs)) ||
             (rc = ensure<char>(P, P->fft_B, 3 * NY * n * K1 * cs)))
             return fail(rc);
-        std::vector<double> tw(2 * n);
-        for (size_t k = 0; k < n / 2; k++) {
+        // [n] exp(-2 pi i k / n), then [n] exp(+2 pi i k / n)
+        std::vector<double> tw(4 * n);
+        for (size_t k = 0; k < n; k++) {
             const double ang = 2.0 * kPi * (double)k / (double)n;
             const double c = cos(ang), sn = sin(ang);
-            tw[2 * k] = c; tw[2 * k + 1] = -sn;                    // forward
-            tw[n + 2 * k] = c; tw[n + 2 * k + 1] = sn;             // inverse
+            tw[2 * k] = c; tw[2 * k + 1] = -sn;
+            tw[2 * n + 2 * k] = c; tw[2 * n + 2 * k + 1] = sn;
         }
         if (P->fp32) {
             std::vector<float> tf(tw.begin(), tw.end());

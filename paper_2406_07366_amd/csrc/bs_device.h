@@ -47,6 +47,15 @@ __device__ __forceinline__ int prev_node_d(const int *off, const int *fil, int j
     return (j > off[f]) ? j - 1 : off[f + 1] - 1;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, so blocks b, b+8,
+// b+16, ... run on one XCD.  With the grid launched as 8 * per blocks, this
+// maps them to the consecutive logical indices [xcd * per, (xcd + 1) * per),
+// so neighbouring logical blocks share an L2.  Indices >= the real count
+// must exit (uniformly over the block).
+__device__ __forceinline__ int xcd_block(int per) {
+    return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
 // counter[key] += 1 for every active lane, with one atomic per distinct key
 // in the wavefront: lanes sharing a key form a group, whose lowest lane adds
 // the group size.  With RET, returns the counter's value before the lane's own

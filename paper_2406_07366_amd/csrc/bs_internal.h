@@ -50,10 +50,10 @@ struct bs_plan_s {
     bs::DBuf spec;          // [3][n][n][n/2+1] complex
     bs::DBuf deconv;        // [K+1] float64: 1 / F(m)^2 per axis
     bs::DBuf fftwork;
-    // pruned transforms (power-of-two grids): twiddles [n/2 forward][n/2
-    // inverse], A [3][n][n][K+1] and B [3][2K+1][n][K+1] complex
+    // pruned transforms (power-of-two grids): twiddles [n forward][n
+    // inverse], A [3][n][n][K+1] and B [3][2K+1][n][K+1] complex; batch sizes
     bool pruned = false;
-    int fft_kb = 1, fft_kz = 1;
+    int fft_rb = 1, fft_kb = 1, fft_kz = 1;
     bs::DBuf fft_tw, fft_A, fft_B;
 
     // short-range cell list
@@ -137,8 +137,8 @@ int fft_forward(bs_plan_t p);
 int fft_inverse(bs_plan_t p);
 
 // fft.hip
-bool pruned_fft_ok(int n);
-void pruned_batches(int n, size_t csize, int *kb, int *kz);
+bool pruned_fft_ok(int n, size_t csize);
+void pruned_batches(int n, size_t csize, int *rb, int *kb, int *kz);
 void pruned_forward(bs_plan_t p);
 void pruned_spectral_op(bs_plan_t p, int psi);
 void pruned_inverse(bs_plan_t p);

@@ -15,12 +15,14 @@
 // exp(-2 pi i j m / n), inverse exp(+2 pi i j m / n), no scaling (the
 // spectral operator carries 1/L^3 and the deconvolution).
 //
-// Each workgroup transforms a batch of sequences held in LDS with element j
-// of sequence s at buf[j * nseq + s] (sequence index fastest, so the lanes of
-// one butterfly step touch consecutive words).  Forward transforms are
-// radix-2 decimation in time (bit-reversed input, natural output); inverse
-// transforms are decimation in frequency (natural input, bit-reversed
-// output), so no reordering pass is needed.
+// Each workgroup transforms a batch of nseq sequences by a Stockham autosort
+// FFT (natural order in and out): passes of radix 16, 8, 4 or 2 done in
+// registers, one item per thread and pass, twiddle factors from a
+// full-circle table.  The first pass reads its elements straight from global
+// memory and the last writes straight to it; passes in between exchange
+// through one LDS buffer with element j of sequence s at buf[j * pitch + s]
+// (pitch = nseq + 1, odd, so strided accesses spread over the banks).  A
+// 256-point transform (16 x 16) therefore touches LDS once each way.
 #include "bs_internal.h"
 #include "bs_device.h"
 
@@ -30,206 +32,291 @@ template <typename R> struct Cx;
 template <> struct Cx<float> { typedef float2 T; };
 template <> struct Cx<double> { typedef double2 T; };
 
-__device__ __forceinline__ int bitrev(int j, int logn) {
-    return (int)(__brev((unsigned)j) >> (32 - logn));
-}
+// cos and sin of 2 pi m / 16
+__device__ constexpr double kCos16[16] = {
+    1.0, 0.92387953251128676, 0.70710678118654752, 0.38268343236508977,
+    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128676,
+    -1.0, -0.92387953251128676, -0.70710678118654752, -0.38268343236508977,
+    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128676};
+__device__ constexpr double kSin16[16] = {
+    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128676,
+    1.0, 0.92387953251128676, 0.70710678118654752, 0.38268343236508977,
+    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128676,
+    -1.0, -0.92387953251128676, -0.70710678118654752, -0.38268343236508977};
 
-// bit-reversed input -> natural output; tw[k] = exp(-2 pi i k / n), k < n/2
-template <typename C>
-__device__ void fft_dit(C *buf, int logn, int nseq, const C *__restrict__ tw) {
-    const int hn = 1 << (logn - 1);
-    for (int s = 1; s <= logn; s++) {
-        const int lh = s - 1, half = 1 << lh, tsh = logn - s;
-        for (int b = threadIdx.x; b < nseq * hn; b += blockDim.x) {
-            const int seq = b % nseq, k = b / nseq;
-            const int j = k & (half - 1), i0 = ((k >> lh) << (lh + 1)) + j, i1 = i0 + half;
-            const C w = tw[j << tsh];
-            C *p0 = buf + i0 * nseq + seq, *p1 = buf + i1 * nseq + seq;
-            const C a = *p0, v = *p1;
-            const C t = {w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x};
-            *p0 = C{a.x + t.x, a.y + t.y};
-            *p1 = C{a.x - t.x, a.y - t.y};
+// In-register DFT of size R <= 16 (sgn -1 forward, +1 inverse): radix-2
+// decimation in time with the bit reversal resolved at compile time.
+template <int R, typename C, typename T>
+__device__ __forceinline__ void dft_regs(C (&v)[R], T sgn) {
+    constexpr int LR = R == 2 ? 1 : (R == 4 ? 2 : (R == 8 ? 3 : 4));
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+        int j = 0;
+#pragma unroll
+        for (int bb = 0; bb < LR; bb++)
+            if (i & (1 << bb)) j |= 1 << (LR - 1 - bb);
+        if (j > i) {
+            const C t = v[i];
+            v[i] = v[j];
+            v[j] = t;
         }
-        __syncthreads();
+    }
+#pragma unroll
+    for (int half = 1; half < R; half <<= 1) {
+#pragma unroll
+        for (int k = 0; k < R; k += 2 * half) {
+#pragma unroll
+            for (int j = 0; j < half; j++) {
+                const int m = j * (8 / half);   // angle 2 pi j / (2 half) = 2 pi m / 16
+                const T c = (T)kCos16[m], s = sgn * (T)kSin16[m];
+                const C bq = v[k + j + half], a = v[k + j];
+                const C t = C{c * bq.x - s * bq.y, c * bq.y + s * bq.x};
+                v[k + j] = C{a.x + t.x, a.y + t.y};
+                v[k + j + half] = C{a.x - t.x, a.y - t.y};
+            }
+        }
     }
 }
 
-// natural input -> bit-reversed output; tw[k] = exp(+2 pi i k / n), k < n/2
-template <typename C>
-__device__ void fft_dif(C *buf, int logn, int nseq, const C *__restrict__ tw) {
-    const int hn = 1 << (logn - 1);
-    for (int s = logn; s >= 1; s--) {
-        const int lh = s - 1, half = 1 << lh, tsh = logn - s;
-        for (int b = threadIdx.x; b < nseq * hn; b += blockDim.x) {
-            const int seq = b % nseq, k = b / nseq;
-            const int j = k & (half - 1), i0 = ((k >> lh) << (lh + 1)) + j, i1 = i0 + half;
-            const C w = tw[j << tsh];
-            C *p0 = buf + i0 * nseq + seq, *p1 = buf + i1 * nseq + seq;
-            const C a = *p0, v = *p1;
-            const C d = {a.x - v.x, a.y - v.y};
-            *p0 = C{a.x + v.x, a.y + v.y};
-            *p1 = C{w.x * d.x - w.y * d.y, w.x * d.y + w.y * d.x};
+// Radix plan of a length-2^logn transform: passes of radix at most 16,
+// balanced (16 = 16, 32 = 8.4, 64 = 8.8, 128 = 16.8, 256 = 16.16,
+// 512 = 8.8.8, 1024 = 16.8.8).  Returns the number of passes.
+__host__ __device__ inline int fft_plan(int logn, int *lr) {
+    int np = 0, rem = logn;
+    while (rem > 0) {
+        const int passes = (rem + 3) / 4;
+        const int l = (rem + passes - 1) / passes;
+        lr[np++] = l;
+        rem -= l;
+    }
+    return np;
+}
+
+// items (threads) per sequence in the pass with the smallest radix
+__host__ __device__ inline int fft_max_nj(int logn) {
+    int lr[4];
+    const int np = fft_plan(logn, lr);
+    int mn = 4;
+    for (int p = 0; p < np; p++) mn = lr[p] < mn ? lr[p] : mn;
+    return (1 << logn) >> mn;
+}
+
+// One radix-R Stockham pass over nseq sequences of length n = nj R (Ns is
+// the product of the radices of the passes before; tw[k] = exp(sgn 2 pi i
+// k / n)).  Thread t owns item (s, j): s = t / nj, j = t % nj when JFAST
+// (lanes along the sequence), else s = t % nseq, j = t / nseq (lanes across
+// sequences).  It reads elements j + r nj (from load() in the first pass,
+// else from LDS), applies the twiddles and an in-register DFT, and writes
+// elements (j - j mod Ns) R + j mod Ns + r Ns (to store() in the last pass,
+// else to LDS).  One LDS buffer: every read is done before any write.
+template <int R, bool JFAST, typename C, typename T, typename Load, typename Store>
+__device__ __forceinline__ void fft_pass(bool first, bool last, int n, int Ns, int nseq,
+                                         int pitch, C *buf, const C *__restrict__ tw, T sgn,
+                                         Load &load, Store &store) {
+    const int nj = n / R;
+    const int t = threadIdx.x;
+    const bool act = t < nj * nseq;
+    const int s = JFAST ? t / nj : t % nseq, j = JFAST ? t % nj : t / nseq;
+    const int jm = j & (Ns - 1);
+    C v[R];
+    if (act) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int e = j + r * nj;
+            v[r] = first ? load(s, e) : buf[e * pitch + s];
         }
-        __syncthreads();
+        if (jm != 0) {
+            const int step = n / (Ns * R);
+#pragma unroll
+            for (int r = 1; r < R; r++) {
+                const C w = tw[jm * r * step];
+                const C u = v[r];
+                v[r] = C{w.x * u.x - w.y * u.y, w.x * u.y + w.y * u.x};
+            }
+        }
+        dft_regs<R>(v, sgn);
+    }
+    __syncthreads();
+    if (act) {
+        const int d0 = (j - jm) * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int e = d0 + r * Ns;
+            if (last) store(s, e, v[r]);
+            else buf[e * pitch + s] = v[r];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool JFAST, typename C, typename T, typename Load, typename Store>
+__device__ void fft_run(int logn, int nseq, int pitch, C *buf, const C *__restrict__ tw, T sgn,
+                        Load load, Store store) {
+    int lr[4];
+    const int np = fft_plan(logn, lr), n = 1 << logn;
+    int Ns = 1;
+    for (int p = 0; p < np; p++) {
+        const bool first = p == 0, last = p == np - 1;
+        switch (lr[p]) {
+            case 1: fft_pass<2, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
+            case 2: fft_pass<4, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
+            case 3: fft_pass<8, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
+            default: fft_pass<16, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
+        }
+        Ns <<= lr[p];
     }
 }
 
-constexpr int kFftLdsBytes = 49152;   // LDS per workgroup for one batch
-constexpr int kFftThreads = 256;
+constexpr int kFftMaxThreads = 512;
+constexpr int kFftLds = 65536;        // LDS per workgroup, at most
 
 // ---------------------------------------------------------------- x pass
-// batch of RB rows (c, z, y); forward: keep modes 0..K
+// nseq rows (c, z, y) per workgroup; forward: keep modes 0..K
 template <typename R>
-__global__ __launch_bounds__(kFftThreads) void k_fft_x_fwd(int logn, int nrows, int K1,
-                                                         const R *__restrict__ grid,
-                                                         const typename Cx<R>::T *__restrict__ tw,
-                                                         typename Cx<R>::T *__restrict__ A) {
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int logn, int nrows, int K1,
+                                                            int nseq, int per,
+                                                            const R *__restrict__ grid,
+                                                            const typename Cx<R>::T *__restrict__ tw,
+                                                            typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
     C *buf = (C *)smem;
-    const int n = 1 << logn, RB = kFftLdsBytes / (int)sizeof(C) / n;
-    const int row0 = blockIdx.x * RB;
-    const int nr = nrows - row0 < RB ? nrows - row0 : RB;
-    for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
-        const int r = i >> logn, j = i & (n - 1);
-        const R v = r < nr ? grid[(size_t)(row0 + r) * n + j] : (R)0;
-        buf[bitrev(j, logn) * RB + r] = C{v, (R)0};
-    }
-    __syncthreads();
-    fft_dit(buf, logn, RB, tw);
-    for (int i = threadIdx.x; i < nr * K1; i += blockDim.x) {
-        const int r = i / K1, m = i - r * K1;
-        A[(size_t)(row0 + r) * K1 + m] = buf[m * RB + r];
-    }
+    const int n = 1 << logn;
+    const int bid = xcd_block(per), nb = (nrows + nseq - 1) / nseq;
+    if (bid >= nb) return;
+    const int row0 = bid * nseq;
+    auto load = [&](int s, int e) {
+        const int row = row0 + s;
+        return C{row < nrows ? grid[(size_t)row * n + e] : (R)0, (R)0};
+    };
+    auto store = [&](int s, int e, C v) {
+        const int row = row0 + s;
+        if (e < K1 && row < nrows) A[(size_t)row * K1 + e] = v;
+    };
+    fft_run<true>(logn, nseq, nseq + 1, buf, tw, (R)-1, load, store);
 }
 
 // inverse: modes 0..K of each row, Hermitian completion, real part out
 template <typename R>
-__global__ __launch_bounds__(kFftThreads) void k_fft_x_inv(int logn, int nrows, int K1,
-                                                         const typename Cx<R>::T *__restrict__ A,
-                                                         const typename Cx<R>::T *__restrict__ tw,
-                                                         R *__restrict__ grid) {
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int logn, int nrows, int K1,
+                                                            int nseq, int per,
+                                                            const typename Cx<R>::T *__restrict__ A,
+                                                            const typename Cx<R>::T *__restrict__ tw,
+                                                            R *__restrict__ grid) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
     C *buf = (C *)smem;
-    const int n = 1 << logn, RB = kFftLdsBytes / (int)sizeof(C) / n;
-    const int row0 = blockIdx.x * RB;
-    const int nr = nrows - row0 < RB ? nrows - row0 : RB;
-    for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
-        const int r = i % RB, m = i / RB;
+    const int n = 1 << logn;
+    const int bid = xcd_block(per), nb = (nrows + nseq - 1) / nseq;
+    if (bid >= nb) return;
+    const int row0 = bid * nseq;
+    auto load = [&](int s, int e) {
+        const int row = row0 + s;
         C v = C{(R)0, (R)0};
-        if (r < nr) {
-            if (m < K1) v = A[(size_t)(row0 + r) * K1 + m];
-            else if (n - m < K1) {
-                const C u = A[(size_t)(row0 + r) * K1 + (n - m)];
+        if (row < nrows) {
+            if (e < K1) v = A[(size_t)row * K1 + e];
+            else if (n - e < K1) {
+                const C u = A[(size_t)row * K1 + (n - e)];
                 v = C{u.x, -u.y};
             }
         }
-        buf[i] = v;
-    }
-    __syncthreads();
-    fft_dif(buf, logn, RB, tw);
-    for (int i = threadIdx.x; i < nr * n; i += blockDim.x) {
-        const int r = i >> logn, j = i & (n - 1);
-        grid[(size_t)(row0 + r) * n + j] = buf[bitrev(j, logn) * RB + r].x;
-    }
+        return v;
+    };
+    auto store = [&](int s, int e, C v) {
+        const int row = row0 + s;
+        if (row < nrows) grid[(size_t)row * n + e] = v.x;
+    };
+    fft_run<true>(logn, nseq, nseq + 1, buf, tw, (R)1, load, store);
 }
 
 // ---------------------------------------------------------------- y pass
-// one workgroup per (c, z) and group of KB columns mx
+// one workgroup per (c, z) and group of nseq columns mx
 template <typename R>
-__global__ __launch_bounds__(kFftThreads) void k_fft_y_fwd(int logn, int K, int KB,
-                                                         const typename Cx<R>::T *__restrict__ A,
-                                                         const typename Cx<R>::T *__restrict__ tw,
-                                                         typename Cx<R>::T *__restrict__ B) {
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int logn, int K, int nseq, int per,
+                                                            const typename Cx<R>::T *__restrict__ A,
+                                                            const typename Cx<R>::T *__restrict__ tw,
+                                                            typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
     C *buf = (C *)smem;
     const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1;
-    const int ngrp = (K1 + KB - 1) / KB;
-    const int g = blockIdx.x % ngrp, cz = blockIdx.x / ngrp;   // cz = c * n + z
+    const int ngrp = (K1 + nseq - 1) / nseq;
+    const int bid = xcd_block(per);
+    if (bid >= 3 * n * ngrp) return;
+    const int g = bid % ngrp, cz = bid / ngrp;   // cz = c * n + z
     const int c = cz >> logn, z = cz & (n - 1);
-    const int kx0 = g * KB;
-    for (int i = threadIdx.x; i < n * KB; i += blockDim.x) {
-        const int y = i / KB, q = i - y * KB;
-        const int kx = kx0 + q;
-        buf[bitrev(y, logn) * KB + q] =
-            kx < K1 ? A[((size_t)cz * n + y) * K1 + kx] : C{(R)0, (R)0};
-    }
-    __syncthreads();
-    fft_dit(buf, logn, KB, tw);
-    for (int i = threadIdx.x; i < NY * KB; i += blockDim.x) {
-        const int myp = i / KB, q = i - myp * KB;
-        const int kx = kx0 + q;
-        if (kx >= K1) continue;
-        int y = myp - K;
-        if (y < 0) y += n;
-        B[(((size_t)c * NY + myp) * n + z) * K1 + kx] = buf[y * KB + q];
-    }
+    const int kx0 = g * nseq;
+    auto load = [&](int s, int e) {
+        const int kx = kx0 + s;
+        return kx < K1 ? A[((size_t)cz * n + e) * K1 + kx] : C{(R)0, (R)0};
+    };
+    auto store = [&](int s, int e, C v) {
+        const int kx = kx0 + s, my = e <= n / 2 ? e : e - n;
+        if (kx < K1 && my >= -K && my <= K)
+            B[(((size_t)c * NY + (my + K)) * n + z) * K1 + kx] = v;
+    };
+    fft_run<false>(logn, nseq, nseq + 1, buf, tw, (R)-1, load, store);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kFftThreads) void k_fft_y_inv(int logn, int K, int KB,
-                                                         const typename Cx<R>::T *__restrict__ B,
-                                                         const typename Cx<R>::T *__restrict__ tw,
-                                                         typename Cx<R>::T *__restrict__ A) {
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int logn, int K, int nseq, int per,
+                                                            const typename Cx<R>::T *__restrict__ B,
+                                                            const typename Cx<R>::T *__restrict__ tw,
+                                                            typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
     C *buf = (C *)smem;
     const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1;
-    const int ngrp = (K1 + KB - 1) / KB;
-    const int g = blockIdx.x % ngrp, cz = blockIdx.x / ngrp;
+    const int ngrp = (K1 + nseq - 1) / nseq;
+    const int bid = xcd_block(per);
+    if (bid >= 3 * n * ngrp) return;
+    const int g = bid % ngrp, cz = bid / ngrp;
     const int c = cz >> logn, z = cz & (n - 1);
-    const int kx0 = g * KB;
-    for (int i = threadIdx.x; i < n * KB; i += blockDim.x) {
-        const int y = i / KB, q = i - y * KB;
-        const int kx = kx0 + q;
-        const int my = y <= n / 2 ? y : y - n;
+    const int kx0 = g * nseq;
+    auto load = [&](int s, int e) {
+        const int kx = kx0 + s, my = e <= n / 2 ? e : e - n;
         C v = C{(R)0, (R)0};
         if (kx < K1 && my >= -K && my <= K)
             v = B[(((size_t)c * NY + (my + K)) * n + z) * K1 + kx];
-        buf[i] = v;
-    }
-    __syncthreads();
-    fft_dif(buf, logn, KB, tw);
-    for (int i = threadIdx.x; i < n * KB; i += blockDim.x) {
-        const int y = i / KB, q = i - y * KB;
-        const int kx = kx0 + q;
-        if (kx < K1) A[((size_t)cz * n + y) * K1 + kx] = buf[bitrev(y, logn) * KB + q];
-    }
+        return v;
+    };
+    auto store = [&](int s, int e, C v) {
+        const int kx = kx0 + s;
+        if (kx < K1) A[((size_t)cz * n + e) * K1 + kx] = v;
+    };
+    fft_run<false>(logn, nseq, nseq + 1, buf, tw, (R)1, load, store);
 }
 
 // ---------------------------------------------------------------- z pass
 // one workgroup per (my, group of KZ columns mx): the three components'
-// z-columns, forward FFT, spectral operator, inverse FFT, written back.
-// Sequence s = c * KZ + q; element mz of it at buf[mz * 3KZ + s].
+// z-columns (sequence s = c KZ + q), forward FFT into LDS, spectral operator,
+// inverse FFT from LDS, written back.
 template <typename R>
-__global__ __launch_bounds__(kFftThreads) void k_fft_z_spectral(
-    int logn, int K, int KZ, int psi, double k0, double inv4a2, double invV,
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
+    int logn, int K, int KZ, int per, int psi, double k0, double inv4a2, double invV,
     const double *__restrict__ dec2, const typename Cx<R>::T *__restrict__ twf,
     const typename Cx<R>::T *__restrict__ twi, typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
     C *buf = (C *)smem;
-    const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1, S = 3 * KZ;
+    const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1, S = 3 * KZ, pitch = S + 1;
     const int ngrp = (K1 + KZ - 1) / KZ;
-    const int g = blockIdx.x % ngrp, myp = blockIdx.x / ngrp;
+    const int bid = xcd_block(per);
+    if (bid >= NY * ngrp) return;
+    const int g = bid % ngrp, myp = bid / ngrp;
     const int kx0 = g * KZ;
     const size_t cstride = (size_t)NY * n * K1;
-    for (int i = threadIdx.x; i < n * S; i += blockDim.x) {
-        const int z = i / S, s = i - z * S;
-        const int c = s / KZ, q = s - c * KZ;
-        const int kx = kx0 + q;
-        buf[bitrev(z, logn) * S + s] =
-            kx < K1 ? B[c * cstride + ((size_t)myp * n + z) * K1 + kx] : C{(R)0, (R)0};
-    }
-    __syncthreads();
-    fft_dit(buf, logn, S, twf);
+    auto gload = [&](int s, int e) {
+        const int c = s / KZ, kx = kx0 + (s - c * KZ);
+        return kx < K1 ? B[c * cstride + ((size_t)myp * n + e) * K1 + kx] : C{(R)0, (R)0};
+    };
+    auto lstore = [&](int s, int e, C v) { buf[e * pitch + s] = v; };
+    fft_run<false>(logn, S, pitch, buf, twf, (R)-1, gload, lstore);
     const int my = myp - K;
     for (int i = threadIdx.x; i < n * KZ; i += blockDim.x) {
         const int z = i / KZ, q = i - z * KZ;
         const int mx = kx0 + q, mz = z <= n / 2 ? z : z - n;
-        C *G0 = buf + z * S + q, *G1 = G0 + KZ, *G2 = G1 + KZ;
+        C *G0 = buf + z * pitch + q, *G1 = G0 + KZ, *G2 = G1 + KZ;
         const int ay = my < 0 ? -my : my, az = mz < 0 ? -mz : mz;
         if (mx >= K1 || az > K || (mx == 0 && my == 0 && mz == 0)) {
             *G0 = *G1 = *G2 = C{(R)0, (R)0};
@@ -256,17 +343,20 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_z_spectral(
         *G2 = C{-ci2, cr2};
     }
     __syncthreads();
-    fft_dif(buf, logn, S, twi);
-    for (int i = threadIdx.x; i < n * S; i += blockDim.x) {
-        const int z = i / S, s = i - z * S;
-        const int c = s / KZ, q = s - c * KZ;
-        const int kx = kx0 + q;
-        if (kx < K1) B[c * cstride + ((size_t)myp * n + z) * K1 + kx] = buf[bitrev(z, logn) * S + s];
-    }
+    auto lload = [&](int s, int e) { return buf[e * pitch + s]; };
+    auto gstore = [&](int s, int e, C v) {
+        const int c = s / KZ, kx = kx0 + (s - c * KZ);
+        if (kx < K1) B[c * cstride + ((size_t)myp * n + e) * K1 + kx] = v;
+    };
+    fft_run<false>(logn, S, pitch, buf, twi, (R)1, lload, gstore);
 }
 
 // --------------------------------------------------------------- launch
-bool pruned_fft_ok(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
+// power of two, and the z pass's smallest batch (3 columns + pad) fits LDS
+bool pruned_fft_ok(int n, size_t csize) {
+    return n >= 16 && n <= 1024 && (n & (n - 1)) == 0 && (size_t)n * 4 * csize < kFftLds &&
+           (size_t)3 * fft_max_nj(__builtin_ctz((unsigned)n)) <= kFftMaxThreads;
+}
 
 static int ilog2(int n) {
     int l = 0;
@@ -277,17 +367,15 @@ static int ilog2(int n) {
 template <typename R>
 static void pruned_fwd(bs_plan_t p) {
     typedef typename Cx<R>::T C;
-    const int n = p->n, logn = ilog2(n), K = p->prm.K, K1 = K + 1;
-    const int nrows = 3 * n * n;
-    const int RB = kFftLdsBytes / (int)sizeof(C) / n;
+    const int n = p->n, logn = ilog2(n), K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(logn);
+    const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twf = (const C *)p->fft_tw.p;
-    hipLaunchKernelGGL(k_fft_x_fwd<R>, dim3(ceil_div(nrows, RB)), dim3(kFftThreads),
-                       RB * n * sizeof(C), p->stream, logn, nrows, K1, (const R *)p->grid.p, twf,
+    const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
+    hipLaunchKernelGGL(k_fft_x_fwd<R>, dim3(8 * px), dim3(RB * mnj), n * (RB + 1) * sizeof(C),
+                       p->stream, logn, nrows, K1, RB, px, (const R *)p->grid.p, twf,
                        (C *)p->fft_A.p);
-    const int KB = p->fft_kb;
-    const int ngrp = ceil_div(K1, KB);
-    hipLaunchKernelGGL(k_fft_y_fwd<R>, dim3(3 * n * ngrp), dim3(kFftThreads), n * KB * sizeof(C),
-                       p->stream, logn, K, KB, (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
+    hipLaunchKernelGGL(k_fft_y_fwd<R>, dim3(8 * py), dim3(KB * mnj), n * (KB + 1) * sizeof(C),
+                       p->stream, logn, K, KB, py, (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
 }
 
 template <typename R>
@@ -297,25 +385,24 @@ static void pruned_spectral(bs_plan_t p, int psi) {
     const double L = p->prm.L;
     const double k0 = 2.0 * kPi / L, inv4a2 = 1.0 / (4.0 * p->prm.alpha * p->prm.alpha);
     const double *dec2 = (const double *)p->deconv.p + (p->prm.K + 1);
-    const C *twf = (const C *)p->fft_tw.p, *twi = twf + n / 2;
-    hipLaunchKernelGGL(k_fft_z_spectral<R>, dim3((2 * K + 1) * ceil_div(K1, KZ)),
-                       dim3(kFftThreads), 3 * n * KZ * sizeof(C), p->stream, logn, K, KZ, psi, k0,
-                       inv4a2, 1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
+    const C *twf = (const C *)p->fft_tw.p, *twi = twf + n;
+    const int pz = ceil_div((2 * K + 1) * ceil_div(K1, KZ), 8);
+    hipLaunchKernelGGL(k_fft_z_spectral<R>, dim3(8 * pz), dim3(3 * KZ * fft_max_nj(logn)),
+                       n * (3 * KZ + 1) * sizeof(C), p->stream, logn, K, KZ, pz, psi, k0, inv4a2,
+                       1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
 }
 
 template <typename R>
 static void pruned_inv(bs_plan_t p) {
     typedef typename Cx<R>::T C;
-    const int n = p->n, logn = ilog2(n), K = p->prm.K, K1 = K + 1;
-    const int nrows = 3 * n * n;
-    const int RB = kFftLdsBytes / (int)sizeof(C) / n;
-    const C *twi = (const C *)p->fft_tw.p + n / 2;
-    const int KB = p->fft_kb;
-    const int ngrp = ceil_div(K1, KB);
-    hipLaunchKernelGGL(k_fft_y_inv<R>, dim3(3 * n * ngrp), dim3(kFftThreads), n * KB * sizeof(C),
-                       p->stream, logn, K, KB, (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
-    hipLaunchKernelGGL(k_fft_x_inv<R>, dim3(ceil_div(nrows, RB)), dim3(kFftThreads),
-                       RB * n * sizeof(C), p->stream, logn, nrows, K1, (const C *)p->fft_A.p, twi,
+    const int n = p->n, logn = ilog2(n), K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(logn);
+    const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
+    const C *twi = (const C *)p->fft_tw.p + n;
+    const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
+    hipLaunchKernelGGL(k_fft_y_inv<R>, dim3(8 * py), dim3(KB * mnj), n * (KB + 1) * sizeof(C),
+                       p->stream, logn, K, KB, py, (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
+    hipLaunchKernelGGL(k_fft_x_inv<R>, dim3(8 * px), dim3(RB * mnj), n * (RB + 1) * sizeof(C),
+                       p->stream, logn, nrows, K1, RB, px, (const C *)p->fft_A.p, twi,
                        (R *)p->grid.p);
 }
 
@@ -329,13 +416,27 @@ void pruned_inverse(bs_plan_t p) {
     if (p->fp32) pruned_inv<float>(p); else pruned_inv<double>(p);
 }
 
-// batch sizes: columns per workgroup in the y pass (KB) and z pass (KZ), so
-// that one batch fills at most kFftLdsBytes of LDS
-void pruned_batches(int n, size_t csize, int *kb, int *kz) {
-    int b = (int)(kFftLdsBytes / (csize * n));
-    int z = (int)(kFftLdsBytes / (3 * csize * n));
-    *kb = b < 1 ? 1 : (b > 16 ? 16 : b);
-    *kz = z < 1 ? 1 : (z > 16 ? 16 : z);
+// Batch sizes: sequences per workgroup for the x and y passes (rb = kb, a
+// power of two) and columns for the z pass (kz, times 3 components): about
+// 256 threads of one item each (128 in float64), with the LDS buffer and its
+// padded pitch within kFftLds.
+static int pow2_floor(int v) {
+    int p = 1;
+    while (2 * p <= v) p *= 2;
+    return p;
+}
+
+void pruned_batches(int n, size_t csize, int *rb, int *kb, int *kz) {
+    const int logn = ilog2(n), mnj = fft_max_nj(logn);
+    const int threads = csize > 8 ? 128 : 256;
+    int b = threads / mnj;
+    const int lds = (int)(kFftLds / (csize * n)) - 1;
+    b = b < lds ? b : lds;
+    b = pow2_floor(b < 1 ? 1 : b);
+    *rb = b;
+    *kb = b;
+    const int z = b / 3;
+    *kz = z < 1 ? 1 : z;
 }
 
 }  // namespace bs

@@ -4,8 +4,8 @@
 //
 // A wavefront per target node, nodes processed in cell order so that
 // consecutive wavefronts read the same few cells.  For each quadrature point
-// of the 27 surrounding cells (or of every cell when fewer than 3 fit along
-// an axis):
+// of the 4 x 4 x 4 cells (edge >= 2 r_c / 3) from the cell of x - r_c on (or
+// of every cell when fewer than 4 fit along an axis):
 // r = s_q - s_i by minimum image (formed in float64), skip the 2Q points of
 // the two segments adjacent to the node, keep r < r_c, and add
 //   v:   g_sr(r) (r x q) / r^3,  g_sr = erfc(alpha r) + (2 alpha r/sqrt(pi)) e^{-alpha^2 r^2}
@@ -16,13 +16,13 @@
 
 namespace bs {
 
-// One wavefront (G = 64 lanes) per target node.  Lanes 0..26 hold one of
-// the 27 cells around the target; the cells' contents are enumerated as one
+// One wavefront (four on small inputs) per target node.  Each lane holds one of the
+// 4 x 4 x 4 cells around the target; the cells' contents are enumerated as one
 // flattened range, 64 candidates per step (every lane busy, independent
 // loads), each lane finding its cell by binary search over the wavefront's
 // prefix sums.  The partial sums are combined by a fixed xor-shuffle tree
 // (deterministic order).
-template <typename R, bool PSI, int G>
+template <typename R, bool PSI, int WPN>
 __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double rc, double alpha,
                                                const int *__restrict__ nperm,
                                                const double *__restrict__ x,
@@ -33,26 +33,32 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
                                                const R *__restrict__ schg,
                                                const int *__restrict__ sseg,
                                                double *__restrict__ out) {
-    static_assert(G == 64, "one wavefront per target");
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = gid / G, lane = gid % G;
-    if (t >= N) return;   // whole wavefronts exit together
+    static_assert(WPN == 1 || WPN == 4, "1 or 4 wavefronts per target");
+    __shared__ R red[4][3];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // WPN = 1: four targets per workgroup; WPN = 4: one target, its
+    // candidate chunks dealt round-robin to the four wavefronts
+    const int t = WPN == 1 ? blockIdx.x * 4 + wave : blockIdx.x;
+    const int part = WPN == 1 ? 0 : wave;
+    if (t >= N) return;   // whole wavefronts (WPN = 1) or the whole workgroup
     const int o = nperm[t];
     const int ip = prev_node_d(off, fil, o);
     const double xi0 = x[3 * o], xi1 = x[3 * o + 1], xi2 = x[3 * o + 2];
     const double invL = 1.0 / L;
-    const int ncell = nc >= 3 ? 27 : 1;
+    // lanes 0..63: the 4 x 4 x 4 cells from the cell of x - r_c on (cells of
+    // edge h >= 2 r_c / 3 hold every point within r_c in 4 per axis)
+    const int ncell = nc >= 4 ? 64 : 1;
     int cs = 0, cn = 0;
     if (lane < ncell) {
         int cidx = 0;
-        if (nc >= 3) {
+        if (nc >= 4) {
             const double ws[3] = {wrap_box(xi0, L), wrap_box(xi1, L), wrap_box(xi2, L)};
-            const int dd[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+            const int dd[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
             int c[3];
             for (int q = 0; q < 3; q++) {
-                int v = (int)(ws[q] * invL * nc);
-                v = (v < 0 ? 0 : (v >= nc ? nc - 1 : v)) + dd[q];
-                c[q] = v < 0 ? v + nc : (v >= nc ? v - nc : v);
+                int v = (int)floor((ws[q] - rc) * invL * nc) + dd[q];
+                v %= nc;
+                c[q] = v < 0 ? v + nc : v;
             }
             cidx = (c[2] * nc + c[1]) * nc + c[0];
         }
@@ -69,10 +75,10 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
     const R rc2 = (R)(rc * rc), a = (R)alpha;
     const R two_over_sqrtpi = (R)1.12837916709551257389615890312154517;
     R acc0 = 0, acc1 = 0, acc2 = 0;
-    for (int q0 = 0; q0 < total; q0 += 64) {
+    for (int q0 = part * 64; q0 < total; q0 += 64 * WPN) {
         const int q = q0 + lane;
         int c = 0;
-        for (int step = 16; step > 0; step >>= 1) {
+        for (int step = 32; step > 0; step >>= 1) {
             const int tc = c + step;
             const int pv = __shfl(excl, tc < ncell ? tc : ncell - 1);
             if (tc < ncell && pv <= q) c = tc;
@@ -106,10 +112,18 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
         }
     }
 #pragma unroll
-    for (int m = G / 2; m > 0; m >>= 1) {
-        acc0 += __shfl_xor(acc0, m, G);
-        acc1 += __shfl_xor(acc1, m, G);
-        acc2 += __shfl_xor(acc2, m, G);
+    for (int m = 32; m > 0; m >>= 1) {
+        acc0 += __shfl_xor(acc0, m, 64);
+        acc1 += __shfl_xor(acc1, m, 64);
+        acc2 += __shfl_xor(acc2, m, 64);
+    }
+    if (WPN > 1) {
+        if (lane == 0) { red[wave][0] = acc0; red[wave][1] = acc1; red[wave][2] = acc2; }
+        __syncthreads();
+        if (wave != 0) return;
+        acc0 = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+        acc1 = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+        acc2 = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
     }
     if (lane == 0) {
         const double inv4pi = 1.0 / (4.0 * kPi);
@@ -119,25 +133,35 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
     }
 }
 
-constexpr int kPairLanes = 64;
+// targets below this count get four wavefronts each (latency hiding on
+// small inputs)
+constexpr int kPairSplitNodes = 16384;
 
-void launch_pairs(bs_plan_t p, int psi, double *out) {
+template <typename R, bool PSI>
+static void pairs_r(bs_plan_t p, double *out) {
     const int N = (int)p->N;
-    dim3 grid(ceil_div((int64_t)N * kPairLanes, 256)), block(256);
+    const bool split = N < kPairSplitNodes;
+    dim3 grid(split ? N : ceil_div(N, 4)), block(256);
     const double L = p->prm.L, rc = p->prm.rcut, alpha = p->prm.alpha;
     const int *nperm = (const int *)p->nd_perm.p, *off = (const int *)p->d_off.p,
               *fil = (const int *)p->d_fil.p, *cs = (const int *)p->pq_start.p,
               *seg = (const int *)p->pq_seg.p;
     const double *x = (const double *)p->d_x.p;
     const double4 *sp = (const double4 *)p->pq_pos.p;
+    const R *q = (const R *)p->pq_chg.p;
+    if (split)
+        hipLaunchKernelGGL((k_pairs<R, PSI, 4>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
+                           nperm, x, off, fil, cs, sp, q, seg, out);
+    else
+        hipLaunchKernelGGL((k_pairs<R, PSI, 1>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
+                           nperm, x, off, fil, cs, sp, q, seg, out);
+}
+
+void launch_pairs(bs_plan_t p, int psi, double *out) {
     if (p->fp32) {
-        const float *q = (const float *)p->pq_chg.p;
-        if (psi) hipLaunchKernelGGL((k_pairs<float, true, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
-        else hipLaunchKernelGGL((k_pairs<float, false, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        if (psi) pairs_r<float, true>(p, out); else pairs_r<float, false>(p, out);
     } else {
-        const double *q = (const double *)p->pq_chg.p;
-        if (psi) hipLaunchKernelGGL((k_pairs<double, true, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
-        else hipLaunchKernelGGL((k_pairs<double, false, kPairLanes>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha, nperm, x, off, fil, cs, sp, q, seg, out);
+        if (psi) pairs_r<double, true>(p, out); else pairs_r<double, false>(p, out);
     }
 }
 

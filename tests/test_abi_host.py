@@ -58,11 +58,12 @@ def test_derived_parameters_of_the_workloads():
     assert math.isclose(r.alpha, 10 / 7, rel_tol=1e-14)          # K (2pi/L)/(2 beta)
     assert math.isclose(r.rcut, r.beta / r.alpha, rel_tol=1e-14)
     assert r.rcut <= L / 2
-    assert r.ncell == 1                                           # r_c > L/3
+    assert r.ncell == 1                                           # 3 L / (2 r_c) < 4
     # 40 ellipses: n = 64 -> K = 20
     r = B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64))
     assert (r.K, r.w) == (20, 8) and math.isclose(r.alpha, 20 / 7, rel_tol=1e-14)
-    assert r.ncell == 5
+    assert r.ncell == 7                                           # edge >= 2 r_c / 3
+    assert L / r.ncell >= 2 * r.rcut / 3
     # tangle: n = 256, tol 1e-5 -> beta 3.5 (next accurate-enough row), w = 7
     r = B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-5, grid_n=256))
     assert (r.K, r.w, r.beta) == (84, 7, 3.5)
@@ -103,3 +104,9 @@ def test_pruned_transforms_need_a_power_of_two_grid():
     assert e.value.code == B.BS_EINVAL
     with pytest.raises(B.BsError):
         B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, fft_mode=7))
+    # two LDS buffers of the z pass must hold 3 columns + pad: float64 up to 512
+    B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-5, grid_n=1024, fft_mode=B.BS_FFT_PRUNED,
+                                   precision=B.BS_FP32_MIXED))
+    with pytest.raises(B.BsError):
+        B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-5, grid_n=1024,
+                                       fft_mode=B.BS_FFT_PRUNED))

@@ -1,9 +1,9 @@
 """CPU model of the pruned 3-D transforms (no GPU).
 
 Re-derives, in numpy with the kernels' own index arithmetic, that
-  * the in-place radix-2 decimation-in-time pass (bit-reversed input) gives
-    the forward DFT in natural order, and the decimation-in-frequency pass
-    (natural input) gives the inverse DFT in bit-reversed order;
+  * the Stockham passes (radix 16, 8, 4, 2 in registers, twiddles from a
+    full-circle table, balanced radices) give the forward and inverse DFT in
+    natural order;
   * the pruned chain  x r2c (modes 0..K) -> y (keep |my| <= K) -> z + spectral
     operator + inverse z -> zero-padded inverse y -> Hermitian c2r along x
     equals full transforms with every mode outside |m_i| <= K zeroed.
@@ -12,64 +12,68 @@ import numpy as np
 import pytest
 
 
-def bitrev(j, logn):
-    return int(format(j, f"0{logn}b")[::-1], 2)
-
-
 def tw(n, sign):
-    k = np.arange(n // 2)
-    return np.exp(sign * 2j * np.pi * k / n)
+    """Full-circle table: tw[k] = exp(sign 2 pi i k / n), k < n."""
+    return np.exp(sign * 2j * np.pi * np.arange(n) / n)
 
 
-def fft_dit(buf, logn, t):
-    """buf[j, s]: element j of sequence s (bit-reversed order on entry)."""
+def dft_regs(v, sign):
+    """Size-R DFT the way the kernel does it: bit-reversed radix-2 decimation
+    in time with twiddles exp(sign 2 pi i m / 16)."""
+    R = len(v)
+    LR = R.bit_length() - 1
+    v = [v[int(format(i, f"0{LR}b")[::-1], 2)] for i in range(R)]
+    half = 1
+    while half < R:
+        for k in range(0, R, 2 * half):
+            for j in range(half):
+                m = j * (8 // half)
+                w = np.exp(sign * 2j * np.pi * m / 16)
+                a, t = v[k + j], w * v[k + j + half]
+                v[k + j], v[k + j + half] = a + t, a - t
+        half *= 2
+    return v
+
+
+def stockham_pass(src, dst, n, R, Ns, t, sign):
+    """One radix-R pass; src/dst[j] is element j (a row over the batch)."""
+    nj = n // R
+    step = n // (Ns * R)
+    for j in range(nj):
+        v = [src[j + r * nj].copy() for r in range(R)]
+        jm = j % Ns
+        for r in range(1, R):
+            v[r] = v[r] * t[jm * r * step]
+        v = dft_regs(v, sign)
+        d0 = (j - jm) * R + jm
+        for r in range(R):
+            dst[d0 + r * Ns] = v[r]
+
+
+def fft_batch(buf, logn, t, sign):
+    """Passes of radix <= 16 chosen as the kernel does; returns the result."""
     n = 1 << logn
-    for s in range(1, logn + 1):
-        lh = s - 1
-        half = 1 << lh
-        tsh = logn - s
-        for k in range(n // 2):
-            j = k & (half - 1)
-            i0 = ((k >> lh) << (lh + 1)) + j
-            i1 = i0 + half
-            w = t[j << tsh]
-            a, v = buf[i0].copy(), buf[i1].copy()
-            buf[i0] = a + w * v
-            buf[i1] = a - w * v
+    a, b = buf.copy(), np.empty_like(buf)
+    Ns, rem = 1, logn
+    while rem > 0:
+        passes = (rem + 3) // 4
+        lr = (rem + passes - 1) // passes
+        stockham_pass(a, b, n, 1 << lr, Ns, t, sign)
+        a, b = b, a
+        Ns <<= lr
+        rem -= lr
+    return a
 
 
-def fft_dif(buf, logn, t):
-    n = 1 << logn
-    for s in range(logn, 0, -1):
-        lh = s - 1
-        half = 1 << lh
-        tsh = logn - s
-        for k in range(n // 2):
-            j = k & (half - 1)
-            i0 = ((k >> lh) << (lh + 1)) + j
-            i1 = i0 + half
-            w = t[j << tsh]
-            a, v = buf[i0].copy(), buf[i1].copy()
-            buf[i0] = a + v
-            buf[i1] = (a - v) * w
-
-
-@pytest.mark.parametrize("logn", [1, 3, 4, 6])
-def test_dit_and_dif_passes(logn):
+@pytest.mark.parametrize("logn", [1, 2, 3, 4, 5, 6, 7, 9])
+def test_stockham_batches(logn):
     n = 1 << logn
     rng = np.random.default_rng(logn)
     x = rng.normal(size=(n, 3)) + 1j * rng.normal(size=(n, 3))
-    b = np.empty_like(x)
-    for j in range(n):
-        b[bitrev(j, logn)] = x[j]
-    fft_dit(b, logn, tw(n, -1))
-    np.testing.assert_allclose(b, np.fft.fft(x, axis=0), rtol=1e-12, atol=1e-12)
-    b = x.copy()
-    fft_dif(b, logn, tw(n, +1))
-    out = np.empty_like(b)
-    for j in range(n):
-        out[j] = b[bitrev(j, logn)]
-    np.testing.assert_allclose(out, np.fft.ifft(x, axis=0) * n, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(fft_batch(x, logn, tw(n, -1), -1), np.fft.fft(x, axis=0),
+                               rtol=1e-11, atol=1e-11 * n)
+    np.testing.assert_allclose(fft_batch(x, logn, tw(n, +1), +1), np.fft.ifft(x, axis=0) * n,
+                               rtol=1e-11, atol=1e-11 * n)
 
 
 def spectral(G, mx, my, mz, K, op):
@@ -97,59 +101,45 @@ def test_pruned_chain_equals_masked_full_transforms(n, K):
     A = np.empty((3, n, n, K1), complex)
     for c in range(3):
         for z in range(n):
-            for y in range(n):
-                b = np.empty(n, complex)
-                for j in range(n):
-                    b[bitrev(j, logn)] = g[c, z, y, j]
-                fft_dit(b, logn, twf)
-                A[c, z, y] = b[:K1]
+            rows = g[c, z].T.astype(complex)           # [x][y]: element j, batch over y
+            A[c, z] = fft_batch(rows, logn, twf, -1)[:K1].T
     # y forward -> B[c][my+K][z][kx]
     B = np.empty((3, NY, n, K1), complex)
     for c in range(3):
         for z in range(n):
-            b = np.empty((n, K1), complex)
-            for y in range(n):
-                b[bitrev(y, logn)] = A[c, z, y]
-            fft_dit(b, logn, twf)
+            res = fft_batch(A[c, z], logn, twf, -1)      # [y][kx]
             for myp in range(NY):
-                B[c, myp, z] = b[(myp - K) % n]
-    # z forward, operator, z inverse (bit-reversed), per (my, kx)
+                B[c, myp, z] = res[(myp - K) % n]
+    # z forward, operator, z inverse, per (my, kx)
     for myp in range(NY):
-        b = np.empty((n, 3, K1), complex)
-        for z in range(n):
-            b[bitrev(z, logn)] = B[:, myp, z, :]
-        fft_dit(b, logn, twf)
+        buf = np.moveaxis(B[:, myp], 1, 0).copy()       # [z][c][kx]
+        res = fft_batch(buf, logn, twf, -1)
         for z in range(n):
             mz = z if z <= n // 2 else z - n
             for q in range(K1):
-                b[z, :, q] = spectral(b[z, :, q], q, myp - K, mz, K, op_curl)
-        fft_dif(b, logn, twi)
-        for z in range(n):
-            B[:, myp, z, :] = b[bitrev(z, logn)]
+                res[z, :, q] = spectral(res[z, :, q], q, myp - K, mz, K, op_curl)
+        out_z = fft_batch(res, logn, twi, +1)
+        B[:, myp] = np.moveaxis(out_z, 0, 1)
     # y inverse (zero padded) -> A[c][z][y][kx]
     for c in range(3):
         for z in range(n):
-            b = np.zeros((n, K1), complex)
+            buf = np.zeros((n, K1), complex)
             for y in range(n):
                 my = y if y <= n // 2 else y - n
                 if -K <= my <= K:
-                    b[y] = B[c, my + K, z]
-            fft_dif(b, logn, twi)
-            for y in range(n):
-                A[c, z, y] = b[bitrev(y, logn)]
+                    buf[y] = B[c, my + K, z]
+            A[c, z] = fft_batch(buf, logn, twi, +1)
     # x inverse: Hermitian completion, real part
     out = np.empty_like(g)
     for c in range(3):
         for z in range(n):
-            for y in range(n):
-                b = np.zeros(n, complex)
-                for m in range(n):
-                    if m < K1:
-                        b[m] = A[c, z, y, m]
-                    elif n - m < K1:
-                        b[m] = np.conj(A[c, z, y, n - m])
-                fft_dif(b, logn, twi)
-                out[c, z, y] = [b[bitrev(j, logn)].real for j in range(n)]
+            buf = np.zeros((n, n), complex)                # [m][y]
+            for m in range(n):
+                if m < K1:
+                    buf[m] = A[c, z, :, m]
+                elif n - m < K1:
+                    buf[m] = np.conj(A[c, z, :, n - m])
+            out[c, z] = fft_batch(buf, logn, twi, +1).real.T
     # reference: full r2c, the operator on the half space, full c2r
     G = np.fft.rfftn(g, axes=(1, 2, 3))           # [c][z][y][x half]
     V = np.zeros_like(G)

@@ -1,0 +1,42 @@
+"""CPU model of the short-range cell window (no GPU).
+
+Cells have edge h = L / nc >= 2 r_c / 3 (nc = floor(3L / (2 r_c (1 + 1e-6)))),
+and a target scans the 4 x 4 x 4 cells starting at the cell of x - r_c.  This
+re-derives, with the kernel's index arithmetic, that every point within r_c
+of the target (minimum image) is in one of those cells, and that the 64 cells
+are distinct whenever nc >= 4.
+"""
+import math
+
+import numpy as np
+import pytest
+
+
+def cell_of(v, L, nc):
+    w = v - L * np.floor(v / L)
+    return np.clip((w / L * nc).astype(int), 0, nc - 1)
+
+
+@pytest.mark.parametrize("rc", [0.144, 0.2917, 0.6, 1.225, 1.5])
+def test_every_point_within_rc_is_in_the_window(rc):
+    L = 2 * math.pi
+    nc = int(math.floor(3 * L / (2 * rc * (1 + 1e-6))))
+    if nc < 4:
+        pytest.skip("one cell holds every point")
+    assert L / nc >= 2 * rc / 3
+    rng = np.random.default_rng(int(rc * 1000))
+    pts = rng.uniform(0, L, (4000, 3))
+    targets = np.concatenate([rng.uniform(0, L, (200, 3)),
+                              rng.choice([0.0, L - 1e-12, rc, L - rc], (60, 3))])
+    pc = cell_of(pts, L, nc)
+    for x in targets:
+        xw = x - L * np.floor(x / L)
+        s = np.floor((xw - rc) / L * nc).astype(int)
+        window = {tuple((s + np.array([a, b, c])) % nc)
+                  for c in range(4) for b in range(4) for a in range(4)}
+        assert len(window) == 64
+        d = pts - x
+        d -= L * np.rint(d / L)
+        near = np.nonzero((d * d).sum(1) < rc * rc)[0]
+        for i in near:
+            assert tuple(pc[i]) in window
