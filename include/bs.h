@@ -88,7 +88,9 @@ typedef struct bs_plan_s *bs_plan_t;
  *   beta   from tol: the beta of the most accurate-enough row of the paper's
  *          Table 1 (tol 1e-3..1e-14 -> beta 2.0..5.5), i.e. the row with the
  *          largest tolerance <= tol;
- *   w      from tol: ceil(-log10(tol)/0.9) + 1 (NUFFT error ~10^(-0.9 w) at
+ *   w      from tol: Table 1's width at the table's own tolerances (4, 6,
+ *          8, ..., 16 for 1e-3, 1e-4, 1e-6, ..., 1e-14); at any other
+ *          tolerance ceil(-log10(tol)/0.9) + 1 (NUFFT error ~10^(-0.9 w) at
  *          sigma = 1.5, App. A, Fig. accuracy_nufft), clamped to [4, 16];
  *   alpha  from the grid: M = floor(grid_n / sigma) resolved modes per
  *          axis, K = floor((M-1)/2), k_max = 2 pi K / L = 2 beta alpha

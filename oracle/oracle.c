@@ -323,6 +323,65 @@ void or_local(const void *h, int64_t nt, const int64_t *tgt, double *v, double *
     }
 }
 
+/* Local terms with the local segments subdivided (Sec. 5.2): on each of the
+ * two segments next to node i, the fraction eps of its parameter interval
+ * that touches node i is the central portion, treated by the Taylor
+ * expansion (eq:BS_local, eq:streamfunction_local with l-, l+ the arc lengths
+ * of the two central portions); the rest of each segment is integrated with
+ * the unsplit kernels (eq:BS, eq:streamfunction_integral) by the 3-point
+ * Gauss-Legendre rule.  Arc lengths of the central portions use the same
+ * 3-point rule.  eps = 1 gives back or_local up to the rule used for l-, l+. */
+void or_local_sub(const void *h, double eps, int64_t nt, const int64_t *tgt, double *v,
+                  double *psi) {
+    const or_t *o = (const or_t *)h;
+    double g3h[4], g3w[4];
+    or_gl_rule(3, g3h, g3w);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nt; t++) {
+        int64_t i = tgt[t], jm = prev_node(o, i);
+        double gam = o->gamma[o->fil[i]];
+        const double *si = o->x + 3 * i, *sd = o->sd + 3 * i, *sdd = o->M + 3 * i;
+        double hm = o->dtau[jm], hp = o->dtau[i];
+        /* central portions: [hm (1-eps), hm] on segment jm, [0, eps hp] on segment i */
+        double lm = 0.0, lp = 0.0, d[3];
+        for (int k = 0; k < 3; k++) {
+            seg_eval(o, jm, hm * (1.0 - eps) + g3h[k] * eps * hm, 1, d);
+            lm += g3w[k] * eps * hm * norm3(d);
+            seg_eval(o, i, g3h[k] * eps * hp, 1, d);
+            lp += g3w[k] * eps * hp * norm3(d);
+        }
+        double lg = log(2.0 * sqrt(lm * lp) / o->a);
+        double sn = norm3(sd), b[3];
+        cross3(sd, sdd, b);
+        double vv[3], pp[3];
+        for (int c = 0; c < 3; c++) {
+            vv[c] = gam / (4 * OR_PI) * b[c] / (sn * sn * sn) * (lg - o->delta);
+            pp[c] = gam / (2 * OR_PI) * sd[c] / sn * (lg - (o->delta - 1.0));
+        }
+        /* remaining portions: [0, hm (1-eps)] on jm, [eps hp, hp] on i */
+        for (int side = 0; side < 2; side++) {
+            int64_t j = side ? i : jm;
+            double h0 = side ? eps * hp : 0.0, len = side ? (1.0 - eps) * hp : (1.0 - eps) * hm;
+            for (int k = 0; k < 3; k++) {
+                double x[3], sdq[3], r[3], rx[3];
+                seg_eval(o, j, h0 + g3h[k] * len, 0, x);
+                seg_eval(o, j, h0 + g3h[k] * len, 1, sdq);
+                for (int c = 0; c < 3; c++) r[c] = x[c] - si[c];
+                double rn = norm3(r), wq = gam * g3w[k] * len / (4 * OR_PI);
+                cross3(r, sdq, rx);
+                for (int c = 0; c < 3; c++) {
+                    vv[c] += wq * rx[c] / (rn * rn * rn);
+                    pp[c] += wq * sdq[c] / rn;
+                }
+            }
+        }
+        for (int c = 0; c < 3; c++) {
+            if (v) v[3 * t + c] = vv[c];
+            if (psi) psi[3 * t + c] = pp[c];
+        }
+    }
+}
+
 /* ------------------------------------------------- Ewald weight functions */
 /* g_sr = erfc(x) + 2x/sqrt(pi) exp(-x^2), g_lr = erf(x) - 2x/sqrt(pi) exp(-x^2)
  * (eq:ewald_derivative_weight_functions), x = alpha r.  For x < 0.5 g_lr is

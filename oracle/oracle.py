@@ -57,6 +57,8 @@ def lib():
         L.or_cyclic_tridiag.argtypes = [C.c_int64, _dp, _dp, _dp, _dp]
         for name in ("or_local",):
             getattr(L, name).argtypes = [C.c_void_p, C.c_int64, _ip, C.c_void_p, C.c_void_p]
+        L.or_local_sub.argtypes = [C.c_void_p, C.c_double, C.c_int64, _ip, C.c_void_p,
+                                   C.c_void_p]
         L.or_shortrange.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int64, _ip,
                                     C.c_void_p, C.c_void_p]
         L.or_selfcorr.argtypes = [C.c_void_p, C.c_double, C.c_int64, _ip, C.c_void_p, C.c_void_p]
@@ -185,6 +187,13 @@ class Oracle:
         lib().or_local(self._h, len(t), t, _ptr(v), _ptr(p))
         return v, p
 
+    def local_sub(self, eps, targets=None):
+        """Local terms with the local segments subdivided (Sec. 5.2)."""
+        t = self._tg(targets)
+        v = np.zeros((len(t), 3)); p = np.zeros((len(t), 3))
+        lib().or_local_sub(self._h, float(eps), len(t), t, _ptr(v), _ptr(p))
+        return v, p
+
     def shortrange(self, alpha, rc, targets=None, psi=True):
         t = self._tg(targets)
         v = np.zeros((len(t), 3)); p = np.zeros((len(t), 3)) if psi else None
@@ -216,9 +225,11 @@ class Oracle:
         lib().or_brute_images(self._h, int(K), len(t), t, v)
         return v
 
-    def ewald(self, alpha, rc, K, targets=None, psi=True, ns_eta=None, ns_tol=1e-13):
-        """Total v (and psi) = local + short + long - self (+ near-singular)."""
-        vl, pl = self.local(targets)
+    def ewald(self, alpha, rc, K, targets=None, psi=True, ns_eta=None, ns_tol=1e-13,
+              local_eps=None):
+        """Total v (and psi) = local + short + long - self (+ near-singular);
+        local_eps subdivides the local segments (Sec. 5.2)."""
+        vl, pl = self.local(targets) if local_eps is None else self.local_sub(local_eps, targets)
         vs, ps = self.shortrange(alpha, rc, targets, psi=psi)
         vL, pL = self.longrange(alpha, K, targets, psi=psi)
         vS, pS = self.selfcorr(alpha, targets)

@@ -134,9 +134,10 @@ static int launch_status(bs_plan_t p, const char *what) {
     return check_hip(p, hipGetLastError(), what);
 }
 
-// Table 1 of the paper: nominal tolerance -> beta.
+// Table 1 of the paper: nominal tolerance -> beta and kernel width w.
 static const double kTabTol[7] = {1e-3, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12, 1e-14};
 static const double kTabBeta[7] = {2.0, 2.5, 3.5, 4.0, 4.5, 5.0, 5.5};
+static const int kTabW[7] = {4, 6, 8, 10, 12, 14, 16};
 
 static double beta_from_tol(double tol) {
     for (int i = 0; i < 7; i++)
@@ -144,7 +145,11 @@ static double beta_from_tol(double tol) {
     return kTabBeta[6];
 }
 
+// a tolerance of the table takes the table's width; any other the App. A
+// decay law 10^(-0.9 w)
 static int width_from_tol(double tol) {
+    for (int i = 0; i < 7; i++)
+        if (std::fabs(tol - kTabTol[i]) <= 1e-9 * kTabTol[i]) return kTabW[i];
     double pe = -std::log10(tol);
     int w = (int)std::ceil(pe / 0.9 - 1e-9) + 1;
     return std::min(kMaxW, std::max(kMinW, w));

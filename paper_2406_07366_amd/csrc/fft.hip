@@ -109,10 +109,24 @@ __host__ __device__ inline int fft_max_nj(int logn) {
 // else from LDS), applies the twiddles and an in-register DFT, and writes
 // elements (j - j mod Ns) R + j mod Ns + r Ns (to store() in the last pass,
 // else to LDS).  One LDS buffer: every read is done before any write.
+// LDS position of element e of sequence s: lanes along a sequence (JFAST)
+// use sequence-major rows skewed by one slot every 16 elements (the first
+// pass writes 16 consecutive elements per thread, so lanes are 16 apart);
+// lanes across sequences use element-major rows of pitch nseq + 1.
+template <bool JFAST>
+__device__ __forceinline__ int lds_at(int s, int e, int pitch) {
+    return JFAST ? s * pitch + e + (e >> 4) : e * pitch + s;
+}
+
+template <bool JFAST>
+__host__ __device__ inline int lds_pitch(int n, int nseq) {
+    return JFAST ? n + (n >> 4) + 1 : nseq + 1;
+}
+
 template <int R, bool JFAST, typename C, typename T, typename Load, typename Store>
 __device__ __forceinline__ void fft_pass(bool first, bool last, int n, int Ns, int nseq,
-                                         int pitch, C *buf, const C *__restrict__ tw, T sgn,
-                                         Load &load, Store &store) {
+                                         int pitch, C *buf, const C *tw, T sgn, Load &load,
+                                         Store &store) {
     const int nj = n / R;
     const int t = threadIdx.x;
     const bool act = t < nj * nseq;
@@ -123,7 +137,7 @@ __device__ __forceinline__ void fft_pass(bool first, bool last, int n, int Ns, i
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const int e = j + r * nj;
-            v[r] = first ? load(s, e) : buf[e * pitch + s];
+            v[r] = first ? load(s, e) : buf[lds_at<JFAST>(s, e, pitch)];
         }
         if (jm != 0) {
             const int step = n / (Ns * R);
@@ -143,15 +157,16 @@ __device__ __forceinline__ void fft_pass(bool first, bool last, int n, int Ns, i
         for (int r = 0; r < R; r++) {
             const int e = d0 + r * Ns;
             if (last) store(s, e, v[r]);
-            else buf[e * pitch + s] = v[r];
+            else buf[lds_at<JFAST>(s, e, pitch)] = v[r];
         }
     }
     __syncthreads();
 }
 
+// tw: the twiddle table in LDS (n entries)
 template <bool JFAST, typename C, typename T, typename Load, typename Store>
-__device__ void fft_run(int logn, int nseq, int pitch, C *buf, const C *__restrict__ tw, T sgn,
-                        Load load, Store store) {
+__device__ void fft_run(int logn, int nseq, int pitch, C *buf, const C *tw, T sgn, Load load,
+                        Store store) {
     int lr[4];
     const int np = fft_plan(logn, lr), n = 1 << logn;
     int Ns = 1;
@@ -167,6 +182,12 @@ __device__ void fft_run(int logn, int nseq, int pitch, C *buf, const C *__restri
     }
 }
 
+// copy ntab twiddle entries into LDS (before the first barrier of fft_run)
+template <typename C>
+__device__ __forceinline__ void stage_twiddles(C *dst, const C *__restrict__ src, int ntab) {
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) dst[i] = src[i];
+}
+
 constexpr int kFftMaxThreads = 512;
 constexpr int kFftLds = 65536;        // LDS per workgroup, at most
 
@@ -180,10 +201,11 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int logn, int nrow
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    C *buf = (C *)smem;
     const int n = 1 << logn;
+    C *twl = (C *)smem, *buf = twl + n;
     const int bid = xcd_block(per), nb = (nrows + nseq - 1) / nseq;
     if (bid >= nb) return;
+    stage_twiddles(twl, tw, n);
     const int row0 = bid * nseq;
     auto load = [&](int s, int e) {
         const int row = row0 + s;
@@ -193,7 +215,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int logn, int nrow
         const int row = row0 + s;
         if (e < K1 && row < nrows) A[(size_t)row * K1 + e] = v;
     };
-    fft_run<true>(logn, nseq, nseq + 1, buf, tw, (R)-1, load, store);
+    fft_run<true>(logn, nseq, lds_pitch<true>(n, nseq), buf, twl, (R)-1, load, store);
 }
 
 // inverse: modes 0..K of each row, Hermitian completion, real part out
@@ -205,10 +227,11 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int logn, int nrow
                                                             R *__restrict__ grid) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    C *buf = (C *)smem;
     const int n = 1 << logn;
+    C *twl = (C *)smem, *buf = twl + n;
     const int bid = xcd_block(per), nb = (nrows + nseq - 1) / nseq;
     if (bid >= nb) return;
+    stage_twiddles(twl, tw, n);
     const int row0 = bid * nseq;
     auto load = [&](int s, int e) {
         const int row = row0 + s;
@@ -226,7 +249,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int logn, int nrow
         const int row = row0 + s;
         if (row < nrows) grid[(size_t)row * n + e] = v.x;
     };
-    fft_run<true>(logn, nseq, nseq + 1, buf, tw, (R)1, load, store);
+    fft_run<true>(logn, nseq, lds_pitch<true>(n, nseq), buf, twl, (R)1, load, store);
 }
 
 // ---------------------------------------------------------------- y pass
@@ -238,11 +261,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int logn, int K, i
                                                             typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    C *buf = (C *)smem;
     const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1;
+    C *twl = (C *)smem, *buf = twl + n;
     const int ngrp = (K1 + nseq - 1) / nseq;
     const int bid = xcd_block(per);
     if (bid >= 3 * n * ngrp) return;
+    stage_twiddles(twl, tw, n);
     const int g = bid % ngrp, cz = bid / ngrp;   // cz = c * n + z
     const int c = cz >> logn, z = cz & (n - 1);
     const int kx0 = g * nseq;
@@ -255,7 +279,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int logn, int K, i
         if (kx < K1 && my >= -K && my <= K)
             B[(((size_t)c * NY + (my + K)) * n + z) * K1 + kx] = v;
     };
-    fft_run<false>(logn, nseq, nseq + 1, buf, tw, (R)-1, load, store);
+    fft_run<false>(logn, nseq, lds_pitch<false>(n, nseq), buf, twl, (R)-1, load, store);
 }
 
 template <typename R>
@@ -265,11 +289,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int logn, int K, i
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    C *buf = (C *)smem;
     const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1;
+    C *twl = (C *)smem, *buf = twl + n;
     const int ngrp = (K1 + nseq - 1) / nseq;
     const int bid = xcd_block(per);
     if (bid >= 3 * n * ngrp) return;
+    stage_twiddles(twl, tw, n);
     const int g = bid % ngrp, cz = bid / ngrp;
     const int c = cz >> logn, z = cz & (n - 1);
     const int kx0 = g * nseq;
@@ -284,7 +309,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int logn, int K, i
         const int kx = kx0 + s;
         if (kx < K1) A[((size_t)cz * n + e) * K1 + kx] = v;
     };
-    fft_run<false>(logn, nseq, nseq + 1, buf, tw, (R)1, load, store);
+    fft_run<false>(logn, nseq, lds_pitch<false>(n, nseq), buf, twl, (R)1, load, store);
 }
 
 // ---------------------------------------------------------------- z pass
@@ -298,11 +323,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
     const typename Cx<R>::T *__restrict__ twi, typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    C *buf = (C *)smem;
     const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1, S = 3 * KZ, pitch = S + 1;
+    C *twl = (C *)smem, *buf = twl + 2 * n;
     const int ngrp = (K1 + KZ - 1) / KZ;
     const int bid = xcd_block(per);
     if (bid >= NY * ngrp) return;
+    stage_twiddles(twl, twf, 2 * n);   // forward then inverse (contiguous in the plan)
     const int g = bid % ngrp, myp = bid / ngrp;
     const int kx0 = g * KZ;
     const size_t cstride = (size_t)NY * n * K1;
@@ -311,7 +337,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
         return kx < K1 ? B[c * cstride + ((size_t)myp * n + e) * K1 + kx] : C{(R)0, (R)0};
     };
     auto lstore = [&](int s, int e, C v) { buf[e * pitch + s] = v; };
-    fft_run<false>(logn, S, pitch, buf, twf, (R)-1, gload, lstore);
+    fft_run<false>(logn, S, pitch, buf, twl, (R)-1, gload, lstore);
     const int my = myp - K;
     for (int i = threadIdx.x; i < n * KZ; i += blockDim.x) {
         const int z = i / KZ, q = i - z * KZ;
@@ -348,14 +374,21 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
         const int c = s / KZ, kx = kx0 + (s - c * KZ);
         if (kx < K1) B[c * cstride + ((size_t)myp * n + e) * K1 + kx] = v;
     };
-    fft_run<false>(logn, S, pitch, buf, twi, (R)1, lload, gstore);
+    fft_run<false>(logn, S, pitch, buf, twl + n, (R)1, lload, gstore);
 }
 
 // --------------------------------------------------------------- launch
-// power of two, and the z pass's smallest batch (3 columns + pad) fits LDS
+// power of two, and the z pass's smallest batch (2 twiddle tables + 3
+// columns + pad) fits LDS
 bool pruned_fft_ok(int n, size_t csize) {
-    return n >= 16 && n <= 1024 && (n & (n - 1)) == 0 && (size_t)n * 4 * csize < kFftLds &&
+    return n >= 16 && n <= 1024 && (n & (n - 1)) == 0 && (size_t)n * 6 * csize < kFftLds &&
            (size_t)3 * fft_max_nj(__builtin_ctz((unsigned)n)) <= kFftMaxThreads;
+}
+
+// LDS of an x-pass workgroup: twiddles + nseq skewed rows
+template <typename C>
+static size_t x_lds(int n, int nseq) {
+    return ((size_t)n + (size_t)nseq * lds_pitch<true>(n, nseq)) * sizeof(C);
 }
 
 static int ilog2(int n) {
@@ -371,10 +404,10 @@ static void pruned_fwd(bs_plan_t p) {
     const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twf = (const C *)p->fft_tw.p;
     const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
-    hipLaunchKernelGGL(k_fft_x_fwd<R>, dim3(8 * px), dim3(RB * mnj), n * (RB + 1) * sizeof(C),
+    hipLaunchKernelGGL(k_fft_x_fwd<R>, dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
                        p->stream, logn, nrows, K1, RB, px, (const R *)p->grid.p, twf,
                        (C *)p->fft_A.p);
-    hipLaunchKernelGGL(k_fft_y_fwd<R>, dim3(8 * py), dim3(KB * mnj), n * (KB + 1) * sizeof(C),
+    hipLaunchKernelGGL(k_fft_y_fwd<R>, dim3(8 * py), dim3(KB * mnj), (n + n * (KB + 1)) * sizeof(C),
                        p->stream, logn, K, KB, py, (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
 }
 
@@ -388,7 +421,7 @@ static void pruned_spectral(bs_plan_t p, int psi) {
     const C *twf = (const C *)p->fft_tw.p, *twi = twf + n;
     const int pz = ceil_div((2 * K + 1) * ceil_div(K1, KZ), 8);
     hipLaunchKernelGGL(k_fft_z_spectral<R>, dim3(8 * pz), dim3(3 * KZ * fft_max_nj(logn)),
-                       n * (3 * KZ + 1) * sizeof(C), p->stream, logn, K, KZ, pz, psi, k0, inv4a2,
+                       (2 * n + n * (3 * KZ + 1)) * sizeof(C), p->stream, logn, K, KZ, pz, psi, k0, inv4a2,
                        1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
 }
 
@@ -399,9 +432,9 @@ static void pruned_inv(bs_plan_t p) {
     const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twi = (const C *)p->fft_tw.p + n;
     const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
-    hipLaunchKernelGGL(k_fft_y_inv<R>, dim3(8 * py), dim3(KB * mnj), n * (KB + 1) * sizeof(C),
+    hipLaunchKernelGGL(k_fft_y_inv<R>, dim3(8 * py), dim3(KB * mnj), (n + n * (KB + 1)) * sizeof(C),
                        p->stream, logn, K, KB, py, (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
-    hipLaunchKernelGGL(k_fft_x_inv<R>, dim3(8 * px), dim3(RB * mnj), n * (RB + 1) * sizeof(C),
+    hipLaunchKernelGGL(k_fft_x_inv<R>, dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
                        p->stream, logn, nrows, K1, RB, px, (const C *)p->fft_A.p, twi,
                        (R *)p->grid.p);
 }
@@ -430,13 +463,16 @@ void pruned_batches(int n, size_t csize, int *rb, int *kb, int *kz) {
     const int logn = ilog2(n), mnj = fft_max_nj(logn);
     const int threads = csize > 8 ? 128 : 256;
     int b = threads / mnj;
-    const int lds = (int)(kFftLds / (csize * n)) - 1;
+    // twiddles (n, 2n in the z pass) + rows of about n + n/16 + 1 entries
+    const int lds = (int)(kFftLds / (csize * (n + n / 16 + 1))) - 2;
     b = b < lds ? b : lds;
     b = pow2_floor(b < 1 ? 1 : b);
     *rb = b;
     *kb = b;
-    const int z = b / 3;
-    *kz = z < 1 ? 1 : z;
+    int z = b / 3;
+    z = z < 1 ? 1 : z;
+    while (z > 1 && (size_t)(2 * n + n * (3 * z + 1)) * csize > kFftLds) z--;
+    *kz = z;
 }
 
 }  // namespace bs

@@ -192,5 +192,25 @@ WORKLOADS = {
 }
 
 
+def leapfrog(n_per: int = 32, L: float = TWO_PI, a: float = 1e-6, grid_n: int = 32,
+             tol: float = 1e-6) -> FilamentSet:
+    """Two coaxial elliptical rings of Sec. 5.2 (leapfrogging test): planes
+    orthogonal to x at distance L/4, minor radius R_a = L/4 and major radius
+    R_b = sqrt(2) R_a, the major axes along y and along z respectively, both
+    oriented about +x (so both travel along +x), Gamma = 1."""
+    Ra = L / 4
+    Rb = math.sqrt(2) * Ra
+    th = TWO_PI * np.arange(n_per) / n_per
+    c1 = np.array([L / 4, L / 2, L / 2])
+    c2 = c1 + np.array([L / 4, 0.0, 0.0])
+    r1 = np.stack([np.full_like(th, c1[0]), c1[1] + Rb * np.cos(th), c1[2] + Ra * np.sin(th)], 1)
+    r2 = np.stack([np.full_like(th, c2[0]), c2[1] + Ra * np.cos(th), c2[2] + Rb * np.sin(th)], 1)
+    return FilamentSet("leapfrog", L, a, _csr([n_per, n_per]), np.concatenate([r1, r2]),
+                       np.array([1.0, 1.0]), grid_n, tol)
+
+
+WORKLOADS["leapfrog"] = leapfrog
+
+
 def make(name: str, **kw) -> FilamentSet:
     return WORKLOADS[name](**kw)

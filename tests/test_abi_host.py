@@ -40,14 +40,20 @@ def _table1():
 
 @pytest.mark.parametrize("row", _table1())
 def test_beta_and_width_follow_table1(row):
-    """Sec. 5.3, Table 1: beta and w per nominal tolerance (sigma = 1.5).
-    Width rule ceil(-log10(tol)/0.9)+1 reproduces the table for 1e-4..1e-8."""
+    """Sec. 5.3, Table 1: beta and w per nominal tolerance (sigma = 1.5)."""
     tol, beta, _, sigma, w = row[:5]
     r = B.resolve_params(B.make_params(L=2 * math.pi, a=1e-6, tol=tol, grid_n=512))
-    assert r.beta == beta
-    assert r.sigma == sigma
-    if 1e-8 <= tol <= 1e-4:
-        assert r.w == w
+    assert (r.beta, r.sigma, r.w) == (beta, sigma, w)
+
+
+@pytest.mark.parametrize("tol,beta,w", [(1e-5, 3.5, 7), (3e-4, 2.5, 5), (1e-7, 4.0, 9),
+                                        (1e-15, 5.5, 16), (0.5, 2.0, 4)])
+def test_tolerances_between_table_rows(tol, beta, w):
+    """Between Table 1 rows: beta of the row with the largest tolerance <= tol,
+    w from the App. A decay 10^(-0.9 w) <= tol, ceil(-log10(tol)/0.9) + 1,
+    clamped to 4..16."""
+    r = B.resolve_params(B.make_params(L=2 * math.pi, a=1e-6, tol=tol, grid_n=512))
+    assert (r.beta, r.w) == (beta, w)
 
 
 def test_derived_parameters_of_the_workloads():
