@@ -13,7 +13,9 @@
  *
  * What each routine follows:
  *   geometry     chord-length parametrisation and periodic cubic spline
- *                (App. B), Gauss-Legendre rule on each segment
+ *                (App. B) in moments form, or the periodic quintic spline
+ *                of App. B in its B-spline form (Cox-de Boor recursion, dense
+ *                interpolation system), Gauss-Legendre rule on each segment
  *                (Sec. 2.7, eq:line_integral_quadrature); vector charges
  *                q = Gamma w_i dtau_j s'_ij (Sec. 3.3, eq:vorticity_fourier_coefs).
  *   local        eq:BS_local and eq:streamfunction_local (Sec. 2.4, 2.6).
@@ -29,7 +31,8 @@
  *   self         eq:velocity_longrange_self, eq:streamfunction_longrange_self
  *                on the same 2Q quadrature points the long-range part uses.
  *   brute        the unsplit sum (alpha = 0) over cubic shells of images.
- *   energy       eq:kinetic_energy_streamfunction, nodal trapezoid in tau.
+ *   energy       eq:kinetic_energy_streamfunction: psi interpolated between
+ *                the nodes by the curve's own spline, Q-point rule per segment.
  *   impulse      p = (1/2V) sum Gamma s x ds (Sec. 5.2).
  *   near-singular  exact integral of the full kernel over one spline segment
  *                (adaptive Gauss-Kronrod 7/15) minus its Q-point sum; and
@@ -52,7 +55,7 @@
 
 typedef struct {
     int64_t nfil, N, Nq;
-    int Q;
+    int Q, order;      /* order 4: cubic (moments form); 6: quintic (B-splines) */
     double L, a, delta;
     int64_t *off;      /* nfil+1 */
     int64_t *fil;      /* N: filament of node */
@@ -61,6 +64,8 @@ typedef struct {
     double *tau;       /* N: parameter at node */
     double *dtau;      /* N: tau_{j+1}-tau_j */
     double *M;         /* N*3 second derivatives at nodes (moments) */
+    double *C;         /* N*3 B-spline coefficients (order 6 only) */
+    double *T;         /* nfil: period of the parameter */
     double *sd;        /* N*3 first derivative at nodes */
     double *ell;       /* N: segment length by the Q-point rule */
     double *qx;        /* Nq*3 quadrature point positions */
@@ -164,11 +169,143 @@ void or_cyclic_tridiag(int64_t n, const double *a, const double *b,
  *   s(t) = M_j (h-t)^3/(6h) + M_{j+1} t^3/(6h)
  *        + (s_j/h - M_j h/6)(h-t) + (s_{j+1}/h - M_{j+1} h/6) t.
  * deriv = 0, 1, 2 returns s, ds/dtau, d2s/dtau2. */
-static void seg_eval(const or_t *o, int64_t j, double t, int deriv, double *out) {
+/* ------------------------------------------- quintic B-splines (App. B) */
+/* B-spline of order k on the k+1 knots kn[0..k], or its d-th derivative, at
+ * x: Cox-de Boor recursion, half-open intervals [kn_i, kn_{i+1}). */
+static double bspl(const double *kn, int k, double x, int d) {
+    if (d == 0) {
+        if (k == 1) return (kn[0] <= x && x < kn[1]) ? 1.0 : 0.0;
+        double v = 0.0;
+        if (kn[k - 1] > kn[0]) v += (x - kn[0]) / (kn[k - 1] - kn[0]) * bspl(kn, k - 1, x, 0);
+        if (kn[k] > kn[1]) v += (kn[k] - x) / (kn[k] - kn[1]) * bspl(kn + 1, k - 1, x, 0);
+        return v;
+    }
+    double v = 0.0;
+    if (kn[k - 1] > kn[0]) v += bspl(kn, k - 1, x, d - 1) / (kn[k - 1] - kn[0]);
+    if (kn[k] > kn[1]) v -= bspl(kn + 1, k - 1, x, d - 1) / (kn[k] - kn[1]);
+    return (k - 1) * v;
+}
+
+/* knot p of filament f, periodically extended: t_{p+n} = t_p + T */
+static double knot(const or_t *o, int64_t f, int64_t p) {
+    int64_t b = o->off[f], n = o->off[f + 1] - b;
+    int64_t q = p % n;
+    if (q < 0) q += n;
+    return o->tau[b + q] + (double)((p - q) / n) * o->T[f];
+}
+
+/* knots of basis function jp (unwrapped index) of order k: t_{jp-k/2..jp+k/2} */
+static void basis_knots(const or_t *o, int64_t f, int64_t jp, int k, double *kn) {
+    for (int i = 0; i <= k; i++) kn[i] = knot(o, f, jp - k / 2 + i);
+}
+
+/* s = sum_j c_j b_j(tau) (eq:spline_from_bspline_basis) at tau = tau_j + t:
+ * the basis functions whose support covers [t_j, t_{j+1}) are j-2..j+3 */
+static void bspline_eval(const or_t *o, const double *coef, int64_t j, double t, int deriv,
+                         double *out) {
+    int64_t f = o->fil[j], b = o->off[f], n = o->off[f + 1] - b, jl = j - b;
+    double x = o->tau[j] + t, kn[8];
+    out[0] = out[1] = out[2] = 0.0;
+    for (int64_t jp = jl - 2; jp <= jl + 3; jp++) {
+        basis_knots(o, f, jp, 6, kn);
+        double w = bspl(kn, 6, x, deriv);
+        int64_t q = ((jp % n) + n) % n;
+        for (int c = 0; c < 3; c++) out[c] += w * coef[3 * (b + q) + c];
+    }
+}
+
+/* dense Gaussian elimination with partial pivoting, nrhs right-hand sides
+ * stored column-wise in r[n][nrhs]; A (n x n, row-major) is destroyed */
+static int dense_solve(int64_t n, double *A, double *r, int nrhs) {
+    for (int64_t c = 0; c < n; c++) {
+        int64_t p = c;
+        for (int64_t i = c + 1; i < n; i++)
+            if (fabs(A[i * n + c]) > fabs(A[p * n + c])) p = i;
+        if (A[p * n + c] == 0.0) return -1;
+        if (p != c) {
+            for (int64_t k = 0; k < n; k++) {
+                double t = A[c * n + k]; A[c * n + k] = A[p * n + k]; A[p * n + k] = t;
+            }
+            for (int k = 0; k < nrhs; k++) {
+                double t = r[c * nrhs + k]; r[c * nrhs + k] = r[p * nrhs + k]; r[p * nrhs + k] = t;
+            }
+        }
+        for (int64_t i = c + 1; i < n; i++) {
+            double m = A[i * n + c] / A[c * n + c];
+            if (m == 0.0) continue;
+            for (int64_t k = c; k < n; k++) A[i * n + k] -= m * A[c * n + k];
+            for (int k = 0; k < nrhs; k++) r[i * nrhs + k] -= m * r[c * nrhs + k];
+        }
+    }
+    for (int64_t c = n - 1; c >= 0; c--) {
+        for (int k = 0; k < nrhs; k++) {
+            double v = r[c * nrhs + k];
+            for (int64_t i = c + 1; i < n; i++) v -= A[c * n + i] * r[i * nrhs + k];
+            r[c * nrhs + k] = v / A[c * n + c];
+        }
+    }
+    return 0;
+}
+
+/* interpolation A c = d with A_ij = b_j(tau_i) (App. B) for the nodal data d
+ * (3 components) of filament f; coefficients into coef */
+static int quintic_fit(const or_t *o, int64_t f, const double *data, double *coef) {
+    int64_t b = o->off[f], n = o->off[f + 1] - b;
+    double *A = (double *)calloc((size_t)(n * n), sizeof(double));
+    double *r = (double *)malloc(sizeof(double) * 3 * n), kn[8];
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t jp = i - 3; jp <= i + 3; jp++) {
+            basis_knots(o, f, jp, 6, kn);
+            int64_t q = ((jp % n) + n) % n;
+            A[i * n + q] += bspl(kn, 6, o->tau[b + i], 0);
+        }
+        for (int c = 0; c < 3; c++) r[3 * i + c] = data[3 * (b + i) + c];
+    }
+    int rc = dense_solve(n, A, r, 3);
+    memcpy(coef + 3 * b, r, sizeof(double) * 3 * n);
+    free(A); free(r);
+    return rc;
+}
+
+/* periodic cubic spline through the nodal data d of filament f in moments
+ * form: h_{k-1} M_{k-1} + 2(h_{k-1}+h_k) M_k + h_k M_{k+1}
+ *     = 6[(d_{k+1}-d_k)/h_k - (d_k-d_{k-1})/h_{k-1}]  (M = d'' at the nodes) */
+static void cubic_fit(const or_t *o, int64_t f, const double *data, double *M) {
+    int64_t b = o->off[f], n = o->off[f + 1] - b;
+    double *aa = (double *)malloc(sizeof(double) * n);
+    double *bb = (double *)malloc(sizeof(double) * n);
+    double *cc = (double *)malloc(sizeof(double) * n);
+    double *rr = (double *)malloc(sizeof(double) * n);
+    double *wk = (double *)malloc(sizeof(double) * 3 * n);
+    for (int64_t k = 0; k < n; k++) {
+        double hm = o->dtau[b + (k + n - 1) % n], hk = o->dtau[b + k];
+        aa[k] = hm; bb[k] = 2.0 * (hm + hk); cc[k] = hk;
+    }
+    for (int c = 0; c < 3; c++) {
+        for (int64_t k = 0; k < n; k++) {
+            int64_t j = b + k, jn = b + (k + 1) % n, jp = b + (k + n - 1) % n;
+            double hm = o->dtau[jp], hk = o->dtau[j];
+            rr[k] = 6.0 * ((data[3 * jn + c] - data[3 * j + c]) / hk -
+                           (data[3 * j + c] - data[3 * jp + c]) / hm);
+        }
+        cyclic_tridiag(n, aa, bb, cc, rr, wk);
+        for (int64_t k = 0; k < n; k++) M[3 * (b + k) + c] = rr[k];
+    }
+    free(aa); free(bb); free(cc); free(rr); free(wk);
+}
+
+/* the spline through nodal data (aux = its moments for order 4, its B-spline
+ * coefficients for order 6) on segment j at tau = tau_j + t */
+static void spline_eval_data(const or_t *o, const double *data, const double *aux, int64_t j,
+                             double t, int deriv, double *out) {
+    if (o->order == 6) {
+        bspline_eval(o, aux, j, t, deriv, out);
+        return;
+    }
     int64_t jn = next_node(o, j);
     double h = o->dtau[j];
-    const double *Mj = o->M + 3 * j, *Mn = o->M + 3 * jn;
-    const double *sj = o->x + 3 * j, *sn = o->x + 3 * jn;
+    const double *Mj = aux + 3 * j, *Mn = aux + 3 * jn;
+    const double *sj = data + 3 * j, *sn = data + 3 * jn;
     double u = h - t;
     for (int c = 0; c < 3; c++) {
         double A = sj[c] / h - Mj[c] * h / 6.0;
@@ -182,6 +319,11 @@ static void seg_eval(const or_t *o, int64_t j, double t, int deriv, double *out)
     }
 }
 
+/* the curve: s, ds/dtau or d2s/dtau2 on segment j at tau = tau_j + t */
+static void seg_eval(const or_t *o, int64_t j, double t, int deriv, double *out) {
+    spline_eval_data(o, o->x, o->order == 6 ? o->C : o->M, j, t, deriv, out);
+}
+
 void or_spline_eval(const void *h, int64_t seg, double u, int deriv, double *out) {
     const or_t *o = (const or_t *)h;
     seg_eval(o, seg, u * o->dtau[seg], deriv, out);
@@ -192,18 +334,18 @@ void or_free(void *h) {
     or_t *o = (or_t *)h;
     if (!o) return;
     free(o->off); free(o->fil); free(o->gamma); free(o->x); free(o->tau);
-    free(o->dtau); free(o->M); free(o->sd); free(o->ell);
+    free(o->dtau); free(o->M); free(o->sd); free(o->ell); free(o->C); free(o->T);
     free(o->qx); free(o->qs); free(o->qc);
     free(o);
 }
 
 void *or_new(int64_t nfil, const int64_t *off, const double *xyz,
-             const double *gamma, double L, double a, double delta, int Q) {
-    if (nfil < 1 || Q < 1 || Q > 4) return NULL;
+             const double *gamma, double L, double a, double delta, int Q, int order) {
+    if (nfil < 1 || Q < 1 || Q > 4 || (order != 4 && order != 6)) return NULL;
     for (int64_t f = 0; f < nfil; f++)
-        if (off[f + 1] - off[f] < 3) return NULL;
+        if (off[f + 1] - off[f] < (order == 6 ? 6 : 3)) return NULL;
     or_t *o = (or_t *)calloc(1, sizeof(or_t));
-    o->nfil = nfil; o->N = off[nfil]; o->Q = Q; o->Nq = o->N * Q;
+    o->nfil = nfil; o->N = off[nfil]; o->Q = Q; o->Nq = o->N * Q; o->order = order;
     o->L = L; o->a = a; o->delta = delta;
     int64_t N = o->N;
     o->off = (int64_t *)malloc(sizeof(int64_t) * (nfil + 1));
@@ -216,6 +358,8 @@ void *or_new(int64_t nfil, const int64_t *off, const double *xyz,
     o->tau = (double *)malloc(sizeof(double) * N);
     o->dtau = (double *)malloc(sizeof(double) * N);
     o->M = (double *)malloc(sizeof(double) * 3 * N);
+    o->C = (double *)calloc((size_t)(3 * N), sizeof(double));
+    o->T = (double *)malloc(sizeof(double) * nfil);
     o->sd = (double *)malloc(sizeof(double) * 3 * N);
     o->ell = (double *)malloc(sizeof(double) * N);
     o->qx = (double *)malloc(sizeof(double) * 3 * o->Nq);
@@ -239,28 +383,14 @@ void *or_new(int64_t nfil, const int64_t *off, const double *xyz,
             if (!(o->dtau[j] > 0.0)) bad = 1;
             if (k + 1 < n) o->tau[jn] = o->tau[j] + o->dtau[j];
         }
-        /* moments system: h_{k-1} M_{k-1} + 2(h_{k-1}+h_k) M_k + h_k M_{k+1}
-         *                 = 6[(s_{k+1}-s_k)/h_k - (s_k-s_{k-1})/h_{k-1}] */
-        double *aa = (double *)malloc(sizeof(double) * n);
-        double *bb = (double *)malloc(sizeof(double) * n);
-        double *cc = (double *)malloc(sizeof(double) * n);
-        double *rr = (double *)malloc(sizeof(double) * n);
-        double *wk = (double *)malloc(sizeof(double) * 3 * n);
-        for (int64_t k = 0; k < n; k++) {
-            double hm = o->dtau[b + (k + n - 1) % n], hk = o->dtau[b + k];
-            aa[k] = hm; bb[k] = 2.0 * (hm + hk); cc[k] = hk;
+        o->T[f] = o->tau[b + n - 1] + o->dtau[b + n - 1];
+        if (bad) continue;
+        if (order == 6) {
+            if (quintic_fit(o, f, o->x, o->C)) bad = 1;
+            for (int64_t k = 0; k < n; k++) bspline_eval(o, o->C, b + k, 0.0, 2, o->M + 3 * (b + k));
+        } else {
+            cubic_fit(o, f, o->x, o->M);
         }
-        for (int c = 0; c < 3; c++) {
-            for (int64_t k = 0; k < n; k++) {
-                int64_t j = b + k, jn = b + (k + 1) % n, jp = b + (k + n - 1) % n;
-                double hm = o->dtau[jp], hk = o->dtau[j];
-                rr[k] = 6.0 * ((o->x[3 * jn + c] - o->x[3 * j + c]) / hk -
-                               (o->x[3 * j + c] - o->x[3 * jp + c]) / hm);
-            }
-            if (!bad) cyclic_tridiag(n, aa, bb, cc, rr, wk);
-            for (int64_t k = 0; k < n; k++) o->M[3 * (b + k) + c] = rr[k];
-        }
-        free(aa); free(bb); free(cc); free(rr); free(wk);
     }
     if (bad) { or_free(o); return NULL; }
 
@@ -328,9 +458,14 @@ void or_local(const void *h, int64_t nt, const int64_t *tgt, double *v, double *
  * that touches node i is the central portion, treated by the Taylor
  * expansion (eq:BS_local, eq:streamfunction_local with l-, l+ the arc lengths
  * of the two central portions); the rest of each segment is integrated with
- * the unsplit kernels (eq:BS, eq:streamfunction_integral) by the 3-point
- * Gauss-Legendre rule.  Arc lengths of the central portions use the same
- * 3-point rule.  eps = 1 gives back or_local up to the rule used for l-, l+. */
+ * the unsplit kernels (eq:BS, eq:streamfunction_integral) by 3-point
+ * Gauss-Legendre rules on panels graded towards the node: in the distance
+ * u from the node (in units of the segment's parameter interval) the panels
+ * are [eps, 2 eps], [2 eps, 4 eps], ..., the last one ending at u = 1, so
+ * that each panel's distance to the node is at least its own length (the
+ * integrand behaves like 1/u there).  Arc lengths of the central portions
+ * use the 3-point rule.  eps = 1 gives back or_local up to the rule used for
+ * l-, l+. */
 void or_local_sub(const void *h, double eps, int64_t nt, const int64_t *tgt, double *v,
                   double *psi) {
     const or_t *o = (const or_t *)h;
@@ -358,20 +493,25 @@ void or_local_sub(const void *h, double eps, int64_t nt, const int64_t *tgt, dou
             vv[c] = gam / (4 * OR_PI) * b[c] / (sn * sn * sn) * (lg - o->delta);
             pp[c] = gam / (2 * OR_PI) * sd[c] / sn * (lg - (o->delta - 1.0));
         }
-        /* remaining portions: [0, hm (1-eps)] on jm, [eps hp, hp] on i */
+        /* remaining portions, distance u from the node in [eps, 1]: on
+         * segment i at t = u hp, on segment jm at t = (1 - u) hm */
         for (int side = 0; side < 2; side++) {
             int64_t j = side ? i : jm;
-            double h0 = side ? eps * hp : 0.0, len = side ? (1.0 - eps) * hp : (1.0 - eps) * hm;
-            for (int k = 0; k < 3; k++) {
-                double x[3], sdq[3], r[3], rx[3];
-                seg_eval(o, j, h0 + g3h[k] * len, 0, x);
-                seg_eval(o, j, h0 + g3h[k] * len, 1, sdq);
-                for (int c = 0; c < 3; c++) r[c] = x[c] - si[c];
-                double rn = norm3(r), wq = gam * g3w[k] * len / (4 * OR_PI);
-                cross3(r, sdq, rx);
-                for (int c = 0; c < 3; c++) {
-                    vv[c] += wq * rx[c] / (rn * rn * rn);
-                    pp[c] += wq * sdq[c] / rn;
+            double hs = side ? hp : hm;
+            for (double u0 = eps; u0 < 1.0; u0 *= 2.0) {
+                double u1 = fmin(2.0 * u0, 1.0);
+                for (int k = 0; k < 3; k++) {
+                    double u = u0 + g3h[k] * (u1 - u0), x[3], sdq[3], r[3], rx[3];
+                    double t = side ? u * hs : (1.0 - u) * hs;
+                    seg_eval(o, j, t, 0, x);
+                    seg_eval(o, j, t, 1, sdq);
+                    for (int c = 0; c < 3; c++) r[c] = x[c] - si[c];
+                    double rn = norm3(r), wq = gam * g3w[k] * (u1 - u0) * hs / (4 * OR_PI);
+                    cross3(r, sdq, rx);
+                    for (int c = 0; c < 3; c++) {
+                        vv[c] += wq * rx[c] / (rn * rn * rn);
+                        pp[c] += wq * sdq[c] / rn;
+                    }
                 }
             }
         }
@@ -651,13 +791,26 @@ void or_brute_images(const void *h, int K, int64_t nt, const int64_t *tgt, doubl
 /* ------------------------------------------------------------ diagnostics */
 /* E = (1/2V) sum_l Gamma_l sum_j psi_j . sdot_j (dtau_{j-1} + dtau_j)/2
  * (eq:kinetic_energy_streamfunction, nodal trapezoid in tau). */
+/* E = (1/2V) sum_l Gamma_l oint psi . ds (eq:kinetic_energy_streamfunction):
+ * psi between the nodes is the spline through its nodal values on the
+ * curve's own knots (cubic or quintic, as the curve), and the line integral
+ * uses the curve's Q-point rule on every segment, so that
+ * E = (1/2V) sum_q psi(tau_q) . q_q with the vector charges q_q. */
 double or_energy(const void *h, const double *psi) {
     const or_t *o = (const or_t *)h;
     double V = o->L * o->L * o->L, e = 0.0;
-    for (int64_t j = 0; j < o->N; j++) {
-        double w = 0.5 * (o->dtau[prev_node(o, j)] + o->dtau[j]);
-        e += o->gamma[o->fil[j]] * dot3(psi + 3 * j, o->sd + 3 * j) * w;
+    double *aux = (double *)calloc((size_t)(3 * o->N), sizeof(double));
+    for (int64_t f = 0; f < o->nfil; f++) {
+        if (o->order == 6) quintic_fit(o, f, psi, aux);
+        else cubic_fit(o, f, psi, aux);
     }
+    for (int64_t j = 0; j < o->N; j++)
+        for (int i = 0; i < o->Q; i++) {
+            double pv[3];
+            spline_eval_data(o, psi, aux, j, o->gl_h[i] * o->dtau[j], 0, pv);
+            e += dot3(pv, o->qc + 3 * (j * o->Q + i));
+        }
+    free(aux);
     return e / (2 * V);
 }
 

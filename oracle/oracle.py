@@ -45,7 +45,8 @@ def lib():
         build()
         L = C.CDLL(_SO)
         L.or_new.restype = C.c_void_p
-        L.or_new.argtypes = [C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int]
+        L.or_new.argtypes = [C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int,
+                             C.c_int]
         L.or_free.argtypes = [C.c_void_p]
         L.or_nquad.restype = C.c_int64
         L.or_nquad.argtypes = [C.c_void_p]
@@ -139,16 +140,20 @@ def reference_params(L: float, beta: float = 6.5, rc: float | None = None):
 class Oracle:
     """FP64 geometry and Ewald components for one filament set."""
 
-    def __init__(self, fs, Q: int = 2):
+    def __init__(self, fs, Q: int = 2, order: int = 4):
+        """order 4: periodic cubic spline; 6: periodic quintic spline (App. B)."""
         self.fs = fs
         self.Q = Q
+        self.order = order
         self.N = fs.n_nodes
         off = np.ascontiguousarray(fs.offsets, dtype=np.int64)
         xyz = np.ascontiguousarray(fs.xyz, dtype=np.float64)
         gam = np.ascontiguousarray(fs.gamma, dtype=np.float64)
-        self._h = lib().or_new(fs.n_fil, off, xyz, gam, fs.L, fs.a, fs.delta, Q)
+        self._h = lib().or_new(fs.n_fil, off, xyz, gam, fs.L, fs.a, fs.delta, Q,
+                               order)
         if not self._h:
-            raise ValueError("invalid filament set (N_l < 3 or zero-length segment)")
+            raise ValueError("invalid filament set (N_l < 3, or < 6 for quintic, or "
+                             "zero-length segment)")
         self.Nq = lib().or_nquad(self._h)
 
     def __del__(self):
