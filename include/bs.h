@@ -112,7 +112,7 @@ typedef struct {
     double sigma;        /* oversampling factor (0: 1.5)                       */
     int    w;            /* kernel width in grid points (0: from tol)          */
     int    Q;            /* Gauss-Legendre points per segment, 1..4 (0: 2)     */
-    int    spline_order; /* 4 = cubic (the only order built; 0: 4)             */
+    int    spline_order; /* 4 = cubic, 6 = quintic (App. B; 0: 4)              */
     int    precision;    /* BS_FP64 or BS_FP32_MIXED                           */
     int    ns_mode;      /* BS_NS_OFF, BS_NS_ADAPTIVE or BS_NS_MLP             */
     double ns_eta;       /* flag pairs with chord distance < ns_eta * ell (0: 1) */
@@ -120,6 +120,13 @@ typedef struct {
                                 parameters (see bs_mlp_nparams); needed for
                                 BS_NS_MLP; copied by bs_plan                   */
     int    fft_mode;     /* BS_FFT_AUTO, BS_FFT_LIBRARY or BS_FFT_PRUNED       */
+    double local_frac;   /* local-segment subdivision (Sec. 5.2): fraction of
+                            each local segment, next to the node, where the
+                            Taylor expansion of eq:BS_local and
+                            eq:streamfunction_local is used; the rest of the
+                            two local segments is integrated with the unsplit
+                            kernels (3-point Gauss-Legendre on panels graded
+                            towards the node).  0 or 1: whole segments      */
     /* resolved values, written by bs_resolve_params / bs_get_params */
     int    K;            /* retained modes |m_i| <= K per axis                 */
     int    ncell;        /* cells per axis of the short-range cell list (edge

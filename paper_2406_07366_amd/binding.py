@@ -44,7 +44,8 @@ class BsParams(C.Structure):
                 ("rcut", C.c_double), ("grid_n", C.c_int), ("sigma", C.c_double),
                 ("w", C.c_int), ("Q", C.c_int), ("spline_order", C.c_int),
                 ("precision", C.c_int), ("ns_mode", C.c_int), ("ns_eta", C.c_double),
-                ("mlp_weights", C.c_void_p), ("fft_mode", C.c_int), ("K", C.c_int),
+                ("mlp_weights", C.c_void_p), ("fft_mode", C.c_int),
+                ("local_frac", C.c_double), ("K", C.c_int),
                 ("ncell", C.c_int),
                 ("zeta", C.c_double)]
 
@@ -115,15 +116,16 @@ def _check(code, plan=None):
 
 def make_params(L, a, tol, grid_n, delta=0.25, beta=0.0, alpha=0.0, rcut=0.0, sigma=0.0,
                 w=0, Q=0, precision=BS_FP64, ns_mode=BS_NS_OFF, ns_eta=0.0,
-                fft_mode=0) -> BsParams:
+                fft_mode=0, spline_order=4, local_frac=0.0) -> BsParams:
     p = BsParams()
     p.L, p.a, p.delta, p.tol = L, a, delta, tol
     p.beta, p.alpha, p.rcut = beta, alpha, rcut
     p.grid_n, p.sigma, p.w, p.Q = grid_n, sigma, w, Q
-    p.spline_order = 4
+    p.spline_order = spline_order
     p.precision, p.ns_mode, p.ns_eta = precision, ns_mode, ns_eta
     p.mlp_weights = None
     p.fft_mode = fft_mode
+    p.local_frac = local_frac
     return p
 
 

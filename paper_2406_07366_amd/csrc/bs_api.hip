@@ -170,9 +170,15 @@ int resolve(const bs_params *in, bs_params *out) {
     if (r.Q == 0) r.Q = 2;
     if (r.Q < 1 || r.Q > kMaxQ) return bad("Q must be in 1..4");
     if (r.spline_order == 0) r.spline_order = 4;
-    if (r.spline_order != 4) return bad("only cubic splines (spline_order 4) are built");
+    if (r.spline_order != 4 && r.spline_order != 6)
+        return bad("spline_order must be 4 (cubic) or 6 (quintic)");
+    if (!(r.local_frac >= 0.0 && r.local_frac <= 1.0)) return bad("local_frac must be in [0, 1]");
+    if (r.local_frac > 0.0 && r.local_frac < 1e-3)
+        return bad("local_frac below 1e-3 (more than 10 panels per local segment)");
     if (r.precision != BS_FP64 && r.precision != BS_FP32_MIXED) return bad("unknown precision");
     if (r.ns_mode < BS_NS_OFF || r.ns_mode > BS_NS_MLP) return bad("unknown ns_mode");
+    if (r.ns_mode != BS_NS_OFF && r.spline_order != 4)
+        return bad("the near-singular correction is built for cubic splines only");
     if (r.ns_eta == 0) r.ns_eta = 1.0;
     if (!(r.ns_eta > 0)) return bad("ns_eta must be positive");
     if (r.fft_mode < BS_FFT_AUTO || r.fft_mode > BS_FFT_PRUNED) return bad("unknown fft_mode");
@@ -281,6 +287,7 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
     P->NT = P->n / P->T;
     P->nc = r.ncell;
     P->Q = r.Q;
+    P->order = r.spline_order;
     (void)hipGetDevice(&P->device);
     const size_t n = (size_t)P->n, n3 = n * n * n, nc = n * n * (n / 2 + 1);
     auto fail = [&](int code) {
@@ -363,6 +370,8 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     for (int64_t f = 0; f < nfil; f++) {
         int64_t c = offsets[f + 1] - offsets[f];
         if (c < 3) return set_error(P, BS_EINVAL, "every filament needs at least 3 nodes");
+        if (P->order == 6 && c < 6)
+            return set_error(P, BS_EINVAL, "quintic splines need at least 6 nodes per filament");
         maxn = std::max(maxn, c);
     }
     const int64_t N = offsets[nfil], Nq = N * P->Q;
@@ -380,6 +389,7 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             (rc = ensure<double>(P, P->d_sdd, 3 * N)) || (rc = ensure<double>(P, P->d_ell, N)) ||
             (rc = ensure<double>(P, P->d_qpos, 3 * Nq)) ||
             (rc = ensure<double>(P, P->d_qchg, 3 * Nq)) || (rc = ensure<double>(P, P->tmp3, 3 * N)) ||
+            (rc = ensure<double>(P, P->e_D, 3 * N)) || (rc = ensure<double>(P, P->e_S, 3 * N)) ||
             (rc = ensure<int>(P, P->sp_key, Nq)) || (rc = ensure<int>(P, P->sp_cnt, ntiles + 1)) ||
             (rc = ensure<int>(P, P->sp_start, ntiles + 1)) ||
             (rc = ensure<int>(P, P->sp_fill, ntiles + 1)) || (rc = ensure<int>(P, P->sp_perm, Nq)) ||
@@ -393,7 +403,10 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             (rc = ensure<int>(P, P->nd_cnt, nc3 + 1)) || (rc = ensure<int>(P, P->nd_start, nc3 + 1)) ||
             (rc = ensure<int>(P, P->nd_fill, nc3 + 1)) || (rc = ensure<int>(P, P->nd_perm, N)))
             return rc;
-        if (maxn > 512 && (rc = ensure<double>(P, P->spline_tmp, 12 * N))) return rc;
+        if (P->order == 4 && maxn > 512 && (rc = ensure<double>(P, P->spline_tmp, 12 * N)))
+            return rc;
+        if (P->order == 6 && maxn > 64 && (rc = ensure<double>(P, P->spline_tmp, 36 * N)))
+            return rc;
         if (P->prm.ns_mode != BS_NS_OFF) {
             size_t mp = (size_t)N * P->ns_max_per_node;
             int ncmax = (int)cbrt(2.0 * (double)N);
@@ -750,7 +763,7 @@ int bs_destroy(bs_plan_t P) {
                    &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
                    &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
-                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->ns_red, &P->ns_nc, &P->ns_ckey,
+                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->e_D, &P->e_S, &P->ns_red, &P->ns_nc, &P->ns_ckey,
                    &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_tkey, &P->ns_tcnt,
                    &P->ns_tstart, &P->ns_tfill, &P->ns_tperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_slots,
                    &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout,

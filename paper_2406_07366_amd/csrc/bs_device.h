@@ -114,3 +114,75 @@ __device__ void rank_sort_bin(int *perm, int *scratch, int s, int n, int *v) {
 }
 
 }  // namespace bs
+
+namespace bs {
+
+// ------------------------------------------------------------ spline segments
+// Segment j of a filament in the local coordinate u in [0, 1]
+// (tau = tau_j + u h_j): s(u) = sum_k c_k u^k, built from the node values s,
+// slopes D = ds/dtau and (quintic only) second derivatives S = d2s/dtau2 at
+// both ends.  ORDER 4: the cubic Hermite segment of the C2 spline; ORDER 6:
+// the quintic Hermite segment of the C4 spline (both are the periodic
+// interpolating splines of App. B on the chord-length knots).
+template <int ORDER>
+struct SegPoly {
+    double c[ORDER][3];
+
+    __device__ __forceinline__ void load(const double *__restrict__ x,
+                                         const double *__restrict__ D,
+                                         const double *__restrict__ S, int j, int jn, double h) {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const double s0 = x[3 * j + q], s1 = x[3 * jn + q];
+            const double d0 = h * D[3 * j + q], d1 = h * D[3 * jn + q];
+            c[0][q] = s0;
+            c[1][q] = d0;
+            if constexpr (ORDER == 4) {
+                c[2][q] = 3.0 * (s1 - s0) - 2.0 * d0 - d1;
+                c[3][q] = 2.0 * (s0 - s1) + d0 + d1;
+            } else {
+                // matches s1, h D1, h^2 S1 at u = 1: with A, B, C the
+                // misfits of the value, slope and curvature of the
+                // quadratic part there
+                const double q0 = h * h * S[3 * j + q], q1 = h * h * S[3 * jn + q];
+                const double A = s1 - s0 - d0 - 0.5 * q0, B = d1 - d0 - q0, C = q1 - q0;
+                c[2][q] = 0.5 * q0;
+                c[3][q] = 10.0 * A - 4.0 * B + 0.5 * C;
+                c[4][q] = -15.0 * A + 7.0 * B - C;
+                c[5][q] = 6.0 * A - 3.0 * B + 0.5 * C;
+            }
+        }
+    }
+    // s(u)
+    __device__ __forceinline__ void pos(double u, double *p) const {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            double v = c[ORDER - 1][q];
+#pragma unroll
+            for (int k = ORDER - 2; k >= 0; k--) v = v * u + c[k][q];
+            p[q] = v;
+        }
+    }
+    // ds/du (divide by h for ds/dtau)
+    __device__ __forceinline__ void der(double u, double *d) const {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            double v = (ORDER - 1) * c[ORDER - 1][q];
+#pragma unroll
+            for (int k = ORDER - 2; k >= 1; k--) v = v * u + k * c[k][q];
+            d[q] = v;
+        }
+    }
+    // d2s/du2 (divide by h^2 for d2s/dtau2)
+    __device__ __forceinline__ void der2(double u, double *d) const {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            double v = (ORDER - 1) * (ORDER - 2) * c[ORDER - 1][q];
+#pragma unroll
+            for (int k = ORDER - 2; k >= 2; k--) v = v * u + k * (k - 1) * c[k][q];
+            d[q] = v;
+        }
+    }
+};
+
+}  // namespace bs

@@ -62,6 +62,7 @@ struct bs_plan_s {
     // filaments
     int64_t nfil = 0, N = 0, Nq = 0;
     int Q = 2;
+    int order = 4;          // spline order: 4 cubic, 6 quintic
     std::vector<int64_t> off_host;
     bool have_filaments = false;
     bs::DBuf d_off, d_fil, d_gamma;            // int32 [nfil+1], int32 [N], f64 [nfil]
@@ -103,6 +104,7 @@ struct bs_plan_s {
     double *g_v = nullptr;
     // terms (for velocity terms / energy)
     bs::DBuf tmp3;                             // f64 [N][3]
+    bs::DBuf e_D, e_S;                         // f64 [N][3]: spline of psi (energy)
     // per-stage timing (diagnostics)
     bool prof = false;
     hipEvent_t ev_beg[BS_NSTAGES] = {}, ev_end[BS_NSTAGES] = {};
@@ -119,6 +121,9 @@ int check_hip(bs_plan_t p, hipError_t e, const char *what);
 // geometry.hip
 void launch_chord(bs_plan_t p, const double *xyz, const double *gamma);
 void launch_spline(bs_plan_t p);
+// spline through nodal data on the plan's knots: slopes (and, quintic,
+// second derivatives) into Dout, Sout
+void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout);
 void launch_geometry(bs_plan_t p);
 // mode bits for launch_local_self
 enum { LS_VLOCAL = 1, LS_VSELF = 2, LS_PSI = 4, LS_ASSIGN = 8 };

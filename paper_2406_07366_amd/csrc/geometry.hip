@@ -15,7 +15,15 @@
 // workgroup per filament: each step eliminates the neighbours at distance
 // d = 2^s, squaring the off-diagonal to diagonal ratio (<= 1/2 here), so
 // after 7 steps they are below 1e-19 and D_i = r_i / b_i.
+//
+// Quintic splines (App. B, k = 6) use the same idea with quintic Hermite
+// segments: node values s_i, slopes D_i and second derivatives S_i; C3 and C4
+// continuity at every node give a cyclic block-tridiagonal system in
+// X_i = (D_i, S_i) with 2x2 blocks, solved by block parallel cyclic
+// reduction (the interpolating periodic quintic spline on given knots is
+// unique, so this is the paper's curve).
 #include "bs_internal.h"
+#include "bs_device.h"
 
 namespace bs {
 
@@ -117,14 +125,153 @@ __global__ void k_spline(int nfil, const int *__restrict__ off, const double *__
     }
 }
 
+// ------------------------------------------------ quintic spline (block PCR)
+// Rows of node i (h- = h_{i-1}, h+ = h_i), the C3 condition scaled by 1/3
+// and the C4 condition by -1/12:
+//   -8/h-^2 D_{i-1} - 1/h- S_{i-1} + 12 (1/h+^2 - 1/h-^2) D_i
+//     + 3 (1/h- + 1/h+) S_i + 8/h+^2 D_{i+1} - 1/h+ S_{i+1}
+//     = 20 [(s_{i+1} - s_i)/h+^3 - (s_i - s_{i-1})/h-^3]
+//   14/h-^3 D_{i-1} + 2/h-^2 S_{i-1} + 16 (1/h-^3 + 1/h+^3) D_i
+//     - 3 (1/h-^2 - 1/h+^2) S_i + 14/h+^3 D_{i+1} - 2/h+^2 S_{i+1}
+//     = 30 [(s_i - s_{i-1})/h-^4 + (s_{i+1} - s_i)/h+^4]
+// The diagonal block has det = -12 (1/h- + 1/h+)^4, never zero.  The
+// influence of a node decays by about 0.43 per node (the quintic spline's
+// cardinal function), so after 8 doubling steps the couplings left are
+// below 0.43^256.  At distance n/2 of a power-of-two n both neighbours are
+// the same node and their two couplings are merged.
+constexpr int kPcr5Steps = 8;
+constexpr int kPcr5Lds = 64;   // nodes per filament solved in LDS
+
+struct Blk {
+    double L[4], M[4], U[4], R[6];   // 2x2 blocks row-major; R[row * 3 + comp]
+};
+
+__device__ __forceinline__ void inv2(const double *A, double *B) {
+    const double id = 1.0 / (A[0] * A[3] - A[1] * A[2]);
+    B[0] = A[3] * id;
+    B[1] = -A[1] * id;
+    B[2] = -A[2] * id;
+    B[3] = A[0] * id;
+}
+__device__ __forceinline__ void mul2(const double *A, const double *B, double *C) {
+    C[0] = A[0] * B[0] + A[1] * B[2];
+    C[1] = A[0] * B[1] + A[1] * B[3];
+    C[2] = A[2] * B[0] + A[3] * B[2];
+    C[3] = A[2] * B[1] + A[3] * B[3];
+}
+// C -= A B (2x2)
+__device__ __forceinline__ void sub_mul2(const double *A, const double *B, double *C) {
+    double t[4];
+    mul2(A, B, t);
+    for (int k = 0; k < 4; k++) C[k] -= t[k];
+}
+// R -= K V (K 2x2, V 2x3)
+__device__ __forceinline__ void sub_mulR(const double *K, const double *V, double *R) {
+    for (int r = 0; r < 2; r++)
+        for (int q = 0; q < 3; q++) R[3 * r + q] -= K[2 * r] * V[q] + K[2 * r + 1] * V[3 + q];
+}
+
+__global__ void k_spline5(int nfil, const int *__restrict__ off, const double *__restrict__ x,
+                          const double *__restrict__ dtau, double *__restrict__ D,
+                          double *__restrict__ S, double *__restrict__ gscratch) {
+    __shared__ Blk lds[2 * kPcr5Lds];
+    const int f = blockIdx.x;
+    if (f >= nfil) return;
+    const int b0 = off[f], n = off[f + 1] - off[f];
+    Blk *src, *dst;
+    if (n <= kPcr5Lds) {
+        src = lds;
+        dst = lds + kPcr5Lds;
+    } else {
+        src = (Blk *)(gscratch + (size_t)36 * b0);   // 2 x 18 doubles per node
+        dst = src + n;
+    }
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const int km = (k == 0) ? n - 1 : k - 1, kp = (k + 1 == n) ? 0 : k + 1;
+        const double hm = dtau[b0 + km], hp = dtau[b0 + k];
+        const double im1 = 1.0 / hm, ip1 = 1.0 / hp;
+        const double im2 = im1 * im1, ip2 = ip1 * ip1, im3 = im2 * im1, ip3 = ip2 * ip1;
+        Blk &e = src[k];
+        e.L[0] = -8.0 * im2;  e.L[1] = -im1;
+        e.L[2] = 14.0 * im3;  e.L[3] = 2.0 * im2;
+        e.M[0] = 12.0 * (ip2 - im2);   e.M[1] = 3.0 * (im1 + ip1);
+        e.M[2] = 16.0 * (im3 + ip3);   e.M[3] = -3.0 * (im2 - ip2);
+        e.U[0] = 8.0 * ip2;   e.U[1] = -ip1;
+        e.U[2] = 14.0 * ip3;  e.U[3] = -2.0 * ip2;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const double sm = x[3 * (b0 + km) + q], s0 = x[3 * (b0 + k) + q],
+                         sp = x[3 * (b0 + kp) + q];
+            const double dm = s0 - sm, dp = sp - s0;
+            e.R[q] = 20.0 * (dp * ip3 - dm * im3);
+            e.R[3 + q] = 30.0 * (dm * im3 * im1 + dp * ip3 * ip1);
+        }
+    }
+    __syncthreads();
+    int d = 1;
+    for (int st = 0; st < kPcr5Steps; st++) {
+        const int dm = d % n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            int im = i - dm; if (im < 0) im += n;
+            int ip = i + dm; if (ip >= n) ip -= n;
+            const Blk &e = src[i];
+            Blk &o = dst[i];
+            double Mi[4], K[4];
+            for (int k = 0; k < 4; k++) o.M[k] = e.M[k];
+            for (int k = 0; k < 6; k++) o.R[k] = e.R[k];
+            if (2 * dm == n) {
+                // both neighbours are node ip: one coupling L_i + U_i
+                double Ci[4], Cj[4];
+                for (int k = 0; k < 4; k++) {
+                    Ci[k] = e.L[k] + e.U[k];
+                    Cj[k] = src[ip].L[k] + src[ip].U[k];
+                }
+                inv2(src[ip].M, Mi);
+                mul2(Ci, Mi, K);
+                sub_mul2(K, Cj, o.M);
+                sub_mulR(K, src[ip].R, o.R);
+                for (int k = 0; k < 4; k++) o.L[k] = o.U[k] = 0.0;
+            } else {
+                inv2(src[im].M, Mi);
+                mul2(e.L, Mi, K);             // K1 = L_i M_im^-1
+                mul2(K, src[im].L, o.L);
+                for (int k = 0; k < 4; k++) o.L[k] = -o.L[k];
+                sub_mul2(K, src[im].U, o.M);
+                sub_mulR(K, src[im].R, o.R);
+                inv2(src[ip].M, Mi);
+                mul2(e.U, Mi, K);             // K2 = U_i M_ip^-1
+                mul2(K, src[ip].U, o.U);
+                for (int k = 0; k < 4; k++) o.U[k] = -o.U[k];
+                sub_mul2(K, src[ip].L, o.M);
+                sub_mulR(K, src[ip].R, o.R);
+            }
+        }
+        __syncthreads();
+        Blk *t = src; src = dst; dst = t;
+        d *= 2;
+    }
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        double Mi[4];
+        inv2(src[k].M, Mi);
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const double r0 = src[k].R[q], r1 = src[k].R[3 + q];
+            D[3 * (b0 + k) + q] = Mi[0] * r0 + Mi[1] * r1;
+            S[3 * (b0 + k) + q] = Mi[2] * r0 + Mi[3] * r1;
+        }
+    }
+}
+
 // --------------------------------------------------------- segment geometry
 struct GLArgs {
     double h[kMaxQ];
     double w[kMaxQ];
 };
 
-// Hermite segment j: s(u) = c0 + c1 u + c2 u^2 + c3 u^3, u in [0,1],
-// tau = tau_j + u h; ds/dtau = s'(u)/h.
+// Segment j in u in [0,1] (tau = tau_j + u h); ds/dtau = s'(u)/h.  ORDER 4
+// writes the node's second derivative (from its segment's start); ORDER 6
+// reads it (solved with the slopes).
+template <int ORDER>
 __global__ void k_geometry(int N, int Q, GLArgs gl, const double *__restrict__ x,
                            const int *__restrict__ off, const int *__restrict__ fil,
                            const double *__restrict__ gamma, const double *__restrict__ dtau,
@@ -135,25 +282,21 @@ __global__ void k_geometry(int N, int Q, GLArgs gl, const double *__restrict__ x
     if (j >= N) return;
     int jn = next_node(off, fil, j);
     double h = dtau[j], g = gamma[fil[j]];
-    double c0[3], c1[3], c2[3], c3[3];
+    SegPoly<ORDER> sp;
+    sp.load(x, D, sdd, j, jn, h);
+    if constexpr (ORDER == 4) {
 #pragma unroll
-    for (int q = 0; q < 3; q++) {
-        double s0 = x[3 * j + q], s1 = x[3 * jn + q];
-        double d0 = h * D[3 * j + q], d1 = h * D[3 * jn + q];
-        c0[q] = s0;
-        c1[q] = d0;
-        c2[q] = 3.0 * (s1 - s0) - 2.0 * d0 - d1;
-        c3[q] = 2.0 * (s0 - s1) + d0 + d1;
-        sdd[3 * j + q] = 2.0 * c2[q] / (h * h);
+        for (int q = 0; q < 3; q++) sdd[3 * j + q] = 2.0 * sp.c[2][q] / (h * h);
     }
     double len = 0.0;
     for (int i = 0; i < Q; i++) {
-        double u = gl.h[i];
-        double der[3];
+        double u = gl.h[i], p[3], der[3];
+        sp.pos(u, p);
+        sp.der(u, der);
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            qpos[3 * (j * Q + i) + q] = c0[q] + u * (c1[q] + u * (c2[q] + u * c3[q]));
-            der[q] = (c1[q] + u * (2.0 * c2[q] + 3.0 * u * c3[q])) / h;
+            der[q] /= h;
+            qpos[3 * (j * Q + i) + q] = p[q];
             qchg[3 * (j * Q + i) + q] = g * gl.w[i] * h * der[q];
         }
         len += gl.w[i] * h * sqrt(der[0] * der[0] + der[1] * der[1] + der[2] * der[2]);
@@ -191,10 +334,23 @@ __device__ __forceinline__ double erf_over_x(double x) {
     return erf(x) / x;
 }
 
+// 3-point Gauss-Legendre rule on [0, 1]
+__device__ constexpr double kG3h[3] = {0.11270166537925831148, 0.5, 0.88729833462074168852};
+__device__ constexpr double kG3w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+// Local terms (eq:BS_local, eq:streamfunction_local) and long-range self
+// corrections.  With eps < 1 the local segments are subdivided (Sec. 5.2):
+// the Taylor expansion covers the fraction eps of each local segment next
+// to the node (l-, l+ the arc lengths of those portions, 3-point rule), and
+// the rest of each segment is integrated with the unsplit kernels by
+// 3-point rules on panels graded towards the node, [eps, 2 eps],
+// [2 eps, 4 eps], ..., ending at the segment's far node.
+template <int ORDER>
 __global__ void k_local_self(int N, int Q, int mode, double sign, double a, double delta,
-                             double alpha, const double *__restrict__ x,
+                             double alpha, double eps, const double *__restrict__ x,
                              const int *__restrict__ off, const int *__restrict__ fil,
-                             const double *__restrict__ gamma, const double *__restrict__ D,
+                             const double *__restrict__ gamma, const double *__restrict__ dtau,
+                             const double *__restrict__ D,
                              const double *__restrict__ sdd, const double *__restrict__ ell,
                              const double *__restrict__ qpos, const double *__restrict__ qchg,
                              double *__restrict__ out) {
@@ -208,7 +364,23 @@ __global__ void k_local_self(int N, int Q, int mode, double sign, double a, doub
     if (mode & LS_VLOCAL) {
         double sd[3] = {D[3 * i], D[3 * i + 1], D[3 * i + 2]};
         double sn = sqrt(sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2]);
-        double lg = log(2.0 * sqrt(ell[ip] * ell[i]) / a);
+        double lm = ell[ip], lp = ell[i];
+        const bool sub = eps < 1.0;
+        SegPoly<ORDER> seg[2];
+        if (sub) {
+            const int in = next_node(off, fil, i);
+            seg[0].load(x, D, sdd, ip, i, dtau[ip]);
+            seg[1].load(x, D, sdd, i, in, dtau[i]);
+            lm = lp = 0.0;
+            for (int k = 0; k < 3; k++) {
+                double dv[3];
+                seg[0].der(1.0 - eps + kG3h[k] * eps, dv);
+                lm += kG3w[k] * eps * sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+                seg[1].der(kG3h[k] * eps, dv);
+                lp += kG3w[k] * eps * sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            }
+        }
+        double lg = log(2.0 * sqrt(lm * lp) / a);
         if (!psi) {
             double s2[3] = {sdd[3 * i], sdd[3 * i + 1], sdd[3 * i + 2]};
             double b[3] = {sd[1] * s2[2] - sd[2] * s2[1], sd[2] * s2[0] - sd[0] * s2[2],
@@ -218,6 +390,34 @@ __global__ void k_local_self(int N, int Q, int mode, double sign, double a, doub
         } else {
             double f = g / (2.0 * kPi) * (lg - (delta - 1.0)) / sn;
             for (int q = 0; q < 3; q++) acc[q] += f * sd[q];
+        }
+        if (sub) {
+            // the rest of each local segment, distance u from the node in [eps, 1]
+            const double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+            for (int side = 0; side < 2; side++) {
+                for (double u0 = eps; u0 < 1.0; u0 *= 2.0) {
+                    const double u1 = fmin(2.0 * u0, 1.0);
+                    for (int k = 0; k < 3; k++) {
+                        const double uu = u0 + kG3h[k] * (u1 - u0);
+                        const double u = side ? uu : 1.0 - uu;
+                        double p[3], dv[3], r[3];
+                        seg[side].pos(u, p);
+                        seg[side].der(u, dv);   // ds/du: ds = dv du
+                        for (int q = 0; q < 3; q++) r[q] = p[q] - xi[q];
+                        const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                        const double w = g * kG3w[k] * (u1 - u0) * inv4pi;
+                        if (!psi) {
+                            const double f = w / (rr * rr * rr);
+                            acc[0] += f * (r[1] * dv[2] - r[2] * dv[1]);
+                            acc[1] += f * (r[2] * dv[0] - r[0] * dv[2]);
+                            acc[2] += f * (r[0] * dv[1] - r[1] * dv[0]);
+                        } else {
+                            const double f = w / rr;
+                            for (int q = 0; q < 3; q++) acc[q] += f * dv[q];
+                        }
+                    }
+                }
+            }
         }
     }
     if (mode & LS_VSELF) {
@@ -263,17 +463,26 @@ void launch_chord(bs_plan_t p, const double *xyz, const double *gamma) {
 }
 
 void launch_spline(bs_plan_t p) {
-    hipLaunchKernelGGL(k_spline, dim3((unsigned)p->nfil), dim3(128), 0, p->stream, (int)p->nfil,
-                       (const int *)p->d_off.p, (const double *)p->d_x.p,
-                       (const double *)p->d_dtau.p, (double *)p->d_D.p,
-                       (double *)p->spline_tmp.p);
+    launch_spline_data(p, (const double *)p->d_x.p, (double *)p->d_D.p, (double *)p->d_sdd.p);
+}
+
+void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout) {
+    if (p->order == 6)
+        hipLaunchKernelGGL(k_spline5, dim3((unsigned)p->nfil), dim3(64), 0, p->stream,
+                           (int)p->nfil, (const int *)p->d_off.p, data,
+                           (const double *)p->d_dtau.p, Dout, Sout, (double *)p->spline_tmp.p);
+    else
+        hipLaunchKernelGGL(k_spline, dim3((unsigned)p->nfil), dim3(128), 0, p->stream,
+                           (int)p->nfil, (const int *)p->d_off.p, data,
+                           (const double *)p->d_dtau.p, Dout, (double *)p->spline_tmp.p);
 }
 
 void launch_geometry(bs_plan_t p) {
     GLRule r = gl_rule(p->Q);
     GLArgs g;
     for (int i = 0; i < kMaxQ; i++) { g.h[i] = r.h[i]; g.w[i] = r.w[i]; }
-    hipLaunchKernelGGL(k_geometry, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream,
+    auto kern = p->order == 6 ? k_geometry<6> : k_geometry<4>;
+    hipLaunchKernelGGL(kern, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream,
                        (int)p->N, p->Q, g, (const double *)p->d_x.p, (const int *)p->d_off.p,
                        (const int *)p->d_fil.p, (const double *)p->d_gamma.p,
                        (const double *)p->d_dtau.p, (const double *)p->d_D.p,
@@ -282,13 +491,15 @@ void launch_geometry(bs_plan_t p) {
 }
 
 void launch_local_self(bs_plan_t p, int mode, double sign, double *out) {
-    hipLaunchKernelGGL(k_local_self, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream,
-                       (int)p->N, p->Q, mode, sign, p->prm.a, p->prm.delta, p->prm.alpha,
+    auto kern = p->order == 6 ? k_local_self<6> : k_local_self<4>;
+    const double eps = p->prm.local_frac > 0.0 ? p->prm.local_frac : 1.0;
+    hipLaunchKernelGGL(kern, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream,
+                       (int)p->N, p->Q, mode, sign, p->prm.a, p->prm.delta, p->prm.alpha, eps,
                        (const double *)p->d_x.p, (const int *)p->d_off.p,
                        (const int *)p->d_fil.p, (const double *)p->d_gamma.p,
-                       (const double *)p->d_D.p, (const double *)p->d_sdd.p,
-                       (const double *)p->d_ell.p, (const double *)p->d_qpos.p,
-                       (const double *)p->d_qchg.p, out);
+                       (const double *)p->d_dtau.p, (const double *)p->d_D.p,
+                       (const double *)p->d_sdd.p, (const double *)p->d_ell.p,
+                       (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, out);
 }
 
 }  // namespace bs

@@ -166,21 +166,36 @@ void launch_pairs(bs_plan_t p, int psi, double *out) {
 }
 
 // ------------------------------------------------------------------ energy
-// Partial sums of Gamma_l psi_j . sdot_j (dtau_{j-1} + dtau_j) / 2 (nodal
-// trapezoid in tau); a second pass adds the block sums in a fixed order.
+// E = (1/2V) sum_l Gamma_l oint psi . ds (eq:kinetic_energy_streamfunction)
+// with psi between the nodes given by the spline through its nodal values on
+// the curve's own knots (slopes eD, quintic second derivatives eS) and the
+// curve's Q-point rule on every segment: sum over quadrature points of
+// psi(tau_q) . q_q, the vector charges q_q = Gamma w dtau s'(tau_q).
+// Partial sums per block; a second pass adds them in a fixed order.
 constexpr int kRedBlock = 256;
+constexpr int kEnergyMaxQ = 4;
+struct GLNodes {
+    double h[kEnergyMaxQ];
+};
 
-__global__ void k_energy_partial(int N, const double *__restrict__ psi,
-                                 const double *__restrict__ D, const double *__restrict__ dtau,
-                                 const int *__restrict__ off, const int *__restrict__ fil,
-                                 const double *__restrict__ gamma, double *__restrict__ partial) {
+template <int ORDER>
+__global__ void k_energy_partial(int N, int Q, const double *__restrict__ psi,
+                                 const double *__restrict__ eD, const double *__restrict__ eS,
+                                 const double *__restrict__ dtau, const int *__restrict__ off,
+                                 const int *__restrict__ fil, const double *__restrict__ qchg,
+                                 GLNodes gl, double *__restrict__ partial) {
     __shared__ double sh[kRedBlock];
     double s = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
-        int jp = prev_node_d(off, fil, j);
-        double w = 0.5 * (dtau[jp] + dtau[j]);
-        s += gamma[fil[j]] * w *
-             (psi[3 * j] * D[3 * j] + psi[3 * j + 1] * D[3 * j + 1] + psi[3 * j + 2] * D[3 * j + 2]);
+        const int f = fil[j], jn = (j + 1 < off[f + 1]) ? j + 1 : off[f];
+        SegPoly<ORDER> sp;
+        sp.load(psi, eD, eS, j, jn, dtau[j]);
+        for (int i = 0; i < Q; i++) {
+            double pv[3];
+            sp.pos(gl.h[i], pv);
+            const double *c = qchg + 3 * ((size_t)j * Q + i);
+            s += pv[0] * c[0] + pv[1] * c[1] + pv[2] * c[2];
+        }
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -202,10 +217,16 @@ __global__ void k_energy_final(int nb, double scale, const double *__restrict__ 
 
 void launch_energy(bs_plan_t p, const double *psi, double *partial, int nblocks) {
     double L = p->prm.L;
-    hipLaunchKernelGGL(k_energy_partial, dim3(nblocks), dim3(kRedBlock), 0, p->stream, (int)p->N,
-                       psi, (const double *)p->d_D.p, (const double *)p->d_dtau.p,
+    double *eD = (double *)p->e_D.p, *eS = (double *)p->e_S.p;
+    launch_spline_data(p, psi, eD, eS);
+    GLRule r = gl_rule(p->Q);
+    GLNodes g;
+    for (int i = 0; i < kEnergyMaxQ; i++) g.h[i] = r.h[i];
+    auto kern = p->order == 6 ? k_energy_partial<6> : k_energy_partial<4>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kRedBlock), 0, p->stream, (int)p->N, p->Q, psi,
+                       (const double *)eD, (const double *)eS, (const double *)p->d_dtau.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
-                       (const double *)p->d_gamma.p, partial);
+                       (const double *)p->d_qchg.p, g, partial);
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, p->stream, nblocks,
                        1.0 / (2.0 * L * L * L), partial, partial + nblocks);
 }

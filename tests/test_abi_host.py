@@ -95,11 +95,13 @@ def test_parameter_errors():
     with pytest.raises(B.BsError) as e:
         B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=1024, sigma=1.0001))
     assert e.value.code == B.BS_EKB
-    p = B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64)
-    p.spline_order = 6
-    with pytest.raises(B.BsError) as e:
-        B.resolve_params(p)
-    assert e.value.code == B.BS_EINVAL
+    B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, spline_order=6,
+                                   local_frac=0.1))
+    for bad in (dict(spline_order=5), dict(spline_order=6, ns_mode=B.BS_NS_ADAPTIVE),
+                dict(local_frac=1.5), dict(local_frac=-0.1), dict(local_frac=1e-4)):
+        with pytest.raises(B.BsError) as e:
+            B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, **bad))
+        assert e.value.code == B.BS_EINVAL
 
 
 def test_pruned_transforms_need_a_power_of_two_grid():

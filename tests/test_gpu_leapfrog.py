@@ -1,10 +1,12 @@
 """Energy and impulse conservation of two leapfrogging elliptical rings
-(Sec. 5.2): RK4 with the spline refitted at every stage, Delta t =
-T_kw(d_min), beta = 3.5 and alpha = 7/L (r_c = L/2).  The energy E of
-eq:kinetic_energy_streamfunction and the axial impulse p_x stay constant to
-the 1e-6 accuracy of the computation while the vortex length changes by
-about a percent; the energy E' = E - (kappa^2 / 4 pi V) * length, obtained
-with the velocity's cut-off in the streamfunction, is not conserved."""
+(Sec. 5.2, Fig. leapfrogging_rings) on the GPU: quintic splines, Q = 3, the
+local segments subdivided with the Taylor expansion on 10 % of each,
+beta = 3.5, alpha = 7/L (r_c = L/2), RK4 with the spline refitted at every
+stage and Delta t = T_kw(d_min), up to t = 2.5 R_a^2/kappa (the first
+passage).  E of eq:kinetic_energy_streamfunction and the axial impulse p_x
+stay constant to the computation's ~1e-6 accuracy while the vortex length
+varies by about 2 %; E' = E - (kappa^2 / 4 pi V) * length, the energy with the
+velocity's cut-off in the streamfunction, is not conserved."""
 import math
 
 import numpy as np
@@ -17,6 +19,7 @@ EULER_GAMMA = 0.5772156649015329
 
 
 def kelvin_period(lam, a, delta=0.25, kappa=1.0):
+    """Sec. 5.2: period of a Kelvin wave of wavelength lam."""
     return 2 * lam ** 2 / kappa / (math.log(lam / (math.pi * a)) + 0.5 - (delta + EULER_GAMMA))
 
 
@@ -28,11 +31,9 @@ def B():
     return binding
 
 
-@pytest.mark.skip(reason="cubic splines leave a 1.7% curvature error at 32 nodes per ring; "
-                         "energy and impulse then drift by ~1e-3 (the oracle shows the same)")
 def test_leapfrogging_rings_conserve_energy_and_impulse(B):
     import torch
-    fs = W.leapfrog()
+    fs = W.leapfrog(a=1e-8)
     L, V = fs.L, fs.L ** 3
     Ra = L / 4
     dmin = 2 * math.pi * Ra / 32
@@ -40,7 +41,8 @@ def test_leapfrogging_rings_conserve_energy_and_impulse(B):
     t_end = 2.5 * Ra ** 2                  # up to the first passage (times in R_a^2 / kappa)
     steps = int(math.ceil(t_end / dt))
     print(f"\n[case] leapfrog N={fs.n_nodes} dt={dt:.4e} steps={steps}", flush=True)
-    plan = B.Plan(B.params_for(fs, alpha=7.0 / L, rcut=L / 2))
+    plan = B.Plan(B.params_for(fs, alpha=7.0 / L, rcut=L / 2, Q=3, spline_order=6,
+                               local_frac=0.1))
     p = plan.params()
     assert p.beta == 3.5 and abs(p.rcut - L / 2) < 1e-14
     xyz, g = B.load_workload(fs)
@@ -73,7 +75,7 @@ def test_leapfrogging_rings_conserve_energy_and_impulse(B):
     x_adv = (x.cpu().numpy()[:, 0] - fs.xyz[:, 0]).mean()
     print(f"  t={steps * dt:.3f}: max |dE/E| {dE:.2e}, |dp_x/p_x| {dp:.2e}, |dL/L| {dL:.2e}, "
           f"|dE'/E'| {dEp:.2e}, mean x advance {x_adv:.3f}")
-    assert x_adv > 0.5                     # the rings travel along +x
-    assert dL > 1e-3                       # the length changes (shape oscillations)
-    assert dE < 2e-6 and dp < 2e-6
-    assert dEp > 30 * dE                   # E' is not conserved
+    assert x_adv > 3.0                     # the rings travel along +x
+    assert 1e-2 < dL < 5e-2                # the length changes by about 2 %
+    assert dE < 3e-6 and dp < 1e-5
+    assert dEp > 100 * dE                  # E' is not conserved
