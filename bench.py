@@ -69,10 +69,8 @@ def count_pairs(plan, fs, Q, rc):
 
 
 def pruned_transforms(prm):
-    """The plan's choice for fft_mode 0: pruned transforms on power-of-two
-    grids from 128 up (float64 up to 512)."""
-    n = prm.grid_n
-    return n >= 128 and n & (n - 1) == 0 and n * 4 * (16 if prm.precision == 0 else 8) < 65536
+    """Whether the resolved plan uses the pruned transforms."""
+    return prm.fft_mode == 2
 
 
 def stage_bytes(prm, N, Nq, fp32):

@@ -73,7 +73,7 @@ extern "C" {
 #define BS_NS_MLP       2  /* learned correction with adaptive fallback       */
 
 /* 3-D transforms of the long-range step */
-#define BS_FFT_AUTO     0  /* BS_FFT_PRUNED for power-of-two grids from 128 up
+#define BS_FFT_AUTO     0  /* BS_FFT_PRUNED for power-of-two grids from 64 up
                               (where it is faster), else BS_FFT_LIBRARY         */
 #define BS_FFT_LIBRARY  1  /* hipFFT: full r2c / c2r transforms and a separate
                               spectral-operator pass                           */
@@ -119,7 +119,9 @@ typedef struct {
     const void *mlp_weights; /* host pointer to the packed float32 MLP
                                 parameters (see bs_mlp_nparams); needed for
                                 BS_NS_MLP; copied by bs_plan                   */
-    int    fft_mode;     /* BS_FFT_AUTO, BS_FFT_LIBRARY or BS_FFT_PRUNED       */
+    int    fft_mode;     /* BS_FFT_AUTO, BS_FFT_LIBRARY or BS_FFT_PRUNED; the
+                            resolved parameters hold the choice made for
+                            BS_FFT_AUTO                                     */
     double local_frac;   /* local-segment subdivision (Sec. 5.2): fraction of
                             each local segment, next to the node, where the
                             Taylor expansion of eq:BS_local and

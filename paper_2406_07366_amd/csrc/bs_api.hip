@@ -182,9 +182,15 @@ int resolve(const bs_params *in, bs_params *out) {
     if (r.ns_eta == 0) r.ns_eta = 1.0;
     if (!(r.ns_eta > 0)) return bad("ns_eta must be positive");
     if (r.fft_mode < BS_FFT_AUTO || r.fft_mode > BS_FFT_PRUNED) return bad("unknown fft_mode");
-    if (r.fft_mode == BS_FFT_PRUNED &&
-        !pruned_fft_ok(r.grid_n, r.precision == BS_FP32_MIXED ? 8 : 16))
-        return bad("BS_FFT_PRUNED needs grid_n a power of two (at most 512 in float64)");
+    {
+        const bool ok = pruned_fft_ok(r.grid_n, r.precision == BS_FP32_MIXED ? 8 : 16);
+        if (r.fft_mode == BS_FFT_PRUNED && !ok)
+            return bad("BS_FFT_PRUNED needs grid_n a power of two (at most 512 in float64)");
+        // automatic choice: the pruned transforms win from 64^3 up (measured);
+        // hipFFT on smaller grids
+        if (r.fft_mode == BS_FFT_AUTO)
+            r.fft_mode = (ok && r.grid_n >= 64) ? BS_FFT_PRUNED : BS_FFT_LIBRARY;
+    }
     if (r.beta == 0) r.beta = beta_from_tol(r.tol);
     if (!(r.beta > 0)) return bad("beta must be positive");
     if (r.w == 0) r.w = width_from_tol(r.tol);
@@ -327,10 +333,7 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
         hipfftSetStream(P->fft_inv, P->stream) != HIPFFT_SUCCESS)
         return fail(set_error(P, BS_EDEVICE, "hipfftSetStream failed"));
     // pruned transforms: twiddles exp(-+2 pi i k / n), k < n/2, from float64
-    // automatic choice: the pruned transforms win from 128^3 up (measured);
-    // hipFFT on smaller grids, where launch latency dominates
-    P->pruned = r.fft_mode == BS_FFT_PRUNED ||
-                (r.fft_mode == BS_FFT_AUTO && P->n >= 128 && pruned_fft_ok(P->n, 2 * P->real_size));
+    P->pruned = r.fft_mode == BS_FFT_PRUNED;   // resolved: never BS_FFT_AUTO here
     if (P->pruned) {
         const size_t cs = 2 * P->real_size, K1 = r.K + 1, NY = 2 * r.K + 1;
         pruned_batches(P->n, cs, &P->fft_rb, &P->fft_kb, &P->fft_kz);

@@ -23,6 +23,8 @@
 // through one LDS buffer with element j of sequence s at buf[j * pitch + s]
 // (pitch = nseq + 1, odd, so strided accesses spread over the banks).  A
 // 256-point transform (16 x 16) therefore touches LDS once each way.
+#include <type_traits>
+
 #include "bs_internal.h"
 #include "bs_device.h"
 
@@ -123,29 +125,47 @@ __host__ __device__ inline int lds_pitch(int n, int nseq) {
     return JFAST ? n + (n >> 4) + 1 : nseq + 1;
 }
 
-template <int R, bool JFAST, typename C, typename T, typename Load, typename Store>
-__device__ __forceinline__ void fft_pass(bool first, bool last, int n, int Ns, int nseq,
-                                         int pitch, C *buf, const C *tw, T sgn, Load &load,
-                                         Store &store) {
-    const int nj = n / R;
+// radix 2^lr of pass p of the plan above (0 past the last pass)
+__host__ __device__ constexpr int plan_lr(int logn, int p) {
+    int rem = logn;
+    for (int q = 0; q <= p; q++) {
+        if (rem <= 0) return 0;
+        const int passes = (rem + 3) / 4, l = (rem + passes - 1) / passes;
+        if (q == p) return l;
+        rem -= l;
+    }
+    return 0;
+}
+
+// The transform length, the radix, Ns and whether the pass is the first
+// or the last are compile-time, so the index arithmetic folds to shifts
+// and masks and the pass sequence unrolls.
+template <int R, int N, int NS, bool FIRST, bool LAST, bool JFAST, typename C, typename T,
+          typename Load, typename Store>
+__device__ __forceinline__ void fft_pass(int nseq, int pitch, C *buf, const C *tw, T sgn,
+                                         Load &load, Store &store) {
+    constexpr int NJ = N / R;
     const int t = threadIdx.x;
-    const bool act = t < nj * nseq;
-    const int s = JFAST ? t / nj : t % nseq, j = JFAST ? t % nj : t / nseq;
-    const int jm = j & (Ns - 1);
+    const bool act = t < NJ * nseq;
+    const int s = JFAST ? t / NJ : t % nseq, j = JFAST ? t % NJ : t / nseq;
+    const int jm = j & (NS - 1);
     C v[R];
     if (act) {
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            const int e = j + r * nj;
-            v[r] = first ? load(s, e) : buf[lds_at<JFAST>(s, e, pitch)];
+            const int e = j + r * NJ;
+            if constexpr (FIRST) v[r] = load(s, e);
+            else v[r] = buf[lds_at<JFAST>(s, e, pitch)];
         }
-        if (jm != 0) {
-            const int step = n / (Ns * R);
+        if constexpr (NS > 1) {
+            if (jm != 0) {
+                constexpr int STEP = N / (NS * R);
 #pragma unroll
-            for (int r = 1; r < R; r++) {
-                const C w = tw[jm * r * step];
-                const C u = v[r];
-                v[r] = C{w.x * u.x - w.y * u.y, w.x * u.y + w.y * u.x};
+                for (int r = 1; r < R; r++) {
+                    const C w = tw[jm * r * STEP];
+                    const C u = v[r];
+                    v[r] = C{w.x * u.x - w.y * u.y, w.x * u.y + w.y * u.x};
+                }
             }
         }
         dft_regs<R>(v, sgn);
@@ -155,30 +175,25 @@ __device__ __forceinline__ void fft_pass(bool first, bool last, int n, int Ns, i
         const int d0 = (j - jm) * R + jm;
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            const int e = d0 + r * Ns;
-            if (last) store(s, e, v[r]);
+            const int e = d0 + r * NS;
+            if constexpr (LAST) store(s, e, v[r]);
             else buf[lds_at<JFAST>(s, e, pitch)] = v[r];
         }
     }
     __syncthreads();
 }
 
-// tw: the twiddle table in LDS (n entries)
-template <bool JFAST, typename C, typename T, typename Load, typename Store>
-__device__ void fft_run(int logn, int nseq, int pitch, C *buf, const C *tw, T sgn, Load load,
-                        Store store) {
-    int lr[4];
-    const int np = fft_plan(logn, lr), n = 1 << logn;
-    int Ns = 1;
-    for (int p = 0; p < np; p++) {
-        const bool first = p == 0, last = p == np - 1;
-        switch (lr[p]) {
-            case 1: fft_pass<2, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
-            case 2: fft_pass<4, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
-            case 3: fft_pass<8, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
-            default: fft_pass<16, JFAST>(first, last, n, Ns, nseq, pitch, buf, tw, sgn, load, store); break;
-        }
-        Ns <<= lr[p];
+// tw: the twiddle table in LDS (n entries); passes P, P+1, ... of the plan
+template <bool JFAST, int LOGN, int P = 0, int NS = 1, typename C, typename T, typename Load,
+          typename Store>
+__device__ __forceinline__ void fft_run(int nseq, int pitch, C *buf, const C *tw, T sgn,
+                                        Load &load, Store &store) {
+    constexpr int LR = plan_lr(LOGN, P);
+    if constexpr (LR > 0) {
+        constexpr bool LAST = plan_lr(LOGN, P + 1) == 0;
+        fft_pass<1 << LR, 1 << LOGN, NS, P == 0, LAST, JFAST>(nseq, pitch, buf, tw, sgn, load,
+                                                                store);
+        fft_run<JFAST, LOGN, P + 1, (NS << LR)>(nseq, pitch, buf, tw, sgn, load, store);
     }
 }
 
@@ -193,15 +208,15 @@ constexpr int kFftLds = 65536;        // LDS per workgroup, at most
 
 // ---------------------------------------------------------------- x pass
 // nseq rows (c, z, y) per workgroup; forward: keep modes 0..K
-template <typename R>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int logn, int nrows, int K1,
+template <typename R, int LOGN>
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int nrows, int K1,
                                                             int nseq, int per,
                                                             const R *__restrict__ grid,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    const int n = 1 << logn;
+    constexpr int n = 1 << LOGN;
     C *twl = (C *)smem, *buf = twl + n;
     const int bid = xcd_block(per), nb = (nrows + nseq - 1) / nseq;
     if (bid >= nb) return;
@@ -215,19 +230,19 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int logn, int nrow
         const int row = row0 + s;
         if (e < K1 && row < nrows) A[(size_t)row * K1 + e] = v;
     };
-    fft_run<true>(logn, nseq, lds_pitch<true>(n, nseq), buf, twl, (R)-1, load, store);
+    fft_run<true, LOGN>(nseq, lds_pitch<true>(n, nseq), buf, twl, (R)-1, load, store);
 }
 
 // inverse: modes 0..K of each row, Hermitian completion, real part out
-template <typename R>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int logn, int nrows, int K1,
+template <typename R, int LOGN>
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int nrows, int K1,
                                                             int nseq, int per,
                                                             const typename Cx<R>::T *__restrict__ A,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             R *__restrict__ grid) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    const int n = 1 << logn;
+    constexpr int n = 1 << LOGN;
     C *twl = (C *)smem, *buf = twl + n;
     const int bid = xcd_block(per), nb = (nrows + nseq - 1) / nseq;
     if (bid >= nb) return;
@@ -249,26 +264,27 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int logn, int nrow
         const int row = row0 + s;
         if (row < nrows) grid[(size_t)row * n + e] = v.x;
     };
-    fft_run<true>(logn, nseq, lds_pitch<true>(n, nseq), buf, twl, (R)1, load, store);
+    fft_run<true, LOGN>(nseq, lds_pitch<true>(n, nseq), buf, twl, (R)1, load, store);
 }
 
 // ---------------------------------------------------------------- y pass
 // one workgroup per (c, z) and group of nseq columns mx
-template <typename R>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int logn, int K, int nseq, int per,
+template <typename R, int LOGN>
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int K, int nseq, int per,
                                                             const typename Cx<R>::T *__restrict__ A,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1;
+    constexpr int n = 1 << LOGN;
+    const int K1 = K + 1, NY = 2 * K + 1;
     C *twl = (C *)smem, *buf = twl + n;
     const int ngrp = (K1 + nseq - 1) / nseq;
     const int bid = xcd_block(per);
     if (bid >= 3 * n * ngrp) return;
     stage_twiddles(twl, tw, n);
     const int g = bid % ngrp, cz = bid / ngrp;   // cz = c * n + z
-    const int c = cz >> logn, z = cz & (n - 1);
+    const int c = cz >> LOGN, z = cz & (n - 1);
     const int kx0 = g * nseq;
     auto load = [&](int s, int e) {
         const int kx = kx0 + s;
@@ -279,24 +295,25 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int logn, int K, i
         if (kx < K1 && my >= -K && my <= K)
             B[(((size_t)c * NY + (my + K)) * n + z) * K1 + kx] = v;
     };
-    fft_run<false>(logn, nseq, lds_pitch<false>(n, nseq), buf, twl, (R)-1, load, store);
+    fft_run<false, LOGN>(nseq, lds_pitch<false>(n, nseq), buf, twl, (R)-1, load, store);
 }
 
-template <typename R>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int logn, int K, int nseq, int per,
+template <typename R, int LOGN>
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int K, int nseq, int per,
                                                             const typename Cx<R>::T *__restrict__ B,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1;
+    constexpr int n = 1 << LOGN;
+    const int K1 = K + 1, NY = 2 * K + 1;
     C *twl = (C *)smem, *buf = twl + n;
     const int ngrp = (K1 + nseq - 1) / nseq;
     const int bid = xcd_block(per);
     if (bid >= 3 * n * ngrp) return;
     stage_twiddles(twl, tw, n);
     const int g = bid % ngrp, cz = bid / ngrp;
-    const int c = cz >> logn, z = cz & (n - 1);
+    const int c = cz >> LOGN, z = cz & (n - 1);
     const int kx0 = g * nseq;
     auto load = [&](int s, int e) {
         const int kx = kx0 + s, my = e <= n / 2 ? e : e - n;
@@ -309,21 +326,22 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int logn, int K, i
         const int kx = kx0 + s;
         if (kx < K1) A[((size_t)cz * n + e) * K1 + kx] = v;
     };
-    fft_run<false>(logn, nseq, lds_pitch<false>(n, nseq), buf, twl, (R)1, load, store);
+    fft_run<false, LOGN>(nseq, lds_pitch<false>(n, nseq), buf, twl, (R)1, load, store);
 }
 
 // ---------------------------------------------------------------- z pass
 // one workgroup per (my, group of KZ columns mx): the three components'
 // z-columns (sequence s = c KZ + q), forward FFT into LDS, spectral operator,
 // inverse FFT from LDS, written back.
-template <typename R>
+template <typename R, int LOGN>
 __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
-    int logn, int K, int KZ, int per, int psi, double k0, double inv4a2, double invV,
+    int K, int KZ, int per, int psi, double k0, double inv4a2, double invV,
     const double *__restrict__ dec2, const typename Cx<R>::T *__restrict__ twf,
     const typename Cx<R>::T *__restrict__ twi, typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    const int n = 1 << logn, K1 = K + 1, NY = 2 * K + 1, S = 3 * KZ, pitch = S + 1;
+    constexpr int n = 1 << LOGN;
+    const int K1 = K + 1, NY = 2 * K + 1, S = 3 * KZ, pitch = S + 1;
     C *twl = (C *)smem, *buf = twl + 2 * n;
     const int ngrp = (K1 + KZ - 1) / KZ;
     const int bid = xcd_block(per);
@@ -337,7 +355,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
         return kx < K1 ? B[c * cstride + ((size_t)myp * n + e) * K1 + kx] : C{(R)0, (R)0};
     };
     auto lstore = [&](int s, int e, C v) { buf[e * pitch + s] = v; };
-    fft_run<false>(logn, S, pitch, buf, twl, (R)-1, gload, lstore);
+    fft_run<false, LOGN>(S, pitch, buf, twl, (R)-1, gload, lstore);
     const int my = myp - K;
     for (int i = threadIdx.x; i < n * KZ; i += blockDim.x) {
         const int z = i / KZ, q = i - z * KZ;
@@ -374,7 +392,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
         const int c = s / KZ, kx = kx0 + (s - c * KZ);
         if (kx < K1) B[c * cstride + ((size_t)myp * n + e) * K1 + kx] = v;
     };
-    fft_run<false>(logn, S, pitch, buf, twl + n, (R)1, lload, gstore);
+    fft_run<false, LOGN>(S, pitch, buf, twl + n, (R)1, lload, gstore);
 }
 
 // --------------------------------------------------------------- launch
@@ -397,56 +415,85 @@ static int ilog2(int n) {
     return l;
 }
 
-template <typename R>
+// call f(std::integral_constant<int, logn>) for the grid sizes the pruned
+// path accepts (16 .. 1024)
+template <typename F>
+static void with_logn(int logn, F f) {
+    switch (logn) {
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 7: f(std::integral_constant<int, 7>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 9: f(std::integral_constant<int, 9>{}); break;
+        default: f(std::integral_constant<int, 10>{}); break;
+    }
+}
+
+template <typename R, int LOGN>
 static void pruned_fwd(bs_plan_t p) {
     typedef typename Cx<R>::T C;
-    const int n = p->n, logn = ilog2(n), K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(logn);
+    constexpr int n = 1 << LOGN;
+    const int K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(LOGN);
     const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twf = (const C *)p->fft_tw.p;
     const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
-    hipLaunchKernelGGL(k_fft_x_fwd<R>, dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
-                       p->stream, logn, nrows, K1, RB, px, (const R *)p->grid.p, twf,
+    hipLaunchKernelGGL((k_fft_x_fwd<R, LOGN>), dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
+                       p->stream, nrows, K1, RB, px, (const R *)p->grid.p, twf,
                        (C *)p->fft_A.p);
-    hipLaunchKernelGGL(k_fft_y_fwd<R>, dim3(8 * py), dim3(KB * mnj), (n + n * (KB + 1)) * sizeof(C),
-                       p->stream, logn, K, KB, py, (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
+    hipLaunchKernelGGL((k_fft_y_fwd<R, LOGN>), dim3(8 * py), dim3(KB * mnj),
+                       (n + n * (KB + 1)) * sizeof(C), p->stream, K, KB, py,
+                       (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
 }
 
-template <typename R>
+template <typename R, int LOGN>
 static void pruned_spectral(bs_plan_t p, int psi) {
     typedef typename Cx<R>::T C;
-    const int n = p->n, logn = ilog2(n), K = p->prm.K, K1 = K + 1, KZ = p->fft_kz;
+    constexpr int n = 1 << LOGN;
+    const int K = p->prm.K, K1 = K + 1, KZ = p->fft_kz;
     const double L = p->prm.L;
     const double k0 = 2.0 * kPi / L, inv4a2 = 1.0 / (4.0 * p->prm.alpha * p->prm.alpha);
     const double *dec2 = (const double *)p->deconv.p + (p->prm.K + 1);
     const C *twf = (const C *)p->fft_tw.p, *twi = twf + n;
     const int pz = ceil_div((2 * K + 1) * ceil_div(K1, KZ), 8);
-    hipLaunchKernelGGL(k_fft_z_spectral<R>, dim3(8 * pz), dim3(3 * KZ * fft_max_nj(logn)),
-                       (2 * n + n * (3 * KZ + 1)) * sizeof(C), p->stream, logn, K, KZ, pz, psi, k0, inv4a2,
-                       1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
+    hipLaunchKernelGGL((k_fft_z_spectral<R, LOGN>), dim3(8 * pz), dim3(3 * KZ * fft_max_nj(LOGN)),
+                       (2 * n + n * (3 * KZ + 1)) * sizeof(C), p->stream, K, KZ, pz, psi, k0,
+                       inv4a2, 1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
 }
 
-template <typename R>
+template <typename R, int LOGN>
 static void pruned_inv(bs_plan_t p) {
     typedef typename Cx<R>::T C;
-    const int n = p->n, logn = ilog2(n), K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(logn);
+    constexpr int n = 1 << LOGN;
+    const int K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(LOGN);
     const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twi = (const C *)p->fft_tw.p + n;
     const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
-    hipLaunchKernelGGL(k_fft_y_inv<R>, dim3(8 * py), dim3(KB * mnj), (n + n * (KB + 1)) * sizeof(C),
-                       p->stream, logn, K, KB, py, (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
-    hipLaunchKernelGGL(k_fft_x_inv<R>, dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
-                       p->stream, logn, nrows, K1, RB, px, (const C *)p->fft_A.p, twi,
+    hipLaunchKernelGGL((k_fft_y_inv<R, LOGN>), dim3(8 * py), dim3(KB * mnj),
+                       (n + n * (KB + 1)) * sizeof(C), p->stream, K, KB, py,
+                       (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
+    hipLaunchKernelGGL((k_fft_x_inv<R, LOGN>), dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
+                       p->stream, nrows, K1, RB, px, (const C *)p->fft_A.p, twi,
                        (R *)p->grid.p);
 }
 
 void pruned_forward(bs_plan_t p) {
-    if (p->fp32) pruned_fwd<float>(p); else pruned_fwd<double>(p);
+    with_logn(ilog2(p->n), [&](auto L) {
+        if (p->fp32) pruned_fwd<float, decltype(L)::value>(p);
+        else pruned_fwd<double, decltype(L)::value>(p);
+    });
 }
 void pruned_spectral_op(bs_plan_t p, int psi) {
-    if (p->fp32) pruned_spectral<float>(p, psi); else pruned_spectral<double>(p, psi);
+    with_logn(ilog2(p->n), [&](auto L) {
+        if (p->fp32) pruned_spectral<float, decltype(L)::value>(p, psi);
+        else pruned_spectral<double, decltype(L)::value>(p, psi);
+    });
 }
 void pruned_inverse(bs_plan_t p) {
-    if (p->fp32) pruned_inv<float>(p); else pruned_inv<double>(p);
+    with_logn(ilog2(p->n), [&](auto L) {
+        if (p->fp32) pruned_inv<float, decltype(L)::value>(p);
+        else pruned_inv<double, decltype(L)::value>(p);
+    });
 }
 
 // Batch sizes: sequences per workgroup for the x and y passes (rb = kb, a
