@@ -231,9 +231,11 @@ int bs_status(bs_plan_t plan);
  * stream and synchronise at their end; bs_stage_times returns the summed
  * milliseconds and the number of timed launches of each stage (arrays of
  * BS_NSTAGES, either may be NULL) and optionally resets them.  Stages:
- *   0 geometry (chord lengths, spline solve, quadrature points)
+ *   0 geometry (chord lengths, spline solve, quadrature points, and the
+ *     velocity's local and self terms, all in one kernel)
  *   1 binning (counting sorts and sorted copies)
- *   2 local and self terms      3 spread        4 forward FFT
+ *   2 (unused: the local and self terms are part of stage 0)
+ *                               3 spread        4 forward FFT
  *   5 spectral operator         6 inverse FFT   7 interpolation
  *   8 short-range pairs         9 near-singular correction
  *  10 near-singular pair search (in bs_set_filaments, when ns_mode is on) */

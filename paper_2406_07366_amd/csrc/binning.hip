@@ -113,6 +113,24 @@ __global__ void k_zero_bins(SortSet S) {
         if (i <= S.nbins[a]) { S.cnt[a][i] = 0; S.fill[a][i] = 0; }
 }
 
+// spread-tile key of a quadrature point and pair-cell key of a position
+__device__ __forceinline__ int tile_key(const double *p, double L, double inv_h, int w, int n,
+                                        int T, int NT) {
+    double f;
+    const int bx = stencil_base(wrap_box(p[0], L), inv_h, w, n, &f);
+    const int by = stencil_base(wrap_box(p[1], L), inv_h, w, n, &f);
+    const int bz = stencil_base(wrap_box(p[2], L), inv_h, w, n, &f);
+    return ((bz / T) * NT + by / T) * NT + bx / T;
+}
+__device__ __forceinline__ int cell_key(const double *p, double L, int nc) {
+    int c[3];
+    for (int q = 0; q < 3; q++) {
+        const int v = (int)(wrap_box(p[q], L) / L * nc);
+        c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+    }
+    return (c[2] * nc + c[1]) * nc + c[0];
+}
+
 // keys of the three sets; counts by wavefront-aggregated atomics (items
 // that are neighbours along a filament mostly share a tile or cell)
 __global__ void k_keys_all(SortSet S, const double *__restrict__ qpos,
@@ -123,30 +141,13 @@ __global__ void k_keys_all(SortSet S, const double *__restrict__ qpos,
     const bool isq = i < Mq, isn = !isq && i < Mq + S.nitems[2];
     int k0 = 0, k1 = 0, k2 = 0;
     if (isq) {
-        double f;
-        double w0 = wrap_box(qpos[3 * i], L), w1 = wrap_box(qpos[3 * i + 1], L),
-               w2 = wrap_box(qpos[3 * i + 2], L);
-        int bx = stencil_base(w0, inv_h, w, n, &f);
-        int by = stencil_base(w1, inv_h, w, n, &f);
-        int bz = stencil_base(w2, inv_h, w, n, &f);
-        k0 = ((bz / T) * NT + by / T) * NT + bx / T;
+        k0 = tile_key(qpos + 3 * i, L, inv_h, w, n, T, NT);
         S.key[0][i] = k0;
-        double ws[3] = {w0, w1, w2};
-        int c[3];
-        for (int q = 0; q < 3; q++) {
-            int v = (int)(ws[q] / L * nc);
-            c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
-        }
-        k1 = (c[2] * nc + c[1]) * nc + c[0];
+        k1 = cell_key(qpos + 3 * i, L, nc);
         S.key[1][i] = k1;
     } else if (isn) {
-        int j = i - Mq;
-        int c[3];
-        for (int q = 0; q < 3; q++) {
-            int v = (int)(wrap_box(x[3 * j + q], L) / L * nc);
-            c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
-        }
-        k2 = (c[2] * nc + c[1]) * nc + c[0];
+        const int j = i - Mq;
+        k2 = cell_key(x + 3 * j, L, nc);
         S.key[2][j] = k2;
     }
     wave_add<false>(S.cnt[0], k0, isq);
@@ -205,27 +206,32 @@ __global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
 // sorted copies for the spread (by tile) and the pairs (by cell), one pass;
 // thread (p, d) handles axis d of sorted entry p (its stencil base and w
 // kernel values, and component d of the charges and pair position)
+struct GatherOut {
+    int4 *base;
+    void *ker, *q, *schg;
+    double4 *spos;
+    int *sseg;
+};
+
 template <typename R>
-__global__ void k_gather_all(int M, int w, int Q, const int *__restrict__ sperm,
-                             const int *__restrict__ pperm, const double *__restrict__ pos,
-                             const double *__restrict__ chg, double L, double inv_h, int n,
-                             double zeta, double inv_den, int4 *__restrict__ base,
-                             R *__restrict__ ker, R *__restrict__ q, double4 *__restrict__ spos,
-                             R *__restrict__ schg, int *__restrict__ sseg) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * M) return;
+__device__ __forceinline__ void gather_one(int t, int w, int Q, const int *__restrict__ sperm,
+                                           const int *__restrict__ pperm,
+                                           const double *__restrict__ pos,
+                                           const double *__restrict__ chg, double L, double inv_h,
+                                           int n, double zeta, double inv_den, const GatherOut &G) {
     const int p = t / 3, d = t - 3 * p;
+    R *ker = (R *)G.ker, *q = (R *)G.q, *schg = (R *)G.schg;
     int o = sperm[p];
     double f;
     const int b = stencil_base(wrap_box(pos[3 * o + d], L), inv_h, w, n, &f);
     const double half = 0.5 * w;
     for (int k = 0; k < w; k++)
         ker[((size_t)p * 3 + d) * w + k] = (R)kb_phi((k - f) / half, zeta, inv_den);
-    int *bp = (int *)(base + p);
+    int *bp = (int *)(G.base + p);
     bp[d] = b;
     q[4 * (size_t)p + d] = (R)chg[3 * o + d];
     o = pperm[p];
-    double *sp = (double *)(spos + p);
+    double *sp = (double *)(G.spos + p);
     sp[d] = wrap_box(pos[3 * o + d], L);
     schg[4 * (size_t)p + d] = (R)chg[3 * o + d];
     if (d == 0) {
@@ -233,8 +239,18 @@ __global__ void k_gather_all(int M, int w, int Q, const int *__restrict__ sperm,
         q[4 * (size_t)p + 3] = (R)0;
         sp[3] = 0.0;
         schg[4 * (size_t)p + 3] = (R)0;
-        sseg[p] = o / Q;
+        G.sseg[p] = o / Q;
     }
+}
+
+template <typename R>
+__global__ void k_gather_all(int M, int w, int Q, const int *__restrict__ sperm,
+                             const int *__restrict__ pperm, const double *__restrict__ pos,
+                             const double *__restrict__ chg, double L, double inv_h, int n,
+                             double zeta, double inv_den, GatherOut G) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * M) return;
+    gather_one<R>(t, w, Q, sperm, pperm, pos, chg, L, inv_h, n, zeta, inv_den, G);
 }
 
 void build_bins(bs_plan_t p) {
@@ -253,10 +269,18 @@ void build_bins(bs_plan_t p) {
     S.nbins[0] = ntiles; S.nbins[1] = nc3; S.nbins[2] = nc3;
     S.nitems[0] = M; S.nitems[1] = M; S.nitems[2] = N;
     const int maxb = ntiles > nc3 ? ntiles : nc3;
+    const double zeta = p->prm.zeta, inv_den = 1.0 / (-expm1(-2.0 * zeta));
+    GatherOut G;
+    G.base = (int4 *)p->sp_base.p;
+    G.ker = p->sp_ker.p;
+    G.q = p->sp_q.p;
+    G.spos = (double4 *)p->pq_pos.p;
+    G.schg = p->pq_chg.p;
+    G.sseg = (int *)p->pq_seg.p;
+    const double *qp = (const double *)p->d_qpos.p, *qc = (const double *)p->d_qchg.p;
     hipLaunchKernelGGL(k_zero_bins, dim3(ceil_div(maxb + 1, bs)), dim3(bs), 0, p->stream, S);
-    hipLaunchKernelGGL(k_keys_all, dim3(ceil_div(M + N, bs)), dim3(bs), 0, p->stream, S,
-                       (const double *)p->d_qpos.p, (const double *)p->d_x.p, L, inv_h, w, n,
-                       p->T, p->NT, p->nc);
+    hipLaunchKernelGGL(k_keys_all, dim3(ceil_div(M + N, bs)), dim3(bs), 0, p->stream, S, qp,
+                       (const double *)p->d_x.p, L, inv_h, w, n, p->T, p->NT, p->nc);
     if (maxb <= (1 << 16)) {
         hipLaunchKernelGGL(k_scan_small, dim3(3), dim3(1024), 0, p->stream, S);
     } else {
@@ -264,19 +288,14 @@ void build_bins(bs_plan_t p) {
     }
     hipLaunchKernelGGL(k_scatter_all, dim3(ceil_div(2 * M + N, bs)), dim3(bs), 0, p->stream, S);
     hipLaunchKernelGGL(k_sort_all, dim3(ntiles + 2 * nc3), dim3(64), 0, p->stream, S);
-    const double zeta = p->prm.zeta, inv_den = 1.0 / (-expm1(-2.0 * zeta));
     if (p->fp32)
-        hipLaunchKernelGGL(k_gather_all<float>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0, p->stream, M,
-                           w, p->Q, S.perm[0], S.perm[1], (const double *)p->d_qpos.p,
-                           (const double *)p->d_qchg.p, L, inv_h, n, zeta, inv_den,
-                           (int4 *)p->sp_base.p, (float *)p->sp_ker.p, (float *)p->sp_q.p,
-                           (double4 *)p->pq_pos.p, (float *)p->pq_chg.p, (int *)p->pq_seg.p);
+        hipLaunchKernelGGL(k_gather_all<float>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0,
+                           p->stream, M, w, p->Q, S.perm[0], S.perm[1], qp, qc, L, inv_h, n, zeta,
+                           inv_den, G);
     else
-        hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0, p->stream,
-                           M, w, p->Q, S.perm[0], S.perm[1], (const double *)p->d_qpos.p,
-                           (const double *)p->d_qchg.p, L, inv_h, n, zeta, inv_den,
-                           (int4 *)p->sp_base.p, (double *)p->sp_ker.p, (double *)p->sp_q.p,
-                           (double4 *)p->pq_pos.p, (double *)p->pq_chg.p, (int *)p->pq_seg.p);
+        hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0,
+                           p->stream, M, w, p->Q, S.perm[0], S.perm[1], qp, qc, L, inv_h, n, zeta,
+                           inv_den, G);
 }
 
 }  // namespace bs

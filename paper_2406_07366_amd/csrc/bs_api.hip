@@ -393,6 +393,7 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             (rc = ensure<double>(P, P->d_qpos, 3 * Nq)) ||
             (rc = ensure<double>(P, P->d_qchg, 3 * Nq)) || (rc = ensure<double>(P, P->tmp3, 3 * N)) ||
             (rc = ensure<double>(P, P->e_D, 3 * N)) || (rc = ensure<double>(P, P->e_S, 3 * N)) ||
+            (rc = ensure<double>(P, P->d_vls, 3 * N)) ||
             (rc = ensure<int>(P, P->sp_key, Nq)) || (rc = ensure<int>(P, P->sp_cnt, ntiles + 1)) ||
             (rc = ensure<int>(P, P->sp_start, ntiles + 1)) ||
             (rc = ensure<int>(P, P->sp_fill, ntiles + 1)) || (rc = ensure<int>(P, P->sp_perm, Nq)) ||
@@ -406,9 +407,10 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             (rc = ensure<int>(P, P->nd_cnt, nc3 + 1)) || (rc = ensure<int>(P, P->nd_start, nc3 + 1)) ||
             (rc = ensure<int>(P, P->nd_fill, nc3 + 1)) || (rc = ensure<int>(P, P->nd_perm, N)))
             return rc;
-        if (P->order == 4 && maxn > 512 && (rc = ensure<double>(P, P->spline_tmp, 12 * N)))
+        if (P->order == 4 && maxn > kPcrLds && (rc = ensure<double>(P, P->spline_tmp, 12 * N)))
             return rc;
-        if (P->order == 6 && maxn > 64 && (rc = ensure<double>(P, P->spline_tmp, 36 * N)))
+        if (P->order == 6 && maxn > kPcr5Lds &&
+            (rc = ensure<double>(P, P->spline_tmp, 36 * N)))
             return rc;
         if (P->prm.ns_mode != BS_NS_OFF) {
             size_t mp = (size_t)N * P->ns_max_per_node;
@@ -451,9 +453,7 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
         P->max_fil_nodes = maxn;
     }
     stage_begin(P, 0);
-    launch_chord(P, xyz, gamma);   // also takes the plan's copies of xyz and gamma
-    launch_spline(P);
-    launch_geometry(P);
+    launch_filaments(P, xyz, gamma);   // also takes the plan's copies of xyz and gamma
     stage_end(P, 0);
     stage_begin(P, 1);
     build_bins(P);
@@ -479,7 +479,8 @@ static int launch_ns(bs_plan_t P, double *out) {
     return BS_OK;
 }
 
-static int long_range(bs_plan_t P, int psi, double *out) {
+// out = base + long-range term (base NULL: out += long-range term)
+static int long_range(bs_plan_t P, int psi, const double *base, double *out) {
     int rc;
     stage_begin(P, 3);
     launch_spread(P);
@@ -506,7 +507,7 @@ static int long_range(bs_plan_t P, int psi, double *out) {
         stage_end(P, 6);
     }
     stage_begin(P, 7);
-    launch_interp(P, out);
+    launch_interp(P, base, out);
     stage_end(P, 7);
     return launch_status(P, "long-range kernels");
 }
@@ -515,10 +516,9 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
     if (!v_out) return set_error(P, BS_EINVAL, "null output");
-    stage_begin(P, 2);
-    launch_local_self(P, LS_VLOCAL | LS_VSELF | LS_ASSIGN, 1.0, v_out);
-    stage_end(P, 2);
-    int rc = long_range(P, 0, v_out);
+    // local - self was formed by set_filaments (d_vls); the interpolation
+    // writes it plus the long-range term
+    int rc = long_range(P, 0, (const double *)P->d_vls.p, v_out);
     if (rc) return rc;
     stage_begin(P, 8);
     launch_pairs(P, 0, v_out);
@@ -543,7 +543,7 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
     if (v_self) launch_local_self(P, LS_VSELF | LS_ASSIGN, 1.0, v_self);
     if (v_long) {
         fill_f64(P, v_long, n3, 0.0);
-        if ((rc = long_range(P, 0, v_long))) return rc;
+        if ((rc = long_range(P, 0, nullptr, v_long))) return rc;
     }
     if (v_short) {
         fill_f64(P, v_short, n3, 0.0);
@@ -561,7 +561,7 @@ int bs_energy(bs_plan_t P, double *E_out, double *psi_out) {
     if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
     double *psi = psi_out ? psi_out : (double *)P->tmp3.p;
     launch_local_self(P, LS_VLOCAL | LS_VSELF | LS_PSI | LS_ASSIGN, 1.0, psi);
-    int rc = long_range(P, 1, psi);
+    int rc = long_range(P, 1, nullptr, psi);
     if (rc) return rc;
     launch_pairs(P, 1, psi);
     const int nb = 512;
@@ -766,7 +766,7 @@ int bs_destroy(bs_plan_t P) {
                    &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
                    &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
-                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->e_D, &P->e_S, &P->ns_red, &P->ns_nc, &P->ns_ckey,
+                   &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->e_D, &P->e_S, &P->d_vls, &P->ns_red, &P->ns_nc, &P->ns_ckey,
                    &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_tkey, &P->ns_tcnt,
                    &P->ns_tstart, &P->ns_tfill, &P->ns_tperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_slots,
                    &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout,

@@ -14,6 +14,10 @@ namespace bs {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kMaxQ = 4;
+// nodes per filament whose spline solve stays in LDS (cubic, quintic);
+// longer filaments use the plan's global scratch
+constexpr int kPcrLds = 128;
+constexpr int kPcr5Lds = 64;
 constexpr int kMinW = 4, kMaxW = 16;
 
 // Gauss-Legendre nodes h_i in [0,1] and weights w_i (sum 1) for Q = 1..4.
@@ -105,6 +109,7 @@ struct bs_plan_s {
     // terms (for velocity terms / energy)
     bs::DBuf tmp3;                             // f64 [N][3]
     bs::DBuf e_D, e_S;                         // f64 [N][3]: spline of psi (energy)
+    bs::DBuf d_vls;                            // f64 [N][3]: local - self velocity
     // per-stage timing (diagnostics)
     bool prof = false;
     hipEvent_t ev_beg[BS_NSTAGES] = {}, ev_end[BS_NSTAGES] = {};
@@ -119,12 +124,12 @@ int set_error(bs_plan_t p, int code, const std::string &msg);
 int check_hip(bs_plan_t p, hipError_t e, const char *what);
 
 // geometry.hip
-void launch_chord(bs_plan_t p, const double *xyz, const double *gamma);
-void launch_spline(bs_plan_t p);
+// chord lengths, spline, quadrature points, charges, segment lengths and the
+// velocity's local-minus-self term (d_vls), one workgroup per filament
+void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma);
 // spline through nodal data on the plan's knots: slopes (and, quintic,
 // second derivatives) into Dout, Sout
 void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout);
-void launch_geometry(bs_plan_t p);
 // mode bits for launch_local_self
 enum { LS_VLOCAL = 1, LS_VSELF = 2, LS_PSI = 4, LS_ASSIGN = 8 };
 void launch_local_self(bs_plan_t p, int mode, double sign, double *out);
@@ -136,7 +141,8 @@ void build_bins(bs_plan_t p);
 // nufft.hip
 void launch_spread(bs_plan_t p);
 void launch_spectral(bs_plan_t p, int psi);
-void launch_interp(bs_plan_t p, double *out);
+// out = base + interpolated long-range term (base NULL: out += ...)
+void launch_interp(bs_plan_t p, const double *base, double *out);
 void launch_modes(bs_plan_t p, double *out);
 int fft_forward(bs_plan_t p);
 int fft_inverse(bs_plan_t p);

@@ -37,29 +37,29 @@ __device__ __forceinline__ int prev_node(const int *off, const int *fil, int j) 
 }
 
 // ------------------------------------------------------------- chord lengths
-// Chord lengths from the caller's node positions, which are copied into the
-// plan's own array on the way (xs may alias xd); thread f < nfil also copies
-// filament f's circulation.
-__global__ void k_chord(int N, int nfil, const double *xs, double *xd,
-                        const double *__restrict__ gs, double *__restrict__ gd,
-                        const int *__restrict__ off, const int *__restrict__ fil,
-                        double *__restrict__ dtau, int *__restrict__ status) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < nfil) gd[j] = gs[j];
-    if (j >= N) return;
-    int jn = next_node(off, fil, j);
-    const double x0 = xs[3 * j], x1 = xs[3 * j + 1], x2 = xs[3 * j + 2];
-    double dx = xs[3 * jn] - x0, dy = xs[3 * jn + 1] - x1, dz = xs[3 * jn + 2] - x2;
-    double h = sqrt(dx * dx + dy * dy + dz * dz);
-    bool ok = isfinite(x0) && isfinite(x1) && isfinite(x2) && isfinite(h) && h > 0.0;
-    if (!ok) atomicOr(status, 1);
-    dtau[j] = ok ? h : 1.0;
-    xd[3 * j] = x0; xd[3 * j + 1] = x1; xd[3 * j + 2] = x2;
+// Chord lengths of filament f from the caller's node positions, which are
+// copied into the plan's own array on the way (xs may alias xd); also the
+// plan's copy of the filament's circulation.  Non-finite positions and
+// zero-length segments set bit 0 of the status word (their chord is taken
+// as 1 so that the rest stays finite).
+__device__ void chord_fil(int f, int b0, int n, const double *xs, double *xd,
+                          const double *__restrict__ gs, double *__restrict__ gd,
+                          double *__restrict__ dtau, int *__restrict__ status) {
+    if (threadIdx.x == 0) gd[f] = gs[f];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const int j = b0 + k, jn = b0 + (k + 1 == n ? 0 : k + 1);
+        const double x0 = xs[3 * j], x1 = xs[3 * j + 1], x2 = xs[3 * j + 2];
+        const double dx = xs[3 * jn] - x0, dy = xs[3 * jn + 1] - x1, dz = xs[3 * jn + 2] - x2;
+        const double h = sqrt(dx * dx + dy * dy + dz * dz);
+        const bool ok = isfinite(x0) && isfinite(x1) && isfinite(x2) && isfinite(h) && h > 0.0;
+        if (!ok) atomicOr(status, 1);
+        dtau[j] = ok ? h : 1.0;
+        xd[3 * j] = x0; xd[3 * j + 1] = x1; xd[3 * j + 2] = x2;
+    }
 }
 
 // ------------------------------------------------------------- spline (PCR)
 constexpr int kPcrSteps = 7;
-constexpr int kPcrLds = 512;   // nodes per filament solved in LDS
 
 struct PcrArrays {
     double *a, *b, *c, *r;     // r holds 3 components: r[3*k + comp]
@@ -91,13 +91,12 @@ __device__ void pcr_solve(int n, PcrArrays A, PcrArrays B) {
     // after an odd number of steps the result is in B
 }
 
-__global__ void k_spline(int nfil, const int *__restrict__ off, const double *__restrict__ x,
-                         const double *__restrict__ dtau, double *__restrict__ D,
-                         double *__restrict__ gscratch) {
+// slopes D of the cubic spline through the nodal data x of one filament
+// (nodes b0 .. b0+n-1); the whole workgroup takes part
+__device__ void spline_cubic_fil(int b0, int n, const double *__restrict__ x,
+                                 const double *__restrict__ dtau, double *__restrict__ D,
+                                 double *__restrict__ gscratch) {
     __shared__ double lds[2 * 6 * kPcrLds];
-    int f = blockIdx.x;
-    if (f >= nfil) return;
-    int b0 = off[f], n = off[f + 1] - off[f];
     double *base;
     if (n <= kPcrLds) base = lds;
     else base = gscratch + (size_t)12 * b0;   // 12 doubles per node
@@ -125,6 +124,14 @@ __global__ void k_spline(int nfil, const int *__restrict__ off, const double *__
     }
 }
 
+__global__ void k_spline(int nfil, const int *__restrict__ off, const double *__restrict__ x,
+                         const double *__restrict__ dtau, double *__restrict__ D,
+                         double *__restrict__ gscratch) {
+    const int f = blockIdx.x;
+    if (f >= nfil) return;
+    spline_cubic_fil(off[f], off[f + 1] - off[f], x, dtau, D, gscratch);
+}
+
 // ------------------------------------------------ quintic spline (block PCR)
 // Rows of node i (h- = h_{i-1}, h+ = h_i), the C3 condition scaled by 1/3
 // and the C4 condition by -1/12:
@@ -140,7 +147,6 @@ __global__ void k_spline(int nfil, const int *__restrict__ off, const double *__
 // below 0.43^256.  At distance n/2 of a power-of-two n both neighbours are
 // the same node and their two couplings are merged.
 constexpr int kPcr5Steps = 8;
-constexpr int kPcr5Lds = 64;   // nodes per filament solved in LDS
 
 struct Blk {
     double L[4], M[4], U[4], R[6];   // 2x2 blocks row-major; R[row * 3 + comp]
@@ -171,13 +177,12 @@ __device__ __forceinline__ void sub_mulR(const double *K, const double *V, doubl
         for (int q = 0; q < 3; q++) R[3 * r + q] -= K[2 * r] * V[q] + K[2 * r + 1] * V[3 + q];
 }
 
-__global__ void k_spline5(int nfil, const int *__restrict__ off, const double *__restrict__ x,
-                          const double *__restrict__ dtau, double *__restrict__ D,
-                          double *__restrict__ S, double *__restrict__ gscratch) {
+// slopes D and second derivatives S of the quintic spline through the nodal
+// data x of one filament; the whole workgroup takes part
+__device__ void spline_quintic_fil(int b0, int n, const double *__restrict__ x,
+                                   const double *__restrict__ dtau, double *__restrict__ D,
+                                   double *__restrict__ S, double *__restrict__ gscratch) {
     __shared__ Blk lds[2 * kPcr5Lds];
-    const int f = blockIdx.x;
-    if (f >= nfil) return;
-    const int b0 = off[f], n = off[f + 1] - off[f];
     Blk *src, *dst;
     if (n <= kPcr5Lds) {
         src = lds;
@@ -262,26 +267,32 @@ __global__ void k_spline5(int nfil, const int *__restrict__ off, const double *_
     }
 }
 
+__global__ void k_spline5(int nfil, const int *__restrict__ off, const double *__restrict__ x,
+                          const double *__restrict__ dtau, double *__restrict__ D,
+                          double *__restrict__ S, double *__restrict__ gscratch) {
+    const int f = blockIdx.x;
+    if (f >= nfil) return;
+    spline_quintic_fil(off[f], off[f + 1] - off[f], x, dtau, D, S, gscratch);
+}
+
 // --------------------------------------------------------- segment geometry
 struct GLArgs {
     double h[kMaxQ];
     double w[kMaxQ];
 };
 
-// Segment j in u in [0,1] (tau = tau_j + u h); ds/dtau = s'(u)/h.  ORDER 4
-// writes the node's second derivative (from its segment's start); ORDER 6
-// reads it (solved with the slopes).
+// Quadrature points, vector charges and segment lengths of segment j (in u
+// in [0,1], tau = tau_j + u h; ds/dtau = s'(u)/h).  ORDER 4 writes the node's
+// second derivative (from its segment's start); ORDER 6 reads it (solved
+// with the slopes).
 template <int ORDER>
-__global__ void k_geometry(int N, int Q, GLArgs gl, const double *__restrict__ x,
-                           const int *__restrict__ off, const int *__restrict__ fil,
-                           const double *__restrict__ gamma, const double *__restrict__ dtau,
-                           const double *__restrict__ D, double *__restrict__ qpos,
-                           double *__restrict__ qchg, double *__restrict__ sdd,
-                           double *__restrict__ ell) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    int jn = next_node(off, fil, j);
-    double h = dtau[j], g = gamma[fil[j]];
+__device__ __forceinline__ void geometry_seg(int j, int jn, double g, int Q, const GLArgs &gl,
+                                             const double *__restrict__ x,
+                                             const double *__restrict__ dtau,
+                                             const double *__restrict__ D,
+                                             double *__restrict__ qpos, double *__restrict__ qchg,
+                                             double *__restrict__ sdd, double *__restrict__ ell) {
+    const double h = dtau[j];
     SegPoly<ORDER> sp;
     sp.load(x, D, sdd, j, jn, h);
     if constexpr (ORDER == 4) {
@@ -345,20 +356,21 @@ __device__ constexpr double kG3w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
 // the rest of each segment is integrated with the unsplit kernels by
 // 3-point rules on panels graded towards the node, [eps, 2 eps],
 // [2 eps, 4 eps], ..., ending at the segment's far node.
+struct LocalArgs {
+    int Q, mode;
+    double sign, a, delta, alpha, eps;
+};
+
+// node i with neighbours ip (previous) and in (next) on its filament
 template <int ORDER>
-__global__ void k_local_self(int N, int Q, int mode, double sign, double a, double delta,
-                             double alpha, double eps, const double *__restrict__ x,
-                             const int *__restrict__ off, const int *__restrict__ fil,
-                             const double *__restrict__ gamma, const double *__restrict__ dtau,
-                             const double *__restrict__ D,
-                             const double *__restrict__ sdd, const double *__restrict__ ell,
-                             const double *__restrict__ qpos, const double *__restrict__ qchg,
-                             double *__restrict__ out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__device__ void local_self_node(int i, int ip, int in, double g, const LocalArgs &la,
+                                const double *__restrict__ x, const double *__restrict__ dtau,
+                                const double *__restrict__ D, const double *__restrict__ sdd,
+                                const double *__restrict__ ell, const double *__restrict__ qpos,
+                                const double *__restrict__ qchg, double *__restrict__ out) {
+    const int Q = la.Q, mode = la.mode;
+    const double a = la.a, delta = la.delta, alpha = la.alpha, eps = la.eps, sign = la.sign;
     const double inv4pi = 1.0 / (4.0 * kPi);
-    int ip = prev_node(off, fil, i);
-    double g = gamma[fil[i]];
     bool psi = (mode & LS_PSI) != 0;
     double acc[3] = {0.0, 0.0, 0.0};
     if (mode & LS_VLOCAL) {
@@ -368,7 +380,6 @@ __global__ void k_local_self(int N, int Q, int mode, double sign, double a, doub
         const bool sub = eps < 1.0;
         SegPoly<ORDER> seg[2];
         if (sub) {
-            const int in = next_node(off, fil, i);
             seg[0].load(x, D, sdd, ip, i, dtau[ip]);
             seg[1].load(x, D, sdd, i, in, dtau[i]);
             lm = lp = 0.0;
@@ -450,16 +461,80 @@ __global__ void k_local_self(int N, int Q, int mode, double sign, double a, doub
     }
 }
 
+template <int ORDER>
+__global__ void k_local_self(int N, LocalArgs la, const double *__restrict__ x,
+                             const int *__restrict__ off, const int *__restrict__ fil,
+                             const double *__restrict__ gamma, const double *__restrict__ dtau,
+                             const double *__restrict__ D, const double *__restrict__ sdd,
+                             const double *__restrict__ ell, const double *__restrict__ qpos,
+                             const double *__restrict__ qchg, double *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    local_self_node<ORDER>(i, prev_node(off, fil, i), next_node(off, fil, i), gamma[fil[i]], la,
+                           x, dtau, D, sdd, ell, qpos, qchg, out);
+}
+
+// ----------------------------------------------------- one filament at once
+// Everything set_filaments derives per filament, in one workgroup per
+// filament: chord lengths (and the plan's copies of the nodes and of the
+// circulation), the spline solve, quadrature points, charges and segment
+// lengths, and the velocity's local term minus the long-range self
+// correction (into vls, which the interpolation adds to the velocity).
+template <int ORDER>
+__global__ void k_filament(int nfil, const int *__restrict__ off, const double *xs,
+                           double *xd, const double *__restrict__ gs, double *__restrict__ gd,
+                           double *__restrict__ dtau, double *__restrict__ D,
+                           double *__restrict__ sdd, double *__restrict__ qpos,
+                           double *__restrict__ qchg, double *__restrict__ ell,
+                           int *__restrict__ status, double *__restrict__ gscratch, GLArgs gl,
+                           LocalArgs la, double *__restrict__ vls) {
+    const int f = blockIdx.x;
+    if (f >= nfil) return;
+    const int b0 = off[f], n = off[f + 1] - off[f];
+    chord_fil(f, b0, n, xs, xd, gs, gd, dtau, status);
+    __syncthreads();
+    if constexpr (ORDER == 4) spline_cubic_fil(b0, n, xd, dtau, D, gscratch);
+    else spline_quintic_fil(b0, n, xd, dtau, D, sdd, gscratch);
+    __syncthreads();
+    const double g = gs[f];
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        geometry_seg<ORDER>(b0 + k, b0 + (k + 1 == n ? 0 : k + 1), g, la.Q, gl, xd, dtau, D, qpos,
+                            qchg, sdd, ell);
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        local_self_node<ORDER>(b0 + k, b0 + (k == 0 ? n - 1 : k - 1), b0 + (k + 1 == n ? 0 : k + 1),
+                               g, la, xd, dtau, D, sdd, ell, qpos, qchg, vls);
+}
+
 // ------------------------------------------------------------------ launch
 static inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
-void launch_chord(bs_plan_t p, const double *xyz, const double *gamma) {
+static LocalArgs local_args(bs_plan_t p, int mode, double sign) {
+    LocalArgs la;
+    la.Q = p->Q;
+    la.mode = mode;
+    la.sign = sign;
+    la.a = p->prm.a;
+    la.delta = p->prm.delta;
+    la.alpha = p->prm.alpha;
+    la.eps = p->prm.local_frac > 0.0 ? p->prm.local_frac : 1.0;
+    return la;
+}
+
+void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
     if (p->N == 0) return;
-    const int64_t items = p->N > p->nfil ? p->N : p->nfil;
-    hipLaunchKernelGGL(k_chord, dim3(blocks_for(items, 256)), dim3(256), 0, p->stream, (int)p->N,
-                       (int)p->nfil, xyz, (double *)p->d_x.p, gamma, (double *)p->d_gamma.p,
-                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
-                       (double *)p->d_dtau.p, (int *)p->d_status.p);
+    GLRule r = gl_rule(p->Q);
+    GLArgs g;
+    for (int i = 0; i < kMaxQ; i++) { g.h[i] = r.h[i]; g.w[i] = r.w[i]; }
+    const LocalArgs la = local_args(p, LS_VLOCAL | LS_VSELF | LS_ASSIGN, 1.0);
+    auto kern = p->order == 6 ? k_filament<6> : k_filament<4>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)p->nfil), dim3(p->order == 6 ? 64 : 128), 0,
+                       p->stream, (int)p->nfil, (const int *)p->d_off.p, xyz,
+                       (double *)p->d_x.p, gamma, (double *)p->d_gamma.p,
+                       (double *)p->d_dtau.p, (double *)p->d_D.p, (double *)p->d_sdd.p,
+                       (double *)p->d_qpos.p, (double *)p->d_qchg.p, (double *)p->d_ell.p,
+                       (int *)p->d_status.p, (double *)p->spline_tmp.p, g, la,
+                       (double *)p->d_vls.p);
 }
 
 void launch_spline(bs_plan_t p) {
@@ -477,29 +552,15 @@ void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *S
                            (const double *)p->d_dtau.p, Dout, (double *)p->spline_tmp.p);
 }
 
-void launch_geometry(bs_plan_t p) {
-    GLRule r = gl_rule(p->Q);
-    GLArgs g;
-    for (int i = 0; i < kMaxQ; i++) { g.h[i] = r.h[i]; g.w[i] = r.w[i]; }
-    auto kern = p->order == 6 ? k_geometry<6> : k_geometry<4>;
-    hipLaunchKernelGGL(kern, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream,
-                       (int)p->N, p->Q, g, (const double *)p->d_x.p, (const int *)p->d_off.p,
-                       (const int *)p->d_fil.p, (const double *)p->d_gamma.p,
-                       (const double *)p->d_dtau.p, (const double *)p->d_D.p,
-                       (double *)p->d_qpos.p, (double *)p->d_qchg.p, (double *)p->d_sdd.p,
-                       (double *)p->d_ell.p);
-}
-
 void launch_local_self(bs_plan_t p, int mode, double sign, double *out) {
     auto kern = p->order == 6 ? k_local_self<6> : k_local_self<4>;
-    const double eps = p->prm.local_frac > 0.0 ? p->prm.local_frac : 1.0;
-    hipLaunchKernelGGL(kern, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream,
-                       (int)p->N, p->Q, mode, sign, p->prm.a, p->prm.delta, p->prm.alpha, eps,
-                       (const double *)p->d_x.p, (const int *)p->d_off.p,
-                       (const int *)p->d_fil.p, (const double *)p->d_gamma.p,
-                       (const double *)p->d_dtau.p, (const double *)p->d_D.p,
-                       (const double *)p->d_sdd.p, (const double *)p->d_ell.p,
-                       (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, out);
+    hipLaunchKernelGGL(kern, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream, (int)p->N,
+                       local_args(p, mode, sign), (const double *)p->d_x.p,
+                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
+                       (const double *)p->d_gamma.p, (const double *)p->d_dtau.p,
+                       (const double *)p->d_D.p, (const double *)p->d_sdd.p,
+                       (const double *)p->d_ell.p, (const double *)p->d_qpos.p,
+                       (const double *)p->d_qchg.p, out);
 }
 
 }  // namespace bs

@@ -360,6 +360,7 @@ __global__ __launch_bounds__(256) void k_interp(int N, int per_xcd, const int *_
                                                 const double *__restrict__ x, double L,
                                                 double inv_h, int n, double zeta, double inv_den,
                                                 const R *__restrict__ grid,
+                                                const double *__restrict__ base,
                                                 double *__restrict__ out) {
     static_assert(3 * W <= G, "one lane per kernel value");
     constexpr int NR = (W * W + G - 1) / G;
@@ -421,16 +422,18 @@ __global__ __launch_bounds__(256) void k_interp(int N, int per_xcd, const int *_
         a2 += __shfl_xor(a2, m, G);
     }
     if (lane == 0) {
-        out[3 * o] += (double)a0;
-        out[3 * o + 1] += (double)a1;
-        out[3 * o + 2] += (double)a2;
+        // base (if given) supplies the value the result is added to
+        const double *b = base ? base : out;
+        out[3 * o] = b[3 * o] + (double)a0;
+        out[3 * o + 1] = b[3 * o + 1] + (double)a1;
+        out[3 * o + 2] = b[3 * o + 2] + (double)a2;
     }
 }
 
 constexpr int kInterpLanes = 64;
 
 template <typename R>
-static void interp_r(bs_plan_t p, double *out) {
+static void interp_r(bs_plan_t p, const double *base, double *out) {
     const int N = (int)p->N;
     const int nblk = ceil_div((int64_t)N * kInterpLanes, 256), per = ceil_div(nblk, 8);
     dim3 grid(8 * per), block(256);
@@ -440,7 +443,7 @@ static void interp_r(bs_plan_t p, double *out) {
     const double *x = (const double *)p->d_x.p;
     const R *g = (const R *)p->grid.p;
 #define INTERP_CASE(WW) \
-    case WW: hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes>), grid, block, 0, p->stream, N, per, perm, x, L, inv_h, p->n, zeta, inv_den, g, out); break;
+    case WW: hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes>), grid, block, 0, p->stream, N, per, perm, x, L, inv_h, p->n, zeta, inv_den, g, base, out); break;
     switch (p->prm.w) {
         INTERP_CASE(4) INTERP_CASE(5) INTERP_CASE(6) INTERP_CASE(7) INTERP_CASE(8)
         INTERP_CASE(9) INTERP_CASE(10) INTERP_CASE(11) INTERP_CASE(12) INTERP_CASE(13)
@@ -450,9 +453,9 @@ static void interp_r(bs_plan_t p, double *out) {
 #undef INTERP_CASE
 }
 
-void launch_interp(bs_plan_t p, double *out) {
-    if (p->fp32) interp_r<float>(p, out);
-    else interp_r<double>(p, out);
+void launch_interp(bs_plan_t p, const double *base, double *out) {
+    if (p->fp32) interp_r<float>(p, base, out);
+    else interp_r<double>(p, base, out);
 }
 
 }  // namespace bs
