@@ -225,6 +225,41 @@ def bigtangle(args, torch, B, W):
     return res
 
 
+def table1(args, torch, B, W):
+    """Sec. 5.3 performance tests on the GPU: random ellipses of 32 nodes,
+    quintic splines, Q = 3, a = 1e-8, FP64; per Table 1 row alpha = C_beta
+    N^(1/3)/L and the smallest grid reaching k_max = 2 beta alpha.  Errors
+    are taken against the tol = 1e-14 run of the same size (as the paper
+    does); the paper's single-core time C_fit N log10 N is quoted as context."""
+    rows = json.load(open(os.path.join(ROOT, "tests", "golden", "table1_parameters.json")))["rows"]
+    for n_ell in (int(v) for v in args.table1.split(",")):
+        fs = W.perf_ellipses(n_ell)
+        N = fs.n_nodes
+        xyz, gamma = B.load_workload(fs)
+        out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        res = {}
+        for tol, beta, C_beta, sigma, w, C_fit, _ in sorted(rows, key=lambda r: r[0]):
+            pp = W.perf_params(N, beta, C_beta, fs.L, sigma, w)
+            plan = B.Plan(B.make_params(L=fs.L, a=fs.a, tol=tol, grid_n=pp["grid_n"],
+                                        alpha=pp["alpha"], w=w, sigma=sigma, Q=3, spline_order=6))
+            prm = plan.params()
+            steps = max(5, min(args.steps, int(2e6 / N)))
+            ms, _ = time_steps(torch, plan, fs, xyz, gamma, out, steps, max(2, args.warmup // 4))
+            plan.status()
+            v = out.cpu().numpy()
+            res[tol] = v
+            ref = res[min(res)]
+            err = rel_l2(v, ref) if tol > min(res) else 0.0
+            paper_us = C_fit * N * math.log10(N)
+            line = {"table1": {"tol": tol, "beta": beta, "N": N, "grid_n": prm.grid_n,
+                               "K": prm.K, "alpha": prm.alpha, "rcut": prm.rcut,
+                               "fft_mode": prm.fft_mode, "ms_per_eval": ms,
+                               "nodes_per_s": N / (ms * 1e-3), "rel_l2_vs_1e-14": err,
+                               "paper_cpu_core_ms": paper_us * 1e-3}}
+            print(json.dumps(line), flush=True)
+            plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +272,10 @@ def main():
                     help="also write per-stage times, rooflines and parameters to this JSON file")
     ap.add_argument("--drift", action="store_true",
                     help="bigtangle: energy drift of a 1e4-node subset against the FP64 oracle")
+    ap.add_argument("--table1", default=None, metavar="SIZES",
+                    help="the paper's performance tests (Sec. 5.3, Table 1) instead of the "
+                         "default line: comma-separated ellipse counts (32 nodes each); one "
+                         "JSON line per tolerance and size, errors against the tol = 1e-14 run")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="end with a plain 256 MiB device copy, the size reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc run")
@@ -249,6 +288,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2406_07366_amd import binding as B
     from paper_2406_07366_amd import workloads as W
+
+    if args.table1:
+        table1(args, torch, B, W)
+        return
 
     if args.workload == "bigtangle":
         res = bigtangle(args, torch, B, W)

@@ -46,24 +46,35 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
     const double xi0 = x[3 * o], xi1 = x[3 * o + 1], xi2 = x[3 * o + 2];
     const double invL = 1.0 / L;
     // lanes 0..63: the 4 x 4 x 4 cells from the cell of x - r_c on (cells of
-    // edge h >= 2 r_c / 3 hold every point within r_c in 4 per axis)
+    // edge h >= 2 r_c / 3 hold every point within r_c in 4 per axis); a cell
+    // whose box lies farther than r_c from x holds no partner and is dropped
     const int ncell = nc >= 4 ? 64 : 1;
     int cs = 0, cn = 0;
     if (lane < ncell) {
         int cidx = 0;
+        bool near = true;
         if (nc >= 4) {
             const double ws[3] = {wrap_box(xi0, L), wrap_box(xi1, L), wrap_box(xi2, L)};
             const int dd[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+            const double h = L / nc;
             int c[3];
+            double d2 = 0.0;
             for (int q = 0; q < 3; q++) {
                 int v = (int)floor((ws[q] - rc) * invL * nc) + dd[q];
+                // distance from x to the cell's extent [v h, (v + 1) h) (unwrapped)
+                const double lo = v * h - ws[q], hi = ws[q] - (v + 1) * h;
+                const double d = lo > 0.0 ? lo : (hi > 0.0 ? hi : 0.0);
+                d2 += d * d;
                 v %= nc;
                 c[q] = v < 0 ? v + nc : v;
             }
             cidx = (c[2] * nc + c[1]) * nc + c[0];
+            near = d2 <= rc * rc * (1.0 + 1e-12);
         }
-        cs = cstart[cidx];
-        cn = cstart[cidx + 1] - cs;
+        if (near) {
+            cs = cstart[cidx];
+            cn = cstart[cidx + 1] - cs;
+        }
     }
     int incl = cn;
     for (int d = 1; d < 64; d <<= 1) {

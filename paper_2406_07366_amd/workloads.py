@@ -212,5 +212,56 @@ def leapfrog(n_per: int = 32, L: float = TWO_PI, a: float = 1e-6, grid_n: int = 
 WORKLOADS["leapfrog"] = leapfrog
 
 
+def perf_ellipses(n_ell: int, n_per: int = 32, seed: int = 1006, L: float = TWO_PI,
+                  a: float = 1e-8, tol: float = 1e-6) -> FilamentSet:
+    """The random-ellipse case of the paper's performance tests (Sec. 5.3,
+    after the third test case of Sec. 5.1): ellipses at uniform random
+    positions with Haar orientations, minor and major radii independent and
+    uniform in [L/16, L/4], Gamma = 1, n_per nodes each equispaced in angle,
+    a = 1e-8.  grid_n is set per tolerance by perf_params."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, L, size=(n_ell, 3))
+    axes = rng.uniform(L / 16, L / 4, size=(n_ell, 2))
+    rot = haar_rotations(rng, n_ell)
+    th = TWO_PI * np.arange(n_per) / n_per
+    local = np.zeros((n_ell, n_per, 3))
+    local[:, :, 0] = axes[:, 0:1] * np.cos(th)[None, :]
+    local[:, :, 1] = axes[:, 1:2] * np.sin(th)[None, :]
+    xyz = centres[:, None, :] + np.einsum("fij,fnj->fni", rot, local)
+    return FilamentSet(f"perf_ellipses[{n_ell}]", L, a, _csr([n_per] * n_ell),
+                       xyz.reshape(-1, 3), np.ones(n_ell), 32, tol)
+
+
+def perf_params(N: int, beta: float, C_beta: float, L: float = TWO_PI, sigma: float = 1.5,
+                w: int = 8):
+    """Parameters of the performance tests for N nodes and one Table 1 row:
+    alpha = C_beta N^(1/3) / L (eq:alpha_optimal_performance), r_c = beta /
+    alpha, and a grid whose retained modes reach k_max = 2 beta alpha
+    (K >= beta alpha L / pi with K = floor((floor(n / sigma) - 1) / 2)): the
+    smallest multiple of 8 with no prime factor above 7 (fast transforms), or
+    the next power of two if it is at most 15 % larger (pruned transforms)."""
+    alpha = C_beta * N ** (1.0 / 3.0) / L
+
+    def ok(n):
+        return n >= w + 8 and (int(n / sigma + 1e-9) - 1) // 2 >= kmin
+
+    def smooth(n):
+        for f in (2, 3, 5, 7):
+            while n % f == 0:
+                n //= f
+        return n == 1
+
+    kmin = math.ceil(beta * alpha * L / math.pi - 1e-9)
+    n = 8
+    while not (ok(n) and smooth(n)):
+        n += 8
+    p2 = 16
+    while not ok(p2):
+        p2 *= 2
+    if p2 <= 1.15 * n:
+        n = p2
+    return dict(alpha=alpha, rcut=beta / alpha, grid_n=n, beta=beta, w=w, sigma=sigma)
+
+
 def make(name: str, **kw) -> FilamentSet:
     return WORKLOADS[name](**kw)

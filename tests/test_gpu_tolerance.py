@@ -55,3 +55,30 @@ def test_velocity_meets_nominal_tolerance(B, ref, row):
     print(f"  beta {p.beta} w {p.w} alpha {p.alpha:.4f} r_c {p.rcut:.4f}: rel_l2 {err:.2e}")
     # the float64 evaluation and the reference's own rounding floor
     assert err <= max(row["tol"], 2e-13)
+
+
+@pytest.mark.parametrize("row", _rows(), ids=lambda r: f"tol{r['tol']:g}")
+def test_performance_workload_meets_tolerance(B, row):
+    """The performance tests' random ellipses (Sec. 5.3: 32 ellipses of 32
+    nodes, radii in [L/16, L/4], a = 1e-8) with the paper's discretisation
+    (quintic splines, Q = 3) and parameters (alpha = C_beta N^(1/3)/L, the
+    smallest grid whose modes reach k_max = 2 beta alpha, Table 1's w):
+    the FP64 velocity meets the row's tolerance against the oracle's
+    converged solution of the same discrete problem."""
+    from oracle import oracle as O
+    fs = W.perf_ellipses(32, tol=row["tol"])
+    pp = W.perf_params(fs.n_nodes, row["beta"], row["C_beta"], fs.L, w=row["w"])
+    print(f"\n[case] perf ellipses N={fs.n_nodes} tol {row['tol']:g} {pp}", flush=True)
+    plan = B.Plan(B.make_params(L=fs.L, a=fs.a, tol=row["tol"], grid_n=pp["grid_n"],
+                                alpha=pp["alpha"], w=pp["w"], Q=3, spline_order=6))
+    p = plan.params()
+    assert p.beta == row["beta"] and abs(p.rcut - pp["rcut"]) < 1e-12
+    xyz, g = B.load_workload(fs)
+    plan.set_filaments(fs.offsets, xyz, g)
+    v = plan.velocity().cpu().numpy()
+    plan.status()
+    plan.close()
+    ref, _ = O.Oracle(fs, Q=3, order=6).reference(psi=False)
+    err = rel_l2(v, ref)
+    print(f"  grid {p.grid_n} K {p.K} alpha {p.alpha:.3f} r_c {p.rcut:.3f}: rel_l2 {err:.2e}")
+    assert err <= max(row["tol"], 2e-13)

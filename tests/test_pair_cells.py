@@ -3,8 +3,9 @@
 Cells have edge h = L / nc >= 2 r_c / 3 (nc = floor(3L / (2 r_c (1 + 1e-6)))),
 and a target scans the 4 x 4 x 4 cells starting at the cell of x - r_c.  This
 re-derives, with the kernel's index arithmetic, that every point within r_c
-of the target (minimum image) is in one of those cells, and that the 64 cells
-are distinct whenever nc >= 4.
+of the target (minimum image) is in one of those cells, that the 64 cells
+are distinct whenever nc >= 4, and that dropping the cells whose box lies
+farther than r_c from the target keeps every such point.
 """
 import math
 
@@ -40,3 +41,17 @@ def test_every_point_within_rc_is_in_the_window(rc):
         near = np.nonzero((d * d).sum(1) < rc * rc)[0]
         for i in near:
             assert tuple(pc[i]) in window
+        # the cull of the kernel: distance from x to the unwrapped cell box
+        h = L / nc
+        kept = set()
+        for c in range(4):
+            for b in range(4):
+                for a in range(4):
+                    v = s + np.array([a, b, c])
+                    lo, hi = v * h - xw, xw - (v + 1) * h
+                    dd = np.where(lo > 0, lo, np.where(hi > 0, hi, 0.0))
+                    if (dd * dd).sum() <= rc * rc * (1 + 1e-12):
+                        kept.add(tuple(v % nc))
+        for i in near:
+            assert tuple(pc[i]) in kept
+        assert len(kept) < 64
