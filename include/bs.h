@@ -114,7 +114,9 @@ typedef struct {
     int    Q;            /* Gauss-Legendre points per segment, 1..4 (0: 2)     */
     int    spline_order; /* 4 = cubic, 6 = quintic (App. B; 0: 4)              */
     int    precision;    /* BS_FP64 or BS_FP32_MIXED                           */
-    int    ns_mode;      /* BS_NS_OFF, BS_NS_ADAPTIVE or BS_NS_MLP             */
+    int    ns_mode;      /* BS_NS_OFF, BS_NS_ADAPTIVE or BS_NS_MLP (the
+                            network is trained on cubic segments: BS_NS_MLP
+                            needs spline_order 4)                           */
     double ns_eta;       /* flag pairs with chord distance < ns_eta * ell (0: 1) */
     const void *mlp_weights; /* host pointer to the packed float32 MLP
                                 parameters (see bs_mlp_nparams); needed for

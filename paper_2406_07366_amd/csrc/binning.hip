@@ -155,27 +155,27 @@ __global__ void k_keys_all(SortSet S, const double *__restrict__ qpos,
     wave_add<false>(S.cnt[2], k2, isn);
 }
 
-// one workgroup per array: exclusive scan of cnt into start (start[n] = total)
+// one workgroup per array: exclusive scan of cnt into start (start[n] = total);
+// thread t takes the contiguous run [t c, (t + 1) c) of c = ceil(n / 1024)
+// entries, so one block-wide scan of the run sums serves the whole array
 __global__ __launch_bounds__(1024) void k_scan_small(SortSet S) {
     __shared__ int sh[1024];
     const int a = blockIdx.x;
     const int n = S.nbins[a];
     const int *in = S.cnt[a];
     int *out = S.start[a];
-    int carry = 0;
-    for (int c0 = 0; c0 < n; c0 += 1024 * 4) {
-        int base = c0 + threadIdx.x * 4, v[4], s = 0;
-        for (int k = 0; k < 4; k++) { v[k] = (base + k < n) ? in[base + k] : 0; s += v[k]; }
-        int tot;
-        int ex = block_exclusive_scan(s, sh, &tot) + carry;
-        for (int k = 0; k < 4; k++) {
-            if (base + k < n) out[base + k] = ex;
-            ex += v[k];
-        }
-        carry += tot;
-        __syncthreads();
+    const int c = (n + blockDim.x - 1) / blockDim.x;
+    const int b0 = threadIdx.x * c, b1 = b0 + c < n ? b0 + c : n;
+    int sum = 0;
+    for (int i = b0; i < b1; i++) sum += in[i];
+    int total;
+    int ex = block_exclusive_scan(sum, sh, &total);
+    for (int i = b0; i < b1; i++) {
+        const int v = in[i];
+        out[i] = ex;
+        ex += v;
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (threadIdx.x == 0) out[n] = total;
 }
 
 __global__ void k_scatter_all(SortSet S) {

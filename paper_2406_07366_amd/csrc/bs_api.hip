@@ -177,8 +177,8 @@ int resolve(const bs_params *in, bs_params *out) {
         return bad("local_frac below 1e-3 (more than 10 panels per local segment)");
     if (r.precision != BS_FP64 && r.precision != BS_FP32_MIXED) return bad("unknown precision");
     if (r.ns_mode < BS_NS_OFF || r.ns_mode > BS_NS_MLP) return bad("unknown ns_mode");
-    if (r.ns_mode != BS_NS_OFF && r.spline_order != 4)
-        return bad("the near-singular correction is built for cubic splines only");
+    if (r.ns_mode == BS_NS_MLP && r.spline_order != 4)
+        return bad("the learned near-singular correction is trained on cubic segments only");
     if (r.ns_eta == 0) r.ns_eta = 1.0;
     if (!(r.ns_eta > 0)) return bad("ns_eta must be positive");
     if (r.fft_mode < BS_FFT_AUTO || r.fft_mode > BS_FFT_PRUNED) return bad("unknown fft_mode");
@@ -417,10 +417,11 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             int ncmax = (int)cbrt(2.0 * (double)N);
             P->ns_ncmax = ncmax < 3 ? 3 : (ncmax > 128 ? 128 : ncmax);
             const size_t nb3 = (size_t)P->ns_ncmax * P->ns_ncmax * P->ns_ncmax;
-            if ((rc = ensure<double>(P, P->ns_red, 1025)) || (rc = ensure<int>(P, P->ns_nc, 1)) ||
-                (rc = ensure<int>(P, P->ns_ckey, N)) || (rc = ensure<int>(P, P->ns_ccnt, nb3 + 1)) ||
-                (rc = ensure<int>(P, P->ns_cstart, nb3 + 1)) ||
-                (rc = ensure<int>(P, P->ns_cfill, nb3 + 1)) || (rc = ensure<int>(P, P->ns_cperm, N)) ||
+            if ((rc = ensure<double>(P, P->ns_red, 2 * 1024 + 1)) ||
+                (rc = ensure<int>(P, P->ns_nc, 2)) || (rc = ensure<int>(P, P->ns_ckey, N)) ||
+                (rc = ensure<int>(P, P->ns_ccnt, 2 * nb3 + 1)) ||
+                (rc = ensure<int>(P, P->ns_cstart, 2 * nb3 + 1)) ||
+                (rc = ensure<int>(P, P->ns_cfill, 2 * nb3 + 1)) || (rc = ensure<int>(P, P->ns_cperm, N)) ||
                 (rc = ensure<int>(P, P->ns_tkey, N)) || (rc = ensure<int>(P, P->ns_tcnt, nb3 + 1)) ||
                 (rc = ensure<int>(P, P->ns_tstart, nb3 + 1)) ||
                 (rc = ensure<int>(P, P->ns_tfill, nb3 + 1)) || (rc = ensure<int>(P, P->ns_tperm, N)) ||

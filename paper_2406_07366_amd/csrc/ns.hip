@@ -38,9 +38,9 @@ constexpr int kNsRedBlocks = 1024;
 
 __global__ void k_ns_reach(int N, const int *__restrict__ off, const int *__restrict__ fil,
                            const double *__restrict__ x, const double *__restrict__ ell,
-                           double eta, double *__restrict__ partial) {
-    __shared__ double sh[256];
-    double m = 0.0;
+                           double eta, double *__restrict__ pmax, double *__restrict__ psum) {
+    __shared__ double sh[256], ss[256];
+    double m = 0.0, sum = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
         const int jn = next_node_d(off, fil, j);
         double c2 = 0.0;
@@ -48,37 +48,66 @@ __global__ void k_ns_reach(int N, const int *__restrict__ off, const int *__rest
             double d = x[3 * jn + q] - x[3 * j + q];
             c2 += d * d;
         }
-        m = fmax(m, eta * ell[j] + 0.5 * sqrt(c2));
+        const double r = eta * ell[j] + 0.5 * sqrt(c2);
+        m = fmax(m, r);
+        sum += r;
     }
     sh[threadIdx.x] = m;
+    ss[threadIdx.x] = sum;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        if (threadIdx.x < o) {
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+            ss[threadIdx.x] += ss[threadIdx.x + o];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) {
+        pmax[blockIdx.x] = sh[0];
+        psum[blockIdx.x] = ss[0];
+    }
 }
 
-// nc = floor(L / max reach), at most ncmax; below 3 a single cell holds every
-// segment (the 27 neighbours would repeat cells)
-__global__ void k_ns_cells(const double *__restrict__ partial, int nparts, double L, int ncmax,
-                           double *__restrict__ maxreach, int *__restrict__ nc_out) {
-    __shared__ double sh[256];
-    double m = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partial[i]);
+// Two cell grids for the segments.  Grid A, of nc_A = floor(L / h) cells per
+// axis with h = min(max reach, 2 x mean reach) (at most ncmax), holds the
+// short segments (reach <= L / nc_A): a target scans the 27 A-cells around
+// its own.  Grid B, of nc_B = floor(L / max reach) cells, holds the few long
+// ones (its cells are at least as large as any reach): a target cell scans
+// the 4 x 4 x 4 B-cells from the B-cell of its lower corner minus one B edge.
+// nc_A < 3: one A-cell holds every segment (and grid B is empty); nc_B < 4:
+// one B-cell.  ncp[0] = nc_A, ncp[1] = nc_B.
+__global__ void k_ns_cells(const double *__restrict__ pmax, const double *__restrict__ psum,
+                           int nparts, int N, double L, int ncmax, double *__restrict__ maxreach,
+                           int *__restrict__ ncp) {
+    __shared__ double sh[256], ss[256];
+    double m = 0.0, sum = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        m = fmax(m, pmax[i]);
+        sum += psum[i];
+    }
     sh[threadIdx.x] = m;
+    ss[threadIdx.x] = sum;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        if (threadIdx.x < o) {
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+            ss[threadIdx.x] += ss[threadIdx.x + o];
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         m = sh[0];
-        double f = m > 0.0 ? floor(L / (m * (1.0 + 1e-9))) : (double)ncmax;
-        int nc = f > (double)ncmax ? ncmax : (int)f;
-        if (nc < 3) nc = 1;
+        const double mean = N > 0 ? ss[0] / N : 0.0;
+        const double h = fmin(m, 2.0 * mean);
+        double f = h > 0.0 ? floor(L / (h * (1.0 + 1e-9))) : (double)ncmax;
+        int na = f > (double)ncmax ? ncmax : (int)f;
+        if (na < 3) na = 1;
+        f = m > 0.0 ? floor(L / (m * (1.0 + 1e-9))) : 1.0;
+        int nb = f > (double)na ? na : (int)f;
+        if (nb < 4 || na == 1) nb = 1;
         *maxreach = m;
-        *nc_out = nc;
+        ncp[0] = na;
+        ncp[1] = nb;
     }
 }
 
@@ -92,24 +121,32 @@ __global__ void k_ns_zero(int n, int *__restrict__ a, int *__restrict__ b) {
     if (i < n) { a[i] = 0; b[i] = 0; }
 }
 
-// segment key: cell of the chord midpoint; target key: cell of the node
+// segment key: A-cell of the chord midpoint (short segments) or nc_A^3 +
+// B-cell of the chord midpoint (long ones); target key: A-cell of the node
 __global__ void k_ns_keys(int N, const int *__restrict__ off, const int *__restrict__ fil,
-                          const double *__restrict__ x, double L, const int *__restrict__ ncp,
-                          int *__restrict__ key, int *__restrict__ cnt, int *__restrict__ tkey,
-                          int *__restrict__ tcnt) {
+                          const double *__restrict__ x, const double *__restrict__ ell, double eta,
+                          double L, const int *__restrict__ ncp, int *__restrict__ key,
+                          int *__restrict__ cnt, int *__restrict__ tkey, int *__restrict__ tcnt) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = j < N;
     int k = 0, kt = 0;
     if (valid) {
-        const int nc = *ncp, jn = next_node_d(off, fil, j);
-        int c[3], d[3];
+        const int na = ncp[0], nb = ncp[1], jn = next_node_d(off, fil, j);
+        double c2 = 0.0, mid[3];
+        int d[3];
         for (int q = 0; q < 3; q++) {
-            c[q] = cell_of(0.5 * (x[3 * j + q] + x[3 * jn + q]), L, nc);
-            d[q] = cell_of(x[3 * j + q], L, nc);
+            const double e = x[3 * jn + q] - x[3 * j + q];
+            c2 += e * e;
+            mid[q] = 0.5 * (x[3 * j + q] + x[3 * jn + q]);
+            d[q] = cell_of(x[3 * j + q], L, na);
         }
-        k = (c[2] * nc + c[1]) * nc + c[0];
+        const bool shortseg = na == 1 || eta * ell[j] + 0.5 * sqrt(c2) <= L / na;
+        const int nc = shortseg ? na : nb;
+        int c[3];
+        for (int q = 0; q < 3; q++) c[q] = cell_of(mid[q], L, nc);
+        k = (c[2] * nc + c[1]) * nc + c[0] + (shortseg ? 0 : na * na * na);
         key[j] = k;
-        kt = (d[2] * nc + d[1]) * nc + d[0];
+        kt = (d[2] * na + d[1]) * na + d[0];
         tkey[j] = kt;
     }
     wave_add<false>(cnt, k, valid);
@@ -139,7 +176,7 @@ __global__ __launch_bounds__(64) void k_ns_sort(const int *__restrict__ ncp,
                                                const int *__restrict__ start, int *__restrict__ perm,
                                                int *__restrict__ scratch) {
     __shared__ int v[kNsSortLds];
-    const int nc = *ncp, nb = nc * nc * nc;
+    const int na = ncp[0], nbb = ncp[1], nb = na * na * na + nbb * nbb * nbb;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         const int s0 = start[b], n = start[b + 1] - s0;
         rank_sort_bin<kNsSortLds>(perm, scratch, s0, n, v);
@@ -328,8 +365,10 @@ __global__ __launch_bounds__(256) void k_ns_flag_cells(NsArgs a, const int *__re
                                                        int *__restrict__ status) {
     __shared__ float4 sm[kNsStage];
     __shared__ int sp[kNsStage];
-    __shared__ int cell_s[27], cell_o[27], tk[256], win_total;
-    const int nc = *a.ncp;
+    // window: the 27 A-cells (entries 0..26), then the B-cells (27..90)
+    constexpr int kWin = 27 + 64;
+    __shared__ int cell_s[kWin], cell_o[kWin], tk[256], tot_a, tot_b;
+    const int nc = a.ncp[0], ncb = a.ncp[1];
     if (nc < 3) return;
     const int nb3 = nc * nc * nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -337,15 +376,46 @@ __global__ __launch_bounds__(256) void k_ns_flag_cells(NsArgs a, const int *__re
     for (int C = blockIdx.x; C < nb3; C += gridDim.x) {
         const int t0 = tstart[C], nt = tstart[C + 1] - t0;
         if (nt == 0) continue;   // uniform over the workgroup
+        const int c0[3] = {C % nc, (C / nc) % nc, C / (nc * nc)};
         if (wave == 0) {
-            const int c0[3] = {C % nc, (C / nc) % nc, C / (nc * nc)};
             int cs, cn, total;
             const int excl = ns_window(a, nc, c0, lane, &cs, &cn, &total);
             if (lane < 27) { cell_s[lane] = cs; cell_o[lane] = excl; }
-            if (lane == 0) win_total = total;
+            if (lane == 0) tot_a = total;
+        } else if (wave == 1) {
+            // B-cells: 4 per axis from the B-cell of (lower corner - B edge),
+            // or the single B-cell
+            int cs = 0, cn = 0;
+            if (ncb >= 4 || lane == 0) {
+                int cidx = 0;
+                if (ncb >= 4) {
+                    const double ha = a.L / nc, hb = a.L / ncb;
+                    const int dd[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+                    int c[3];
+                    for (int q = 0; q < 3; q++) {
+                        int v = (int)floor((c0[q] * ha - hb) / hb) + dd[q];
+                        v %= ncb;
+                        c[q] = v < 0 ? v + ncb : v;
+                    }
+                    cidx = (c[2] * ncb + c[1]) * ncb + c[0];
+                }
+                cidx += nb3;
+                cs = a.cstart[cidx];
+                cn = a.cstart[cidx + 1] - cs;
+            }
+            int incl = cn;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int v = __shfl_up(incl, d);
+                if (lane >= d) incl += v;
+            }
+            cell_s[27 + lane] = cs;
+            cell_o[27 + lane] = incl - cn;   // relative; tot_a added below
+            if (lane == 63) tot_b = incl;
         }
         __syncthreads();
-        const int total = win_total;
+        if (threadIdx.x < 64) cell_o[27 + threadIdx.x] += tot_a;
+        __syncthreads();
+        const int total = tot_a + tot_b;
         for (int g0 = 0; g0 < nt; g0 += 256) {
             const int ng = nt - g0 < 256 ? nt - g0 : 256;
             for (int i = threadIdx.x; i < ng; i += blockDim.x) tk[i] = 0;
@@ -354,9 +424,9 @@ __global__ __launch_bounds__(256) void k_ns_flag_cells(NsArgs a, const int *__re
                 for (int i = threadIdx.x; i < cn; i += blockDim.x) {
                     const int q = c0 + i;
                     int c = 0;
-                    for (int step = 16; step > 0; step >>= 1) {
+                    for (int step = 64; step > 0; step >>= 1) {
                         const int tc = c + step;
-                        if (tc < 27 && cell_o[tc] <= q) c = tc;
+                        if (tc < kWin && cell_o[tc] <= q) c = tc;
                     }
                     const int p = cell_s[c] + (q - cell_o[c]);
                     sm[i] = a.segM[p];
@@ -405,13 +475,15 @@ __global__ void k_ns_compact(int64_t total_slots, int maxpn, const int *__restri
     }
 }
 
-// cubic Hermite segment j as c0 + c1 u + c2 u^2 + c3 u^3
+// spline segment j as c0 + c1 u + ... + c5 u^5, u in [0, 1]: the cubic
+// Hermite segment (c4 = c5 = 0) from node values and slopes, or, when the
+// nodal second derivatives S are given, the quintic Hermite segment
 struct Seg {
-    double c0[3], c1[3], c2[3], c3[3];
+    double c0[3], c1[3], c2[3], c3[3], c4[3], c5[3];
 };
 
 __device__ __forceinline__ Seg load_seg(int j, const int *off, const int *fil, const double *x,
-                                        const double *D, const double *dtau) {
+                                        const double *D, const double *S, const double *dtau) {
     Seg s;
     int jn = next_node_d(off, fil, j);
     double h = dtau[j];
@@ -420,10 +492,31 @@ __device__ __forceinline__ Seg load_seg(int j, const int *off, const int *fil, c
         double d0 = h * D[3 * j + q], d1 = h * D[3 * jn + q];
         s.c0[q] = s0;
         s.c1[q] = d0;
-        s.c2[q] = 3.0 * (s1 - s0) - 2.0 * d0 - d1;
-        s.c3[q] = 2.0 * (s0 - s1) + d0 + d1;
+        if (S) {
+            const double q0 = h * h * S[3 * j + q], q1 = h * h * S[3 * jn + q];
+            const double A = s1 - s0 - d0 - 0.5 * q0, B = d1 - d0 - q0, C = q1 - q0;
+            s.c2[q] = 0.5 * q0;
+            s.c3[q] = 10.0 * A - 4.0 * B + 0.5 * C;
+            s.c4[q] = -15.0 * A + 7.0 * B - C;
+            s.c5[q] = 6.0 * A - 3.0 * B + 0.5 * C;
+        } else {
+            s.c2[q] = 3.0 * (s1 - s0) - 2.0 * d0 - d1;
+            s.c3[q] = 2.0 * (s0 - s1) + d0 + d1;
+            s.c4[q] = s.c5[q] = 0.0;
+        }
     }
     return s;
+}
+
+// component q of s(u), s'(u), s''(u)
+__device__ __forceinline__ double seg_p(const Seg &s, int q, double u) {
+    return s.c0[q] + u * (s.c1[q] + u * (s.c2[q] + u * (s.c3[q] + u * (s.c4[q] + u * s.c5[q]))));
+}
+__device__ __forceinline__ double seg_d(const Seg &s, int q, double u) {
+    return s.c1[q] + u * (2.0 * s.c2[q] + u * (3.0 * s.c3[q] + u * (4.0 * s.c4[q] + u * 5.0 * s.c5[q])));
+}
+__device__ __forceinline__ double seg_dd(const Seg &s, int q, double u) {
+    return 2.0 * s.c2[q] + u * (6.0 * s.c3[q] + u * (12.0 * s.c4[q] + u * 20.0 * s.c5[q]));
 }
 
 // integral over u in [a, b] of (s(u) - x) x s'(u) / |s(u) - x|^3 with
@@ -435,8 +528,8 @@ __device__ void ns_panel(const Seg &s, const double *x, double a, double b, cons
         double u = m + hw * R.x[k];
         double r[3], d[3];
         for (int q = 0; q < 3; q++) {
-            r[q] = s.c0[q] + u * (s.c1[q] + u * (s.c2[q] + u * s.c3[q])) - x[q];
-            d[q] = s.c1[q] + u * (2.0 * s.c2[q] + 3.0 * u * s.c3[q]);
+            r[q] = seg_p(s, q, u) - x[q];
+            d[q] = seg_d(s, q, u);
         }
         double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         double f = R.w[k] * hw / (r2 * sqrt(r2));
@@ -452,8 +545,8 @@ __device__ void ns_panel(const Seg &s, const double *x, double a, double b, cons
 // (ratio 3) away from it.
 __device__ __forceinline__ void seg_eval(const Seg &s, double u, double *p, double *d1) {
     for (int q = 0; q < 3; q++) {
-        p[q] = s.c0[q] + u * (s.c1[q] + u * (s.c2[q] + u * s.c3[q]));
-        d1[q] = s.c1[q] + u * (2.0 * s.c2[q] + 3.0 * u * s.c3[q]);
+        p[q] = seg_p(s, q, u);
+        d1[q] = seg_d(s, q, u);
     }
 }
 
@@ -464,7 +557,7 @@ __device__ double closest_u(const Seg &s, const double *xs) {
     for (int k = 0; k <= 8; k++) {
         double u = k / 8.0, r2 = 0.0;
         for (int q = 0; q < 3; q++) {
-            double r = s.c0[q] + u * (s.c1[q] + u * (s.c2[q] + u * s.c3[q])) - xs[q];
+            double r = seg_p(s, q, u) - xs[q];
             r2 += r * r;
         }
         if (r2 < best) { best = r2; ub = u; }
@@ -472,9 +565,9 @@ __device__ double closest_u(const Seg &s, const double *xs) {
     for (int it = 0; it < 8; it++) {
         double g = 0.0, dg = 0.0;
         for (int q = 0; q < 3; q++) {
-            double r = s.c0[q] + ub * (s.c1[q] + ub * (s.c2[q] + ub * s.c3[q])) - xs[q];
-            double d1 = s.c1[q] + ub * (2.0 * s.c2[q] + 3.0 * ub * s.c3[q]);
-            double d2 = 2.0 * s.c2[q] + 6.0 * ub * s.c3[q];
+            double r = seg_p(s, q, ub) - xs[q];
+            double d1 = seg_d(s, q, ub);
+            double d2 = seg_dd(s, q, ub);
             g += r * d1;
             dg += d1 * d1 + r * d2;
         }
@@ -540,12 +633,12 @@ __device__ __forceinline__ void unpack_shift(int sh, const double *x, double L, 
 
 // Exact segment integral minus its Q-point sum, for one (node, segment) pair.
 __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, const double *x,
-                        const double *D, const double *dtau, const double *gamma,
+                        const double *D, const double *S, const double *dtau, const double *gamma,
                         const double *qpos, const double *qchg, int Q, double L,
                         const NsRule &R, double *out) {
     double xs[3];
     unpack_shift(sh, x + 3 * o, L, xs);
-    Seg s = load_seg(sg, off, fil, x, D, dtau);
+    Seg s = load_seg(sg, off, fil, x, D, S, dtau);
     double acc[3], qs[3];
     ns_seg_integral(s, xs, R, acc);
     ns_qsum(sg, xs, qpos, qchg, Q, qs);
@@ -556,14 +649,14 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
 __global__ __launch_bounds__(256) void k_ns_integrate(
     const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
     const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ D, const double *__restrict__ dtau,
+    const double *__restrict__ D, const double *__restrict__ S, const double *__restrict__ dtau,
     const double *__restrict__ gamma, const double *__restrict__ qpos,
     const double *__restrict__ qchg, int Q, double L, NsRule R, double *__restrict__ pout) {
     const int P = *total;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         int2 pr = pairs[p];
         double out[3];
-        ns_pair(pnode[p], pr.x, pr.y, off, fil, x, D, dtau, gamma, qpos, qchg, Q, L, R, out);
+        ns_pair(pnode[p], pr.x, pr.y, off, fil, x, D, S, dtau, gamma, qpos, qchg, Q, L, R, out);
         pout[3 * (size_t)p] = out[0];
         pout[3 * (size_t)p + 1] = out[1];
         pout[3 * (size_t)p + 2] = out[2];
@@ -773,6 +866,7 @@ __global__ void k_ns_samples(int64_t n, const double *__restrict__ U, NsRule R,
         s.c1[q] = D0[q];
         s.c2[q] = 3.0 * (B[q] - A[q]) - 2.0 * D0[q] - D1[q];
         s.c3[q] = 2.0 * (A[q] - B[q]) + D0[q] + D1[q];
+        s.c4[q] = s.c5[q] = 0.0;
     }
     double I[3];
     ns_seg_integral(s, x, R, I);
@@ -841,11 +935,11 @@ __global__ __launch_bounds__(256) void k_ns_combine(
         double A[3], B[3], D0[3], D1[3], xs[3];
         pair_geometry(o, pr.x, pr.y, off, fil, x, D, dtau, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
-        Seg sgm = load_seg(pr.x, off, fil, x, D, dtau);
+        Seg sgm = load_seg(pr.x, off, fil, x, D, nullptr, dtau);
         const TangentBase tb = tangent_baseline(sgm, xs, F.h);
         double out[3];
         if (!F.inbox || (double)box.err[ns_bin(tb.dstar)] > box.tol) {
-            ns_pair(o, pr.x, pr.y, off, fil, x, D, dtau, gamma, qpos, qchg, Q, L, R, out);
+            ns_pair(o, pr.x, pr.y, off, fil, x, D, nullptr, dtau, gamma, qpos, qchg, Q, L, R, out);
             atomicAdd(nfallback, 1);
         } else {
             // segment integral = I_tan + mult * (network output in the chord
@@ -877,23 +971,24 @@ void ns_build_pairs(bs_plan_t p) {
     double *red = (double *)p->ns_red.p;
     const int nred = ceil_div(N, bs) < kNsRedBlocks ? ceil_div(N, bs) : kNsRedBlocks;
     hipLaunchKernelGGL(k_ns_reach, dim3(nred), dim3(bs), 0, p->stream, N, off, fil, x, ell,
-                       p->prm.ns_eta, red + 1);
-    hipLaunchKernelGGL(k_ns_cells, dim3(1), dim3(bs), 0, p->stream, red + 1, nred, p->prm.L,
-                       p->ns_ncmax, red, ncp);
+                       p->prm.ns_eta, red + 1, red + 1 + kNsRedBlocks);
+    hipLaunchKernelGGL(k_ns_cells, dim3(1), dim3(bs), 0, p->stream, red + 1,
+                       red + 1 + kNsRedBlocks, nred, N, p->prm.L, p->ns_ncmax, red, ncp);
     int *tkey = (int *)p->ns_tkey.p, *tcnt = (int *)p->ns_tcnt.p, *tstart = (int *)p->ns_tstart.p;
     int *tfill = (int *)p->ns_tfill.p, *tperm = (int *)p->ns_tperm.p;
-    hipLaunchKernelGGL(k_ns_zero, dim3(ceil_div(nb3 + 1, bs)), dim3(bs), 0, p->stream, nb3 + 1,
-                       ccnt, cfill);
+    // segment keys span both grids (nc_B <= nc_A <= ncmax)
+    hipLaunchKernelGGL(k_ns_zero, dim3(ceil_div(2 * nb3 + 1, bs)), dim3(bs), 0, p->stream,
+                       2 * nb3 + 1, ccnt, cfill);
     hipLaunchKernelGGL(k_ns_zero, dim3(ceil_div(nb3 + 1, bs)), dim3(bs), 0, p->stream, nb3 + 1,
                        tcnt, tfill);
     hipLaunchKernelGGL(k_ns_keys, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, off, fil, x,
-                       p->prm.L, (const int *)ncp, ckey, ccnt, tkey, tcnt);
-    exclusive_scan(p, ccnt, cstart, nb3);
+                       ell, p->prm.ns_eta, p->prm.L, (const int *)ncp, ckey, ccnt, tkey, tcnt);
+    exclusive_scan(p, ccnt, cstart, 2 * nb3);
     exclusive_scan(p, tcnt, tstart, nb3);
     hipLaunchKernelGGL(k_ns_scatter, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
                        (const int *)ckey, (const int *)cstart, cfill, cperm, (const int *)tkey,
                        (const int *)tstart, tfill, tperm);
-    const int nsort = nb3 < 4096 ? nb3 : 4096;
+    const int nsort = 2 * nb3 < 4096 ? 2 * nb3 : 4096;
     hipLaunchKernelGGL(k_ns_sort, dim3(nsort), dim3(64), 0, p->stream, (const int *)ncp,
                        (const int *)cstart, cperm, ckey);
     hipLaunchKernelGGL(k_ns_gather, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
@@ -933,6 +1028,7 @@ void launch_ns_adaptive(bs_plan_t p, double *v) {
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
                        (const double *)p->d_x.p, (const double *)p->d_D.p,
+                       p->order == 6 ? (const double *)p->d_sdd.p : nullptr,
                        (const double *)p->d_dtau.p, (const double *)p->d_gamma.p,
                        (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q,
                        p->prm.L, R, (double *)p->ns_pout.p);

@@ -97,7 +97,7 @@ def test_parameter_errors():
     assert e.value.code == B.BS_EKB
     B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, spline_order=6,
                                    local_frac=0.1))
-    for bad in (dict(spline_order=5), dict(spline_order=6, ns_mode=B.BS_NS_ADAPTIVE),
+    for bad in (dict(spline_order=5), dict(spline_order=6, ns_mode=B.BS_NS_MLP),
                 dict(local_frac=1.5), dict(local_frac=-0.1), dict(local_frac=1e-4)):
         with pytest.raises(B.BsError) as e:
             B.resolve_params(B.make_params(L=L, a=1e-6, tol=1e-6, grid_n=64, **bad))

@@ -147,7 +147,7 @@ def test_quintic_rk4_follows_oracle(B):
     plan.close()
 
 
-def test_quintic_rejects_short_filaments_and_ns(B):
+def test_quintic_rejects_short_filaments_and_the_network(B):
     fs = ragged([5, 9])
     plan = B.Plan(B.params_for(fs, spline_order=6))
     xyz, g = B.load_workload(fs)
@@ -155,4 +155,19 @@ def test_quintic_rejects_short_filaments_and_ns(B):
         plan.set_filaments(fs.offsets, xyz, g)
     plan.close()
     with pytest.raises(B.BsError):
-        B.Plan(B.params_for(fs, spline_order=6, ns_mode=B.BS_NS_ADAPTIVE))
+        B.Plan(B.params_for(fs, spline_order=6, ns_mode=B.BS_NS_MLP))
+
+
+def test_quintic_near_singular_term_matches_oracle(B):
+    """The adaptive near-singular correction on quintic segments (the exact
+    segment integral of the quintic Hermite segment minus its Q-point sum)
+    against the oracle's Gauss-Kronrod integrals on its B-spline segments."""
+    fs = W.ringpairs(npairs=150, nbg=20, seed=77)
+    fs.grid_n, fs.tol = 64, 1e-6
+    plan = make_plan(B, fs, ns_mode=B.BS_NS_ADAPTIVE, spline_order=6, Q=3)
+    dv = np_(plan.velocity_terms()["ns"])
+    ref, cnt = O.Oracle(fs, Q=3, order=6).ns_correction(eta=1.0)
+    err = rel_l2(dv, ref)
+    print(f"  quintic ns term rel_l2 {err:.2e}, flagged pairs {cnt.sum()}")
+    assert cnt.sum() > fs.n_nodes and err < 1e-10
+    plan.close()

@@ -1,12 +1,16 @@
 """CPU model of the near-singular pair search's cell bookkeeping (no GPU).
 
-Segments are binned by chord midpoint into nc^3 cells with
-nc = floor(L / max_j reach_j), reach_j = eta*ell_j + |B_j - A_j|/2 (nc < 3:
-one cell).  The flag pass of a target scans the 27 cells around the target's
-cell.  This test re-derives, on random tangles with long and short segments
-and targets near the box faces, that every pair a brute-force search flags
-(chord distance below eta*ell_j, minimum image) has its segment inside that
-window, and that the 27 cells are distinct whenever nc >= 3.
+Segments are binned by chord midpoint into two grids, reach_j =
+eta*ell_j + |B_j - A_j|/2.  Grid A has nc_A = floor(L / h) cells per axis,
+h = min(max reach, 2 x mean reach) (nc_A < 3: one cell), and holds the short
+segments (reach <= L / nc_A); a target scans the 27 A-cells around its own.
+Grid B has nc_B = floor(L / max reach) cells (at most nc_A; below 4: one
+cell) and holds the long segments; a target in A-cell c scans the 4 x 4 x 4
+B-cells from the B-cell of c's lower corner minus one B edge.  This test
+re-derives, on random tangles with long and short segments and targets near
+the box faces, that every pair a brute-force search flags (chord distance
+below eta*ell_j, minimum image) has its segment inside the window of its
+grid, and that the window cells are distinct, so every pair is found once.
 """
 import math
 
@@ -42,23 +46,39 @@ def test_flagged_segments_lie_in_the_27_cells(seed):
     B = A + ln[:, None] * d / np.linalg.norm(d, axis=1)[:, None]
     ell = ln * rng.uniform(1.0, 1.2, nseg)           # arc length >= chord
     reach = eta * ell + 0.5 * np.linalg.norm(B - A, axis=1)
-    nc = int(math.floor(L / (reach.max() * (1 + 1e-9))))
-    nc = 1 if nc < 3 else nc
-    mcell = cell_of(0.5 * (A + B), L, nc)
+    h = min(reach.max(), 2 * reach.mean())
+    na = int(math.floor(L / (h * (1 + 1e-9))))
+    na = 1 if na < 3 else na
+    nb = min(int(math.floor(L / (reach.max() * (1 + 1e-9)))), na)
+    nb = 1 if (nb < 4 or na == 1) else nb
+    short = (na == 1) | (reach <= L / na)
+    assert (~short).sum() < short.sum()          # few long segments
+    acell = cell_of(0.5 * (A + B), L, na)
+    bcell = cell_of(0.5 * (A + B), L, nb)
     # targets: near the segments (the interesting case) and near box faces
     x = np.concatenate([A + rng.normal(scale=0.05, size=A.shape),
                         rng.choice([0.0, L - 1e-12], size=(100, 3)) + rng.normal(scale=1e-3, size=(100, 3))])
+    ha, hb = L / na, L / nb
     for xi in x:
         dist = chord_dist(A, B, xi[None], L)
         flagged = np.nonzero(dist < eta * ell)[0]
-        c0 = cell_of(xi, L, nc)
-        if nc >= 3:
-            window = {tuple((c0 + np.array([dx, dy, dz])) % nc)
-                      for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)}
-            assert len(window) == 27
-            for j in flagged:
-                assert tuple(mcell[j]) in window, (xi, j)
-        # single cell: every segment is scanned
+        c0 = cell_of(xi, L, na)
+        if na < 3:
+            continue                              # one cell: every segment is scanned
+        wa = {tuple((c0 + np.array([dx, dy, dz])) % na)
+              for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)}
+        assert len(wa) == 27
+        if nb >= 4:
+            v0 = np.floor((c0 * ha - hb) / hb).astype(int)
+            wb = {tuple((v0 + np.array([dx, dy, dz])) % nb)
+                  for dz in range(4) for dy in range(4) for dx in range(4)}
+            assert len(wb) == 64
+        for j in flagged:
+            if short[j]:
+                assert tuple(acell[j]) in wa, (xi, j)
+            elif nb >= 4:
+                assert tuple(bcell[j]) in wb, (xi, j)
+            # nb == 1: the single B-cell is scanned by every target
 
 
 def test_cell_count_matches_the_reach_bound():
