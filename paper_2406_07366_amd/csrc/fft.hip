@@ -139,61 +139,72 @@ __host__ __device__ constexpr int plan_lr(int logn, int p) {
 
 // The transform length, the radix, Ns and whether the pass is the first
 // or the last are compile-time, so the index arithmetic folds to shifts
-// and masks and the pass sequence unrolls.
-template <int R, int N, int NS, bool FIRST, bool LAST, bool JFAST, typename C, typename T,
-          typename Load, typename Store>
+// and masks and the pass sequence unrolls.  Each thread owns IPT items
+// (t, t + blockDim, ...), all read before the barrier and written after it.
+template <int R, int N, int NS, bool FIRST, bool LAST, bool JFAST, int IPT, typename C,
+          typename T, typename Load, typename Store>
 __device__ __forceinline__ void fft_pass(int nseq, int pitch, C *buf, const C *tw, T sgn,
                                          Load &load, Store &store) {
     constexpr int NJ = N / R;
-    const int t = threadIdx.x;
-    const bool act = t < NJ * nseq;
-    const int s = JFAST ? t / NJ : t % nseq, j = JFAST ? t % NJ : t / nseq;
-    const int jm = j & (NS - 1);
-    C v[R];
-    if (act) {
+    C v[IPT][R];
+    int sv[IPT], jv[IPT];
+    bool act[IPT];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int e = j + r * NJ;
-            if constexpr (FIRST) v[r] = load(s, e);
-            else v[r] = buf[lds_at<JFAST>(s, e, pitch)];
-        }
-        if constexpr (NS > 1) {
-            if (jm != 0) {
-                constexpr int STEP = N / (NS * R);
+    for (int it = 0; it < IPT; it++) {
+        const int t = threadIdx.x + it * blockDim.x;
+        act[it] = t < NJ * nseq;
+        const int s = JFAST ? t / NJ : t % nseq, j = JFAST ? t % NJ : t / nseq;
+        sv[it] = s;
+        jv[it] = j;
+        if (act[it]) {
+            const int jm = j & (NS - 1);
 #pragma unroll
-                for (int r = 1; r < R; r++) {
-                    const C w = tw[jm * r * STEP];
-                    const C u = v[r];
-                    v[r] = C{w.x * u.x - w.y * u.y, w.x * u.y + w.y * u.x};
+            for (int r = 0; r < R; r++) {
+                const int e = j + r * NJ;
+                if constexpr (FIRST) v[it][r] = load(s, e);
+                else v[it][r] = buf[lds_at<JFAST>(s, e, pitch)];
+            }
+            if constexpr (NS > 1) {
+                if (jm != 0) {
+                    constexpr int STEP = N / (NS * R);
+#pragma unroll
+                    for (int r = 1; r < R; r++) {
+                        const C w = tw[jm * r * STEP];
+                        const C u = v[it][r];
+                        v[it][r] = C{w.x * u.x - w.y * u.y, w.x * u.y + w.y * u.x};
+                    }
                 }
             }
+            dft_regs<R>(v[it], sgn);
         }
-        dft_regs<R>(v, sgn);
     }
     __syncthreads();
-    if (act) {
-        const int d0 = (j - jm) * R + jm;
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int e = d0 + r * NS;
-            if constexpr (LAST) store(s, e, v[r]);
-            else buf[lds_at<JFAST>(s, e, pitch)] = v[r];
+    for (int it = 0; it < IPT; it++) {
+        if (act[it]) {
+            const int j = jv[it], jm = j & (NS - 1), d0 = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int e = d0 + r * NS;
+                if constexpr (LAST) store(sv[it], e, v[it][r]);
+                else buf[lds_at<JFAST>(sv[it], e, pitch)] = v[it][r];
+            }
         }
     }
     __syncthreads();
 }
 
 // tw: the twiddle table in LDS (n entries); passes P, P+1, ... of the plan
-template <bool JFAST, int LOGN, int P = 0, int NS = 1, typename C, typename T, typename Load,
-          typename Store>
+template <bool JFAST, int LOGN, int IPT = 1, int P = 0, int NS = 1, typename C, typename T,
+          typename Load, typename Store>
 __device__ __forceinline__ void fft_run(int nseq, int pitch, C *buf, const C *tw, T sgn,
                                         Load &load, Store &store) {
     constexpr int LR = plan_lr(LOGN, P);
     if constexpr (LR > 0) {
         constexpr bool LAST = plan_lr(LOGN, P + 1) == 0;
-        fft_pass<1 << LR, 1 << LOGN, NS, P == 0, LAST, JFAST>(nseq, pitch, buf, tw, sgn, load,
-                                                                store);
-        fft_run<JFAST, LOGN, P + 1, (NS << LR)>(nseq, pitch, buf, tw, sgn, load, store);
+        fft_pass<1 << LR, 1 << LOGN, NS, P == 0, LAST, JFAST, IPT>(nseq, pitch, buf, tw, sgn,
+                                                                     load, store);
+        fft_run<JFAST, LOGN, IPT, P + 1, (NS << LR)>(nseq, pitch, buf, tw, sgn, load, store);
     }
 }
 
@@ -204,7 +215,17 @@ __device__ __forceinline__ void stage_twiddles(C *dst, const C *__restrict__ src
 }
 
 constexpr int kFftMaxThreads = 512;
-constexpr int kFftLds = 65536;        // LDS per workgroup, at most
+constexpr int kFftLds = 65536;        // LDS per workgroup, at most (x, y passes)
+constexpr int kFftLdsZ = 81920;       // z pass with several items per thread (two
+                                      // workgroups per CU; measured faster than one)
+
+// items per thread of the z pass: large float32 grids take several columns
+// per thread so that a workgroup spans enough adjacent columns mx for its
+// loads and stores to coalesce (measured slower in float64, where the LDS
+// then allows one workgroup per CU)
+__host__ __device__ constexpr int z_ipt(int logn, int csize) {
+    return logn >= 9 && csize == 8 ? 4 : 1;
+}
 
 // ---------------------------------------------------------------- x pass
 // nseq rows (c, z, y) per workgroup; forward: keep modes 0..K
@@ -333,7 +354,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int K, int nseq, i
 // one workgroup per (my, group of KZ columns mx): the three components'
 // z-columns (sequence s = c KZ + q), forward FFT into LDS, spectral operator,
 // inverse FFT from LDS, written back.
-template <typename R, int LOGN>
+template <typename R, int LOGN, int IPT>
 __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
     int K, int KZ, int per, int psi, double k0, double inv4a2, double invV,
     const double *__restrict__ dec2, const typename Cx<R>::T *__restrict__ twf,
@@ -355,7 +376,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
         return kx < K1 ? B[c * cstride + ((size_t)myp * n + e) * K1 + kx] : C{(R)0, (R)0};
     };
     auto lstore = [&](int s, int e, C v) { buf[e * pitch + s] = v; };
-    fft_run<false, LOGN>(S, pitch, buf, twl, (R)-1, gload, lstore);
+    fft_run<false, LOGN, IPT>(S, pitch, buf, twl, (R)-1, gload, lstore);
     const int my = myp - K;
     for (int i = threadIdx.x; i < n * KZ; i += blockDim.x) {
         const int z = i / KZ, q = i - z * KZ;
@@ -392,7 +413,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
         const int c = s / KZ, kx = kx0 + (s - c * KZ);
         if (kx < K1) B[c * cstride + ((size_t)myp * n + e) * K1 + kx] = v;
     };
-    fft_run<false, LOGN>(S, pitch, buf, twl + n, (R)1, lload, gstore);
+    fft_run<false, LOGN, IPT>(S, pitch, buf, twl + n, (R)1, lload, gstore);
 }
 
 // --------------------------------------------------------------- launch
@@ -456,9 +477,14 @@ static void pruned_spectral(bs_plan_t p, int psi) {
     const double *dec2 = (const double *)p->deconv.p + (p->prm.K + 1);
     const C *twf = (const C *)p->fft_tw.p, *twi = twf + n;
     const int pz = ceil_div((2 * K + 1) * ceil_div(K1, KZ), 8);
-    hipLaunchKernelGGL((k_fft_z_spectral<R, LOGN>), dim3(8 * pz), dim3(3 * KZ * fft_max_nj(LOGN)),
-                       (2 * n + n * (3 * KZ + 1)) * sizeof(C), p->stream, K, KZ, pz, psi, k0,
-                       inv4a2, 1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
+    constexpr int IPT = z_ipt(LOGN, (int)sizeof(C));
+    const size_t lds = (2 * n + n * (3 * KZ + 1)) * sizeof(C);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_fft_z_spectral<R, LOGN, IPT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_fft_z_spectral<R, LOGN, IPT>), dim3(8 * pz),
+                       dim3(ceil_div(3 * KZ * fft_max_nj(LOGN), IPT)), lds, p->stream, K, KZ, pz,
+                       psi, k0, inv4a2, 1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
 }
 
 template <typename R, int LOGN>
@@ -507,7 +533,7 @@ static int pow2_floor(int v) {
 }
 
 void pruned_batches(int n, size_t csize, int *rb, int *kb, int *kz) {
-    const int logn = ilog2(n), mnj = fft_max_nj(logn);
+    const int logn = ilog2(n), mnj = fft_max_nj(logn), ipt = z_ipt(logn, (int)csize);
     const int threads = csize > 8 ? 128 : 256;
     int b = threads / mnj;
     // twiddles (n, 2n in the z pass) + rows of about n + n/16 + 1 entries
@@ -516,9 +542,14 @@ void pruned_batches(int n, size_t csize, int *rb, int *kb, int *kz) {
     b = pow2_floor(b < 1 ? 1 : b);
     *rb = b;
     *kb = b;
-    int z = b / 3;
+    // z pass: 3 kz sequences of mnj items, ipt items per thread, at most
+    // kFftMaxThreads threads; LDS 2 twiddle tables + 3 kz + 1 columns
+    const size_t zlds = ipt > 1 ? kFftLdsZ : kFftLds;
+    int z = ipt > 1 ? kFftMaxThreads * ipt / (3 * mnj) : b / 3;
     z = z < 1 ? 1 : z;
-    while (z > 1 && (size_t)(2 * n + n * (3 * z + 1)) * csize > kFftLds) z--;
+    while (z > 1 && ((size_t)(2 * n + n * (3 * z + 1)) * csize > zlds ||
+                     ceil_div(3 * z * mnj, ipt) > kFftMaxThreads))
+        z--;
     *kz = z;
 }
 

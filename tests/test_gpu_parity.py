@@ -246,9 +246,11 @@ def test_graph_replay_matches_eager(B):
         plan.close()
 
 
-def _pruned_vs_library(B, precision):
+def _pruned_vs_library(B, precision, grid_n=None):
     import torch
     fs = W.ellipses()
+    if grid_n:
+        fs.grid_n = grid_n
     out = {}
     for mode in (B.BS_FFT_PRUNED, B.BS_FFT_LIBRARY):
         plan = make_plan(B, fs, precision=precision, fft_mode=mode)
@@ -260,11 +262,14 @@ def _pruned_vs_library(B, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_pruned_transforms_agree_with_hipfft(B, precision):
+@pytest.mark.parametrize("grid_n", [64, 128, 256, 512])
+def test_pruned_transforms_agree_with_hipfft(B, precision, grid_n):
     """The pruned transforms with the fused spectral operator: velocity,
     streamfunction and energy agree with the full hipFFT r2c / c2r path to
-    rounding (float64) or float32 rounding (mixed)."""
-    out = _pruned_vs_library(B, precision)
+    rounding (float64) or float32 rounding (mixed), on every radix plan the
+    workloads use (64 = 8.8, 128 = 16.8, 256 = 16.16, 512 = 8.8.8, whose z
+    pass takes four columns per thread)."""
+    out = _pruned_vs_library(B, precision, grid_n)
     (va, pa, Ea), (vb, pb, Eb) = out[B.BS_FFT_PRUNED], out[B.BS_FFT_LIBRARY]
     tol = 1e-12 if precision == 0 else 2e-6
     dv, dp = rel_l2(va, vb), rel_l2(pa, pb)
