@@ -355,10 +355,12 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
 // takes targets w, w + 4, ...  and scans each chunk 64 candidates per step.
 // Flagged candidates are ranked with a ballot, so each target's pairs are
 // written in candidate order to its max_per_node slots.  Targets are taken
-// 256 at a time (their running counts live in LDS).
-constexpr int kNsStage = 2048;
+// 256 at a time (their running counts live in LDS).  Staging 1024 records at
+// a time and at most 84 VGPRs keep six wavefronts per SIMD (measured faster
+// than larger stages at lower occupancy).
+constexpr int kNsStage = 1024;
 
-__global__ __launch_bounds__(256) void k_ns_flag_cells(NsArgs a, const int *__restrict__ tstart,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_ns_flag_cells(NsArgs a, const int *__restrict__ tstart,
                                                        const int *__restrict__ tperm,
                                                        int *__restrict__ cnt,
                                                        int2 *__restrict__ slots,
