@@ -155,27 +155,43 @@ __global__ void k_keys_all(SortSet S, const double *__restrict__ qpos,
     wave_add<false>(S.cnt[2], k2, isn);
 }
 
-// one workgroup per array: exclusive scan of cnt into start (start[n] = total);
-// thread t takes the contiguous run [t c, (t + 1) c) of c = ceil(n / 1024)
-// entries, so one block-wide scan of the run sums serves the whole array
+// one workgroup per array: exclusive scan of cnt into start (start[n] =
+// total).  Wavefront w owns the contiguous segment [w seg, (w + 1) seg) and
+// reads it 64 entries at a time (coalesced): a first pass sums it, the
+// segment offsets are formed from the 16 sums in LDS, and a second pass
+// scans each 64-entry chunk by shuffles while writing.
 __global__ __launch_bounds__(1024) void k_scan_small(SortSet S) {
-    __shared__ int sh[1024];
+    __shared__ int wsum[16];
     const int a = blockIdx.x;
     const int n = S.nbins[a];
     const int *in = S.cnt[a];
     int *out = S.start[a];
-    const int c = (n + blockDim.x - 1) / blockDim.x;
-    const int b0 = threadIdx.x * c, b1 = b0 + c < n ? b0 + c : n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int seg = ((n + nw - 1) / nw + 63) / 64 * 64;
+    const int b0 = wave * seg, b1 = b0 + seg < n ? b0 + seg : n;
     int sum = 0;
-    for (int i = b0; i < b1; i++) sum += in[i];
-    int total;
-    int ex = block_exclusive_scan(sum, sh, &total);
-    for (int i = b0; i < b1; i++) {
-        const int v = in[i];
-        out[i] = ex;
-        ex += v;
+    for (int i = b0 + lane; i < b1; i += 64) sum += in[i];
+    for (int m = 32; m > 0; m >>= 1) sum += __shfl_xor(sum, m);
+    if (lane == 0) wsum[wave] = sum;
+    __syncthreads();
+    int carry = 0;
+    for (int w = 0; w < wave; w++) carry += wsum[w];
+    for (int c0 = b0; c0 < b1; c0 += 64) {
+        const int i = c0 + lane;
+        const int v = i < b1 ? in[i] : 0;
+        int incl = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl, d);
+            if (lane >= d) incl += u;
+        }
+        if (i < b1) out[i] = carry + incl - v;
+        carry += __shfl(incl, 63);
     }
-    if (threadIdx.x == 0) out[n] = total;
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < nw; w++) tot += wsum[w];
+        out[n] = tot;
+    }
 }
 
 __global__ void k_scatter_all(SortSet S) {

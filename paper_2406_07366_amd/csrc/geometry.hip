@@ -462,7 +462,7 @@ __device__ void local_self_node(int i, int ip, int in, double g, const LocalArgs
 }
 
 template <int ORDER>
-__global__ void k_local_self(int N, LocalArgs la, const double *__restrict__ x,
+__global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const double *__restrict__ x,
                              const int *__restrict__ off, const int *__restrict__ fil,
                              const double *__restrict__ gamma, const double *__restrict__ dtau,
                              const double *__restrict__ D, const double *__restrict__ sdd,
@@ -481,7 +481,7 @@ __global__ void k_local_self(int N, LocalArgs la, const double *__restrict__ x,
 // lengths, and the velocity's local term minus the long-range self
 // correction (into vls, which the interpolation adds to the velocity).
 template <int ORDER>
-__global__ void k_filament(int nfil, const int *__restrict__ off, const double *xs,
+__global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restrict__ off, const double *xs,
                            double *xd, const double *__restrict__ gs, double *__restrict__ gd,
                            double *__restrict__ dtau, double *__restrict__ D,
                            double *__restrict__ sdd, double *__restrict__ qpos,
