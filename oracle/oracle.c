@@ -65,6 +65,7 @@ typedef struct {
     double *dtau;      /* N: tau_{j+1}-tau_j */
     double *M;         /* N*3 second derivatives at nodes (moments) */
     double *C;         /* N*3 B-spline coefficients (order 6 only) */
+    double *shift;     /* nfil*3: s(tau + T) = s(tau) + shift (n L; 0: closed) */
     double *T;         /* nfil: period of the parameter */
     double *sd;        /* N*3 first derivative at nodes */
     double *ell;       /* N: segment length by the Q-point rule */
@@ -92,6 +93,32 @@ static inline int64_t next_node(const or_t *o, int64_t j) {
 static inline int64_t prev_node(const or_t *o, int64_t j) {
     int64_t f = o->fil[j];
     return (j > o->off[f]) ? j - 1 : o->off[f + 1] - 1;
+}
+
+/* Sec. 2.1: a filament satisfies s(tau + T) = s(tau) + n L (n = 0: closed).
+ * The node after the last one is the first node moved by n L; wrap(o, j)
+ * is 1 when segment j is that closing segment. */
+static inline int wraps(const or_t *o, int64_t j) {
+    return j + 1 == o->off[o->fil[j] + 1];
+}
+
+/* position of the end of segment j in the frame of its start (nodal data
+ * other than positions repeats with period T: shifted = 0) */
+static inline void seg_end(const or_t *o, const double *data, int64_t j, int shifted,
+                           double *out) {
+    int64_t jn = next_node(o, j);
+    const double *sh = o->shift + 3 * o->fil[j];
+    int w = shifted && wraps(o, j);
+    for (int c = 0; c < 3; c++) out[c] = data[3 * jn + c] + (w ? sh[c] : 0.0);
+}
+
+/* offset that brings the points of segment seg (adjacent to node i) into
+ * the frame of node i: -n L for the closing segment ending at the first
+ * node, else 0 */
+static inline void adj_offset(const or_t *o, int64_t i, int64_t seg, double *E) {
+    int64_t f = o->fil[i];
+    int w = (i == o->off[f]) && seg == prev_node(o, i);
+    for (int c = 0; c < 3; c++) E[c] = w ? -o->shift[3 * f + c] : 0.0;
 }
 
 /* ------------------------------------------------- Gauss-Legendre on [0,1] */
@@ -202,15 +229,17 @@ static void basis_knots(const or_t *o, int64_t f, int64_t jp, int k, double *kn)
 /* s = sum_j c_j b_j(tau) (eq:spline_from_bspline_basis) at tau = tau_j + t:
  * the basis functions whose support covers [t_j, t_{j+1}) are j-2..j+3 */
 static void bspline_eval(const or_t *o, const double *coef, int64_t j, double t, int deriv,
-                         double *out) {
+                         int shifted, double *out) {
     int64_t f = o->fil[j], b = o->off[f], n = o->off[f + 1] - b, jl = j - b;
     double x = o->tau[j] + t, kn[8];
     out[0] = out[1] = out[2] = 0.0;
     for (int64_t jp = jl - 2; jp <= jl + 3; jp++) {
         basis_knots(o, f, jp, 6, kn);
         double w = bspl(kn, 6, x, deriv);
-        int64_t q = ((jp % n) + n) % n;
-        for (int c = 0; c < 3; c++) out[c] += w * coef[3 * (b + q) + c];
+        int64_t q = ((jp % n) + n) % n, k = (jp - q) / n;
+        /* c_{jp} = c_{jp mod n} + k n L for positions (Sec. 2.1) */
+        for (int c = 0; c < 3; c++)
+            out[c] += w * (coef[3 * (b + q) + c] + (shifted ? k * o->shift[3 * f + c] : 0.0));
     }
 }
 
@@ -249,17 +278,22 @@ static int dense_solve(int64_t n, double *A, double *r, int nrhs) {
 
 /* interpolation A c = d with A_ij = b_j(tau_i) (App. B) for the nodal data d
  * (3 components) of filament f; coefficients into coef */
-static int quintic_fit(const or_t *o, int64_t f, const double *data, double *coef) {
+static int quintic_fit(const or_t *o, int64_t f, const double *data, int shifted,
+                       double *coef) {
     int64_t b = o->off[f], n = o->off[f + 1] - b;
     double *A = (double *)calloc((size_t)(n * n), sizeof(double));
     double *r = (double *)malloc(sizeof(double) * 3 * n), kn[8];
     for (int64_t i = 0; i < n; i++) {
+        for (int c = 0; c < 3; c++) r[3 * i + c] = data[3 * (b + i) + c];
         for (int64_t jp = i - 3; jp <= i + 3; jp++) {
             basis_knots(o, f, jp, 6, kn);
-            int64_t q = ((jp % n) + n) % n;
-            A[i * n + q] += bspl(kn, 6, o->tau[b + i], 0);
+            int64_t q = ((jp % n) + n) % n, k = (jp - q) / n;
+            double w = bspl(kn, 6, o->tau[b + i], 0);
+            A[i * n + q] += w;
+            /* the wrapped coefficients carry k n L: moved to the right side */
+            if (shifted && k != 0)
+                for (int c = 0; c < 3; c++) r[3 * i + c] -= w * k * o->shift[3 * f + c];
         }
-        for (int c = 0; c < 3; c++) r[3 * i + c] = data[3 * (b + i) + c];
     }
     int rc = dense_solve(n, A, r, 3);
     memcpy(coef + 3 * b, r, sizeof(double) * 3 * n);
@@ -270,7 +304,7 @@ static int quintic_fit(const or_t *o, int64_t f, const double *data, double *coe
 /* periodic cubic spline through the nodal data d of filament f in moments
  * form: h_{k-1} M_{k-1} + 2(h_{k-1}+h_k) M_k + h_k M_{k+1}
  *     = 6[(d_{k+1}-d_k)/h_k - (d_k-d_{k-1})/h_{k-1}]  (M = d'' at the nodes) */
-static void cubic_fit(const or_t *o, int64_t f, const double *data, double *M) {
+static void cubic_fit(const or_t *o, int64_t f, const double *data, int shifted, double *M) {
     int64_t b = o->off[f], n = o->off[f + 1] - b;
     double *aa = (double *)malloc(sizeof(double) * n);
     double *bb = (double *)malloc(sizeof(double) * n);
@@ -283,10 +317,11 @@ static void cubic_fit(const or_t *o, int64_t f, const double *data, double *M) {
     }
     for (int c = 0; c < 3; c++) {
         for (int64_t k = 0; k < n; k++) {
-            int64_t j = b + k, jn = b + (k + 1) % n, jp = b + (k + n - 1) % n;
-            double hm = o->dtau[jp], hk = o->dtau[j];
-            rr[k] = 6.0 * ((data[3 * jn + c] - data[3 * j + c]) / hk -
-                           (data[3 * j + c] - data[3 * jp + c]) / hm);
+            int64_t j = b + k, jp = b + (k + n - 1) % n;
+            double hm = o->dtau[jp], hk = o->dtau[j], en[3], ep[3];
+            seg_end(o, data, j, shifted, en);     /* s_{k+1} in the frame of s_k */
+            seg_end(o, data, jp, shifted, ep);    /* s_k in the frame of s_{k-1} */
+            rr[k] = 6.0 * ((en[c] - data[3 * j + c]) / hk - (ep[c] - data[3 * jp + c]) / hm);
         }
         cyclic_tridiag(n, aa, bb, cc, rr, wk);
         for (int64_t k = 0; k < n; k++) M[3 * (b + k) + c] = rr[k];
@@ -297,15 +332,16 @@ static void cubic_fit(const or_t *o, int64_t f, const double *data, double *M) {
 /* the spline through nodal data (aux = its moments for order 4, its B-spline
  * coefficients for order 6) on segment j at tau = tau_j + t */
 static void spline_eval_data(const or_t *o, const double *data, const double *aux, int64_t j,
-                             double t, int deriv, double *out) {
+                             double t, int deriv, int shifted, double *out) {
     if (o->order == 6) {
-        bspline_eval(o, aux, j, t, deriv, out);
+        bspline_eval(o, aux, j, t, deriv, shifted, out);
         return;
     }
     int64_t jn = next_node(o, j);
-    double h = o->dtau[j];
+    double h = o->dtau[j], sn[3];
     const double *Mj = aux + 3 * j, *Mn = aux + 3 * jn;
-    const double *sj = data + 3 * j, *sn = data + 3 * jn;
+    const double *sj = data + 3 * j;
+    seg_end(o, data, j, shifted, sn);
     double u = h - t;
     for (int c = 0; c < 3; c++) {
         double A = sj[c] / h - Mj[c] * h / 6.0;
@@ -321,7 +357,7 @@ static void spline_eval_data(const or_t *o, const double *data, const double *au
 
 /* the curve: s, ds/dtau or d2s/dtau2 on segment j at tau = tau_j + t */
 static void seg_eval(const or_t *o, int64_t j, double t, int deriv, double *out) {
-    spline_eval_data(o, o->x, o->order == 6 ? o->C : o->M, j, t, deriv, out);
+    spline_eval_data(o, o->x, o->order == 6 ? o->C : o->M, j, t, deriv, 1, out);
 }
 
 void or_spline_eval(const void *h, int64_t seg, double u, int deriv, double *out) {
@@ -335,12 +371,14 @@ void or_free(void *h) {
     if (!o) return;
     free(o->off); free(o->fil); free(o->gamma); free(o->x); free(o->tau);
     free(o->dtau); free(o->M); free(o->sd); free(o->ell); free(o->C); free(o->T);
+    free(o->shift);
     free(o->qx); free(o->qs); free(o->qc);
     free(o);
 }
 
 void *or_new(int64_t nfil, const int64_t *off, const double *xyz,
-             const double *gamma, double L, double a, double delta, int Q, int order) {
+             const double *gamma, double L, double a, double delta, int Q, int order,
+             const int64_t *periods) {
     if (nfil < 1 || Q < 1 || Q > 4 || (order != 4 && order != 6)) return NULL;
     for (int64_t f = 0; f < nfil; f++)
         if (off[f + 1] - off[f] < (order == 6 ? 6 : 3)) return NULL;
@@ -360,6 +398,9 @@ void *or_new(int64_t nfil, const int64_t *off, const double *xyz,
     o->M = (double *)malloc(sizeof(double) * 3 * N);
     o->C = (double *)calloc((size_t)(3 * N), sizeof(double));
     o->T = (double *)malloc(sizeof(double) * nfil);
+    o->shift = (double *)calloc((size_t)(3 * nfil), sizeof(double));
+    if (periods)
+        for (int64_t k = 0; k < 3 * nfil; k++) o->shift[k] = (double)periods[k] * L;
     o->sd = (double *)malloc(sizeof(double) * 3 * N);
     o->ell = (double *)malloc(sizeof(double) * N);
     o->qx = (double *)malloc(sizeof(double) * 3 * o->Nq);
@@ -377,8 +418,9 @@ void *or_new(int64_t nfil, const int64_t *off, const double *xyz,
         o->tau[b] = 0.0;
         for (int64_t k = 0; k < n; k++) {
             int64_t j = b + k, jn = b + (k + 1) % n;
-            double d[3] = {o->x[3 * jn] - o->x[3 * j], o->x[3 * jn + 1] - o->x[3 * j + 1],
-                           o->x[3 * jn + 2] - o->x[3 * j + 2]};
+            double e[3];
+            seg_end(o, o->x, j, 1, e);
+            double d[3] = {e[0] - o->x[3 * j], e[1] - o->x[3 * j + 1], e[2] - o->x[3 * j + 2]};
             o->dtau[j] = norm3(d);
             if (!(o->dtau[j] > 0.0)) bad = 1;
             if (k + 1 < n) o->tau[jn] = o->tau[j] + o->dtau[j];
@@ -386,10 +428,11 @@ void *or_new(int64_t nfil, const int64_t *off, const double *xyz,
         o->T[f] = o->tau[b + n - 1] + o->dtau[b + n - 1];
         if (bad) continue;
         if (order == 6) {
-            if (quintic_fit(o, f, o->x, o->C)) bad = 1;
-            for (int64_t k = 0; k < n; k++) bspline_eval(o, o->C, b + k, 0.0, 2, o->M + 3 * (b + k));
+            if (quintic_fit(o, f, o->x, 1, o->C)) bad = 1;
+            for (int64_t k = 0; k < n; k++)
+                bspline_eval(o, o->C, b + k, 0.0, 2, 1, o->M + 3 * (b + k));
         } else {
-            cubic_fit(o, f, o->x, o->M);
+            cubic_fit(o, f, o->x, 1, o->M);
         }
     }
     if (bad) { or_free(o); return NULL; }
@@ -497,7 +540,8 @@ void or_local_sub(const void *h, double eps, int64_t nt, const int64_t *tgt, dou
          * segment i at t = u hp, on segment jm at t = (1 - u) hm */
         for (int side = 0; side < 2; side++) {
             int64_t j = side ? i : jm;
-            double hs = side ? hp : hm;
+            double hs = side ? hp : hm, E[3];
+            adj_offset(o, i, j, E);
             for (double u0 = eps; u0 < 1.0; u0 *= 2.0) {
                 double u1 = fmin(2.0 * u0, 1.0);
                 for (int k = 0; k < 3; k++) {
@@ -505,7 +549,7 @@ void or_local_sub(const void *h, double eps, int64_t nt, const int64_t *tgt, dou
                     double t = side ? u * hs : (1.0 - u) * hs;
                     seg_eval(o, j, t, 0, x);
                     seg_eval(o, j, t, 1, sdq);
-                    for (int c = 0; c < 3; c++) r[c] = x[c] - si[c];
+                    for (int c = 0; c < 3; c++) r[c] = x[c] + E[c] - si[c];
                     double rn = norm3(r), wq = gam * g3w[k] * (u1 - u0) * hs / (4 * OR_PI);
                     cross3(r, sdq, rx);
                     for (int c = 0; c < 3; c++) {
@@ -560,7 +604,8 @@ void or_shortrange(const void *h, double alpha, double rc, int64_t nt,
         for (int64_t q = 0; q < o->Nq; q++) {
             int64_t seg = q / o->Q;
             int adj = (seg == i || seg == ip);
-            double gam_dummy = 0; (void)gam_dummy;
+            double E[3] = {0, 0, 0};   /* image holding the local copy of an adjacent segment */
+            if (adj) adj_offset(o, i, seg, E);
             double d0[3], sh[3];
             for (int c = 0; c < 3; c++) {
                 d0[c] = o->qx[3 * q + c] - xi[c];
@@ -571,9 +616,9 @@ void or_shortrange(const void *h, double alpha, double rc, int64_t nt,
             for (int nz = -nm; nz <= nm; nz++) {
                 double r[3] = {d0[0] + sh[0] + nx * L, d0[1] + sh[1] + ny * L,
                                d0[2] + sh[2] + nz * L};
-                int unshifted = (fabs(sh[0] + nx * L) < 0.5 * L &&
-                                 fabs(sh[1] + ny * L) < 0.5 * L &&
-                                 fabs(sh[2] + nz * L) < 0.5 * L);
+                int unshifted = (fabs(sh[0] + nx * L - E[0]) < 0.5 * L &&
+                                 fabs(sh[1] + ny * L - E[1]) < 0.5 * L &&
+                                 fabs(sh[2] + nz * L - E[2]) < 0.5 * L);
                 if (adj && unshifted) continue;
                 double r2 = dot3(r, r);
                 if (r2 >= rc * rc || r2 == 0.0) continue;
@@ -610,8 +655,9 @@ void or_selfcorr(const void *h, double alpha, int64_t nt, const int64_t *tgt,
         for (int s = 0; s < 2; s++)
             for (int k = 0; k < o->Q; k++) {
                 int64_t q = segs[s] * o->Q + k;
-                double r[3], cr[3];
-                for (int c = 0; c < 3; c++) r[c] = o->qx[3 * q + c] - xi[c];
+                double r[3], cr[3], E[3];
+                adj_offset(o, i, segs[s], E);
+                for (int c = 0; c < 3; c++) r[c] = o->qx[3 * q + c] + E[c] - xi[c];
                 double rr = norm3(r);
                 const double *qc = o->qc + 3 * q;
                 cross3(r, qc, cr);
@@ -801,13 +847,13 @@ double or_energy(const void *h, const double *psi) {
     double V = o->L * o->L * o->L, e = 0.0;
     double *aux = (double *)calloc((size_t)(3 * o->N), sizeof(double));
     for (int64_t f = 0; f < o->nfil; f++) {
-        if (o->order == 6) quintic_fit(o, f, psi, aux);
-        else cubic_fit(o, f, psi, aux);
+        if (o->order == 6) quintic_fit(o, f, psi, 0, aux);
+        else cubic_fit(o, f, psi, 0, aux);
     }
     for (int64_t j = 0; j < o->N; j++)
         for (int i = 0; i < o->Q; i++) {
             double pv[3];
-            spline_eval_data(o, psi, aux, j, o->gl_h[i] * o->dtau[j], 0, pv);
+            spline_eval_data(o, psi, aux, j, o->gl_h[i] * o->dtau[j], 0, 0, pv);
             e += dot3(pv, o->qc + 3 * (j * o->Q + i));
         }
     free(aux);
@@ -993,8 +1039,9 @@ void or_chord_integral(const double *A, const double *B, const double *x,
 /* Distance from x to the chord of segment seg and the image shift of x that
  * realises it (minimum image of the chord midpoint). */
 static double chord_distance(const or_t *o, int64_t seg, const double *x, double *shift) {
-    int64_t jn = next_node(o, seg);
-    const double *A = o->x + 3 * seg, *B = o->x + 3 * jn;
+    const double *A = o->x + 3 * seg;
+    double B[3];
+    seg_end(o, o->x, seg, 1, B);
     double m[3], e[3], r[3];
     for (int k = 0; k < 3; k++) {
         m[k] = 0.5 * (A[k] + B[k]);

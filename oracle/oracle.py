@@ -46,7 +46,7 @@ def lib():
         L = C.CDLL(_SO)
         L.or_new.restype = C.c_void_p
         L.or_new.argtypes = [C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int,
-                             C.c_int]
+                             C.c_int, C.c_void_p]
         L.or_free.argtypes = [C.c_void_p]
         L.or_nquad.restype = C.c_int64
         L.or_nquad.argtypes = [C.c_void_p]
@@ -149,8 +149,10 @@ class Oracle:
         off = np.ascontiguousarray(fs.offsets, dtype=np.int64)
         xyz = np.ascontiguousarray(fs.xyz, dtype=np.float64)
         gam = np.ascontiguousarray(fs.gamma, dtype=np.float64)
+        per = getattr(fs, "periods", None)
+        self._per = None if per is None else np.ascontiguousarray(per, dtype=np.int64)
         self._h = lib().or_new(fs.n_fil, off, xyz, gam, fs.L, fs.a, fs.delta, Q,
-                               order)
+                               order, _ptr(self._per))
         if not self._h:
             raise ValueError("invalid filament set (N_l < 3, or < 6 for quintic, or "
                              "zero-length segment)")

@@ -55,6 +55,9 @@ class FilamentSet:
     grid_n: int
     tol: float
     delta: float = 0.25
+    # per filament, the lattice vector n of s(tau + T) = s(tau) + n L
+    # (Sec. 2.1); None: every filament is closed
+    periods: np.ndarray | None = None
 
     @property
     def n_nodes(self) -> int:
@@ -261,6 +264,37 @@ def perf_params(N: int, beta: float, C_beta: float, L: float = TWO_PI, sigma: fl
     if p2 <= 1.15 * n:
         n = p2
     return dict(alpha=alpha, rcut=beta / alpha, grid_n=n, beta=beta, w=w, sigma=sigma)
+
+
+def six_lines(n_per: int = 128, L: float = TWO_PI, a: float = 1e-8, grid_n: int = 64,
+              tol: float = 1e-6, signs=(1, 1, 1)) -> FilamentSet:
+    """The infinite-lines case of Sec. 5.1: straight lines through the box,
+    a pair along each Cartesian axis with opposite orientations (zero net
+    vorticity), n_per nodes each.  The lines along z pass through
+    (x, y) = (1/8, 3/8) L and (5/8, 7/8) L, those along x through
+    (y, z) = the same, those along y through (z, x) = the same, so that no
+    two lines meet (the closest pairs are L/4 apart); signs[a] orients the
+    first line of the pair along axis a (+1: along +axis)."""
+    u = L * np.arange(n_per) / n_per
+    parts, periods, gam = [], [], []
+    for ax in range(3):                       # 0: x-lines, 1: y-lines, 2: z-lines
+        t1, t2 = (ax + 1) % 3, (ax + 2) % 3    # transverse axes (cyclic)
+        for k, (c1, c2) in enumerate(((0.125, 0.375), (0.625, 0.875))):
+            sgn = signs[ax] * (1 if k == 0 else -1)
+            p = np.zeros((n_per, 3))
+            p[:, ax] = u if sgn > 0 else L - u
+            p[:, t1] = c1 * L
+            p[:, t2] = c2 * L
+            parts.append(p)
+            per = [0, 0, 0]
+            per[ax] = sgn
+            periods.append(per)
+            gam.append(1.0)
+    return FilamentSet("six_lines", L, a, _csr([n_per] * 6), np.concatenate(parts),
+                       np.array(gam), grid_n, tol, periods=np.array(periods, dtype=np.int64))
+
+
+WORKLOADS["six_lines"] = six_lines
 
 
 def make(name: str, **kw) -> FilamentSet:

@@ -204,6 +204,103 @@ def test_total_is_independent_of_alpha():
         assert rel_l2(p, ps[0]) < 1e-12
 
 
+def _lattice_velocity_of_straight_lines(fs, M=12):
+    """Velocity on infinite straight lines from 2-D periodic point-vortex
+    sums: a line along axis a is a point vortex in the plane of the two
+    other axes (t1, t2) = (a + 1, a + 2) mod 3; the vortices of one row
+    (period L along t1) sum in closed form,
+      u_t1 = -G/(2L) sinh(2 pi Y/L) / (cosh(2 pi Y/L) - cos(2 pi X/L)),
+      u_t2 =  G/(2L) sin(2 pi X/L)  / (cosh(2 pi Y/L) - cos(2 pi X/L)),
+    rows m L apart are summed symmetrically (a pair of opposite lines
+    converges), the line's own row is zero on the line, and the mean of the
+    row sums over the cell, -G1 (Y2 - Y1)/L^2 along t1 for the pair, is
+    removed (the periodic solution with the k = 0 mode dropped has zero mean
+    velocity)."""
+    L, off = fs.L, fs.offsets
+    lines = []
+    for l in range(fs.n_fil):
+        n = fs.periods[l]
+        ax = int(np.nonzero(n)[0][0])
+        t1, t2 = (ax + 1) % 3, (ax + 2) % 3
+        p0 = fs.xyz[off[l]]
+        lines.append((ax, t1, t2, int(n[ax]) * fs.gamma[l], p0[t1], p0[t2]))
+    v = np.zeros((fs.n_nodes, 3))
+    for l2 in range(fs.n_fil):
+        for i in range(off[l2], off[l2 + 1]):
+            p = fs.xyz[i]
+            for l, (ax, t1, t2, G, c1, c2) in enumerate(lines):
+                X = p[t1] - c1
+                for m in range(-M, M + 1):
+                    if l == l2 and m == 0:
+                        continue
+                    Y = p[t2] - c2 - m * L
+                    den = math.cosh(2 * math.pi * Y / L) - math.cos(2 * math.pi * X / L)
+                    v[i, t1] += -G / (2 * L) * math.sinh(2 * math.pi * Y / L) / den
+                    v[i, t2] += G / (2 * L) * math.sin(2 * math.pi * X / L) / den
+    for ax in range(3):
+        (G1, Y1), (G2, Y2) = [(G, c2) for (a, _, _, G, _, c2) in lines if a == ax]
+        assert abs(G1 + G2) < 1e-12
+        v[:, (ax + 1) % 3] += G1 * (Y2 - Y1) / L ** 2
+    return v
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_infinite_straight_lines_match_2d_lattice_sums(order):
+    """Sec. 2.1 and the infinite-lines case of Sec. 5.1: unclosed filaments
+    with s(tau + T) = s(tau) + n L.  Straight lines make the 3-D periodic
+    problem a 2-D one per direction, summed independently in closed form;
+    the oracle (spline, quadrature, Ewald split with the closing segment of
+    each line shifted by n L) agrees to rounding, and every line moves
+    along itself (v . s' > 0, as the paper arranges the orientations)."""
+    fs = W.six_lines(n_per=128)
+    o = O.Oracle(fs, Q=4, order=order)
+    v, _ = o.reference(psi=False)
+    ref = _lattice_velocity_of_straight_lines(fs)
+    # rounding of the spline solves (the dense quintic one: ~1e-10)
+    assert np.abs(v - ref).max() < 2e-10 * np.abs(ref).max()
+    sd = o.nodes()["sdot"]
+    assert ((v * sd).sum(1) > 0.1).all()
+
+
+def _helices(n_per=48, amp=0.4):
+    """Two wavy infinite lines along +z and -z (periods +-e_z)."""
+    L = 2 * math.pi
+    tau = L * np.arange(n_per) / n_per
+    parts = []
+    for k, (cx, cy, sgn) in enumerate(((L / 4, L / 3, 1), (3 * L / 4, 2 * L / 3, -1))):
+        z = tau if sgn > 0 else L - tau
+        parts.append(np.stack([cx + amp * np.cos(2 * z + k), cy + amp * np.sin(3 * z), z], 1))
+    return W.FilamentSet("helices", L, 1e-6, np.array([0, n_per, 2 * n_per]),
+                         np.concatenate(parts), np.array([1.0, 1.0]), 32, 1e-6,
+                         periods=np.array([[0, 0, 1], [0, 0, -1]]))
+
+
+@pytest.mark.parametrize("order,eps", [(4, None), (6, 0.1)])
+def test_infinite_curves_total_is_independent_of_alpha(order, eps):
+    """Sec. 3.1 on curved unclosed filaments: the short-range exclusion of
+    the local segments, the self correction and the subdivided local term
+    must all take the closing segment in the node's own frame, otherwise
+    the sum depends on alpha."""
+    fs = _helices()
+    o = O.Oracle(fs, Q=3, order=order)
+    L = fs.L
+    vs, ps = [], []
+    for beta, rc in [(6.5, L), (6.5, L / 2), (7.0, 1.9)]:
+        prm = O.reference_params(L, beta, rc)
+        v, p = o.ewald(prm["alpha"], prm["rc"], prm["K"], local_eps=eps)
+        vs.append(v); ps.append(p)
+    for v, p in zip(vs[1:], ps[1:]):
+        assert rel_l2(v, vs[0]) < 1e-11
+        assert rel_l2(p, ps[0]) < 1e-11
+    # the closing segments matter: treating the lines as closed curves
+    # (no shift) gives a different, wrong answer
+    closed = W.FilamentSet(fs.name, L, fs.a, fs.offsets, fs.xyz, fs.gamma, 32, 1e-6)
+    prm = O.reference_params(L, 6.5, L)
+    vc, _ = O.Oracle(closed, Q=3, order=order).ewald(prm["alpha"], prm["rc"], prm["K"],
+                                                        local_eps=eps)
+    assert rel_l2(vc, vs[0]) > 1e-2
+
+
 def test_brute_force_image_sum_equals_ewald_plus_uniform_dipole_term():
     """Unsplit discrete sum over cubic shells of images |n|_inf <= K,
     Richardson-extrapolated in 1/K^2, minus the Ewald result must be the same
