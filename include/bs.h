@@ -151,7 +151,8 @@ int bs_resolve_params(const bs_params *p, bs_params *out);
 int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out);
 
 /* Load a filament set.
- *   nfil     number of closed filaments (>= 1);
+ *   nfil     number of filaments (>= 1; closed unless bs_set_periods
+ *            says otherwise);
  *   offsets  HOST int64 [nfil+1], offsets[0] = 0, filament l owns nodes
  *            offsets[l] .. offsets[l+1]-1, each filament has >= 3 nodes;
  *   xyz      DEVICE float64 [N][3], N = offsets[nfil], unwrapped positions
@@ -165,6 +166,26 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out);
  * bs_status() (outputs computed from such input are meaningless). */
 int bs_set_filaments(bs_plan_t plan, int64_t nfil, const int64_t *offsets,
                      const double *xyz, const double *gamma);
+
+/* Infinite periodic filaments (Sec. 2.1: a curve that is not closed in the
+ * cell but repeats with the domain, s(tau + T) = s(tau) + n L with n an
+ * integer vector).
+ *   nfil     number of filaments of the sets loaded afterwards;
+ *   periods  HOST int64 [nfil][3]: n for each filament, (0,0,0) for a closed
+ *            one; |n_i| <= 2^20.  NULL: every filament closed (the default).
+ * For filament l with n != 0 the node after its last node is its first node
+ * shifted by n L: the last segment, the spline (whose derivatives stay
+ * periodic) and the local terms use that shifted node.  Positions are
+ * otherwise as in bs_set_filaments (one period of nodes, unwrapped).  The
+ * long-range sum omits k = 0 (eq:velocity_longrange_physical needs zero
+ * mean vorticity): with sum_l Gamma_l n_l != 0 the result is that of the
+ * filaments in a uniform background of the opposite mean vorticity.
+ * The setting stays until changed; it drops the loaded filaments (and a
+ * recorded bs_step graph), so bs_set_filaments must follow, with the same
+ * nfil (BS_EINVAL otherwise).  Errors: BS_EINVAL (nfil < 1, |n_i| too
+ * large), BS_ENOMEM; after an error every filament counts as closed.
+ * Synchronises the plan stream. */
+int bs_set_periods(bs_plan_t plan, int64_t nfil, const int64_t *periods);
 
 /* Velocity at every node: v_out DEVICE float64 [N][3] (overwritten).
  * v = v_local + v_short + v_long - v_self, plus, when ns_mode is not

@@ -25,7 +25,7 @@ BS_FFT_AUTO, BS_FFT_LIBRARY, BS_FFT_PRUNED = 0, 1, 2
 _CODES = {0: "BS_OK", -1: "BS_EINVAL", -2: "BS_EMINIMG", -3: "BS_ETOL", -4: "BS_EKB",
           -5: "BS_ENOMEM", -6: "BS_EDEVICE", -7: "BS_ESTATE"}
 
-EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_velocity",
+EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_set_periods", "bs_velocity",
             "bs_velocity_terms", "bs_energy", "bs_vorticity_modes", "bs_geometry",
             "bs_status", "bs_set_profiling", "bs_stage_times", "bs_get_params",
             "bs_destroy", "bs_last_error", "bs_mlp_nparams", "bs_mlp_create",
@@ -74,6 +74,7 @@ _vp = C.c_void_p
 _lib.bs_resolve_params.argtypes = [C.POINTER(BsParams), C.POINTER(BsParams)]
 _lib.bs_plan.argtypes = [C.POINTER(BsParams), _vp, C.POINTER(_vp)]
 _lib.bs_set_filaments.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int64), _vp, _vp]
+_lib.bs_set_periods.argtypes = [_vp, C.c_int64, _vp]
 _lib.bs_velocity.argtypes = [_vp, _vp]
 _lib.bs_velocity_terms.argtypes = [_vp] + [_vp] * 5
 _lib.bs_energy.argtypes = [_vp, C.POINTER(C.c_double), _vp]
@@ -189,6 +190,16 @@ class Plan:
                                      _ptr(xyz), _ptr(gamma)), self._h)
         self.N = int(off[-1])
         self.nfil = len(off) - 1
+
+    def set_periods(self, periods):
+        """Period vectors n [nfil][3] of infinite filaments (None: all closed)."""
+        if periods is None:
+            _check(_lib.bs_set_periods(self._h, 0, None), self._h)
+            return
+        per = np.ascontiguousarray(periods, dtype=np.int64)
+        assert per.ndim == 2 and per.shape[1] == 3
+        self._periods = per
+        _check(_lib.bs_set_periods(self._h, len(per), per.ctypes.data_as(_vp)), self._h)
 
     def _out(self, out):
         if out is None:

@@ -363,6 +363,34 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
     return BS_OK;
 }
 
+static void drop_graph(bs_plan_t P);
+
+int bs_set_periods(bs_plan_t P, int64_t nfil, const int64_t *periods) {
+    if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
+    drop_graph(P);
+    P->have_filaments = false;
+    P->nper = 0;
+    if (!periods) return BS_OK;
+    if (nfil < 1) return set_error(P, BS_EINVAL, "need nfil >= 1");
+    std::vector<double> sh(3 * nfil);
+    bool any = false;
+    for (int64_t k = 0; k < 3 * nfil; k++) {
+        if (periods[k] < -(1 << 20) || periods[k] > (1 << 20))
+            return set_error(P, BS_EINVAL, "period counts must lie in [-2^20, 2^20]");
+        sh[k] = (double)periods[k] * P->prm.L;
+        any = any || periods[k] != 0;
+    }
+    if (!any) return BS_OK;   // all closed
+    int rc;
+    if ((rc = ensure<double>(P, P->d_shift, 3 * nfil)) ||
+        (rc = check_hip(P, hipMemcpyAsync(P->d_shift.p, sh.data(), sizeof(double) * 3 * nfil,
+                                          hipMemcpyHostToDevice, P->stream), "copy shifts")) ||
+        (rc = check_hip(P, hipStreamSynchronize(P->stream), "sync")))
+        return rc;
+    P->nper = nfil;
+    return BS_OK;
+}
+
 int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const double *xyz,
                      const double *gamma) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
@@ -379,6 +407,9 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     }
     const int64_t N = offsets[nfil], Nq = N * P->Q;
     if (Nq >= ((int64_t)1 << 31) / 4) return set_error(P, BS_EINVAL, "too many nodes");
+    if (P->nper && P->nper != nfil)
+        return set_error(P, BS_EINVAL, "periods were set for " + std::to_string(P->nper) +
+                                           " filaments, not " + std::to_string(nfil));
     bool same = P->have_filaments && P->nfil == nfil &&
                 std::equal(offsets, offsets + nfil + 1, P->off_host.begin());
     int rc;
@@ -388,6 +419,7 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
         P->have_filaments = false;
         if ((rc = ensure<int>(P, P->d_off, nfil + 1)) || (rc = ensure<int>(P, P->d_fil, N)) ||
             (rc = ensure<double>(P, P->d_gamma, nfil)) || (rc = ensure<double>(P, P->d_x, 3 * N)) ||
+            (rc = ensure<double>(P, P->d_xn, 3 * N)) ||
             (rc = ensure<double>(P, P->d_dtau, N)) || (rc = ensure<double>(P, P->d_D, 3 * N)) ||
             (rc = ensure<double>(P, P->d_sdd, 3 * N)) || (rc = ensure<double>(P, P->d_ell, N)) ||
             (rc = ensure<double>(P, P->d_qpos, 3 * Nq)) ||
@@ -762,7 +794,7 @@ int bs_destroy(bs_plan_t P) {
     if (P->fft_fwd) hipfftDestroy(P->fft_fwd);
     if (P->fft_inv) hipfftDestroy(P->fft_inv);
     DBuf *all[] = {&P->grid, &P->spec, &P->deconv, &P->fftwork, &P->fft_tw, &P->fft_A, &P->fft_B, &P->d_off, &P->d_fil,
-                   &P->d_gamma, &P->d_x, &P->d_dtau, &P->d_D, &P->d_sdd, &P->d_ell,
+                   &P->d_gamma, &P->d_x, &P->d_xn, &P->d_shift, &P->d_dtau, &P->d_D, &P->d_sdd, &P->d_ell,
                    &P->d_qpos, &P->d_qchg, &P->d_status, &P->sp_key, &P->sp_cnt, &P->sp_start,
                    &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,

@@ -128,12 +128,15 @@ template <int ORDER>
 struct SegPoly {
     double c[ORDER][3];
 
+    // s0 = x[j], s1 = xe[je] (the end node in the segment's own frame);
+    // D, S at nodes j and jn
     __device__ __forceinline__ void load(const double *__restrict__ x,
+                                         const double *__restrict__ xe, int je,
                                          const double *__restrict__ D,
                                          const double *__restrict__ S, int j, int jn, double h) {
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            const double s0 = x[3 * j + q], s1 = x[3 * jn + q];
+            const double s0 = x[3 * j + q], s1 = xe[3 * je + q];
             const double d0 = h * D[3 * j + q], d1 = h * D[3 * jn + q];
             c[0][q] = s0;
             c[1][q] = d0;

@@ -71,6 +71,12 @@ struct bs_plan_s {
     bool have_filaments = false;
     bs::DBuf d_off, d_fil, d_gamma;            // int32 [nfil+1], int32 [N], f64 [nfil]
     bs::DBuf d_x;                              // f64 [N][3] private copy of nodes
+    bs::DBuf d_xn;                             // f64 [N][3] end node of segment j in
+                                               // j's frame (next node, plus the
+                                               // filament's period shift after the
+                                               // last node of an infinite filament)
+    bs::DBuf d_shift;                          // f64 [nfil][3] period shifts n_l L
+    int64_t nper = 0;                          // filaments the shifts were set for
     bs::DBuf d_dtau, d_D, d_sdd, d_ell;        // node geometry
     bs::DBuf d_qpos, d_qchg;                   // f64 [Nq][3]
     bs::DBuf d_status;                         // int32 device status word
@@ -127,8 +133,8 @@ int check_hip(bs_plan_t p, hipError_t e, const char *what);
 // chord lengths, spline, quadrature points, charges, segment lengths and the
 // velocity's local-minus-self term (d_vls), one workgroup per filament
 void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma);
-// spline through nodal data on the plan's knots: slopes (and, quintic,
-// second derivatives) into Dout, Sout
+// spline through periodic nodal data (such as the streamfunction) on the
+// plan's knots: slopes (and, quintic, second derivatives) into Dout, Sout
 void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout);
 // mode bits for launch_local_self
 enum { LS_VLOCAL = 1, LS_VSELF = 2, LS_PSI = 4, LS_ASSIGN = 8 };

@@ -39,21 +39,34 @@ __device__ __forceinline__ int prev_node(const int *off, const int *fil, int j) 
 // ------------------------------------------------------------- chord lengths
 // Chord lengths of filament f from the caller's node positions, which are
 // copied into the plan's own array on the way (xs may alias xd); also the
-// plan's copy of the filament's circulation.  Non-finite positions and
-// zero-length segments set bit 0 of the status word (their chord is taken
-// as 1 so that the rest stays finite).
+// plan's copy of the filament's circulation and the end node of every
+// segment in the segment's own frame (xn).  An infinite filament
+// (s(tau + T) = s(tau) + n L, Sec. 2.1) has its period shift n L in shift;
+// its last segment ends at the first node plus that shift.  shift NULL: all
+// filaments closed.  Non-finite positions and zero-length segments set bit 0
+// of the status word (their chord is taken as 1 so that the rest stays
+// finite).
 __device__ void chord_fil(int f, int b0, int n, const double *xs, double *xd,
+                          double *__restrict__ xn, const double *__restrict__ shift,
                           const double *__restrict__ gs, double *__restrict__ gd,
                           double *__restrict__ dtau, int *__restrict__ status) {
     if (threadIdx.x == 0) gd[f] = gs[f];
+    double sh[3] = {0.0, 0.0, 0.0};
+    if (shift)
+        for (int q = 0; q < 3; q++) sh[q] = shift[3 * f + q];
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const int j = b0 + k, jn = b0 + (k + 1 == n ? 0 : k + 1);
+        const bool last = k + 1 == n;
+        const int j = b0 + k, jn = last ? b0 : j + 1;
         const double x0 = xs[3 * j], x1 = xs[3 * j + 1], x2 = xs[3 * j + 2];
-        const double dx = xs[3 * jn] - x0, dy = xs[3 * jn + 1] - x1, dz = xs[3 * jn + 2] - x2;
+        const double e0 = last ? xs[3 * jn] + sh[0] : xs[3 * jn];
+        const double e1 = last ? xs[3 * jn + 1] + sh[1] : xs[3 * jn + 1];
+        const double e2 = last ? xs[3 * jn + 2] + sh[2] : xs[3 * jn + 2];
+        const double dx = e0 - x0, dy = e1 - x1, dz = e2 - x2;
         const double h = sqrt(dx * dx + dy * dy + dz * dz);
         const bool ok = isfinite(x0) && isfinite(x1) && isfinite(x2) && isfinite(h) && h > 0.0;
         if (!ok) atomicOr(status, 1);
         dtau[j] = ok ? h : 1.0;
+        xn[3 * j] = e0; xn[3 * j + 1] = e1; xn[3 * j + 2] = e2;
         xd[3 * j] = x0; xd[3 * j + 1] = x1; xd[3 * j + 2] = x2;
     }
 }
@@ -92,8 +105,11 @@ __device__ void pcr_solve(int n, PcrArrays A, PcrArrays B) {
 }
 
 // slopes D of the cubic spline through the nodal data x of one filament
-// (nodes b0 .. b0+n-1); the whole workgroup takes part
+// (nodes b0 .. b0+n-1); xn: end node of each segment in its own frame, for
+// positions (NULL for periodic data such as the streamfunction); the whole
+// workgroup takes part
 __device__ void spline_cubic_fil(int b0, int n, const double *__restrict__ x,
+                                 const double *__restrict__ xn,
                                  const double *__restrict__ dtau, double *__restrict__ D,
                                  double *__restrict__ gscratch) {
     __shared__ double lds[2 * 6 * kPcrLds];
@@ -111,8 +127,10 @@ __device__ void spline_cubic_fil(int b0, int n, const double *__restrict__ x,
         A.c[k] = hm;
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            double sm = x[3 * (b0 + km) + q], s0 = x[3 * (b0 + k) + q], sp = x[3 * (b0 + kp) + q];
-            A.r[3 * k + q] = 3.0 * (hk * (s0 - sm) / hm + hm * (sp - s0) / hk);
+            const double s0 = x[3 * (b0 + k) + q], sm = x[3 * (b0 + km) + q];
+            const double dm = (xn ? xn[3 * (b0 + km) + q] : s0) - sm;
+            const double dp = (xn ? xn[3 * (b0 + k) + q] : x[3 * (b0 + kp) + q]) - s0;
+            A.r[3 * k + q] = 3.0 * (hk * dm / hm + hm * dp / hk);
         }
     }
     __syncthreads();
@@ -125,11 +143,11 @@ __device__ void spline_cubic_fil(int b0, int n, const double *__restrict__ x,
 }
 
 __global__ void k_spline(int nfil, const int *__restrict__ off, const double *__restrict__ x,
-                         const double *__restrict__ dtau, double *__restrict__ D,
-                         double *__restrict__ gscratch) {
+                         const double *__restrict__ xn, const double *__restrict__ dtau,
+                         double *__restrict__ D, double *__restrict__ gscratch) {
     const int f = blockIdx.x;
     if (f >= nfil) return;
-    spline_cubic_fil(off[f], off[f + 1] - off[f], x, dtau, D, gscratch);
+    spline_cubic_fil(off[f], off[f + 1] - off[f], x, xn, dtau, D, gscratch);
 }
 
 // ------------------------------------------------ quintic spline (block PCR)
@@ -180,6 +198,7 @@ __device__ __forceinline__ void sub_mulR(const double *K, const double *V, doubl
 // slopes D and second derivatives S of the quintic spline through the nodal
 // data x of one filament; the whole workgroup takes part
 __device__ void spline_quintic_fil(int b0, int n, const double *__restrict__ x,
+                                   const double *__restrict__ xn,
                                    const double *__restrict__ dtau, double *__restrict__ D,
                                    double *__restrict__ S, double *__restrict__ gscratch) {
     __shared__ Blk lds[2 * kPcr5Lds];
@@ -205,9 +224,9 @@ __device__ void spline_quintic_fil(int b0, int n, const double *__restrict__ x,
         e.U[2] = 14.0 * ip3;  e.U[3] = -2.0 * ip2;
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            const double sm = x[3 * (b0 + km) + q], s0 = x[3 * (b0 + k) + q],
-                         sp = x[3 * (b0 + kp) + q];
-            const double dm = s0 - sm, dp = sp - s0;
+            const double s0 = x[3 * (b0 + k) + q], sm = x[3 * (b0 + km) + q];
+            const double dm = (xn ? xn[3 * (b0 + km) + q] : s0) - sm;
+            const double dp = (xn ? xn[3 * (b0 + k) + q] : x[3 * (b0 + kp) + q]) - s0;
             e.R[q] = 20.0 * (dp * ip3 - dm * im3);
             e.R[3 + q] = 30.0 * (dm * im3 * im1 + dp * ip3 * ip1);
         }
@@ -268,11 +287,12 @@ __device__ void spline_quintic_fil(int b0, int n, const double *__restrict__ x,
 }
 
 __global__ void k_spline5(int nfil, const int *__restrict__ off, const double *__restrict__ x,
-                          const double *__restrict__ dtau, double *__restrict__ D,
-                          double *__restrict__ S, double *__restrict__ gscratch) {
+                          const double *__restrict__ xn, const double *__restrict__ dtau,
+                          double *__restrict__ D, double *__restrict__ S,
+                          double *__restrict__ gscratch) {
     const int f = blockIdx.x;
     if (f >= nfil) return;
-    spline_quintic_fil(off[f], off[f + 1] - off[f], x, dtau, D, S, gscratch);
+    spline_quintic_fil(off[f], off[f + 1] - off[f], x, xn, dtau, D, S, gscratch);
 }
 
 // --------------------------------------------------------- segment geometry
@@ -288,13 +308,14 @@ struct GLArgs {
 template <int ORDER>
 __device__ __forceinline__ void geometry_seg(int j, int jn, double g, int Q, const GLArgs &gl,
                                              const double *__restrict__ x,
+                                             const double *__restrict__ xn,
                                              const double *__restrict__ dtau,
                                              const double *__restrict__ D,
                                              double *__restrict__ qpos, double *__restrict__ qchg,
                                              double *__restrict__ sdd, double *__restrict__ ell) {
     const double h = dtau[j];
     SegPoly<ORDER> sp;
-    sp.load(x, D, sdd, j, jn, h);
+    sp.load(x, xn, j, D, sdd, j, jn, h);
     if constexpr (ORDER == 4) {
 #pragma unroll
         for (int q = 0; q < 3; q++) sdd[3 * j + q] = 2.0 * sp.c[2][q] / (h * h);
@@ -361,10 +382,14 @@ struct LocalArgs {
     double sign, a, delta, alpha, eps;
 };
 
-// node i with neighbours ip (previous) and in (next) on its filament
+// node i with neighbours ip (previous) and in (next) on its filament.
+// Segment ip lies in the frame of node ip, where node i sits at xn[ip]
+// (x[i] plus the period shift when i is the first node of an infinite
+// filament); segment i lies in the frame of node i.
 template <int ORDER>
 __device__ void local_self_node(int i, int ip, int in, double g, const LocalArgs &la,
-                                const double *__restrict__ x, const double *__restrict__ dtau,
+                                const double *__restrict__ x, const double *__restrict__ xn,
+                                const double *__restrict__ dtau,
                                 const double *__restrict__ D, const double *__restrict__ sdd,
                                 const double *__restrict__ ell, const double *__restrict__ qpos,
                                 const double *__restrict__ qchg, double *__restrict__ out) {
@@ -380,8 +405,8 @@ __device__ void local_self_node(int i, int ip, int in, double g, const LocalArgs
         const bool sub = eps < 1.0;
         SegPoly<ORDER> seg[2];
         if (sub) {
-            seg[0].load(x, D, sdd, ip, i, dtau[ip]);
-            seg[1].load(x, D, sdd, i, in, dtau[i]);
+            seg[0].load(x, xn, ip, D, sdd, ip, i, dtau[ip]);
+            seg[1].load(x, xn, i, D, sdd, i, in, dtau[i]);
             lm = lp = 0.0;
             for (int k = 0; k < 3; k++) {
                 double dv[3];
@@ -404,8 +429,8 @@ __device__ void local_self_node(int i, int ip, int in, double g, const LocalArgs
         }
         if (sub) {
             // the rest of each local segment, distance u from the node in [eps, 1]
-            const double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
             for (int side = 0; side < 2; side++) {
+                const double *xi = side ? x + 3 * i : xn + 3 * ip;
                 for (double u0 = eps; u0 < 1.0; u0 *= 2.0) {
                     const double u1 = fmin(2.0 * u0, 1.0);
                     for (int k = 0; k < 3; k++) {
@@ -436,9 +461,10 @@ __device__ void local_self_node(int i, int ip, int in, double g, const LocalArgs
 #pragma unroll
         for (int s = 0; s < 2; s++)
             for (int k = 0; k < Q; k++) {
-                int qi = (s == 0 ? ip : i) * Q + k;
+                const int qi = (s == 0 ? ip : i) * Q + k;
+                const double *xi = s == 0 ? xn + 3 * ip : x + 3 * i;
                 double r[3], c[3];
-                for (int q = 0; q < 3; q++) r[q] = qpos[3 * qi + q] - x[3 * i + q];
+                for (int q = 0; q < 3; q++) r[q] = qpos[3 * qi + q] - xi[q];
                 const double *ch = qchg + 3 * qi;
                 double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
                 if (!psi) {
@@ -463,7 +489,7 @@ __device__ void local_self_node(int i, int ip, int in, double g, const LocalArgs
 
 template <int ORDER>
 __global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const double *__restrict__ x,
-                             const int *__restrict__ off, const int *__restrict__ fil,
+                             const double *__restrict__ xn, const int *__restrict__ off, const int *__restrict__ fil,
                              const double *__restrict__ gamma, const double *__restrict__ dtau,
                              const double *__restrict__ D, const double *__restrict__ sdd,
                              const double *__restrict__ ell, const double *__restrict__ qpos,
@@ -471,7 +497,7 @@ __global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const d
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     local_self_node<ORDER>(i, prev_node(off, fil, i), next_node(off, fil, i), gamma[fil[i]], la,
-                           x, dtau, D, sdd, ell, qpos, qchg, out);
+                           x, xn, dtau, D, sdd, ell, qpos, qchg, out);
 }
 
 // ----------------------------------------------------- one filament at once
@@ -482,7 +508,9 @@ __global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const d
 // correction (into vls, which the interpolation adds to the velocity).
 template <int ORDER>
 __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restrict__ off, const double *xs,
-                           double *xd, const double *__restrict__ gs, double *__restrict__ gd,
+                           double *xd, double *__restrict__ xn,
+                           const double *__restrict__ shift,
+                           const double *__restrict__ gs, double *__restrict__ gd,
                            double *__restrict__ dtau, double *__restrict__ D,
                            double *__restrict__ sdd, double *__restrict__ qpos,
                            double *__restrict__ qchg, double *__restrict__ ell,
@@ -491,19 +519,19 @@ __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restric
     const int f = blockIdx.x;
     if (f >= nfil) return;
     const int b0 = off[f], n = off[f + 1] - off[f];
-    chord_fil(f, b0, n, xs, xd, gs, gd, dtau, status);
+    chord_fil(f, b0, n, xs, xd, xn, shift, gs, gd, dtau, status);
     __syncthreads();
-    if constexpr (ORDER == 4) spline_cubic_fil(b0, n, xd, dtau, D, gscratch);
-    else spline_quintic_fil(b0, n, xd, dtau, D, sdd, gscratch);
+    if constexpr (ORDER == 4) spline_cubic_fil(b0, n, xd, xn, dtau, D, gscratch);
+    else spline_quintic_fil(b0, n, xd, xn, dtau, D, sdd, gscratch);
     __syncthreads();
     const double g = gs[f];
     for (int k = threadIdx.x; k < n; k += blockDim.x)
-        geometry_seg<ORDER>(b0 + k, b0 + (k + 1 == n ? 0 : k + 1), g, la.Q, gl, xd, dtau, D, qpos,
-                            qchg, sdd, ell);
+        geometry_seg<ORDER>(b0 + k, b0 + (k + 1 == n ? 0 : k + 1), g, la.Q, gl, xd, xn, dtau, D,
+                            qpos, qchg, sdd, ell);
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += blockDim.x)
         local_self_node<ORDER>(b0 + k, b0 + (k == 0 ? n - 1 : k - 1), b0 + (k + 1 == n ? 0 : k + 1),
-                               g, la, xd, dtau, D, sdd, ell, qpos, qchg, vls);
+                               g, la, xd, xn, dtau, D, sdd, ell, qpos, qchg, vls);
 }
 
 // ------------------------------------------------------------------ launch
@@ -530,25 +558,23 @@ void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
     auto kern = p->order == 6 ? k_filament<6> : k_filament<4>;
     hipLaunchKernelGGL(kern, dim3((unsigned)p->nfil), dim3(p->order == 6 ? 64 : 128), 0,
                        p->stream, (int)p->nfil, (const int *)p->d_off.p, xyz,
-                       (double *)p->d_x.p, gamma, (double *)p->d_gamma.p,
+                       (double *)p->d_x.p, (double *)p->d_xn.p,
+                       p->nper ? (const double *)p->d_shift.p : nullptr, gamma,
+                       (double *)p->d_gamma.p,
                        (double *)p->d_dtau.p, (double *)p->d_D.p, (double *)p->d_sdd.p,
                        (double *)p->d_qpos.p, (double *)p->d_qchg.p, (double *)p->d_ell.p,
                        (int *)p->d_status.p, (double *)p->spline_tmp.p, g, la,
                        (double *)p->d_vls.p);
 }
 
-void launch_spline(bs_plan_t p) {
-    launch_spline_data(p, (const double *)p->d_x.p, (double *)p->d_D.p, (double *)p->d_sdd.p);
-}
-
 void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout) {
     if (p->order == 6)
         hipLaunchKernelGGL(k_spline5, dim3((unsigned)p->nfil), dim3(64), 0, p->stream,
-                           (int)p->nfil, (const int *)p->d_off.p, data,
+                           (int)p->nfil, (const int *)p->d_off.p, data, (const double *)nullptr,
                            (const double *)p->d_dtau.p, Dout, Sout, (double *)p->spline_tmp.p);
     else
         hipLaunchKernelGGL(k_spline, dim3((unsigned)p->nfil), dim3(128), 0, p->stream,
-                           (int)p->nfil, (const int *)p->d_off.p, data,
+                           (int)p->nfil, (const int *)p->d_off.p, data, (const double *)nullptr,
                            (const double *)p->d_dtau.p, Dout, (double *)p->spline_tmp.p);
 }
 
@@ -556,7 +582,7 @@ void launch_local_self(bs_plan_t p, int mode, double sign, double *out) {
     auto kern = p->order == 6 ? k_local_self<6> : k_local_self<4>;
     hipLaunchKernelGGL(kern, dim3(blocks_for(p->N, 256)), dim3(256), 0, p->stream, (int)p->N,
                        local_args(p, mode, sign), (const double *)p->d_x.p,
-                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
+                       (const double *)p->d_xn.p, (const int *)p->d_off.p, (const int *)p->d_fil.p,
                        (const double *)p->d_gamma.p, (const double *)p->d_dtau.p,
                        (const double *)p->d_D.p, (const double *)p->d_sdd.p,
                        (const double *)p->d_ell.p, (const double *)p->d_qpos.p,

@@ -36,16 +36,16 @@ struct NsRule {
 // the target.  The cell count is decided on the device from that maximum.
 constexpr int kNsRedBlocks = 1024;
 
-__global__ void k_ns_reach(int N, const int *__restrict__ off, const int *__restrict__ fil,
-                           const double *__restrict__ x, const double *__restrict__ ell,
-                           double eta, double *__restrict__ pmax, double *__restrict__ psum) {
+// x: nodes; xn: end node of each segment in the segment's own frame
+__global__ void k_ns_reach(int N, const double *__restrict__ x, const double *__restrict__ xn,
+                           const double *__restrict__ ell, double eta,
+                           double *__restrict__ pmax, double *__restrict__ psum) {
     __shared__ double sh[256], ss[256];
     double m = 0.0, sum = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
-        const int jn = next_node_d(off, fil, j);
         double c2 = 0.0;
         for (int q = 0; q < 3; q++) {
-            double d = x[3 * jn + q] - x[3 * j + q];
+            double d = xn[3 * j + q] - x[3 * j + q];
             c2 += d * d;
         }
         const double r = eta * ell[j] + 0.5 * sqrt(c2);
@@ -123,21 +123,21 @@ __global__ void k_ns_zero(int n, int *__restrict__ a, int *__restrict__ b) {
 
 // segment key: A-cell of the chord midpoint (short segments) or nc_A^3 +
 // B-cell of the chord midpoint (long ones); target key: A-cell of the node
-__global__ void k_ns_keys(int N, const int *__restrict__ off, const int *__restrict__ fil,
-                          const double *__restrict__ x, const double *__restrict__ ell, double eta,
+__global__ void k_ns_keys(int N, const double *__restrict__ x, const double *__restrict__ xn,
+                          const double *__restrict__ ell, double eta,
                           double L, const int *__restrict__ ncp, int *__restrict__ key,
                           int *__restrict__ cnt, int *__restrict__ tkey, int *__restrict__ tcnt) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = j < N;
     int k = 0, kt = 0;
     if (valid) {
-        const int na = ncp[0], nb = ncp[1], jn = next_node_d(off, fil, j);
+        const int na = ncp[0], nb = ncp[1];
         double c2 = 0.0, mid[3];
         int d[3];
         for (int q = 0; q < 3; q++) {
-            const double e = x[3 * jn + q] - x[3 * j + q];
+            const double e = xn[3 * j + q] - x[3 * j + q];
             c2 += e * e;
-            mid[q] = 0.5 * (x[3 * j + q] + x[3 * jn + q]);
+            mid[q] = 0.5 * (x[3 * j + q] + xn[3 * j + q]);
             d[q] = cell_of(x[3 * j + q], L, na);
         }
         const bool shortseg = na == 1 || eta * ell[j] + 0.5 * sqrt(c2) <= L / na;
@@ -186,21 +186,21 @@ __global__ __launch_bounds__(64) void k_ns_sort(const int *__restrict__ ncp,
 
 // cell-ordered copies of each segment's end points, weight ell and index,
 // and the float32 sphere (wrapped chord midpoint, reach) of the prefilter
-__global__ void k_ns_gather(int N, const int *__restrict__ perm, const int *__restrict__ off,
-                            const int *__restrict__ fil, const double *__restrict__ x,
+__global__ void k_ns_gather(int N, const int *__restrict__ perm, const double *__restrict__ x,
+                            const double *__restrict__ xn,
                             const double *__restrict__ ell, double eta, double L,
                             double4 *__restrict__ segA, double4 *__restrict__ segB,
                             float4 *__restrict__ segM) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const int j = perm[p], jn = next_node_d(off, fil, j);
+    const int j = perm[p];
     segA[p] = make_double4(x[3 * j], x[3 * j + 1], x[3 * j + 2], ell[j]);
-    segB[p] = make_double4(x[3 * jn], x[3 * jn + 1], x[3 * jn + 2], (double)j);
+    segB[p] = make_double4(xn[3 * j], xn[3 * j + 1], xn[3 * j + 2], (double)j);
     double c2 = 0.0, m[3];
     for (int q = 0; q < 3; q++) {
-        const double d = x[3 * jn + q] - x[3 * j + q];
+        const double d = xn[3 * j + q] - x[3 * j + q];
         c2 += d * d;
-        m[q] = wrap_box(0.5 * (x[3 * j + q] + x[3 * jn + q]), L);
+        m[q] = wrap_box(0.5 * (x[3 * j + q] + xn[3 * j + q]), L);
     }
     segM[p] = make_float4((float)m[0], (float)m[1], (float)m[2],
                           (float)(eta * ell[j] + 0.5 * sqrt(c2)));
@@ -484,13 +484,15 @@ struct Seg {
     double c0[3], c1[3], c2[3], c3[3], c4[3], c5[3];
 };
 
+// (from node j to xn[j], its end node in the segment's own frame)
 __device__ __forceinline__ Seg load_seg(int j, const int *off, const int *fil, const double *x,
-                                        const double *D, const double *S, const double *dtau) {
+                                        const double *xn, const double *D, const double *S,
+                                        const double *dtau) {
     Seg s;
     int jn = next_node_d(off, fil, j);
     double h = dtau[j];
     for (int q = 0; q < 3; q++) {
-        double s0 = x[3 * j + q], s1 = x[3 * jn + q];
+        double s0 = x[3 * j + q], s1 = xn[3 * j + q];
         double d0 = h * D[3 * j + q], d1 = h * D[3 * jn + q];
         s.c0[q] = s0;
         s.c1[q] = d0;
@@ -635,12 +637,12 @@ __device__ __forceinline__ void unpack_shift(int sh, const double *x, double L, 
 
 // Exact segment integral minus its Q-point sum, for one (node, segment) pair.
 __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, const double *x,
-                        const double *D, const double *S, const double *dtau, const double *gamma,
+                        const double *xn, const double *D, const double *S, const double *dtau, const double *gamma,
                         const double *qpos, const double *qchg, int Q, double L,
                         const NsRule &R, double *out) {
     double xs[3];
     unpack_shift(sh, x + 3 * o, L, xs);
-    Seg s = load_seg(sg, off, fil, x, D, S, dtau);
+    Seg s = load_seg(sg, off, fil, x, xn, D, S, dtau);
     double acc[3], qs[3];
     ns_seg_integral(s, xs, R, acc);
     ns_qsum(sg, xs, qpos, qchg, Q, qs);
@@ -651,14 +653,16 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
 __global__ __launch_bounds__(256) void k_ns_integrate(
     const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
     const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ D, const double *__restrict__ S, const double *__restrict__ dtau,
-    const double *__restrict__ gamma, const double *__restrict__ qpos,
-    const double *__restrict__ qchg, int Q, double L, NsRule R, double *__restrict__ pout) {
+    const double *__restrict__ xn, const double *__restrict__ D, const double *__restrict__ S,
+    const double *__restrict__ dtau, const double *__restrict__ gamma,
+    const double *__restrict__ qpos, const double *__restrict__ qchg, int Q, double L, NsRule R,
+    double *__restrict__ pout) {
     const int P = *total;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         int2 pr = pairs[p];
         double out[3];
-        ns_pair(pnode[p], pr.x, pr.y, off, fil, x, D, S, dtau, gamma, qpos, qchg, Q, L, R, out);
+        ns_pair(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg, Q, L, R,
+                out);
         pout[3 * (size_t)p] = out[0];
         pout[3 * (size_t)p + 1] = out[1];
         pout[3 * (size_t)p + 2] = out[2];
@@ -890,13 +894,13 @@ __global__ void k_ns_samples(int64_t n, const double *__restrict__ U, NsRule R,
 // segment over u in [0, 1] in units of its chord length h (the sample box's
 // frame), and the image-shifted target.
 __device__ __forceinline__ void pair_geometry(int o, int sg, int sh, const int *off, const int *fil,
-                                              const double *x, const double *D,
+                                              const double *x, const double *xn, const double *D,
                                               const double *dtau, double L, double *A,
                                               double *B, double *D0, double *D1, double *xs) {
     int jn = next_node_d(off, fil, sg);
     double h2 = 0.0;
     for (int q = 0; q < 3; q++) {
-        A[q] = x[3 * sg + q]; B[q] = x[3 * jn + q];
+        A[q] = x[3 * sg + q]; B[q] = xn[3 * sg + q];
         h2 += (B[q] - A[q]) * (B[q] - A[q]);
     }
     const double sc = dtau[sg] / sqrt(h2);
@@ -910,13 +914,13 @@ __device__ __forceinline__ void pair_geometry(int o, int sg, int sh, const int *
 __global__ __launch_bounds__(256) void k_ns_features(
     const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
     const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ D, const double *__restrict__ dtau, double L,
-    float *__restrict__ X) {
+    const double *__restrict__ xn, const double *__restrict__ D, const double *__restrict__ dtau,
+    double L, float *__restrict__ X) {
     const int P = *total;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         int2 pr = pairs[p];
         double A[3], B[3], D0[3], D1[3], xs[3];
-        pair_geometry(pnode[p], pr.x, pr.y, off, fil, x, D, dtau, L, A, B, D0, D1, xs);
+        pair_geometry(pnode[p], pr.x, pr.y, off, fil, x, xn, D, dtau, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
         for (int k = 0; k < 8; k++) X[8 * (size_t)p + k] = F.f[k];
     }
@@ -926,7 +930,7 @@ __global__ __launch_bounds__(256) void k_ns_features(
 __global__ __launch_bounds__(256) void k_ns_combine(
     const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
     const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ D, const double *__restrict__ dtau,
+    const double *__restrict__ xn, const double *__restrict__ D, const double *__restrict__ dtau,
     const double *__restrict__ gamma, const double *__restrict__ qpos,
     const double *__restrict__ qchg, int Q, double L, NsRule R, NsBox box,
     const float *__restrict__ Y, double *__restrict__ pout, int *__restrict__ nfallback) {
@@ -935,13 +939,14 @@ __global__ __launch_bounds__(256) void k_ns_combine(
         int2 pr = pairs[p];
         const int o = pnode[p];
         double A[3], B[3], D0[3], D1[3], xs[3];
-        pair_geometry(o, pr.x, pr.y, off, fil, x, D, dtau, L, A, B, D0, D1, xs);
+        pair_geometry(o, pr.x, pr.y, off, fil, x, xn, D, dtau, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
-        Seg sgm = load_seg(pr.x, off, fil, x, D, nullptr, dtau);
+        Seg sgm = load_seg(pr.x, off, fil, x, xn, D, nullptr, dtau);
         const TangentBase tb = tangent_baseline(sgm, xs, F.h);
         double out[3];
         if (!F.inbox || (double)box.err[ns_bin(tb.dstar)] > box.tol) {
-            ns_pair(o, pr.x, pr.y, off, fil, x, D, nullptr, dtau, gamma, qpos, qchg, Q, L, R, out);
+            ns_pair(o, pr.x, pr.y, off, fil, x, xn, D, nullptr, dtau, gamma, qpos, qchg, Q, L, R,
+                    out);
             atomicAdd(nfallback, 1);
         } else {
             // segment integral = I_tan + mult * (network output in the chord
@@ -970,9 +975,10 @@ void ns_build_pairs(bs_plan_t p) {
     int *cfill = (int *)p->ns_cfill.p, *cperm = (int *)p->ns_cperm.p;
     const int *off = (const int *)p->d_off.p, *fil = (const int *)p->d_fil.p;
     const double *x = (const double *)p->d_x.p, *ell = (const double *)p->d_ell.p;
+    const double *xn = (const double *)p->d_xn.p;
     double *red = (double *)p->ns_red.p;
     const int nred = ceil_div(N, bs) < kNsRedBlocks ? ceil_div(N, bs) : kNsRedBlocks;
-    hipLaunchKernelGGL(k_ns_reach, dim3(nred), dim3(bs), 0, p->stream, N, off, fil, x, ell,
+    hipLaunchKernelGGL(k_ns_reach, dim3(nred), dim3(bs), 0, p->stream, N, x, xn, ell,
                        p->prm.ns_eta, red + 1, red + 1 + kNsRedBlocks);
     hipLaunchKernelGGL(k_ns_cells, dim3(1), dim3(bs), 0, p->stream, red + 1,
                        red + 1 + kNsRedBlocks, nred, N, p->prm.L, p->ns_ncmax, red, ncp);
@@ -983,7 +989,7 @@ void ns_build_pairs(bs_plan_t p) {
                        2 * nb3 + 1, ccnt, cfill);
     hipLaunchKernelGGL(k_ns_zero, dim3(ceil_div(nb3 + 1, bs)), dim3(bs), 0, p->stream, nb3 + 1,
                        tcnt, tfill);
-    hipLaunchKernelGGL(k_ns_keys, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, off, fil, x,
+    hipLaunchKernelGGL(k_ns_keys, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, x, xn,
                        ell, p->prm.ns_eta, p->prm.L, (const int *)ncp, ckey, ccnt, tkey, tcnt);
     exclusive_scan(p, ccnt, cstart, 2 * nb3);
     exclusive_scan(p, tcnt, tstart, nb3);
@@ -994,7 +1000,7 @@ void ns_build_pairs(bs_plan_t p) {
     hipLaunchKernelGGL(k_ns_sort, dim3(nsort), dim3(64), 0, p->stream, (const int *)ncp,
                        (const int *)cstart, cperm, ckey);
     hipLaunchKernelGGL(k_ns_gather, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
-                       (const int *)cperm, off, fil, x, ell, p->prm.ns_eta, p->prm.L,
+                       (const int *)cperm, x, xn, ell, p->prm.ns_eta, p->prm.L,
                        (double4 *)p->ns_segA.p, (double4 *)p->ns_segB.p,
                        (float4 *)p->ns_segM.p);
     NsArgs a;
@@ -1029,8 +1035,8 @@ void launch_ns_adaptive(bs_plan_t p, double *v) {
     hipLaunchKernelGGL(k_ns_integrate, dim3(1024), dim3(256), 0, p->stream, start + N,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
-                       (const double *)p->d_x.p, (const double *)p->d_D.p,
-                       p->order == 6 ? (const double *)p->d_sdd.p : nullptr,
+                       (const double *)p->d_x.p, (const double *)p->d_xn.p,
+                       (const double *)p->d_D.p, p->order == 6 ? (const double *)p->d_sdd.p : nullptr,
                        (const double *)p->d_dtau.p, (const double *)p->d_gamma.p,
                        (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q,
                        p->prm.L, R, (double *)p->ns_pout.p);
@@ -1061,8 +1067,9 @@ void launch_ns_mlp(bs_plan_t p, double *v) {
     hipLaunchKernelGGL(k_ns_features, dim3(1024), dim3(256), 0, p->stream, total,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
-                       (const double *)p->d_x.p, (const double *)p->d_D.p,
-                       (const double *)p->d_dtau.p, p->prm.L, (float *)p->ns_X.p);
+                       (const double *)p->d_x.p, (const double *)p->d_xn.p,
+                       (const double *)p->d_D.p, (const double *)p->d_dtau.p, p->prm.L,
+                       (float *)p->ns_X.p);
     mlp_forward_device(p->mlp, total, (int64_t)N * p->ns_max_per_node, (const float *)p->ns_X.p,
                        (float *)p->ns_Y.p, p->stream);
     NsBox box;
@@ -1073,8 +1080,9 @@ void launch_ns_mlp(bs_plan_t p, double *v) {
     hipLaunchKernelGGL(k_ns_combine, dim3(1024), dim3(256), 0, p->stream, total,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
-                       (const double *)p->d_x.p, (const double *)p->d_D.p,
-                       (const double *)p->d_dtau.p, (const double *)p->d_gamma.p,
+                       (const double *)p->d_x.p, (const double *)p->d_xn.p,
+                       (const double *)p->d_D.p, (const double *)p->d_dtau.p,
+                       (const double *)p->d_gamma.p,
                        (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q,
                        p->prm.L, R, box, (const float *)p->ns_Y.p, (double *)p->ns_pout.p,
                        (int *)p->ns_fallback.p);

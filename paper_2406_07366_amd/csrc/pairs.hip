@@ -200,7 +200,7 @@ __global__ void k_energy_partial(int N, int Q, const double *__restrict__ psi,
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
         const int f = fil[j], jn = (j + 1 < off[f + 1]) ? j + 1 : off[f];
         SegPoly<ORDER> sp;
-        sp.load(psi, eD, eS, j, jn, dtau[j]);
+        sp.load(psi, psi, jn, eD, eS, j, jn, dtau[j]);
         for (int i = 0; i < Q; i++) {
             double pv[3];
             sp.pos(gl.h[i], pv);

@@ -297,5 +297,23 @@ def six_lines(n_per: int = 128, L: float = TWO_PI, a: float = 1e-8, grid_n: int 
 WORKLOADS["six_lines"] = six_lines
 
 
+def helices(n_per: int = 48, amp: float = 0.4, L: float = TWO_PI, a: float = 1e-6,
+            grid_n: int = 32, tol: float = 1e-6) -> FilamentSet:
+    """Two wavy infinite lines (periods +e_z and -e_z, zero net vorticity)
+    about the axes (x, y) = (L/4, L/3) and (3L/4, 2L/3): curved unclosed
+    filaments, for the closing segment's treatment in every term."""
+    tau = L * np.arange(n_per) / n_per
+    parts = []
+    for k, (cx, cy, sgn) in enumerate(((L / 4, L / 3, 1), (3 * L / 4, 2 * L / 3, -1))):
+        z = tau if sgn > 0 else L - tau
+        parts.append(np.stack([cx + amp * np.cos(2 * z + k), cy + amp * np.sin(3 * z), z], 1))
+    return FilamentSet("helices", L, a, _csr([n_per] * 2), np.concatenate(parts),
+                       np.array([1.0, 1.0]), grid_n, tol,
+                       periods=np.array([[0, 0, 1], [0, 0, -1]], dtype=np.int64))
+
+
+WORKLOADS["helices"] = helices
+
+
 def make(name: str, **kw) -> FilamentSet:
     return WORKLOADS[name](**kw)

@@ -262,26 +262,13 @@ def test_infinite_straight_lines_match_2d_lattice_sums(order):
     assert ((v * sd).sum(1) > 0.1).all()
 
 
-def _helices(n_per=48, amp=0.4):
-    """Two wavy infinite lines along +z and -z (periods +-e_z)."""
-    L = 2 * math.pi
-    tau = L * np.arange(n_per) / n_per
-    parts = []
-    for k, (cx, cy, sgn) in enumerate(((L / 4, L / 3, 1), (3 * L / 4, 2 * L / 3, -1))):
-        z = tau if sgn > 0 else L - tau
-        parts.append(np.stack([cx + amp * np.cos(2 * z + k), cy + amp * np.sin(3 * z), z], 1))
-    return W.FilamentSet("helices", L, 1e-6, np.array([0, n_per, 2 * n_per]),
-                         np.concatenate(parts), np.array([1.0, 1.0]), 32, 1e-6,
-                         periods=np.array([[0, 0, 1], [0, 0, -1]]))
-
-
 @pytest.mark.parametrize("order,eps", [(4, None), (6, 0.1)])
 def test_infinite_curves_total_is_independent_of_alpha(order, eps):
     """Sec. 3.1 on curved unclosed filaments: the short-range exclusion of
     the local segments, the self correction and the subdivided local term
     must all take the closing segment in the node's own frame, otherwise
     the sum depends on alpha."""
-    fs = _helices()
+    fs = W.helices()
     o = O.Oracle(fs, Q=3, order=order)
     L = fs.L
     vs, ps = [], []
