@@ -301,6 +301,13 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
         bs_destroy(P);
         return code;
     };
+    if ((rc = check_hip(P, hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking),
+                        "hipStreamCreateWithFlags")) ||
+        (rc = check_hip(P, hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming),
+                        "hipEventCreateWithFlags")) ||
+        (rc = check_hip(P, hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming),
+                        "hipEventCreateWithFlags")))
+        return fail(rc);
     if ((rc = ensure<char>(P, P->grid, 3 * n3 * P->real_size))) return fail(rc);
     if ((rc = ensure<char>(P, P->spec, 3 * nc * 2 * P->real_size))) return fail(rc);
     if ((rc = ensure<double>(P, P->deconv, 2 * (r.K + 1)))) return fail(rc);
@@ -512,8 +519,10 @@ static int launch_ns(bs_plan_t P, double *out) {
     return BS_OK;
 }
 
-// out = base + long-range term (base NULL: out += long-range term)
-static int long_range(bs_plan_t P, int psi, const double *base, double *out) {
+// out = base + long-range term (base NULL: out += long-range term); with
+// join set, the interpolation waits for that event first
+static int long_range(bs_plan_t P, int psi, const double *base, double *out,
+                      hipEvent_t join = nullptr) {
     int rc;
     stage_begin(P, 3);
     launch_spread(P);
@@ -539,6 +548,8 @@ static int long_range(bs_plan_t P, int psi, const double *base, double *out) {
         if ((rc = fft_inverse(P))) return rc;
         stage_end(P, 6);
     }
+    if (join && (rc = check_hip(P, hipStreamWaitEvent(P->stream, join, 0), "hipStreamWaitEvent")))
+        return rc;
     stage_begin(P, 7);
     launch_interp(P, base, out);
     stage_end(P, 7);
@@ -549,18 +560,32 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
     if (!v_out) return set_error(P, BS_EINVAL, "null output");
-    // local - self was formed by set_filaments (d_vls); the interpolation
-    // writes it plus the long-range term
-    int rc = long_range(P, 0, (const double *)P->d_vls.p, v_out);
-    if (rc) return rc;
+    if (P->prm.ns_mode == BS_NS_MLP && !P->mlp)
+        return set_error(P, BS_ESTATE, "BS_NS_MLP plan without bs_set_mlp");
+    // local - self was formed by set_filaments (d_vls).  The short-range sum
+    // and the near-singular correction run on the side stream into
+    // tmp3 = (local - self) + short (+ near-singular), concurrently with the
+    // spread and the transforms on the plan stream; the interpolation waits
+    // for them and writes v = tmp3 + long-range.
+    double *t3 = (double *)P->tmp3.p;
+    int rc;
+    if ((rc = check_hip(P, hipEventRecord(P->ev_fork, P->stream), "hipEventRecord")) ||
+        (rc = check_hip(P, hipStreamWaitEvent(P->side, P->ev_fork, 0), "hipStreamWaitEvent")))
+        return rc;
+    const hipStream_t plan_stream = P->stream;
+    P->stream = P->side;   // launches below go to the side stream
     stage_begin(P, 8);
-    launch_pairs(P, 0, v_out);
+    launch_pairs(P, 0, (const double *)P->d_vls.p, t3);
     stage_end(P, 8);
     if (P->prm.ns_mode != BS_NS_OFF) {
         stage_begin(P, 9);
-        if ((rc = launch_ns(P, v_out))) return rc;
+        rc = launch_ns(P, t3);
         stage_end(P, 9);
     }
+    P->stream = plan_stream;
+    const hipError_t ej = hipEventRecord(P->ev_join, P->side);
+    if (rc || (rc = check_hip(P, ej, "hipEventRecord"))) return rc;
+    if ((rc = long_range(P, 0, t3, v_out, P->ev_join))) return rc;
     if ((rc = launch_status(P, "pair kernel"))) return rc;
     stage_collect(P);
     return BS_OK;
@@ -580,7 +605,7 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
     }
     if (v_short) {
         fill_f64(P, v_short, n3, 0.0);
-        launch_pairs(P, 0, v_short);
+        launch_pairs(P, 0, nullptr, v_short);
     }
     if (v_ns) {
         fill_f64(P, v_ns, n3, 0.0);
@@ -596,7 +621,7 @@ int bs_energy(bs_plan_t P, double *E_out, double *psi_out) {
     launch_local_self(P, LS_VLOCAL | LS_VSELF | LS_PSI | LS_ASSIGN, 1.0, psi);
     int rc = long_range(P, 1, nullptr, psi);
     if (rc) return rc;
-    launch_pairs(P, 1, psi);
+    launch_pairs(P, 1, nullptr, psi);
     const int nb = 512;
     double *partial = (double *)P->red_tmp.p;   // nb + 1 doubles
     launch_energy(P, psi, partial, nb);
@@ -786,6 +811,12 @@ int bs_get_params(bs_plan_t P, bs_params *resolved) {
 int bs_destroy(bs_plan_t P) {
     if (!P) return BS_OK;
     (void)hipStreamSynchronize(P->stream);
+    if (P->side) {
+        (void)hipStreamSynchronize(P->side);
+        (void)hipStreamDestroy(P->side);
+    }
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     drop_graph(P);
     for (int s = 0; s < BS_NSTAGES; s++) {
         if (P->ev_beg[s]) (void)hipEventDestroy(P->ev_beg[s]);

@@ -40,6 +40,11 @@ struct Geometry;  // device views, see geometry.hip
 struct bs_plan_s {
     bs_params prm{};        // resolved parameters
     hipStream_t stream = nullptr;
+    // side stream (default priority): the short-range sum and the
+    // near-singular correction of bs_velocity run there, concurrently with
+    // the long-range chain on the plan stream; fork and join by events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     std::string err;
     int fp32 = 0;           // precision == BS_FP32_MIXED
@@ -161,7 +166,8 @@ void pruned_spectral_op(bs_plan_t p, int psi);
 void pruned_inverse(bs_plan_t p);
 
 // pairs.hip
-void launch_pairs(bs_plan_t p, int psi, double *out);
+// out = base + short-range term (base NULL: out += short-range term)
+void launch_pairs(bs_plan_t p, int psi, const double *base, double *out);
 
 // ns.hip
 void ns_build_pairs(bs_plan_t p);

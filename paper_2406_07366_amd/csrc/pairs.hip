@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
                                                const double4 *__restrict__ spos,
                                                const R *__restrict__ schg,
                                                const int *__restrict__ sseg,
+                                               const double *__restrict__ base,
                                                double *__restrict__ out) {
     static_assert(WPN == 1 || WPN == 4, "1 or 4 wavefronts per target");
     __shared__ R red[4][3];
@@ -138,9 +139,11 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
     }
     if (lane == 0) {
         const double inv4pi = 1.0 / (4.0 * kPi);
-        out[3 * o] += (double)acc0 * inv4pi;
-        out[3 * o + 1] += (double)acc1 * inv4pi;
-        out[3 * o + 2] += (double)acc2 * inv4pi;
+        const double *b = base ? base : out;
+        const double b0 = b[3 * o], b1 = b[3 * o + 1], b2 = b[3 * o + 2];
+        out[3 * o] = b0 + (double)acc0 * inv4pi;
+        out[3 * o + 1] = b1 + (double)acc1 * inv4pi;
+        out[3 * o + 2] = b2 + (double)acc2 * inv4pi;
     }
 }
 
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
 constexpr int kPairSplitNodes = 16384;
 
 template <typename R, bool PSI>
-static void pairs_r(bs_plan_t p, double *out) {
+static void pairs_r(bs_plan_t p, const double *base, double *out) {
     const int N = (int)p->N;
     const bool split = N < kPairSplitNodes;
     dim3 grid(split ? N : ceil_div(N, 4)), block(256);
@@ -162,17 +165,17 @@ static void pairs_r(bs_plan_t p, double *out) {
     const R *q = (const R *)p->pq_chg.p;
     if (split)
         hipLaunchKernelGGL((k_pairs<R, PSI, 4>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
-                           nperm, x, off, fil, cs, sp, q, seg, out);
+                           nperm, x, off, fil, cs, sp, q, seg, base, out);
     else
         hipLaunchKernelGGL((k_pairs<R, PSI, 1>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
-                           nperm, x, off, fil, cs, sp, q, seg, out);
+                           nperm, x, off, fil, cs, sp, q, seg, base, out);
 }
 
-void launch_pairs(bs_plan_t p, int psi, double *out) {
+void launch_pairs(bs_plan_t p, int psi, const double *base, double *out) {
     if (p->fp32) {
-        if (psi) pairs_r<float, true>(p, out); else pairs_r<float, false>(p, out);
+        if (psi) pairs_r<float, true>(p, base, out); else pairs_r<float, false>(p, base, out);
     } else {
-        if (psi) pairs_r<double, true>(p, out); else pairs_r<double, false>(p, out);
+        if (psi) pairs_r<double, true>(p, base, out); else pairs_r<double, false>(p, base, out);
     }
 }
 
