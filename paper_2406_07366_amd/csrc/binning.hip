@@ -107,11 +107,6 @@ struct SortSet {
     int nbins[3], nitems[3];
 };
 
-__global__ void k_zero_bins(SortSet S) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int a = 0; a < 3; a++)
-        if (i <= S.nbins[a]) { S.cnt[a][i] = 0; S.fill[a][i] = 0; }
-}
 
 // spread-tile key of a quadrature point and pair-cell key of a position
 __device__ __forceinline__ int tile_key(const double *p, double L, double inv_h, int w, int n,
@@ -221,7 +216,9 @@ __global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
 
 // sorted copies for the spread (by tile) and the pairs (by cell), one pass;
 // thread (p, d) handles axis d of sorted entry p (its stencil base and w
-// kernel values, and component d of the charges and pair position)
+// kernel values, and component d of the charges and pair position).  A
+// separate launch from the per-bin sort: there a heavy bin's workgroup would
+// gather its entries alone (measured 5.5 + 6.4 us -> 21.6 us fused).
 struct GatherOut {
     int4 *base;
     void *ker, *q, *schg;
@@ -294,7 +291,7 @@ void build_bins(bs_plan_t p) {
     G.schg = p->pq_chg.p;
     G.sseg = (int *)p->pq_seg.p;
     const double *qp = (const double *)p->d_qpos.p, *qc = (const double *)p->d_qchg.p;
-    hipLaunchKernelGGL(k_zero_bins, dim3(ceil_div(maxb + 1, bs)), dim3(bs), 0, p->stream, S);
+    // the counters were cleared by the per-filament kernel (bin_clear)
     hipLaunchKernelGGL(k_keys_all, dim3(ceil_div(M + N, bs)), dim3(bs), 0, p->stream, S, qp,
                        (const double *)p->d_x.p, L, inv_h, w, n, p->T, p->NT, p->nc);
     if (maxb <= (1 << 16)) {
@@ -312,6 +309,17 @@ void build_bins(bs_plan_t p) {
         hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0,
                            p->stream, M, w, p->Q, S.perm[0], S.perm[1], qp, qc, L, inv_h, n, zeta,
                            inv_den, G);
+}
+
+BinClear bin_clear(bs_plan_t p) {
+    BinClear c;
+    c.p[0] = (int *)p->sp_cnt.p; c.p[1] = (int *)p->sp_fill.p;
+    c.p[2] = (int *)p->pq_cnt.p; c.p[3] = (int *)p->pq_fill.p;
+    c.p[4] = (int *)p->nd_cnt.p; c.p[5] = (int *)p->nd_fill.p;
+    const int ntiles = p->NT * p->NT * p->NT, nc3 = p->nc * p->nc * p->nc;
+    c.n[0] = c.n[1] = ntiles + 1;
+    c.n[2] = c.n[3] = c.n[4] = c.n[5] = nc3 + 1;
+    return c;
 }
 
 }  // namespace bs

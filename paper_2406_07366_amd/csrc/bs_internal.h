@@ -148,6 +148,13 @@ void launch_local_self(bs_plan_t p, int mode, double sign, double *out);
 // binning.hip
 void exclusive_scan(bs_plan_t p, const int *in, int *out, int n);
 void build_bins(bs_plan_t p);
+// the counters of the three bin sorts (count and fill per set), cleared by
+// the per-filament kernel ahead of build_bins
+struct BinClear {
+    int *p[6];
+    int n[6];
+};
+BinClear bin_clear(bs_plan_t p);
 
 // nufft.hip
 void launch_spread(bs_plan_t p);

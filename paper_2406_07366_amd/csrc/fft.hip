@@ -350,6 +350,83 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int K, int nseq, i
     fft_run<false, LOGN>(nseq, lds_pitch<false>(n, nseq), buf, twl, (R)1, load, store);
 }
 
+// ------------------------------------------- x and y passes fused (n <= 64)
+// On small grids one workgroup takes a whole (c, z) plane: the x transforms
+// of its n rows with modes 0..K kept in LDS, then the y transforms of those
+// K + 1 columns (and the reverse for the inverse), so the plane needs one
+// launch and no intermediate array in HBM.  A 64^2 plane in float64 needs
+// 93 KB of LDS (one workgroup per CU; 192 workgroups).
+constexpr int kFftXYMaxLogn = 6;
+
+template <typename C>
+__host__ __device__ constexpr size_t xy_lds(int n, int K1) {
+    return ((size_t)n + (size_t)n * K1 + (size_t)n * (n + (n >> 4) + 1)) * sizeof(C);
+}
+
+template <typename R, int LOGN>
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_xy_fwd(int K, int per,
+                                                             const R *__restrict__ grid,
+                                                             const typename Cx<R>::T *__restrict__ tw,
+                                                             typename Cx<R>::T *__restrict__ B) {
+    typedef typename Cx<R>::T C;
+    extern __shared__ unsigned char smem[];
+    constexpr int n = 1 << LOGN;
+    const int K1 = K + 1, NY = 2 * K + 1;
+    C *twl = (C *)smem, *P = twl + n, *buf = P + n * K1;   // P[y][kx]
+    const int cz = xcd_block(per);   // c * n + z
+    if (cz >= 3 * n) return;
+    stage_twiddles(twl, tw, n);
+    const int c = cz >> LOGN, z = cz & (n - 1);
+    const R *plane = grid + (size_t)cz * n * n;
+    auto xload = [&](int s, int e) { return C{plane[(size_t)s * n + e], (R)0}; };
+    auto xstore = [&](int s, int e, C v) {
+        if (e < K1) P[s * K1 + e] = v;
+    };
+    fft_run<true, LOGN>(n, lds_pitch<true>(n, n), buf, twl, (R)-1, xload, xstore);
+    auto yload = [&](int s, int e) { return P[e * K1 + s]; };
+    auto ystore = [&](int s, int e, C v) {
+        const int my = e <= n / 2 ? e : e - n;
+        if (my >= -K && my <= K) B[(((size_t)c * NY + (my + K)) * n + z) * K1 + s] = v;
+    };
+    fft_run<false, LOGN>(K1, lds_pitch<false>(n, K1), buf, twl, (R)-1, yload, ystore);
+}
+
+template <typename R, int LOGN>
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_yx_inv(int K, int per,
+                                                             const typename Cx<R>::T *__restrict__ B,
+                                                             const typename Cx<R>::T *__restrict__ tw,
+                                                             R *__restrict__ grid) {
+    typedef typename Cx<R>::T C;
+    extern __shared__ unsigned char smem[];
+    constexpr int n = 1 << LOGN;
+    const int K1 = K + 1, NY = 2 * K + 1;
+    C *twl = (C *)smem, *P = twl + n, *buf = P + n * K1;
+    const int cz = xcd_block(per);
+    if (cz >= 3 * n) return;
+    stage_twiddles(twl, tw, n);
+    const int c = cz >> LOGN, z = cz & (n - 1);
+    auto yload = [&](int s, int e) {
+        const int my = e <= n / 2 ? e : e - n;
+        C v = C{(R)0, (R)0};
+        if (my >= -K && my <= K) v = B[(((size_t)c * NY + (my + K)) * n + z) * K1 + s];
+        return v;
+    };
+    auto ystore = [&](int s, int e, C v) { P[e * K1 + s] = v; };
+    fft_run<false, LOGN>(K1, lds_pitch<false>(n, K1), buf, twl, (R)1, yload, ystore);
+    R *plane = grid + (size_t)cz * n * n;
+    auto xload = [&](int s, int e) {
+        C v = C{(R)0, (R)0};
+        if (e < K1) v = P[s * K1 + e];
+        else if (n - e < K1) {
+            const C u = P[s * K1 + (n - e)];
+            v = C{u.x, -u.y};
+        }
+        return v;
+    };
+    auto xstore = [&](int s, int e, C v) { plane[(size_t)s * n + e] = v.x; };
+    fft_run<true, LOGN>(n, lds_pitch<true>(n, n), buf, twl, (R)1, xload, xstore);
+}
+
 // ---------------------------------------------------------------- z pass
 // one workgroup per (my, group of KZ columns mx): the three components'
 // z-columns (sequence s = c KZ + q), forward FFT into LDS, spectral operator,
@@ -458,6 +535,16 @@ static void pruned_fwd(bs_plan_t p) {
     const int K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(LOGN);
     const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twf = (const C *)p->fft_tw.p;
+    if constexpr (LOGN <= kFftXYMaxLogn) {
+        const size_t lds = xy_lds<C>(n, K1);
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_fft_xy_fwd<R, LOGN>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const int per = ceil_div(3 * n, 8);
+        hipLaunchKernelGGL((k_fft_xy_fwd<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
+                           K, per, (const R *)p->grid.p, twf, (C *)p->fft_B.p);
+        return;
+    }
     const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
     hipLaunchKernelGGL((k_fft_x_fwd<R, LOGN>), dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
                        p->stream, nrows, K1, RB, px, (const R *)p->grid.p, twf,
@@ -494,6 +581,16 @@ static void pruned_inv(bs_plan_t p) {
     const int K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(LOGN);
     const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twi = (const C *)p->fft_tw.p + n;
+    if constexpr (LOGN <= kFftXYMaxLogn) {
+        const size_t lds = xy_lds<C>(n, K1);
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_fft_yx_inv<R, LOGN>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const int per = ceil_div(3 * n, 8);
+        hipLaunchKernelGGL((k_fft_yx_inv<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
+                           K, per, (const C *)p->fft_B.p, twi, (R *)p->grid.p);
+        return;
+    }
     const int px = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
     hipLaunchKernelGGL((k_fft_y_inv<R, LOGN>), dim3(8 * py), dim3(KB * mnj),
                        (n + n * (KB + 1)) * sizeof(C), p->stream, K, KB, py,

@@ -505,7 +505,8 @@ __global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const d
 // filament: chord lengths (and the plan's copies of the nodes and of the
 // circulation), the spline solve, quadrature points, charges and segment
 // lengths, and the velocity's local term minus the long-range self
-// correction (into vls, which the interpolation adds to the velocity).
+// correction (into vls, which the velocity sums start from).  The workgroups
+// also clear the binning counters on the way.
 template <int ORDER>
 __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restrict__ off, const double *xs,
                            double *xd, double *__restrict__ xn,
@@ -515,9 +516,13 @@ __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restric
                            double *__restrict__ sdd, double *__restrict__ qpos,
                            double *__restrict__ qchg, double *__restrict__ ell,
                            int *__restrict__ status, double *__restrict__ gscratch, GLArgs gl,
-                           LocalArgs la, double *__restrict__ vls) {
+                           LocalArgs la, double *__restrict__ vls, BinClear bc) {
     const int f = blockIdx.x;
     if (f >= nfil) return;
+    // clear the binning counters for the kernels that follow on the stream
+    for (int a = 0; a < 6; a++)
+        for (int i = f * blockDim.x + threadIdx.x; i < bc.n[a]; i += nfil * blockDim.x)
+            bc.p[a][i] = 0;
     const int b0 = off[f], n = off[f + 1] - off[f];
     chord_fil(f, b0, n, xs, xd, xn, shift, gs, gd, dtau, status);
     __syncthreads();
@@ -564,7 +569,7 @@ void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
                        (double *)p->d_dtau.p, (double *)p->d_D.p, (double *)p->d_sdd.p,
                        (double *)p->d_qpos.p, (double *)p->d_qchg.p, (double *)p->d_ell.p,
                        (int *)p->d_status.p, (double *)p->spline_tmp.p, g, la,
-                       (double *)p->d_vls.p);
+                       (double *)p->d_vls.p, bin_clear(p));
 }
 
 void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout) {

@@ -262,13 +262,14 @@ def _pruned_vs_library(B, precision, grid_n=None):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("grid_n", [64, 128, 256, 512])
+@pytest.mark.parametrize("grid_n", [32, 64, 128, 256, 512])
 def test_pruned_transforms_agree_with_hipfft(B, precision, grid_n):
     """The pruned transforms with the fused spectral operator: velocity,
     streamfunction and energy agree with the full hipFFT r2c / c2r path to
     rounding (float64) or float32 rounding (mixed), on every radix plan the
-    workloads use (64 = 8.8, 128 = 16.8, 256 = 16.16, 512 = 8.8.8, whose z
-    pass takes four columns per thread)."""
+    workloads use (32 = 8.4 and 64 = 8.8, whose x and y passes run fused per
+    plane, 128 = 16.8, 256 = 16.16, 512 = 8.8.8, whose z pass takes four
+    columns per thread)."""
     out = _pruned_vs_library(B, precision, grid_n)
     (va, pa, Ea), (vb, pb, Eb) = out[B.BS_FFT_PRUNED], out[B.BS_FFT_LIBRARY]
     tol = 1e-12 if precision == 0 else 2e-6
