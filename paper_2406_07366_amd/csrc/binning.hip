@@ -196,11 +196,11 @@ __global__ void k_scatter_all(SortSet S) {
     if (a == 1 && i >= S.nitems[1]) { i -= S.nitems[1]; a = 2; }
     const bool valid = !(a == 2 && i >= S.nitems[2]);
     const int k = valid ? S.key[a][i] : 0;
-    int slot = 0;
-    for (int s = 0; s < 3; s++) {
-        const int r = wave_add<true>(S.fill[s], k, valid && a == s);
-        if (a == s) slot = r;
-    }
+    // one atomic per (set, bin) group of the wavefront, all issued together
+    const WaveGroup g = wave_group(k, a, valid);
+    int old = 0;
+    if (valid && (int)(threadIdx.x & 63) == g.leader) old = atomicAdd(S.fill[a] + k, g.size);
+    const int slot = __shfl(old, g.leader) + g.rank;
     if (valid) S.perm[a][S.start[a][k] + slot] = i;
 }
 

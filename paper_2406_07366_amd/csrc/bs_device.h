@@ -56,34 +56,50 @@ __device__ __forceinline__ int xcd_block(int per) {
     return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
 }
 
-// counter[key] += 1 for every active lane, with one atomic per distinct key
-// in the wavefront: lanes sharing a key form a group, whose lowest lane adds
-// the group size.  With RET, returns the counter's value before the lane's own
-// increment (the group's old value plus the lane's rank in the group, in lane
-// order); else 0.  Call from converged control flow (every lane of the
-// wavefront), with active false for lanes that have no item.
-template <bool RET>
-__device__ __forceinline__ int wave_add(int *counter, int key, bool active) {
+// Groups of the active lanes of a wavefront with equal (tag, tag2): each lane
+// learns its group's lowest lane (itself when inactive) and its rank in the
+// group in lane order; the lowest lane also learns the group size.  No
+// memory access: the callers then issue one atomic per group, all groups at
+// once, so a wavefront waits for one atomic round trip whatever the number
+// of distinct keys.  Call from converged control flow (every lane).
+struct WaveGroup {
+    int leader, rank, size;
+};
+__device__ __forceinline__ WaveGroup wave_group(int tag, int tag2, bool active) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     unsigned long long todo = __ballot(active);
-    int result = 0;
+    WaveGroup g{lane, 0, 0};
     while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int kl = __shfl(key, leader);
-        const unsigned long long grp = __ballot(active && key == kl) & todo;
-        int old = 0;
-        if (lane == leader) {
-            if (RET) old = atomicAdd(counter + kl, __popcll(grp));
-            else atomicAdd(counter + kl, __popcll(grp));
+        const int l = __ffsll((long long)todo) - 1;
+        const int tl = __shfl(tag, l), tl2 = __shfl(tag2, l);
+        const unsigned long long grp = __ballot(active && tag == tl && tag2 == tl2) & todo;
+        if ((grp >> lane) & 1ull) {
+            g.leader = l;
+            g.rank = __popcll(grp & below);
         }
-        if (RET) {
-            old = __shfl(old, leader);
-            if ((grp >> lane) & 1ull) result = old + __popcll(grp & below);
-        }
+        if (lane == l) g.size = __popcll(grp);
         todo &= ~grp;
     }
-    return result;
+    return g;
+}
+
+// counter[key] += 1 for every active lane, with one atomic per distinct key
+// in the wavefront (the group's lowest lane adds the group size).  With RET,
+// returns the counter's value before the lane's own increment (the group's
+// old value plus the lane's rank in the group, in lane order); else 0.  Call
+// from converged control flow, with active false for lanes that have no item.
+template <bool RET>
+__device__ __forceinline__ int wave_add(int *counter, int key, bool active) {
+    const WaveGroup g = wave_group(key, 0, active);
+    const int lane = threadIdx.x & 63;
+    int old = 0;
+    if (active && lane == g.leader) {
+        if (RET) old = atomicAdd(counter + key, g.size);
+        else atomicAdd(counter + key, g.size);
+    }
+    if (!RET) return 0;
+    return __shfl(old, g.leader) + g.rank;
 }
 
 // Orders the distinct entries perm[s .. s+n) ascending: every entry's rank is

@@ -162,8 +162,13 @@ __global__ void k_ns_scatter(int N, const int *__restrict__ key, const int *__re
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = j < N;
     const int k = valid ? key[j] : 0, kt = valid ? tkey[j] : 0;
-    const int r = wave_add<true>(fill, k, valid);
-    const int rt = wave_add<true>(tfill, kt, valid);
+    // both atomics of a group leader in flight together
+    const WaveGroup g = wave_group(k, 0, valid), gt = wave_group(kt, 0, valid);
+    const int lane = threadIdx.x & 63;
+    int o = 0, ot = 0;
+    if (valid && lane == g.leader) o = atomicAdd(fill + k, g.size);
+    if (valid && lane == gt.leader) ot = atomicAdd(tfill + kt, gt.size);
+    const int r = __shfl(o, g.leader) + g.rank, rt = __shfl(ot, gt.leader) + gt.rank;
     if (valid) {
         perm[start[k] + r] = j;
         tperm[tstart[kt] + rt] = j;
