@@ -108,48 +108,6 @@ struct SortSet {
 };
 
 
-// spread-tile key of a quadrature point and pair-cell key of a position
-__device__ __forceinline__ int tile_key(const double *p, double L, double inv_h, int w, int n,
-                                        int T, int NT) {
-    double f;
-    const int bx = stencil_base(wrap_box(p[0], L), inv_h, w, n, &f);
-    const int by = stencil_base(wrap_box(p[1], L), inv_h, w, n, &f);
-    const int bz = stencil_base(wrap_box(p[2], L), inv_h, w, n, &f);
-    return ((bz / T) * NT + by / T) * NT + bx / T;
-}
-__device__ __forceinline__ int cell_key(const double *p, double L, int nc) {
-    int c[3];
-    for (int q = 0; q < 3; q++) {
-        const int v = (int)(wrap_box(p[q], L) / L * nc);
-        c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
-    }
-    return (c[2] * nc + c[1]) * nc + c[0];
-}
-
-// keys of the three sets; counts by wavefront-aggregated atomics (items
-// that are neighbours along a filament mostly share a tile or cell)
-__global__ void k_keys_all(SortSet S, const double *__restrict__ qpos,
-                           const double *__restrict__ x, double L, double inv_h, int w, int n,
-                           int T, int NT, int nc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int Mq = S.nitems[0];
-    const bool isq = i < Mq, isn = !isq && i < Mq + S.nitems[2];
-    int k0 = 0, k1 = 0, k2 = 0;
-    if (isq) {
-        k0 = tile_key(qpos + 3 * i, L, inv_h, w, n, T, NT);
-        S.key[0][i] = k0;
-        k1 = cell_key(qpos + 3 * i, L, nc);
-        S.key[1][i] = k1;
-    } else if (isn) {
-        const int j = i - Mq;
-        k2 = cell_key(x + 3 * j, L, nc);
-        S.key[2][j] = k2;
-    }
-    wave_add<false>(S.cnt[0], k0, isq);
-    wave_add<false>(S.cnt[1], k1, isq);
-    wave_add<false>(S.cnt[2], k2, isn);
-}
-
 // one workgroup per array: exclusive scan of cnt into start (start[n] =
 // total).  Wavefront w owns the contiguous segment [w seg, (w + 1) seg) and
 // reads it 64 entries at a time (coalesced): a first pass sums it, the
@@ -211,6 +169,12 @@ __global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
     if (a == 2 && b >= S.nbins[2]) return;
     __shared__ int v[kSortLds];
     int s = S.start[a][b], n = S.start[a][b + 1] - s;
+    // the bin's counters are not read again: clear them for the next call
+    // (the per-filament kernel counts into them)
+    if (threadIdx.x == 0) {
+        S.cnt[a][b] = 0;
+        S.fill[a][b] = 0;
+    }
     rank_sort_bin<kSortLds>(S.perm[a], S.key[a], s, n, v);
 }
 
@@ -291,9 +255,7 @@ void build_bins(bs_plan_t p) {
     G.schg = p->pq_chg.p;
     G.sseg = (int *)p->pq_seg.p;
     const double *qp = (const double *)p->d_qpos.p, *qc = (const double *)p->d_qchg.p;
-    // the counters were cleared by the per-filament kernel (bin_clear)
-    hipLaunchKernelGGL(k_keys_all, dim3(ceil_div(M + N, bs)), dim3(bs), 0, p->stream, S, qp,
-                       (const double *)p->d_x.p, L, inv_h, w, n, p->T, p->NT, p->nc);
+    // keys and counts come from the per-filament kernel (bin_keys)
     if (maxb <= (1 << 16)) {
         hipLaunchKernelGGL(k_scan_small, dim3(3), dim3(1024), 0, p->stream, S);
     } else {
@@ -311,15 +273,15 @@ void build_bins(bs_plan_t p) {
                            inv_den, G);
 }
 
-BinClear bin_clear(bs_plan_t p) {
-    BinClear c;
-    c.p[0] = (int *)p->sp_cnt.p; c.p[1] = (int *)p->sp_fill.p;
-    c.p[2] = (int *)p->pq_cnt.p; c.p[3] = (int *)p->pq_fill.p;
-    c.p[4] = (int *)p->nd_cnt.p; c.p[5] = (int *)p->nd_fill.p;
-    const int ntiles = p->NT * p->NT * p->NT, nc3 = p->nc * p->nc * p->nc;
-    c.n[0] = c.n[1] = ntiles + 1;
-    c.n[2] = c.n[3] = c.n[4] = c.n[5] = nc3 + 1;
-    return c;
+BinKeys bin_keys(bs_plan_t p) {
+    BinKeys k;
+    k.key[0] = (int *)p->sp_key.p; k.cnt[0] = (int *)p->sp_cnt.p;
+    k.key[1] = (int *)p->pq_key.p; k.cnt[1] = (int *)p->pq_cnt.p;
+    k.key[2] = (int *)p->nd_key.p; k.cnt[2] = (int *)p->nd_cnt.p;
+    k.L = p->prm.L;
+    k.inv_h = p->n / p->prm.L;
+    k.w = p->prm.w; k.n = p->n; k.T = p->T; k.NT = p->NT; k.nc = p->nc;
+    return k;
 }
 
 }  // namespace bs

@@ -475,6 +475,16 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
                  (rc = ensure<int>(P, P->ns_fallback, 1))))
                 return rc;
         }
+        // the bin counters start at zero; afterwards each call's per-bin
+        // sort clears them for the next
+        const size_t nb_t = sizeof(int) * (ntiles + 1), nb_c = sizeof(int) * (nc3 + 1);
+        if ((rc = check_hip(P, hipMemsetAsync(P->sp_cnt.p, 0, nb_t, P->stream), "memset")) ||
+            (rc = check_hip(P, hipMemsetAsync(P->sp_fill.p, 0, nb_t, P->stream), "memset")) ||
+            (rc = check_hip(P, hipMemsetAsync(P->pq_cnt.p, 0, nb_c, P->stream), "memset")) ||
+            (rc = check_hip(P, hipMemsetAsync(P->pq_fill.p, 0, nb_c, P->stream), "memset")) ||
+            (rc = check_hip(P, hipMemsetAsync(P->nd_cnt.p, 0, nb_c, P->stream), "memset")) ||
+            (rc = check_hip(P, hipMemsetAsync(P->nd_fill.p, 0, nb_c, P->stream), "memset")))
+            return rc;
         std::vector<int> off32(nfil + 1), fil32(N);
         for (int64_t f = 0; f <= nfil; f++) off32[f] = (int)offsets[f];
         for (int64_t f = 0; f < nfil; f++)

@@ -24,6 +24,24 @@ __device__ __forceinline__ int stencil_base(double xw, double inv_h, int w, int 
     return b < 0 ? b + n : b;
 }
 
+// spread-tile key of a quadrature point and pair-cell key of a position
+__device__ __forceinline__ int tile_key(const double *p, double L, double inv_h, int w, int n,
+                                        int T, int NT) {
+    double f;
+    const int bx = stencil_base(wrap_box(p[0], L), inv_h, w, n, &f);
+    const int by = stencil_base(wrap_box(p[1], L), inv_h, w, n, &f);
+    const int bz = stencil_base(wrap_box(p[2], L), inv_h, w, n, &f);
+    return ((bz / T) * NT + by / T) * NT + bx / T;
+}
+__device__ __forceinline__ int cell_key(const double *p, double L, int nc) {
+    int c[3];
+    for (int q = 0; q < 3; q++) {
+        const int v = (int)(wrap_box(p[q], L) / L * nc);
+        c[q] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+    }
+    return (c[2] * nc + c[1]) * nc + c[0];
+}
+
 // Backward Kaiser-Bessel kernel, normalised to 1 at the centre:
 //   phi(z) = sinh(zeta sqrt(1-z^2)) / (sinh(zeta) sqrt(1-z^2)),  |z| <= 1
 // (eq:kaiser_bessel_bw up to the constant pi/sinh(zeta), which the

@@ -148,13 +148,16 @@ void launch_local_self(bs_plan_t p, int mode, double sign, double *out);
 // binning.hip
 void exclusive_scan(bs_plan_t p, const int *in, int *out, int n);
 void build_bins(bs_plan_t p);
-// the counters of the three bin sorts (count and fill per set), cleared by
-// the per-filament kernel ahead of build_bins
-struct BinClear {
-    int *p[6];
-    int n[6];
+// what the per-filament kernel needs to key and count the three bin sorts
+// (quadrature points by spread tile and by pair cell, nodes by pair cell);
+// the counters start at zero (cleared at allocation, and by the per-bin sort
+// of the previous call)
+struct BinKeys {
+    int *key[3], *cnt[3];
+    double L, inv_h;
+    int w, n, T, NT, nc;
 };
-BinClear bin_clear(bs_plan_t p);
+BinKeys bin_keys(bs_plan_t p);
 
 // nufft.hip
 void launch_spread(bs_plan_t p);

@@ -23,6 +23,7 @@
 // through one LDS buffer with element j of sequence s at buf[j * pitch + s]
 // (pitch = nseq + 1, odd, so strided accesses spread over the banks).  A
 // 256-point transform (16 x 16) therefore touches LDS once each way.
+#include <atomic>
 #include <type_traits>
 
 #include "bs_internal.h"
@@ -513,6 +514,22 @@ static int ilog2(int n) {
     return l;
 }
 
+// Kernels with more than 64 KB of dynamic LDS need the limit raised; the
+// call is slow next to a launch, so it is made once per kernel and device,
+// to the hardware maximum (a permission, not an allocation: plans with
+// different needs share it safely).
+constexpr int kLdsHwMax = 163840;
+template <auto FN>
+static void allow_big_lds(int device) {
+    static std::atomic<unsigned long long> done{0};
+    const unsigned long long bit = 1ull << (device & 63);
+    if (!(done.load(std::memory_order_acquire) & bit)) {
+        (void)hipFuncSetAttribute((const void *)FN, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kLdsHwMax);
+        done.fetch_or(bit, std::memory_order_acq_rel);
+    }
+}
+
 // call f(std::integral_constant<int, logn>) for the grid sizes the pruned
 // path accepts (16 .. 1024)
 template <typename F>
@@ -537,9 +554,7 @@ static void pruned_fwd(bs_plan_t p) {
     const C *twf = (const C *)p->fft_tw.p;
     if constexpr (LOGN <= kFftXYMaxLogn) {
         const size_t lds = xy_lds<C>(n, K1);
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_fft_xy_fwd<R, LOGN>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (lds > 65536) allow_big_lds<k_fft_xy_fwd<R, LOGN>>(p->device);
         const int per = ceil_div(3 * n, 8);
         hipLaunchKernelGGL((k_fft_xy_fwd<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
                            K, per, (const R *)p->grid.p, twf, (C *)p->fft_B.p);
@@ -566,9 +581,7 @@ static void pruned_spectral(bs_plan_t p, int psi) {
     const int pz = ceil_div((2 * K + 1) * ceil_div(K1, KZ), 8);
     constexpr int IPT = z_ipt(LOGN, (int)sizeof(C));
     const size_t lds = (2 * n + n * (3 * KZ + 1)) * sizeof(C);
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_fft_z_spectral<R, LOGN, IPT>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (lds > 65536) allow_big_lds<k_fft_z_spectral<R, LOGN, IPT>>(p->device);
     hipLaunchKernelGGL((k_fft_z_spectral<R, LOGN, IPT>), dim3(8 * pz),
                        dim3(ceil_div(3 * KZ * fft_max_nj(LOGN), IPT)), lds, p->stream, K, KZ, pz,
                        psi, k0, inv4a2, 1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
@@ -583,9 +596,7 @@ static void pruned_inv(bs_plan_t p) {
     const C *twi = (const C *)p->fft_tw.p + n;
     if constexpr (LOGN <= kFftXYMaxLogn) {
         const size_t lds = xy_lds<C>(n, K1);
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_fft_yx_inv<R, LOGN>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (lds > 65536) allow_big_lds<k_fft_yx_inv<R, LOGN>>(p->device);
         const int per = ceil_div(3 * n, 8);
         hipLaunchKernelGGL((k_fft_yx_inv<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
                            K, per, (const C *)p->fft_B.p, twi, (R *)p->grid.p);

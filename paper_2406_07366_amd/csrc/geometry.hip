@@ -505,8 +505,8 @@ __global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const d
 // filament: chord lengths (and the plan's copies of the nodes and of the
 // circulation), the spline solve, quadrature points, charges and segment
 // lengths, and the velocity's local term minus the long-range self
-// correction (into vls, which the velocity sums start from).  The workgroups
-// also clear the binning counters on the way.
+// correction (into vls, which the velocity sums start from).  The keys and
+// counts of the bin sorts that follow are formed here too.
 template <int ORDER>
 __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restrict__ off, const double *xs,
                            double *xd, double *__restrict__ xn,
@@ -516,13 +516,9 @@ __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restric
                            double *__restrict__ sdd, double *__restrict__ qpos,
                            double *__restrict__ qchg, double *__restrict__ ell,
                            int *__restrict__ status, double *__restrict__ gscratch, GLArgs gl,
-                           LocalArgs la, double *__restrict__ vls, BinClear bc) {
+                           LocalArgs la, double *__restrict__ vls, BinKeys bk) {
     const int f = blockIdx.x;
     if (f >= nfil) return;
-    // clear the binning counters for the kernels that follow on the stream
-    for (int a = 0; a < 6; a++)
-        for (int i = f * blockDim.x + threadIdx.x; i < bc.n[a]; i += nfil * blockDim.x)
-            bc.p[a][i] = 0;
     const int b0 = off[f], n = off[f + 1] - off[f];
     chord_fil(f, b0, n, xs, xd, xn, shift, gs, gd, dtau, status);
     __syncthreads();
@@ -534,6 +530,34 @@ __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restric
         geometry_seg<ORDER>(b0 + k, b0 + (k + 1 == n ? 0 : k + 1), g, la.Q, gl, xd, xn, dtau, D,
                             qpos, qchg, sdd, ell);
     __syncthreads();
+    // bin keys and counts of the filament's quadrature points (spread tile,
+    // pair cell) and nodes (pair cell); whole-workgroup trip counts, as the
+    // counting is wavefront-aggregated
+    const int nq = n * la.Q;
+    for (int t0 = 0; t0 < nq; t0 += blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        const bool act = t < nq;
+        const int qi = b0 * la.Q + t;
+        int k0 = 0, k1 = 0;
+        if (act) {
+            k0 = tile_key(qpos + 3 * qi, bk.L, bk.inv_h, bk.w, bk.n, bk.T, bk.NT);
+            k1 = cell_key(qpos + 3 * qi, bk.L, bk.nc);
+            bk.key[0][qi] = k0;
+            bk.key[1][qi] = k1;
+        }
+        wave_add<false>(bk.cnt[0], k0, act);
+        wave_add<false>(bk.cnt[1], k1, act);
+    }
+    for (int t0 = 0; t0 < n; t0 += blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        const bool act = t < n;
+        int k2 = 0;
+        if (act) {
+            k2 = cell_key(xd + 3 * (b0 + t), bk.L, bk.nc);
+            bk.key[2][b0 + t] = k2;
+        }
+        wave_add<false>(bk.cnt[2], k2, act);
+    }
     for (int k = threadIdx.x; k < n; k += blockDim.x)
         local_self_node<ORDER>(b0 + k, b0 + (k == 0 ? n - 1 : k - 1), b0 + (k + 1 == n ? 0 : k + 1),
                                g, la, xd, xn, dtau, D, sdd, ell, qpos, qchg, vls);
@@ -569,7 +593,7 @@ void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
                        (double *)p->d_dtau.p, (double *)p->d_D.p, (double *)p->d_sdd.p,
                        (double *)p->d_qpos.p, (double *)p->d_qchg.p, (double *)p->d_ell.p,
                        (int *)p->d_status.p, (double *)p->spline_tmp.p, g, la,
-                       (double *)p->d_vls.p, bin_clear(p));
+                       (double *)p->d_vls.p, bin_keys(p));
 }
 
 void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout) {
