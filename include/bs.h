@@ -194,7 +194,10 @@ int bs_set_periods(bs_plan_t plan, int64_t nfil, const int64_t *periods);
  * Q-point sum of that segment is replaced by its exact integral of the full
  * Biot-Savart kernel.  At most 64 such segments per node are kept: a node
  * with more is reported by bs_status (BS_EINVAL).  BS_ESTATE if no
- * filaments were set. */
+ * filaments were set (or BS_NS_MLP without bs_set_mlp).  The short-range
+ * and near-singular terms run on a second stream that the plan owns, forked
+ * from and joined back into the plan stream by events: as seen from the
+ * plan stream, the call's work is ordered like any other. */
 int bs_velocity(bs_plan_t plan, double *v_out);
 
 /* Velocity split into its terms, each a DEVICE float64 [N][3] array or
@@ -251,7 +254,11 @@ int bs_status(bs_plan_t plan);
 
 /* Per-stage timing, for measurement.  While enabled, bs_set_filaments and
  * bs_velocity record HIP events before and after each stage on the plan
- * stream and synchronise at their end; bs_stage_times returns the summed
+ * stream and synchronise at their end, and bs_velocity runs its stages one
+ * after another on the plan stream (otherwise the short-range sum and the
+ * near-singular correction run on a second stream of the plan, beside the
+ * long-range stages, joined before the call's work ends on the plan
+ * stream); bs_stage_times returns the summed
  * milliseconds and the number of timed launches of each stage (arrays of
  * BS_NSTAGES, either may be NULL) and optionally resets them.  Stages:
  *   0 geometry (chord lengths, spline solve, quadrature points, and the

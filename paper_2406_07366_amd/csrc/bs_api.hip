@@ -576,16 +576,21 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     // and the near-singular correction run on the side stream into
     // tmp3 = (local - self) + short (+ near-singular), concurrently with the
     // spread and the transforms on the plan stream; the interpolation waits
-    // for them and writes v = tmp3 + long-range.
+    // for them and writes v = tmp3 + long-range.  With per-stage timing on,
+    // everything stays on the plan stream, so that each stage's events
+    // bracket its own kernels only.
     double *t3 = (double *)P->tmp3.p;
+    const bool side = !P->prof;
     int rc;
-    if ((rc = check_hip(P, hipEventRecord(P->ev_fork, P->stream), "hipEventRecord")) ||
-        (rc = check_hip(P, hipStreamWaitEvent(P->side, P->ev_fork, 0), "hipStreamWaitEvent")))
+    if (side &&
+        ((rc = check_hip(P, hipEventRecord(P->ev_fork, P->stream), "hipEventRecord")) ||
+         (rc = check_hip(P, hipStreamWaitEvent(P->side, P->ev_fork, 0), "hipStreamWaitEvent"))))
         return rc;
     const hipStream_t plan_stream = P->stream;
-    P->stream = P->side;   // launches below go to the side stream
+    if (side) P->stream = P->side;   // launches below go to the side stream
+    rc = BS_OK;
     stage_begin(P, 8);
-    launch_pairs(P, 0, (const double *)P->d_vls.p, t3);
+    launch_pairs(P, 0, (const double *)P->d_vls.p, t3, false);
     stage_end(P, 8);
     if (P->prm.ns_mode != BS_NS_OFF) {
         stage_begin(P, 9);
@@ -593,9 +598,9 @@ int bs_velocity(bs_plan_t P, double *v_out) {
         stage_end(P, 9);
     }
     P->stream = plan_stream;
-    const hipError_t ej = hipEventRecord(P->ev_join, P->side);
+    const hipError_t ej = side ? hipEventRecord(P->ev_join, P->side) : hipSuccess;
     if (rc || (rc = check_hip(P, ej, "hipEventRecord"))) return rc;
-    if ((rc = long_range(P, 0, t3, v_out, P->ev_join))) return rc;
+    if ((rc = long_range(P, 0, t3, v_out, side ? P->ev_join : nullptr))) return rc;
     if ((rc = launch_status(P, "pair kernel"))) return rc;
     stage_collect(P);
     return BS_OK;
@@ -615,7 +620,7 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
     }
     if (v_short) {
         fill_f64(P, v_short, n3, 0.0);
-        launch_pairs(P, 0, nullptr, v_short);
+        launch_pairs(P, 0, nullptr, v_short, true);
     }
     if (v_ns) {
         fill_f64(P, v_ns, n3, 0.0);
@@ -631,7 +636,7 @@ int bs_energy(bs_plan_t P, double *E_out, double *psi_out) {
     launch_local_self(P, LS_VLOCAL | LS_VSELF | LS_PSI | LS_ASSIGN, 1.0, psi);
     int rc = long_range(P, 1, nullptr, psi);
     if (rc) return rc;
-    launch_pairs(P, 1, nullptr, psi);
+    launch_pairs(P, 1, nullptr, psi, true);
     const int nb = 512;
     double *partial = (double *)P->red_tmp.p;   // nb + 1 doubles
     launch_energy(P, psi, partial, nb);

@@ -176,8 +176,10 @@ void pruned_spectral_op(bs_plan_t p, int psi);
 void pruned_inverse(bs_plan_t p);
 
 // pairs.hip
-// out = base + short-range term (base NULL: out += short-range term)
-void launch_pairs(bs_plan_t p, int psi, const double *base, double *out);
+// out = base + short-range term (base NULL: out += short-range term);
+// alone: nothing else runs beside it (more wavefronts per target on small
+// inputs)
+void launch_pairs(bs_plan_t p, int psi, const double *base, double *out, bool alone);
 
 // ns.hip
 void ns_build_pairs(bs_plan_t p);

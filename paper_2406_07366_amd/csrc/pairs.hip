@@ -148,15 +148,15 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
 }
 
 // targets below this count get four wavefronts each (latency hiding on
-// small inputs), but only when the pair sum runs alone: on the side stream,
+// small inputs), but only when the pair sum runs alone: in the velocity,
 // beside the spread and the transforms, one wavefront per target leaves them
 // more of the chip (64^3 ellipses: 110 -> 107 us per evaluation)
 constexpr int kPairSplitNodes = 16384;
 
 template <typename R, bool PSI>
-static void pairs_r(bs_plan_t p, const double *base, double *out) {
+static void pairs_r(bs_plan_t p, const double *base, double *out, bool alone) {
     const int N = (int)p->N;
-    const bool split = N < kPairSplitNodes && p->stream != p->side;
+    const bool split = N < kPairSplitNodes && alone;
     dim3 grid(split ? N : ceil_div(N, 4)), block(256);
     const double L = p->prm.L, rc = p->prm.rcut, alpha = p->prm.alpha;
     const int *nperm = (const int *)p->nd_perm.p, *off = (const int *)p->d_off.p,
@@ -173,11 +173,13 @@ static void pairs_r(bs_plan_t p, const double *base, double *out) {
                            nperm, x, off, fil, cs, sp, q, seg, base, out);
 }
 
-void launch_pairs(bs_plan_t p, int psi, const double *base, double *out) {
+void launch_pairs(bs_plan_t p, int psi, const double *base, double *out, bool alone) {
     if (p->fp32) {
-        if (psi) pairs_r<float, true>(p, base, out); else pairs_r<float, false>(p, base, out);
+        if (psi) pairs_r<float, true>(p, base, out, alone);
+        else pairs_r<float, false>(p, base, out, alone);
     } else {
-        if (psi) pairs_r<double, true>(p, base, out); else pairs_r<double, false>(p, base, out);
+        if (psi) pairs_r<double, true>(p, base, out, alone);
+        else pairs_r<double, false>(p, base, out, alone);
     }
 }
 
