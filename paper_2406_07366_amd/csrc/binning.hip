@@ -84,10 +84,10 @@ __global__ void k_scan_apply(const int *__restrict__ in, int n, const int *__res
 }
 
 // out[0..n-1] = exclusive scan of in, out[n] = total.  in and out may not
-// alias.  Requires n <= kScanTile^2 (4.2 M bins).
-void exclusive_scan(bs_plan_t p, const int *in, int *out, int n) {
+// alias.  Requires n <= kScanTile^2 (4.2 M bins); sums: kScanTile ints of
+// scratch, private to the stream.
+void exclusive_scan(bs_plan_t p, const int *in, int *out, int n, int *sums) {
     int nb = ceil_div(n, kScanTile);
-    int *sums = (int *)p->red_tmp.p;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, p->stream, in, n, sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, p->stream, sums, nb, out + n);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanBlock), 0, p->stream, in, n, sums, out);
@@ -259,7 +259,8 @@ void build_bins(bs_plan_t p) {
     if (maxb <= (1 << 16)) {
         hipLaunchKernelGGL(k_scan_small, dim3(3), dim3(1024), 0, p->stream, S);
     } else {
-        for (int a = 0; a < 3; a++) exclusive_scan(p, S.cnt[a], S.start[a], S.nbins[a]);
+        for (int a = 0; a < 3; a++)
+            exclusive_scan(p, S.cnt[a], S.start[a], S.nbins[a], (int *)p->red_tmp.p);
     }
     hipLaunchKernelGGL(k_scatter_all, dim3(ceil_div(2 * M + N, bs)), dim3(bs), 0, p->stream, S);
     hipLaunchKernelGGL(k_sort_all, dim3(ntiles + 2 * nc3), dim3(64), 0, p->stream, S);

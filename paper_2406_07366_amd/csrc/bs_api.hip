@@ -306,6 +306,8 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
         (rc = check_hip(P, hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming),
                         "hipEventCreateWithFlags")) ||
         (rc = check_hip(P, hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming),
+                        "hipEventCreateWithFlags")) ||
+        (rc = check_hip(P, hipEventCreateWithFlags(&P->ev_ns, hipEventDisableTiming),
                         "hipEventCreateWithFlags")))
         return fail(rc);
     if ((rc = ensure<char>(P, P->grid, 3 * n3 * P->real_size))) return fail(rc);
@@ -313,6 +315,7 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
     if ((rc = ensure<double>(P, P->deconv, 2 * (r.K + 1)))) return fail(rc);
     if ((rc = ensure<int>(P, P->d_status, 1))) return fail(rc);
     if ((rc = ensure<int>(P, P->red_tmp, 8192))) return fail(rc);
+    if ((rc = ensure<int>(P, P->scan_tmp, 8192))) return fail(rc);
     if ((rc = check_hip(P, hipMemsetAsync(P->d_status.p, 0, sizeof(int), P->stream), "memset")))
         return fail(rc);
     // deconvolution table: [1/F(m)] then [1/F(m)^2], m = 0..K
@@ -372,6 +375,15 @@ int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out) {
 
 static void drop_graph(bs_plan_t P);
 
+// order the plan stream after the side stream's pending pair search (the
+// calls that read its results or overwrite its inputs on the plan stream)
+static int join_side(bs_plan_t P) {
+    if (!P->side_pending) return BS_OK;
+    int rc = check_hip(P, hipStreamWaitEvent(P->stream, P->ev_ns, 0), "hipStreamWaitEvent");
+    if (!rc) P->side_pending = false;
+    return rc;
+}
+
 int bs_set_periods(bs_plan_t P, int64_t nfil, const int64_t *periods) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     drop_graph(P);
@@ -414,6 +426,8 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     }
     const int64_t N = offsets[nfil], Nq = N * P->Q;
     if (Nq >= ((int64_t)1 << 31) / 4) return set_error(P, BS_EINVAL, "too many nodes");
+    int rc0 = join_side(P);   // the previous search reads what this call rewrites
+    if (rc0) return rc0;
     if (P->nper && P->nper != nfil)
         return set_error(P, BS_EINVAL, "periods were set for " + std::to_string(P->nper) +
                                            " filaments, not " + std::to_string(nfil));
@@ -509,9 +523,24 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     build_bins(P);
     stage_end(P, 1);
     if (P->prm.ns_mode != BS_NS_OFF) {
+        // the pair search needs only the geometry and the node order: it runs
+        // on the side stream, where the velocity's short-range and
+        // near-singular terms follow it (per-stage timing keeps it here)
+        const bool side = !P->prof;
+        if (side &&
+            ((rc = check_hip(P, hipEventRecord(P->ev_fork, P->stream), "hipEventRecord")) ||
+             (rc = check_hip(P, hipStreamWaitEvent(P->side, P->ev_fork, 0), "hipStreamWaitEvent"))))
+            return rc;
+        const hipStream_t plan_stream = P->stream;
+        if (side) P->stream = P->side;
         stage_begin(P, 10);
         ns_build_pairs(P);
         stage_end(P, 10);
+        P->stream = plan_stream;
+        if (side) {
+            if ((rc = check_hip(P, hipEventRecord(P->ev_ns, P->side), "hipEventRecord"))) return rc;
+            P->side_pending = true;
+        }
     }
     if ((rc = launch_status(P, "geometry kernels"))) return rc;
     P->have_filaments = true;
@@ -582,6 +611,7 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     double *t3 = (double *)P->tmp3.p;
     const bool side = !P->prof;
     int rc;
+    if (!side && (rc = join_side(P))) return rc;
     if (side &&
         ((rc = check_hip(P, hipEventRecord(P->ev_fork, P->stream), "hipEventRecord")) ||
          (rc = check_hip(P, hipStreamWaitEvent(P->side, P->ev_fork, 0), "hipStreamWaitEvent"))))
@@ -601,6 +631,7 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     const hipError_t ej = side ? hipEventRecord(P->ev_join, P->side) : hipSuccess;
     if (rc || (rc = check_hip(P, ej, "hipEventRecord"))) return rc;
     if ((rc = long_range(P, 0, t3, v_out, side ? P->ev_join : nullptr))) return rc;
+    P->side_pending = false;   // the plan stream now waits for all side work
     if ((rc = launch_status(P, "pair kernel"))) return rc;
     stage_collect(P);
     return BS_OK;
@@ -611,6 +642,7 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
     int rc;
+    if ((rc = join_side(P))) return rc;
     const size_t n3 = 3 * (size_t)P->N;
     if (v_local) launch_local_self(P, LS_VLOCAL | LS_ASSIGN, 1.0, v_local);
     if (v_self) launch_local_self(P, LS_VSELF | LS_ASSIGN, 1.0, v_self);
@@ -632,6 +664,8 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
 int bs_energy(bs_plan_t P, double *E_out, double *psi_out) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     if (!P->have_filaments) return set_error(P, BS_ESTATE, "bs_set_filaments not called");
+    int rc0 = join_side(P);
+    if (rc0) return rc0;
     double *psi = psi_out ? psi_out : (double *)P->tmp3.p;
     launch_local_self(P, LS_VLOCAL | LS_VSELF | LS_PSI | LS_ASSIGN, 1.0, psi);
     int rc = long_range(P, 1, nullptr, psi);
@@ -680,6 +714,7 @@ int bs_geometry(bs_plan_t P, double *qpos, double *qcharge, double *sdot, double
 int bs_status(bs_plan_t P) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     int st = 0, rc;
+    if ((rc = join_side(P))) return rc;
     if ((rc = check_hip(P, hipMemcpyAsync(&st, P->d_status.p, sizeof(int), hipMemcpyDeviceToHost,
                                           P->stream), "read status")) ||
         (rc = check_hip(P, hipStreamSynchronize(P->stream), "sync")))
@@ -802,6 +837,7 @@ int bs_set_mlp(bs_plan_t P, bs_mlp_t mlp, const float *err_table, int nbins) {
 int bs_ns_counts(bs_plan_t P, int64_t *npairs, int64_t *nfallback) {
     if (!P) return set_error(nullptr, BS_EINVAL, "null plan");
     int np = 0, nf = 0, rc;
+    if ((rc = join_side(P))) return rc;
     if (P->prm.ns_mode != BS_NS_OFF && P->have_filaments) {
         if ((rc = check_hip(P, hipMemcpyAsync(&np, (int *)P->ns_start.p + P->N, sizeof(int),
                                               hipMemcpyDeviceToHost, P->stream), "read count")))
@@ -832,6 +868,7 @@ int bs_destroy(bs_plan_t P) {
     }
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    if (P->ev_ns) (void)hipEventDestroy(P->ev_ns);
     drop_graph(P);
     for (int s = 0; s < BS_NSTAGES; s++) {
         if (P->ev_beg[s]) (void)hipEventDestroy(P->ev_beg[s]);

@@ -45,6 +45,12 @@ struct bs_plan_s {
     // the long-range chain on the plan stream; fork and join by events
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the near-singular pair search of bs_set_filaments also runs on the side
+    // stream (beside the velocity's long-range stages); until a later call
+    // joins the side stream back, side_pending is set and ev_ns marks the
+    // search's end
+    hipEvent_t ev_ns = nullptr;
+    bool side_pending = false;
     int device = 0;
     std::string err;
     int fp32 = 0;           // precision == BS_FP32_MIXED
@@ -146,7 +152,7 @@ enum { LS_VLOCAL = 1, LS_VSELF = 2, LS_PSI = 4, LS_ASSIGN = 8 };
 void launch_local_self(bs_plan_t p, int mode, double sign, double *out);
 
 // binning.hip
-void exclusive_scan(bs_plan_t p, const int *in, int *out, int n);
+void exclusive_scan(bs_plan_t p, const int *in, int *out, int n, int *sums);
 void build_bins(bs_plan_t p);
 // what the per-filament kernel needs to key and count the three bin sorts
 // (quadrature points by spread tile and by pair cell, nodes by pair cell);

@@ -996,8 +996,9 @@ void ns_build_pairs(bs_plan_t p) {
                        tcnt, tfill);
     hipLaunchKernelGGL(k_ns_keys, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N, x, xn,
                        ell, p->prm.ns_eta, p->prm.L, (const int *)ncp, ckey, ccnt, tkey, tcnt);
-    exclusive_scan(p, ccnt, cstart, 2 * nb3);
-    exclusive_scan(p, tcnt, tstart, nb3);
+    int *sums = (int *)p->scan_tmp.p;   // the search may run on the side stream
+    exclusive_scan(p, ccnt, cstart, 2 * nb3, sums);
+    exclusive_scan(p, tcnt, tstart, nb3, sums);
     hipLaunchKernelGGL(k_ns_scatter, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
                        (const int *)ckey, (const int *)cstart, cfill, cperm, (const int *)tkey,
                        (const int *)tstart, tfill, tperm);
@@ -1023,7 +1024,7 @@ void ns_build_pairs(bs_plan_t p) {
     const int nwave = ceil_div((int64_t)N * 64, bs);
     hipLaunchKernelGGL(k_ns_flag, dim3(nwave < 1024 ? nwave : 1024), dim3(bs), 0, p->stream, a,
                        cnt, (int2 *)p->ns_slots.p, (int *)p->d_status.p);
-    exclusive_scan(p, cnt, start, N);
+    exclusive_scan(p, cnt, start, N, sums);
     const int64_t ns = (int64_t)N * p->ns_max_per_node;
     hipLaunchKernelGGL(k_ns_compact, dim3(ceil_div(ns, bs)), dim3(bs), 0, p->stream, ns,
                        p->ns_max_per_node, (const int *)cnt, (const int *)start,
