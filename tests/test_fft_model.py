@@ -6,7 +6,9 @@ Re-derives, in numpy with the kernels' own index arithmetic, that
     natural order;
   * the pruned chain  x r2c (modes 0..K) -> y (keep |my| <= K) -> z + spectral
     operator + inverse z -> zero-padded inverse y -> Hermitian c2r along x
-    equals full transforms with every mode outside |m_i| <= K zeroed.
+    equals full transforms with every mode outside |m_i| <= K zeroed, with
+    the forward x transform taking two real rows per complex sequence as the
+    kernel does (spectra separated through Z(n - k)).
 """
 import numpy as np
 import pytest
@@ -97,12 +99,18 @@ def test_pruned_chain_equals_masked_full_transforms(n, K):
     g = rng.normal(size=(3, n, n, n))             # [c][z][y][x]
     K1, NY = K + 1, 2 * K + 1
     twf, twi = tw(n, -1), tw(n, +1)
-    # x forward: rows (c, z, y), modes 0..K -> A[c][z][y][kx]
+    # x forward: rows (c, z, y) two at a time (y even and y + 1 as the real
+    # and imaginary parts of one complex sequence), spectra separated with
+    # Z(n - k); modes 0..K -> A[c][z][y][kx]
     A = np.empty((3, n, n, K1), complex)
+    k = np.arange(K1)
     for c in range(3):
         for z in range(n):
-            rows = g[c, z].T.astype(complex)           # [x][y]: element j, batch over y
-            A[c, z] = fft_batch(rows, logn, twf, -1)[:K1].T
+            rows = (g[c, z, 0::2] + 1j * g[c, z, 1::2]).T     # [x][pair]
+            Z = fft_batch(rows, logn, twf, -1)                 # [k][pair]
+            Zm = np.conj(Z[(n - k) % n])
+            A[c, z, 0::2] = ((Z[:K1] + Zm) / 2).T
+            A[c, z, 1::2] = ((Z[:K1] - Zm) / 2j).T
     # y forward -> B[c][my+K][z][kx]
     B = np.empty((3, NY, n, K1), complex)
     for c in range(3):
