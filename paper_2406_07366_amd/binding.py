@@ -60,7 +60,7 @@ class BsError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+    raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2406_07366_amd.build "
                       "(hipcc --offload-arch=gfx950)")
 
 # torch ships its own HIP runtime (same soname as the system one).  Loading
