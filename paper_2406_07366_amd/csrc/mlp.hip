@@ -150,6 +150,10 @@ __device__ void load_weights_lds(const unsigned short *__restrict__ wg, const fl
 }
 
 // ------------------------------------------------------------- inference
+// The same arithmetic as mlp_tile_forward, with every weight operand and
+// bias of the network held in registers across the wavefront's tiles (40
+// A operands and 13 bias blocks, read from LDS once): a tile then costs its
+// 40 MFMAs, 192 SiLUs per sample and the input and output accesses only.
 __global__ __launch_bounds__(256) void k_mlp_infer(int64_t B, const int *__restrict__ Bdev,
                                                    const float *__restrict__ X,
                                                    const unsigned short *__restrict__ wg,
@@ -161,13 +165,73 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int64_t B, const int *__restr
     __syncthreads();
     if (Bdev) B = *Bdev;
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int g = l >> 4;
+    bf16x4 A1[4], A2[4][4], A3[4][4], A4[4];
+    f32x4 C1[4], C2[4], C3[4], C4;
+#pragma unroll
+    for (int ob = 0; ob < 4; ob++) {
+        A1[ob] = load_a(W + kW1p, 16, 16 * ob, 0, l);
+        A4[ob] = load_a(W + kW4p, 64, 0, 16 * ob, l);
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) {
+            A2[ob][kb] = load_a(W + kW2, 64, 16 * ob, 16 * kb, l);
+            A3[ob][kb] = load_a(W + kW3, 64, 16 * ob, 16 * kb, l);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            C1[ob][r] = b[kB1 + 16 * ob + 4 * g + r];
+            C2[ob][r] = b[kB2 + 16 * ob + 4 * g + r];
+            C3[ob][r] = b[kB3 + 16 * ob + 4 * g + r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) C4[r] = b[kB4p + 4 * g + r];
     const int64_t ntiles = (B + 15) / 16;
     for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntiles; t += (int64_t)gridDim.x * nw) {
-        Fwd f;
-        mlp_tile_forward(W, b, X, B, 16 * t, l, f);
-        int64_t s = 16 * t + (l & 15);
-        if ((l >> 4) == 0 && s < B)
-            for (int r = 0; r < 3; r++) Y[3 * s + r] = f.y[r];
+        const int64_t s = 16 * t + (l & 15);
+        float xv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (s < B) {
+            const float *xs = X + 8 * s + 4 * (g & 1);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const float v = xs[r];
+                const float hi = bf2f(f2bf(v));
+                xv[r] = (g < 2) ? hi : v - hi;
+            }
+        }
+        bf16x4 x, h[4], hn[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) x[r] = (short)f2bf(xv[r]);
+#pragma unroll
+        for (int ob = 0; ob < 4; ob++) {
+            f32x4 a = mfma16(A1[ob], x, C1[ob]);
+#pragma unroll
+            for (int r = 0; r < 4; r++) a[r] = silu(a[r]);
+            h[ob] = to_bf(a);
+        }
+#pragma unroll
+        for (int ob = 0; ob < 4; ob++) {
+            f32x4 acc = C2[ob];
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++) acc = mfma16(A2[ob][kb], h[kb], acc);
+#pragma unroll
+            for (int r = 0; r < 4; r++) acc[r] = silu(acc[r]);
+            hn[ob] = to_bf(acc);
+        }
+#pragma unroll
+        for (int ob = 0; ob < 4; ob++) {
+            f32x4 acc = C3[ob];
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++) acc = mfma16(A3[ob][kb], hn[kb], acc);
+#pragma unroll
+            for (int r = 0; r < 4; r++) acc[r] = silu(acc[r]);
+            h[ob] = to_bf(acc);
+        }
+        f32x4 y = C4;
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) y = mfma16(A4[kb], h[kb], y);
+        if (g == 0 && s < B)
+            for (int r = 0; r < 3; r++) Y[3 * s + r] = y[r];
     }
 }
 
