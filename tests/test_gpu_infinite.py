@@ -218,3 +218,39 @@ def test_periods_must_match_the_filament_count(B):
     v_inf = np_(plan.velocity())
     assert rel_l2(v_closed, v_inf) > 1e-2
     plan.close()
+
+
+@pytest.mark.parametrize("name", ["six_lines", "ellipses"])
+def test_error_against_beta_follows_the_truncation_estimate(B, name):
+    """The accuracy study of Sec. 5.1 on the GPU: alpha = 24/L fixed, beta
+    varied (r_c = beta / alpha and k_max = 2 beta alpha, i.e. K =
+    ceil(beta alpha L / pi) on grids of 68, 96 and 128 points at sigma = 2),
+    reference the oracle at beta = 8; with a converged NUFFT (w = 16) the
+    error stays below the rms estimate eq:error_trunc_velocity and falls like
+    exp(-beta^2), for the long-range-dominated infinite lines (whose error is
+    the Fourier truncation alone: no pair lies within r_c) as for the random
+    ellipses."""
+    fs = W.six_lines() if name == "six_lines" else W.ellipses()
+    L = fs.L
+    V = L ** 3
+    alpha = 24 / L
+    o = O.Oracle(fs, Q=2, order=4)
+    vr, _ = o.ewald(alpha, 8 / alpha, int(math.ceil(8 * alpha * L / math.pi)), psi=False)
+    Lt = o.length()
+    vrms = math.sqrt((vr ** 2).sum(1).mean())
+    errs = []
+    for beta, n in ((2.0, 68), (3.0, 96), (4.0, 128)):
+        fs.grid_n = n
+        plan = make_plan(B, fs, alpha=alpha, rcut=beta / alpha, Q=2, sigma=2.0, w=16)
+        assert plan.params().K == int(math.ceil(beta * alpha * L / math.pi))
+        v = np_(plan.velocity())
+        plan.close()
+        est = (Lt / (math.sqrt(math.pi) * alpha * V)
+               + math.sqrt(Lt / (8 * math.pi * V)) / beta) * math.exp(-beta ** 2) / vrms
+        err = rel_l2(v, vr)
+        print(f"  {name} beta {beta}: rel_l2 {err:.3e}, estimate {est:.3e}")
+        assert err < est
+        errs.append(err)
+    for b0, b1, e0, e1 in zip((2.0, 3.0), (3.0, 4.0), errs, errs[1:]):
+        r = e1 / e0 / math.exp(b0 ** 2 - b1 ** 2)
+        assert 0.1 < r < 10

@@ -467,6 +467,35 @@ def test_truncation_estimate_bounds_measured_error():
         assert e1 < e0 / 10
 
 
+def test_truncation_estimate_bounds_error_on_the_infinite_lines():
+    """Sec. 5.1 accuracy study on the infinite lines (alpha = 24/L fixed,
+    beta varied, reference beta = 8, K = ceil(beta alpha L / pi)): the rms
+    estimate eq:error_trunc_velocity bounds the measured error and the error
+    falls like exp(-beta^2), here where the velocity is entirely long-range."""
+    fs = W.six_lines()
+    o = O.Oracle(fs, Q=2, order=4)
+    L = fs.L; V = L ** 3
+    alpha = 24 / L
+
+    def K_of(beta):
+        return int(math.ceil(beta * alpha * L / math.pi))
+    vr, _ = o.ewald(alpha, 8 / alpha, K_of(8), psi=False)
+    Lt = o.length()
+    vrms = math.sqrt((vr ** 2).sum(1).mean())
+    errs = []
+    for beta in (2.0, 3.0, 4.0):
+        v, _ = o.ewald(alpha, beta / alpha, K_of(beta), psi=False)
+        est = (Lt / (math.sqrt(math.pi) * alpha * V)
+               + math.sqrt(Lt / (8 * math.pi * V)) / beta) * math.exp(-beta ** 2) / vrms
+        err = rel_l2(v, vr)
+        assert err < est
+        errs.append(err)
+    for b0, b1, e0, e1 in zip((2.0, 3.0), (3.0, 4.0), errs, errs[1:]):
+        # exp(-beta^2) decay, within a factor of 10 either way
+        r = e1 / e0 / math.exp(b0 ** 2 - b1 ** 2)
+        assert 0.1 < r < 10
+
+
 def test_symmetries():
     """Translation invariance, linearity in Gamma, orientation reversal and a
     90-degree rotation of the box about z (Sec. 2.2, eq:BS)."""
