@@ -315,5 +315,20 @@ def helices(n_per: int = 48, amp: float = 0.4, L: float = TWO_PI, a: float = 1e-
 WORKLOADS["helices"] = helices
 
 
+def trefoil(n: int = 512, L: float = TWO_PI, a: float = 1e-6, grid_n: int = 64,
+            tol: float = 1e-6) -> FilamentSet:
+    """The trefoil knot of Sec. 5.1: one knotted curve X(theta) =
+    R (sin t + 2 sin 2t, cos t - 2 cos 2t, -sin 3t), R = L/6, n nodes
+    equispaced in theta, centred in the box, Gamma = 1."""
+    R = L / 6
+    th = 2 * np.pi * np.arange(n) / n
+    x = R * np.stack([np.sin(th) + 2 * np.sin(2 * th), np.cos(th) - 2 * np.cos(2 * th),
+                      -np.sin(3 * th)], 1) + L / 2
+    return FilamentSet("trefoil", L, a, _csr([n]), x, np.array([1.0]), grid_n, tol)
+
+
+WORKLOADS["trefoil"] = trefoil
+
+
 def make(name: str, **kw) -> FilamentSet:
     return WORKLOADS[name](**kw)

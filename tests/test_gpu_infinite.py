@@ -220,17 +220,17 @@ def test_periods_must_match_the_filament_count(B):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["six_lines", "ellipses"])
+@pytest.mark.parametrize("name", ["trefoil", "six_lines", "ellipses"])
 def test_error_against_beta_follows_the_truncation_estimate(B, name):
     """The accuracy study of Sec. 5.1 on the GPU: alpha = 24/L fixed, beta
     varied (r_c = beta / alpha and k_max = 2 beta alpha, i.e. K =
     ceil(beta alpha L / pi) on grids of 68, 96 and 128 points at sigma = 2),
     reference the oracle at beta = 8; with a converged NUFFT (w = 16) the
     error stays below the rms estimate eq:error_trunc_velocity and falls like
-    exp(-beta^2), for the long-range-dominated infinite lines (whose error is
-    the Fourier truncation alone: no pair lies within r_c) as for the random
-    ellipses."""
-    fs = W.six_lines() if name == "six_lines" else W.ellipses()
+    exp(-beta^2), for the three cases of that section: the trefoil knot, the
+    long-range-dominated infinite lines (whose error is the Fourier
+    truncation alone: no pair lies within r_c) and the random ellipses."""
+    fs = W.make(name)
     L = fs.L
     V = L ** 3
     alpha = 24 / L
