@@ -235,22 +235,32 @@ def test_error_against_beta_follows_the_truncation_estimate(B, name):
     V = L ** 3
     alpha = 24 / L
     o = O.Oracle(fs, Q=2, order=4)
-    vr, _ = o.ewald(alpha, 8 / alpha, int(math.ceil(8 * alpha * L / math.pi)), psi=False)
+    vr, pr = o.ewald(alpha, 8 / alpha, int(math.ceil(8 * alpha * L / math.pi)))
     Lt = o.length()
     vrms = math.sqrt((vr ** 2).sum(1).mean())
-    errs = []
+    prms = math.sqrt((pr ** 2).sum(1).mean())
+    errs, perrs = [], []
     for beta, n in ((2.0, 68), (3.0, 96), (4.0, 128)):
         fs.grid_n = n
         plan = make_plan(B, fs, alpha=alpha, rcut=beta / alpha, Q=2, sigma=2.0, w=16)
         assert plan.params().K == int(math.ceil(beta * alpha * L / math.pi))
         v = np_(plan.velocity())
+        _, psi = plan.energy()
+        psi = np_(psi)
         plan.close()
         est = (Lt / (math.sqrt(math.pi) * alpha * V)
                + math.sqrt(Lt / (8 * math.pi * V)) / beta) * math.exp(-beta ** 2) / vrms
-        err = rel_l2(v, vr)
-        print(f"  {name} beta {beta}: rel_l2 {err:.3e}, estimate {est:.3e}")
+        pest = (Lt / (alpha * V) + math.sqrt(Lt / (8 * math.pi * V)) / math.sqrt(beta)) \
+            * math.exp(-beta ** 2) / beta ** 1.5 / (2 * alpha) / prms
+        err, perr = rel_l2(v, vr), rel_l2(psi, pr)
+        print(f"  {name} beta {beta}: v rel_l2 {err:.3e} (estimate {est:.3e}), "
+              f"psi {perr:.3e} (estimate {pest:.3e})")
         assert err < est
+        # eq:error_trunc_streamfunction: an estimate, within a factor 2 here
+        # (the paper finds its estimates upper bounds "in almost all cases")
+        assert perr < 2 * pest
         errs.append(err)
-    for b0, b1, e0, e1 in zip((2.0, 3.0), (3.0, 4.0), errs, errs[1:]):
-        r = e1 / e0 / math.exp(b0 ** 2 - b1 ** 2)
-        assert 0.1 < r < 10
+        perrs.append(perr)
+    for b0, b1, e0, e1, p0, p1 in zip((2.0, 3.0), (3.0, 4.0), errs, errs[1:], perrs, perrs[1:]):
+        d = math.exp(b0 ** 2 - b1 ** 2)
+        assert 0.1 < e1 / e0 / d < 10 and 0.1 < p1 / p0 / d < 10
