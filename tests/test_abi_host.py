@@ -26,6 +26,31 @@ def test_library_exports_every_declared_symbol():
     assert sorted(B.EXPORTED) == sorted(names)
 
 
+def test_header_is_plain_c(tmp_path):
+    """The boundary takes no C++ or torch types: the header compiles as
+    strict C99, and a C program that calls only host-side entry points
+    links against the library."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text('#include "bs.h"\n#include <stdio.h>\n'
+                   "int main(void) {\n"
+                   "  bs_params p = {0}, r;\n"
+                   "  p.L = 6.283185307179586; p.a = 1e-6; p.tol = 1e-6; p.grid_n = 64;\n"
+                   "  int rc = bs_resolve_params(&p, &r);\n"
+                   '  printf("%d %d %d\\n", rc, r.K, r.w);\n'
+                   "  return rc;\n}\n")
+    lib = os.path.dirname(B.LIB_PATH)
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    "-L", lib, "-lbs", "-Wl,-rpath," + lib], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert out == ["0", "20", "8"]
+
+
 def test_params_struct_matches_header_field_order():
     src = open(os.path.join(ROOT, "include", "bs.h")).read()
     body = src[src.index("typedef struct {"):src.index("} bs_params;")]
