@@ -6,6 +6,7 @@ velocity: everything comes from the other lines and the images) and two
 curved unclosed lines, where the closing segment of each line (last node to
 the first node shifted by n L) enters the spline, the quadrature, the local
 term, the self correction and the near-singular search."""
+import dataclasses
 import math
 
 import numpy as np
@@ -264,3 +265,74 @@ def test_error_against_beta_follows_the_truncation_estimate(B, name):
     for b0, b1, e0, e1, p0, p1 in zip((2.0, 3.0), (3.0, 4.0), errs, errs[1:], perrs, perrs[1:]):
         d = math.exp(b0 ** 2 - b1 ** 2)
         assert 0.1 < e1 / e0 / d < 10 and 0.1 < p1 / p0 / d < 10
+
+
+def relabel(fs, k):
+    """The same curves with every filament's first node moved k places along
+    it: nodes k..n-1, then 0..k-1 shifted by n_l L (no shift for a closed
+    filament).  The closing segment is then another piece of the curve.
+    Returns the new set and, for every new node, its original index."""
+    xyz, idx = [], []
+    for l in range(fs.n_fil):
+        s, e = fs.offsets[l], fs.offsets[l + 1]
+        n = e - s
+        kk = k % n
+        order = np.r_[np.arange(s + kk, e), np.arange(s, s + kk)]
+        x = fs.xyz[order].copy()
+        x[n - kk:] += fs.periods[l] * fs.L
+        xyz.append(x)
+        idx.append(order)
+    return (dataclasses.replace(fs, name=f"{fs.name}>>{k}", xyz=np.concatenate(xyz)),
+            np.concatenate(idx))
+
+
+@pytest.mark.parametrize("case", ["plain", "adaptive", "network"])
+def test_moving_the_closing_segment_changes_nothing(B, case):
+    """An infinite filament has no distinguished node: starting it k nodes
+    later (the closing segment moves to another piece of the curve) must
+    give the same velocity and energy at every physical node, to rounding,
+    through every term: spline, quadrature, local and self terms, pairs,
+    long range and the near-singular search and integrals (adaptive, and the
+    network's features with its table opened in every bin).
+
+    The curves are moved off the grid planes first: a node exactly on one
+    (these lines have z = i L / 40, a multiple of h = L / 32 every fifth
+    node) can land one rounding step below it after the + n L shift and the
+    wrap into the box, which moves its interpolation stencil by one point;
+    the truncated Kaiser-Bessel kernel is 2 zeta e^-zeta ~ 2e-6 (not 0) at
+    the stencil's edge, so such a node's long-range velocity jumps by that
+    fraction, a tolerance-sized step of the method and not a rounding
+    difference."""
+    fs = W.helices(n_per=40, amp=0.3) if case == "plain" else line_near_ring()
+    fs = dataclasses.replace(fs, xyz=fs.xyz + np.array([0.0137, 0.0071, 0.0193]))
+    kw = {"plain": {}, "adaptive": {"ns_mode": B.BS_NS_ADAPTIVE},
+          "network": {"ns_mode": B.BS_NS_MLP}}[case]
+    vs, Es = [], []
+    for k in (0, 7, 23):
+        f2, idx = relabel(fs, k)
+        print(f"\n[case] {f2.name} N={f2.n_nodes} {case}", flush=True)
+        plan = B.Plan(B.params_for(f2, Q=2, **kw))
+        if case == "network":
+            _, _, nb = B.ns_error_bins()
+            plan.set_mlp(B.MLP(B.mlp_init(3)), np.zeros(nb, dtype=np.float32))
+        plan.set_periods(f2.periods)
+        xyz, g = B.load_workload(f2)
+        plan.set_filaments(f2.offsets, xyz, g)
+        v = np.empty((f2.n_nodes, 3))
+        v[idx] = np_(plan.velocity())
+        E, _ = plan.energy(want_psi=False)
+        plan.status()
+        if case != "plain":
+            npairs, nfb = plan.ns_counts()
+            assert npairs > 0
+            if case == "network":
+                assert nfb < npairs
+        plan.close()
+        vs.append(v)
+        Es.append(E)
+    scale = np.abs(vs[0]).max()
+    for v, E in zip(vs[1:], Es[1:]):
+        print(f"  {case}: max |dv| / max |v| {np.abs(v - vs[0]).max() / scale:.2e}, "
+              f"dE/E {abs(E / Es[0] - 1):.2e}")
+        assert np.abs(v - vs[0]).max() < 1e-11 * scale
+        assert abs(E / Es[0] - 1) < 1e-11
