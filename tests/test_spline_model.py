@@ -2,7 +2,7 @@
 
 Re-derives in numpy, with the kernels' own coefficients and index arithmetic,
 that
-  * the cyclic tridiagonal slope system of the cubic spline, solved by seven
+  * the cyclic tridiagonal slope system of the cubic spline, solved by six
     steps of parallel cyclic reduction with periodic neighbour indices, is
     the periodic cubic interpolating spline (also for power-of-two n, where
     at distance n/2 both neighbours are the same node);
@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 import scipy.interpolate
 
-PCR_STEPS_CUBIC = 7
+PCR_STEPS_CUBIC = 6
 PCR_STEPS_QUINTIC = 8
 
 
@@ -65,6 +65,35 @@ def test_cubic_pcr_matches_periodic_cubic_spline(n):
     D = cubic_pcr(h, x)
     sp = scipy.interpolate.CubicSpline(tau, np.vstack([x, x[:1]]), bc_type="periodic")
     np.testing.assert_allclose(D, sp(tau[:-1], 1), rtol=0, atol=1e-12)
+
+
+def test_six_reduction_steps_suffice_for_any_spacing():
+    """Every row has |a| + |c| = |b| / 2; a reduction step maps the ratio
+    lambda = max (|a| + |c|) / |b| to at most lambda^2 / (1 - lambda^2), so
+    six steps leave couplings below 4e-15 of the diagonal whatever n and
+    the spacings.  Checked on chord lengths spread over 3000:1: the six-step
+    slopes equal a dense solve of the cyclic system."""
+    lam = 0.5
+    for _ in range(PCR_STEPS_CUBIC):
+        lam = lam * lam / (1 - lam * lam)
+    assert lam < 4.1e-15
+    rng = np.random.default_rng(7)
+    for n in (3, 5, 16, 40, 64, 127, 128):
+        for _ in range(5):
+            h = np.exp(rng.uniform(-4, 4, n))
+            tau = np.concatenate([[0], np.cumsum(h)])
+            x = rng.normal(size=(n, 3))
+            hm = np.roll(h, 1)
+            A = np.zeros((n, n))
+            for i in range(n):
+                A[i, (i - 1) % n] += h[i]
+                A[i, i] += 2 * (hm[i] + h[i])
+                A[i, (i + 1) % n] += hm[i]
+            d = (np.roll(x, -1, 0) - x) / h[:, None]
+            r = 3 * (h[:, None] * np.roll(d, 1, 0) + hm[:, None] * d)
+            ref = np.linalg.solve(A, r)
+            D = cubic_pcr(h, x)
+            assert np.abs(D - ref).max() <= 1e-13 * np.abs(ref).max(), (n, tau[-1])
 
 
 # ----------------------------------------------------------------- quintic
