@@ -19,9 +19,21 @@ namespace bs {
 // One wavefront (four on small inputs) per target node.  Each lane holds one of the
 // 4 x 4 x 4 cells around the target; the cells' contents are enumerated as one
 // flattened range, 64 candidates per step (every lane busy, independent
-// loads), each lane finding its cell by binary search over the wavefront's
-// prefix sums.  The partial sums are combined by a fixed xor-shuffle tree
-// (deterministic order).
+// loads).  The range is mapped to point indices in chunks of kMapCap: every
+// lane writes its cell's run of point indices into the wavefront's own LDS
+// map, and each candidate then takes its point index with one LDS read.  The
+// partial sums are combined by a fixed xor-shuffle tree (deterministic order).
+constexpr int kMapCap = 1024;
+
+// LDS written by some lanes of a wavefront and read by others of the same
+// wavefront: wait for the stores and keep the compiler from moving memory
+// operations across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R, bool PSI, int WPN>
 __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double rc, double alpha,
                                                const int *__restrict__ nperm,
@@ -36,6 +48,7 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
                                                double *__restrict__ out) {
     static_assert(WPN == 1 || WPN == 4, "1 or 4 wavefronts per target");
     __shared__ R red[4][3];
+    __shared__ int pmap[4][kMapCap];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // WPN = 1: four targets per workgroup; WPN = 4: one target, its
     // candidate chunks dealt round-robin to the four wavefronts
@@ -87,41 +100,47 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
     const R rc2 = (R)(rc * rc), a = (R)alpha;
     const R two_over_sqrtpi = (R)1.12837916709551257389615890312154517;
     R acc0 = 0, acc1 = 0, acc2 = 0;
-    for (int q0 = part * 64; q0 < total; q0 += 64 * WPN) {
-        const int q = q0 + lane;
-        int c = 0;
-        for (int step = 32; step > 0; step >>= 1) {
-            const int tc = c + step;
-            const int pv = __shfl(excl, tc < ncell ? tc : ncell - 1);
-            if (tc < ncell && pv <= q) c = tc;
+    static_assert(kMapCap % (64 * WPN) == 0, "chunks keep the lanes' candidate order");
+    int *map = pmap[wave];
+    const int cs0 = __shfl(cs, 0);   // one cell (nc < 4): point index = cs0 + q
+    // chunks start at multiples of kMapCap (a multiple of 64 WPN), so every
+    // lane meets its candidates in the same order as in one flat range
+    for (int c0 = 0; c0 < total; c0 += kMapCap) {
+        const int cend = min(total, c0 + kMapCap);
+        if (ncell > 1) {
+            const int lo = max(excl, c0), hi = min(excl + cn, cend);
+            for (int j = lo; j < hi; j++) map[j - c0] = cs + (j - excl);
+            wave_lds_sync();
         }
-        const int p = __shfl(cs, c) + (q - __shfl(excl, c));
-        if (q >= total) continue;
-        const int sg = sseg[p];
-        if (sg == o || sg == ip) continue;
-        const double4 sp = spos[p];
-        double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
-        rx -= L * rint(rx * invL);
-        ry -= L * rint(ry * invL);
-        rz -= L * rint(rz * invL);
-        const R fx = (R)rx, fy = (R)ry, fz = (R)rz;
-        const R r2 = fx * fx + fy * fy + fz * fz;
-        if (!(r2 < rc2) || r2 == (R)0) continue;
-        const R rr = sqrt(r2);
-        const R ar = a * rr;
-        const R ec = erfc(ar);
-        const R *qq = schg + 4 * (size_t)p;
-        const R q0v = qq[0], q1v = qq[1], q2v = qq[2];
-        if (PSI) {
-            const R f = ec / rr;
-            acc0 += f * q0v; acc1 += f * q1v; acc2 += f * q2v;
-        } else {
-            const R g = ec + two_over_sqrtpi * ar * exp(-ar * ar);
-            const R f = g / (r2 * rr);
-            acc0 += f * (fy * q2v - fz * q1v);
-            acc1 += f * (fz * q0v - fx * q2v);
-            acc2 += f * (fx * q1v - fy * q0v);
+        for (int q = c0 + part * 64 + lane; q < cend; q += 64 * WPN) {
+            const int p = ncell > 1 ? map[q - c0] : cs0 + q;
+            const int sg = sseg[p];
+            const double4 sp = spos[p];
+            if (sg == o || sg == ip) continue;
+            double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
+            rx -= L * rint(rx * invL);
+            ry -= L * rint(ry * invL);
+            rz -= L * rint(rz * invL);
+            const R fx = (R)rx, fy = (R)ry, fz = (R)rz;
+            const R r2 = fx * fx + fy * fy + fz * fz;
+            if (!(r2 < rc2) || r2 == (R)0) continue;
+            const R rr = sqrt(r2);
+            const R ar = a * rr;
+            const R ec = erfc(ar);
+            const R *qq = schg + 4 * (size_t)p;
+            const R q0v = qq[0], q1v = qq[1], q2v = qq[2];
+            if (PSI) {
+                const R f = ec / rr;
+                acc0 += f * q0v; acc1 += f * q1v; acc2 += f * q2v;
+            } else {
+                const R g = ec + two_over_sqrtpi * ar * exp(-ar * ar);
+                const R f = g / (r2 * rr);
+                acc0 += f * (fy * q2v - fz * q1v);
+                acc1 += f * (fz * q0v - fx * q2v);
+                acc2 += f * (fx * q1v - fy * q0v);
+            }
         }
+        if (ncell > 1) wave_lds_sync();   // reads done before the next chunk is written
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) {

@@ -55,3 +55,38 @@ def test_every_point_within_rc_is_in_the_window(rc):
         for i in near:
             assert tuple(pc[i]) in kept
         assert len(kept) < 64
+
+
+@pytest.mark.parametrize("wpn", [1, 4])
+def test_chunked_candidate_map_gives_every_lane_its_flat_order(wpn):
+    """The pair kernel maps its flattened candidate range (the 64 cells' runs
+    laid end to end) to point indices in chunks of 1024: each lane writes
+    its cell's run within the chunk into the map, and the candidates
+    q = c0 + 64 part + lane, step 64 WPN, read it.  Every candidate must be
+    written exactly once before it is read, map to its own point, and every
+    lane must meet its candidates in the order of one flat pass."""
+    cap = 1024
+    rng = np.random.default_rng(wpn)
+    for trial in range(20):
+        cn = rng.integers(0, 400 if trial % 2 else 30, 64)
+        cn[rng.uniform(size=64) < 0.3] = 0
+        cs = rng.integers(0, 10 ** 6, 64)
+        excl = np.concatenate([[0], np.cumsum(cn)[:-1]])
+        total = int(cn.sum())
+        flat = np.concatenate([cs[c] + np.arange(cn[c]) for c in range(64)] + [np.zeros(0, int)])
+        for part in range(wpn):
+            order = {lane: [] for lane in range(64)}
+            for c0 in range(0, total, cap):
+                cend = min(total, c0 + cap)
+                m = np.full(cap, -1)
+                for lane in range(64):
+                    lo, hi = max(excl[lane], c0), min(excl[lane] + cn[lane], cend)
+                    for j in range(lo, hi):
+                        assert m[j - c0] == -1
+                        m[j - c0] = cs[lane] + (j - excl[lane])
+                for lane in range(64):
+                    for q in range(c0 + part * 64 + lane, cend, 64 * wpn):
+                        assert m[q - c0] == flat[q]
+                        order[lane].append(q)
+            for lane in range(64):
+                assert order[lane] == list(range(part * 64 + lane, total, 64 * wpn))
