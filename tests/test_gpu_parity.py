@@ -83,6 +83,27 @@ def test_terms_match_oracle_at_same_parameters(B):
                                rtol=0, atol=1e-13 * np.abs(v).max())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_short_range_with_thousands_of_candidates_per_target(B, precision):
+    """Ring pairs on a 64^3 grid: ~1900 candidates per target (up to ~3000),
+    so the pair kernel maps its candidate range in two or three LDS chunks
+    for nearly every target.  The short-range term at every 7th node against
+    the oracle's (same quadrature points, same r_c), in both precisions."""
+    fs = W.ringpairs(npairs=200, nbg=20, seed=11)
+    fs.grid_n, fs.tol = 64, 1e-6
+    kw = {"precision": B.BS_FP32_MIXED} if precision == "mixed" else {}
+    plan = make_plan(B, fs, **kw)
+    prm = plan.params()
+    assert prm.ncell >= 4
+    short = np_(plan.velocity_terms()["short"])
+    plan.close()
+    tg = np.arange(0, fs.n_nodes, 7)
+    ref, _ = O.Oracle(fs).shortrange(prm.alpha, prm.rcut, targets=tg, psi=False)
+    err = rel_l2(short[tg], ref)
+    print(f"  ring pairs short-range ({precision}): rel_l2 {err:.2e} over {len(tg)} targets")
+    assert err < (1e-12 if precision == "fp64" else 1e-6)
+
+
 def test_vorticity_modes_match_direct_sums(B):
     """Type-1 NUFFT (spread + FFT + deconvolution) against the direct sums
     of eq:vorticity_fourier_coefs."""
