@@ -467,6 +467,41 @@ def test_truncation_estimate_bounds_measured_error():
         assert e1 < e0 / 10
 
 
+@pytest.mark.parametrize("order", [4, 6])
+def test_infinite_curves_have_no_distinguished_node(order):
+    """Sec. 2.1: an infinite filament is the same curve whichever node is
+    called first.  Starting each helix 13 nodes later (nodes 13..n-1, then
+    0..12 shifted by nL) moves the closing segment to another piece of the
+    curve; velocity, streamfunction and energy at every physical node must
+    not change.  The curves are moved off the grid planes first, so that no
+    point's interpolation stencil depends on a rounding step."""
+    import dataclasses
+    fs = W.helices(n_per=40, amp=0.3)
+    fs = dataclasses.replace(fs, xyz=fs.xyz + np.array([0.0137, 0.0071, 0.0193]))
+    k = 13
+    xyz, idx = [], []
+    for l in range(fs.n_fil):
+        s0, e0 = fs.offsets[l], fs.offsets[l + 1]
+        n = e0 - s0
+        order_l = np.r_[np.arange(s0 + k, e0), np.arange(s0, s0 + k)]
+        x = fs.xyz[order_l].copy()
+        x[n - k:] += fs.periods[l] * fs.L
+        xyz.append(x)
+        idx.append(order_l)
+    f2 = dataclasses.replace(fs, xyz=np.concatenate(xyz))
+    idx = np.concatenate(idx)
+    prm = O.reference_params(fs.L, 6.5, fs.L / 2)
+    res = []
+    for f in (fs, f2):
+        o = O.Oracle(f, Q=2, order=order)
+        v, p = o.ewald(prm["alpha"], prm["rc"], prm["K"])
+        res.append((v, p, o.energy(p)))
+    (v0, p0, E0), (v1, p1, E1) = res
+    assert rel_l2(v1, v0[idx]) < 1e-12
+    assert rel_l2(p1, p0[idx]) < 1e-12
+    assert abs(E1 / E0 - 1) < 1e-12
+
+
 def test_truncation_estimate_bounds_error_on_the_infinite_lines():
     """Sec. 5.1 accuracy study on the infinite lines (alpha = 24/L fixed,
     beta varied, reference beta = 8, K = ceil(beta alpha L / pi)): the rms
