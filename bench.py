@@ -6,10 +6,17 @@ short-range pairs, spread, FFT, spectral operator, inverse FFT,
 interpolation), i.e. the whole hot path from node positions to node
 velocities, on one MI355X.
 
-Default workload: 40 random ellipses x 64 nodes (N = 2560), grid 64^3,
-tolerance 1e-6, FP64 path (the accuracy bar of the metric: rel. l2 error
-<= 1e-6 against the converged FP64 CPU oracle).  The FP32-mixed path is timed
-on the same workload and reported beside it.
+Default workload: the large random Fourier tangle (10000 curves x 100 nodes,
+N = 1e6, grid 512^3), the largest single-GPU configuration.  Two legs:
+  plain   every step in float64, near-singular pairs by the adaptive
+          integrator, parameters of tolerance 1e-6 (the metric's accuracy
+          bar: rel. l2 error <= 1e-6 against the FP64 CPU oracle) -> "value";
+  learned float32 spread, transforms, interpolation and pairs, near-singular
+          pairs by the trained network (trained here, on the GPU, by the
+          library's own kernels) with its adaptive fallback, tolerance 1e-5
+          (bar 1e-5) -> "config.other_precision".
+Errors are taken at the nodes of the oracle's stored reference (sampled on
+large workloads).  Other workloads: --workload ellipses | tangle | ringpairs.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -146,85 +153,6 @@ def cpu_baseline(fs, prm, budget_s=10.0):
                       f"{dt:.1f} s"}
 
 
-EULER_GAMMA = 0.5772156649015329
-
-
-def kelvin_period(lam, a, delta=0.25, kappa=1.0):
-    """T_kw(lambda) of Sec. 5.2; the RK4 step is dt = T_kw(l_min)."""
-    return 2 * lam ** 2 / kappa / (math.log(lam / (math.pi * a)) + 0.5 - (delta + EULER_GAMMA))
-
-
-def min_chord(fs):
-    x = fs.xyz
-    nxt = np.arange(fs.n_nodes) + 1
-    nxt[fs.offsets[1:] - 1] = fs.offsets[:-1]
-    return float(np.linalg.norm(x[nxt] - x, axis=1).min())
-
-
-def rk4_run(torch, B, plan, fs, steps, dt):
-    """steps RK4 steps on device positions; energy after each step."""
-    xyz, g = B.load_workload(fs)
-    plan.set_filaments(fs.offsets, xyz, g)
-    E = [plan.energy(want_psi=False)[0]]
-    times = []
-    for _ in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.rk4_step(fs.offsets, xyz, g, dt)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        plan.set_filaments(fs.offsets, xyz, g)
-        E.append(plan.energy(want_psi=False)[0])
-    plan.status()
-    return np.array(E), np.array(times), xyz.cpu().numpy()
-
-
-def bigtangle(args, torch, B, W):
-    """Large tangle (N = 1e6, grid 512^3, FP32-mixed + learned correction):
-    velocity throughput, 10 RK4 steps with energy, and the energy drift of the
-    first 100 filaments (1e4 nodes) against the FP64 oracle's energies stored
-    by tests/golden/make_references.py (--drift)."""
-    from paper_2406_07366_amd import ns_mlp
-    fs = W.bigtangle()
-    N = fs.n_nodes
-    dt = kelvin_period(min_chord(fs), fs.a)
-    log(f"[bench] bigtangle N={N}, dt = T_kw(l_min) = {dt:.3e}")
-    mlp, table, _ = ns_mlp.train(n_train=1_000_000, n_val=100_000, epochs=40, batch=8192, log=log)
-    plan = B.Plan(B.params_for(fs, precision=B.BS_FP32_MIXED, ns_mode=B.BS_NS_MLP))
-    plan.set_mlp(mlp, table)
-    xyz, g = B.load_workload(fs)
-    out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
-    ms, _ = time_steps(torch, plan, fs, xyz, g, out, args.steps, args.warmup)
-    st = stage_profile(torch, plan, fs, xyz, g, out, max(5, args.steps // 2))
-    npairs, nfb = plan.ns_counts()
-    log(f"[bench] bigtangle: {ms:.3f} ms per velocity eval, {N / ms * 1e3:.4g} nodes/s; "
-        f"ns pairs {npairs}")
-    log("[bench]   stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in st.items()))
-    E, tsteps, _ = rk4_run(torch, B, plan, fs, 10, dt)
-    drift = E / E[0] - 1
-    log(f"[bench] RK4 10 steps: {tsteps.mean() * 1e3:.2f} ms/step, energy drift "
-        + " ".join(f"{d:.2e}" for d in drift))
-    res = {"ms_per_eval": ms, "nodes_per_s": N / ms * 1e3, "stages": st, "dt": dt,
-           "rk4_ms_per_step": tsteps.mean() * 1e3, "energy": E.tolist(), "drift": drift.tolist(),
-           "ns_pairs": npairs}
-    if args.drift:
-        sub = fs.subset(100)
-        sub.grid_n = 128
-        log(f"[bench] drift subset N={sub.n_nodes}, grid 128^3")
-        ps = B.Plan(B.params_for(sub, precision=B.BS_FP32_MIXED, ns_mode=B.BS_NS_MLP))
-        ps.set_mlp(mlp, table)
-        Eg, _, _ = rk4_run(torch, B, ps, sub, 10, dt)
-        gold = load_reference("bigtangle_subset_energy")
-        assert gold is not None and abs(float(gold["dt"]) - dt) < 1e-12 * dt
-        Eo = gold["E"]
-        rel = np.abs(Eg - Eo) / np.abs(Eo)
-        log("[bench] subset |E_gpu - E_oracle|/E_oracle per step: " + " ".join(f"{r:.2e}" for r in rel))
-        log("[bench] subset drift gpu " + " ".join(f"{d:.2e}" for d in Eg / Eg[0] - 1))
-        log("[bench] subset drift oracle " + " ".join(f"{d:.2e}" for d in Eo / Eo[0] - 1))
-        res["subset"] = {"E_gpu": Eg.tolist(), "E_oracle": Eo.tolist(), "rel": rel.tolist()}
-    return res
-
-
 def table1(args, torch, B, W):
     """Sec. 5.3 performance tests on the GPU: random ellipses of 32 nodes,
     quintic splines, Q = 3, a = 1e-8, FP64; per Table 1 row alpha = C_beta
@@ -260,18 +188,68 @@ def table1(args, torch, B, W):
             plan.close()
 
 
+
+
+def cpu_baseline_sampled(fs, n_targets=384, seed=0):
+    """The oracle as it stands on a bounded sample of a large workload.  Its
+    reference evaluation (direct Fourier sums with beta = 6, r_c = L, K = 12,
+    brute-force short-range sums over every periodic image within r_c, exact
+    near-singular segment integrals) costs a fixed part (spline fit of every
+    filament and the Fourier coefficients of all quadrature points) plus a
+    part per target node; both are timed, the second on n_targets nodes, and
+    nodes/s = N / (fixed + N * per_target)."""
+    from oracle import oracle as O
+    prm = O.reference_params(fs.L, 6.0)
+    idx = np.sort(np.random.default_rng(seed).choice(fs.n_nodes, n_targets, replace=False))
+    t0 = time.perf_counter()
+    o = O.Oracle(fs)
+    o.longrange(prm["alpha"], prm["K"], idx[:1], psi=False)
+    t1 = time.perf_counter()
+    o.local(idx)
+    o.shortrange(prm["alpha"], prm["rc"], idx, psi=False)
+    o.selfcorr(prm["alpha"], idx)
+    o.ns_correction(1.0, idx)
+    t2 = time.perf_counter()
+    fixed, per = t1 - t0, (t2 - t1) / n_targets
+    return {"value": fs.n_nodes / (fixed + fs.n_nodes * per), "unit": "nodes/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{fs.name} (N={fs.n_nodes}): spline fit and Fourier coefficients of all "
+                      f"{fs.n_nodes * 2} quadrature points ({fixed:.1f} s, K={prm['K']}, "
+                      f"r_c=L, beta=6) plus local, short-range, self and exact near-singular "
+                      f"terms at {n_targets} sampled nodes ({t2 - t1:.1f} s); nodes/s = "
+                      f"N / (fixed + N * per-node)"}
+
+
+# per workload: the legs (name, precision, near-singular mode, tolerance)
+def legs_for(name, B):
+    if name in ("bigtangle", "ringpairs"):
+        return [("plain", B.BS_FP64, B.BS_NS_ADAPTIVE, 1e-6),
+                ("learned", B.BS_FP32_MIXED, B.BS_NS_MLP, 1e-5)]
+    return [("plain", B.BS_FP64, B.BS_NS_OFF, 1e-6),
+            ("mixed", B.BS_FP32_MIXED, B.BS_NS_OFF, 1e-5)]
+
+
+def errors(v, gold):
+    """rel. l2 error over the reference nodes (eq:def_relative_errors) and the
+    largest per-node error relative to the rms reference velocity."""
+    idx, ref = gold["idx"], gold["v"]
+    d = v[idx] - ref
+    vrms = math.sqrt((ref ** 2).sum(1).mean())
+    return (math.sqrt((d ** 2).sum(1).mean()) / vrms,
+            float(np.sqrt((d ** 2).sum(1)).max() / vrms))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ellipses")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="bigtangle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--detail", default=None,
                     help="also write per-stage times, rooflines and parameters to this JSON file")
-    ap.add_argument("--drift", action="store_true",
-                    help="bigtangle: energy drift of a 1e4-node subset against the FP64 oracle")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated subset of the legs to run (profiling runs)")
     ap.add_argument("--table1", default=None, metavar="SIZES",
                     help="the paper's performance tests (Sec. 5.3, Table 1) instead of the "
                          "default line: comma-separated ellipse counts (32 nodes each); one "
@@ -281,7 +259,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "only single-GPU runs are implemented: the sharded multi-GPU path does not exist; use --gpus 1"}))
+        print(json.dumps({"error": "only single-GPU runs exist: every box here has one GPU and "
+                                   "the sharded multi-GPU path is not built; use --gpus 1"}))
         sys.exit(2)
 
     import torch
@@ -293,45 +272,29 @@ def main():
         table1(args, torch, B, W)
         return
 
-    if args.workload == "bigtangle":
-        res = bigtangle(args, torch, B, W)
-        if args.detail:
-            os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
-            with open(args.detail, "w") as f:
-                json.dump(res, f, indent=1, default=float)
-        print(json.dumps({"workload": "bigtangle", "nodes_per_s": res["nodes_per_s"],
-                          "rk4_ms_per_step": res["rk4_ms_per_step"],
-                          "drift_last": res["drift"][-1]}), flush=True)
-        return
-
     fs = W.make(args.workload)
     N = fs.n_nodes
-    log(f"[bench] workload {fs.name} N={N} grid={fs.grid_n}^3 tol={fs.tol}")
-    xyz, gamma = B.load_workload(fs)
-    out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
-
-    # reference solution (converged oracle, stored), sampled on large workloads
+    log(f"[bench] workload {fs.name} N={N} grid={fs.grid_n}^3")
     gold = load_reference(fs.name)
     if gold is None:
         raise SystemExit(f"no stored reference for {fs.name}: run tests/golden/make_references.py")
-    idx, ref = gold["idx"], gold["v"]
+    xyz, gamma = B.load_workload(fs)
+    out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
 
-    ns_eta = None
+    legs = legs_for(fs.name, B)
+    if args.legs:
+        keep = args.legs.split(",")
+        legs = [l for l in legs if l[0] in keep]
     mlp = table = None
-    if fs.name == "ringpairs":
-        # near-singular pairs dominate: plain = FP64 + adaptive integrals,
-        # learned = FP32-mixed + the trained network (trained here, on the GPU)
+    if any(l[2] == B.BS_NS_MLP for l in legs):
         from paper_2406_07366_amd import ns_mlp
-        log("[bench] training the near-singular network (1e6 samples) ...")
-        mlp, table, info = ns_mlp.train(n_train=1_000_000, n_val=100_000, epochs=40,
-                                        batch=8192, log=log)
-        variants = {"fp64": (B.BS_FP64, B.BS_NS_ADAPTIVE), "mixed": (B.BS_FP32_MIXED, B.BS_NS_MLP)}
-        ns_eta = 1.0
-    else:
-        variants = {"fp64": (B.BS_FP64, B.BS_NS_OFF), "mixed": (B.BS_FP32_MIXED, B.BS_NS_OFF)}
+        log("[bench] training the near-singular network on the GPU (1e6 samples) ...")
+        mlp, table, _ = ns_mlp.train(n_train=1_000_000, n_val=100_000, epochs=40,
+                                     batch=8192, log=log)
 
     results = {}
-    for prec_name, (prec, ns_mode) in variants.items():
+    for name, prec, ns_mode, tol in legs:
+        fs.tol = tol
         plan = B.Plan(B.params_for(fs, precision=prec, ns_mode=ns_mode))
         if ns_mode == B.BS_NS_MLP:
             plan.set_mlp(mlp, table)
@@ -339,15 +302,18 @@ def main():
         plan.set_filaments(fs.offsets, xyz, gamma)
         plan.velocity(out)
         plan.status()
-        err = rel_l2(out.cpu().numpy()[idx], ref)
+        err, errmax = errors(out.cpu().numpy(), gold)
         ms_host, ms_ev = time_steps(torch, plan, fs, xyz, gamma, out, args.steps, args.warmup)
-        st = stage_profile(torch, plan, fs, xyz, gamma, out, max(20, args.steps // 4))
+        plan.status()
+        st = stage_profile(torch, plan, fs, xyz, gamma, out, max(3, args.steps // 4))
         npairs, nfb = plan.ns_counts() if ns_mode != B.BS_NS_OFF else (0, 0)
-        log(f"[bench] {prec_name} (ns_mode {ns_mode}): {ms_host:.4f} ms/step (events {ms_ev:.4f}), "
-            f"rel_l2 {err:.3e}, {N / ms_host * 1e3:.4g} nodes/s, ns pairs {npairs}")
+        log(f"[bench] {name} (prec {prec}, ns_mode {ns_mode}, tol {tol:g}): {ms_host:.4f} ms/step "
+            f"(events {ms_ev:.4f}), rel_l2 {err:.3e} (max/rms {errmax:.2e}), "
+            f"{N / ms_host * 1e3:.4g} nodes/s, ns pairs {npairs} fallback {nfb}")
         log("[bench]   stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in st.items()))
-        results[prec_name] = dict(ms=ms_host, ms_events=ms_ev, err=err, stages=st,
-                                  prm=prm.as_dict(), plan=plan, ns_mode=ns_mode, ns_pairs=npairs)
+        results[name] = dict(ms=ms_host, ms_events=ms_ev, err=err, errmax=errmax, stages=st,
+                             prm=prm.as_dict(), plan=plan, ns_mode=ns_mode, tol=tol,
+                             precision=prec, ns_pairs=npairs, ns_fallback=nfb)
 
     if args.pmc_calibrate:
         src_t = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -357,33 +323,36 @@ def main():
         torch.cuda.synchronize()
         del src_t, dst_t
 
-    primary = results[args.precision]
+    pname = legs[0][0]
+    primary = results[pname]
     prm = primary["prm"]
-    fp32 = args.precision == "mixed"
+    fp32 = primary["precision"] == B.BS_FP32_MIXED
+    rp = B.resolve_params(B.params_for(fs, precision=primary["precision"]))
     Nq = N * prm["Q"]
-    npairs = count_pairs(primary["plan"], fs, prm["Q"], prm["rcut"])
-    sb = stage_bytes(B.resolve_params(B.params_for(fs, precision=int(fp32))), N, Nq, fp32)
+    sb = stage_bytes(rp, N, Nq, fp32)
     st = primary["stages"]
     roof_all = {}
     for k, b in sb.items():
         if st.get(k, 0) > 0:
             roof_all[k] = dict(bound="hbm", achieved=b / (st[k] * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                                unit="GB/s", bytes=b, ms=st[k])
-    if st.get("pairs", 0) > 0:
+    if st.get("pairs", 0) > 0 and N <= 300_000:
+        npairs = count_pairs(primary["plan"], fs, prm["Q"], prm["rcut"])
         peak = FP32_VECTOR_TFLOPS if fp32 else FP64_VECTOR_TFLOPS
         fl = npairs * PAIR_FLOP
         roof_all["pairs"] = dict(bound="alu", achieved=fl / (st["pairs"] * 1e-3) / 1e12,
                                  peak=peak, unit="TFLOP/s", flops=fl, pairs=npairs,
                                  ms=st["pairs"])
-    # dominant single-kernel stage (stage events then time exactly one kernel)
+    # dominant single-kernel stage (the stage events then time exactly one kernel)
     dom = max((k for k in roof_all if k in SINGLE_KERNEL_STAGES), key=lambda k: roof_all[k]["ms"])
     d = roof_all[dom]
     srcname = SINGLE_KERNEL_STAGES[dom]
-    if dom == "spectral" and pruned_transforms(B.resolve_params(B.params_for(fs))):
+    if dom == "spectral" and pruned_transforms(rp):
         srcname = "fft.hip"         # the spectral operator runs inside the z transform
     src = os.path.join(ROOT, "paper_2406_07366_amd", "csrc", srcname)
     traffic = read_traffic(os.path.join(ROOT, "profiles",
-                                        f"pmc_{dom}_{fs.name}_{args.precision}.txt"), src)
+                                        f"pmc_{dom}_{fs.name}_{'mixed' if fp32 else 'fp64'}.txt"),
+                           src)
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"],
                 "peak": d["peak"], "unit": d["unit"], "frac": d["achieved"] / d["peak"],
                 "traffic": traffic}
@@ -393,27 +362,39 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle baseline ...")
-        cpu = cpu_baseline(fs, B.resolve_params(B.params_for(fs)))
+        if N > 300_000:
+            cpu = cpu_baseline_sampled(fs)
+        else:
+            cpu = cpu_baseline(fs, rp)
         log(f"[bench] cpu baseline {cpu['value']:.4g} nodes/s on {cpu['cores']} threads")
 
+    def leg_summary(r):
+        return {"nodes_per_s": N / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+                "rel_l2_err": r["err"], "max_err_over_rms": r["errmax"], "tol": r["tol"],
+                "meets_tol": r["err"] <= r["tol"],
+                "dtype": "f32+f64" if r["precision"] == B.BS_FP32_MIXED else "f64",
+                "ns_mode": ["off", "adaptive", "learned"][r["ns_mode"]],
+                "ns_pairs": r["ns_pairs"], "ns_fallback": r["ns_fallback"]}
+
     value = N / (primary["ms"] * 1e-3)
-    other = "mixed" if args.precision == "fp64" else "fp64"
+    cfg = {"workload": f"{fs.name}: {fs.n_fil} filaments, N={N}, grid {fs.grid_n}^3, "
+                       f"Q={prm['Q']}, w={prm['w']}, beta={prm['beta']}, tol {primary['tol']:g}",
+           "rel_l2_err": primary["err"], "max_err_over_rms": primary["errmax"],
+           "meets_tol": primary["err"] <= primary["tol"],
+           "ns_mode": ["off", "adaptive", "learned"][primary["ns_mode"]],
+           "ns_pairs": primary["ns_pairs"]}
+    others = [n for n in results if n != pname]
+    if others:
+        cfg["other_precision"] = dict(name=others[0], **leg_summary(results[others[0]]))
     line = {
         "metric": "filament nodes/s per velocity eval at rel. L2 err <= 1e-6 vs FP64 oracle; "
                   "FP32+MLP vs plain",
         "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": primary["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{fs.name}: {fs.n_fil} filaments, N={N}, grid {fs.grid_n}^3, "
-                               f"tol {fs.tol:g}, Q={prm['Q']}, w={prm['w']}, "
-                               f"beta={prm['beta']}",
-                   "rel_l2_err": primary["err"],
-                   "ns_mode": primary["ns_mode"],
-                   "other_precision": {"name": other, "nodes_per_s": N / (results[other]["ms"] * 1e-3),
-                                       "rel_l2_err": results[other]["err"],
-                                       "ns_mode": results[other]["ns_mode"]}},
+        "config": cfg,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -421,9 +402,10 @@ def main():
         os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
         with open(args.detail, "w") as f:
             json.dump({"line": line, "roofline_all": roof_all,
+                       "legs": {k: leg_summary(v) for k, v in results.items()},
                        "stages": {k: v["stages"] for k, v in results.items()},
-                       "params": {k: v["prm"] for k, v in results.items()},
-                       "pairs": npairs}, f, indent=1, default=float)
+                       "params": {k: v["prm"] for k, v in results.items()}},
+                      f, indent=1, default=float)
     for r in results.values():
         r["plan"].close()
     print(json.dumps(line), flush=True)

@@ -7,6 +7,11 @@ run from the repository root:  python tests/golden/make_references.py [names]
   ref_tangle.npz     velocities at 256 sampled nodes of the 1e5-node tangle
   ref_ringpairs.npz  velocities (with exact near-singular segment integrals)
                      at 256 sampled nodes of the ring-pair workload
+  ref_bigtangle.npz  velocities (with exact near-singular segment integrals)
+                     at 512 sampled nodes of the 1e6-node tangle: 256 drawn
+                     uniformly, 256 among the nodes that have a node of
+                     another filament within 0.05 (where near-singular pairs
+                     occur)
   ref_bigtangle_subset_energy.npz
                      energy after each of 10 RK4 steps of the first 100
                      filaments of the 1e6-node tangle (dt = Kelvin period of
@@ -66,6 +71,29 @@ def ringpairs():
     np.savez(os.path.join(HERE, "ref_ringpairs.npz"), idx=idx, v=v)
 
 
+def close_nodes(fs, radius=0.05):
+    """Nodes with a node of another filament within radius (minimum image):
+    input selection only, by a k-d tree over the node positions."""
+    from scipy.spatial import cKDTree
+    fil = np.repeat(np.arange(fs.n_fil), np.diff(fs.offsets))
+    x = np.mod(fs.xyz, fs.L) % fs.L
+    tree = cKDTree(x, boxsize=fs.L)
+    pairs = tree.query_pairs(radius, output_type="ndarray")
+    other = pairs[fil[pairs[:, 0]] != fil[pairs[:, 1]]]
+    return np.unique(other.ravel())
+
+
+def bigtangle():
+    fs = W.bigtangle()
+    uni = sample_idx(fs.n_nodes)
+    close = close_nodes(fs)
+    rng = np.random.default_rng(1)
+    near = np.sort(rng.choice(np.setdiff1d(close, uni), 256, replace=False))
+    idx = np.concatenate([uni, near])
+    v, _ = O.Oracle(fs).reference(targets=idx, beta=6.0, psi=False, ns_eta=1.0)
+    np.savez(os.path.join(HERE, "ref_bigtangle.npz"), idx=idx, v=v, n_uniform=len(uni))
+
+
 def bigtangle_subset_energy(steps=10):
     full = W.bigtangle()
     dt = kelvin_period(min_chord(full), full.a)
@@ -98,7 +126,7 @@ def bigtangle_subset_energy(steps=10):
 
 
 JOBS = {"ellipses": ellipses, "tangle": tangle, "ringpairs": ringpairs,
-        "bigtangle_subset_energy": bigtangle_subset_energy}
+        "bigtangle": bigtangle, "bigtangle_subset_energy": bigtangle_subset_energy}
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(JOBS)):

@@ -1,0 +1,157 @@
+"""Full-size large tangle (10000 random Fourier curves, N = 1e6 nodes, grid
+512^3) against the oracle's stored reference velocities (beta = 6, exact
+near-singular segment integrals) at 512 sampled nodes: 256 drawn uniformly
+and 256 among the nodes near another filament (tests/golden/make_references.py).
+
+Two legs, the metric's rel. l2 error (Sec. 5.1, eq:def_relative_errors) and
+the largest per-node error relative to the rms reference velocity:
+  * plain: every step in float64, near-singular pairs by the adaptive
+    integrator, parameters of tolerance 1e-6: rel. l2 <= 1e-6;
+  * mixed + learned: float32 spread, transforms, interpolation and pairs,
+    near-singular pairs by the trained network with its fallback, tolerance
+    1e-5: rel. l2 <= 1e-5.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2406_07366_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_07366_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def case(B):
+    fs = W.bigtangle()
+    gold = np.load(os.path.join(GOLDEN, "ref_bigtangle.npz"))
+    xyz, g = B.load_workload(fs)
+    return fs, gold, xyz, g
+
+
+def errors(v, gold):
+    idx, ref = gold["idx"], gold["v"]
+    d = v[idx] - ref
+    vrms = math.sqrt((ref ** 2).sum(1).mean())
+    rel = math.sqrt((d ** 2).sum(1).mean()) / vrms
+    nu = int(gold["n_uniform"])
+    rel_u = math.sqrt((d[:nu] ** 2).sum(1).mean() / (ref[:nu] ** 2).sum(1).mean())
+    rel_n = math.sqrt((d[nu:] ** 2).sum(1).mean() / (ref[nu:] ** 2).sum(1).mean())
+    mx = float(np.sqrt((d ** 2).sum(1)).max() / vrms)
+    return rel, rel_u, rel_n, mx
+
+
+def run(B, fs, xyz, g, **kw):
+    import torch
+    mlp = kw.pop("mlp", None)
+    plan = B.Plan(B.params_for(fs, **kw))
+    if mlp is not None:
+        plan.set_mlp(*mlp)
+    plan.set_filaments(fs.offsets, xyz, g)
+    out = torch.empty((fs.n_nodes, 3), dtype=torch.float64, device="cuda")
+    plan.velocity(out)
+    plan.status()
+    counts = plan.ns_counts()
+    v = out.cpu().numpy()
+    plan.close()
+    return v, counts
+
+
+def test_bigtangle_plain_fp64(B, case):
+    fs, gold, xyz, g = case
+    fs.tol = 1e-6
+    print(f"\n[case] bigtangle N={fs.n_nodes} grid {fs.grid_n}^3 fp64 + adaptive, tol 1e-6",
+          flush=True)
+    v, (npairs, nfb) = run(B, fs, xyz, g, precision=B.BS_FP64, ns_mode=B.BS_NS_ADAPTIVE)
+    rel, ru, rn, mx = errors(v, gold)
+    print(f"  rel_l2 {rel:.3e} (uniform {ru:.3e}, near {rn:.3e}), max/rms {mx:.3e}, "
+          f"ns pairs {npairs}")
+    assert rel <= 1e-6 and ru <= 1e-6 and rn <= 1e-6
+    assert mx <= 5e-6
+
+
+def test_bigtangle_mixed_learned(B, case):
+    from paper_2406_07366_amd import ns_mlp
+    fs, gold, xyz, g = case
+    fs.tol = 1e-5
+    print(f"\n[case] bigtangle N={fs.n_nodes} grid {fs.grid_n}^3 mixed + learned, tol 1e-5",
+          flush=True)
+    mlp, table, _ = ns_mlp.train(n_train=1_000_000, n_val=100_000, epochs=40, batch=8192)
+    v, (npairs, nfb) = run(B, fs, xyz, g, precision=B.BS_FP32_MIXED, ns_mode=B.BS_NS_MLP,
+                           mlp=(mlp, table))
+    rel, ru, rn, mx = errors(v, gold)
+    print(f"  rel_l2 {rel:.3e} (uniform {ru:.3e}, near {rn:.3e}), max/rms {mx:.3e}, "
+          f"ns pairs {npairs}, fallback {nfb} ({nfb / max(npairs, 1):.1%})")
+    assert rel <= 1e-5 and ru <= 1e-5 and rn <= 1e-5
+    assert mx <= 5e-5
+
+
+EULER_GAMMA = 0.5772156649015329
+
+
+def kelvin_period(lam, a, delta=0.25, kappa=1.0):
+    """T_kw(lambda) of Sec. 5.2; the RK4 step is dt = T_kw(l_min)."""
+    return 2 * lam ** 2 / kappa / (math.log(lam / (math.pi * a)) + 0.5 - (delta + EULER_GAMMA))
+
+
+def test_bigtangle_subset_energy_drift(B):
+    """The first 100 filaments of the large tangle (1e4 nodes, grid 128^3,
+    mixed + learned, tolerance 1e-5) advanced by 10 RK4 steps with the whole
+    tangle's time step, Delta t = T_kw(l_min) (Sec. 5.2): the energy after
+    every step (eq:kinetic_energy_streamfunction) against the oracle's
+    energies of the same run (beta = 6, exact near-singular integrals),
+    and the two drifts E(t)/E(0) - 1 against each other."""
+    import torch
+    from paper_2406_07366_amd import ns_mlp
+    full = W.bigtangle()
+    nxt = np.arange(full.n_nodes) + 1
+    nxt[full.offsets[1:] - 1] = full.offsets[:-1]
+    lmin = float(np.linalg.norm(full.xyz[nxt] - full.xyz, axis=1).min())
+    dt = kelvin_period(lmin, full.a)
+    gold = np.load(os.path.join(GOLDEN, "ref_bigtangle_subset_energy.npz"))
+    assert abs(float(gold["dt"]) - dt) <= 1e-12 * dt
+    fs = full.subset(100)
+    fs.grid_n = 128
+    print(f"\n[case] bigtangle subset N={fs.n_nodes} grid 128^3 RK4 x10 dt={dt:.3e}", flush=True)
+    mlp, table, _ = ns_mlp.train(n_train=1_000_000, n_val=100_000, epochs=40, batch=8192)
+    plan = B.Plan(B.params_for(fs, precision=B.BS_FP32_MIXED, ns_mode=B.BS_NS_MLP))
+    plan.set_mlp(mlp, table)
+    xyz, g = B.load_workload(fs)
+    plan.set_filaments(fs.offsets, xyz, g)
+    E = [plan.energy(want_psi=False)[0]]
+    for _ in range(10):
+        plan.rk4_step(fs.offsets, xyz, g, dt)
+        plan.set_filaments(fs.offsets, xyz, g)
+        E.append(plan.energy(want_psi=False)[0])
+    plan.status()
+    torch.cuda.synchronize()
+    E = np.array(E)
+    Eo = gold["E"]
+    rel = np.abs(E - Eo) / np.abs(Eo)
+    dg, do = E / E[0] - 1, Eo / Eo[0] - 1
+    print("  |E - E_oracle| / E_oracle: " + " ".join(f"{r:.1e}" for r in rel))
+    print("  drift gpu    " + " ".join(f"{r:.2e}" for r in dg))
+    print("  drift oracle " + " ".join(f"{r:.2e}" for r in do))
+    # energy to the plan's tolerance at every step; the drifts agree to a
+    # small fraction of their size
+    assert rel.max() <= 1e-5
+    assert np.abs(dg - do).max() <= 3e-2 * np.abs(do).max() + 1e-9
+    # final positions against the oracle's: the displacement over the 10
+    # steps to 10 x the velocity tolerance
+    xf = xyz.cpu().numpy()
+    dx = np.linalg.norm(xf - gold["x_final"], axis=1).max()
+    disp = np.linalg.norm(gold["x_final"] - fs.xyz, axis=1).max()
+    print(f"  max |x_gpu - x_oracle| after 10 steps: {dx:.2e} (largest displacement {disp:.2e})")
+    assert dx <= 1e-4 * disp
+    plan.close()
