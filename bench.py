@@ -8,13 +8,15 @@ velocities, on one MI355X.
 
 Default workload: the large random Fourier tangle (10000 curves x 100 nodes,
 N = 1e6, grid 512^3), the largest single-GPU configuration.  Two legs:
-  plain   every step in float64, near-singular pairs by the adaptive
+  plain   every step in float64, near-singular pairs by the graded-panel
           integrator, parameters of tolerance 1e-6 (the metric's accuracy
           bar: rel. l2 error <= 1e-6 against the FP64 CPU oracle) -> "value";
   learned float32 spread, transforms, interpolation and pairs, near-singular
           pairs by the trained network (trained here, on the GPU, by the
-          library's own kernels) with its adaptive fallback, tolerance 1e-5
-          (bar 1e-5) -> "config.other_precision".
+          library's own kernels) where its error indicator allows, else the
+          graded panels, tolerance 1e-5 (bar 1e-5) -> "config.other_precision".
+--legs mapped,mixed adds FP64 with the fixed-cost mapped rule and FP32 with
+the graded panels alone (no network).
 Errors are taken at the nodes of the oracle's stored reference (sampled on
 large workloads).  Other workloads: --workload ellipses | tangle | ringpairs.
 
@@ -220,13 +222,19 @@ def cpu_baseline_sampled(fs, n_targets=384, seed=0):
                       f"N / (fixed + N * per-node)"}
 
 
-# per workload: the legs (name, precision, near-singular mode, tolerance)
+# per workload: the legs (name, precision, near-singular mode, tolerance);
+# the first two run by default, the others when named by --legs
 def legs_for(name, B):
     if name in ("bigtangle", "ringpairs"):
         return [("plain", B.BS_FP64, B.BS_NS_ADAPTIVE, 1e-6),
-                ("learned", B.BS_FP32_MIXED, B.BS_NS_MLP, 1e-5)]
+                ("learned", B.BS_FP32_MIXED, B.BS_NS_MLP, 1e-5),
+                ("mapped", B.BS_FP64, B.BS_NS_MAPPED, 1e-6),
+                ("mixed", B.BS_FP32_MIXED, B.BS_NS_ADAPTIVE, 1e-5)]
     return [("plain", B.BS_FP64, B.BS_NS_OFF, 1e-6),
             ("mixed", B.BS_FP32_MIXED, B.BS_NS_OFF, 1e-5)]
+
+
+NS_NAMES = ["off", "adaptive", "learned", "mapped"]
 
 
 def errors(v, gold):
@@ -285,6 +293,8 @@ def main():
     if args.legs:
         keep = args.legs.split(",")
         legs = [l for l in legs if l[0] in keep]
+    else:
+        legs = legs[:2]
     mlp = table = None
     if any(l[2] == B.BS_NS_MLP for l in legs):
         from paper_2406_07366_amd import ns_mlp
@@ -309,7 +319,8 @@ def main():
         npairs, nfb = plan.ns_counts() if ns_mode != B.BS_NS_OFF else (0, 0)
         log(f"[bench] {name} (prec {prec}, ns_mode {ns_mode}, tol {tol:g}): {ms_host:.4f} ms/step "
             f"(events {ms_ev:.4f}), rel_l2 {err:.3e} (max/rms {errmax:.2e}), "
-            f"{N / ms_host * 1e3:.4g} nodes/s, ns pairs {npairs} fallback {nfb}")
+            f"{N / ms_host * 1e3:.4g} nodes/s, ns pairs {npairs}"
+            + (f", by network {npairs - nfb}" if ns_mode == B.BS_NS_MLP else ""))
         log("[bench]   stages (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in st.items()))
         results[name] = dict(ms=ms_host, ms_events=ms_ev, err=err, errmax=errmax, stages=st,
                              prm=prm.as_dict(), plan=plan, ns_mode=ns_mode, tol=tol,
@@ -373,19 +384,23 @@ def main():
                 "rel_l2_err": r["err"], "max_err_over_rms": r["errmax"], "tol": r["tol"],
                 "meets_tol": r["err"] <= r["tol"],
                 "dtype": "f32+f64" if r["precision"] == B.BS_FP32_MIXED else "f64",
-                "ns_mode": ["off", "adaptive", "learned"][r["ns_mode"]],
-                "ns_pairs": r["ns_pairs"], "ns_fallback": r["ns_fallback"]}
+                "ns_mode": NS_NAMES[r["ns_mode"]],
+                "ns_pairs": r["ns_pairs"],
+                "ns_by_network": (r["ns_pairs"] - r["ns_fallback"]
+                                  if r["ns_mode"] == B.BS_NS_MLP else 0)}
 
     value = N / (primary["ms"] * 1e-3)
     cfg = {"workload": f"{fs.name}: {fs.n_fil} filaments, N={N}, grid {fs.grid_n}^3, "
                        f"Q={prm['Q']}, w={prm['w']}, beta={prm['beta']}, tol {primary['tol']:g}",
            "rel_l2_err": primary["err"], "max_err_over_rms": primary["errmax"],
            "meets_tol": primary["err"] <= primary["tol"],
-           "ns_mode": ["off", "adaptive", "learned"][primary["ns_mode"]],
+           "ns_mode": NS_NAMES[primary["ns_mode"]],
            "ns_pairs": primary["ns_pairs"]}
     others = [n for n in results if n != pname]
     if others:
         cfg["other_precision"] = dict(name=others[0], **leg_summary(results[others[0]]))
+    for extra in others[1:]:
+        cfg[f"leg_{extra}"] = leg_summary(results[extra])
     line = {
         "metric": "filament nodes/s per velocity eval at rel. L2 err <= 1e-6 vs FP64 oracle; "
                   "FP32+MLP vs plain",

@@ -69,8 +69,14 @@ extern "C" {
 /* near-singular treatment of (node, segment) pairs closer than
  * ns_eta * segment length (not part of the paper; see bs_velocity) */
 #define BS_NS_OFF       0
-#define BS_NS_ADAPTIVE  1  /* graded Gauss-Legendre panels on the spline segment */
-#define BS_NS_MLP       2  /* learned correction with adaptive fallback       */
+#define BS_NS_ADAPTIVE  1  /* graded Gauss-Legendre panels on the spline segment
+                              (converged to rounding; the reference integrator) */
+#define BS_NS_MLP       2  /* learned correction where its error indicator
+                              allows, else the graded panels (bs_set_mlp)      */
+#define BS_NS_MAPPED    3  /* fixed-cost rule: sinh-mapped 2 x 16-point
+                              Gauss-Legendre split at the closest point, with
+                              the tangent segment's closed form as a control
+                              variate                                        */
 
 /* 3-D transforms of the long-range step */
 #define BS_FFT_AUTO     0  /* BS_FFT_PRUNED for power-of-two grids from 64 up
@@ -114,13 +120,11 @@ typedef struct {
     int    Q;            /* Gauss-Legendre points per segment, 1..4 (0: 2)     */
     int    spline_order; /* 4 = cubic, 6 = quintic (App. B; 0: 4)              */
     int    precision;    /* BS_FP64 or BS_FP32_MIXED                           */
-    int    ns_mode;      /* BS_NS_OFF, BS_NS_ADAPTIVE or BS_NS_MLP (the
-                            network is trained on cubic segments: BS_NS_MLP
-                            needs spline_order 4)                           */
+    int    ns_mode;      /* BS_NS_OFF, BS_NS_ADAPTIVE, BS_NS_MLP or
+                            BS_NS_MAPPED (the network is trained on cubic
+                            segments: BS_NS_MLP needs spline_order 4; its
+                            network is attached by bs_set_mlp)              */
     double ns_eta;       /* flag pairs with chord distance < ns_eta * ell (0: 1) */
-    const void *mlp_weights; /* host pointer to the packed float32 MLP
-                                parameters (see bs_mlp_nparams); needed for
-                                BS_NS_MLP; copied by bs_plan                   */
     int    fft_mode;     /* BS_FFT_AUTO, BS_FFT_LIBRARY or BS_FFT_PRUNED; the
                             resolved parameters hold the choice made for
                             BS_FFT_AUTO                                     */
@@ -144,13 +148,24 @@ typedef struct {
  * rcut would exceed L/2), BS_EKB. */
 int bs_resolve_params(const bs_params *p, bs_params *out);
 
-/* Create a plan on the current HIP device.  hip_stream is a hipStream_t
- * (NULL = the null stream); every later call enqueues on it.  Allocates
- * the grids and builds the FFT plans.  *out receives the handle (NULL on
- * error).  Errors as bs_resolve_params, plus BS_ENOMEM, BS_EDEVICE. */
+/* Create a plan on the current HIP device for one box period L, core a and
+ * Delta (Sec. 2.3, eq:BS_local), Ewald parameters alpha, r_c (Sec. 3,
+ * eq:ewald_velocity_splitting; Sec. 4 for beta) and NUFFT parameters sigma,
+ * w (Sec. 3.3, App. A, Table 1), after bs_resolve_params' derivation.
+ *   p           parameters (read during the call, not kept);
+ *   hip_stream  a hipStream_t (NULL = the null stream); every later call
+ *               enqueues on it;
+ *   out         receives the handle (NULL on error).
+ * Allocates the grids (3 [n]^3 reals and their spectra) and builds the FFT
+ * plans; the plan owns them until bs_destroy.  Errors as
+ * bs_resolve_params, plus BS_ENOMEM, BS_EDEVICE. */
 int bs_plan(const bs_params *p, void *hip_stream, bs_plan_t *out);
 
-/* Load a filament set.
+/* Load a filament set: closed oriented curves through ordered nodes
+ * (Sec. 2.1) with one circulation each (Sec. 2.2, eq:BS), interpolated by
+ * the periodic spline on chord-length knots (App. B) and discretised by Q
+ * Gauss-Legendre points per segment (Sec. 2.7,
+ * eq:line_integral_quadrature).
  *   nfil     number of filaments (>= 1; closed unless bs_set_periods
  *            says otherwise);
  *   offsets  HOST int64 [nfil+1], offsets[0] = 0, filament l owns nodes
@@ -188,11 +203,18 @@ int bs_set_filaments(bs_plan_t plan, int64_t nfil, const int64_t *offsets,
 int bs_set_periods(bs_plan_t plan, int64_t nfil, const int64_t *periods);
 
 /* Velocity at every node: v_out DEVICE float64 [N][3] (overwritten).
- * v = v_local + v_short + v_long - v_self, plus, when ns_mode is not
- * BS_NS_OFF, the near-singular correction: for every non-adjacent segment
- * whose chord lies closer than ns_eta * (segment length) to the node, the
- * Q-point sum of that segment is replaced by its exact integral of the full
- * Biot-Savart kernel.  At most 64 such segments per node are kept: a node
+ * v = v_local + v_short + v_long - v_self (Sec. 3,
+ * eq:ewald_velocity_splitting): the local term eq:BS_local, the short-range
+ * sum eq:velocity_shortrange within r_c (minimum image), the long-range term
+ * from the vorticity's Fourier coefficients eq:vorticity_fourier_coefs
+ * through eq:velocity_longrange_physical (type-1 NUFFT, Gaussian-filtered
+ * i k x / k^2, type-2 NUFFT; Sec. 3.3, App. A) and the self correction
+ * eq:velocity_longrange_self.  Plus, when ns_mode is not BS_NS_OFF, the
+ * near-singular correction (not in the paper): for every non-adjacent
+ * segment whose chord lies closer than ns_eta * (segment length) to the
+ * node, the Q-point sum of that segment is replaced by its integral of the
+ * full Biot-Savart kernel (exact to rounding with BS_NS_ADAPTIVE; the mapped
+ * rule's or the network's value with BS_NS_MAPPED, BS_NS_MLP).  At most 64 such segments per node are kept: a node
  * with more is reported by bs_status (BS_EINVAL).  BS_ESTATE if no
  * filaments were set (or BS_NS_MLP without bs_set_mlp).  The short-range
  * and near-singular terms run on a second stream that the plan owns, forked
@@ -206,9 +228,14 @@ int bs_velocity(bs_plan_t plan, double *v_out);
 int bs_velocity_terms(bs_plan_t plan, double *v_local, double *v_short,
                       double *v_long, double *v_self, double *v_ns);
 
-/* Streamfunction at every node (psi_out DEVICE [N][3], or NULL) and the
- * kinetic energy per unit density E (HOST double).  Synchronises the plan
- * stream.  BS_ESTATE if no filaments were set. */
+/* Streamfunction at every node (psi_out DEVICE [N][3], or NULL;
+ * eq:ewald_streamfunction_splitting with eq:streamfunction_local,
+ * eq:streamfunction_shortrange, the long-range streamfunction and
+ * eq:streamfunction_longrange_self) and the kinetic energy per unit density
+ * E = (1/2V) sum_l Gamma_l oint psi . ds (eq:kinetic_energy_streamfunction),
+ * written to *E_out (HOST double, may be NULL); psi between the nodes is the
+ * spline through its nodal values, integrated by the curve's Q-point rule.
+ * Synchronises the plan stream.  BS_ESTATE if no filaments were set. */
 int bs_energy(bs_plan_t plan, double *E_out, double *psi_out);
 
 /* Fourier coefficients of the vorticity recovered from the spread grid
@@ -316,17 +343,36 @@ int bs_ns_samples(int64_t n, const double *U, float *X, float *T, double *aux,
                   void *hip_stream);
 /* range [lo, hi] of (distance to the chord)/h covered by the network, and
  * the number of log-spaced bins of its error table (binned by the distance
- * to the curve over h, values below lo falling in the first bin) */
+ * to the chord over h, values outside [lo, hi] falling in the end bins) */
 int bs_ns_error_bins(double *lo, double *hi, int *nbins);
-/* Attach a trained network to a BS_NS_MLP plan.  err_table[nbins] is the
- * largest relative error of the learned segment integral seen on held-out
- * samples in each log10(d/h) bin; pairs in bins whose error exceeds the
- * plan's tol, or outside the sample box, use the adaptive integrator.  The
- * plan keeps the pointer: the network must outlive its use by the plan. */
+/* Error table of a trained network on held-out samples of bs_ns_samples
+ * (X, T DEVICE float32 [n][8], [n][3]; aux DEVICE float64 [n][7], as
+ * written by bs_ns_samples; n >= 1): per distance bin (bs_ns_error_bins),
+ * the root-mean-square (rms_out) and largest (max_out) error of the learned
+ * raw segment integral |I_tan + m y - I| in units of the chord length
+ * (h = 1), I the plain method's graded-panel integral; HOST float [nbins]
+ * each (either may be NULL); +inf in a bin without samples.  Runs on the
+ * network's stream and synchronises it; allocates and frees a scratch of
+ * 12 n bytes.  Errors: BS_EINVAL (sizes, nbins), BS_ENOMEM, BS_EDEVICE. */
+int bs_ns_error_table(bs_mlp_t mlp, int64_t n, const float *X, const float *T,
+                      const double *aux, float *rms_out, float *max_out, int nbins);
+/* Attach a trained network to a BS_NS_MLP plan.  err_table[nbins] holds the
+ * rms error per distance bin (bs_ns_error_table's rms_out).  A pair (node
+ * i, segment of length h, circulation Gamma) takes the learned integral
+ * when its inputs lie in the sample box and
+ *     err_table[bin] * |Gamma| / (4 pi h) * sqrt(P / N) <= tol * v_scale,
+ * P the flagged pairs of the N nodes and v_scale the rms over the nodes of
+ * the velocity's local, self and short-range terms (formed before the
+ * correction): the pairs' errors then add to at most about tol times the rms
+ * velocity.  Every other pair takes the graded panels (BS_NS_ADAPTIVE).  The
+ * table is copied; the plan keeps the network handle, which must outlive
+ * its use by the plan.  Drops a recorded bs_step graph.  Errors: BS_ESTATE
+ * (plan not BS_NS_MLP), BS_EINVAL (null network, nbins, negative entry). */
 int bs_set_mlp(bs_plan_t plan, bs_mlp_t mlp, const float *err_table, int nbins);
 /* Synchronise; number of flagged near-singular pairs of the loaded
- * filaments, and number of those the learned path handed to the adaptive
- * integrator in the last velocity evaluation (0 if none ran). */
+ * filaments, and number of those the learned path handed to the graded
+ * panels in the last velocity evaluation (0 if none ran; the network carried
+ * the rest). */
 int bs_ns_counts(bs_plan_t plan, int64_t *npairs, int64_t *nfallback);
 
 /* Parameters actually used (all derived fields filled). */

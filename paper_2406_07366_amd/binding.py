@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbs.so")
 BS_OK, BS_EINVAL, BS_EMINIMG, BS_ETOL, BS_EKB, BS_ENOMEM, BS_EDEVICE, BS_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
 BS_FP64, BS_FP32_MIXED = 0, 1
-BS_NS_OFF, BS_NS_ADAPTIVE, BS_NS_MLP = 0, 1, 2
+BS_NS_OFF, BS_NS_ADAPTIVE, BS_NS_MLP, BS_NS_MAPPED = 0, 1, 2, 3
 BS_FFT_AUTO, BS_FFT_LIBRARY, BS_FFT_PRUNED = 0, 1, 2
 
 _CODES = {0: "BS_OK", -1: "BS_EINVAL", -2: "BS_EMINIMG", -3: "BS_ETOL", -4: "BS_EKB",
@@ -30,7 +30,8 @@ EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_set_periods"
             "bs_status", "bs_set_profiling", "bs_stage_times", "bs_get_params",
             "bs_destroy", "bs_last_error", "bs_mlp_nparams", "bs_mlp_create",
             "bs_mlp_forward", "bs_mlp_loss_grad", "bs_mlp_adam_step", "bs_mlp_get_params",
-            "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_set_mlp", "bs_ns_counts", "bs_rk4_step", "bs_step", "bs_set_graph",
+            "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_ns_error_table",
+            "bs_set_mlp", "bs_ns_counts", "bs_rk4_step", "bs_step", "bs_set_graph",
             "bs_graph_active"]
 
 NSTAGES = 11
@@ -44,13 +45,13 @@ class BsParams(C.Structure):
                 ("rcut", C.c_double), ("grid_n", C.c_int), ("sigma", C.c_double),
                 ("w", C.c_int), ("Q", C.c_int), ("spline_order", C.c_int),
                 ("precision", C.c_int), ("ns_mode", C.c_int), ("ns_eta", C.c_double),
-                ("mlp_weights", C.c_void_p), ("fft_mode", C.c_int),
+                ("fft_mode", C.c_int),
                 ("local_frac", C.c_double), ("K", C.c_int),
                 ("ncell", C.c_int),
                 ("zeta", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "mlp_weights"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class BsError(RuntimeError):
@@ -97,6 +98,7 @@ _lib.bs_mlp_get_params.argtypes = [_vp, _vp]
 _lib.bs_mlp_destroy.argtypes = [_vp]
 _lib.bs_ns_samples.argtypes = [C.c_int64, _vp, _vp, _vp, _vp, _vp]
 _lib.bs_ns_error_bins.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
+_lib.bs_ns_error_table.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_int]
 _lib.bs_set_mlp.argtypes = [_vp, _vp, _vp, C.c_int]
 _lib.bs_ns_counts.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
 _lib.bs_rk4_step.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int64), _vp, _vp, C.c_double]
@@ -124,7 +126,6 @@ def make_params(L, a, tol, grid_n, delta=0.25, beta=0.0, alpha=0.0, rcut=0.0, si
     p.grid_n, p.sigma, p.w, p.Q = grid_n, sigma, w, Q
     p.spline_order = spline_order
     p.precision, p.ns_mode, p.ns_eta = precision, ns_mode, ns_eta
-    p.mlp_weights = None
     p.fft_mode = fft_mode
     p.local_frac = local_frac
     return p
@@ -379,6 +380,19 @@ def ns_error_bins():
     lo, hi, nb = C.c_double(), C.c_double(), C.c_int()
     _check(_lib.bs_ns_error_bins(C.byref(lo), C.byref(hi), C.byref(nb)))
     return lo.value, hi.value, nb.value
+
+
+def ns_error_table(mlp, X, T, A):
+    """Per distance bin, rms and max error of the learned raw segment
+    integral on samples (X, T, A) of ns_samples (computed by the library)."""
+    _, _, nb = ns_error_bins()
+    rms = np.zeros(nb, dtype=np.float32)
+    mx = np.zeros(nb, dtype=np.float32)
+    X, T = mlp._f32(X), mlp._f32(T)
+    assert A.is_cuda and A.dtype == mlp._torch.float64 and A.is_contiguous()
+    _check(_lib.bs_ns_error_table(mlp._h, X.shape[0], _ptr(X), _ptr(T), _ptr(A),
+                                  rms.ctypes.data_as(_vp), mx.ctypes.data_as(_vp), nb))
+    return rms, mx
 
 
 def ns_samples(U, aux=True):

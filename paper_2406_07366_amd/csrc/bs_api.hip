@@ -176,7 +176,7 @@ int resolve(const bs_params *in, bs_params *out) {
     if (r.local_frac > 0.0 && r.local_frac < 1e-3)
         return bad("local_frac below 1e-3 (more than 10 panels per local segment)");
     if (r.precision != BS_FP64 && r.precision != BS_FP32_MIXED) return bad("unknown precision");
-    if (r.ns_mode < BS_NS_OFF || r.ns_mode > BS_NS_MLP) return bad("unknown ns_mode");
+    if (r.ns_mode < BS_NS_OFF || r.ns_mode > BS_NS_MAPPED) return bad("unknown ns_mode");
     if (r.ns_mode == BS_NS_MLP && r.spline_order != 4)
         return bad("the learned near-singular correction is trained on cubic segments only");
     if (r.ns_eta == 0) r.ns_eta = 1.0;
@@ -486,7 +486,8 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
                 return rc;
             if (P->prm.ns_mode == BS_NS_MLP &&
                 ((rc = ensure<float>(P, P->ns_X, 8 * mp)) || (rc = ensure<float>(P, P->ns_Y, 3 * mp)) ||
-                 (rc = ensure<int>(P, P->ns_fallback, 1))))
+                 (rc = ensure<int>(P, P->ns_fallback, 4)) || (rc = ensure<int>(P, P->ns_learn, mp)) ||
+                 (rc = ensure<int>(P, P->ns_fblist, mp)) || (rc = ensure<double>(P, P->ns_vs, 1 + 3 * 256))))
                 return rc;
         }
         // the bin counters start at zero; afterwards each call's per-bin
@@ -497,7 +498,10 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             (rc = check_hip(P, hipMemsetAsync(P->pq_cnt.p, 0, nb_c, P->stream), "memset")) ||
             (rc = check_hip(P, hipMemsetAsync(P->pq_fill.p, 0, nb_c, P->stream), "memset")) ||
             (rc = check_hip(P, hipMemsetAsync(P->nd_cnt.p, 0, nb_c, P->stream), "memset")) ||
-            (rc = check_hip(P, hipMemsetAsync(P->nd_fill.p, 0, nb_c, P->stream), "memset")))
+            (rc = check_hip(P, hipMemsetAsync(P->nd_fill.p, 0, nb_c, P->stream), "memset")) ||
+            (P->ns_fallback.p &&
+             (rc = check_hip(P, hipMemsetAsync(P->ns_fallback.p, 0, P->ns_fallback.bytes,
+                                               P->stream), "memset"))))
             return rc;
         std::vector<int> off32(nfil + 1), fil32(N);
         for (int64_t f = 0; f <= nfil; f++) off32[f] = (int)offsets[f];
@@ -548,13 +552,19 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     return BS_OK;
 }
 
-static int launch_ns(bs_plan_t P, double *out) {
+// out += near-singular correction; base: the velocity terms formed so far at
+// the nodes (the learned path's velocity scale is their rms)
+static int launch_ns(bs_plan_t P, double *out, const double *base) {
     if (P->prm.ns_mode == BS_NS_ADAPTIVE) {
         launch_ns_adaptive(P, out);
         return BS_OK;
     }
+    if (P->prm.ns_mode == BS_NS_MAPPED) {
+        launch_ns_mapped(P, out);
+        return BS_OK;
+    }
     if (!P->mlp) return set_error(P, BS_ESTATE, "BS_NS_MLP plan without bs_set_mlp");
-    launch_ns_mlp(P, out);
+    launch_ns_mlp(P, out, base);
     return BS_OK;
 }
 
@@ -624,7 +634,7 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     stage_end(P, 8);
     if (P->prm.ns_mode != BS_NS_OFF) {
         stage_begin(P, 9);
-        rc = launch_ns(P, t3);
+        rc = launch_ns(P, t3, t3);   // t3 = local - self + short so far
         stage_end(P, 9);
     }
     P->stream = plan_stream;
@@ -656,7 +666,9 @@ int bs_velocity_terms(bs_plan_t P, double *v_local, double *v_short, double *v_l
     }
     if (v_ns) {
         fill_f64(P, v_ns, n3, 0.0);
-        if (P->prm.ns_mode != BS_NS_OFF && (rc = launch_ns(P, v_ns))) return rc;
+        if (P->prm.ns_mode != BS_NS_OFF &&
+            (rc = launch_ns(P, v_ns, (const double *)P->d_vls.p)))
+            return rc;
     }
     return launch_status(P, "velocity terms");
 }
@@ -829,6 +841,11 @@ int bs_set_mlp(bs_plan_t P, bs_mlp_t mlp, const float *err_table, int nbins) {
     if (P->prm.ns_mode != BS_NS_MLP) return set_error(P, BS_ESTATE, "plan is not BS_NS_MLP");
     if (!mlp || !err_table || nbins != want)
         return set_error(P, BS_EINVAL, "need a network and an error table of bs_ns_error_bins bins");
+    for (int b = 0; b < nbins; b++)
+        if (!(err_table[b] >= 0.0f)) return set_error(P, BS_EINVAL, "error table entry < 0 or NaN");
+    // a recorded bs_step graph holds the previous network's buffers and the
+    // previous table in its kernel arguments
+    drop_graph(P);
     P->mlp = mlp;
     for (int b = 0; b < nbins; b++) P->ns_err[b] = err_table[b];
     return BS_OK;
@@ -842,11 +859,14 @@ int bs_ns_counts(bs_plan_t P, int64_t *npairs, int64_t *nfallback) {
         if ((rc = check_hip(P, hipMemcpyAsync(&np, (int *)P->ns_start.p + P->N, sizeof(int),
                                               hipMemcpyDeviceToHost, P->stream), "read count")))
             return rc;
+        int c4[4] = {0, 0, 0, 0};
         if (P->prm.ns_mode == BS_NS_MLP && P->ns_fallback.p &&
-            (rc = check_hip(P, hipMemcpyAsync(&nf, P->ns_fallback.p, sizeof(int),
+            (rc = check_hip(P, hipMemcpyAsync(c4, P->ns_fallback.p, sizeof(c4),
                                               hipMemcpyDeviceToHost, P->stream), "read count")))
             return rc;
         if ((rc = check_hip(P, hipStreamSynchronize(P->stream), "sync"))) return rc;
+        // the gate closed: every pair went to the plain integrator
+        if (P->prm.ns_mode == BS_NS_MLP) nf = c4[2] ? c4[1] : (c4[3] ? np : 0);
     }
     if (npairs) *npairs = np;
     if (nfallback) *nfallback = nf;
@@ -886,7 +906,8 @@ int bs_destroy(bs_plan_t P) {
                    &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_tkey, &P->ns_tcnt,
                    &P->ns_tstart, &P->ns_tfill, &P->ns_tperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_slots,
                    &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout,
-                   &P->ns_X, &P->ns_Y, &P->ns_fallback, &P->rk_k, &P->rk_s};
+                   &P->ns_X, &P->ns_Y, &P->ns_fallback, &P->ns_learn, &P->ns_fblist, &P->ns_vs, &P->rk_k,
+                   &P->rk_s};
     for (DBuf *b : all) release(*b);
     delete P;
     return BS_OK;

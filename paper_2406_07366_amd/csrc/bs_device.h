@@ -70,6 +70,15 @@ __device__ __forceinline__ int prev_node_d(const int *off, const int *fil, int j
 // maps them to the consecutive logical indices [xcd * per, (xcd + 1) * per),
 // so neighbouring logical blocks share an L2.  Indices >= the real count
 // must exit (uniformly over the block).
+// LDS written by some lanes of a wavefront and read by others of the same
+// wavefront: wait for the stores and keep the compiler from moving memory
+// operations across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int xcd_block(int per) {
     return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
 }

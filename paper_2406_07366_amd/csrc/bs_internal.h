@@ -114,7 +114,12 @@ struct bs_plan_s {
     // learned correction
     bs_mlp_t mlp = nullptr;
     float ns_err[16] = {};
-    bs::DBuf ns_X, ns_Y, ns_fallback;
+    bs::DBuf ns_X, ns_Y;                       // features, outputs of the learned pairs
+    bs::DBuf ns_fallback;                      // int32 [2]: learned pairs, plain-integrator pairs
+    bs::DBuf ns_learn;                         // int32 [pairs]: pairs the network takes
+    bs::DBuf ns_fblist;                        // int32 [pairs]: pairs the learned
+                                               // path hands to the graded panels
+    bs::DBuf ns_vs;                            // f64 [1 + blocks]: velocity scale
     // RK4 stage buffers
     bs::DBuf rk_k, rk_s;
     // graph replay of bs_step
@@ -189,13 +194,18 @@ void launch_pairs(bs_plan_t p, int psi, const double *base, double *out, bool al
 
 // ns.hip
 void ns_build_pairs(bs_plan_t p);
+// v += near-singular correction (graded panels / mapped rule / learned with
+// the graded panels where its indicator refuses; base: the array whose rms
+// over the nodes is the learned path's velocity scale)
 void launch_ns_adaptive(bs_plan_t p, double *v);
-void launch_ns_mlp(bs_plan_t p, double *v);
+void launch_ns_mapped(bs_plan_t p, double *v);
+void launch_ns_mlp(bs_plan_t p, double *v, const double *base);
 // mlp.hip: inference with the sample count read on the device
 void mlp_forward_device(bs_mlp_t m, const int *Bdev, int64_t Bmax, const float *X, float *Y,
                         hipStream_t stream);
+hipStream_t mlp_stream(bs_mlp_t m);
 
-// energy.hip
+// pairs.hip (with the short-range sums): the energy line integral
 void launch_energy(bs_plan_t p, const double *psi, double *partial, int nblocks);
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

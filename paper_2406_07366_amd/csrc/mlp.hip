@@ -469,6 +469,8 @@ struct bs_mlp_s {
 };
 
 namespace bs {
+hipStream_t mlp_stream(bs_mlp_t M) { return M->stream; }
+
 void mlp_forward_device(bs_mlp_t M, const int *Bdev, int64_t Bmax, const float *X, float *Y,
                         hipStream_t stream) {
     int64_t tiles = (Bmax + 15) / 16;

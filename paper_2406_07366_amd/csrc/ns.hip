@@ -7,16 +7,21 @@
 //   dv_i += (Gamma_j/4pi) int_seg (s - s_i) x ds / |s - s_i|^3  -  sum_Q(...)
 // (the same image of the segment as the chord test, minimum image).
 //
-// Passes (all deterministic, no host synchronisation):
-//   flag   one thread per node scans the quadrature points of the cells around
-//          it (the pair cell list), tests each segment's chord once (at the
-//          first of its quadrature points that lies in the scanned window),
-//          and counts (pass 0) or writes (pass 1) the flagged pairs in scan
-//          order into a per-node slice of the pair list;
-//   integrate  one thread per pair: closest point of the cubic segment to the
-//          target by Newton steps, then Gauss-Legendre panels graded
-//          geometrically (ratio 3) away from it, 16 points per panel, float64;
-//   apply  one thread per node adds its pairs' corrections in list order.
+// Passes (no host synchronisation):
+//   search  segments binned by chord midpoint, targets by node cell; one
+//           workgroup per target cell tests the window's segments and writes
+//           each node's flagged pairs in a fixed order; compacted pair list;
+//   integrate  one thread per pair, float64, by one of
+//           - graded panels: closest point of the segment to the target by
+//             Newton steps, 16-point Gauss-Legendre panels graded
+//             geometrically (ratio 3) away from it (converged to rounding);
+//           - the mapped rule: sinh-mapped 16-point rules on either side of
+//             the closest point, the tangent segment as a control variate
+//             (fixed cost);
+//           - the learned correction where its error indicator allows (the
+//             network runs only on those pairs), the graded panels elsewhere;
+//   apply   one thread per node adds its pairs' corrections in list order
+//           (deterministic whatever order the pairs were computed in).
 #include "bs_internal.h"
 #include "bs_device.h"
 
@@ -655,15 +660,19 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
     for (int q = 0; q < 3; q++) out[q] = g4 * acc[q] - qs[q] / (4.0 * kPi);
 }
 
+// every pair (list == nullptr, count = total pairs), or the pairs listed
 __global__ __launch_bounds__(256) void k_ns_integrate(
-    const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
-    const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ xn, const double *__restrict__ D, const double *__restrict__ S,
-    const double *__restrict__ dtau, const double *__restrict__ gamma,
-    const double *__restrict__ qpos, const double *__restrict__ qchg, int Q, double L, NsRule R,
-    double *__restrict__ pout) {
-    const int P = *total;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+    const int *__restrict__ count, const int *__restrict__ list, const int *__restrict__ pnode,
+    const int2 *__restrict__ pairs, const int *__restrict__ off, const int *__restrict__ fil,
+    const double *__restrict__ x, const double *__restrict__ xn, const double *__restrict__ D,
+    const double *__restrict__ S, const double *__restrict__ dtau,
+    const double *__restrict__ gamma, const double *__restrict__ qpos,
+    const double *__restrict__ qchg, int Q, double L, NsRule R, double *__restrict__ pout,
+    const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const int P = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        const int p = list ? list[i] : i;
         int2 pr = pairs[p];
         double out[3];
         ns_pair(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg, Q, L, R,
@@ -708,9 +717,17 @@ constexpr double kNsDmin = 0.9, kNsDmax = 1.1;   // |D0|, |D1| range
 constexpr double kNsRlo = 1e-3, kNsRhi = 1.1;    // d_c / h range
 constexpr int kNsBins = 12;                      // log10(d_c/h) bins of the error table
 
+// Error indicator of the learned integral: err[b] is the root-mean-square
+// error (raw integral, chord length h = 1) of the learned segment integral on
+// held-out samples whose distance to the chord falls in bin b, measured
+// against the plain method's graded-panel integrals (bs_ns_error_table).  A
+// pair takes the network when err[b] |Gamma| / (4 pi h) sqrt(P / N) <= tol *
+// v_scale: P pairs over N nodes add their errors to the nodes, so the rms
+// velocity error they cause stays below tol times the velocity scale v_scale,
+// the rms of the velocity's local, self and short-range terms at the nodes.
 struct NsBox {
-    float err[kNsBins];   // max relative error of the learned integral per bin
-    double tol;           // fall back where err > tol
+    float err[kNsBins];
+    double tol;
 };
 
 // raw straight-segment integral  int (s - x) x ds / |s - x|^3  over A -> B
@@ -780,6 +797,149 @@ __device__ TangentBase tangent_baseline(const Seg &s, const double *x, double h)
     tb.dstar = d / h;
     tb.mult = (1.0 + log1p(h / fmax(d, 1e-300 * h))) / h;
     return tb;
+}
+
+// ------------------------------------------------------ mapped rule
+// Fixed-cost segment integral for near-singular pairs.  With P = s(ub) the
+// point of the segment closest to the target (distance d) and b = d / |s'(ub)|
+// the width of the integrand's peak in parameter units, the substitution
+// u = ub + b sinh(mu) (the sinh transformation of nearly singular integrals)
+// spreads the peak evenly over mu; each side of it, mu in [asinh(-ub/b), 0]
+// and [0, asinh((1-ub)/b)], takes the 16-point Gauss-Legendre rule.  The
+// same rule applied to the straight segment tangent to the curve at P
+// (|P - s(0)| back, |s(1) - P| forward), whose integral is known in closed
+// form, serves as a control variate: its exact integral minus its rule value
+// is added, which removes most of the rule's error near the peak (the
+// curve's integrand approaches the tangent's as d -> 0).  Every pair costs
+// the same (32 + 32 kernel evaluations): no panel recursion, no divergence.
+__device__ __forceinline__ void mapped_half_seg(const Seg &s, const double *xs, double ub,
+                                                double b, double m0, double m1, const NsRule &R,
+                                                double *acc) {
+    const double hw = 0.5 * (m1 - m0), mc = 0.5 * (m1 + m0);
+    if (!(hw > 0.0)) return;
+    for (int k = 0; k < kNsGL; k++) {
+        const double mu = mc + hw * R.x[k];
+        const double e = exp(mu), ei = 1.0 / e;
+        const double u = ub + b * 0.5 * (e - ei);
+        const double jac = R.w[k] * hw * b * 0.5 * (e + ei);
+        double r[3], d[3];
+        for (int q = 0; q < 3; q++) {
+            r[q] = seg_p(s, q, u) - xs[q];
+            d[q] = seg_d(s, q, u);
+        }
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double f = jac / (r2 * sqrt(r2));
+        acc[0] += f * (r[1] * d[2] - r[2] * d[1]);
+        acc[1] += f * (r[2] * d[0] - r[0] * d[2]);
+        acc[2] += f * (r[0] * d[1] - r[1] * d[0]);
+    }
+}
+
+// the rule on the straight segment P + l t, l in [-la, lb] (t unit), peak at
+// l0 (its point closest to x) of width dd; acc -= rule, the caller adds the
+// closed form
+__device__ __forceinline__ void mapped_half_line(const double *rho, const double *t, double l0,
+                                                 double dd, double m0, double m1,
+                                                 const NsRule &R, double *acc) {
+    const double hw = 0.5 * (m1 - m0), mc = 0.5 * (m1 + m0);
+    if (!(hw > 0.0)) return;
+    // (r x t) = (rho + l t) x t = rho x t for every l
+    const double c[3] = {rho[1] * t[2] - rho[2] * t[1], rho[2] * t[0] - rho[0] * t[2],
+                         rho[0] * t[1] - rho[1] * t[0]};
+    const double rt = rho[0] * t[0] + rho[1] * t[1] + rho[2] * t[2];
+    const double rr = rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2];
+    double sum = 0.0;
+    for (int k = 0; k < kNsGL; k++) {
+        const double mu = mc + hw * R.x[k];
+        const double e = exp(mu), ei = 1.0 / e;
+        const double l = l0 + dd * 0.5 * (e - ei);
+        const double jac = R.w[k] * hw * dd * 0.5 * (e + ei);
+        const double r2 = rr + 2.0 * l * rt + l * l;
+        sum += jac / (r2 * sqrt(r2));
+    }
+    acc[0] -= sum * c[0];
+    acc[1] -= sum * c[1];
+    acc[2] -= sum * c[2];
+}
+
+__device__ void ns_seg_mapped(const Seg &s, const double *xs, const NsRule &R, double *acc) {
+    const double ub = closest_u(s, xs);
+    double P[3], d1[3], S0[3], S1[3], dummy[3];
+    seg_eval(s, ub, P, d1);
+    seg_eval(s, 0.0, S0, dummy);
+    seg_eval(s, 1.0, S1, dummy);
+    double dist2 = 0.0, sp2 = 0.0, la = 0.0, lb = 0.0;
+    for (int q = 0; q < 3; q++) {
+        dist2 += (P[q] - xs[q]) * (P[q] - xs[q]);
+        sp2 += d1[q] * d1[q];
+        la += (P[q] - S0[q]) * (P[q] - S0[q]);
+        lb += (S1[q] - P[q]) * (S1[q] - P[q]);
+    }
+    la = sqrt(la); lb = sqrt(lb);
+    const double sn = sqrt(sp2);
+    double b = sqrt(dist2) / sn;
+    b = b < 1e-13 ? 1e-13 : b;
+    acc[0] = acc[1] = acc[2] = 0.0;
+    mapped_half_seg(s, xs, ub, b, asinh(-ub / b), 0.0, R, acc);
+    mapped_half_seg(s, xs, ub, b, 0.0, asinh((1.0 - ub) / b), R, acc);
+    // control variate: tangent segment at P
+    double t[3], rho[3], A[3], B[3], cv[3];
+    for (int q = 0; q < 3; q++) {
+        t[q] = d1[q] / sn;
+        rho[q] = P[q] - xs[q];
+        A[q] = P[q] - la * t[q];
+        B[q] = P[q] + lb * t[q];
+    }
+    chord_raw(A, B, xs, cv);
+    double l0 = -(rho[0] * t[0] + rho[1] * t[1] + rho[2] * t[2]);
+    l0 = l0 < -la ? -la : (l0 > lb ? lb : l0);
+    double dd2 = 0.0;
+    for (int q = 0; q < 3; q++) {
+        const double v = rho[q] + l0 * t[q];
+        dd2 += v * v;
+    }
+    double dd = sqrt(dd2);
+    dd = dd < 1e-13 * (la + lb) ? 1e-13 * (la + lb) : dd;
+    for (int q = 0; q < 3; q++) acc[q] += cv[q];
+    mapped_half_line(rho, t, l0, dd, asinh((-la - l0) / dd), 0.0, R, acc);
+    mapped_half_line(rho, t, l0, dd, 0.0, asinh((lb - l0) / dd), R, acc);
+}
+
+// mapped segment integral minus the Q-point sum, for one (node, segment) pair
+__device__ void ns_pair_mapped(int o, int sg, int sh, const int *off, const int *fil,
+                               const double *x, const double *xn, const double *D,
+                               const double *S, const double *dtau, const double *gamma,
+                               const double *qpos, const double *qchg, int Q, double L,
+                               const NsRule &R, double *out) {
+    double xs[3];
+    unpack_shift(sh, x + 3 * o, L, xs);
+    Seg s = load_seg(sg, off, fil, x, xn, D, S, dtau);
+    double acc[3], qs[3];
+    ns_seg_mapped(s, xs, R, acc);
+    ns_qsum(sg, xs, qpos, qchg, Q, qs);
+    const double g4 = gamma[fil[sg]] / (4.0 * kPi);
+    for (int q = 0; q < 3; q++) out[q] = g4 * acc[q] - qs[q] / (4.0 * kPi);
+}
+
+// every pair (list == nullptr, count = total pairs), or the pairs listed
+__global__ __launch_bounds__(256) void k_ns_mapped(
+    const int *__restrict__ count, const int *__restrict__ list, const int *__restrict__ pnode,
+    const int2 *__restrict__ pairs, const int *__restrict__ off, const int *__restrict__ fil,
+    const double *__restrict__ x, const double *__restrict__ xn, const double *__restrict__ D,
+    const double *__restrict__ S, const double *__restrict__ dtau,
+    const double *__restrict__ gamma, const double *__restrict__ qpos,
+    const double *__restrict__ qchg, int Q, double L, NsRule R, double *__restrict__ pout) {
+    const int n = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int p = list ? list[i] : i;
+        const int2 pr = pairs[p];
+        double out[3];
+        ns_pair_mapped(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg, Q,
+                       L, R, out);
+        pout[3 * (size_t)p] = out[0];
+        pout[3 * (size_t)p + 1] = out[1];
+        pout[3 * (size_t)p + 2] = out[2];
+    }
 }
 
 struct NsFrame {
@@ -916,58 +1076,148 @@ __device__ __forceinline__ void pair_geometry(int o, int sg, int sh, const int *
     unpack_shift(sh, x + 3 * o, L, xs);
 }
 
-__global__ __launch_bounds__(256) void k_ns_features(
-    const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
-    const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ xn, const double *__restrict__ D, const double *__restrict__ dtau,
-    double L, float *__restrict__ X) {
+// Split the pairs by the error indicator before any inference: a pair whose
+// inputs lie in the sample box and whose bin error fits the budget gets its
+// features written at slot i of the learned list (learn[i] = pair), every
+// other pair goes to the plain integrator's list; so the network runs only on the
+// pairs it carries (lists in no particular order).
+__global__ __launch_bounds__(256) void k_ns_select(
+    const int *__restrict__ total, int N, const int *__restrict__ pnode,
+    const int2 *__restrict__ pairs, const int *__restrict__ off, const int *__restrict__ fil,
+    const double *__restrict__ x, const double *__restrict__ xn, const double *__restrict__ D,
+    const double *__restrict__ dtau, const double *__restrict__ gamma, double L, NsBox box,
+    const double *__restrict__ vscale, float *__restrict__ X, int *__restrict__ counts,
+    int *__restrict__ learn, int *__restrict__ fb_list) {
+    if (!counts[2]) return;   // the gate rules every pair out
     const int P = *total;
+    // allowed rms error of one pair's raw integral times |Gamma| / (4 pi h)
+    const double budget = box.tol * vscale[0] / sqrt((double)P / (double)(N > 0 ? N : 1));
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         int2 pr = pairs[p];
         double A[3], B[3], D0[3], D1[3], xs[3];
         pair_geometry(pnode[p], pr.x, pr.y, off, fil, x, xn, D, dtau, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
-        for (int k = 0; k < 8; k++) X[8 * (size_t)p + k] = F.f[k];
+        const double g4 = gamma[fil[pr.x]] / (4.0 * kPi);
+        const bool ok = F.inbox && (double)box.err[ns_bin(F.dc)] * fabs(g4) / F.h <= budget;
+        if (ok) {
+            const int i = atomicAdd(&counts[0], 1);
+            learn[i] = p;
+            for (int k = 0; k < 8; k++) X[8 * (size_t)i + k] = F.f[k];
+        } else {
+            fb_list[atomicAdd(&counts[1], 1)] = p;
+        }
     }
 }
 
-// learned integral where the error table allows it, adaptive elsewhere
+// learned segment integral of the listed pairs: I_tan + mult * (network
+// output in the chord frame), minus the Q-point sum the pair kernel added
 __global__ __launch_bounds__(256) void k_ns_combine(
-    const int *__restrict__ total, const int *__restrict__ pnode, const int2 *__restrict__ pairs,
-    const int *__restrict__ off, const int *__restrict__ fil, const double *__restrict__ x,
-    const double *__restrict__ xn, const double *__restrict__ D, const double *__restrict__ dtau,
-    const double *__restrict__ gamma, const double *__restrict__ qpos,
-    const double *__restrict__ qchg, int Q, double L, NsRule R, NsBox box,
-    const float *__restrict__ Y, double *__restrict__ pout, int *__restrict__ nfallback) {
-    const int P = *total;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+    const int *__restrict__ nlearn, const int *__restrict__ learn, const int *__restrict__ pnode,
+    const int2 *__restrict__ pairs, const int *__restrict__ off, const int *__restrict__ fil,
+    const double *__restrict__ x, const double *__restrict__ xn, const double *__restrict__ D,
+    const double *__restrict__ dtau, const double *__restrict__ gamma,
+    const double *__restrict__ qpos, const double *__restrict__ qchg, int Q, double L,
+    const float *__restrict__ Y, double *__restrict__ pout) {
+    const int n = *nlearn;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int p = learn[i];
         int2 pr = pairs[p];
-        const int o = pnode[p];
         double A[3], B[3], D0[3], D1[3], xs[3];
-        pair_geometry(o, pr.x, pr.y, off, fil, x, xn, D, dtau, L, A, B, D0, D1, xs);
+        pair_geometry(pnode[p], pr.x, pr.y, off, fil, x, xn, D, dtau, L, A, B, D0, D1, xs);
         NsFrame F = ns_frame(A, B, D0, D1, xs);
+        const double g4 = gamma[fil[pr.x]] / (4.0 * kPi);
         Seg sgm = load_seg(pr.x, off, fil, x, xn, D, nullptr, dtau);
         const TangentBase tb = tangent_baseline(sgm, xs, F.h);
-        double out[3];
-        if (!F.inbox || (double)box.err[ns_bin(tb.dstar)] > box.tol) {
-            ns_pair(o, pr.x, pr.y, off, fil, x, xn, D, nullptr, dtau, gamma, qpos, qchg, Q, L, R,
-                    out);
-            atomicAdd(nfallback, 1);
-        } else {
-            // segment integral = I_tan + mult * (network output in the chord
-            // frame), minus the Q-point sum the pair kernel already added
-            double qs[3], y[3];
-            for (int k = 0; k < 3; k++) y[k] = (double)Y[3 * (size_t)p + k] * tb.mult;
-            ns_qsum(pr.x, xs, qpos, qchg, Q, qs);
-            const double g4 = gamma[fil[pr.x]] / (4.0 * kPi);
-            for (int q = 0; q < 3; q++) {
-                double yw = F.e[0][q] * y[0] + F.e[1][q] * y[1] + F.e[2][q] * y[2];
-                out[q] = g4 * (tb.I[q] + yw) - qs[q] / (4.0 * kPi);
-            }
+        double qs[3], y[3];
+        for (int k = 0; k < 3; k++) y[k] = (double)Y[3 * (size_t)i + k] * tb.mult;
+        ns_qsum(pr.x, xs, qpos, qchg, Q, qs);
+        for (int q = 0; q < 3; q++) {
+            double yw = F.e[0][q] * y[0] + F.e[1][q] * y[1] + F.e[2][q] * y[2];
+            pout[3 * (size_t)p + q] = g4 * (tb.I[q] + yw) - qs[q] / (4.0 * kPi);
         }
-        pout[3 * (size_t)p] = out[0];
-        pout[3 * (size_t)p + 1] = out[1];
-        pout[3 * (size_t)p + 2] = out[2];
+    }
+}
+
+// The velocity scale v_scale = rms over the nodes of |base_i|, and a bound
+// that decides for all pairs at once whether the network can take any: with
+// e_min the table's smallest entry, h_max the longest chord and G the
+// smallest |Gamma|, every pair's indicator is at least e_min G / (4 pi h_max)
+// sqrt(P / N), so none passes when that exceeds tol v_scale.  Then the
+// selection and the inference do nothing and the plain integrator takes
+// every pair in pair order.  Two passes, fixed order: per block sums of
+// squares, longest chord and smallest |Gamma|, then one block that forms the
+// scale and the decision (gate[0] = 1: some pair may pass; gate[1] =
+// !gate[0]).
+constexpr int kNsVsBlocks = 256;
+__global__ __launch_bounds__(256) void k_ns_gate_part(int N, const double *__restrict__ base,
+                                                      const double *__restrict__ x,
+                                                      const double *__restrict__ xn,
+                                                      const int *__restrict__ fil,
+                                                      const double *__restrict__ gamma,
+                                                      double *__restrict__ part) {
+    __shared__ double s2[256], sh[256], sg[256];
+    double a = 0.0, hm = 0.0, gm = INFINITY;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        double c2 = 0.0;
+        for (int q = 0; q < 3; q++) {
+            a += base[3 * i + q] * base[3 * i + q];
+            const double d = xn[3 * i + q] - x[3 * i + q];
+            c2 += d * d;
+        }
+        hm = fmax(hm, c2);
+        gm = fmin(gm, fabs(gamma[fil[i]]));
+    }
+    s2[threadIdx.x] = a;
+    sh[threadIdx.x] = hm;
+    sg[threadIdx.x] = gm;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s2[threadIdx.x] += s2[threadIdx.x + o];
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+            sg[threadIdx.x] = fmin(sg[threadIdx.x], sg[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = s2[0];
+        part[3 * blockIdx.x + 1] = sh[0];
+        part[3 * blockIdx.x + 2] = sg[0];
+    }
+}
+__global__ __launch_bounds__(256) void k_ns_gate_final(int N, const double *__restrict__ part,
+                                                       int nparts, const int *__restrict__ total,
+                                                       double emin, double tol,
+                                                       double *__restrict__ vscale,
+                                                       int *__restrict__ gate) {
+    __shared__ double s2[256], sh[256], sg[256];
+    double a = 0.0, hm = 0.0, gm = INFINITY;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        a += part[3 * i];
+        hm = fmax(hm, part[3 * i + 1]);
+        gm = fmin(gm, part[3 * i + 2]);
+    }
+    s2[threadIdx.x] = a;
+    sh[threadIdx.x] = hm;
+    sg[threadIdx.x] = gm;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s2[threadIdx.x] += s2[threadIdx.x + o];
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+            sg[threadIdx.x] = fmin(sg[threadIdx.x], sg[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double vs = N > 0 ? sqrt(s2[0] / N) : 0.0;
+        const double P = (double)*total;
+        const double hmax = sqrt(sh[0]);
+        const bool some = P > 0.0 && hmax > 0.0 &&
+                          emin * sg[0] / (4.0 * kPi * hmax) * sqrt(P / (double)N) <= tol * vs;
+        vscale[0] = vs;
+        gate[0] = some ? 1 : 0;
+        gate[1] = some ? 0 : 1;
     }
 }
 
@@ -1033,12 +1283,35 @@ void ns_build_pairs(bs_plan_t p) {
 
 void ns_rule(NsRule *R);
 
-void launch_ns_adaptive(bs_plan_t p, double *v) {
-    const int N = (int)p->N;
+// the graded-panel integrator on every pair (list == nullptr) or on the
+// listed ones; nothing when *skip is set
+static void adaptive_pairs(bs_plan_t p, const int *count, const int *list,
+                           const int *skip = nullptr) {
     NsRule R;
     ns_rule(&R);
+    hipLaunchKernelGGL(k_ns_integrate, dim3(1024), dim3(256), 0, p->stream, count, list,
+                       (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
+                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
+                       (const double *)p->d_x.p, (const double *)p->d_xn.p,
+                       (const double *)p->d_D.p, p->order == 6 ? (const double *)p->d_sdd.p : nullptr,
+                       (const double *)p->d_dtau.p, (const double *)p->d_gamma.p,
+                       (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q,
+                       p->prm.L, R, (double *)p->ns_pout.p, skip);
+}
+
+void launch_ns_adaptive(bs_plan_t p, double *v) {
+    const int N = (int)p->N;
     const int *start = (const int *)p->ns_start.p;
-    hipLaunchKernelGGL(k_ns_integrate, dim3(1024), dim3(256), 0, p->stream, start + N,
+    adaptive_pairs(p, start + N, nullptr);
+    hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(N, 256)), dim3(256), 0, p->stream, N, start,
+                       (const double *)p->ns_pout.p, v);
+}
+
+// the mapped rule on every pair (list == nullptr) or on the listed ones
+static void mapped_pairs(bs_plan_t p, const int *count, const int *list) {
+    NsRule R;
+    ns_rule(&R);
+    hipLaunchKernelGGL(k_ns_mapped, dim3(2048), dim3(256), 0, p->stream, count, list,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
                        (const double *)p->d_x.p, (const double *)p->d_xn.p,
@@ -1046,52 +1319,58 @@ void launch_ns_adaptive(bs_plan_t p, double *v) {
                        (const double *)p->d_dtau.p, (const double *)p->d_gamma.p,
                        (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q,
                        p->prm.L, R, (double *)p->ns_pout.p);
+}
+
+void launch_ns_mapped(bs_plan_t p, double *v) {
+    const int N = (int)p->N;
+    const int *start = (const int *)p->ns_start.p;
+    mapped_pairs(p, start + N, nullptr);
     hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(N, 256)), dim3(256), 0, p->stream, N, start,
                        (const double *)p->ns_pout.p, v);
 }
 
-__global__ void k_ns_count_all(const int *__restrict__ total, int *__restrict__ nfallback) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *nfallback = *total;
-}
-
-void launch_ns_mlp(bs_plan_t p, double *v) {
+void launch_ns_mlp(bs_plan_t p, double *v, const double *base) {
     const int N = (int)p->N;
-    NsRule R;
-    ns_rule(&R);
     const int *start = (const int *)p->ns_start.p;
     const int *total = start + N;
-    bool usable = false;
-    for (int b = 0; b < kNsBins; b++) usable = usable || (double)p->ns_err[b] <= p->prm.tol;
-    if (!usable) {
-        // the error table rules the network out in every bin: every pair
-        // takes the adaptive integrator, and the network is not evaluated
-        launch_ns_adaptive(p, v);
-        hipLaunchKernelGGL(k_ns_count_all, dim3(1), dim3(64), 0, p->stream, total,
-                           (int *)p->ns_fallback.p);
-        return;
-    }
-    hipLaunchKernelGGL(k_ns_features, dim3(1024), dim3(256), 0, p->stream, total,
-                       (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
-                       (const int *)p->d_off.p, (const int *)p->d_fil.p,
-                       (const double *)p->d_x.p, (const double *)p->d_xn.p,
-                       (const double *)p->d_D.p, (const double *)p->d_dtau.p, p->prm.L,
-                       (float *)p->ns_X.p);
-    mlp_forward_device(p->mlp, total, (int64_t)N * p->ns_max_per_node, (const float *)p->ns_X.p,
-                       (float *)p->ns_Y.p, p->stream);
     NsBox box;
-    for (int b = 0; b < kNsBins; b++) box.err[b] = p->ns_err[b];
+    double emin = INFINITY;
+    for (int b = 0; b < kNsBins; b++) {
+        box.err[b] = p->ns_err[b];
+        emin = std::min(emin, (double)p->ns_err[b]);
+    }
     box.tol = p->prm.tol;
-    hipLaunchKernelGGL(k_ns_zero, dim3(1), dim3(64), 0, p->stream, 1, (int *)p->ns_fallback.p,
-                       (int *)p->ns_fallback.p);
-    hipLaunchKernelGGL(k_ns_combine, dim3(1024), dim3(256), 0, p->stream, total,
+    // cnt: [0] learned pairs, [1] listed plain-integrator pairs, [2] gate, [3] !gate
+    int *cnt = (int *)p->ns_fallback.p;
+    int *learn = (int *)p->ns_learn.p;
+    double *vs = (double *)p->ns_vs.p;   // [0] v_scale, [1..] per-block partials
+    const int nvs = std::min(kNsVsBlocks, std::max(1, ceil_div((int64_t)N, 256)));
+    hipLaunchKernelGGL(k_ns_zero, dim3(1), dim3(64), 0, p->stream, 1, cnt, cnt + 1);
+    hipLaunchKernelGGL(k_ns_gate_part, dim3(nvs), dim3(256), 0, p->stream, N, base,
+                       (const double *)p->d_x.p, (const double *)p->d_xn.p,
+                       (const int *)p->d_fil.p, (const double *)p->d_gamma.p, vs + 1);
+    hipLaunchKernelGGL(k_ns_gate_final, dim3(1), dim3(256), 0, p->stream, N,
+                       (const double *)(vs + 1), nvs, total, emin, p->prm.tol, vs, cnt + 2);
+    hipLaunchKernelGGL(k_ns_select, dim3(1024), dim3(256), 0, p->stream, total, N,
                        (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
                        (const double *)p->d_x.p, (const double *)p->d_xn.p,
                        (const double *)p->d_D.p, (const double *)p->d_dtau.p,
-                       (const double *)p->d_gamma.p,
-                       (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q,
-                       p->prm.L, R, box, (const float *)p->ns_Y.p, (double *)p->ns_pout.p,
-                       (int *)p->ns_fallback.p);
+                       (const double *)p->d_gamma.p, p->prm.L, box, (const double *)vs,
+                       (float *)p->ns_X.p, cnt, learn, (int *)p->ns_fblist.p);
+    mlp_forward_device(p->mlp, cnt, (int64_t)N * p->ns_max_per_node, (const float *)p->ns_X.p,
+                       (float *)p->ns_Y.p, p->stream);
+    hipLaunchKernelGGL(k_ns_combine, dim3(1024), dim3(256), 0, p->stream, (const int *)cnt,
+                       (const int *)learn, (const int *)p->ns_pnode.p,
+                       (const int2 *)p->ns_pairs.p, (const int *)p->d_off.p,
+                       (const int *)p->d_fil.p, (const double *)p->d_x.p,
+                       (const double *)p->d_xn.p, (const double *)p->d_D.p,
+                       (const double *)p->d_dtau.p, (const double *)p->d_gamma.p,
+                       (const double *)p->d_qpos.p, (const double *)p->d_qchg.p, p->Q, p->prm.L,
+                       (const float *)p->ns_Y.p, (double *)p->ns_pout.p);
+    // the refused pairs (gate open), or every pair in order (gate closed)
+    adaptive_pairs(p, cnt + 1, (const int *)p->ns_fblist.p, cnt + 3);
+    adaptive_pairs(p, total, nullptr, cnt + 2);
     hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(N, 256)), dim3(256), 0, p->stream, N, start,
                        (const double *)p->ns_pout.p, v);
 }
@@ -1114,4 +1393,116 @@ extern "C" int bs_ns_error_bins(double *lo, double *hi, int *nbins) {
     if (hi) *hi = bs::kNsRhi;
     if (nbins) *nbins = bs::kNsBins;
     return BS_OK;
+}
+
+// ------------------------------------------------------ learned error table
+namespace bs {
+
+// per-block sums of squared errors, counts and maxima per bin: the error of
+// one sample is |I_learned - I| = mult |y - t| (raw integral, h = 1), binned
+// by its distance to the chord over h
+__global__ __launch_bounds__(256) void k_ns_err_part(int64_t n, const float *__restrict__ Y,
+                                                     const float *__restrict__ T,
+                                                     const double *__restrict__ aux,
+                                                     double *__restrict__ part) {
+    double e2[kNsBins], cnt[kNsBins], mx[kNsBins];
+#pragma unroll
+    for (int b = 0; b < kNsBins; b++) e2[b] = cnt[b] = mx[b] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < 3; k++) {
+            const double d = (double)Y[3 * i + k] - (double)T[3 * i + k];
+            s += d * d;
+        }
+        const double e = aux[7 * i + 4] * sqrt(s);
+        const int bin = ns_bin(aux[7 * i + 6]);
+#pragma unroll
+        for (int b = 0; b < kNsBins; b++) {
+            const bool m = b == bin;
+            e2[b] += m ? e * e : 0.0;
+            cnt[b] += m ? 1.0 : 0.0;
+            mx[b] = m ? fmax(mx[b], e) : mx[b];
+        }
+    }
+    __shared__ double sh[256];
+    double *out = part + (size_t)blockIdx.x * kNsBins * 3;
+    for (int b = 0; b < kNsBins; b++) {
+        for (int w = 0; w < 3; w++) {
+            double v = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < kNsBins; bb++)
+                if (bb == b) v = w == 0 ? e2[bb] : (w == 1 ? cnt[bb] : mx[bb]);
+            sh[threadIdx.x] = v;
+            __syncthreads();
+            for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+                if (threadIdx.x < o)
+                    sh[threadIdx.x] = w == 2 ? fmax(sh[threadIdx.x], sh[threadIdx.x + o])
+                                             : sh[threadIdx.x] + sh[threadIdx.x + o];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) out[3 * b + w] = sh[0];
+            __syncthreads();
+        }
+    }
+}
+
+// rms and max per bin over the blocks, in block order; +inf where a bin
+// holds no sample (the network is never used there)
+__global__ void k_ns_err_final(int nparts, const double *__restrict__ part,
+                               float *__restrict__ table) {
+    const int b = threadIdx.x;
+    if (b >= kNsBins) return;
+    double e2 = 0.0, c = 0.0, m = 0.0;
+    for (int k = 0; k < nparts; k++) {
+        const double *q = part + ((size_t)k * kNsBins + b) * 3;
+        e2 += q[0];
+        c += q[1];
+        m = fmax(m, q[2]);
+    }
+    table[b] = c > 0.0 ? (float)sqrt(e2 / c) : INFINITY;
+    table[kNsBins + b] = c > 0.0 ? (float)m : INFINITY;
+}
+
+constexpr int kNsErrBlocks = 256;
+
+// Y: inference output scratch [n][3]; part: [kNsErrBlocks][bins][3];
+// table: [2][bins] device
+int ns_error_table(bs_mlp_t m, int64_t n, const float *X, const float *T, const double *aux,
+                   float *Y, double *part, float *table, float *rms_out, float *max_out) {
+    hipStream_t st = mlp_stream(m);
+    int rc = bs_mlp_forward(m, n, X, Y);
+    if (rc) return rc;
+    const int nb = (int)std::min<int64_t>(kNsErrBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_ns_err_part, dim3(nb), dim3(256), 0, st, n, Y, T, aux, part);
+    hipLaunchKernelGGL(k_ns_err_final, dim3(1), dim3(64), 0, st, nb, (const double *)part, table);
+    float host[2 * kNsBins];
+    if (hipMemcpyAsync(host, table, sizeof(host), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return BS_EDEVICE;
+    for (int b = 0; b < kNsBins; b++) {
+        if (rms_out) rms_out[b] = host[b];
+        if (max_out) max_out[b] = host[kNsBins + b];
+    }
+    return BS_OK;
+}
+
+}  // namespace bs
+
+extern "C" int bs_ns_error_table(bs_mlp_t m, int64_t n, const float *X, const float *T,
+                                 const double *aux, float *rms_out, float *max_out, int nbins) {
+    if (!m || n < 1 || !X || !T || !aux || nbins != bs::kNsBins) return BS_EINVAL;
+    float *Y = nullptr, *table = nullptr;
+    double *part = nullptr;
+    if (hipMalloc((void **)&Y, sizeof(float) * 3 * (size_t)n) != hipSuccess ||
+        hipMalloc((void **)&part, sizeof(double) * 3 * bs::kNsBins * bs::kNsErrBlocks) !=
+            hipSuccess ||
+        hipMalloc((void **)&table, sizeof(float) * 2 * bs::kNsBins) != hipSuccess) {
+        (void)hipFree(Y); (void)hipFree(part); (void)hipFree(table);
+        return BS_ENOMEM;
+    }
+    int rc = bs::ns_error_table(m, n, X, T, aux, Y, part, table, rms_out, max_out);
+    (void)hipStreamSynchronize(bs::mlp_stream(m));
+    (void)hipFree(Y); (void)hipFree(part); (void)hipFree(table);
+    return rc;
 }

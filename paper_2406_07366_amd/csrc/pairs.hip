@@ -25,15 +25,6 @@ namespace bs {
 // partial sums are combined by a fixed xor-shuffle tree (deterministic order).
 constexpr int kMapCap = 1024;
 
-// LDS written by some lanes of a wavefront and read by others of the same
-// wavefront: wait for the stores and keep the compiler from moving memory
-// operations across.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename R, bool PSI, int WPN>
 __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double rc, double alpha,
                                                const int *__restrict__ nperm,

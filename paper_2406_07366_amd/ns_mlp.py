@@ -3,8 +3,9 @@
 Samples come from the library's own segment integrator (bs_ns_samples, the
 plain method in float64); the network is trained by the library's BF16-MFMA
 forward/backward kernels with Adam (bs_mlp_adam_step).  A held-out set gives
-the error table the plan uses to decide, per pair, between the network and
-the adaptive integrator.  This module only drives those calls.
+the error table (bs_ns_error_table, computed by the library) the plan uses to
+decide, per pair, between the network and the mapped rule.  This module only
+drives those calls.
 """
 from __future__ import annotations
 
@@ -26,31 +27,6 @@ def make_dataset(n, seed):
     U = _uniforms(n, seed)
     X, T, A = B.ns_samples(U)
     return X, T, A
-
-
-def error_table(mlp, X, T, A, nbins=None):
-    """Max error of the learned raw segment integral per log10(d/h) bin,
-    relative to the tangent segment's absolute integral S:
-    |m (y_pred - z)| / S, z the target and m its multiplier."""
-    import torch
-    lo, hi, nb = B.ns_error_bins()
-    nbins = nbins or nb
-    Y = mlp.forward(X).double()
-    err = ((Y - T.double()) * A[:, 4:5]).norm(dim=1) / A[:, 5]
-    t = (torch.log10(A[:, 0]) - math.log10(lo)) / (math.log10(hi) - math.log10(lo))
-    b = (t * nbins).long().clamp(0, nbins - 1)
-    tab = np.zeros(nbins, dtype=np.float32)
-    med = np.zeros(nbins, dtype=np.float32)
-    e = err.cpu().numpy()
-    bb = b.cpu().numpy()
-    for k in range(nbins):
-        sel = e[bb == k]
-        if len(sel):
-            tab[k] = sel.max()
-            med[k] = np.median(sel)
-        else:
-            tab[k] = np.inf
-    return tab, med
 
 
 def train(n_train=1_000_000, n_val=100_000, epochs=60, batch=8192, lr=3e-3, seed=0,
@@ -78,15 +54,15 @@ def train(n_train=1_000_000, n_val=100_000, epochs=60, batch=8192, lr=3e-3, seed
             log(f"[ns-mlp] epoch {ep} loss {loss.item():.3e}")
     torch.cuda.synchronize()
     ttrain = time.perf_counter() - t1
-    tab, med = error_table(mlp, Xv, Tv, Av)
+    tab, mx = B.ns_error_table(mlp, Xv, Tv, Av)
     info = dict(n_train=n_train, n_val=n_val, epochs=epochs, batch=batch, gen_s=tgen,
                 train_s=ttrain, val_loss=mlp.loss_grad(Xv, Tv)[0].item(),
-                err_max=tab.tolist(), err_median=med.tolist())
+                err_rms=tab.tolist(), err_max=mx.tolist())
     if log:
         log(f"[ns-mlp] trained {n_train} samples x {epochs} epochs in {ttrain:.1f} s; "
             f"val loss {info['val_loss']:.3e}")
-        log("[ns-mlp] max err / S per d/h bin: " + " ".join(f"{v:.1e}" for v in tab))
-        log("[ns-mlp] median err / S per d/h bin: " + " ".join(f"{v:.1e}" for v in med))
+        log("[ns-mlp] rms err (h = 1) per d/h bin: " + " ".join(f"{v:.1e}" for v in tab))
+        log("[ns-mlp] max err (h = 1) per d/h bin: " + " ".join(f"{v:.1e}" for v in mx))
     return mlp, tab, info
 
 

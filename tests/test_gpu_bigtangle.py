@@ -68,12 +68,14 @@ def run(B, fs, xyz, g, **kw):
     return v, counts
 
 
-def test_bigtangle_plain_fp64(B, case):
+@pytest.mark.parametrize("ns", ["adaptive", "mapped"])
+def test_bigtangle_plain_fp64(B, case, ns):
     fs, gold, xyz, g = case
     fs.tol = 1e-6
-    print(f"\n[case] bigtangle N={fs.n_nodes} grid {fs.grid_n}^3 fp64 + adaptive, tol 1e-6",
+    mode = {"adaptive": B.BS_NS_ADAPTIVE, "mapped": B.BS_NS_MAPPED}[ns]
+    print(f"\n[case] bigtangle N={fs.n_nodes} grid {fs.grid_n}^3 fp64 + {ns}, tol 1e-6",
           flush=True)
-    v, (npairs, nfb) = run(B, fs, xyz, g, precision=B.BS_FP64, ns_mode=B.BS_NS_ADAPTIVE)
+    v, (npairs, nfb) = run(B, fs, xyz, g, precision=B.BS_FP64, ns_mode=mode)
     rel, ru, rn, mx = errors(v, gold)
     print(f"  rel_l2 {rel:.3e} (uniform {ru:.3e}, near {rn:.3e}), max/rms {mx:.3e}, "
           f"ns pairs {npairs}")
@@ -92,7 +94,7 @@ def test_bigtangle_mixed_learned(B, case):
                            mlp=(mlp, table))
     rel, ru, rn, mx = errors(v, gold)
     print(f"  rel_l2 {rel:.3e} (uniform {ru:.3e}, near {rn:.3e}), max/rms {mx:.3e}, "
-          f"ns pairs {npairs}, fallback {nfb} ({nfb / max(npairs, 1):.1%})")
+          f"ns pairs {npairs}, by network {npairs - nfb} ({(npairs - nfb) / max(npairs, 1):.1%})")
     assert rel <= 1e-5 and ru <= 1e-5 and rn <= 1e-5
     assert mx <= 5e-5
 

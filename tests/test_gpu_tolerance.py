@@ -57,16 +57,36 @@ def test_velocity_meets_nominal_tolerance(B, ref, row):
     assert err <= max(row["tol"], 2e-13)
 
 
-@pytest.mark.parametrize("row", _rows(), ids=lambda r: f"tol{r['tol']:g}")
-def test_performance_workload_meets_tolerance(B, row):
-    """The performance tests' random ellipses (Sec. 5.3: 32 ellipses of 32
-    nodes, radii in [L/16, L/4], a = 1e-8) with the paper's discretisation
-    (quintic splines, Q = 3) and parameters (alpha = C_beta N^(1/3)/L, the
-    smallest grid whose modes reach k_max = 2 beta alpha, Table 1's w):
-    the FP64 velocity meets the row's tolerance against the oracle's
-    converged solution of the same discrete problem."""
+_REFS = {}
+
+
+def _perf_reference(n_ell):
+    """The oracle's converged solution of the performance workload (beta =
+    6.5, r_c = L: every image within L summed), computed once per size."""
     from oracle import oracle as O
-    fs = W.perf_ellipses(32, tol=row["tol"])
+    if n_ell not in _REFS:
+        fs = W.perf_ellipses(n_ell)
+        o = O.Oracle(fs, Q=3, order=6)
+        _REFS[n_ell] = (o, o.reference(psi=False)[0])
+    return _REFS[n_ell]
+
+
+@pytest.mark.parametrize("n_ell", [32, 128], ids=lambda n: f"N{32 * n}")
+@pytest.mark.parametrize("row", _rows(), ids=lambda r: f"tol{r['tol']:g}")
+def test_performance_workload_meets_tolerance(B, row, n_ell):
+    """The performance tests' random ellipses (Sec. 5.3: ellipses of 32
+    nodes, radii in [L/16, L/4], a = 1e-8; 32 and 128 of them) with the
+    paper's discretisation (quintic splines, Q = 3) and parameters (alpha =
+    C_beta N^(1/3)/L, the smallest grid whose modes reach k_max = 2 beta
+    alpha, Table 1's w): the FP64 velocity against the oracle's converged
+    solution of the same discrete problem meets the row's tolerance, except
+    where the row's own parameters do not: Table 1's beta = 2.0 for tol 1e-3
+    leaves a real-space truncation error of 0.9e-3 (1024 nodes) to 1.2e-3
+    (4096 nodes) in the oracle itself, with exact Fourier sums at the same
+    alpha, r_c and K.  There the bound is that truncation error, +10 %."""
+    fs = W.perf_ellipses(n_ell, tol=row["tol"])
+    if n_ell > 32 and row["tol"] < 1e-6:
+        pytest.skip("the oracle's direct Fourier sums at these K take minutes at 4096 nodes")
     pp = W.perf_params(fs.n_nodes, row["beta"], row["C_beta"], fs.L, w=row["w"])
     print(f"\n[case] perf ellipses N={fs.n_nodes} tol {row['tol']:g} {pp}", flush=True)
     plan = B.Plan(B.make_params(L=fs.L, a=fs.a, tol=row["tol"], grid_n=pp["grid_n"],
@@ -78,7 +98,13 @@ def test_performance_workload_meets_tolerance(B, row):
     v = plan.velocity().cpu().numpy()
     plan.status()
     plan.close()
-    ref, _ = O.Oracle(fs, Q=3, order=6).reference(psi=False)
+    o, ref = _perf_reference(n_ell)
     err = rel_l2(v, ref)
+    bound = max(row["tol"], 2e-13)
+    if row["tol"] >= 1e-4:
+        vt, _ = o.ewald(p.alpha, p.rcut, p.K, psi=False)
+        trunc = rel_l2(vt, ref)
+        print(f"  oracle truncation error at the same alpha, r_c, K: {trunc:.2e}")
+        bound = max(bound, 1.1 * trunc)
     print(f"  grid {p.grid_n} K {p.K} alpha {p.alpha:.3f} r_c {p.rcut:.3f}: rel_l2 {err:.2e}")
-    assert err <= max(row["tol"], 2e-13)
+    assert err <= bound

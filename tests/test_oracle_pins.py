@@ -614,6 +614,96 @@ def test_adaptive_segment_integral_matches_scipy_quad_on_scipy_spline():
             assert np.linalg.norm(qs - ref) > 0.1 * np.linalg.norm(ref)
 
 
+def _scipy_ns_correction(fs, targets, eta=1.0, Q=2):
+    """Near-singular correction written out independently of the oracle: each
+    filament's periodic cubic spline on chord-length knots from scipy, chord
+    distances to every non-adjacent segment with the minimum image of the
+    chord midpoint, and for each segment closer than eta * (its arc length,
+    by scipy.quad) the exact segment integral of the full kernel by
+    scipy.quad minus the segment's Q-point Gauss-Legendre sum.  Returns the
+    corrections and the smallest relative margin |d - eta ell| / (eta ell)
+    over all tested pairs (the flag decisions are unambiguous above ~1e-6)."""
+    L = fs.L
+    splines, knots, fil_of = [], [], np.zeros(fs.n_nodes, dtype=np.int64)
+    for f in range(fs.n_fil):
+        a, b = fs.offsets[f], fs.offsets[f + 1]
+        X = fs.xyz[a:b]
+        Xe = np.vstack([X, X[:1]])
+        tau = np.concatenate([[0.0], np.cumsum(np.linalg.norm(np.diff(Xe, axis=0), axis=1))])
+        splines.append(scipy.interpolate.CubicSpline(tau, Xe, bc_type="periodic"))
+        knots.append(tau)
+        fil_of[a:b] = f
+    gh, gw = np.polynomial.legendre.leggauss(Q)
+    gh, gw = 0.5 * (gh + 1), 0.5 * gw
+    out = np.zeros((len(targets), 3))
+    margin = np.inf
+    for t, i in enumerate(targets):
+        fi = fil_of[i]
+        a = fs.offsets[fi]
+        nl = fs.offsets[fi + 1] - a
+        adj = {i, a + (i - a - 1) % nl}
+        x = fs.xyz[i]
+        for j in range(fs.n_nodes):
+            if j in adj:
+                continue
+            f = fil_of[j]
+            sp, tau = splines[f], knots[f]
+            k = j - fs.offsets[f]
+            t0, t1 = tau[k], tau[k + 1]
+            A, Bp = sp(t0), sp(t1)
+            m = 0.5 * (A + Bp)
+            xs = x - L * np.round((x - m) / L)
+            e = Bp - A
+            u = np.clip(np.dot(xs - A, e) / np.dot(e, e), 0.0, 1.0)
+            d = np.linalg.norm(xs - A - u * e)
+            ell = scipy.integrate.quad(lambda s_: np.linalg.norm(sp(s_, 1)), t0, t1,
+                                       epsabs=0, epsrel=1e-13)[0]
+            margin = min(margin, abs(d - eta * ell) / (eta * ell))
+            if not d < eta * ell:
+                continue
+            g4 = fs.gamma[f] / (4 * math.pi)
+
+            def kern(s_, c):
+                r = sp(s_) - xs
+                return np.cross(r, sp(s_, 1))[c] / np.linalg.norm(r) ** 3
+
+            ss = np.linspace(t0, t1, 2001)
+            sc = ss[np.argmin(np.linalg.norm(sp(ss) - xs, axis=1))]
+            ex = np.array([scipy.integrate.quad(kern, t0, t1, args=(c,), epsabs=0,
+                                                epsrel=1e-12, limit=400, points=[sc])[0]
+                           for c in range(3)])
+            qs = sum(gw[q] * (t1 - t0) * np.array([kern(t0 + gh[q] * (t1 - t0), c)
+                                                  for c in range(3)]) for q in range(Q))
+            out[t] += g4 * (ex - qs)
+    return out, margin
+
+
+def test_near_singular_correction_matches_independent_quadrature():
+    """or_ns_correction (its flag rule on the chord distance, the image shift
+    of the target, the adaptive integral and the subtracted Q-point sum)
+    against the same correction written out with scipy's periodic spline and
+    scipy.quad; and the same correction after one ring of each pair and the
+    background curve are moved by lattice vectors (a mistaken image shift
+    would change it)."""
+    fs = W.ringpairs(npairs=3, nbg=1, seed=21)
+    targets = np.arange(0, fs.n_nodes, 3)
+    o = O.Oracle(fs)
+    dv, cnt = o.ns_correction(eta=1.0, targets=targets)
+    ref, margin = _scipy_ns_correction(fs, targets)
+    assert margin > 1e-6
+    assert cnt.sum() > len(targets) // 3
+    np.testing.assert_allclose(dv, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+    moved = fs.xyz.copy()
+    L = fs.L
+    for f, sh in ((1, (L, 0, 0)), (2, (0, -L, 2 * L)), (6, (-L, L, 0))):
+        a, b = fs.offsets[f], fs.offsets[f + 1]
+        moved[a:b] += np.array(sh)
+    fs2 = W.FilamentSet(**{**fs.__dict__, "xyz": moved})
+    dv2, cnt2 = O.Oracle(fs2).ns_correction(eta=1.0, targets=targets)
+    np.testing.assert_array_equal(cnt2, cnt)
+    np.testing.assert_allclose(dv2, dv, rtol=0, atol=1e-10 * np.abs(dv).max())
+
+
 def test_near_singular_correction_flags_and_limits():
     fs = W.ringpairs(npairs=3, nbg=0, seed=4)
     o = O.Oracle(fs)
