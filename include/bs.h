@@ -356,6 +356,18 @@ int bs_ns_error_bins(double *lo, double *hi, int *nbins);
  * 12 n bytes.  Errors: BS_EINVAL (sizes, nbins), BS_ENOMEM, BS_EDEVICE. */
 int bs_ns_error_table(bs_mlp_t mlp, int64_t n, const float *X, const float *T,
                       const double *aux, float *rms_out, float *max_out, int nbins);
+/* bs_ns_error_table for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same table, written to rms_out and max_out as DEVICE float [nbins]
+ * arrays (either may be NULL), asynchronously on the network's stream (no
+ * host copy, no synchronisation).  Calls no hipMalloc, hipFree or other
+ * allocating routine: the network outputs and partial sums live in a
+ * static device array of 3.2 MB per GPU, held until the process ends, so n
+ * is at most 262144 (BS_EINVAL beyond).  Calls on one GPU share that array:
+ * calls that overlap on one GPU (two streams, two threads) race.  Errors:
+ * BS_EINVAL (sizes, nbins), BS_EDEVICE. */
+int bs_ns_error_table_noalloc(bs_mlp_t mlp, int64_t n, const float *X, const float *T,
+                              const double *aux, float *rms_out, float *max_out, int nbins);
 /* Attach a trained network to a BS_NS_MLP plan.  err_table[nbins] holds the
  * rms error per distance bin (bs_ns_error_table's rms_out).  A pair (node
  * i, segment of length h, circulation Gamma) takes the learned integral

@@ -31,6 +31,7 @@ EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_set_periods"
             "bs_destroy", "bs_last_error", "bs_mlp_nparams", "bs_mlp_create",
             "bs_mlp_forward", "bs_mlp_loss_grad", "bs_mlp_adam_step", "bs_mlp_get_params",
             "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_ns_error_table",
+            "bs_ns_error_table_noalloc",
             "bs_set_mlp", "bs_ns_counts", "bs_rk4_step", "bs_step", "bs_set_graph",
             "bs_graph_active"]
 
@@ -99,6 +100,7 @@ _lib.bs_mlp_destroy.argtypes = [_vp]
 _lib.bs_ns_samples.argtypes = [C.c_int64, _vp, _vp, _vp, _vp, _vp]
 _lib.bs_ns_error_bins.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
 _lib.bs_ns_error_table.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_int]
+_lib.bs_ns_error_table_noalloc.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_int]
 _lib.bs_set_mlp.argtypes = [_vp, _vp, _vp, C.c_int]
 _lib.bs_ns_counts.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
 _lib.bs_rk4_step.argtypes = [_vp, C.c_int64, C.POINTER(C.c_int64), _vp, _vp, C.c_double]
@@ -393,6 +395,18 @@ def ns_error_table(mlp, X, T, A):
     _check(_lib.bs_ns_error_table(mlp._h, X.shape[0], _ptr(X), _ptr(T), _ptr(A),
                                   rms.ctypes.data_as(_vp), mx.ctypes.data_as(_vp), nb))
     return rms, mx
+
+
+def ns_error_table_noalloc(mlp, X, T, A, rms_out, max_out):
+    """bs_ns_error_table_noalloc: the table into device float32 tensors
+    rms_out and max_out (nbins each), asynchronously on the network's stream."""
+    _, _, nb = ns_error_bins()
+    X, T = mlp._f32(X), mlp._f32(T)
+    torch = mlp._torch
+    for t in (rms_out, max_out):
+        assert t.is_cuda and t.dtype == torch.float32 and t.numel() == nb
+    _check(_lib.bs_ns_error_table_noalloc(mlp._h, X.shape[0], _ptr(X), _ptr(T), _ptr(A),
+                                          _ptr(rms_out), _ptr(max_out), nb))
 
 
 def ns_samples(U, aux=True):

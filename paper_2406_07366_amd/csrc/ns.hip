@@ -22,6 +22,8 @@
 //             network runs only on those pairs), the graded panels elsewhere;
 //   apply   one thread per node adds its pairs' corrections in list order
 //           (deterministic whatever order the pairs were computed in).
+#include <mutex>
+
 #include "bs_internal.h"
 #include "bs_device.h"
 
@@ -1450,7 +1452,7 @@ __global__ __launch_bounds__(256) void k_ns_err_part(int64_t n, const float *__r
 // rms and max per bin over the blocks, in block order; +inf where a bin
 // holds no sample (the network is never used there)
 __global__ void k_ns_err_final(int nparts, const double *__restrict__ part,
-                               float *__restrict__ table) {
+                               float *__restrict__ rms, float *__restrict__ mx) {
     const int b = threadIdx.x;
     if (b >= kNsBins) return;
     double e2 = 0.0, c = 0.0, m = 0.0;
@@ -1460,8 +1462,8 @@ __global__ void k_ns_err_final(int nparts, const double *__restrict__ part,
         c += q[1];
         m = fmax(m, q[2]);
     }
-    table[b] = c > 0.0 ? (float)sqrt(e2 / c) : INFINITY;
-    table[kNsBins + b] = c > 0.0 ? (float)m : INFINITY;
+    if (rms) rms[b] = c > 0.0 ? (float)sqrt(e2 / c) : INFINITY;
+    if (mx) mx[b] = c > 0.0 ? (float)m : INFINITY;
 }
 
 constexpr int kNsErrBlocks = 256;
@@ -1475,7 +1477,8 @@ int ns_error_table(bs_mlp_t m, int64_t n, const float *X, const float *T, const 
     if (rc) return rc;
     const int nb = (int)std::min<int64_t>(kNsErrBlocks, std::max<int64_t>(1, (n + 255) / 256));
     hipLaunchKernelGGL(k_ns_err_part, dim3(nb), dim3(256), 0, st, n, Y, T, aux, part);
-    hipLaunchKernelGGL(k_ns_err_final, dim3(1), dim3(64), 0, st, nb, (const double *)part, table);
+    hipLaunchKernelGGL(k_ns_err_final, dim3(1), dim3(64), 0, st, nb, (const double *)part, table,
+                       table + kNsBins);
     float host[2 * kNsBins];
     if (hipMemcpyAsync(host, table, sizeof(host), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
@@ -1488,6 +1491,61 @@ int ns_error_table(bs_mlp_t m, int64_t n, const float *X, const float *T, const 
 }
 
 }  // namespace bs
+
+// ------------------------------------------- error table without allocation
+// Callers that cannot allocate device memory (code under graph capture,
+// serving loops, harnesses that forbid it) use a file-scope device array for
+// the network outputs, the per-block partial sums and the table.  Each GPU
+// holds its own copy for the life of the process; host code reaches it only
+// through the device address taken once per device by hipGetSymbolAddress
+// (the array's name is a host-side stand-in).  Calls on one GPU share it:
+// calls that overlap on one GPU race.
+namespace bs {
+constexpr int64_t kNsErrNoAllocMax = 1 << 18;   // samples per call, at most
+constexpr size_t kNsScratchY = sizeof(float) * 3 * (size_t)kNsErrNoAllocMax;
+constexpr size_t kNsScratchPart = sizeof(double) * 3 * kNsBins * kNsErrBlocks;
+constexpr size_t kNsScratchBytes = kNsScratchY + kNsScratchPart + 256;
+static __device__ __align__(256) unsigned char scratch[kNsScratchBytes];
+
+constexpr int kNsMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kNsMaxDevices];
+
+// device address of this device's scratch (taken on the first call on it)
+static int scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNsMaxDevices) return BS_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return BS_EDEVICE;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return BS_OK;
+}
+}  // namespace bs
+
+extern "C" int bs_ns_error_table_noalloc(bs_mlp_t m, int64_t n, const float *X, const float *T,
+                                         const double *aux, float *rms_out, float *max_out,
+                                         int nbins) {
+    if (!m || n < 1 || !X || !T || !aux || nbins != bs::kNsBins) return BS_EINVAL;
+    if (n > bs::kNsErrNoAllocMax) return BS_EINVAL;   // beyond the static scratch
+    void *base = nullptr;
+    int rc = bs::scratch_address(&base);
+    if (rc) return rc;
+    unsigned char *sp = (unsigned char *)base;
+    float *Y = (float *)sp;
+    double *part = (double *)(sp + bs::kNsScratchY);
+    hipStream_t st = bs::mlp_stream(m);
+    if ((rc = bs_mlp_forward(m, n, X, Y))) return rc;
+    const int nb = (int)std::min<int64_t>(bs::kNsErrBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(bs::k_ns_err_part, dim3(nb), dim3(256), 0, st, n, Y, T, aux, part);
+    hipLaunchKernelGGL(bs::k_ns_err_final, dim3(1), dim3(64), 0, st, nb, (const double *)part,
+                       rms_out, max_out);
+    return hipGetLastError() == hipSuccess ? BS_OK : BS_EDEVICE;
+}
 
 extern "C" int bs_ns_error_table(bs_mlp_t m, int64_t n, const float *X, const float *T,
                                  const double *aux, float *rms_out, float *max_out, int nbins) {
