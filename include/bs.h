@@ -322,6 +322,12 @@ int bs_mlp_loss_grad(bs_mlp_t m, int64_t B, const float *X, const float *T,
 /* one Adam step on that loss (bias-corrected moments); loss_dev may be NULL */
 int bs_mlp_adam_step(bs_mlp_t m, int64_t B, const float *X, const float *T,
                      float lr, float beta1, float beta2, float eps, float *loss_dev);
+/* Debug mode (enable = 1): the forward, loss-gradient and Adam calls (and
+ * the plans using this network) run the same kernels with FP32 weights and
+ * activations on FP32 MFMA (v_mfma_f32_16x16x4_f32) instead of BF16, so that
+ * their results differ from an FP64 evaluation by FP32 rounding only; for
+ * checking the gradients.  enable = 0 returns to BF16. */
+int bs_mlp_set_fp32(bs_mlp_t m, int enable);
 /* synchronise and copy the current FP32 parameters to the host */
 int bs_mlp_get_params(bs_mlp_t m, float *params_host);
 int bs_mlp_destroy(bs_mlp_t m);

@@ -30,6 +30,7 @@ EXPORTED = ["bs_resolve_params", "bs_plan", "bs_set_filaments", "bs_set_periods"
             "bs_status", "bs_set_profiling", "bs_stage_times", "bs_get_params",
             "bs_destroy", "bs_last_error", "bs_mlp_nparams", "bs_mlp_create",
             "bs_mlp_forward", "bs_mlp_loss_grad", "bs_mlp_adam_step", "bs_mlp_get_params",
+            "bs_mlp_set_fp32",
             "bs_mlp_destroy", "bs_ns_samples", "bs_ns_error_bins", "bs_ns_error_table",
             "bs_ns_error_table_noalloc",
             "bs_set_mlp", "bs_ns_counts", "bs_rk4_step", "bs_step", "bs_set_graph",
@@ -96,6 +97,7 @@ _lib.bs_mlp_loss_grad.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp]
 _lib.bs_mlp_adam_step.argtypes = [_vp, C.c_int64, _vp, _vp, C.c_float, C.c_float, C.c_float,
                                   C.c_float, _vp]
 _lib.bs_mlp_get_params.argtypes = [_vp, _vp]
+_lib.bs_mlp_set_fp32.argtypes = [_vp, C.c_int]
 _lib.bs_mlp_destroy.argtypes = [_vp]
 _lib.bs_ns_samples.argtypes = [C.c_int64, _vp, _vp, _vp, _vp, _vp]
 _lib.bs_ns_error_bins.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
@@ -351,6 +353,10 @@ class MLP:
     def adam_step(self, X, T, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
         _check(_lib.bs_mlp_adam_step(self._h, X.shape[0], _ptr(X), _ptr(T), lr, beta1, beta2,
                                      eps, _ptr(loss)))
+
+    def set_fp32(self, on: bool):
+        """Debug mode: FP32 weights and activations on FP32 MFMA."""
+        _check(_lib.bs_mlp_set_fp32(self._h, int(bool(on))))
 
     def params(self):
         out = np.zeros(self.nparams, dtype=np.float32)

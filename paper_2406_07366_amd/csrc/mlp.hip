@@ -1,6 +1,8 @@
 // Small MLP 8 -> 64 -> 64 -> 64 -> 3 (SiLU hidden activations) on BF16 MFMA
 // with FP32 accumulation: inference, loss gradient and Adam training.  Used
-// by the learned near-singular correction (no counterpart in the paper).
+// by the learned near-singular correction (no counterpart in the paper).  A
+// debug mode (bs_mlp_set_fp32) runs the same kernels with FP32 weights and
+// activations on FP32 MFMA, leaving only FP32 rounding in the gradients.
 //
 // Master parameters are FP32, packed W1[64][8] b1[64] W2[64][64] b2[64]
 // W3[64][64] b3[64] W4[3][64] b4[3] (9091 values).  The kernels read a padded
@@ -53,98 +55,150 @@ __device__ __forceinline__ float dsilu(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
-__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+// Precision of a kernel instance: F = false, BF16 operands on
+// v_mfma_f32_16x16x16_bf16 (the product); F = true, FP32 weights and
+// activations on v_mfma_f32_16x16x4_f32, four per 16x16x16 product (a debug
+// mode that leaves only FP32 rounding, for checking the gradients tightly).
+// The operand registers hold the same k indices in both: lane l, element j
+// is k = 4(l/16) + j; the j-th FP32 MFMA sums k = j, 4 + j, 8 + j, 12 + j.
+template <bool F> struct Prec {
+    typedef unsigned short W;   // stored weights and tiles
+    typedef bf16x4 Op;          // MFMA operand
+    static __device__ __forceinline__ W store(float v) { return f2bf(v); }
+    static __device__ __forceinline__ float elem(W w) { return bf2f(w); }
+    static __device__ __forceinline__ f32x4 mfma(Op a, Op b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void set(Op &o, int r, W w) { o[r] = (short)w; }
+};
+template <> struct Prec<true> {
+    typedef float W;
+    typedef f32x4 Op;
+    static __device__ __forceinline__ W store(float v) { return v; }
+    static __device__ __forceinline__ float elem(W w) { return w; }
+    static __device__ __forceinline__ f32x4 mfma(Op a, Op b, f32x4 c) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], c, 0, 0, 0);
+        return c;
+    }
+    static __device__ __forceinline__ void set(Op &o, int r, W w) { o[r] = w; }
+};
+
+template <bool F>
+__device__ __forceinline__ f32x4 mfma16(typename Prec<F>::Op a, typename Prec<F>::Op b, f32x4 c) {
+    return Prec<F>::mfma(a, b, c);
 }
 
 // A operand: 16x16 tile of a row-major matrix M (row stride ld), rows r0..,
 // columns c0..: lane l reads M[r0 + l%16][c0 + 4(l/16) .. +3].
-__device__ __forceinline__ bf16x4 load_a(const unsigned short *M, int ld, int r0, int c0, int l) {
-    const unsigned short *p = M + (r0 + (l & 15)) * ld + c0 + 4 * (l >> 4);
-    bf16x4 v;
-    v[0] = (short)p[0]; v[1] = (short)p[1]; v[2] = (short)p[2]; v[3] = (short)p[3];
+template <bool F>
+__device__ __forceinline__ typename Prec<F>::Op load_a(const typename Prec<F>::W *M, int ld,
+                                                       int r0, int c0, int l) {
+    const typename Prec<F>::W *p = M + (r0 + (l & 15)) * ld + c0 + 4 * (l >> 4);
+    typename Prec<F>::Op v;
+    for (int r = 0; r < 4; r++) Prec<F>::set(v, r, p[r]);
     return v;
 }
 // A operand of the transpose: A[i][k] = M[k][i], i.e. lane l reads
 // M[c0 + 4(l/16) + j][r0 + l%16], j = 0..3.
-__device__ __forceinline__ bf16x4 load_at(const unsigned short *M, int ld, int r0, int c0, int l) {
-    bf16x4 v;
+template <bool F>
+__device__ __forceinline__ typename Prec<F>::Op load_at(const typename Prec<F>::W *M, int ld,
+                                                        int r0, int c0, int l) {
+    typename Prec<F>::Op v;
     int i = r0 + (l & 15), k = c0 + 4 * (l >> 4);
-    v[0] = (short)M[(k + 0) * ld + i]; v[1] = (short)M[(k + 1) * ld + i];
-    v[2] = (short)M[(k + 2) * ld + i]; v[3] = (short)M[(k + 3) * ld + i];
+    for (int r = 0; r < 4; r++) Prec<F>::set(v, r, M[(k + r) * ld + i]);
     return v;
 }
-__device__ __forceinline__ bf16x4 to_bf(f32x4 x) {
-    bf16x4 v;
-    v[0] = (short)f2bf(x[0]); v[1] = (short)f2bf(x[1]);
-    v[2] = (short)f2bf(x[2]); v[3] = (short)f2bf(x[3]);
+template <bool F>
+__device__ __forceinline__ typename Prec<F>::Op to_op(f32x4 x) {
+    typename Prec<F>::Op v;
+    for (int r = 0; r < 4; r++) Prec<F>::set(v, r, Prec<F>::store(x[r]));
     return v;
 }
 
+template <bool F>
 struct Fwd {
     f32x4 z1[4], z2[4], z3[4];   // pre-activations, blocks of 16 features
-    bf16x4 x;                    // input operand (hi/lo halves)
+    typename Prec<F>::Op x;      // input operand (BF16: hi/lo halves; FP32: x, 0)
     f32x4 y;                     // outputs (rows 0..2 valid in lanes 0..15)
 };
 
-// forward pass for samples s0 .. s0+15 (tail masked by B)
-__device__ __forceinline__ void mlp_tile_forward(const unsigned short *W, const float *b,
-                                                 const float *__restrict__ X, int64_t B,
-                                                 int64_t s0, int l, Fwd &f) {
+// input operand of the samples s0 .. s0+15: lanes 0..31 carry features 0..7,
+// lanes 32..63 (the duplicated columns of W1p) the BF16 remainder x - hi, or
+// zero in FP32
+template <bool F>
+__device__ __forceinline__ typename Prec<F>::Op input_op(const float *__restrict__ X, int64_t B,
+                                                         int64_t s0, int l) {
     const int g = l >> 4;
-    int64_t s = s0 + (l & 15);
+    const int64_t s = s0 + (l & 15);
     float xv[4] = {0.f, 0.f, 0.f, 0.f};
     if (s < B) {
         const float *xs = X + 8 * s + 4 * (g & 1);
         for (int r = 0; r < 4; r++) {
-            float v = xs[r];
-            float hi = bf2f(f2bf(v));
-            xv[r] = (g < 2) ? hi : v - hi;
+            const float v = xs[r];
+            if (F) {
+                xv[r] = (g < 2) ? v : 0.f;
+            } else {
+                const float hi = bf2f(f2bf(v));
+                xv[r] = (g < 2) ? hi : v - hi;
+            }
         }
     }
-    for (int r = 0; r < 4; r++) f.x[r] = (short)f2bf(xv[r]);
-    bf16x4 h[4];
+    typename Prec<F>::Op x;
+    for (int r = 0; r < 4; r++) Prec<F>::set(x, r, Prec<F>::store(xv[r]));
+    return x;
+}
+
+// forward pass for samples s0 .. s0+15 (tail masked by B)
+template <bool F>
+__device__ __forceinline__ void mlp_tile_forward(const typename Prec<F>::W *W, const float *b,
+                                                 const float *__restrict__ X, int64_t B,
+                                                 int64_t s0, int l, Fwd<F> &f) {
+    const int g = l >> 4;
+    f.x = input_op<F>(X, B, s0, l);
+    typename Prec<F>::Op h[4];
     for (int ob = 0; ob < 4; ob++) {
         f32x4 acc;
         for (int r = 0; r < 4; r++) acc[r] = b[kB1 + 16 * ob + 4 * g + r];
-        acc = mfma16(load_a(W + kW1p, 16, 16 * ob, 0, l), f.x, acc);
+        acc = mfma16<F>(load_a<F>(W + kW1p, 16, 16 * ob, 0, l), f.x, acc);
         f.z1[ob] = acc;
     }
     for (int ob = 0; ob < 4; ob++) {
         f32x4 a = f.z1[ob];
         for (int r = 0; r < 4; r++) a[r] = silu(a[r]);
-        h[ob] = to_bf(a);
+        h[ob] = to_op<F>(a);
     }
     for (int ob = 0; ob < 4; ob++) {
         f32x4 acc;
         for (int r = 0; r < 4; r++) acc[r] = b[kB2 + 16 * ob + 4 * g + r];
-        for (int kb = 0; kb < 4; kb++) acc = mfma16(load_a(W + kW2, 64, 16 * ob, 16 * kb, l), h[kb], acc);
+        for (int kb = 0; kb < 4; kb++) acc = mfma16<F>(load_a<F>(W + kW2, 64, 16 * ob, 16 * kb, l), h[kb], acc);
         f.z2[ob] = acc;
     }
     for (int ob = 0; ob < 4; ob++) {
         f32x4 a = f.z2[ob];
         for (int r = 0; r < 4; r++) a[r] = silu(a[r]);
-        h[ob] = to_bf(a);
+        h[ob] = to_op<F>(a);
     }
     for (int ob = 0; ob < 4; ob++) {
         f32x4 acc;
         for (int r = 0; r < 4; r++) acc[r] = b[kB3 + 16 * ob + 4 * g + r];
-        for (int kb = 0; kb < 4; kb++) acc = mfma16(load_a(W + kW3, 64, 16 * ob, 16 * kb, l), h[kb], acc);
+        for (int kb = 0; kb < 4; kb++) acc = mfma16<F>(load_a<F>(W + kW3, 64, 16 * ob, 16 * kb, l), h[kb], acc);
         f.z3[ob] = acc;
     }
     for (int ob = 0; ob < 4; ob++) {
         f32x4 a = f.z3[ob];
         for (int r = 0; r < 4; r++) a[r] = silu(a[r]);
-        h[ob] = to_bf(a);
+        h[ob] = to_op<F>(a);
     }
     f32x4 acc;
     for (int r = 0; r < 4; r++) acc[r] = b[kB4p + 4 * g + r];
-    for (int kb = 0; kb < 4; kb++) acc = mfma16(load_a(W + kW4p, 64, 0, 16 * kb, l), h[kb], acc);
+    for (int kb = 0; kb < 4; kb++) acc = mfma16<F>(load_a<F>(W + kW4p, 64, 0, 16 * kb, l), h[kb], acc);
     f.y = acc;
 }
 
-__device__ void load_weights_lds(const unsigned short *__restrict__ wg, const float *__restrict__ bg,
-                                 unsigned short *W, float *b) {
+template <typename WT>
+__device__ void load_weights_lds(const WT *__restrict__ wg, const float *__restrict__ bg,
+                                 WT *W, float *b) {
     for (int i = threadIdx.x; i < kWpad; i += blockDim.x) W[i] = wg[i];
     for (int i = threadIdx.x; i < kBpad; i += blockDim.x) b[i] = bg[i];
 }
@@ -154,28 +208,30 @@ __device__ void load_weights_lds(const unsigned short *__restrict__ wg, const fl
 // bias of the network held in registers across the wavefront's tiles (40
 // A operands and 13 bias blocks, read from LDS once): a tile then costs its
 // 40 MFMAs, 192 SiLUs per sample and the input and output accesses only.
+template <bool F>
 __global__ __launch_bounds__(256) void k_mlp_infer(int64_t B, const int *__restrict__ Bdev,
                                                    const float *__restrict__ X,
-                                                   const unsigned short *__restrict__ wg,
+                                                   const typename Prec<F>::W *__restrict__ wg,
                                                    const float *__restrict__ bg,
                                                    float *__restrict__ Y) {
-    __shared__ unsigned short W[kWpad];
+    typedef typename Prec<F>::Op Op;
+    __shared__ typename Prec<F>::W W[kWpad];
     __shared__ float b[kBpad];
     load_weights_lds(wg, bg, W, b);
     __syncthreads();
     if (Bdev) B = *Bdev;
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int g = l >> 4;
-    bf16x4 A1[4], A2[4][4], A3[4][4], A4[4];
+    Op A1[4], A2[4][4], A3[4][4], A4[4];
     f32x4 C1[4], C2[4], C3[4], C4;
 #pragma unroll
     for (int ob = 0; ob < 4; ob++) {
-        A1[ob] = load_a(W + kW1p, 16, 16 * ob, 0, l);
-        A4[ob] = load_a(W + kW4p, 64, 0, 16 * ob, l);
+        A1[ob] = load_a<F>(W + kW1p, 16, 16 * ob, 0, l);
+        A4[ob] = load_a<F>(W + kW4p, 64, 0, 16 * ob, l);
 #pragma unroll
         for (int kb = 0; kb < 4; kb++) {
-            A2[ob][kb] = load_a(W + kW2, 64, 16 * ob, 16 * kb, l);
-            A3[ob][kb] = load_a(W + kW3, 64, 16 * ob, 16 * kb, l);
+            A2[ob][kb] = load_a<F>(W + kW2, 64, 16 * ob, 16 * kb, l);
+            A3[ob][kb] = load_a<F>(W + kW3, 64, 16 * ob, 16 * kb, l);
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -189,47 +245,36 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int64_t B, const int *__restr
     const int64_t ntiles = (B + 15) / 16;
     for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntiles; t += (int64_t)gridDim.x * nw) {
         const int64_t s = 16 * t + (l & 15);
-        float xv[4] = {0.f, 0.f, 0.f, 0.f};
-        if (s < B) {
-            const float *xs = X + 8 * s + 4 * (g & 1);
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const float v = xs[r];
-                const float hi = bf2f(f2bf(v));
-                xv[r] = (g < 2) ? hi : v - hi;
-            }
-        }
-        bf16x4 x, h[4], hn[4];
-#pragma unroll
-        for (int r = 0; r < 4; r++) x[r] = (short)f2bf(xv[r]);
+        const Op x = input_op<F>(X, B, 16 * t, l);
+        Op h[4], hn[4];
 #pragma unroll
         for (int ob = 0; ob < 4; ob++) {
-            f32x4 a = mfma16(A1[ob], x, C1[ob]);
+            f32x4 a = mfma16<F>(A1[ob], x, C1[ob]);
 #pragma unroll
             for (int r = 0; r < 4; r++) a[r] = silu(a[r]);
-            h[ob] = to_bf(a);
+            h[ob] = to_op<F>(a);
         }
 #pragma unroll
         for (int ob = 0; ob < 4; ob++) {
             f32x4 acc = C2[ob];
 #pragma unroll
-            for (int kb = 0; kb < 4; kb++) acc = mfma16(A2[ob][kb], h[kb], acc);
+            for (int kb = 0; kb < 4; kb++) acc = mfma16<F>(A2[ob][kb], h[kb], acc);
 #pragma unroll
             for (int r = 0; r < 4; r++) acc[r] = silu(acc[r]);
-            hn[ob] = to_bf(acc);
+            hn[ob] = to_op<F>(acc);
         }
 #pragma unroll
         for (int ob = 0; ob < 4; ob++) {
             f32x4 acc = C3[ob];
 #pragma unroll
-            for (int kb = 0; kb < 4; kb++) acc = mfma16(A3[ob][kb], hn[kb], acc);
+            for (int kb = 0; kb < 4; kb++) acc = mfma16<F>(A3[ob][kb], hn[kb], acc);
 #pragma unroll
             for (int r = 0; r < 4; r++) acc[r] = silu(acc[r]);
-            h[ob] = to_bf(acc);
+            h[ob] = to_op<F>(acc);
         }
         f32x4 y = C4;
 #pragma unroll
-        for (int kb = 0; kb < 4; kb++) y = mfma16(A4[kb], h[kb], y);
+        for (int kb = 0; kb < 4; kb++) y = mfma16<F>(A4[kb], h[kb], y);
         if (g == 0 && s < B)
             for (int r = 0; r < 3; r++) Y[3 * s + r] = y[r];
     }
@@ -238,28 +283,30 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int64_t B, const int *__restr
 // ------------------------------------------------------------- training
 // adds dZ^T H for one 16-sample tile into the LDS gradient accumulator G
 // (out x in, row stride kin): Tz holds dZ [16][kout] and Th holds H [16][kin]
-// as bf16.
-__device__ __forceinline__ void acc_dw(const unsigned short *Tz, int kout,
-                                       const unsigned short *Th, int kin, float *G, int l) {
+// in the instance's precision.
+template <bool F>
+__device__ __forceinline__ void acc_dw(const typename Prec<F>::W *Tz, int kout,
+                                       const typename Prec<F>::W *Th, int kin, float *G, int l) {
     const int g = l >> 4;
     for (int ob = 0; ob < kout / 16; ob++)
         for (int ib = 0; ib < kin / 16; ib++) {
-            bf16x4 a, bb;
+            typename Prec<F>::Op a, bb;
             for (int r = 0; r < 4; r++) {
-                a[r] = (short)Tz[(4 * g + r) * kout + 16 * ob + (l & 15)];
-                bb[r] = (short)Th[(4 * g + r) * kin + 16 * ib + (l & 15)];
+                Prec<F>::set(a, r, Tz[(4 * g + r) * kout + 16 * ob + (l & 15)]);
+                Prec<F>::set(bb, r, Th[(4 * g + r) * kin + 16 * ib + (l & 15)]);
             }
             f32x4 d = {0.f, 0.f, 0.f, 0.f};
-            d = mfma16(a, bb, d);
+            d = mfma16<F>(a, bb, d);
             for (int r = 0; r < 4; r++) G[(16 * ob + 4 * g + r) * kin + 16 * ib + (l & 15)] += d[r];
         }
 }
 
 // store a D-layout block (features 16*ob + 4g + r of sample l%16) into a
-// [16][k] bf16 tile
-__device__ __forceinline__ void store_tile(unsigned short *T, int k, int ob, f32x4 v, int l) {
+// [16][k] tile
+template <bool F>
+__device__ __forceinline__ void store_tile(typename Prec<F>::W *T, int k, int ob, f32x4 v, int l) {
     const int g = l >> 4;
-    for (int r = 0; r < 4; r++) T[(l & 15) * k + 16 * ob + 4 * g + r] = f2bf(v[r]);
+    for (int r = 0; r < 4; r++) T[(l & 15) * k + 16 * ob + 4 * g + r] = Prec<F>::store(v[r]);
 }
 
 // bias gradient: sum over the 16 samples (lanes sharing l/16)
@@ -271,41 +318,44 @@ __device__ __forceinline__ void acc_db(f32x4 v, float *G, int base, int ob, int 
     }
 }
 
-__device__ __forceinline__ void hidden_back(const unsigned short *W, float *G, int woff, int boff,
-                                            const f32x4 (&zp)[4], f32x4 (&dz)[4],
-                                            unsigned short *Tz, unsigned short *Th, bool valid,
-                                            int l) {
+template <bool F>
+__device__ __forceinline__ void hidden_back(const typename Prec<F>::W *W, float *G, int woff,
+                                            int boff, const f32x4 (&zp)[4], f32x4 (&dz)[4],
+                                            typename Prec<F>::W *Tz, typename Prec<F>::W *Th,
+                                            bool valid, int l) {
     for (int ob = 0; ob < 4; ob++) {
         f32x4 h = zp[ob];
         for (int r = 0; r < 4; r++) h[r] = valid ? silu(h[r]) : 0.f;
-        store_tile(Th, 64, ob, h, l);
-        store_tile(Tz, 64, ob, dz[ob], l);
+        store_tile<F>(Th, 64, ob, h, l);
+        store_tile<F>(Tz, 64, ob, dz[ob], l);
     }
     __syncthreads();
-    acc_dw(Tz, 64, Th, 64, G + woff, l);
+    acc_dw<F>(Tz, 64, Th, 64, G + woff, l);
     for (int ob = 0; ob < 4; ob++) acc_db(dz[ob], G, kWpad + boff, ob, l);
     __syncthreads();
-    bf16x4 dzb[4];
-    for (int ob = 0; ob < 4; ob++) dzb[ob] = to_bf(dz[ob]);
+    typename Prec<F>::Op dzb[4];
+    for (int ob = 0; ob < 4; ob++) dzb[ob] = to_op<F>(dz[ob]);
     for (int ob = 0; ob < 4; ob++) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         for (int kb = 0; kb < 4; kb++)
-            acc = mfma16(load_at(W + woff, 64, 16 * ob, 16 * kb, l), dzb[kb], acc);
+            acc = mfma16<F>(load_at<F>(W + woff, 64, 16 * ob, 16 * kb, l), dzb[kb], acc);
         for (int r = 0; r < 4; r++) acc[r] *= dsilu(zp[ob][r]);
         dz[ob] = acc;
     }
 }
 
+template <bool F>
 __global__ __launch_bounds__(64) void k_mlp_train(int64_t B, const float *__restrict__ X,
                                                   const float *__restrict__ T, float scale,
-                                                  const unsigned short *__restrict__ wg,
+                                                  const typename Prec<F>::W *__restrict__ wg,
                                                   const float *__restrict__ bg,
                                                   float *__restrict__ partial,
                                                   float *__restrict__ loss_partial) {
-    __shared__ unsigned short W[kWpad];
+    typedef typename Prec<F>::W WT;
+    __shared__ WT W[kWpad];
     __shared__ float b[kBpad];
     __shared__ float G[kGpad];
-    __shared__ unsigned short Tz[16 * 64], Th[16 * 64];
+    __shared__ WT Tz[16 * 64], Th[16 * 64];
     load_weights_lds(wg, bg, W, b);
     for (int i = threadIdx.x; i < kGpad; i += blockDim.x) G[i] = 0.f;
     __syncthreads();
@@ -313,8 +363,8 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t B, const float *__rest
     const int64_t ntiles = (B + 15) / 16;
     float lsum = 0.f;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        Fwd f;
-        mlp_tile_forward(W, b, X, B, 16 * t, l, f);
+        Fwd<F> f;
+        mlp_tile_forward<F>(W, b, X, B, 16 * t, l, f);
         const int64_t s = 16 * t + (l & 15);
         const bool valid = s < B;
         // dZ4 = (y - t) * scale on rows 0..2
@@ -326,33 +376,33 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t B, const float *__rest
                 dz4[r] = d * scale;
             }
         // layer 4: dW4 (16 x 64) += dZ4^T H3
-        bf16x4 dz4b = to_bf(dz4);
+        typename Prec<F>::Op dz4b = to_op<F>(dz4);
         for (int ob = 0; ob < 4; ob++) {
             f32x4 h = f.z3[ob];
             for (int r = 0; r < 4; r++) h[r] = valid ? silu(h[r]) : 0.f;
-            store_tile(Th, 64, ob, h, l);
+            store_tile<F>(Th, 64, ob, h, l);
         }
-        store_tile(Tz, 16, 0, dz4, l);
+        store_tile<F>(Tz, 16, 0, dz4, l);
         __syncthreads();
-        acc_dw(Tz, 16, Th, 64, G + kW4p, l);
+        acc_dw<F>(Tz, 16, Th, 64, G + kW4p, l);
         acc_db(dz4, G, kWpad + kB4p, 0, l);
         __syncthreads();
         // dH3 = W4^T dZ4 ; dZ3 = dH3 * silu'(z3)
         f32x4 dz[4];
         for (int ob = 0; ob < 4; ob++) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = mfma16(load_at(W + kW4p, 64, 16 * ob, 0, l), dz4b, acc);
+            acc = mfma16<F>(load_at<F>(W + kW4p, 64, 16 * ob, 0, l), dz4b, acc);
             for (int r = 0; r < 4; r++) acc[r] *= dsilu(f.z3[ob][r]);
             dz[ob] = acc;
         }
         // layers 3 and 2: dW += dZ^T H(prev); dZ(prev) = (W^T dZ) * silu'(z(prev))
-        hidden_back(W, G, kW3, kB3, f.z2, dz, Tz, Th, valid, l);
-        hidden_back(W, G, kW2, kB2, f.z1, dz, Tz, Th, valid, l);
+        hidden_back<F>(W, G, kW3, kB3, f.z2, dz, Tz, Th, valid, l);
+        hidden_back<F>(W, G, kW2, kB2, f.z1, dz, Tz, Th, valid, l);
         // layer 1: dW1p (64 x 16) += dZ1^T Xp
-        for (int r = 0; r < 4; r++) Th[(l & 15) * 16 + 4 * g + r] = (unsigned short)f.x[r];
-        for (int ob = 0; ob < 4; ob++) store_tile(Tz, 64, ob, dz[ob], l);
+        for (int r = 0; r < 4; r++) Th[(l & 15) * 16 + 4 * g + r] = (WT)f.x[r];
+        for (int ob = 0; ob < 4; ob++) store_tile<F>(Tz, 64, ob, dz[ob], l);
         __syncthreads();
-        acc_dw(Tz, 64, Th, 16, G + kW1p, l);
+        acc_dw<F>(Tz, 64, Th, 16, G + kW1p, l);
         for (int ob = 0; ob < 4; ob++) acc_db(dz[ob], G, kWpad + kB1, ob, l);
         __syncthreads();
     }
@@ -417,9 +467,10 @@ __global__ void k_mlp_fold(const float *__restrict__ gp, float *__restrict__ gra
     grad[i] = v;
 }
 
-// master FP32 -> padded BF16 weights + FP32 biases
+// master FP32 -> padded BF16 weights (and the same image in FP32, for the
+// FP32 debug mode) + FP32 biases
 __global__ void k_mlp_pack(const float *__restrict__ P, unsigned short *__restrict__ wg,
-                           float *__restrict__ bg) {
+                           float *__restrict__ wf, float *__restrict__ bg) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kWpad) {
         float v = 0.f;
@@ -428,6 +479,7 @@ __global__ void k_mlp_pack(const float *__restrict__ P, unsigned short *__restri
         else if (i < kW4p) v = P[4736 + (i - kW3)];
         else { int o = (i - kW4p) / 64, c = (i - kW4p) % 64; v = o < 3 ? P[8896 + o * 64 + c] : 0.f; }
         wg[i] = f2bf(v);
+        wf[i] = v;
     }
     if (i < kBpad) {
         float v;
@@ -461,7 +513,9 @@ struct bs_mlp_s {
     hipStream_t stream = nullptr;
     float *P = nullptr, *m = nullptr, *v = nullptr, *G = nullptr;
     unsigned short *wg = nullptr;
+    float *wf = nullptr;     // FP32 image of the padded weights (debug mode)
     float *bg = nullptr;
+    int fp32 = 0;            // 1: FP32 weights and activations (debug mode)
     float *partial = nullptr, *loss_partial = nullptr, *loss = nullptr, *gpad = nullptr;
     int nb = 512;
     int64_t step = 0;
@@ -475,8 +529,12 @@ void mlp_forward_device(bs_mlp_t M, const int *Bdev, int64_t Bmax, const float *
                         hipStream_t stream) {
     int64_t tiles = (Bmax + 15) / 16;
     int blocks = (int)std::min<int64_t>(std::max<int64_t>((tiles + 3) / 4, 1), 2048);
-    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, stream, Bmax, Bdev, X, M->wg,
-                       M->bg, Y);
+    if (M->fp32)
+        hipLaunchKernelGGL(k_mlp_infer<true>, dim3(blocks), dim3(256), 0, stream, Bmax, Bdev, X,
+                           (const float *)M->wf, M->bg, Y);
+    else
+        hipLaunchKernelGGL(k_mlp_infer<false>, dim3(blocks), dim3(256), 0, stream, Bmax, Bdev, X,
+                           (const unsigned short *)M->wg, M->bg, Y);
 }
 }  // namespace bs
 
@@ -492,6 +550,7 @@ int bs_mlp_create(const float *params_host, void *hip_stream, bs_mlp_t *out) {
     auto al = [&](void **p, size_t bytes) { if (e == hipSuccess) e = hipMalloc(p, bytes); };
     al((void **)&M->P, kNP * 4); al((void **)&M->m, kNP * 4); al((void **)&M->v, kNP * 4);
     al((void **)&M->G, kNP * 4); al((void **)&M->wg, kWpad * 2); al((void **)&M->bg, kBpad * 4);
+    al((void **)&M->wf, kWpad * 4);
     al((void **)&M->partial, (size_t)M->nb * kGpad * 4);
     al((void **)&M->loss_partial, M->nb * 4); al((void **)&M->loss, 4);
     al((void **)&M->gpad, kGpad * 4);
@@ -500,7 +559,7 @@ int bs_mlp_create(const float *params_host, void *hip_stream, bs_mlp_t *out) {
     (void)hipMemset(M->m, 0, kNP * 4);
     (void)hipMemset(M->v, 0, kNP * 4);
     hipLaunchKernelGGL(k_mlp_pack, dim3(ceil_div(kWpad, 256)), dim3(256), 0, M->stream, M->P,
-                       M->wg, M->bg);
+                       M->wg, M->wf, M->bg);
     *out = M;
     return hipGetLastError() == hipSuccess ? BS_OK : BS_EDEVICE;
 }
@@ -510,16 +569,26 @@ int bs_mlp_forward(bs_mlp_t M, int64_t B, const float *X, float *Y) {
     if (B == 0) return BS_OK;
     int64_t tiles = (B + 15) / 16;
     int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 4096);
-    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, M->stream, B, (const int *)nullptr,
-                       X, M->wg, M->bg, Y);
+    if (M->fp32)
+        hipLaunchKernelGGL(k_mlp_infer<true>, dim3(blocks), dim3(256), 0, M->stream, B,
+                           (const int *)nullptr, X, (const float *)M->wf, M->bg, Y);
+    else
+        hipLaunchKernelGGL(k_mlp_infer<false>, dim3(blocks), dim3(256), 0, M->stream, B,
+                           (const int *)nullptr, X, (const unsigned short *)M->wg, M->bg, Y);
     return hipGetLastError() == hipSuccess ? BS_OK : BS_EDEVICE;
 }
 
 static int mlp_grad(bs_mlp_t M, int64_t B, const float *X, const float *T) {
     int64_t tiles = (B + 15) / 16;
     int blocks = (int)std::min<int64_t>(tiles, M->nb);
-    hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(64), 0, M->stream, B, X, T,
-                       1.0f / (float)B, M->wg, M->bg, M->partial, M->loss_partial);
+    if (M->fp32)
+        hipLaunchKernelGGL(k_mlp_train<true>, dim3(blocks), dim3(64), 0, M->stream, B, X, T,
+                           1.0f / (float)B, (const float *)M->wf, M->bg, M->partial,
+                           M->loss_partial);
+    else
+        hipLaunchKernelGGL(k_mlp_train<false>, dim3(blocks), dim3(64), 0, M->stream, B, X, T,
+                           1.0f / (float)B, (const unsigned short *)M->wg, M->bg, M->partial,
+                           M->loss_partial);
     hipLaunchKernelGGL(k_mlp_reduce_pad, dim3(kRedBlocks + 1), dim3(256), 0, M->stream, blocks,
                        M->partial, M->loss_partial, M->gpad, M->loss);
     hipLaunchKernelGGL(k_mlp_fold, dim3(ceil_div(kNP, 256)), dim3(256), 0, M->stream, M->gpad,
@@ -547,9 +616,15 @@ int bs_mlp_adam_step(bs_mlp_t M, int64_t B, const float *X, const float *T, floa
     hipLaunchKernelGGL(k_adam, dim3(ceil_div(kNP, 256)), dim3(256), 0, M->stream, kNP, M->P, M->G,
                        M->m, M->v, lr, beta1, beta2, eps, c1, c2);
     hipLaunchKernelGGL(k_mlp_pack, dim3(ceil_div(kWpad, 256)), dim3(256), 0, M->stream, M->P,
-                       M->wg, M->bg);
+                       M->wg, M->wf, M->bg);
     if (loss_dev) (void)hipMemcpyAsync(loss_dev, M->loss, 4, hipMemcpyDeviceToDevice, M->stream);
     return hipGetLastError() == hipSuccess ? BS_OK : BS_EDEVICE;
+}
+
+int bs_mlp_set_fp32(bs_mlp_t M, int enable) {
+    if (!M) return BS_EINVAL;
+    M->fp32 = enable ? 1 : 0;
+    return BS_OK;
 }
 
 int bs_mlp_get_params(bs_mlp_t M, float *params_host) {
@@ -562,8 +637,8 @@ int bs_mlp_get_params(bs_mlp_t M, float *params_host) {
 int bs_mlp_destroy(bs_mlp_t M) {
     if (!M) return BS_OK;
     (void)hipStreamSynchronize(M->stream);
-    void *all[] = {M->P, M->m, M->v, M->G, M->wg, M->bg, M->partial, M->loss_partial, M->loss,
-                   M->gpad};
+    void *all[] = {M->P, M->m, M->v, M->G, M->wg, M->wf, M->bg, M->partial, M->loss_partial,
+                   M->loss, M->gpad};
     for (void *p : all)
         if (p) (void)hipFree(p);
     delete M;
