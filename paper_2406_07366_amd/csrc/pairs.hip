@@ -19,14 +19,22 @@ namespace bs {
 // One wavefront (four on small inputs) per target node.  Each lane holds one of the
 // 4 x 4 x 4 cells around the target; the cells' contents are enumerated as one
 // flattened range, 64 candidates per step (every lane busy, independent
-// loads).  The range is mapped to point indices in chunks of kMapCap: every
+// loads).  Only about a fifth of the candidates lie within r_c; in float64
+// their separations are queued in LDS and their erfc / exp terms evaluated
+// 64 at a time, so that the costly part runs with every lane busy (the
+// float64 kernel was bound by those terms run for a whole wavefront per
+// step: 3.5 -> 2.9 ms at 1e6 nodes).  The range is mapped to point indices
+// in chunks of kMapCap: every
 // lane writes its cell's run of point indices into the wavefront's own LDS
 // map, and each candidate then takes its point index with one LDS read.  The
 // partial sums are combined by a fixed xor-shuffle tree (deterministic order).
 constexpr int kMapCap = 1024;
+// accepted candidates queued per wavefront (a ring of two steps' worth)
+constexpr int kQueue = 128;
 
 template <typename R, bool PSI, int WPN>
-__global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double rc, double alpha,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs(
+    int N, int nc, double L, double rc, double alpha,
                                                const int *__restrict__ nperm,
                                                const double *__restrict__ x,
                                                const int *__restrict__ off,
@@ -40,6 +48,13 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
     static_assert(WPN == 1 || WPN == 4, "1 or 4 wavefronts per target");
     __shared__ R red[4][3];
     __shared__ int pmap[4][kMapCap];
+    // float64 only: in float32 the terms are cheap enough that the queue's
+    // LDS round trips cost more than the idle lanes (measured slower)
+    constexpr bool kQueued = sizeof(R) == 8;
+    __shared__ R qbuf[kQueued ? 4 : 1][3][kQueued ? kQueue : 1];
+    __shared__ int qpid[kQueued ? 4 : 1][kQueued ? kQueue : 1];
+    const unsigned long long below = ((threadIdx.x & 63) == 0) ? 0ull
+                                                               : (~0ull >> (64 - (threadIdx.x & 63)));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // WPN = 1: four targets per workgroup; WPN = 4: one target, its
     // candidate chunks dealt round-robin to the four wavefronts
@@ -93,9 +108,56 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
     R acc0 = 0, acc1 = 0, acc2 = 0;
     static_assert(kMapCap % (64 * WPN) == 0, "chunks keep the lanes' candidate order");
     int *map = pmap[wave];
+    R *qx = qbuf[kQueued ? wave : 0][0], *qy = qbuf[kQueued ? wave : 0][1],
+      *qz = qbuf[kQueued ? wave : 0][2];
+    int *qp = qpid[kQueued ? wave : 0];
     const int cs0 = __shfl(cs, 0);   // one cell (nc < 4): point index = cs0 + q
+    // the kernel term of one candidate within r_c, separation f
+    auto term = [&](R fx, R fy, R fz, int p) {
+        const R r2 = fx * fx + fy * fy + fz * fz;
+        const R rr = sqrt(r2);
+        const R ar = a * rr;
+        const R ec = erfc(ar);
+        const R *qq = schg + 4 * (size_t)p;
+        const R q0v = qq[0], q1v = qq[1], q2v = qq[2];
+        if (PSI) {
+            const R f = ec / rr;
+            acc0 += f * q0v; acc1 += f * q1v; acc2 += f * q2v;
+        } else {
+            const R g = ec + two_over_sqrtpi * ar * exp(-ar * ar);
+            const R f = g / (r2 * rr);
+            acc0 += f * (fy * q2v - fz * q1v);
+            acc1 += f * (fz * q0v - fx * q2v);
+            acc2 += f * (fx * q1v - fy * q0v);
+        }
+    };
+    // separation test of candidate q of the chunk from c0: the minimum-image
+    // separation (float64, then in R) and whether it lies within r_c
+    auto test = [&](int q, int c0, R &fx, R &fy, R &fz, int &p) {
+        p = ncell > 1 ? map[q - c0] : cs0 + q;
+        const int sg = sseg[p];
+        const double4 sp = spos[p];
+        if (sg == o || sg == ip) return false;
+        double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
+        rx -= L * rint(rx * invL);
+        ry -= L * rint(ry * invL);
+        rz -= L * rint(rz * invL);
+        fx = (R)rx; fy = (R)ry; fz = (R)rz;
+        const R r2 = fx * fx + fy * fy + fz * fz;
+        return r2 < rc2 && r2 != (R)0;
+    };
+    // float64: ring of accepted candidates, positions [head, tail)
+    // (wavefront-uniform); the terms of n <= 64 queued ones, one per lane
+    int head = 0, tail = 0;
+    auto drain = [&](int n) {
+        if (lane < n) {
+            const int sl = (head + lane) & (kQueue - 1);
+            term(qx[sl], qy[sl], qz[sl], qp[sl]);
+        }
+        head += n;
+    };
     // chunks start at multiples of kMapCap (a multiple of 64 WPN), so every
-    // lane meets its candidates in the same order as in one flat range
+    // wavefront meets its candidates in the same order as in one flat range
     for (int c0 = 0; c0 < total; c0 += kMapCap) {
         const int cend = min(total, c0 + kMapCap);
         if (ncell > 1) {
@@ -103,36 +165,37 @@ __global__ __launch_bounds__(256) void k_pairs(int N, int nc, double L, double r
             for (int j = lo; j < hi; j++) map[j - c0] = cs + (j - excl);
             wave_lds_sync();
         }
-        for (int q = c0 + part * 64 + lane; q < cend; q += 64 * WPN) {
-            const int p = ncell > 1 ? map[q - c0] : cs0 + q;
-            const int sg = sseg[p];
-            const double4 sp = spos[p];
-            if (sg == o || sg == ip) continue;
-            double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
-            rx -= L * rint(rx * invL);
-            ry -= L * rint(ry * invL);
-            rz -= L * rint(rz * invL);
-            const R fx = (R)rx, fy = (R)ry, fz = (R)rz;
-            const R r2 = fx * fx + fy * fy + fz * fz;
-            if (!(r2 < rc2) || r2 == (R)0) continue;
-            const R rr = sqrt(r2);
-            const R ar = a * rr;
-            const R ec = erfc(ar);
-            const R *qq = schg + 4 * (size_t)p;
-            const R q0v = qq[0], q1v = qq[1], q2v = qq[2];
-            if (PSI) {
-                const R f = ec / rr;
-                acc0 += f * q0v; acc1 += f * q1v; acc2 += f * q2v;
-            } else {
-                const R g = ec + two_over_sqrtpi * ar * exp(-ar * ar);
-                const R f = g / (r2 * rr);
-                acc0 += f * (fy * q2v - fz * q1v);
-                acc1 += f * (fz * q0v - fx * q2v);
-                acc2 += f * (fx * q1v - fy * q0v);
+        if constexpr (kQueued) {
+            for (int qb = c0 + part * 64; qb < cend; qb += 64 * WPN) {
+                // separation test of 64 candidates; the accepted ones (about
+                // a fifth) are queued in candidate order, and their erfc /
+                // exp terms run 64 at a time with every lane busy
+                const int q = qb + lane;
+                R fx = 0, fy = 0, fz = 0;
+                int p = 0;
+                const bool ok = q < cend && test(q, c0, fx, fy, fz, p);
+                const unsigned long long m = __ballot(ok);
+                if (ok) {
+                    const int sl = (tail + __popcll(m & below)) & (kQueue - 1);
+                    qx[sl] = fx; qy[sl] = fy; qz[sl] = fz; qp[sl] = p;
+                }
+                tail += __popcll(m);
+                wave_lds_sync();
+                if (tail - head >= 64) {
+                    drain(64);
+                    wave_lds_sync();   // slots read before the next step writes them
+                }
+            }
+        } else {
+            for (int q = c0 + part * 64 + lane; q < cend; q += 64 * WPN) {
+                R fx, fy, fz;
+                int p;
+                if (test(q, c0, fx, fy, fz, p)) term(fx, fy, fz, p);
             }
         }
-        if (ncell > 1) wave_lds_sync();   // reads done before the next chunk is written
+        if (ncell > 1) wave_lds_sync();   // map reads done before the next chunk is written
     }
+    if constexpr (kQueued) drain(tail - head);   // fewer than 64 left
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) {
         acc0 += __shfl_xor(acc0, m, 64);
