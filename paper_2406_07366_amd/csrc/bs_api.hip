@@ -480,6 +480,7 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
                 (rc = ensure<int>(P, P->ns_tfill, nb3 + 1)) || (rc = ensure<int>(P, P->ns_tperm, N)) ||
                 (rc = ensure<double4>(P, P->ns_segA, N)) || (rc = ensure<double4>(P, P->ns_segB, N)) ||
                 (rc = ensure<float4>(P, P->ns_segM, N)) ||
+                (rc = ensure<float4>(P, P->ns_segH, N)) ||
                 (rc = ensure<int2>(P, P->ns_slots, mp)) || (rc = ensure<int>(P, P->ns_cnt, N + 1)) ||
                 (rc = ensure<int>(P, P->ns_start, N + 1)) || (rc = ensure<int2>(P, P->ns_pairs, mp)) ||
                 (rc = ensure<int>(P, P->ns_pnode, mp)) || (rc = ensure<double>(P, P->ns_pout, 3 * mp)))
@@ -904,7 +905,7 @@ int bs_destroy(bs_plan_t P) {
                    &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
                    &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->e_D, &P->e_S, &P->d_vls, &P->ns_red, &P->ns_nc, &P->ns_ckey,
                    &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_tkey, &P->ns_tcnt,
-                   &P->ns_tstart, &P->ns_tfill, &P->ns_tperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_slots,
+                   &P->ns_tstart, &P->ns_tfill, &P->ns_tperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_segH, &P->ns_slots,
                    &P->ns_cnt, &P->ns_start, &P->ns_pairs, &P->ns_pnode, &P->ns_pout,
                    &P->ns_X, &P->ns_Y, &P->ns_fallback, &P->ns_learn, &P->ns_fblist, &P->ns_vs, &P->rk_k,
                    &P->rk_s};

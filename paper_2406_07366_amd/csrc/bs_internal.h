@@ -108,14 +108,16 @@ struct bs_plan_s {
     bs::DBuf ns_ckey, ns_ccnt, ns_cstart, ns_cfill, ns_cperm;   // segments by midpoint cell
     bs::DBuf ns_tkey, ns_tcnt, ns_tstart, ns_tfill, ns_tperm;   // targets by node cell
     bs::DBuf ns_segA, ns_segB;                 // double4 [N] cell-ordered end points
-    bs::DBuf ns_segM;                          // float4 [N] midpoint and reach (prefilter)
+    bs::DBuf ns_segM, ns_segH;                 // float4 [N] flag-test capsules (midpoint,
+                                               // eta ell; half chord, periods)
     bs::DBuf ns_slots;                         // int2 [N][max_per_node] per-node flag output
     bs::DBuf ns_cnt, ns_start, ns_pairs, ns_pnode, ns_pout;
     // learned correction
     bs_mlp_t mlp = nullptr;
     float ns_err[16] = {};
     bs::DBuf ns_X, ns_Y;                       // features, outputs of the learned pairs
-    bs::DBuf ns_fallback;                      // int32 [2]: learned pairs, plain-integrator pairs
+    bs::DBuf ns_fallback;                      // int32 [4]: learned pairs, plain-integrator pairs,
+                                               // gate open, gate closed (set on the device)
     bs::DBuf ns_learn;                         // int32 [pairs]: pairs the network takes
     bs::DBuf ns_fblist;                        // int32 [pairs]: pairs the learned
                                                // path hands to the graded panels

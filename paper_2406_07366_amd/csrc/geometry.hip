@@ -13,8 +13,9 @@
 // unique, so this is the same curve as the paper's B-spline form.  The
 // cyclic tridiagonal system is solved by parallel cyclic reduction, one
 // workgroup per filament: each step eliminates the neighbours at distance
-// d = 2^s, squaring the off-diagonal to diagonal ratio (<= 1/2 here), so
-// after 7 steps they are below 1e-19 and D_i = r_i / b_i.
+// d = 2^s, which shrinks the off-diagonal to diagonal ratio from 1/2 to
+// below rounding in kPcrSteps = 6 steps (the bound is below), after which
+// D_i = r_i / b_i.
 //
 // Quintic splines (App. B, k = 6) use the same idea with quintic Hermite
 // segments: node values s_i, slopes D_i and second derivatives S_i; C3 and C4
@@ -106,7 +107,7 @@ __device__ void pcr_solve(int n, PcrArrays A, PcrArrays B) {
         PcrArrays t = src; src = dst; dst = t;
         d *= 2;
     }
-    // after an odd number of steps the result is in B
+    // the last step wrote B if kPcrSteps is odd, A if it is even
 }
 
 // slopes D of the cubic spline through the nodal data x of one filament

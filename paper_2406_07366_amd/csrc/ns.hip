@@ -196,26 +196,45 @@ __global__ __launch_bounds__(64) void k_ns_sort(const int *__restrict__ ncp,
     }
 }
 
+// period index of v (floor(v / L), clamped to +-511) and v wrapped into the
+// box by it; kept consistent so that v = w + L k up to rounding
+__device__ __forceinline__ int period_of(double v, double L, double *w) {
+    double k = floor(v / L);
+    k = k < -511.0 ? -511.0 : (k > 511.0 ? 511.0 : k);
+    *w = v - L * k;
+    return (int)k;
+}
+__device__ __forceinline__ int pack_periods(const int *k) {
+    return ((k[0] + 512) << 20) | ((k[1] + 512) << 10) | (k[2] + 512);
+}
+
 // cell-ordered copies of each segment's end points, weight ell and index,
-// and the float32 sphere (wrapped chord midpoint, reach) of the prefilter
+// and the float32 capsule of the flag test: chord midpoint moved into the
+// box and eta ell (segM), half chord and the midpoint's packed period
+// indices (segH)
 __global__ void k_ns_gather(int N, const int *__restrict__ perm, const double *__restrict__ x,
                             const double *__restrict__ xn,
                             const double *__restrict__ ell, double eta, double L,
                             double4 *__restrict__ segA, double4 *__restrict__ segB,
-                            float4 *__restrict__ segM) {
+                            float4 *__restrict__ segM, float4 *__restrict__ segH) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int j = perm[p];
     segA[p] = make_double4(x[3 * j], x[3 * j + 1], x[3 * j + 2], ell[j]);
     segB[p] = make_double4(xn[3 * j], xn[3 * j + 1], xn[3 * j + 2], (double)j);
-    double c2 = 0.0, m[3];
+    double m[3], h[3];
+    int k[3];
     for (int q = 0; q < 3; q++) {
-        const double d = xn[3 * j + q] - x[3 * j + q];
-        c2 += d * d;
-        m[q] = wrap_box(0.5 * (x[3 * j + q] + xn[3 * j + q]), L);
+        h[q] = 0.5 * (xn[3 * j + q] - x[3 * j + q]);
+        k[q] = period_of(0.5 * (x[3 * j + q] + xn[3 * j + q]), L, &m[q]);
     }
+    // a midpoint beyond the clamped period range gets a negative eta ell,
+    // which sends every test against it to the float64 decision
+    const bool clamped = abs(k[0]) == 511 || abs(k[1]) == 511 || abs(k[2]) == 511;
     segM[p] = make_float4((float)m[0], (float)m[1], (float)m[2],
-                          (float)(eta * ell[j] + 0.5 * sqrt(c2)));
+                          clamped ? -1.f : (float)(eta * ell[j]));
+    segH[p] = make_float4((float)h[0], (float)h[1], (float)h[2],
+                          __int_as_float(pack_periods(k)));
 }
 
 // chord distance from x to segment A->B with A, B shifted by the minimum
@@ -240,16 +259,18 @@ struct NsArgs {
     int N, max_per_node;
     double L, eta;
     const double *x;
-    const int *off, *fil, *nperm, *ncp, *cstart;
+    const int *off, *fil, *nperm, *ncp, *cstart, *segj;
     const double4 *segA, *segB;
-    const float4 *segM;
+    const float4 *segM, *segH;
 };
 
 // Target of a flag test: the node, its previous node (the two adjacent
-// segments are excluded), its position in float64 and wrapped float32.
+// segments are excluded), its position in float32 moved into the box with
+// its period indices (packed as in segH); exact: beyond the clamped period
+// range, every test in float64.
 struct NsTarget {
-    int o, ip;
-    double x[3];
+    int o, ip, kp;
+    bool exact;
     float xf[3];
 };
 
@@ -257,35 +278,82 @@ __device__ __forceinline__ NsTarget ns_target(const NsArgs &a, int o) {
     NsTarget T;
     T.o = o;
     T.ip = prev_node_d(a.off, a.fil, o);
+    int k[3];
     for (int q = 0; q < 3; q++) {
-        T.x[q] = a.x[3 * o + q];
-        T.xf[q] = (float)wrap_box(T.x[q], a.L);
+        double w;
+        k[q] = period_of(a.x[3 * o + q], a.L, &w);
+        T.xf[q] = (float)w;
     }
+    T.kp = pack_periods(k);
+    T.exact = abs(k[0]) == 511 || abs(k[1]) == 511 || abs(k[2]) == 511;
     return T;
 }
 
-// Does segment record p (cell order) flag target T?  First a float32 test
-// against the sphere (chord midpoint, reach) that holds every target the
-// segment can flag, with a margin that covers the float32 rounding of both
-// points; then the float64 chord distance < eta * ell.  On success returns
-// the segment index and the target's image shift, periods per axis packed as
-// three 10-bit fields (+-511 periods).
-__device__ __forceinline__ bool ns_test(const NsArgs &a, const NsTarget &T, float4 M4, int p,
-                                        int *sg_out, int *sh_out) {
-    const float Lf = (float)a.L, iLf = (float)(1.0 / a.L), margin = (float)(1e-5 * a.L);
-    float dx = T.xf[0] - M4.x, dy = T.xf[1] - M4.y, dz = T.xf[2] - M4.z;
-    dx -= Lf * rintf(dx * iLf); dy -= Lf * rintf(dy * iLf); dz -= Lf * rintf(dz * iLf);
-    const float r = M4.w + margin;
-    if (!(dx * dx + dy * dy + dz * dz < r * r)) return false;
+// The float64 decision: chord distance < eta * ell for segment record p
+// (cell order); on success the segment index and the target's image shift,
+// periods per axis packed as three 10-bit fields (+-511 periods).
+__device__ __forceinline__ bool ns_test_exact(const NsArgs &a, const NsTarget &T, int p,
+                                           int *sg_out, int *sh_out) {
     const double4 A4 = a.segA[p], B4 = a.segB[p];
     const int sg = (int)B4.w;
     if (sg == T.o || sg == T.ip) return false;
     const double A[3] = {A4.x, A4.y, A4.z}, Bv[3] = {B4.x, B4.y, B4.z};
+    const double x[3] = {a.x[3 * T.o], a.x[3 * T.o + 1], a.x[3 * T.o + 2]};
     double xs[3];
-    if (!(chord_dist(A, Bv, T.x, a.L, xs) < a.eta * A4.w)) return false;
+    if (!(chord_dist(A, Bv, x, a.L, xs) < a.eta * A4.w)) return false;
     int sh = 0;
     for (int q = 0; q < 3; q++) {
-        int sv = (int)rint((xs[q] - T.x[q]) / a.L);
+        int sv = (int)rint((xs[q] - x[q]) / a.L);
+        sv = sv < -511 ? -511 : (sv > 511 ? 511 : sv);
+        sh = (sh << 10) | (sv + 512);
+    }
+    *sg_out = sg;
+    *sh_out = sh;
+    return true;
+}
+
+// Does segment record p flag target T?  The capsule test in float32: the
+// distance from the target to the chord (midpoint M4, half chord H4, minimum
+// image of the midpoint) against eta ell (M4.w).  Both points carry at most a
+// few 1e-8 L of rounding, so a distance more than 1e-5 L inside or outside
+// the capsule decides as the float64 test would; the band between, and
+// targets near half a period from the midpoint (where the image could
+// differ), go to the float64 test.  An accepted target's image shift follows
+// from the period indices: the float64 test shifts the target by
+// -rint((x - m) / L) periods, and x - m = (x_box - m_box) + L (k_x - k_m).
+__device__ __forceinline__ bool ns_test(const NsArgs &a, const NsTarget &T, float4 M4, float4 H4,
+                                        int p, int *sg_out, int *sh_out) {
+    const float Lf = (float)a.L, iLf = (float)(1.0 / a.L), band = (float)(1e-5 * a.L);
+    float d[3], w[3], far = 0.f;
+    const float m[3] = {M4.x, M4.y, M4.z}, h[3] = {H4.x, H4.y, H4.z};
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const float t = (T.xf[q] - m[q]) * iLf;
+        w[q] = rintf(t);
+        far = fmaxf(far, fabsf(t - w[q]));
+        d[q] = fmaf(-Lf, w[q], T.xf[q] - m[q]);
+    }
+    const float hh = h[0] * h[0] + h[1] * h[1] + h[2] * h[2];
+    float u = (d[0] * h[0] + d[1] * h[1] + d[2] * h[2]) * __builtin_amdgcn_rcpf(hh);
+    u = hh > 0.f ? fminf(fmaxf(u, -1.f), 1.f) : 0.f;
+    float r2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const float e = fmaf(-u, h[q], d[q]);
+        r2 = fmaf(e, e, r2);
+    }
+    const float lo = M4.w - band, hi = M4.w + band;
+    if (!(lo > 0.f) || far > 0.45f || T.exact) return ns_test_exact(a, T, p, sg_out, sh_out);
+    if (r2 >= hi * hi) return false;
+    if (r2 > lo * lo) return ns_test_exact(a, T, p, sg_out, sh_out);
+    const int sg = a.segj[p];
+    if (sg == T.o || sg == T.ip) return false;
+    const int km = __float_as_int(H4.w);
+    int sh = 0;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const int sh_q = 20 - 10 * q;
+        int sv = -(((T.kp >> sh_q) & 1023) - ((km >> sh_q) & 1023) + (int)w[q]);
         sv = sv < -511 ? -511 : (sv > 511 ? 511 : sv);
         sh = (sh << 10) | (sv + 512);
     }
@@ -346,7 +414,8 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
         for (int q0 = 0; q0 < total; q0 += 64) {
             const int q = q0 + lane;
             int sg = 0, sh = 0;
-            const bool flag = q < total && ns_test(a, T, a.segM[s0 + q], s0 + q, &sg, &sh);
+            const bool flag =
+                q < total && ns_test(a, T, a.segM[s0 + q], a.segH[s0 + q], s0 + q, &sg, &sh);
             const unsigned long long m = __ballot(flag);
             if (flag) {
                 const int slot = k + __popcll(m & below);
@@ -367,17 +436,17 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
 // takes targets w, w + 4, ...  and scans each chunk 64 candidates per step.
 // Flagged candidates are ranked with a ballot, so each target's pairs are
 // written in candidate order to its max_per_node slots.  Targets are taken
-// 256 at a time (their running counts live in LDS).  Staging 1024 records at
-// a time and at most 84 VGPRs keep six wavefronts per SIMD (measured faster
-// than larger stages at lower occupancy).
-constexpr int kNsStage = 1024;
+// 256 at a time (their running counts live in LDS).  Records of 36 B (two
+// float4 capsules and the index), 640 at a time, and at most 96 VGPRs keep
+// five wavefronts per SIMD.
+constexpr int kNsStage = 640;
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_ns_flag_cells(NsArgs a, const int *__restrict__ tstart,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_ns_flag_cells(NsArgs a, const int *__restrict__ tstart,
                                                        const int *__restrict__ tperm,
                                                        int *__restrict__ cnt,
                                                        int2 *__restrict__ slots,
                                                        int *__restrict__ status) {
-    __shared__ float4 sm[kNsStage];
+    __shared__ float4 sm[kNsStage], sh4[kNsStage];
     __shared__ int sp[kNsStage];
     // window: the 27 A-cells (entries 0..26), then the B-cells (27..90)
     constexpr int kWin = 27 + 64;
@@ -444,6 +513,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                     }
                     const int p = cell_s[c] + (q - cell_o[c]);
                     sm[i] = a.segM[p];
+                    sh4[i] = a.segH[p];
                     sp[i] = p;
                 }
                 __syncthreads();
@@ -454,7 +524,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                     for (int j0 = 0; j0 < cn; j0 += 64) {
                         const int j = j0 + lane;
                         int sg = 0, sh = 0;
-                        const bool flag = j < cn && ns_test(a, T, sm[j], sp[j], &sg, &sh);
+                        const bool flag =
+                            j < cn && ns_test(a, T, sm[j], sh4[j], sp[j], &sg, &sh);
                         const unsigned long long m = __ballot(flag);
                         if (flag) {
                             const int slot = k + __popcll(m & below);
@@ -476,16 +547,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
 }
 
-// compact list: node o's pairs at [start[o], start[o] + cnt[o]), owner pnode
-__global__ void k_ns_compact(int64_t total_slots, int maxpn, const int *__restrict__ cnt,
+// compact list: node o's pairs at [start[o], start[o] + cnt[o]), owner
+// pnode; kNsCompactLanes lanes per node step through its used slots only
+constexpr int kNsCompactLanes = 16;
+__global__ void k_ns_compact(int N, int maxpn, const int *__restrict__ cnt,
                              const int *__restrict__ start, const int2 *__restrict__ slots,
                              int2 *__restrict__ pairs, int *__restrict__ pnode) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total_slots) return;
-    const int o = (int)(i / maxpn), s = (int)(i % maxpn);
-    if (s < cnt[o]) {
-        pairs[start[o] + s] = slots[i];
-        pnode[start[o] + s] = o;
+    const int o = (int)(i / kNsCompactLanes);
+    if (o >= N) return;
+    const int n = cnt[o], b = start[o];
+    for (int s = (int)(i % kNsCompactLanes); s < n; s += kNsCompactLanes) {
+        pairs[b + s] = slots[(size_t)o * maxpn + s];
+        pnode[b + s] = o;
     }
 }
 
@@ -1260,14 +1334,15 @@ void ns_build_pairs(bs_plan_t p) {
     hipLaunchKernelGGL(k_ns_gather, dim3(ceil_div(N, bs)), dim3(bs), 0, p->stream, N,
                        (const int *)cperm, x, xn, ell, p->prm.ns_eta, p->prm.L,
                        (double4 *)p->ns_segA.p, (double4 *)p->ns_segB.p,
-                       (float4 *)p->ns_segM.p);
+                       (float4 *)p->ns_segM.p, (float4 *)p->ns_segH.p);
     NsArgs a;
     a.N = N; a.max_per_node = p->ns_max_per_node;
     a.L = p->prm.L; a.eta = p->prm.ns_eta;
     a.x = x; a.off = off; a.fil = fil;
     a.nperm = (const int *)p->nd_perm.p; a.ncp = ncp; a.cstart = cstart;
     a.segA = (const double4 *)p->ns_segA.p; a.segB = (const double4 *)p->ns_segB.p;
-    a.segM = (const float4 *)p->ns_segM.p;
+    a.segM = (const float4 *)p->ns_segM.p; a.segH = (const float4 *)p->ns_segH.p;
+    a.segj = (const int *)cperm;
     int *cnt = (int *)p->ns_cnt.p, *start = (int *)p->ns_start.p;
     // exactly one of the two does work, depending on the cell count
     hipLaunchKernelGGL(k_ns_flag_cells, dim3(nb3 < 8192 ? nb3 : 8192), dim3(bs), 0, p->stream, a,
@@ -1277,9 +1352,8 @@ void ns_build_pairs(bs_plan_t p) {
     hipLaunchKernelGGL(k_ns_flag, dim3(nwave < 1024 ? nwave : 1024), dim3(bs), 0, p->stream, a,
                        cnt, (int2 *)p->ns_slots.p, (int *)p->d_status.p);
     exclusive_scan(p, cnt, start, N, sums);
-    const int64_t ns = (int64_t)N * p->ns_max_per_node;
-    hipLaunchKernelGGL(k_ns_compact, dim3(ceil_div(ns, bs)), dim3(bs), 0, p->stream, ns,
-                       p->ns_max_per_node, (const int *)cnt, (const int *)start,
+    hipLaunchKernelGGL(k_ns_compact, dim3(ceil_div((int64_t)N * kNsCompactLanes, bs)), dim3(bs),
+                       0, p->stream, N, p->ns_max_per_node, (const int *)cnt, (const int *)start,
                        (const int2 *)p->ns_slots.p, (int2 *)p->ns_pairs.p, (int *)p->ns_pnode.p);
 }
 

@@ -164,6 +164,7 @@ def test_near_singular_pairs_on_the_closing_segment_match_oracle(B):
     err = rel_l2(dv, ref)
     print(f"  ns term rel_l2 {err:.2e}, flagged pairs {cnt.sum()}, |dv| max {np.abs(ref).max():.2e}")
     assert cnt.sum() > 0 and err < 1e-10
+    assert plan.ns_counts()[0] == int(cnt.sum())
     # ring nodes near the closing segment (line nodes n-1 -> 0 + L e_z) are
     # among the flagged targets
     assert cnt[fs.offsets[2]:].sum() > 0 and np.abs(ref[fs.offsets[2]:]).max() > 0

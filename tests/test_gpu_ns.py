@@ -48,6 +48,8 @@ def test_ns_term_matches_oracle(B):
     dv = t["ns"].cpu().numpy()
     ref, cnt = O.Oracle(fs).ns_correction(eta=1.0)
     assert cnt.sum() > fs.n_nodes          # ring partners are flagged
+    # the flagged set: same number of pairs as the oracle's float64 test
+    assert plan.ns_counts()[0] == int(cnt.sum())
     err = rel_l2(dv, ref)
     print(f"  ns term rel_l2 {err:.2e}, flagged pairs {cnt.sum()}")
     assert err < 1e-10
