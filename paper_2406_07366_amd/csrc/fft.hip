@@ -4,12 +4,20 @@
 // operator is applied between the forward and inverse z transforms of the
 // same columns, so it costs no pass of its own.
 //
-//   x forward   grid [3][n][n][n] real (x fastest)  ->  A [3][z][y][0..K]
-//   y forward   A, FFT along y, keep my in [-K, K]  ->  B [3][my+K][z][0..K]
-//   z fused     B, FFT along z, spectral operator (modes with |mz| > K, k = 0
-//               zeroed), inverse FFT along z           ->  B (in place)
-//   y inverse   B, zero-padded inverse FFT along y  ->  A [3][z][y][0..K]
+//   x forward   grid [3][n][n][n] real (x fastest), rows r = (c n + z) n + y
+//               ->  A [0..K][3 n^2]: mode kx of every row, rows fastest
+//   y forward   A, FFT along y (sequence q = (3 kx + c) n + z is contiguous),
+//               keep my in [-K, K]   ->  B [my+K][0..K][3][n] (z fastest)
+//   z fused     B, FFT along z (contiguous), spectral operator (modes with
+//               |mz| > K, k = 0 zeroed), inverse FFT along z  ->  B in place
+//   y inverse   B, zero-padded inverse FFT along y  ->  A
 //   x inverse   A, Hermitian c2r along x             ->  grid
+//
+// Every pass reads or writes whole contiguous sequences on one side; on the
+// other it moves 128-B runs (16 float32 or 8 float64 complex values of
+// neighbouring rows or z), which is why a workgroup takes that many
+// sequences.  (On grids up to 64^3 the x and y passes are fused per plane
+// and B is laid out [3][my+K][z][0..K]; see k_fft_xy_fwd.)
 //
 // Conventions are those of an unnormalised r2c / c2r pair: forward
 // exp(-2 pi i j m / n), inverse exp(+2 pi i j m / n), no scaling (the
@@ -142,10 +150,18 @@ __host__ __device__ constexpr int plan_lr(int logn, int p) {
 // or the last are compile-time, so the index arithmetic folds to shifts
 // and masks and the pass sequence unrolls.  Each thread owns IPT items
 // (t, t + blockDim, ...), all read before the barrier and written after it.
-template <int R, int N, int NS, bool FIRST, bool LAST, bool JFAST, int IPT, typename C,
-          typename T, typename Load, typename Store>
+// The first pass applies no twiddles, so hook() (the twiddle table's own
+// copy into LDS) runs after its loads are issued: one memory round trip for
+// both.  TWCONJ: the table holds exp(-2 pi i k / n) and the pass uses its
+// conjugates (an inverse transform from the forward table).
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+template <int R, int N, int NS, bool FIRST, bool LAST, bool JFAST, int IPT, bool TWCONJ,
+          typename C, typename T, typename Load, typename Store, typename Hook>
 __device__ __forceinline__ void fft_pass(int nseq, int pitch, C *buf, const C *tw, T sgn,
-                                         Load &load, Store &store) {
+                                         Load &load, Store &store, Hook &hook) {
     constexpr int NJ = N / R;
     C v[IPT][R];
     int sv[IPT], jv[IPT];
@@ -158,19 +174,26 @@ __device__ __forceinline__ void fft_pass(int nseq, int pitch, C *buf, const C *t
         sv[it] = s;
         jv[it] = j;
         if (act[it]) {
-            const int jm = j & (NS - 1);
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 const int e = j + r * NJ;
                 if constexpr (FIRST) v[it][r] = load(s, e);
                 else v[it][r] = buf[lds_at<JFAST>(s, e, pitch)];
             }
+        }
+    }
+    if constexpr (FIRST) hook();
+#pragma unroll
+    for (int it = 0; it < IPT; it++) {
+        if (act[it]) {
             if constexpr (NS > 1) {
+                const int jm = jv[it] & (NS - 1);
                 if (jm != 0) {
                     constexpr int STEP = N / (NS * R);
 #pragma unroll
                     for (int r = 1; r < R; r++) {
-                        const C w = tw[jm * r * STEP];
+                        const C w0 = tw[jm * r * STEP];
+                        const C w = TWCONJ ? C{w0.x, -w0.y} : w0;
                         const C u = v[it][r];
                         v[it][r] = C{w.x * u.x - w.y * u.y, w.x * u.y + w.y * u.x};
                     }
@@ -196,17 +219,26 @@ __device__ __forceinline__ void fft_pass(int nseq, int pitch, C *buf, const C *t
 }
 
 // tw: the twiddle table in LDS (n entries); passes P, P+1, ... of the plan
-template <bool JFAST, int LOGN, int IPT = 1, int P = 0, int NS = 1, typename C, typename T,
-          typename Load, typename Store>
-__device__ __forceinline__ void fft_run(int nseq, int pitch, C *buf, const C *tw, T sgn,
-                                        Load &load, Store &store) {
+template <bool JFAST, int LOGN, int IPT = 1, bool TWCONJ = false, int P = 0, int NS = 1,
+          typename C, typename T, typename Load, typename Store, typename Hook>
+__device__ __forceinline__ void fft_run_h(int nseq, int pitch, C *buf, const C *tw, T sgn,
+                                          Load &load, Store &store, Hook &hook) {
     constexpr int LR = plan_lr(LOGN, P);
     if constexpr (LR > 0) {
         constexpr bool LAST = plan_lr(LOGN, P + 1) == 0;
-        fft_pass<1 << LR, 1 << LOGN, NS, P == 0, LAST, JFAST, IPT>(nseq, pitch, buf, tw, sgn,
-                                                                     load, store);
-        fft_run<JFAST, LOGN, IPT, P + 1, (NS << LR)>(nseq, pitch, buf, tw, sgn, load, store);
+        fft_pass<1 << LR, 1 << LOGN, NS, P == 0, LAST, JFAST, IPT, TWCONJ>(nseq, pitch, buf, tw,
+                                                                           sgn, load, store, hook);
+        fft_run_h<JFAST, LOGN, IPT, TWCONJ, P + 1, (NS << LR)>(nseq, pitch, buf, tw, sgn, load,
+                                                               store, hook);
     }
+}
+
+template <bool JFAST, int LOGN, int IPT = 1, bool TWCONJ = false, typename C, typename T,
+          typename Load, typename Store>
+__device__ __forceinline__ void fft_run(int nseq, int pitch, C *buf, const C *tw, T sgn,
+                                        Load &load, Store &store) {
+    NoHook none;
+    fft_run_h<JFAST, LOGN, IPT, TWCONJ>(nseq, pitch, buf, tw, sgn, load, store, none);
 }
 
 // copy ntab twiddle entries into LDS (before the first barrier of fft_run)
@@ -215,29 +247,29 @@ __device__ __forceinline__ void stage_twiddles(C *dst, const C *__restrict__ src
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) dst[i] = src[i];
 }
 
+// cnt items into LDS: store(i, load(i)), with up to B loads of each thread in
+// flight before their LDS stores (a plain loop would wait for every load)
+template <int B, typename Load, typename Store>
+__device__ __forceinline__ void gather_lds(int cnt, Load &load, Store &store) {
+    for (int i0 = threadIdx.x; i0 < cnt; i0 += B * blockDim.x) {
+        decltype(load(0)) v[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const int i = i0 + b * (int)blockDim.x;
+            if (i < cnt) v[b] = load(i);
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const int i = i0 + b * (int)blockDim.x;
+            if (i < cnt) store(i, v[b]);
+        }
+    }
+}
+
 constexpr int kFftMaxThreads = 512;
 constexpr int kFftLds = 65536;        // LDS per workgroup, at most (x, y passes)
 constexpr int kFftLdsZ = 81920;       // z pass with several items per thread (two
                                       // workgroups per CU; measured faster than one)
-
-// Persistent workgroups (inverse x pass): a launch holds 8 P workgroups (P
-// per XCD) for nlog logical blocks; the logical blocks [x per, (x + 1) per)
-// of XCD x (per = ceil(nlog / 8)) are taken by its P workgroups in turn, so
-// workgroups that run together on an XCD work on neighbouring blocks, and
-// each workgroup stages the twiddle table into LDS once for all its blocks.
-// At 512^3 in float64 the inverse x pass has 3 n^2 / 2 row pairs, and one
-// table copy per two rows cost as much as the rows (3.3 -> 1.8 ms); the y
-// and z passes, with fewer and heavier blocks, measured slower this way.
-#define FFT_BLOCKS(nlog, per)                                                        \
-    for (int li_ = (int)(blockIdx.x / 8), bid = (int)(blockIdx.x % 8) * (per) + li_;  \
-         li_ < (per) && bid < (nlog); li_ += (int)(gridDim.x / 8),                    \
-             bid = (int)(blockIdx.x % 8) * (per) + li_)
-constexpr int kFftPersistPerXcd = 256;   // at most 8 x 256 workgroups per launch
-
-static inline int persist_grid(int nlog) {
-    const int per = (nlog + 7) / 8;
-    return 8 * (per < kFftPersistPerXcd ? per : kFftPersistPerXcd);
-}
 
 // items per thread of the z pass: large float32 grids take several columns
 // per thread so that a workgroup spans enough adjacent columns mx for its
@@ -247,146 +279,240 @@ __host__ __device__ constexpr int z_ipt(int logn, int csize) {
     return logn >= 9 && csize == 8 ? 4 : 1;
 }
 
-// ---------------------------------------------------------------- x pass
-// Forward: two real rows per complex transform.  Sequence s of a workgroup
-// carries rows a = 2 (pair0 + s) and b = a + 1 as z = x_a + i x_b; the
-// spectra separate as X_a(k) = (Z(k) + conj Z(n-k)) / 2 and
-// X_b(k) = (Z(k) - conj Z(n-k)) / (2i) for the kept modes k = 0..K: half the
-// transforms and half the LDS per row (256^3: 246 -> 235 us with the y pass
-// in float64).  npairs = nrows / 2 sequences in all, nseq per workgroup.  The
-// inverse keeps one row per transform: pairing it (z = X_a + i X_b) made
-// its Hermitian loads the cost (284 -> 311 us in float64).
+// -------------------------------------------- large grids (n >= 128)
+// Sequences per workgroup: the 128-B run (16 float32 or 8 float64 complex
+// values) of the transposed side; items per thread so that a workgroup has at
+// most kFftMaxThreads threads.
+template <typename C> __host__ __device__ constexpr int run_len() { return 128 / (int)sizeof(C); }
+__host__ __device__ constexpr int min_radix_log(int logn) {
+    int m = 4;
+    for (int p = 0; plan_lr(logn, p) > 0; p++) m = plan_lr(logn, p) < m ? plan_lr(logn, p) : m;
+    return m;
+}
+__host__ __device__ constexpr int fft_ipt(int logn, int nseq) {
+    const int items = nseq * ((1 << logn) >> min_radix_log(logn));
+    return items <= kFftMaxThreads ? 1 : items / kFftMaxThreads;
+}
+__host__ __device__ constexpr int fft_threads(int logn, int nseq) {
+    return nseq * ((1 << logn) >> min_radix_log(logn)) / fft_ipt(logn, nseq);
+}
+// (my, mx) columns per z-pass workgroup (times 3 components)
+template <typename C> __host__ __device__ constexpr int z_cols() { return 2; }
+
+// x forward: run_len rows (consecutive y) per workgroup, two real rows per
+// complex transform: sequence s carries rows a = row0 + 2 s and b = a + 1 as
+// z = x_a + i x_b, and the spectra separate as X_a(k) = (Z(k) + conj Z(n-k))
+// / 2, X_b(k) = (Z(k) - conj Z(n-k)) / (2i) for the kept modes k = 0..K.
+// Mode k of the workgroup's rows goes to A[k][row0 ..] as one run.
 template <typename R, int LOGN>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int npairs, int K1,
-                                                            int nseq, int per,
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int nrows, int K1, int per,
                                                             const R *__restrict__ grid,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN;
+    constexpr int n = 1 << LOGN, ROWS = run_len<C>(), NSEQ = ROWS / 2;
+    constexpr int IPT = fft_ipt(LOGN, NSEQ);
     C *twl = (C *)smem, *buf = twl + n;
-    const int bid = xcd_block(per), nb = (npairs + nseq - 1) / nseq;
-    if (bid >= nb) return;
-    stage_twiddles(twl, tw, n);
-    const int pair0 = bid * nseq;
-    const int pitch = lds_pitch<true>(n, nseq);
+    const int bid = xcd_block(per);
+    if (bid >= nrows / ROWS) return;
+    const size_t row0 = (size_t)bid * ROWS;
+    const int pitch = lds_pitch<true>(n, NSEQ);
     auto load = [&](int s, int e) {
-        const int pr = pair0 + s;
-        C v = C{(R)0, (R)0};
-        if (pr < npairs) v = C{grid[(size_t)(2 * pr) * n + e], grid[(size_t)(2 * pr + 1) * n + e]};
-        return v;
+        return C{grid[(row0 + 2 * s) * n + e], grid[(row0 + 2 * s + 1) * n + e]};
     };
     // the spectrum Z stays in LDS (every read of the last pass precedes its
     // barrier, so its writes may go back into the same buffer)
     auto lstore = [&](int s, int e, C v) { buf[lds_at<true>(s, e, pitch)] = v; };
-    fft_run<true, LOGN>(nseq, pitch, buf, twl, (R)-1, load, lstore);
-    for (int i = threadIdx.x; i < nseq * K1; i += blockDim.x) {
-        const int s = i / K1, k = i - s * K1, pr = pair0 + s;
-        if (pr >= npairs) continue;
-        const C z = buf[lds_at<true>(s, k, pitch)];
-        const C zm = buf[lds_at<true>(s, k == 0 ? 0 : n - k, pitch)];
+    auto hook = [&]() { stage_twiddles(twl, tw, n); };
+    fft_run_h<true, LOGN, IPT>(NSEQ, pitch, buf, twl, (R)-1, load, lstore, hook);
+#pragma unroll 4
+    for (int i = threadIdx.x; i < ROWS * K1; i += blockDim.x) {
+        const int r = i % ROWS, k = i / ROWS, sq = r >> 1;
+        const C z = buf[lds_at<true>(sq, k, pitch)];
+        const C zm = buf[lds_at<true>(sq, k == 0 ? 0 : n - k, pitch)];
         const R h = (R)0.5;
-        A[(size_t)(2 * pr) * K1 + k] = C{h * (z.x + zm.x), h * (z.y - zm.y)};
-        A[(size_t)(2 * pr + 1) * K1 + k] = C{h * (z.y + zm.y), h * (zm.x - z.x)};
+        A[(size_t)k * nrows + row0 + r] = (r & 1) ? C{h * (z.y + zm.y), h * (zm.x - z.x)}
+                                                  : C{h * (z.x + zm.x), h * (z.y - zm.y)};
     }
 }
 
-// inverse: modes 0..K of each row, Hermitian completion, real part out
+// x inverse: run_len rows per workgroup; modes 0..K of each row gathered from
+// A[k][row0 ..] into LDS, Hermitian completion, real part out
 template <typename R, int LOGN>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int nrows, int K1,
-                                                            int nseq, int per,
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int nrows, int K1, int per,
                                                             const typename Cx<R>::T *__restrict__ A,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             R *__restrict__ grid) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN;
+    constexpr int n = 1 << LOGN, ROWS = run_len<C>();
+    constexpr int IPT = fft_ipt(LOGN, ROWS);
     C *twl = (C *)smem, *buf = twl + n;
-    const int nb = (nrows + nseq - 1) / nseq;
-    stage_twiddles(twl, tw, n);
-    FFT_BLOCKS(nb, per) {
-        const int row0 = bid * nseq;
-        auto load = [&](int s, int e) {
-            const int row = row0 + s;
-            C v = C{(R)0, (R)0};
-            if (row < nrows) {
-                if (e < K1) v = A[(size_t)row * K1 + e];
-                else if (n - e < K1) {
-                    const C u = A[(size_t)row * K1 + (n - e)];
-                    v = C{u.x, -u.y};
-                }
-            }
-            return v;
-        };
-        auto store = [&](int s, int e, C v) {
-            const int row = row0 + s;
-            if (row < nrows) grid[(size_t)row * n + e] = v.x;
-        };
-        fft_run<true, LOGN>(nseq, lds_pitch<true>(n, nseq), buf, twl, (R)1, load, store);
-    }
+    const int bid = xcd_block(per);
+    if (bid >= nrows / ROWS) return;
+    const size_t row0 = (size_t)bid * ROWS;
+    const int pitch = lds_pitch<true>(n, ROWS);
+    // the runs of modes 0..K, then the twiddle table, in one batched copy
+    const int nin = ROWS * K1;
+    auto gl = [&](int i) {
+        return i < nin ? A[(size_t)(i / ROWS) * nrows + row0 + i % ROWS] : tw[i - nin];
+    };
+    auto gs = [&](int i, C v) {
+        if (i < nin) buf[lds_at<true>(i % ROWS, i / ROWS, pitch)] = v;
+        else twl[i - nin] = v;
+    };
+    gather_lds<8>(nin + n, gl, gs);
+    __syncthreads();
+    auto load = [&](int s, int e) {
+        C v = C{(R)0, (R)0};
+        if (e < K1) v = buf[lds_at<true>(s, e, pitch)];
+        else if (n - e < K1) {
+            const C u = buf[lds_at<true>(s, n - e, pitch)];
+            v = C{u.x, -u.y};
+        }
+        return v;
+    };
+    auto store = [&](int s, int e, C v) { grid[(row0 + s) * n + e] = v.x; };
+    fft_run<true, LOGN, IPT>(ROWS, pitch, buf, twl, (R)1, load, store);
 }
 
-// ---------------------------------------------------------------- y pass
-// one workgroup per (c, z) and group of nseq columns mx
+// y forward: run_len sequences q = (3 kx + c) n + z0 + s (contiguous in A);
+// mode my of the workgroup's sequences goes to B[my + K][kx][c][z0 ..] as
+// one run
 template <typename R, int LOGN>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int K, int nseq, int per,
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int K, int per,
                                                             const typename Cx<R>::T *__restrict__ A,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN;
+    constexpr int n = 1 << LOGN, SEQ = run_len<C>();
+    constexpr int IPT = fft_ipt(LOGN, SEQ);
     const int K1 = K + 1, NY = 2 * K + 1;
     C *twl = (C *)smem, *buf = twl + n;
-    const int ngrp = (K1 + nseq - 1) / nseq;
     const int bid = xcd_block(per);
-    if (bid >= 3 * n * ngrp) return;
-    stage_twiddles(twl, tw, n);
-    const int g = bid % ngrp, cz = bid / ngrp;   // cz = c * n + z
-    const int c = cz >> LOGN, z = cz & (n - 1);
-    const int kx0 = g * nseq;
-    auto load = [&](int s, int e) {
-        const int kx = kx0 + s;
-        return kx < K1 ? A[((size_t)cz * n + e) * K1 + kx] : C{(R)0, (R)0};
-    };
-    auto store = [&](int s, int e, C v) {
-        const int kx = kx0 + s, my = e <= n / 2 ? e : e - n;
-        if (kx < K1 && my >= -K && my <= K)
-            B[(((size_t)c * NY + (my + K)) * n + z) * K1 + kx] = v;
-    };
-    fft_run<false, LOGN>(nseq, lds_pitch<false>(n, nseq), buf, twl, (R)-1, load, store);
+    if (bid >= 3 * n / SEQ * K1) return;
+    const size_t q0 = (size_t)bid * SEQ;
+    const int pitch = lds_pitch<true>(n, SEQ);
+    auto load = [&](int s, int e) { return A[(q0 + s) * n + e]; };
+    auto lstore = [&](int s, int e, C v) { buf[lds_at<true>(s, e, pitch)] = v; };
+    auto hook = [&]() { stage_twiddles(twl, tw, n); };
+    fft_run_h<true, LOGN, IPT>(SEQ, pitch, buf, twl, (R)-1, load, lstore, hook);
+    const size_t kxc = q0 >> LOGN;   // 3 kx + c
+    const int z0 = (int)(q0 & (n - 1));
+#pragma unroll 4
+    for (int i = threadIdx.x; i < SEQ * NY; i += blockDim.x) {
+        const int s = i % SEQ, ky = i / SEQ, my = ky - K;
+        B[((size_t)ky * 3 * K1 + kxc) * n + z0 + s] = buf[lds_at<true>(s, my < 0 ? my + n : my, pitch)];
+    }
 }
 
+// y inverse: the B runs of run_len sequences into LDS (modes |my| > K zero),
+// inverse FFT along y, whole sequences out to A
 template <typename R, int LOGN>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int K, int nseq, int per,
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int K, int per,
                                                             const typename Cx<R>::T *__restrict__ B,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN;
-    const int K1 = K + 1, NY = 2 * K + 1;
+    constexpr int n = 1 << LOGN, SEQ = run_len<C>();
+    constexpr int IPT = fft_ipt(LOGN, SEQ);
+    const int K1 = K + 1;
     C *twl = (C *)smem, *buf = twl + n;
-    const int ngrp = (K1 + nseq - 1) / nseq;
     const int bid = xcd_block(per);
-    if (bid >= 3 * n * ngrp) return;
-    stage_twiddles(twl, tw, n);
-    const int g = bid % ngrp, cz = bid / ngrp;
-    const int c = cz >> LOGN, z = cz & (n - 1);
-    const int kx0 = g * nseq;
-    auto load = [&](int s, int e) {
-        const int kx = kx0 + s, my = e <= n / 2 ? e : e - n;
+    if (bid >= 3 * n / SEQ * K1) return;
+    const size_t q0 = (size_t)bid * SEQ, kxc = q0 >> LOGN;
+    const int z0 = (int)(q0 & (n - 1));
+    const int pitch = lds_pitch<true>(n, SEQ);
+    // the runs of modes |my| <= K (the rest zero), then the twiddle table, in
+    // one batched copy
+    const int nin = SEQ * n;
+    auto gl = [&](int i) {
         C v = C{(R)0, (R)0};
-        if (kx < K1 && my >= -K && my <= K)
-            v = B[(((size_t)c * NY + (my + K)) * n + z) * K1 + kx];
+        if (i < nin) {
+            const int e = i / SEQ, my = e <= n / 2 ? e : e - n;
+            if (my >= -K && my <= K) v = B[((size_t)(my + K) * 3 * K1 + kxc) * n + z0 + i % SEQ];
+        } else {
+            v = tw[i - nin];
+        }
         return v;
     };
-    auto store = [&](int s, int e, C v) {
-        const int kx = kx0 + s;
-        if (kx < K1) A[((size_t)cz * n + e) * K1 + kx] = v;
+    auto gs = [&](int i, C v) {
+        if (i < nin) buf[lds_at<true>(i % SEQ, i / SEQ, pitch)] = v;
+        else twl[i - nin] = v;
     };
-    fft_run<false, LOGN>(nseq, lds_pitch<false>(n, nseq), buf, twl, (R)1, load, store);
+    gather_lds<8>(nin + n, gl, gs);
+    __syncthreads();
+    auto load = [&](int s, int e) { return buf[lds_at<true>(s, e, pitch)]; };
+    auto store = [&](int s, int e, C v) { A[(q0 + s) * n + e] = v; };
+    fft_run<true, LOGN, IPT>(SEQ, pitch, buf, twl, (R)1, load, store);
+}
+
+// z pass: z_cols (my, mx) columns per workgroup, their three components'
+// z-sequences contiguous in B: forward FFT into LDS, spectral operator,
+// inverse FFT from LDS, written back in place
+template <typename R, int LOGN>
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_zt_spectral(
+    int K, int per, int psi, double k0, double inv4a2, double invV,
+    const double *__restrict__ dec2, const typename Cx<R>::T *__restrict__ twf,
+    typename Cx<R>::T *__restrict__ B) {
+    typedef typename Cx<R>::T C;
+    extern __shared__ unsigned char smem[];
+    constexpr int n = 1 << LOGN, KZ = z_cols<C>(), S = 3 * KZ;
+    constexpr int IPT = fft_ipt(LOGN, S);
+    const int K1 = K + 1, ncol = (2 * K + 1) * K1;
+    C *twl = (C *)smem, *buf = twl + n;   // forward table only
+    const int bid = xcd_block(per), col0 = bid * KZ;
+    if (col0 >= ncol) return;
+    const int nseq = 3 * (ncol - col0 < KZ ? ncol - col0 : KZ);
+    C *Bw = B + (size_t)col0 * 3 * n;
+    const int pitch = lds_pitch<true>(n, S);
+    auto gload = [&](int s, int e) {
+        return s < nseq ? Bw[(size_t)s * n + e] : C{(R)0, (R)0};
+    };
+    auto lstore = [&](int s, int e, C v) { buf[lds_at<true>(s, e, pitch)] = v; };
+    auto hook = [&]() { stage_twiddles(twl, twf, n); };
+    fft_run_h<true, LOGN, IPT>(S, pitch, buf, twl, (R)-1, gload, lstore, hook);
+    for (int i = threadIdx.x; i < KZ * n; i += blockDim.x) {
+        const int kk = i >> LOGN, z = i & (n - 1), col = col0 + kk;
+        if (col >= ncol) continue;
+        const int ky = col / K1, mx = col - ky * K1, my = ky - K, mz = z <= n / 2 ? z : z - n;
+        C *G0 = buf + lds_at<true>(3 * kk, z, pitch), *G1 = buf + lds_at<true>(3 * kk + 1, z, pitch),
+          *G2 = buf + lds_at<true>(3 * kk + 2, z, pitch);
+        const int ay = my < 0 ? -my : my, az = mz < 0 ? -mz : mz;
+        if (az > K || (mx == 0 && my == 0 && mz == 0)) {
+            *G0 = *G1 = *G2 = C{(R)0, (R)0};
+            continue;
+        }
+        const double kx = k0 * mx, ky_ = k0 * my, kz = k0 * mz;
+        const double k2 = kx * kx + ky_ * ky_ + kz * kz;
+        const double f = exp(-k2 * inv4a2) / k2 * invV * dec2[mx] * dec2[ay] * dec2[az];
+        const C g0 = *G0, g1 = *G1, g2 = *G2;
+        if (psi) {
+            const R fr = (R)f;
+            *G0 = C{g0.x * fr, g0.y * fr};
+            *G1 = C{g1.x * fr, g1.y * fr};
+            *G2 = C{g2.x * fr, g2.y * fr};
+            continue;
+        }
+        // i (k x G) f
+        const R fkx = (R)(kx * f), fky = (R)(ky_ * f), fkz = (R)(kz * f);
+        const R cr0 = fky * g2.x - fkz * g1.x, ci0 = fky * g2.y - fkz * g1.y;
+        const R cr1 = fkz * g0.x - fkx * g2.x, ci1 = fkz * g0.y - fkx * g2.y;
+        const R cr2 = fkx * g1.x - fky * g0.x, ci2 = fkx * g1.y - fky * g0.y;
+        *G0 = C{-ci0, cr0};
+        *G1 = C{-ci1, cr1};
+        *G2 = C{-ci2, cr2};
+    }
+    __syncthreads();
+    auto lload = [&](int s, int e) { return buf[lds_at<true>(s, e, pitch)]; };
+    auto gstore = [&](int s, int e, C v) {
+        if (s < nseq) Bw[(size_t)s * n + e] = v;
+    };
+    // inverse from the forward table (conjugated twiddles)
+    fft_run<true, LOGN, IPT, true>(S, pitch, buf, twl, (R)1, lload, gstore);
 }
 
 // ------------------------------------------- x and y passes fused (n <= 64)
@@ -466,10 +592,11 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_yx_inv(int K, int per,
     fft_run<true, LOGN>(n, lds_pitch<true>(n, n), buf, twl, (R)1, xload, xstore);
 }
 
-// ---------------------------------------------------------------- z pass
-// one workgroup per (my, group of KZ columns mx): the three components'
-// z-columns (sequence s = c KZ + q), forward FFT into LDS, spectral operator,
-// inverse FFT from LDS, written back.
+// ------------------------------------------------ z pass (n <= 64)
+// one workgroup per (my, group of KZ columns mx) of the per-plane layout
+// B [3][my+K][z][0..K]: the three components' z-columns (sequence
+// s = c KZ + q), forward FFT into LDS, spectral operator, inverse FFT from
+// LDS, written back.
 template <typename R, int LOGN, int IPT>
 __global__ __launch_bounds__(kFftMaxThreads) void k_fft_z_spectral(
     int K, int KZ, int per, int psi, double k0, double inv4a2, double invV,
@@ -540,12 +667,6 @@ bool pruned_fft_ok(int n, size_t csize) {
            (size_t)3 * fft_max_nj(__builtin_ctz((unsigned)n)) <= kFftMaxThreads;
 }
 
-// LDS of an x-pass workgroup: twiddles + nseq skewed rows
-template <typename C>
-static size_t x_lds(int n, int nseq) {
-    return ((size_t)n + (size_t)nseq * lds_pitch<true>(n, nseq)) * sizeof(C);
-}
-
 static int ilog2(int n) {
     int l = 0;
     while ((1 << l) < n) l++;
@@ -583,12 +704,17 @@ static void with_logn(int logn, F f) {
     }
 }
 
+// LDS of a large-grid pass: ntw twiddles + nseq skewed sequences
+template <typename C>
+static size_t seq_lds(int n, int nseq, int ntw) {
+    return ((size_t)ntw + (size_t)nseq * lds_pitch<true>(n, nseq)) * sizeof(C);
+}
+
 template <typename R, int LOGN>
 static void pruned_fwd(bs_plan_t p) {
     typedef typename Cx<R>::T C;
     constexpr int n = 1 << LOGN;
     const int K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(LOGN);
-    const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twf = (const C *)p->fft_tw.p;
     if constexpr (LOGN <= kFftXYMaxLogn) {
         const size_t lds = xy_lds<C>(n, K1);
@@ -596,33 +722,49 @@ static void pruned_fwd(bs_plan_t p) {
         const int per = ceil_div(3 * n, 8);
         hipLaunchKernelGGL((k_fft_xy_fwd<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
                            K, per, (const R *)p->grid.p, twf, (C *)p->fft_B.p);
-        return;
+    } else {
+        constexpr int RUN = run_len<C>();
+        const int nrows = 3 * n * n;
+        const int px = ceil_div(nrows / RUN, 8), py = ceil_div(3 * n / RUN * K1, 8);
+        const size_t lx = seq_lds<C>(n, RUN / 2, n), ly = seq_lds<C>(n, RUN, n);
+        if (lx > 65536) allow_big_lds<k_fft_x_fwd<R, LOGN>>(p->device);
+        if (ly > 65536) allow_big_lds<k_fft_y_fwd<R, LOGN>>(p->device);
+        hipLaunchKernelGGL((k_fft_x_fwd<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, RUN / 2)),
+                           lx, p->stream, nrows, K1, px, (const R *)p->grid.p, twf,
+                           (C *)p->fft_A.p);
+        hipLaunchKernelGGL((k_fft_y_fwd<R, LOGN>), dim3(8 * py), dim3(fft_threads(LOGN, RUN)), ly,
+                           p->stream, K, py, (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
     }
-    const int px = ceil_div(ceil_div(nrows / 2, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
-    hipLaunchKernelGGL((k_fft_x_fwd<R, LOGN>), dim3(8 * px), dim3(RB * mnj), x_lds<C>(n, RB),
-                       p->stream, nrows / 2, K1, RB, px, (const R *)p->grid.p, twf,
-                       (C *)p->fft_A.p);
-    hipLaunchKernelGGL((k_fft_y_fwd<R, LOGN>), dim3(8 * py), dim3(KB * mnj),
-                       (n + n * (KB + 1)) * sizeof(C), p->stream, K, KB, py,
-                       (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
 }
 
 template <typename R, int LOGN>
 static void pruned_spectral(bs_plan_t p, int psi) {
     typedef typename Cx<R>::T C;
     constexpr int n = 1 << LOGN;
-    const int K = p->prm.K, K1 = K + 1, KZ = p->fft_kz;
+    const int K = p->prm.K, K1 = K + 1;
     const double L = p->prm.L;
     const double k0 = 2.0 * kPi / L, inv4a2 = 1.0 / (4.0 * p->prm.alpha * p->prm.alpha);
     const double *dec2 = (const double *)p->deconv.p + (p->prm.K + 1);
     const C *twf = (const C *)p->fft_tw.p, *twi = twf + n;
-    const int pz = ceil_div((2 * K + 1) * ceil_div(K1, KZ), 8);
-    constexpr int IPT = z_ipt(LOGN, (int)sizeof(C));
-    const size_t lds = (2 * n + n * (3 * KZ + 1)) * sizeof(C);
-    if (lds > 65536) allow_big_lds<k_fft_z_spectral<R, LOGN, IPT>>(p->device);
-    hipLaunchKernelGGL((k_fft_z_spectral<R, LOGN, IPT>), dim3(8 * pz),
-                       dim3(ceil_div(3 * KZ * fft_max_nj(LOGN), IPT)), lds, p->stream, K, KZ, pz,
-                       psi, k0, inv4a2, 1.0 / (L * L * L), dec2, twf, twi, (C *)p->fft_B.p);
+    if constexpr (LOGN <= kFftXYMaxLogn) {
+        const int KZ = p->fft_kz;
+        const int pz = ceil_div((2 * K + 1) * ceil_div(K1, KZ), 8);
+        constexpr int IPT = z_ipt(LOGN, (int)sizeof(C));
+        const size_t lds = (2 * n + n * (3 * KZ + 1)) * sizeof(C);
+        if (lds > 65536) allow_big_lds<k_fft_z_spectral<R, LOGN, IPT>>(p->device);
+        hipLaunchKernelGGL((k_fft_z_spectral<R, LOGN, IPT>), dim3(8 * pz),
+                           dim3(ceil_div(3 * KZ * fft_max_nj(LOGN), IPT)), lds, p->stream, K, KZ,
+                           pz, psi, k0, inv4a2, 1.0 / (L * L * L), dec2, twf, twi,
+                           (C *)p->fft_B.p);
+    } else {
+        constexpr int KZ = z_cols<C>();
+        const int pz = ceil_div(ceil_div((2 * K + 1) * K1, KZ), 8);
+        const size_t lds = seq_lds<C>(n, 3 * KZ, n);
+        if (lds > 65536) allow_big_lds<k_fft_zt_spectral<R, LOGN>>(p->device);
+        hipLaunchKernelGGL((k_fft_zt_spectral<R, LOGN>), dim3(8 * pz),
+                           dim3(fft_threads(LOGN, 3 * KZ)), lds, p->stream, K, pz, psi, k0, inv4a2,
+                           1.0 / (L * L * L), dec2, twf, (C *)p->fft_B.p);
+    }
 }
 
 template <typename R, int LOGN>
@@ -630,7 +772,6 @@ static void pruned_inv(bs_plan_t p) {
     typedef typename Cx<R>::T C;
     constexpr int n = 1 << LOGN;
     const int K = p->prm.K, K1 = K + 1, mnj = fft_max_nj(LOGN);
-    const int nrows = 3 * n * n, RB = p->fft_rb, KB = p->fft_kb;
     const C *twi = (const C *)p->fft_tw.p + n;
     if constexpr (LOGN <= kFftXYMaxLogn) {
         const size_t lds = xy_lds<C>(n, K1);
@@ -638,15 +779,20 @@ static void pruned_inv(bs_plan_t p) {
         const int per = ceil_div(3 * n, 8);
         hipLaunchKernelGGL((k_fft_yx_inv<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
                            K, per, (const C *)p->fft_B.p, twi, (R *)p->grid.p);
-        return;
+    } else {
+        constexpr int RUN = run_len<C>();
+        const int nrows = 3 * n * n;
+        const int px = ceil_div(nrows / RUN, 8), py = ceil_div(3 * n / RUN * K1, 8);
+        const size_t l = seq_lds<C>(n, RUN, n);
+        if (l > 65536) {
+            allow_big_lds<k_fft_y_inv<R, LOGN>>(p->device);
+            allow_big_lds<k_fft_x_inv<R, LOGN>>(p->device);
+        }
+        hipLaunchKernelGGL((k_fft_y_inv<R, LOGN>), dim3(8 * py), dim3(fft_threads(LOGN, RUN)), l,
+                           p->stream, K, py, (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
+        hipLaunchKernelGGL((k_fft_x_inv<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, RUN)), l,
+                           p->stream, nrows, K1, px, (const C *)p->fft_A.p, twi, (R *)p->grid.p);
     }
-    const int pxi = ceil_div(ceil_div(nrows, RB), 8), py = ceil_div(3 * n * ceil_div(K1, KB), 8);
-    hipLaunchKernelGGL((k_fft_y_inv<R, LOGN>), dim3(8 * py), dim3(KB * mnj),
-                       (n + n * (KB + 1)) * sizeof(C), p->stream, K, KB, py,
-                       (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
-    hipLaunchKernelGGL((k_fft_x_inv<R, LOGN>), dim3(persist_grid(ceil_div(nrows, RB))),
-                       dim3(RB * mnj), x_lds<C>(n, RB), p->stream, nrows, K1, RB, pxi,
-                       (const C *)p->fft_A.p, twi, (R *)p->grid.p);
 }
 
 void pruned_forward(bs_plan_t p) {
