@@ -565,10 +565,22 @@ __global__ void k_ns_compact(int N, int maxpn, const int *__restrict__ cnt,
 
 // spline segment j as c0 + c1 u + ... + c5 u^5, u in [0, 1]: the cubic
 // Hermite segment (c4 = c5 = 0) from node values and slopes, or, when the
-// nodal second derivatives S are given, the quintic Hermite segment
+// nodal second derivatives S are given, the quintic Hermite segment; the
+// derivative's coefficients k c_k are kept beside them (e2 = 2 c2, ...)
 struct Seg {
     double c0[3], c1[3], c2[3], c3[3], c4[3], c5[3];
+    double e2[3], e3[3], e4[3], e5[3];
 };
+
+// the derivative's coefficients from c0 .. c5 (every Seg is finished by it)
+__device__ __forceinline__ void seg_derivs(Seg &s) {
+    for (int q = 0; q < 3; q++) {
+        s.e2[q] = 2.0 * s.c2[q];
+        s.e3[q] = 3.0 * s.c3[q];
+        s.e4[q] = 4.0 * s.c4[q];
+        s.e5[q] = 5.0 * s.c5[q];
+    }
+}
 
 // (from node j to xn[j], its end node in the segment's own frame)
 __device__ __forceinline__ Seg load_seg(int j, const int *off, const int *fil, const double *x,
@@ -595,22 +607,41 @@ __device__ __forceinline__ Seg load_seg(int j, const int *off, const int *fil, c
             s.c4[q] = s.c5[q] = 0.0;
         }
     }
+    seg_derivs(s);
     return s;
 }
 
-// component q of s(u), s'(u), s''(u)
+// component q of s(u), s'(u), s''(u); DEG = 3 leaves out the terms that
+// vanish on cubic segments (the same values: a zero term adds exactly 0)
+template <int DEG = 5>
 __device__ __forceinline__ double seg_p(const Seg &s, int q, double u) {
+    if constexpr (DEG == 3) return s.c0[q] + u * (s.c1[q] + u * (s.c2[q] + u * s.c3[q]));
     return s.c0[q] + u * (s.c1[q] + u * (s.c2[q] + u * (s.c3[q] + u * (s.c4[q] + u * s.c5[q]))));
 }
+template <int DEG = 5>
 __device__ __forceinline__ double seg_d(const Seg &s, int q, double u) {
-    return s.c1[q] + u * (2.0 * s.c2[q] + u * (3.0 * s.c3[q] + u * (4.0 * s.c4[q] + u * 5.0 * s.c5[q])));
+    if constexpr (DEG == 3) return s.c1[q] + u * (s.e2[q] + u * s.e3[q]);
+    return s.c1[q] + u * (s.e2[q] + u * (s.e3[q] + u * (s.e4[q] + u * s.e5[q])));
 }
+template <int DEG = 5>
 __device__ __forceinline__ double seg_dd(const Seg &s, int q, double u) {
-    return 2.0 * s.c2[q] + u * (6.0 * s.c3[q] + u * (12.0 * s.c4[q] + u * 20.0 * s.c5[q]));
+    if constexpr (DEG == 3) return s.e2[q] + u * 2.0 * s.e3[q];
+    return s.e2[q] + u * (2.0 * s.e3[q] + u * (3.0 * s.e4[q] + u * 4.0 * s.e5[q]));
+}
+
+// 1 / sqrt(a) for a > 0: the hardware estimate and two Newton steps
+// y <- y (3 - a y^2) / 2 (each squares the relative error), to rounding
+__device__ __forceinline__ double rsqrt_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
 }
 
 // integral over u in [a, b] of (s(u) - x) x s'(u) / |s(u) - x|^3 with
 // kNsGL-point Gauss-Legendre
+template <int DEG = 5>
 __device__ void ns_panel(const Seg &s, const double *x, double a, double b, const NsRule &R,
                          double *acc) {
     double m = 0.5 * (a + b), hw = 0.5 * (b - a);
@@ -618,11 +649,12 @@ __device__ void ns_panel(const Seg &s, const double *x, double a, double b, cons
         double u = m + hw * R.x[k];
         double r[3], d[3];
         for (int q = 0; q < 3; q++) {
-            r[q] = seg_p(s, q, u) - x[q];
-            d[q] = seg_d(s, q, u);
+            r[q] = seg_p<DEG>(s, q, u) - x[q];
+            d[q] = seg_d<DEG>(s, q, u);
         }
-        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        double f = R.w[k] * hw / (r2 * sqrt(r2));
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double y = rsqrt_nr(r2);
+        const double f = R.w[k] * hw * (y * y * y);
         acc[0] += f * (r[1] * d[2] - r[2] * d[1]);
         acc[1] += f * (r[2] * d[0] - r[0] * d[2]);
         acc[2] += f * (r[0] * d[1] - r[1] * d[0]);
@@ -633,21 +665,24 @@ __device__ void ns_panel(const Seg &s, const double *x, double a, double b, cons
 // cubic segment: closest point by a coarse scan and Newton steps on
 // (s - x) . s' = 0, then 16-point Gauss-Legendre panels graded geometrically
 // (ratio 3) away from it.
+template <int DEG = 5>
 __device__ __forceinline__ void seg_eval(const Seg &s, double u, double *p, double *d1) {
     for (int q = 0; q < 3; q++) {
-        p[q] = seg_p(s, q, u);
-        d1[q] = seg_d(s, q, u);
+        p[q] = seg_p<DEG>(s, q, u);
+        d1[q] = seg_d<DEG>(s, q, u);
     }
 }
 
 // parameter of the point of the segment closest to x: best of a coarse scan,
-// then Newton steps on (s - x) . s' = 0 kept inside [0, 1]
+// then Newton steps on (s - x) . s' = 0 kept inside [0, 1], until a step
+// moves u by less than 1e-14
+template <int DEG = 5>
 __device__ double closest_u(const Seg &s, const double *xs) {
     double ub = 0.0, best = 1e300;
     for (int k = 0; k <= 8; k++) {
         double u = k / 8.0, r2 = 0.0;
         for (int q = 0; q < 3; q++) {
-            double r = seg_p(s, q, u) - xs[q];
+            double r = seg_p<DEG>(s, q, u) - xs[q];
             r2 += r * r;
         }
         if (r2 < best) { best = r2; ub = u; }
@@ -655,24 +690,27 @@ __device__ double closest_u(const Seg &s, const double *xs) {
     for (int it = 0; it < 8; it++) {
         double g = 0.0, dg = 0.0;
         for (int q = 0; q < 3; q++) {
-            double r = seg_p(s, q, ub) - xs[q];
-            double d1 = seg_d(s, q, ub);
-            double d2 = seg_dd(s, q, ub);
+            double r = seg_p<DEG>(s, q, ub) - xs[q];
+            double d1 = seg_d<DEG>(s, q, ub);
+            double d2 = seg_dd<DEG>(s, q, ub);
             g += r * d1;
             dg += d1 * d1 + r * d2;
         }
         if (!(dg > 0.0)) break;
         double un = ub - g / dg;
         un = un < 0.0 ? 0.0 : (un > 1.0 ? 1.0 : un);
+        const bool done = fabs(un - ub) < 1e-14;
         ub = un;
+        if (done) break;
     }
     return ub;
 }
 
+template <int DEG = 5>
 __device__ void ns_seg_integral(const Seg &s, const double *xs, const NsRule &R, double *acc) {
-    const double ub = closest_u(s, xs);
+    const double ub = closest_u<DEG>(s, xs);
     double P[3], d1[3];
-    seg_eval(s, ub, P, d1);
+    seg_eval<DEG>(s, ub, P, d1);
     const double r2 = (P[0] - xs[0]) * (P[0] - xs[0]) + (P[1] - xs[1]) * (P[1] - xs[1]) +
                       (P[2] - xs[2]) * (P[2] - xs[2]);
     const double sp2 = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
@@ -682,12 +720,12 @@ __device__ void ns_seg_integral(const Seg &s, const double *xs, const NsRule &R,
     delta = delta < 1e-13 ? 1e-13 : delta;
     acc[0] = acc[1] = acc[2] = 0.0;
     double a0 = ub - delta < 0.0 ? 0.0 : ub - delta, b0 = ub + delta > 1.0 ? 1.0 : ub + delta;
-    if (b0 > a0) ns_panel(s, xs, a0, b0, R, acc);
+    if (b0 > a0) ns_panel<DEG>(s, xs, a0, b0, R, acc);
     double edge = a0, width = delta;
     while (edge > 0.0) {
         double nxt = ub - 3.0 * width;
         if (nxt < 0.0) nxt = 0.0;
-        ns_panel(s, xs, nxt, edge, R, acc);
+        ns_panel<DEG>(s, xs, nxt, edge, R, acc);
         edge = nxt;
         width *= 3.0;
     }
@@ -695,7 +733,7 @@ __device__ void ns_seg_integral(const Seg &s, const double *xs, const NsRule &R,
     while (edge < 1.0) {
         double nxt = ub + 3.0 * width;
         if (nxt > 1.0) nxt = 1.0;
-        ns_panel(s, xs, edge, nxt, R, acc);
+        ns_panel<DEG>(s, xs, edge, nxt, R, acc);
         edge = nxt;
         width *= 3.0;
     }
@@ -708,8 +746,9 @@ __device__ void ns_qsum(int sg, const double *xs, const double *qpos, const doub
     for (int i = 0; i < Q; i++) {
         const double *qp = qpos + 3 * ((size_t)sg * Q + i), *qc = qchg + 3 * ((size_t)sg * Q + i);
         double r[3] = {qp[0] - xs[0], qp[1] - xs[1], qp[2] - xs[2]};
-        double rr2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        double f = 1.0 / (rr2 * sqrt(rr2));
+        const double rr2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double y = rsqrt_nr(rr2);
+        const double f = y * y * y;
         qs[0] += f * (r[1] * qc[2] - r[2] * qc[1]);
         qs[1] += f * (r[2] * qc[0] - r[0] * qc[2]);
         qs[2] += f * (r[0] * qc[1] - r[1] * qc[0]);
@@ -721,7 +760,9 @@ __device__ __forceinline__ void unpack_shift(int sh, const double *x, double L, 
     for (int q = 0; q < 3; q++) xs[q] = x[q] + shv[q] * L;
 }
 
-// Exact segment integral minus its Q-point sum, for one (node, segment) pair.
+// Exact segment integral minus its Q-point sum, for one (node, segment) pair
+// (DEG 3: cubic segments, S == NULL)
+template <int DEG>
 __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, const double *x,
                         const double *xn, const double *D, const double *S, const double *dtau, const double *gamma,
                         const double *qpos, const double *qchg, int Q, double L,
@@ -730,7 +771,7 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
     unpack_shift(sh, x + 3 * o, L, xs);
     Seg s = load_seg(sg, off, fil, x, xn, D, S, dtau);
     double acc[3], qs[3];
-    ns_seg_integral(s, xs, R, acc);
+    ns_seg_integral<DEG>(s, xs, R, acc);
     ns_qsum(sg, xs, qpos, qchg, Q, qs);
     const double g4 = gamma[fil[sg]] / (4.0 * kPi);
     for (int q = 0; q < 3; q++) out[q] = g4 * acc[q] - qs[q] / (4.0 * kPi);
@@ -751,8 +792,12 @@ __global__ __launch_bounds__(256) void k_ns_integrate(
         const int p = list ? list[i] : i;
         int2 pr = pairs[p];
         double out[3];
-        ns_pair(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg, Q, L, R,
-                out);
+        if (S)
+            ns_pair<5>(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg, Q, L,
+                       R, out);
+        else
+            ns_pair<3>(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg, Q, L,
+                       R, out);
         pout[3 * (size_t)p] = out[0];
         pout[3 * (size_t)p + 1] = out[1];
         pout[3 * (size_t)p + 2] = out[2];
@@ -888,6 +933,7 @@ __device__ TangentBase tangent_baseline(const Seg &s, const double *x, double h)
 // is added, which removes most of the rule's error near the peak (the
 // curve's integrand approaches the tangent's as d -> 0).  Every pair costs
 // the same (32 + 32 kernel evaluations): no panel recursion, no divergence.
+template <int DEG>
 __device__ __forceinline__ void mapped_half_seg(const Seg &s, const double *xs, double ub,
                                                 double b, double m0, double m1, const NsRule &R,
                                                 double *acc) {
@@ -900,11 +946,12 @@ __device__ __forceinline__ void mapped_half_seg(const Seg &s, const double *xs, 
         const double jac = R.w[k] * hw * b * 0.5 * (e + ei);
         double r[3], d[3];
         for (int q = 0; q < 3; q++) {
-            r[q] = seg_p(s, q, u) - xs[q];
-            d[q] = seg_d(s, q, u);
+            r[q] = seg_p<DEG>(s, q, u) - xs[q];
+            d[q] = seg_d<DEG>(s, q, u);
         }
         const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const double f = jac / (r2 * sqrt(r2));
+        const double y = rsqrt_nr(r2);
+        const double f = jac * (y * y * y);
         acc[0] += f * (r[1] * d[2] - r[2] * d[1]);
         acc[1] += f * (r[2] * d[0] - r[0] * d[2]);
         acc[2] += f * (r[0] * d[1] - r[1] * d[0]);
@@ -931,19 +978,21 @@ __device__ __forceinline__ void mapped_half_line(const double *rho, const double
         const double l = l0 + dd * 0.5 * (e - ei);
         const double jac = R.w[k] * hw * dd * 0.5 * (e + ei);
         const double r2 = rr + 2.0 * l * rt + l * l;
-        sum += jac / (r2 * sqrt(r2));
+        const double y = rsqrt_nr(r2);
+        sum += jac * (y * y * y);
     }
     acc[0] -= sum * c[0];
     acc[1] -= sum * c[1];
     acc[2] -= sum * c[2];
 }
 
+template <int DEG>
 __device__ void ns_seg_mapped(const Seg &s, const double *xs, const NsRule &R, double *acc) {
-    const double ub = closest_u(s, xs);
+    const double ub = closest_u<DEG>(s, xs);
     double P[3], d1[3], S0[3], S1[3], dummy[3];
-    seg_eval(s, ub, P, d1);
-    seg_eval(s, 0.0, S0, dummy);
-    seg_eval(s, 1.0, S1, dummy);
+    seg_eval<DEG>(s, ub, P, d1);
+    seg_eval<DEG>(s, 0.0, S0, dummy);
+    seg_eval<DEG>(s, 1.0, S1, dummy);
     double dist2 = 0.0, sp2 = 0.0, la = 0.0, lb = 0.0;
     for (int q = 0; q < 3; q++) {
         dist2 += (P[q] - xs[q]) * (P[q] - xs[q]);
@@ -956,8 +1005,8 @@ __device__ void ns_seg_mapped(const Seg &s, const double *xs, const NsRule &R, d
     double b = sqrt(dist2) / sn;
     b = b < 1e-13 ? 1e-13 : b;
     acc[0] = acc[1] = acc[2] = 0.0;
-    mapped_half_seg(s, xs, ub, b, asinh(-ub / b), 0.0, R, acc);
-    mapped_half_seg(s, xs, ub, b, 0.0, asinh((1.0 - ub) / b), R, acc);
+    mapped_half_seg<DEG>(s, xs, ub, b, asinh(-ub / b), 0.0, R, acc);
+    mapped_half_seg<DEG>(s, xs, ub, b, 0.0, asinh((1.0 - ub) / b), R, acc);
     // control variate: tangent segment at P
     double t[3], rho[3], A[3], B[3], cv[3];
     for (int q = 0; q < 3; q++) {
@@ -982,6 +1031,7 @@ __device__ void ns_seg_mapped(const Seg &s, const double *xs, const NsRule &R, d
 }
 
 // mapped segment integral minus the Q-point sum, for one (node, segment) pair
+template <int DEG>
 __device__ void ns_pair_mapped(int o, int sg, int sh, const int *off, const int *fil,
                                const double *x, const double *xn, const double *D,
                                const double *S, const double *dtau, const double *gamma,
@@ -991,7 +1041,7 @@ __device__ void ns_pair_mapped(int o, int sg, int sh, const int *off, const int 
     unpack_shift(sh, x + 3 * o, L, xs);
     Seg s = load_seg(sg, off, fil, x, xn, D, S, dtau);
     double acc[3], qs[3];
-    ns_seg_mapped(s, xs, R, acc);
+    ns_seg_mapped<DEG>(s, xs, R, acc);
     ns_qsum(sg, xs, qpos, qchg, Q, qs);
     const double g4 = gamma[fil[sg]] / (4.0 * kPi);
     for (int q = 0; q < 3; q++) out[q] = g4 * acc[q] - qs[q] / (4.0 * kPi);
@@ -1010,8 +1060,12 @@ __global__ __launch_bounds__(256) void k_ns_mapped(
         const int p = list ? list[i] : i;
         const int2 pr = pairs[p];
         double out[3];
-        ns_pair_mapped(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg, Q,
-                       L, R, out);
+        if (S)
+            ns_pair_mapped<5>(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg,
+                              Q, L, R, out);
+        else
+            ns_pair_mapped<3>(pnode[p], pr.x, pr.y, off, fil, x, xn, D, S, dtau, gamma, qpos, qchg,
+                              Q, L, R, out);
         pout[3 * (size_t)p] = out[0];
         pout[3 * (size_t)p + 1] = out[1];
         pout[3 * (size_t)p + 2] = out[2];
@@ -1115,8 +1169,9 @@ __global__ void k_ns_samples(int64_t n, const double *__restrict__ U, NsRule R,
         s.c3[q] = 2.0 * (A[q] - B[q]) + D0[q] + D1[q];
         s.c4[q] = s.c5[q] = 0.0;
     }
+    seg_derivs(s);
     double I[3];
-    ns_seg_integral(s, x, R, I);
+    ns_seg_integral<3>(s, x, R, I);
     const TangentBase tb = tangent_baseline(s, x, 1.0);
     NsFrame F = ns_frame(A, B, D0, D1, x);
     for (int k = 0; k < 8; k++) X[8 * i + k] = F.f[k];
