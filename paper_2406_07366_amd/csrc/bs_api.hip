@@ -90,15 +90,19 @@ static void kernel_ft_table(int K, int w, int n, double zeta, double *F) {
     }
 }
 
-// 16-point Gauss-Legendre rule for the near-singular panels
+// Gauss-Legendre rules of the near-singular integrals: 16 points (the mapped
+// rule, each side of the peak) and 12 points (the graded panels)
 struct NsRule {
-    double x[16];
-    double w[16];
+    double x[16], w[16];
+    double x12[12], w12[12];
 };
 void ns_rule(NsRule *R) {
-    static NsRule cached;
-    static bool have = false;
-    if (!have) { legendre_rule(16, cached.x, cached.w); have = true; }
+    static const NsRule cached = [] {
+        NsRule r;
+        legendre_rule(16, r.x, r.w);
+        legendre_rule(12, r.x12, r.w12);
+        return r;
+    }();
     *R = cached;
 }
 
