@@ -453,6 +453,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     // window: the 27 A-cells (entries 0..26), then the B-cells (27..90)
     constexpr int kWin = 27 + 64;
     __shared__ int cell_s[kWin], cell_o[kWin], tk[256], tot_a, tot_b;
+    __shared__ int t_o[256], t_ip[256], t_kp[256];   // targets of the group (kp bit 30: exact)
+    __shared__ float t_xf[3][256];
     const int nc = a.ncp[0], ncb = a.ncp[1];
     if (nc < 3) return;
     const int nb3 = nc * nc * nc;
@@ -503,7 +505,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const int total = tot_a + tot_b;
         for (int g0 = 0; g0 < nt; g0 += 256) {
             const int ng = nt - g0 < 256 ? nt - g0 : 256;
-            for (int i = threadIdx.x; i < ng; i += blockDim.x) tk[i] = 0;
+            // each target's flag-test data, once (one thread per target; the
+            // chunk loop below reads it from LDS)
+            for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+                const NsTarget T = ns_target(a, tperm[t0 + g0 + i]);
+                tk[i] = 0;
+                t_o[i] = T.o;
+                t_ip[i] = T.ip;
+                t_kp[i] = T.kp | (T.exact ? 1 << 30 : 0);
+                t_xf[0][i] = T.xf[0]; t_xf[1][i] = T.xf[1]; t_xf[2][i] = T.xf[2];
+            }
             for (int c0 = 0; c0 < total; c0 += kNsStage) {
                 const int cn = total - c0 < kNsStage ? total - c0 : kNsStage;
                 for (int i = threadIdx.x; i < cn; i += blockDim.x) {
@@ -520,7 +531,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 }
                 __syncthreads();
                 for (int ti = wave; ti < ng; ti += 4) {
-                    const NsTarget T = ns_target(a, tperm[t0 + g0 + ti]);
+                    NsTarget T;
+                    T.o = t_o[ti];
+                    T.ip = t_ip[ti];
+                    T.kp = t_kp[ti] & ((1 << 30) - 1);
+                    T.exact = (t_kp[ti] >> 30) & 1;
+                    T.xf[0] = t_xf[0][ti]; T.xf[1] = t_xf[1][ti]; T.xf[2] = t_xf[2][ti];
                     int2 *out = slots + (size_t)T.o * a.max_per_node;
                     int k = tk[ti];
                     for (int j0 = 0; j0 < cn; j0 += 64) {
@@ -540,7 +556,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 __syncthreads();
             }
             for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-                const int o = tperm[t0 + g0 + i], k = tk[i];
+                const int o = t_o[i], k = tk[i];
                 if (k > a.max_per_node) atomicOr(status, 2);
                 cnt[o] = k < a.max_per_node ? k : a.max_per_node;
             }
