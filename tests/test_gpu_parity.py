@@ -289,8 +289,9 @@ def test_pruned_transforms_agree_with_hipfft(B, precision, grid_n):
     streamfunction and energy agree with the full hipFFT r2c / c2r path to
     rounding (float64) or float32 rounding (mixed), on every radix plan the
     workloads use (32 = 8.4 and 64 = 8.8, whose x and y passes run fused per
-    plane, 128 = 16.8, 256 = 16.16, 512 = 8.8.8, whose z pass takes four
-    columns per thread)."""
+    plane, and 128 = 16.8, 256 = 16.16, 512 = 8.8.8, whose passes exchange
+    transposed intermediate arrays; the 512 plans take two items per thread
+    in float32)."""
     out = _pruned_vs_library(B, precision, grid_n)
     (va, pa, Ea), (vb, pb, Eb) = out[B.BS_FFT_PRUNED], out[B.BS_FFT_LIBRARY]
     tol = 1e-12 if precision == 0 else 2e-6
