@@ -284,6 +284,13 @@ __host__ __device__ constexpr int z_ipt(int logn, int csize) {
 // values) of the transposed side; items per thread so that a workgroup has at
 // most kFftMaxThreads threads.
 template <typename C> __host__ __device__ constexpr int run_len() { return 128 / (int)sizeof(C); }
+// rows per x-pass workgroup, sequences per y-pass workgroup (the inverse y
+// pass measured faster at 8 sequences in float32 too: 64-B runs, half the LDS,
+// twice the workgroups per CU: 1.23 -> 1.05 ms for the inverse at 512^3;
+// the forward pass and the x passes slower that way)
+template <typename C> __host__ __device__ constexpr int x_rows() { return run_len<C>(); }
+template <typename C> __host__ __device__ constexpr int y_seqs() { return run_len<C>(); }
+template <typename C> __host__ __device__ constexpr int y_inv_seqs() { return 8; }
 __host__ __device__ constexpr int min_radix_log(int logn) {
     int m = 4;
     for (int p = 0; plan_lr(logn, p) > 0; p++) m = plan_lr(logn, p) < m ? plan_lr(logn, p) : m;
@@ -296,8 +303,10 @@ __host__ __device__ constexpr int fft_ipt(int logn, int nseq) {
 __host__ __device__ constexpr int fft_threads(int logn, int nseq) {
     return nseq * ((1 << logn) >> min_radix_log(logn)) / fft_ipt(logn, nseq);
 }
-// (my, mx) columns per z-pass workgroup (times 3 components)
-template <typename C> __host__ __device__ constexpr int z_cols() { return 2; }
+// (my, mx) columns per z-pass workgroup (times 3 components): one, so that
+// the LDS allows the most workgroups per CU (two measured 0.68 -> 0.88 ms in
+// float64 and 0.32 -> 0.47 ms in float32 at 512^3)
+template <typename C> __host__ __device__ constexpr int z_cols() { return 1; }
 
 // x forward: run_len rows (consecutive y) per workgroup, two real rows per
 // complex transform: sequence s carries rows a = row0 + 2 s and b = a + 1 as
@@ -311,7 +320,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int nrows, int K1,
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN, ROWS = run_len<C>(), NSEQ = ROWS / 2;
+    constexpr int n = 1 << LOGN, ROWS = x_rows<C>(), NSEQ = ROWS / 2;
     constexpr int IPT = fft_ipt(LOGN, NSEQ);
     C *twl = (C *)smem, *buf = twl + n;
     const int bid = xcd_block(per);
@@ -337,8 +346,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int nrows, int K1,
     }
 }
 
-// x inverse: run_len rows per workgroup; modes 0..K of each row gathered from
-// A[k][row0 ..] into LDS, Hermitian completion, real part out
+// x inverse: run_len rows per workgroup, two rows per complex transform.
+// The modes 0..K of the rows are gathered from A[k][row0 ..] into LDS (row r
+// at spec[r K1 ..]); sequence s transforms Z = X_a + i X_b of rows a = 2 s,
+// b = a + 1, both spectra Hermitian-completed, so that row a is Re z and row
+// b is Im z.  The gathered spectra share the LDS of the transform's buffer:
+// its first pass reads all of them before it writes.
 template <typename R, int LOGN>
 __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int nrows, int K1, int per,
                                                             const typename Cx<R>::T *__restrict__ A,
@@ -346,35 +359,42 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int nrows, int K1,
                                                             R *__restrict__ grid) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN, ROWS = run_len<C>();
-    constexpr int IPT = fft_ipt(LOGN, ROWS);
-    C *twl = (C *)smem, *buf = twl + n;
+    constexpr int n = 1 << LOGN, ROWS = x_rows<C>(), NSEQ = ROWS / 2;
+    constexpr int IPT = fft_ipt(LOGN, NSEQ);
+    C *twl = (C *)smem, *buf = twl + n, *spec = buf;
     const int bid = xcd_block(per);
     if (bid >= nrows / ROWS) return;
     const size_t row0 = (size_t)bid * ROWS;
-    const int pitch = lds_pitch<true>(n, ROWS);
+    const int pitch = lds_pitch<true>(n, NSEQ);
     // the runs of modes 0..K, then the twiddle table, in one batched copy
     const int nin = ROWS * K1;
     auto gl = [&](int i) {
         return i < nin ? A[(size_t)(i / ROWS) * nrows + row0 + i % ROWS] : tw[i - nin];
     };
     auto gs = [&](int i, C v) {
-        if (i < nin) buf[lds_at<true>(i % ROWS, i / ROWS, pitch)] = v;
+        if (i < nin) spec[(i % ROWS) * K1 + i / ROWS] = v;
         else twl[i - nin] = v;
     };
     gather_lds<8>(nin + n, gl, gs);
     __syncthreads();
-    auto load = [&](int s, int e) {
+    auto herm = [&](int r, int e) {
         C v = C{(R)0, (R)0};
-        if (e < K1) v = buf[lds_at<true>(s, e, pitch)];
+        if (e < K1) v = spec[r * K1 + e];
         else if (n - e < K1) {
-            const C u = buf[lds_at<true>(s, n - e, pitch)];
+            const C u = spec[r * K1 + (n - e)];
             v = C{u.x, -u.y};
         }
         return v;
     };
-    auto store = [&](int s, int e, C v) { grid[(row0 + s) * n + e] = v.x; };
-    fft_run<true, LOGN, IPT>(ROWS, pitch, buf, twl, (R)1, load, store);
+    auto load = [&](int s, int e) {
+        const C a = herm(2 * s, e), b = herm(2 * s + 1, e);
+        return C{a.x - b.y, a.y + b.x};
+    };
+    auto store = [&](int s, int e, C v) {
+        grid[(row0 + 2 * s) * n + e] = v.x;
+        grid[(row0 + 2 * s + 1) * n + e] = v.y;
+    };
+    fft_run<true, LOGN, IPT>(NSEQ, pitch, buf, twl, (R)1, load, store);
 }
 
 // y forward: run_len sequences q = (3 kx + c) n + z0 + s (contiguous in A);
@@ -387,7 +407,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_fwd(int K, int per,
                                                             typename Cx<R>::T *__restrict__ B) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN, SEQ = run_len<C>();
+    constexpr int n = 1 << LOGN, SEQ = y_seqs<C>();
     constexpr int IPT = fft_ipt(LOGN, SEQ);
     const int K1 = K + 1, NY = 2 * K + 1;
     C *twl = (C *)smem, *buf = twl + n;
@@ -417,7 +437,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_y_inv(int K, int per,
                                                             typename Cx<R>::T *__restrict__ A) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN, SEQ = run_len<C>();
+    constexpr int n = 1 << LOGN, SEQ = y_inv_seqs<C>();
     constexpr int IPT = fft_ipt(LOGN, SEQ);
     const int K1 = K + 1;
     C *twl = (C *)smem, *buf = twl + n;
@@ -723,16 +743,16 @@ static void pruned_fwd(bs_plan_t p) {
         hipLaunchKernelGGL((k_fft_xy_fwd<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
                            K, per, (const R *)p->grid.p, twf, (C *)p->fft_B.p);
     } else {
-        constexpr int RUN = run_len<C>();
+        constexpr int XR = x_rows<C>(), YS = y_seqs<C>();
         const int nrows = 3 * n * n;
-        const int px = ceil_div(nrows / RUN, 8), py = ceil_div(3 * n / RUN * K1, 8);
-        const size_t lx = seq_lds<C>(n, RUN / 2, n), ly = seq_lds<C>(n, RUN, n);
+        const int px = ceil_div(nrows / XR, 8), py = ceil_div(3 * n / YS * K1, 8);
+        const size_t lx = seq_lds<C>(n, XR / 2, n), ly = seq_lds<C>(n, YS, n);
         if (lx > 65536) allow_big_lds<k_fft_x_fwd<R, LOGN>>(p->device);
         if (ly > 65536) allow_big_lds<k_fft_y_fwd<R, LOGN>>(p->device);
-        hipLaunchKernelGGL((k_fft_x_fwd<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, RUN / 2)),
+        hipLaunchKernelGGL((k_fft_x_fwd<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, XR / 2)),
                            lx, p->stream, nrows, K1, px, (const R *)p->grid.p, twf,
                            (C *)p->fft_A.p);
-        hipLaunchKernelGGL((k_fft_y_fwd<R, LOGN>), dim3(8 * py), dim3(fft_threads(LOGN, RUN)), ly,
+        hipLaunchKernelGGL((k_fft_y_fwd<R, LOGN>), dim3(8 * py), dim3(fft_threads(LOGN, YS)), ly,
                            p->stream, K, py, (const C *)p->fft_A.p, twf, (C *)p->fft_B.p);
     }
 }
@@ -780,18 +800,17 @@ static void pruned_inv(bs_plan_t p) {
         hipLaunchKernelGGL((k_fft_yx_inv<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
                            K, per, (const C *)p->fft_B.p, twi, (R *)p->grid.p);
     } else {
-        constexpr int RUN = run_len<C>();
+        constexpr int XR = x_rows<C>(), YS = y_inv_seqs<C>();
         const int nrows = 3 * n * n;
-        const int px = ceil_div(nrows / RUN, 8), py = ceil_div(3 * n / RUN * K1, 8);
-        const size_t l = seq_lds<C>(n, RUN, n);
-        if (l > 65536) {
-            allow_big_lds<k_fft_y_inv<R, LOGN>>(p->device);
-            allow_big_lds<k_fft_x_inv<R, LOGN>>(p->device);
-        }
-        hipLaunchKernelGGL((k_fft_y_inv<R, LOGN>), dim3(8 * py), dim3(fft_threads(LOGN, RUN)), l,
+        const int px = ceil_div(nrows / XR, 8), py = ceil_div(3 * n / YS * K1, 8);
+        const size_t ly = seq_lds<C>(n, YS, n), lx = seq_lds<C>(n, XR / 2, n);
+        if (ly > 65536) allow_big_lds<k_fft_y_inv<R, LOGN>>(p->device);
+        if (lx > 65536) allow_big_lds<k_fft_x_inv<R, LOGN>>(p->device);
+        hipLaunchKernelGGL((k_fft_y_inv<R, LOGN>), dim3(8 * py), dim3(fft_threads(LOGN, YS)), ly,
                            p->stream, K, py, (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
-        hipLaunchKernelGGL((k_fft_x_inv<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, RUN)), l,
-                           p->stream, nrows, K1, px, (const C *)p->fft_A.p, twi, (R *)p->grid.p);
+        hipLaunchKernelGGL((k_fft_x_inv<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, XR / 2)),
+                           lx, p->stream, nrows, K1, px, (const C *)p->fft_A.p, twi,
+                           (R *)p->grid.p);
     }
 }
 
