@@ -186,8 +186,7 @@ __global__ __launch_bounds__(64) void k_sort_all(SortSet S) {
 struct GatherOut {
     int4 *base;
     void *ker, *q, *schg;
-    double4 *spos;
-    int *sseg;
+    double4 *spos;   // w: the point's segment index
 };
 
 template <typename R>
@@ -214,9 +213,8 @@ __device__ __forceinline__ void gather_one(int t, int w, int Q, const int *__res
     if (d == 0) {
         bp[3] = 0;
         q[4 * (size_t)p + 3] = (R)0;
-        sp[3] = 0.0;
+        sp[3] = (double)(o / Q);
         schg[4 * (size_t)p + 3] = (R)0;
-        G.sseg[p] = o / Q;
     }
 }
 
@@ -253,7 +251,6 @@ void build_bins(bs_plan_t p) {
     G.q = p->sp_q.p;
     G.spos = (double4 *)p->pq_pos.p;
     G.schg = p->pq_chg.p;
-    G.sseg = (int *)p->pq_seg.p;
     const double *qp = (const double *)p->d_qpos.p, *qc = (const double *)p->d_qchg.p;
     // keys and counts come from the per-filament kernel (bin_keys)
     if (maxb <= (1 << 16)) {

@@ -460,7 +460,7 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             (rc = ensure<int>(P, P->pq_cnt, nc3 + 1)) || (rc = ensure<int>(P, P->pq_start, nc3 + 1)) ||
             (rc = ensure<int>(P, P->pq_fill, nc3 + 1)) || (rc = ensure<int>(P, P->pq_perm, Nq)) ||
             (rc = ensure<double4>(P, P->pq_pos, Nq)) || (rc = ensure<char>(P, P->pq_chg, Nq * 4 * rs)) ||
-            (rc = ensure<int>(P, P->pq_seg, Nq)) || (rc = ensure<int>(P, P->nd_key, N)) ||
+            (rc = ensure<int>(P, P->nd_key, N)) ||
             (rc = ensure<int>(P, P->nd_cnt, nc3 + 1)) || (rc = ensure<int>(P, P->nd_start, nc3 + 1)) ||
             (rc = ensure<int>(P, P->nd_fill, nc3 + 1)) || (rc = ensure<int>(P, P->nd_perm, N)))
             return rc;
@@ -906,7 +906,7 @@ int bs_destroy(bs_plan_t P) {
                    &P->d_qpos, &P->d_qchg, &P->d_status, &P->sp_key, &P->sp_cnt, &P->sp_start,
                    &P->sp_fill, &P->sp_perm, &P->sp_base, &P->sp_ker, &P->sp_q, &P->pq_key,
                    &P->pq_cnt, &P->pq_start, &P->pq_fill, &P->pq_perm, &P->pq_pos, &P->pq_chg,
-                   &P->pq_seg, &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
+                   &P->nd_key, &P->nd_cnt, &P->nd_start, &P->nd_fill, &P->nd_perm,
                    &P->scan_tmp, &P->red_tmp, &P->spline_tmp, &P->tmp3, &P->e_D, &P->e_S, &P->d_vls, &P->ns_red, &P->ns_nc, &P->ns_ckey,
                    &P->ns_ccnt, &P->ns_cstart, &P->ns_cfill, &P->ns_cperm, &P->ns_tkey, &P->ns_tcnt,
                    &P->ns_tstart, &P->ns_tfill, &P->ns_tperm, &P->ns_segA, &P->ns_segB, &P->ns_segM, &P->ns_segH, &P->ns_slots,

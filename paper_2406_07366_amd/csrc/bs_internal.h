@@ -96,7 +96,7 @@ struct bs_plan_s {
     bs::DBuf sp_base, sp_ker, sp_q;
     // pair binning
     bs::DBuf pq_key, pq_cnt, pq_start, pq_fill, pq_perm;
-    bs::DBuf pq_pos, pq_chg, pq_seg;
+    bs::DBuf pq_pos, pq_chg;                   // double4 (position, segment), charges
     bs::DBuf nd_key, nd_cnt, nd_start, nd_fill, nd_perm;
     // scan scratch, reductions, spline scratch (filaments over 512 nodes)
     bs::DBuf scan_tmp, red_tmp, spline_tmp;

@@ -42,7 +42,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                const int *__restrict__ cstart,
                                                const double4 *__restrict__ spos,
                                                const R *__restrict__ schg,
-                                               const int *__restrict__ sseg,
                                                const double *__restrict__ base,
                                                double *__restrict__ out) {
     static_assert(WPN == 1 || WPN == 4, "1 or 4 wavefronts per target");
@@ -135,8 +134,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // separation (float64, then in R) and whether it lies within r_c
     auto test = [&](int q, int c0, R &fx, R &fy, R &fz, int &p) {
         p = ncell > 1 ? map[q - c0] : cs0 + q;
-        const int sg = sseg[p];
-        const double4 sp = spos[p];
+        const double4 sp = spos[p];   // w: the point's segment index
+        const int sg = (int)sp.w;
         if (sg == o || sg == ip) return false;
         double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
         rx -= L * rint(rx * invL);
@@ -233,17 +232,16 @@ static void pairs_r(bs_plan_t p, const double *base, double *out, bool alone) {
     dim3 grid(split ? N : ceil_div(N, 4)), block(256);
     const double L = p->prm.L, rc = p->prm.rcut, alpha = p->prm.alpha;
     const int *nperm = (const int *)p->nd_perm.p, *off = (const int *)p->d_off.p,
-              *fil = (const int *)p->d_fil.p, *cs = (const int *)p->pq_start.p,
-              *seg = (const int *)p->pq_seg.p;
+              *fil = (const int *)p->d_fil.p, *cs = (const int *)p->pq_start.p;
     const double *x = (const double *)p->d_x.p;
     const double4 *sp = (const double4 *)p->pq_pos.p;
     const R *q = (const R *)p->pq_chg.p;
     if (split)
         hipLaunchKernelGGL((k_pairs<R, PSI, 4>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
-                           nperm, x, off, fil, cs, sp, q, seg, base, out);
+                           nperm, x, off, fil, cs, sp, q, base, out);
     else
         hipLaunchKernelGGL((k_pairs<R, PSI, 1>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
-                           nperm, x, off, fil, cs, sp, q, seg, base, out);
+                           nperm, x, off, fil, cs, sp, q, base, out);
 }
 
 void launch_pairs(bs_plan_t p, int psi, const double *base, double *out, bool alone) {
