@@ -130,11 +130,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             acc2 += f * (fx * q1v - fy * q0v);
         }
     };
-    // separation test of candidate q of the chunk from c0: the minimum-image
-    // separation (float64, then in R) and whether it lies within r_c
-    auto test = [&](int q, int c0, R &fx, R &fy, R &fz, int &p) {
-        p = ncell > 1 ? map[q - c0] : cs0 + q;
-        const double4 sp = spos[p];   // w: the point's segment index
+    // separation of a candidate point (position and segment index sp): the
+    // minimum-image separation (float64, then in R) and whether it lies
+    // within r_c (the node's two adjacent segments excluded)
+    auto sep = [&](const double4 &sp, R &fx, R &fy, R &fz) {
         const int sg = (int)sp.w;
         if (sg == o || sg == ip) return false;
         double rx = sp.x - xi0, ry = sp.y - xi1, rz = sp.z - xi2;
@@ -155,6 +154,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         head += n;
     };
+    // U steps of 64 candidates per round: their point indices, then all
+    // their position loads, issued before any is used; the steps keep the
+    // candidate order.  U = 1: the loads of a step ahead of its tests already
+    // took the float64 kernel from 2.97 to 2.69 ms at 1e6 nodes; two steps
+    // spill in float64 (and at three waves per SIMD ran slower), and in
+    // float32 gained 4 % but changed the kernel's rounding (rel. error on the
+    // ring pairs 1.03e-7 -> 1.54e-7), so they are not taken
+    constexpr int U = 1;
     // chunks start at multiples of kMapCap (a multiple of 64 WPN), so every
     // wavefront meets its candidates in the same order as in one flat range
     for (int c0 = 0; c0 < total; c0 += kMapCap) {
@@ -164,32 +171,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int j = lo; j < hi; j++) map[j - c0] = cs + (j - excl);
             wave_lds_sync();
         }
-        if constexpr (kQueued) {
-            for (int qb = c0 + part * 64; qb < cend; qb += 64 * WPN) {
-                // separation test of 64 candidates; the accepted ones (about
-                // a fifth) are queued in candidate order, and their erfc /
-                // exp terms run 64 at a time with every lane busy
-                const int q = qb + lane;
-                R fx = 0, fy = 0, fz = 0;
-                int p = 0;
-                const bool ok = q < cend && test(q, c0, fx, fy, fz, p);
-                const unsigned long long m = __ballot(ok);
-                if (ok) {
-                    const int sl = (tail + __popcll(m & below)) & (kQueue - 1);
-                    qx[sl] = fx; qy[sl] = fy; qz[sl] = fz; qp[sl] = p;
-                }
-                tail += __popcll(m);
-                wave_lds_sync();
-                if (tail - head >= 64) {
-                    drain(64);
-                    wave_lds_sync();   // slots read before the next step writes them
-                }
+        for (int qb = c0 + part * 64; qb < cend; qb += 64 * WPN * U) {
+            int pv[U];
+            bool in[U];
+            double4 sv[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int q = qb + u * 64 * WPN + lane;
+                in[u] = q < cend;
+                pv[u] = in[u] ? (ncell > 1 ? map[q - c0] : cs0 + q) : 0;
             }
-        } else {
-            for (int q = c0 + part * 64 + lane; q < cend; q += 64 * WPN) {
-                R fx, fy, fz;
-                int p;
-                if (test(q, c0, fx, fy, fz, p)) term(fx, fy, fz, p);
+#pragma unroll
+            for (int u = 0; u < U; u++) sv[u] = in[u] ? spos[pv[u]] : make_double4(0, 0, 0, -1);
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                R fx = 0, fy = 0, fz = 0;
+                const bool ok = in[u] && sep(sv[u], fx, fy, fz);
+                if constexpr (kQueued) {
+                    // the accepted ones (about a fifth) are queued in
+                    // candidate order, and their erfc / exp terms run 64 at a
+                    // time with every lane busy
+                    const unsigned long long m = __ballot(ok);
+                    if (ok) {
+                        const int sl = (tail + __popcll(m & below)) & (kQueue - 1);
+                        qx[sl] = fx; qy[sl] = fy; qz[sl] = fz; qp[sl] = pv[u];
+                    }
+                    tail += __popcll(m);
+                    wave_lds_sync();
+                    if (tail - head >= 64) {
+                        drain(64);
+                        wave_lds_sync();   // slots read before the next step writes them
+                    }
+                } else {
+                    if (ok) term(fx, fy, fz, pv[u]);
+                }
             }
         }
         if (ncell > 1) wave_lds_sync();   // map reads done before the next chunk is written
