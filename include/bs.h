@@ -70,7 +70,7 @@ extern "C" {
  * ns_eta * segment length (not part of the paper; see bs_velocity) */
 #define BS_NS_OFF       0
 #define BS_NS_ADAPTIVE  1  /* graded Gauss-Legendre panels on the spline segment
-                              (relative error ~1e-14; the reference integrator) */
+                              (relative error ~1e-11; the reference integrator) */
 #define BS_NS_MLP       2  /* learned correction where its error indicator
                               allows, else the graded panels (bs_set_mlp)      */
 #define BS_NS_MAPPED    3  /* fixed-cost rule: sinh-mapped 2 x 16-point

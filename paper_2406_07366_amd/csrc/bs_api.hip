@@ -91,15 +91,18 @@ static void kernel_ft_table(int K, int w, int n, double zeta, double *F) {
 }
 
 // Gauss-Legendre rules of the near-singular integrals: 16 points (the mapped
-// rule, each side of the peak) and 12 points (the graded panels)
+// rule, each side of the peak), 10 and 12 points (the graded panels on cubic
+// and quintic segments)
 struct NsRule {
     double x[16], w[16];
+    double x10[10], w10[10];
     double x12[12], w12[12];
 };
 void ns_rule(NsRule *R) {
     static const NsRule cached = [] {
         NsRule r;
         legendre_rule(16, r.x, r.w);
+        legendre_rule(10, r.x10, r.w10);
         legendre_rule(12, r.x12, r.w12);
         return r;
     }();

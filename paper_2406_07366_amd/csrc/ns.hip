@@ -13,8 +13,9 @@
 //           each node's flagged pairs in a fixed order; compacted pair list;
 //   integrate  one thread per pair, float64, by one of
 //           - graded panels: closest point of the segment to the target by
-//             Newton steps, 12-point Gauss-Legendre panels graded
-//             geometrically (ratio 3) away from it (error ~1e-14 relative);
+//             Newton steps, 10-point (cubic) or 12-point (quintic)
+//             Gauss-Legendre panels graded geometrically (ratio 3) away
+//             from it (error ~1e-11 relative);
 //           - the mapped rule: sinh-mapped 16-point rules on either side of
 //             the closest point, the tangent segment as a control variate
 //             (fixed cost);
@@ -30,11 +31,11 @@
 namespace bs {
 
 constexpr int kNsGL = 16;        // mapped rule, each side of the peak
-constexpr int kNsPanelGL = 12;   // graded panels
 struct NsRule {
     double x[kNsGL];   // nodes on [-1, 1]
     double w[kNsGL];
-    double x12[kNsPanelGL], w12[kNsPanelGL];
+    double x10[10], w10[10];   // graded panels, cubic segments
+    double x12[12], w12[12];   // graded panels, quintic segments
 };
 
 // ------------------------------------------------------------ cell grid
@@ -657,18 +658,24 @@ __device__ __forceinline__ double rsqrt_nr(double a) {
     return y;
 }
 
-// integral over u in [a, b] of (s(u) - x) x s'(u) / |s(u) - x|^3 with the
-// kNsPanelGL-point Gauss-Legendre rule.  On the graded panels below, the
-// integrand's complex singularity near the closest point (2 delta off the
-// real axis) lies outside the Bernstein ellipse of parameter 3.7 of every
-// panel (4.2 for the centre panel; clipped panels only shrink), so the
-// rule's relative error is of order 3.7^-24 = 2e-14.
+// integral over u in [a, b] of (s(u) - x) x s'(u) / |s(u) - x|^3 by
+// Gauss-Legendre: 10 points on cubic segments, 12 on quintic ones.  On the
+// graded panels below, the integrand's complex singularity near the closest
+// point (2 delta off the real axis) lies outside the Bernstein ellipse of
+// parameter 3.7 of every panel (4.2 for the centre panel; clipped panels
+// only shrink), so the rule's relative error is of order 3.7^-20 = 4e-12 at
+// 10 points (measured on cubic segments against the oracle's adaptive
+// Gauss-Kronrod: 9e-12; 12 points gave 2e-13 for 13 % more time).  Quintic
+// segments, whose |s(u) - x|^2 has more complex roots, measured 8e-10 at 10
+// points and 7e-13 at 12, so they keep 12.
 template <int DEG = 5>
 __device__ void ns_panel(const Seg &s, const double *x, double a, double b, const NsRule &R,
                          double *acc) {
+    constexpr int NG = DEG == 3 ? 10 : 12;
+    const double *gx = DEG == 3 ? R.x10 : R.x12, *gw = DEG == 3 ? R.w10 : R.w12;
     double m = 0.5 * (a + b), hw = 0.5 * (b - a);
-    for (int k = 0; k < kNsPanelGL; k++) {
-        double u = m + hw * R.x12[k];
+    for (int k = 0; k < NG; k++) {
+        double u = m + hw * gx[k];
         double r[3], d[3];
         for (int q = 0; q < 3; q++) {
             r[q] = seg_p<DEG>(s, q, u) - x[q];
@@ -676,7 +683,7 @@ __device__ void ns_panel(const Seg &s, const double *x, double a, double b, cons
         }
         const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         const double y = rsqrt_nr(r2);
-        const double f = R.w12[k] * hw * (y * y * y);
+        const double f = gw[k] * hw * (y * y * y);
         acc[0] += f * (r[1] * d[2] - r[2] * d[1]);
         acc[1] += f * (r[2] * d[0] - r[0] * d[2]);
         acc[2] += f * (r[0] * d[1] - r[1] * d[0]);
