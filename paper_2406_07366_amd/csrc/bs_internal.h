@@ -187,6 +187,9 @@ void pruned_batches(int n, size_t csize, int *rb, int *kb, int *kz);
 void pruned_forward(bs_plan_t p);
 void pruned_spectral_op(bs_plan_t p, int psi);
 void pruned_inverse(bs_plan_t p);
+// the inverse transforms leave the grid [n][n][n][3] (components interleaved)
+// rather than [3][n][n][n]: the pruned path on grids above 64^3
+bool grid_interleaved(bs_plan_t p);
 
 // pairs.hip
 // out = base + short-range term (base NULL: out += short-range term);

@@ -11,7 +11,9 @@
 //   z fused     B, FFT along z (contiguous), spectral operator (modes with
 //               |mz| > K, k = 0 zeroed), inverse FFT along z  ->  B in place
 //   y inverse   B, zero-padded inverse FFT along y  ->  A
-//   x inverse   A, Hermitian c2r along x             ->  grid
+//   x inverse   A, Hermitian c2r along x  ->  grid with the three components
+//               interleaved, [n][n][n][3] (the interpolation's layout; the
+//               spread writes [3][n][n][n])
 //
 // Every pass reads or writes whole contiguous sequences on one side; on the
 // other it moves 128-B runs (16 float32 or 8 float64 complex values of
@@ -298,10 +300,11 @@ __host__ __device__ constexpr int min_radix_log(int logn) {
 }
 __host__ __device__ constexpr int fft_ipt(int logn, int nseq) {
     const int items = nseq * ((1 << logn) >> min_radix_log(logn));
-    return items <= kFftMaxThreads ? 1 : items / kFftMaxThreads;
+    return (items + kFftMaxThreads - 1) / kFftMaxThreads;   // rounded up
 }
 __host__ __device__ constexpr int fft_threads(int logn, int nseq) {
-    return nseq * ((1 << logn) >> min_radix_log(logn)) / fft_ipt(logn, nseq);
+    const int items = nseq * ((1 << logn) >> min_radix_log(logn)), ipt = fft_ipt(logn, nseq);
+    return (items + ipt - 1) / ipt;
 }
 // (my, mx) columns per z-pass workgroup (times 3 components): one, so that
 // the LDS allows the most workgroups per CU (two measured 0.68 -> 0.88 ms in
@@ -346,53 +349,82 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_fwd(int nrows, int K1,
     }
 }
 
-// x inverse: run_len rows per workgroup, two rows per complex transform.
-// The modes 0..K of the rows are gathered from A[k][row0 ..] into LDS (row r
-// at spec[r K1 ..]); sequence s transforms Z = X_a + i X_b of rows a = 2 s,
-// b = a + 1, both spectra Hermitian-completed, so that row a is Re z and row
-// b is Im z.  The gathered spectra share the LDS of the transform's buffer:
-// its first pass reads all of them before it writes.
+// x inverse into the interpolation's layout: the grid leaves the inverse
+// with its three components interleaved, g[((z n + y) n + x) 3 + c], so that
+// a node's stencil row of three components is one contiguous run (the
+// interpolation touches about half the cache lines it touches in [3][n]^3:
+// 2.23 -> 1.63 ms in float64 at 512^3).  A workgroup takes the rows
+// (z, y0 .. y0 + Y - 1) of all three components: the modes 0..K of each are
+// gathered from A[k][(c n + z) n + y0 ..] (runs of Y) into LDS, and 3Y / 2
+// complex transforms produce them, two real rows each: c0 + i c1 of row y,
+// and c2 of rows y, y + 1 (both spectra Hermitian-completed).  Every (z, y)
+// row's 3 n values are written by this workgroup alone.  The gathered
+// spectra share the LDS of the transform's buffer: its first pass reads all
+// of them before it writes.
+template <typename C> __host__ __device__ constexpr int xi_rows() { return 64 / (int)sizeof(C); }
+
 template <typename R, int LOGN>
-__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int nrows, int K1, int per,
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int K1, int per,
                                                             const typename Cx<R>::T *__restrict__ A,
                                                             const typename Cx<R>::T *__restrict__ tw,
                                                             R *__restrict__ grid) {
     typedef typename Cx<R>::T C;
     extern __shared__ unsigned char smem[];
-    constexpr int n = 1 << LOGN, ROWS = x_rows<C>(), NSEQ = ROWS / 2;
+    constexpr int n = 1 << LOGN, Y = xi_rows<C>(), NSEQ = 3 * Y / 2;
     constexpr int IPT = fft_ipt(LOGN, NSEQ);
+    constexpr size_t nrows = (size_t)3 * n * n;
     C *twl = (C *)smem, *buf = twl + n, *spec = buf;
     const int bid = xcd_block(per);
-    if (bid >= nrows / ROWS) return;
-    const size_t row0 = (size_t)bid * ROWS;
+    if (bid >= n * (n / Y)) return;
+    const int z = bid / (n / Y), y0 = (bid - z * (n / Y)) * Y;
     const int pitch = lds_pitch<true>(n, NSEQ);
-    // the runs of modes 0..K, then the twiddle table, in one batched copy
-    const int nin = ROWS * K1;
+    // the runs of modes 0..K (index i = (k 3 + c) Y + yy), then the twiddle
+    // table, in one batched copy; spectrum of (c, yy) at spec[(c Y + yy) K1]
+    const int nin = 3 * Y * K1;
     auto gl = [&](int i) {
-        return i < nin ? A[(size_t)(i / ROWS) * nrows + row0 + i % ROWS] : tw[i - nin];
+        if (i >= nin) return tw[i - nin];
+        const int yy = i % Y, kc = i / Y, c = kc % 3, k = kc / 3;
+        return A[(size_t)k * nrows + ((size_t)c * n + z) * n + y0 + yy];
     };
     auto gs = [&](int i, C v) {
-        if (i < nin) spec[(i % ROWS) * K1 + i / ROWS] = v;
-        else twl[i - nin] = v;
+        if (i < nin) {
+            const int yy = i % Y, kc = i / Y, c = kc % 3, k = kc / 3;
+            spec[(c * Y + yy) * K1 + k] = v;
+        } else {
+            twl[i - nin] = v;
+        }
     };
     gather_lds<8>(nin + n, gl, gs);
     __syncthreads();
-    auto herm = [&](int r, int e) {
+    auto herm = [&](int c, int yy, int e) {
+        const C *sp = spec + (c * Y + yy) * K1;
         C v = C{(R)0, (R)0};
-        if (e < K1) v = spec[r * K1 + e];
+        if (e < K1) v = sp[e];
         else if (n - e < K1) {
-            const C u = spec[r * K1 + (n - e)];
+            const C u = sp[n - e];
             v = C{u.x, -u.y};
         }
         return v;
     };
+    // sequence s < Y: components 0 and 1 of row y0 + s; s >= Y: component 2
+    // of rows y0 + 2 (s - Y) and the next
     auto load = [&](int s, int e) {
-        const C a = herm(2 * s, e), b = herm(2 * s + 1, e);
+        C a, b;
+        if (s < Y) { a = herm(0, s, e); b = herm(1, s, e); }
+        else { a = herm(2, 2 * (s - Y), e); b = herm(2, 2 * (s - Y) + 1, e); }
         return C{a.x - b.y, a.y + b.x};
     };
+    R *plane = grid + (size_t)3 * n * ((size_t)z * n + y0);
     auto store = [&](int s, int e, C v) {
-        grid[(row0 + 2 * s) * n + e] = v.x;
-        grid[(row0 + 2 * s + 1) * n + e] = v.y;
+        if (s < Y) {
+            R *g = plane + (size_t)3 * ((size_t)s * n + e);
+            g[0] = v.x;
+            g[1] = v.y;
+        } else {
+            R *g = plane + (size_t)3 * ((size_t)(2 * (s - Y)) * n + e) + 2;
+            g[0] = v.x;
+            g[3 * n] = v.y;
+        }
     };
     fft_run<true, LOGN, IPT>(NSEQ, pitch, buf, twl, (R)1, load, store);
 }
@@ -744,6 +776,9 @@ static void pruned_fwd(bs_plan_t p) {
                            K, per, (const R *)p->grid.p, twf, (C *)p->fft_B.p);
     } else {
         constexpr int XR = x_rows<C>(), YS = y_seqs<C>();
+        static_assert(fft_threads(LOGN, XR / 2) <= kFftMaxThreads &&
+                          fft_threads(LOGN, YS) <= kFftMaxThreads,
+                      "workgroups within the kernels' launch bounds");
         const int nrows = 3 * n * n;
         const int px = ceil_div(nrows / XR, 8), py = ceil_div(3 * n / YS * K1, 8);
         const size_t lx = seq_lds<C>(n, XR / 2, n), ly = seq_lds<C>(n, YS, n);
@@ -778,6 +813,8 @@ static void pruned_spectral(bs_plan_t p, int psi) {
                            (C *)p->fft_B.p);
     } else {
         constexpr int KZ = z_cols<C>();
+        static_assert(fft_threads(LOGN, 3 * KZ) <= kFftMaxThreads,
+                      "workgroups within the kernel's launch bounds");
         const int pz = ceil_div(ceil_div((2 * K + 1) * K1, KZ), 8);
         const size_t lds = seq_lds<C>(n, 3 * KZ, n);
         if (lds > 65536) allow_big_lds<k_fft_zt_spectral<R, LOGN>>(p->device);
@@ -800,19 +837,22 @@ static void pruned_inv(bs_plan_t p) {
         hipLaunchKernelGGL((k_fft_yx_inv<R, LOGN>), dim3(8 * per), dim3(n * mnj), lds, p->stream,
                            K, per, (const C *)p->fft_B.p, twi, (R *)p->grid.p);
     } else {
-        constexpr int XR = x_rows<C>(), YS = y_inv_seqs<C>();
-        const int nrows = 3 * n * n;
-        const int px = ceil_div(nrows / XR, 8), py = ceil_div(3 * n / YS * K1, 8);
-        const size_t ly = seq_lds<C>(n, YS, n), lx = seq_lds<C>(n, XR / 2, n);
+        constexpr int YS = y_inv_seqs<C>(), XY = xi_rows<C>(), XS = 3 * XY / 2;
+        static_assert(fft_threads(LOGN, YS) <= kFftMaxThreads &&
+                          fft_threads(LOGN, XS) <= kFftMaxThreads,
+                      "workgroups within the kernels' launch bounds");
+        const int px = ceil_div(n * (n / XY), 8), py = ceil_div(3 * n / YS * K1, 8);
+        const size_t ly = seq_lds<C>(n, YS, n), lx = seq_lds<C>(n, XS, n);
         if (ly > 65536) allow_big_lds<k_fft_y_inv<R, LOGN>>(p->device);
         if (lx > 65536) allow_big_lds<k_fft_x_inv<R, LOGN>>(p->device);
         hipLaunchKernelGGL((k_fft_y_inv<R, LOGN>), dim3(8 * py), dim3(fft_threads(LOGN, YS)), ly,
                            p->stream, K, py, (const C *)p->fft_B.p, twi, (C *)p->fft_A.p);
-        hipLaunchKernelGGL((k_fft_x_inv<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, XR / 2)),
-                           lx, p->stream, nrows, K1, px, (const C *)p->fft_A.p, twi,
-                           (R *)p->grid.p);
+        hipLaunchKernelGGL((k_fft_x_inv<R, LOGN>), dim3(8 * px), dim3(fft_threads(LOGN, XS)),
+                           lx, p->stream, K1, px, (const C *)p->fft_A.p, twi, (R *)p->grid.p);
     }
 }
+
+bool grid_interleaved(bs_plan_t p) { return p->pruned && p->n > (1 << kFftXYMaxLogn); }
 
 void pruned_forward(bs_plan_t p) {
     with_logn(ilog2(p->n), [&](auto L) {

@@ -364,7 +364,7 @@ void launch_modes(bs_plan_t p, double *out) {
 // pair-cell order, and consecutive blocks of them stay on one XCD (blocks
 // b, b+8, ... run on one XCD), so the grid rows that neighbouring nodes share
 // are fetched into one L2.
-template <typename R, int W, int G>
+template <typename R, int W, int G, bool IL>
 __global__ __launch_bounds__(256) void k_interp(int N, int per_xcd, const int *__restrict__ perm,
                                                 const double *__restrict__ x, double L,
                                                 double inv_h, int n, double zeta, double inv_den,
@@ -412,14 +412,22 @@ __global__ __launch_bounds__(256) void k_interp(int N, int per_xcd, const int *_
 #pragma unroll
     for (int i = 0; i < NR; i++) {
         if (lane + i * G < W * W) {
-            const R *g = grid + col[i];
+            // IL: components interleaved, [n][n][n][3]; else [3][n][n][n]
+            const R *g = grid + (IL ? 3 : 1) * col[i];
             R s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
             for (int kz = 0; kz < W; kz++) {
-                const size_t c = (size_t)iz[kz] * n2;
-                s0 += pz[kz] * g[c];
-                s1 += pz[kz] * g[n3 + c];
-                s2 += pz[kz] * g[2 * n3 + c];
+                if constexpr (IL) {
+                    const size_t c = 3 * (size_t)iz[kz] * n2;
+                    s0 += pz[kz] * g[c];
+                    s1 += pz[kz] * g[c + 1];
+                    s2 += pz[kz] * g[c + 2];
+                } else {
+                    const size_t c = (size_t)iz[kz] * n2;
+                    s0 += pz[kz] * g[c];
+                    s1 += pz[kz] * g[n3 + c];
+                    s2 += pz[kz] * g[2 * n3 + c];
+                }
             }
             a0 += wxy[i] * s0; a1 += wxy[i] * s1; a2 += wxy[i] * s2;
         }
@@ -451,8 +459,12 @@ static void interp_r(bs_plan_t p, const double *base, double *out) {
     const int *perm = (const int *)p->nd_perm.p;
     const double *x = (const double *)p->d_x.p;
     const R *g = (const R *)p->grid.p;
+    const bool il = grid_interleaved(p);
 #define INTERP_CASE(WW) \
-    case WW: hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes>), grid, block, 0, p->stream, N, per, perm, x, L, inv_h, p->n, zeta, inv_den, g, base, out); break;
+    case WW: \
+        if (il) hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes, true>), grid, block, 0, p->stream, N, per, perm, x, L, inv_h, p->n, zeta, inv_den, g, base, out); \
+        else hipLaunchKernelGGL((k_interp<R, WW, kInterpLanes, false>), grid, block, 0, p->stream, N, per, perm, x, L, inv_h, p->n, zeta, inv_den, g, base, out); \
+        break;
     switch (p->prm.w) {
         INTERP_CASE(4) INTERP_CASE(5) INTERP_CASE(6) INTERP_CASE(7) INTERP_CASE(8)
         INTERP_CASE(9) INTERP_CASE(10) INTERP_CASE(11) INTERP_CASE(12) INTERP_CASE(13)
