@@ -338,6 +338,7 @@ def main():
     primary = results[pname]
     prm = primary["prm"]
     fp32 = primary["precision"] == B.BS_FP32_MIXED
+    fs.tol = primary["tol"]   # the legs loop left the last leg's tolerance
     rp = B.resolve_params(B.params_for(fs, precision=primary["precision"]))
     Nq = N * prm["Q"]
     sb = stage_bytes(rp, N, Nq, fp32)
