@@ -414,19 +414,28 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_x_inv(int K1, int per,
         else { a = herm(2, 2 * (s - Y), e); b = herm(2, 2 * (s - Y) + 1, e); }
         return C{a.x - b.y, a.y + b.x};
     };
-    R *plane = grid + (size_t)3 * n * ((size_t)z * n + y0);
-    auto store = [&](int s, int e, C v) {
+    // the last pass writes the real rows into LDS in the grid's interleaved
+    // order (its barrier has retired every read of the buffer), and the
+    // workgroup then copies its Y rows of 3 n values to the grid as one
+    // contiguous block in 16-B stores (the block fits the transform's buffer)
+    R *outl = (R *)buf;
+    auto lstore = [&](int s, int e, C v) {
         if (s < Y) {
-            R *g = plane + (size_t)3 * ((size_t)s * n + e);
+            R *g = outl + 3 * (s * n + e);
             g[0] = v.x;
             g[1] = v.y;
         } else {
-            R *g = plane + (size_t)3 * ((size_t)(2 * (s - Y)) * n + e) + 2;
+            R *g = outl + 3 * ((2 * (s - Y)) * n + e) + 2;
             g[0] = v.x;
             g[3 * n] = v.y;
         }
     };
-    fft_run<true, LOGN, IPT>(NSEQ, pitch, buf, twl, (R)1, load, store);
+    fft_run<true, LOGN, IPT>(NSEQ, pitch, buf, twl, (R)1, load, lstore);
+    typedef typename std::conditional<sizeof(R) == 8, double2, float4>::type V;
+    constexpr int PER = 16 / (int)sizeof(R), NV = 3 * n * Y / PER;
+    const V *src = (const V *)outl;
+    V *dst = (V *)(grid + (size_t)3 * n * ((size_t)z * n + y0));
+    for (int i = threadIdx.x; i < NV; i += blockDim.x) dst[i] = src[i];
 }
 
 // y forward: run_len sequences q = (3 kx + c) n + z0 + s (contiguous in A);
