@@ -21,25 +21,55 @@
 namespace bs {
 
 // ----------------------------------------------------------------- spread
-// One wavefront owns a T^3 tile of the grid.  Lane l owns the columns
-// (lx, ly) = (l % T, (l / T) % T) of the tile over ZL = T^3 / 64 z cells
-// starting at (l / T^2) ZL (T = 8: every lane a full column of 8 cells;
-// T = 4: one cell per lane) and accumulates them in registers.
-//
+// One wavefront owns a T^3 tile of the grid and accumulates it in registers.
 // Candidates are the points whose stencil base lies in one of the nbv^3
-// bins that can reach the tile.  They are staged 64 at a time: lane c turns
-// candidate c's 3W kernel values into the tile's frame (T weights per axis,
-// zero where the stencil misses the tile), and the candidates that overlap
-// the tile are compacted into LDS with a ballot, in candidate order.  Every
-// lane then runs through the staged candidates in that order, adding
-// q wx[lx] wy[ly] wz[z] to its cells.  Each grid cell is written exactly once,
-// with no atomics and a fixed summation order (bitwise reproducible), and
-// the LDS holds only the staged candidates.
+// bins that can reach the tile.  They are staged 64 at a time (lane c loads
+// candidate c), and the candidates that overlap the tile are compacted into
+// LDS with a ballot, in candidate order.  Each grid cell is written exactly
+// once, with no atomics and a fixed summation order (bitwise reproducible),
+// and the LDS holds only the staged candidates.
+//
+// T = 8, one wavefront per tile (matrix cores): the tile's sum over its
+// candidates p is a matrix product, G[(c, z)][(y, x)] =
+// sum_p A[(c, z)][p] B[p][(y, x)] with A = q_c wz[z] (24 rows) and
+// B = wy[y] wx[x] (64 columns), so it runs on v_mfma_*_16x16x4, four
+// candidates per instruction: rows padded to 32 (row block 0: c = 0, 1;
+// block 1: c = 2 and 8 zero rows), columns in 4 blocks of two y rows.  Per 4
+// candidates a lane reads 9 staged values and issues 8 MFMAs (the vector form
+// reads 13 values per candidate for its 24 FMAs).  The kernel values are
+// staged as they are, with each axis's offset into the tile, so that a
+// lane's loads of base, kernel values and charge go out together: the time
+// of a tile is mostly the latency of its two rounds of global loads (bin
+// starts, then candidates).
+//
+// Vector form (T = 4, and tiles split over several wavefronts on small
+// grids): lane c turns its candidate's kernel values into the tile's frame
+// (T weights per axis, zero where the stencil misses the tile) before
+// staging; lane l owns the columns (lx, ly) = (l % T, (l / T) % T) over
+// ZL = T^3 / 64 z cells from (l / T^2) ZL and adds q wx[lx] wy[ly] wz[z] per
+// candidate; the partial tiles of the wavefronts are summed in LDS.
 //
 // Tiles are spread over the 8 XCDs in contiguous ranges (blocks b, b+8, ...
 // run on one XCD), so neighbouring tiles, which share candidate bins and the
 // cache lines of their grid rows, go through the same L2.
-template <typename R, int W, int TT, int WAVES>
+//
+template <typename R> struct Mfma4;
+template <> struct Mfma4<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V op(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ constexpr int row(int k4, int v) { return k4 + 4 * v; }
+};
+template <> struct Mfma4<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V op(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ constexpr int row(int k4, int v) { return 4 * k4 + v; }
+};
+
+template <typename R, int W, int TT, int WAVES, bool MMA>
 __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, int per_xcd,
                                                        const int *__restrict__ start,
                                                        const int4 *__restrict__ base,
@@ -48,13 +78,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
                                                        R *__restrict__ grid) {
     constexpr int T3 = TT * TT * TT;
     constexpr int ZL = T3 / 64;
-    constexpr int SW = 3 * TT + 4;   // staged words: T weights per axis, q, pad
+    // staged words per candidate: the vector form stages T weights per axis
+    // in the tile's frame, the MMA form the W kernel values per axis as they
+    // are (with the stencil index of the tile's first cell per axis in soff);
+    // both then q and a pad
+    constexpr int SW = MMA ? 3 * W + 4 : 3 * TT + 4;
     constexpr int NBMAX = 1 + (W - 1 + TT - 1) / TT;   // bins per axis that reach a tile
     constexpr int NB3 = NBMAX * NBMAX * NBMAX;
     // staging area per wavefront; reused for the sum over wavefronts
     constexpr int STAGE = WAVES * 64 * SW, RED = WAVES > 1 ? WAVES * 3 * T3 : 0;
     __shared__ R lds[STAGE > RED ? STAGE : RED];
     __shared__ int bin_s[NB3], bin_o[NB3], bin_total;
+    __shared__ int soff[MMA ? WAVES * 64 : 1];
     const int ntiles = NT * NT * NT;
     const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tile >= ntiles) return;
@@ -62,9 +97,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
     const int t0[3] = {tx * TT, ty * TT, tz * TT};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane % TT, ly = (lane / TT) % TT, lz0 = (lane / (TT * TT)) * ZL;
+    static_assert(!MMA || (TT == 8 && WAVES == 1), "the matrix-core form: 8^3 tiles, one wavefront");
+    typedef typename Mfma4<R>::V V4;
+    const int i16 = lane & 15, k4 = lane >> 4;
     R acc[3][ZL];
+    V4 dacc[2][4];   // [row block][column block] (MMA form)
 #pragma unroll
     for (int z = 0; z < ZL; z++) acc[0][z] = acc[1][z] = acc[2][z] = (R)0;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) dacc[a][b] = V4{(R)0, (R)0, (R)0, (R)0};
     // start of each bin and exclusive prefix of the bin sizes, in LDS
     // (bins taken 64 at a time by wavefront 0, prefix by shuffles)
     const int nbins = nbv * nbv * nbv;   // nbv <= NBMAX (checked by the launcher)
@@ -109,6 +152,44 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
             if (tb < nbins && bin_o[tb] <= ci) b = tb;
         }
         const int g = bin_s[b] + (ci - bin_o[b]);
+        unsigned long long m;
+        if constexpr (MMA) {
+            // the candidate's base, kernel values and charge, all loaded at
+            // once; offset o of axis a = stencil index of the tile's first
+            // cell, in [1 - T, W - 1] when the stencil reaches the tile (one
+            // interval: the plan keeps n >= W + T)
+            R kv[3 * W], qv[3];
+            int offp = 0;
+            bool act = false;
+            if (ci < total) {
+                const int4 bb = base[g];
+                const R *kg = ker + (size_t)g * 3 * W;
+#pragma unroll
+                for (int j = 0; j < 3 * W; j++) kv[j] = kg[j];
+#pragma unroll
+                for (int c = 0; c < 3; c++) qv[c] = q[4 * (size_t)g + c];
+                const int bv[3] = {bb.x, bb.y, bb.z};
+                act = true;
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    int off = t0[a] - bv[a];
+                    if (off < 0) off += n;
+                    const int o = off < W ? off : off - n;
+                    act = act && o > -TT;
+                    offp |= (o + TT) << (5 * a);
+                }
+            }
+            m = __ballot(act);
+            if (act) {
+                const int slot = __popcll(m & below);
+                R *s = st + slot * SW;
+#pragma unroll
+                for (int j = 0; j < 3 * W; j++) s[j] = kv[j];
+#pragma unroll
+                for (int c = 0; c < 3; c++) s[3 * W + c] = qv[c];
+                soff[wave * 64 + slot] = offp;
+            }
+        } else {
         R wgt[3][TT];
         bool act = false;
         if (ci < total) {
@@ -132,7 +213,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
                 act = act && any;
             }
         }
-        const unsigned long long m = __ballot(act);
+        m = __ballot(act);
         if (act) {
             R *s = st + __popcll(m & below) * SW;
 #pragma unroll
@@ -143,21 +224,74 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
             s[3 * TT + 1] = q[4 * (size_t)g + 1];
             s[3 * TT + 2] = q[4 * (size_t)g + 2];
         }
+        }
         __syncthreads();
         const int na = __popcll(m);
-        for (int c = 0; c < na; c++) {
-            const R *s = st + c * SW;
-            const R wxy = s[lx] * s[TT + ly];
-            const R qx = s[3 * TT] * wxy, qy = s[3 * TT + 1] * wxy, qz = s[3 * TT + 2] * wxy;
+        if constexpr (MMA) {
+            // candidates 4 at a time: A[(c, z)][k] = q_c wz[z] (rows 0..15: c = 0, 1;
+            // rows 16..23: c = 2; rows 24..31 zero), B[k][(y, x)] = wy[y] wx[x]
+            // (column block b: y = 2b, 2b + 1), the weight of tile cell l
+            // along an axis being kernel value o + l (zero outside 0..W-1);
+            // a missing candidate gives zero rows
+            for (int c0 = 0; c0 < na; c0 += 4) {
+                const int c = c0 + k4;
+                R a0 = (R)0, a1 = (R)0, bv[4] = {(R)0, (R)0, (R)0, (R)0};
+                if (c < na) {
+                    const R *s = st + c * SW;
+                    const int op = soff[wave * 64 + c];
+                    const int kx = (op & 31) - TT + (i16 & 7), ky = ((op >> 5) & 31) - TT + (i16 >> 3),
+                              kz = ((op >> 10) & 31) - TT + (i16 & 7);
+                    const R wx = (unsigned)kx < (unsigned)W ? s[kx] : (R)0;
+                    const R wz = (unsigned)kz < (unsigned)W ? s[2 * W + kz] : (R)0;
+                    a0 = s[3 * W + (i16 >> 3)] * wz;
+                    if (i16 < 8) a1 = s[3 * W + 2] * wz;
 #pragma unroll
-            for (int z = 0; z < ZL; z++) {
-                const R wz = s[2 * TT + lz0 + z];
-                acc[0][z] += qx * wz;
-                acc[1][z] += qy * wz;
-                acc[2][z] += qz * wz;
+                    for (int b = 0; b < 4; b++) {
+                        const int k = ky + 2 * b;
+                        bv[b] = ((unsigned)k < (unsigned)W ? s[W + k] : (R)0) * wx;
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    dacc[0][b] = Mfma4<R>::op(a0, bv[b], dacc[0][b]);
+                    dacc[1][b] = Mfma4<R>::op(a1, bv[b], dacc[1][b]);
+                }
+            }
+        } else {
+            for (int c = 0; c < na; c++) {
+                const R *s = st + c * SW;
+                const R wxy = s[lx] * s[TT + ly];
+                const R qx = s[3 * TT] * wxy, qy = s[3 * TT + 1] * wxy, qz = s[3 * TT + 2] * wxy;
+#pragma unroll
+                for (int z = 0; z < ZL; z++) {
+                    const R wz = s[2 * TT + lz0 + z];
+                    acc[0][z] += qx * wz;
+                    acc[1][z] += qy * wz;
+                    acc[2][z] += qz * wz;
+                }
             }
         }
         __syncthreads();
+    }
+    const size_t n3 = (size_t)n * n * n;
+    if constexpr (MMA) {
+        // result element (row block a, column block b, v): row r = 16 a + row(k4, v)
+        // (component r / 8, z = r % 8; rows 24..31 are padding), column
+        // 16 b + i16 (y = 2 b + i16 / 8, x = i16 % 8)
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int r = 16 * a + Mfma4<R>::row(k4, v);
+                    if (r < 24) {
+                        const size_t gi = ((size_t)(t0[2] + (r & 7)) * n + (t0[1] + 2 * b + (i16 >> 3))) * n +
+                                          (t0[0] + (i16 & 7));
+                        grid[(size_t)(r >> 3) * n3 + gi] = dacc[a][b][v];
+                    }
+                }
+        return;
     }
     if (WAVES > 1) {
         // cell (lx, ly, lz0 + z) of wavefront w's partial tile
@@ -178,7 +312,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
             }
         }
     }
-    const size_t n3 = (size_t)n * n * n;
 #pragma unroll
     for (int z = 0; z < ZL; z++) {
         const size_t gi = ((size_t)(t0[2] + lz0 + z) * n + (t0[1] + ly)) * n + (t0[0] + lx);
@@ -192,8 +325,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
 // wavefronts (more parallelism for small grids), and float32 grids of at most
 // kSpreadWideTiles tiles over 8 (a 64^3 grid of 8^3 tiles: the busiest tile
 // holds ~5x the mean candidate count).  The float64 variant stays at 4: at 8
-// its staging area (112 KB) leaves one workgroup per CU, and the per-candidate
-// LDS reads, not the FMAs, bound the loop (measured 21 -> 31 us)
+// its staging area (112 KB) leaves one workgroup per CU
 constexpr int kSpreadSplitTiles = 8192;
 constexpr int kSpreadWideTiles = 512;
 
@@ -214,15 +346,19 @@ static void spread_tt(bs_plan_t p) {
     R *g = (R *)p->grid.p;
 #define SPREAD_CASE(WW)                                                                          \
     case WW:                                                                                     \
-        if (wide)                                                                                \
-            hipLaunchKernelGGL((k_spread<R, WW, TT, 8>), grid, block, 0, p->stream, p->n, p->NT, \
-                               nbv, per, start, base, ker, q, g);                                \
-        else if (split)                                                                          \
-            hipLaunchKernelGGL((k_spread<R, WW, TT, 4>), grid, block, 0, p->stream, p->n, p->NT, \
-                               nbv, per, start, base, ker, q, g);                                \
+        if constexpr (sizeof(R) == 4) {                                                          \
+            if (wide) {                                                                          \
+                hipLaunchKernelGGL((k_spread<R, WW, TT, 8, false>), grid, block, 0, p->stream,   \
+                                   p->n, p->NT, nbv, per, start, base, ker, q, g);               \
+                break;                                                                           \
+            }                                                                                    \
+        }                                                                                        \
+        if (split)                                                                               \
+            hipLaunchKernelGGL((k_spread<R, WW, TT, 4, false>), grid, block, 0, p->stream, p->n, \
+                               p->NT, nbv, per, start, base, ker, q, g);                         \
         else                                                                                     \
-            hipLaunchKernelGGL((k_spread<R, WW, TT, 1>), grid, block, 0, p->stream, p->n, p->NT, \
-                               nbv, per, start, base, ker, q, g);                                \
+            hipLaunchKernelGGL((k_spread<R, WW, TT, 1, TT == 8>), grid, block, 0, p->stream,     \
+                               p->n, p->NT, nbv, per, start, base, ker, q, g);                   \
         break;
     switch (w) {
         SPREAD_CASE(4) SPREAD_CASE(5) SPREAD_CASE(6) SPREAD_CASE(7) SPREAD_CASE(8)
