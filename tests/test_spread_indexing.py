@@ -102,3 +102,35 @@ def test_plan_rejects_grids_too_small_for_the_tiles():
         B.resolve_params(B.make_params(L=2 * math.pi, a=1e-6, tol=1e-6, grid_n=16, w=10,
                                        alpha=1.0, rcut=1.0))
     assert e.value.code == B.BS_EINVAL
+
+
+def offset_weights_index(b, t0, n, W, TT):
+    """The matrix-core form's per-axis mapping: one offset o per axis (the
+    stencil index of the tile's first cell, taken in [1 - T, W - 1] when the
+    stencil reaches the tile), tile cell l taking kernel value o + l when it
+    lies in 0..W-1."""
+    off = (t0 - b) % n
+    o = off if off < W else off - n
+    if o <= -TT:
+        return None
+    return [o + l if 0 <= o + l < W else None for l in range(TT)]
+
+
+@pytest.mark.parametrize("n", [16, 24, 32, 40, 64])
+def test_offset_form_matches_tile_frame_weights(n):
+    T = 8
+    for W in range(4, 17):
+        if n < W + T:
+            continue
+        for b in range(n):
+            for t in range(n // T):
+                ref = tile_weights_index(b, t * T, n, W, T)
+                got = offset_weights_index(b, t * T, n, W, T)
+                if got is None:
+                    assert all(k is None for k in ref), (n, W, b, t)
+                else:
+                    assert got == ref, (n, W, b, t)
+                    # the packed offset o + T fits 5 bits
+                    off = (t * T - b) % n
+                    o = off if off < W else off - n
+                    assert 1 <= o + T <= 31
