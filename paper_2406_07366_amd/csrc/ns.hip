@@ -365,6 +365,25 @@ __device__ __forceinline__ bool ns_test(const NsArgs &a, const NsTarget &T, floa
     return true;
 }
 
+// Necessary condition for ns_test to accept: a target within eta ell of
+// the chord lies within eta ell + |half chord| of its midpoint's nearest
+// image.  r2m = (|h| + eta ell + 1e-5 L)^2 per segment record (the margin
+// covers the float32 rounding of both points); targets near half a period
+// from the midpoint pass, as they go to the float64 test there.
+__device__ __forceinline__ bool ns_pretest(const float *xf, float4 M4, float r2m, float Lf,
+                                           float iLf) {
+    const float m[3] = {M4.x, M4.y, M4.z};
+    float r2 = 0.f, far = 0.f;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const float t = (xf[q] - m[q]) * iLf, w = rintf(t);
+        far = fmaxf(far, fabsf(t - w));
+        const float d = fmaf(-Lf, w, xf[q] - m[q]);
+        r2 = fmaf(d, d, r2);
+    }
+    return r2 < r2m || far > 0.45f;
+}
+
 // Lanes 0..26 of a wavefront: start and size of one of the 27 cells around
 // cell (c0x, c0y, c0z) (lane 0: the single cell when nc < 3); returns the
 // lane's exclusive prefix of the sizes and the total in *total.
@@ -439,10 +458,14 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
 // takes targets w, w + 4, ...  and scans each chunk 64 candidates per step.
 // Flagged candidates are ranked with a ballot, so each target's pairs are
 // written in candidate order to its max_per_node slots.  Targets are taken
-// 256 at a time (their running counts live in LDS).  Records of 36 B (two
-// float4 capsules and the index), 640 at a time, and at most 96 VGPRs keep
-// five wavefronts per SIMD.
-constexpr int kNsStage = 640;
+// 256 at a time (their running counts live in LDS).  A cheap sphere test
+// (ns_pretest) runs first on every candidate; the ~3 % that pass it are
+// queued per wavefront, in candidate order, and the capsule test runs on
+// the queue 64 at a time, so the order of each target's pairs is that of
+// the full scan.  Records of 40 B (two float4 capsules, the sphere radius
+// and the index), 512 at a time, and at most 96 VGPRs keep five wavefronts
+// per SIMD.
+constexpr int kNsStage = 512;
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_ns_flag_cells(NsArgs a, const int *__restrict__ tstart,
                                                        const int *__restrict__ tperm,
@@ -451,6 +474,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                                                        int *__restrict__ status) {
     __shared__ float4 sm[kNsStage], sh4[kNsStage];
     __shared__ int sp[kNsStage];
+    __shared__ float sr2[kNsStage];
+    __shared__ short sq[4][128];   // per wavefront: queued candidates
     // window: the 27 A-cells (entries 0..26), then the B-cells (27..90)
     constexpr int kWin = 27 + 64;
     __shared__ int cell_s[kWin], cell_o[kWin], tk[256], tot_a, tot_b;
@@ -460,6 +485,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     if (nc < 3) return;
     const int nb3 = nc * nc * nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float Lf = (float)a.L, iLf = (float)(1.0 / a.L), band = (float)(1e-5 * a.L);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int C = blockIdx.x; C < nb3; C += gridDim.x) {
         const int t0 = tstart[C], nt = tstart[C + 1] - t0;
@@ -526,9 +552,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         if (tc < kWin && cell_o[tc] <= q) c = tc;
                     }
                     const int p = cell_s[c] + (q - cell_o[c]);
-                    sm[i] = a.segM[p];
-                    sh4[i] = a.segH[p];
+                    const float4 M4 = a.segM[p], H4 = a.segH[p];
+                    sm[i] = M4;
+                    sh4[i] = H4;
                     sp[i] = p;
+                    const float r = sqrtf(H4.x * H4.x + H4.y * H4.y + H4.z * H4.z) + M4.w + band;
+                    sr2[i] = r * r;
                 }
                 __syncthreads();
                 for (int ti = wave; ti < ng; ti += 4) {
@@ -540,17 +569,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     T.xf[0] = t_xf[0][ti]; T.xf[1] = t_xf[1][ti]; T.xf[2] = t_xf[2][ti];
                     int2 *out = slots + (size_t)T.o * a.max_per_node;
                     int k = tk[ti];
-                    for (int j0 = 0; j0 < cn; j0 += 64) {
-                        const int j = j0 + lane;
+                    short *qw = sq[wave];
+                    // capsule test on the first nq (<= 64) queued candidates
+                    auto drain = [&](int nq) {
+                        const int j = lane < nq ? qw[lane] : 0;
                         int sg = 0, sh = 0;
                         const bool flag =
-                            j < cn && ns_test(a, T, sm[j], sh4[j], sp[j], &sg, &sh);
+                            lane < nq && ns_test(a, T, sm[j], sh4[j], sp[j], &sg, &sh);
                         const unsigned long long m = __ballot(flag);
                         if (flag) {
                             const int slot = k + __popcll(m & below);
                             if (slot < a.max_per_node) out[slot] = make_int2(sg, sh);
                         }
                         k += __popcll(m);
+                    };
+                    // pre-test 64 candidates per step while any are left; drain
+                    // the queue when it holds 64, and to the end after the last
+                    int nq = 0;
+                    for (int j0 = 0;;) {
+                        if (j0 < cn) {
+                            const int j = j0 + lane;
+                            const bool pass =
+                                j < cn && (T.exact || ns_pretest(T.xf, sm[j], sr2[j], Lf, iLf));
+                            const unsigned long long m = __ballot(pass);
+                            if (pass) qw[nq + __popcll(m & below)] = (short)j;
+                            nq += __popcll(m);
+                            j0 += 64;
+                        }
+                        const bool done = j0 >= cn;
+                        if (nq >= 64 || (done && nq > 0)) {
+                            const int d = nq < 64 ? nq : 64;
+                            drain(d);
+                            const short rest = lane < nq - d ? qw[d + lane] : (short)0;
+                            if (lane < nq - d) qw[lane] = rest;
+                            nq -= d;
+                        }
+                        if (done && nq == 0) break;
                     }
                     if (lane == 0) tk[ti] = k;
                 }

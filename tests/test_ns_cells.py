@@ -87,3 +87,54 @@ def test_cell_count_matches_the_reach_bound():
         nc = int(math.floor(L / (r * (1 + 1e-9))))
         nc = 1 if nc < 3 else nc
         assert nc == 1 or L / nc >= r
+
+
+def pretest_f32(x, A, B, eta_ell, L):
+    """The search's sphere pre-test, in float32 as the kernel does it: the
+    target against the nearest image of the chord midpoint, radius
+    |half chord| + eta ell + 1e-5 L; near half a period it passes."""
+    f = np.float32
+    Lf, iLf, band = f(L), f(1.0 / L), f(1e-5 * L)
+    xf = wrap(x, L).astype(np.float32)
+    m = (0.5 * (A + B)).astype(np.float32)
+    h = (0.5 * (B - A)).astype(np.float32)
+    t = (xf - m) * iLf
+    w = np.rint(t).astype(np.float32)
+    far = np.abs(t - w).max(-1)
+    d = (xf - m) - Lf * w
+    r2 = (d * d).sum(-1, dtype=np.float32)
+    r = np.sqrt((h * h).sum(-1, dtype=np.float32)) + eta_ell.astype(np.float32) + band
+    return (r2 < r * r) | (far > f(0.45))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pretest_passes_every_flagged_pair(seed):
+    # targets at and just inside eta ell of random chords (in all periodic
+    # images and across the box faces): the pre-test must never drop a pair
+    # the float64 chord test flags, and it should drop most of the others
+    rng = np.random.default_rng(100 + seed)
+    L = 2 * math.pi
+    n = 20000
+    A = rng.uniform(-0.2 * L, 1.2 * L, (n, 3))
+    B = A + rng.normal(0, 0.01 * L, (n, 3)) * rng.uniform(0.05, 1.0, (n, 1))
+    ell = np.linalg.norm(B - A, axis=1) * rng.uniform(1.0, 1.3, n)
+    eta_ell = 1.0 * ell
+    t = rng.uniform(0, 1, (n, 1))
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    rad = eta_ell * rng.uniform(0.0, 1.5, n)
+    x = A + t * (B - A) + rad[:, None] * u + L * rng.integers(-2, 3, (n, 3))
+    flagged = chord_dist(A, B, x, L) < eta_ell
+    passed = pretest_f32(x, A, B, eta_ell, L)
+    assert flagged.sum() > n // 4
+    assert np.all(passed[flagged])
+    # targets spread over a few reaches around the chord (the cells a
+    # target scans), in any periodic image
+    reach = eta_ell + 0.5 * np.linalg.norm(B - A, axis=1)
+    xr = (0.5 * (A + B) + rng.uniform(-3, 3, (n, 3)) * reach[:, None]
+          + L * rng.integers(-2, 3, (n, 3)))
+    fr = chord_dist(A, B, xr, L) < eta_ell
+    pr = pretest_f32(xr, A, B, eta_ell, L)
+    assert np.all(pr[fr])
+    # the sphere holds at most ~2x the capsule's volume (plus the margin)
+    assert pr.mean() < 3.0 * fr.mean() + 0.01, (pr.mean(), fr.mean())
