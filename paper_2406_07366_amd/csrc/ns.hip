@@ -368,8 +368,9 @@ __device__ __forceinline__ bool ns_test(const NsArgs &a, const NsTarget &T, floa
 // Necessary condition for ns_test to accept: a target within eta ell of
 // the chord lies within eta ell + |half chord| of its midpoint's nearest
 // image.  r2m = (|h| + eta ell + 1e-5 L)^2 per segment record (the margin
-// covers the float32 rounding of both points); targets near half a period
-// from the midpoint pass, as they go to the float64 test there.
+// covers the float32 rounding of both points; infinite for records whose
+// midpoint lies beyond the clamped period range); targets near half a
+// period from the midpoint pass, as they go to the float64 test there.
 __device__ __forceinline__ bool ns_pretest(const float *xf, float4 M4, float r2m, float Lf,
                                            float iLf) {
     const float m[3] = {M4.x, M4.y, M4.z};
@@ -556,8 +557,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     sm[i] = M4;
                     sh4[i] = H4;
                     sp[i] = p;
+                    // (a midpoint beyond the clamped period range carries a
+                    // negative eta ell: every target passes to the capsule test,
+                    // which sends it to the float64 decision)
                     const float r = sqrtf(H4.x * H4.x + H4.y * H4.y + H4.z * H4.z) + M4.w + band;
-                    sr2[i] = r * r;
+                    sr2[i] = M4.w < 0.f ? INFINITY : r * r;
                 }
                 __syncthreads();
                 for (int ti = wave; ti < ng; ti += 4) {

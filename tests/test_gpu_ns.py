@@ -120,3 +120,26 @@ def test_mapped_ringpairs_full_sampled(B):
     mx = np.sqrt((d ** 2).sum(1)).max() / math.sqrt((ref ** 2).sum(1).mean())
     print(f"  ringpairs mapped sampled rel_l2 {err:.3e}, max/rms {mx:.2e}")
     assert err <= 1e-5 and mx <= 5e-5
+
+
+def test_far_images_take_the_float64_decision(B):
+    """Every node 600 periods out along x: targets and chord midpoints lie
+    beyond the packed period range, so the search's float32 tests (the
+    sphere pre-test and the capsule test) pass every candidate to the
+    float64 decision, which must flag the same pairs as for the unshifted
+    tangle, with the same correction."""
+    import copy
+    fs = small_ringpairs()
+    far = copy.deepcopy(fs)
+    far.xyz = np.asarray(fs.xyz, dtype=np.float64) + np.array([600.0 * fs.L, 0.0, 0.0])
+    far.name = fs.name + "+600L"
+    p0 = make_plan(B, fs, ns_mode=B.BS_NS_ADAPTIVE)
+    d0 = p0.velocity_terms()["ns"].cpu().numpy()
+    n0 = p0.ns_counts()[0]
+    p1 = make_plan(B, far, ns_mode=B.BS_NS_ADAPTIVE)
+    d1 = p1.velocity_terms()["ns"].cpu().numpy()
+    n1 = p1.ns_counts()[0]
+    err = rel_l2(d1, d0)
+    print(f"  shifted: flagged pairs {n1} (unshifted {n0}), ns term rel diff {err:.2e}")
+    assert n1 == n0 and n0 > fs.n_nodes
+    assert err < 1e-8
