@@ -190,40 +190,40 @@ __global__ __launch_bounds__(64 * WAVES) void k_spread(int n, int NT, int nbv, i
                 soff[wave * 64 + slot] = offp;
             }
         } else {
-        R wgt[3][TT];
-        bool act = false;
-        if (ci < total) {
-            const int4 bb = base[g];
-            const int bv[3] = {bb.x, bb.y, bb.z};
-            act = true;
+            R wgt[3][TT];
+            bool act = false;
+            if (ci < total) {
+                const int4 bb = base[g];
+                const int bv[3] = {bb.x, bb.y, bb.z};
+                act = true;
 #pragma unroll
-            for (int a = 0; a < 3; a++) {
-                // stencil index of the tile's first cell along axis a
-                int off = t0[a] - bv[a];
-                if (off < 0) off += n;
-                bool any = false;
+                for (int a = 0; a < 3; a++) {
+                    // stencil index of the tile's first cell along axis a
+                    int off = t0[a] - bv[a];
+                    if (off < 0) off += n;
+                    bool any = false;
 #pragma unroll
-                for (int l = 0; l < TT; l++) {
-                    int k = off + l;
-                    if (k >= n) k -= n;
-                    R wv = (R)0;
-                    if (k < W) { wv = ker[((size_t)g * 3 + a) * W + k]; any = true; }
-                    wgt[a][l] = wv;
+                    for (int l = 0; l < TT; l++) {
+                        int k = off + l;
+                        if (k >= n) k -= n;
+                        R wv = (R)0;
+                        if (k < W) { wv = ker[((size_t)g * 3 + a) * W + k]; any = true; }
+                        wgt[a][l] = wv;
+                    }
+                    act = act && any;
                 }
-                act = act && any;
             }
-        }
-        m = __ballot(act);
-        if (act) {
-            R *s = st + __popcll(m & below) * SW;
+            m = __ballot(act);
+            if (act) {
+                R *s = st + __popcll(m & below) * SW;
 #pragma unroll
-            for (int a = 0; a < 3; a++)
+                for (int a = 0; a < 3; a++)
 #pragma unroll
-                for (int l = 0; l < TT; l++) s[a * TT + l] = wgt[a][l];
-            s[3 * TT] = q[4 * (size_t)g];
-            s[3 * TT + 1] = q[4 * (size_t)g + 1];
-            s[3 * TT + 2] = q[4 * (size_t)g + 2];
-        }
+                    for (int l = 0; l < TT; l++) s[a * TT + l] = wgt[a][l];
+                s[3 * TT] = q[4 * (size_t)g];
+                s[3 * TT + 1] = q[4 * (size_t)g + 1];
+                s[3 * TT + 2] = q[4 * (size_t)g + 2];
+            }
         }
         __syncthreads();
         const int na = __popcll(m);
