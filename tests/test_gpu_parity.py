@@ -124,6 +124,34 @@ def test_vorticity_modes_match_direct_sums(B):
         plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("w", [4, 8, 16])
+def test_matrix_core_spread_against_direct_sums(B, w, precision):
+    """The spread on a grid of at least 8192 tiles of 8^3 takes its
+    matrix-core form.  A 192^3 grid (13824 tiles) with few retained modes
+    (sigma = 4, so M = 48 and K = 23) lets the type-1 output be checked
+    against the direct sums of eq:vorticity_fourier_coefs at every mode, for
+    kernel widths with 1, 8 and 27 candidate bins per tile."""
+    fs = W.ellipses()
+    fs.grid_n = 192
+    kw = dict(sigma=4.0, w=w)
+    if precision == "mixed":
+        kw["precision"] = B.BS_FP32_MIXED
+    plan = make_plan(B, fs, **kw)
+    prm = plan.params()
+    assert prm.grid_n == 192 and prm.K == 23
+    m = np_(plan.vorticity_modes())
+    plan.close()
+    gpu = m[..., 0] + 1j * m[..., 1]
+    ref = O.Oracle(fs).omega_hat(prm.K)
+    l2 = np.linalg.norm(gpu - ref) / np.linalg.norm(ref)
+    mx = np.abs(gpu - ref).max() / np.abs(ref).max()
+    print(f"  w={w} {precision}: rel_l2 {l2:.2e} max {mx:.2e}")
+    floor = 1e-11 if precision == "fp64" else 2e-6
+    assert l2 < max(10 ** (-0.9 * w + 1), floor)
+    assert mx < max(10 ** (-0.9 * w + 2), 10 * floor)
+
+
 @pytest.mark.parametrize("name", ["ring", "ellipses"])
 def test_velocity_fp64_meets_1e6(B, name):
     fs = W.make(name)
