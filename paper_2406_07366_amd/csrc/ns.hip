@@ -366,23 +366,14 @@ __device__ __forceinline__ bool ns_test(const NsArgs &a, const NsTarget &T, floa
 }
 
 // Necessary condition for ns_test to accept: a target within eta ell of
-// the chord lies within eta ell + |half chord| of its midpoint's nearest
-// image.  r2m = (|h| + eta ell + 1e-5 L)^2 per segment record (the margin
-// covers the float32 rounding of both points; infinite for records whose
-// midpoint lies beyond the clamped period range); targets near half a
-// period from the midpoint pass, as they go to the float64 test there.
-__device__ __forceinline__ bool ns_pretest(const float *xf, float4 M4, float r2m, float Lf,
-                                           float iLf) {
-    const float m[3] = {M4.x, M4.y, M4.z};
-    float r2 = 0.f, far = 0.f;
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-        const float t = (xf[q] - m[q]) * iLf, w = rintf(t);
-        far = fmaxf(far, fabsf(t - w));
-        const float d = fmaf(-Lf, w, xf[q] - m[q]);
-        r2 = fmaf(d, d, r2);
-    }
-    return r2 < r2m || far > 0.45f;
+// the chord lies within eta ell + |half chord| of the chord midpoint's
+// nearest image.  The staged midpoint m is that image for every target of
+// the cell (section below), r2m = (|h| + eta ell + 1e-5 L)^2 (the margin
+// covers the float32 rounding of both points), infinite for records that
+// every target passes.
+__device__ __forceinline__ bool ns_pretest(const float *xf, float4 M4, float r2m) {
+    const float d0 = xf[0] - M4.x, d1 = xf[1] - M4.y, d2 = xf[2] - M4.z;
+    return fmaf(d2, d2, fmaf(d1, d1, d0 * d0)) < r2m;
 }
 
 // Lanes 0..26 of a wavefront: start and size of one of the 27 cells around
@@ -492,6 +483,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const int t0 = tstart[C], nt = tstart[C + 1] - t0;
         if (nt == 0) continue;   // uniform over the workgroup
         const int c0[3] = {C % nc, (C / nc) % nc, C / (nc * nc)};
+        const float cc[3] = {(float)((c0[0] + 0.5) * a.L / nc), (float)((c0[1] + 0.5) * a.L / nc),
+                             (float)((c0[2] + 0.5) * a.L / nc)};   // the cell's centre
         if (wave == 0) {
             int cs, cn, total;
             const int excl = ns_window(a, nc, c0, lane, &cs, &cn, &total);
@@ -553,15 +546,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         if (tc < kWin && cell_o[tc] <= q) c = tc;
                     }
                     const int p = cell_s[c] + (q - cell_o[c]);
-                    const float4 M4 = a.segM[p], H4 = a.segH[p];
+                    float4 M4 = a.segM[p], H4 = a.segH[p];
+                    // the midpoint's image nearest the cell's centre, with its
+                    // period indices moved by the same shift (the capsule
+                    // test's float decision and image shift are unchanged):
+                    // for every target of the cell that is the nearest image
+                    // when the window lies within 0.45 L of the cell
+                    // (window A: 2 h_A, five or more cells per axis; window
+                    // B: 3 h_B, eight or more).  Other records, and midpoints
+                    // beyond the clamped period range (negative eta ell, sent
+                    // to the float64 decision), pass every target.
+                    float r2m = INFINITY;
+                    if ((q < tot_a ? nc >= 5 : ncb >= 8) && M4.w >= 0.f) {
+                        int km = __float_as_int(H4.w);
+                        float m[3] = {M4.x, M4.y, M4.z};
+#pragma unroll
+                        for (int ax = 0; ax < 3; ax++) {
+                            const float sft = rintf((cc[ax] - m[ax]) * iLf);
+                            m[ax] = fmaf(Lf, sft, m[ax]);
+                            km -= (int)sft * (1 << (20 - 10 * ax));
+                        }
+                        M4.x = m[0]; M4.y = m[1]; M4.z = m[2];
+                        H4.w = __int_as_float(km);
+                        const float r = sqrtf(H4.x * H4.x + H4.y * H4.y + H4.z * H4.z) + M4.w + band;
+                        r2m = r * r;
+                    }
                     sm[i] = M4;
                     sh4[i] = H4;
                     sp[i] = p;
-                    // (a midpoint beyond the clamped period range carries a
-                    // negative eta ell: every target passes to the capsule test,
-                    // which sends it to the float64 decision)
-                    const float r = sqrtf(H4.x * H4.x + H4.y * H4.y + H4.z * H4.z) + M4.w + band;
-                    sr2[i] = M4.w < 0.f ? INFINITY : r * r;
+                    sr2[i] = r2m;
                 }
                 __syncthreads();
                 for (int ti = wave; ti < ng; ti += 4) {
@@ -594,7 +607,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         if (j0 < cn) {
                             const int j = j0 + lane;
                             const bool pass =
-                                j < cn && (T.exact || ns_pretest(T.xf, sm[j], sr2[j], Lf, iLf));
+                                j < cn && (T.exact || ns_pretest(T.xf, sm[j], sr2[j]));
                             const unsigned long long m = __ballot(pass);
                             if (pass) qw[nq + __popcll(m & below)] = (short)j;
                             nq += __popcll(m);
