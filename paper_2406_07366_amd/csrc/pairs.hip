@@ -19,9 +19,10 @@ namespace bs {
 
 // g_sr(x) = erfc(x) + (2/sqrt(pi)) x exp(-x^2) = exp(-x^2) (erfcx(x) +
 // (2/sqrt(pi)) x): one exponential, with erfcx = P(Z) / (4 + x),
-// Z = (4 - x) / (4 + x), from its fitted polynomial (relative error 3e-15
-// for x = alpha r below the beta of every tolerance in Table 1, 7e-14 where
-// the term is below 1e-15 of its value at r = 0)
+// Z = (4 - x) / (4 + x), from its fitted polynomial (float64: relative
+// error 3e-15 for x = alpha r below the beta of every tolerance in Table 1,
+// 7e-14 where the term is below 1e-15 of its value at r = 0; float32:
+// 4e-7, below the float32 rounding of exp(-x^2) for x near beta)
 __device__ __forceinline__ double g_short(double x) {
     constexpr double two_over_sqrtpi = 1.12837916709551257389615890312154517;
     const double inv = 1.0 / (kErfcxShift + x);
@@ -33,7 +34,12 @@ __device__ __forceinline__ double g_short(double x) {
 }
 __device__ __forceinline__ float g_short(float x) {
     constexpr float two_over_sqrtpi = 1.12837916709551257389615890312154517f;
-    return erfcf(x) + two_over_sqrtpi * x * expf(-x * x);
+    const float inv = __builtin_amdgcn_rcpf((float)kErfcxShift + x);
+    const float z = ((float)kErfcxShift - x) * inv;
+    float p = kErfcxP32[kErfcxDeg32];
+#pragma unroll
+    for (int k = kErfcxDeg32 - 1; k >= 0; k--) p = fmaf(p, z, kErfcxP32[k]);
+    return expf(-x * x) * fmaf(p, inv, two_over_sqrtpi * x);
 }
 
 // One wavefront (four on small inputs) per target node.  Each lane holds one of the

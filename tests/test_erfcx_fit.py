@@ -44,6 +44,28 @@ def test_table_matches_erfcx():
     assert np.abs(erfcx_kernel(far) / erfcx(far) - 1).max() < 2e-13
 
 
+def table32():
+    src = open(os.path.join(CSRC, "erfcx_fit.h")).read()
+    body = re.search(r"kErfcxP32\[kErfcxDeg32 \+ 1\] = \{([^}]*)\}", src).group(1)
+    return [np.float32(v.strip().rstrip("f")) for v in body.replace("\n", " ").split(",")
+            if v.strip()]
+
+
+def test_float32_table_matches_erfcx():
+    # the float32 kernel's evaluation: float32 reciprocal, Z and Horner
+    f = np.float32
+    shift, _ = table()
+    coef = table32()
+    x = np.linspace(0.0, 6.0, 200001).astype(f)
+    inv = (f(1.0) / (f(shift) + x)).astype(f)
+    z = ((f(shift) - x) * inv).astype(f)
+    p = np.full_like(z, coef[-1])
+    for c in coef[-2::-1]:
+        p = (p * z + c).astype(f)
+    got = (p * inv).astype(np.float64)
+    assert np.abs(got / erfcx(x.astype(np.float64)) - 1).max() < 1e-6
+
+
 def test_short_range_factor():
     x = np.linspace(0.0, 6.0, 100001)
     ref = erfc(x) + 2 / math.sqrt(math.pi) * x * np.exp(-x * x)
