@@ -531,13 +531,11 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
     stage_begin(P, 0);
     launch_filaments(P, xyz, gamma);   // also takes the plan's copies of xyz and gamma
     stage_end(P, 0);
-    stage_begin(P, 1);
-    build_bins(P);
-    stage_end(P, 1);
     if (P->prm.ns_mode != BS_NS_OFF) {
-        // the pair search needs only the geometry and the node order: it runs
-        // on the side stream, where the velocity's short-range and
-        // near-singular terms follow it (per-stage timing keeps it here)
+        // the pair search needs only the geometry: it runs on the side stream,
+        // beside the binning, and the velocity's short-range and
+        // near-singular terms follow it there (per-stage timing keeps it on
+        // the plan's stream)
         const bool side = !P->prof;
         if (side &&
             ((rc = check_hip(P, hipEventRecord(P->ev_fork, P->stream), "hipEventRecord")) ||
@@ -554,6 +552,9 @@ int bs_set_filaments(bs_plan_t P, int64_t nfil, const int64_t *offsets, const do
             P->side_pending = true;
         }
     }
+    stage_begin(P, 1);
+    build_bins(P);
+    stage_end(P, 1);
     if ((rc = launch_status(P, "geometry kernels"))) return rc;
     P->have_filaments = true;
     stage_collect(P);

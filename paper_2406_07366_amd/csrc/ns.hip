@@ -262,7 +262,7 @@ struct NsArgs {
     int N, max_per_node;
     double L, eta;
     const double *x;
-    const int *off, *fil, *nperm, *ncp, *cstart, *segj;
+    const int *off, *fil, *ncp, *cstart, *segj;
     const double4 *segA, *segB;
     const float4 *segM, *segH;
 };
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256) void k_ns_flag(NsArgs a, int *__restrict__ cnt
     const int lane = gid & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int t = gid >> 6; t < a.N; t += (gridDim.x * blockDim.x) >> 6) {
-        const NsTarget T = ns_target(a, a.nperm[t]);
+        const NsTarget T = ns_target(a, t);
         const int zero[3] = {0, 0, 0};
         int cs, cn, total;
         ns_window(a, 1, zero, lane, &cs, &cn, &total);
@@ -1494,7 +1494,7 @@ void ns_build_pairs(bs_plan_t p) {
     a.N = N; a.max_per_node = p->ns_max_per_node;
     a.L = p->prm.L; a.eta = p->prm.ns_eta;
     a.x = x; a.off = off; a.fil = fil;
-    a.nperm = (const int *)p->nd_perm.p; a.ncp = ncp; a.cstart = cstart;
+    a.ncp = ncp; a.cstart = cstart;
     a.segA = (const double4 *)p->ns_segA.p; a.segB = (const double4 *)p->ns_segB.p;
     a.segM = (const float4 *)p->ns_segM.p; a.segH = (const float4 *)p->ns_segH.p;
     a.segj = (const int *)cperm;
