@@ -137,6 +137,17 @@ static void fill_f64(bs_plan_t p, double *ptr, size_t n, double v) {
                        n, v);
 }
 
+__global__ void k_add_f64(double *__restrict__ y, const double *__restrict__ x, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += x[i];
+}
+
+static void add_f64(bs_plan_t p, double *y, const double *x, size_t n) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_add_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p->stream, y, x,
+                       n);
+}
+
 static int launch_status(bs_plan_t p, const char *what) {
     return check_hip(p, hipGetLastError(), what);
 }
@@ -623,10 +634,13 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     // local - self was formed by set_filaments (d_vls).  The short-range sum
     // and the near-singular correction run on the side stream into
     // tmp3 = (local - self) + short (+ near-singular), concurrently with the
-    // spread and the transforms on the plan stream; the interpolation waits
-    // for them and writes v = tmp3 + long-range.  With per-stage timing on,
-    // everything stays on the plan stream, so that each stage's events
-    // bracket its own kernels only.
+    // spread and the transforms on the plan stream.  Without the correction
+    // the interpolation waits for them and writes v = tmp3 + long-range;
+    // with it (the side stream's longer chain) the interpolation writes the
+    // long-range term alone and tmp3 is added once the side work is in, so
+    // that the correction's integrals can run beside the interpolation (the
+    // same sum, bitwise).  With per-stage timing on, everything stays on the
+    // plan stream, so that each stage's events bracket its own kernels only.
     double *t3 = (double *)P->tmp3.p;
     const bool side = !P->prof;
     int rc;
@@ -649,7 +663,15 @@ int bs_velocity(bs_plan_t P, double *v_out) {
     P->stream = plan_stream;
     const hipError_t ej = side ? hipEventRecord(P->ev_join, P->side) : hipSuccess;
     if (rc || (rc = check_hip(P, ej, "hipEventRecord"))) return rc;
-    if ((rc = long_range(P, 0, t3, v_out, side ? P->ev_join : nullptr))) return rc;
+    if (side && P->prm.ns_mode != BS_NS_OFF) {
+        fill_f64(P, v_out, 3 * (size_t)P->N, 0.0);
+        if ((rc = long_range(P, 0, nullptr, v_out))) return rc;
+        if ((rc = check_hip(P, hipStreamWaitEvent(P->stream, P->ev_join, 0), "hipStreamWaitEvent")))
+            return rc;
+        add_f64(P, v_out, t3, 3 * (size_t)P->N);
+    } else if ((rc = long_range(P, 0, t3, v_out, side ? P->ev_join : nullptr))) {
+        return rc;
+    }
     P->side_pending = false;   // the plan stream now waits for all side work
     if ((rc = launch_status(P, "pair kernel"))) return rc;
     stage_collect(P);
