@@ -1515,13 +1515,19 @@ void ns_build_pairs(bs_plan_t p) {
 void ns_rule(NsRule *R);
 
 // the graded-panel integrator on every pair (list == nullptr) or on the
-// listed ones; nothing when *skip is set
+// listed ones; nothing when *skip is set.  The pair count is known on the
+// device only: the grid strides over it with many more workgroups than fit
+// at once (three wavefronts per SIMD at its 158 VGPRs), so that the last
+// round does not run the CUs a third full (1024 workgroups: 1.48 ms for the
+// 1.1e7 pairs of the 1e6-node tangle; 12288: 1.36 ms)
+constexpr int kNsIntegrateBlocks = 12288;
+
 static void adaptive_pairs(bs_plan_t p, const int *count, const int *list,
                            const int *skip = nullptr) {
     NsRule R;
     ns_rule(&R);
-    hipLaunchKernelGGL(k_ns_integrate, dim3(1024), dim3(256), 0, p->stream, count, list,
-                       (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
+    hipLaunchKernelGGL(k_ns_integrate, dim3(kNsIntegrateBlocks), dim3(256), 0, p->stream,
+                       count, list, (const int *)p->ns_pnode.p, (const int2 *)p->ns_pairs.p,
                        (const int *)p->d_off.p, (const int *)p->d_fil.p,
                        (const double *)p->d_x.p, (const double *)p->d_xn.p,
                        (const double *)p->d_D.p, p->order == 6 ? (const double *)p->d_sdd.p : nullptr,
