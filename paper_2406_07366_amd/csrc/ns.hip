@@ -904,20 +904,41 @@ __global__ __launch_bounds__(256) void k_ns_integrate(
     }
 }
 
-// owner node of each pair slot (for the per-pair kernel)
-__global__ void k_ns_apply(int N, const int *__restrict__ pstart, const double *__restrict__ pout,
-                           double *__restrict__ v) {
-    int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= N) return;
+// v[o] += the sum of node o's pair terms, in pair order.  The pairs of a
+// workgroup's 256 nodes are one contiguous range of pout: it is staged
+// through LDS in chunks with coalesced loads (a thread walking its own pairs
+// in global memory touched a cache line per lane), and each node then sums
+// its own pairs from LDS in the same order.  Launched with 256 threads.
+constexpr int kNsApplyChunk = 1024;   // pairs per staged chunk (24 KB)
+__global__ __launch_bounds__(256) void k_ns_apply(int N, const int *__restrict__ pstart,
+                                                  const double *__restrict__ pout,
+                                                  double *__restrict__ v) {
+    __shared__ double sp[3 * kNsApplyChunk];
+    const int o0 = blockIdx.x * 256, o = o0 + (int)threadIdx.x;
+    if (o0 >= N) return;   // uniform over the workgroup
+    const int oe = o0 + 256 < N ? o0 + 256 : N;
+    const int p0 = pstart[o0], p1 = pstart[oe];
+    int ps = 0, pe = 0;
+    if (o < N) { ps = pstart[o]; pe = pstart[o + 1]; }
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int p = pstart[o]; p < pstart[o + 1]; p++) {
-        s0 += pout[3 * (size_t)p];
-        s1 += pout[3 * (size_t)p + 1];
-        s2 += pout[3 * (size_t)p + 2];
+    for (int c0 = p0; c0 < p1; c0 += kNsApplyChunk) {
+        const int cn = p1 - c0 < kNsApplyChunk ? p1 - c0 : kNsApplyChunk;
+        __syncthreads();   // the previous chunk's reads are done
+        const double *src = pout + 3 * (size_t)c0;
+        for (int i = threadIdx.x; i < 3 * cn; i += 256) sp[i] = src[i];
+        __syncthreads();
+        const int a = ps > c0 ? ps : c0, b = pe < c0 + cn ? pe : c0 + cn;
+        for (int q = a - c0; q < b - c0; q++) {
+            s0 += sp[3 * q];
+            s1 += sp[3 * q + 1];
+            s2 += sp[3 * q + 2];
+        }
     }
-    v[3 * o] += s0;
-    v[3 * o + 1] += s1;
-    v[3 * o + 2] += s2;
+    if (o < N) {
+        v[3 * o] += s0;
+        v[3 * o + 1] += s1;
+        v[3 * o + 2] += s2;
+    }
 }
 
 // ------------------------------------------------------ learned correction
