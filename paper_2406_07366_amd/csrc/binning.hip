@@ -189,20 +189,22 @@ struct GatherOut {
     double4 *spos;   // w: the point's segment index
 };
 
+// (the w kernel values of thread t go to lk[0 .. w-1]; the caller writes them
+// to ker[t w ..])
 template <typename R>
 __device__ __forceinline__ void gather_one(int t, int w, int Q, const int *__restrict__ sperm,
                                            const int *__restrict__ pperm,
                                            const double *__restrict__ pos,
                                            const double *__restrict__ chg, double L, double inv_h,
-                                           int n, double zeta, double inv_den, const GatherOut &G) {
+                                           int n, double zeta, double inv_den, const GatherOut &G,
+                                           R *lk) {
     const int p = t / 3, d = t - 3 * p;
-    R *ker = (R *)G.ker, *q = (R *)G.q, *schg = (R *)G.schg;
+    R *q = (R *)G.q, *schg = (R *)G.schg;
     int o = sperm[p];
     double f;
     const int b = stencil_base(wrap_box(pos[3 * o + d], L), inv_h, w, n, &f);
     const double half = 0.5 * w;
-    for (int k = 0; k < w; k++)
-        ker[((size_t)p * 3 + d) * w + k] = (R)kb_phi((k - f) / half, zeta, inv_den);
+    for (int k = 0; k < w; k++) lk[k] = (R)kb_phi((k - f) / half, zeta, inv_den);
     int *bp = (int *)(G.base + p);
     bp[d] = b;
     q[4 * (size_t)p + d] = (R)chg[3 * o + d];
@@ -218,14 +220,30 @@ __device__ __forceinline__ void gather_one(int t, int w, int Q, const int *__res
     }
 }
 
+// Thread t = 3 p + d writes its kernel values at ker[t w ..], so those of a
+// workgroup form one contiguous range: they are staged in LDS and written out
+// with consecutive threads on consecutive words (a thread writing its own w
+// values touched a cache line per lane in each store).  256 threads, w <= 16.
+constexpr int kGatherBlock = 256;
 template <typename R>
-__global__ void k_gather_all(int M, int w, int Q, const int *__restrict__ sperm,
-                             const int *__restrict__ pperm, const double *__restrict__ pos,
-                             const double *__restrict__ chg, double L, double inv_h, int n,
-                             double zeta, double inv_den, GatherOut G) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * M) return;
-    gather_one<R>(t, w, Q, sperm, pperm, pos, chg, L, inv_h, n, zeta, inv_den, G);
+__global__ __launch_bounds__(kGatherBlock) void k_gather_all(int M, int w, int Q,
+                                                             const int *__restrict__ sperm,
+                                                             const int *__restrict__ pperm,
+                                                             const double *__restrict__ pos,
+                                                             const double *__restrict__ chg,
+                                                             double L, double inv_h, int n,
+                                                             double zeta, double inv_den,
+                                                             GatherOut G) {
+    __shared__ R lk[kGatherBlock * 16];
+    const int t0 = blockIdx.x * kGatherBlock, t = t0 + (int)threadIdx.x;
+    if (t0 >= 3 * M) return;   // uniform over the workgroup
+    if (t < 3 * M)
+        gather_one<R>(t, w, Q, sperm, pperm, pos, chg, L, inv_h, n, zeta, inv_den, G,
+                      lk + threadIdx.x * w);
+    __syncthreads();
+    const int nt = 3 * M - t0 < kGatherBlock ? 3 * M - t0 : kGatherBlock;
+    R *ker = (R *)G.ker + (size_t)t0 * w;
+    for (int i = threadIdx.x; i < nt * w; i += kGatherBlock) ker[i] = lk[i];
 }
 
 void build_bins(bs_plan_t p) {
@@ -262,11 +280,13 @@ void build_bins(bs_plan_t p) {
     hipLaunchKernelGGL(k_scatter_all, dim3(ceil_div(2 * M + N, bs)), dim3(bs), 0, p->stream, S);
     hipLaunchKernelGGL(k_sort_all, dim3(ntiles + 2 * nc3), dim3(64), 0, p->stream, S);
     if (p->fp32)
-        hipLaunchKernelGGL(k_gather_all<float>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0,
+        hipLaunchKernelGGL(k_gather_all<float>, dim3(ceil_div(3 * (int64_t)M, kGatherBlock)),
+                           dim3(kGatherBlock), 0,
                            p->stream, M, w, p->Q, S.perm[0], S.perm[1], qp, qc, L, inv_h, n, zeta,
                            inv_den, G);
     else
-        hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(3 * (int64_t)M, bs)), dim3(bs), 0,
+        hipLaunchKernelGGL(k_gather_all<double>, dim3(ceil_div(3 * (int64_t)M, kGatherBlock)),
+                           dim3(kGatherBlock), 0,
                            p->stream, M, w, p->Q, S.perm[0], S.perm[1], qp, qc, L, inv_h, n, zeta,
                            inv_den, G);
 }
