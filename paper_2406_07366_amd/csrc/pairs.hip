@@ -60,7 +60,7 @@ constexpr int kQueue = 128;
 
 template <typename R, bool PSI, int WPN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs(
-    int N, int nc, double L, double rc, double alpha,
+    int N, int nc, int per_xcd, double L, double rc, double alpha,
                                                const int *__restrict__ nperm,
                                                const double *__restrict__ x,
                                                const int *__restrict__ off,
@@ -82,8 +82,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                                : (~0ull >> (64 - (threadIdx.x & 63)));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // WPN = 1: four targets per workgroup; WPN = 4: one target, its
-    // candidate chunks dealt round-robin to the four wavefronts
-    const int t = WPN == 1 ? blockIdx.x * 4 + wave : blockIdx.x;
+    // candidate chunks dealt round-robin to the four wavefronts.  Targets
+    // come in cell order, and consecutive workgroups of them stay on one XCD
+    // (blocks b, b + 8, ... run on one XCD), so that the candidate windows
+    // that neighbouring cells share are fetched into one L2
+    const int blk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int t = WPN == 1 ? blk * 4 + wave : blk;
     const int part = WPN == 1 ? 0 : wave;
     if (t >= N) return;   // whole wavefronts (WPN = 1) or the whole workgroup
     const int o = nperm[t];
@@ -268,7 +272,8 @@ template <typename R, bool PSI>
 static void pairs_r(bs_plan_t p, const double *base, double *out, bool alone) {
     const int N = (int)p->N;
     const bool split = N < kPairSplitNodes && alone;
-    dim3 grid(split ? N : ceil_div(N, 4)), block(256);
+    const int nblk = split ? N : ceil_div(N, 4), per = ceil_div(nblk, 8);
+    dim3 grid(8 * per), block(256);
     const double L = p->prm.L, rc = p->prm.rcut, alpha = p->prm.alpha;
     const int *nperm = (const int *)p->nd_perm.p, *off = (const int *)p->d_off.p,
               *fil = (const int *)p->d_fil.p, *cs = (const int *)p->pq_start.p;
@@ -276,10 +281,10 @@ static void pairs_r(bs_plan_t p, const double *base, double *out, bool alone) {
     const double4 *sp = (const double4 *)p->pq_pos.p;
     const R *q = (const R *)p->pq_chg.p;
     if (split)
-        hipLaunchKernelGGL((k_pairs<R, PSI, 4>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
+        hipLaunchKernelGGL((k_pairs<R, PSI, 4>), grid, block, 0, p->stream, N, p->nc, per, L, rc, alpha,
                            nperm, x, off, fil, cs, sp, q, base, out);
     else
-        hipLaunchKernelGGL((k_pairs<R, PSI, 1>), grid, block, 0, p->stream, N, p->nc, L, rc, alpha,
+        hipLaunchKernelGGL((k_pairs<R, PSI, 1>), grid, block, 0, p->stream, N, p->nc, per, L, rc, alpha,
                            nperm, x, off, fil, cs, sp, q, base, out);
 }
 
