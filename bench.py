@@ -44,6 +44,8 @@ PAIR_FLOP = 60.0               # per interacting pair (erfc, exp, sqrt, div, cro
 # stages made of exactly one kernel launch, and the source file of that kernel
 SINGLE_KERNEL_STAGES = {"spread": "nufft.hip", "spectral": "nufft.hip", "interp": "nufft.hip",
                         "pairs": "pairs.hip"}
+# the single-kernel stages on the plan's stream (the pair sum runs on the second)
+PLAN_STREAM_STAGES = ("spread", "spectral", "interp")
 
 
 def log(*a):
@@ -73,7 +75,8 @@ def count_pairs(plan, fs, Q, rc):
     qp = plan.geometry()["qpos"].cpu().numpy()
     L = fs.L
     tree = cKDTree(np.mod(qp, L) % L, boxsize=L)
-    cnt = tree.query_ball_point(np.mod(fs.xyz, L) % L, rc, return_length=True)
+    cnt = tree.query_ball_point(np.mod(fs.xyz, L) % L, rc, return_length=True,
+                                workers=min(16, os.cpu_count() or 1))
     return int(cnt.sum()) - 2 * Q * fs.n_nodes
 
 
@@ -262,6 +265,11 @@ def main():
                     help="the paper's performance tests (Sec. 5.3, Table 1) instead of the "
                          "default line: comma-separated ellipse counts (32 nodes each); one "
                          "JSON line per tolerance and size, errors against the tol = 1e-14 run")
+    ap.add_argument("--stage-pass", action="store_true",
+                    help="run only the per-stage timing pass (stages one after another, as the "
+                         "roofline's kernel durations are measured) for --steps evaluations of "
+                         "each leg and print its stage times: the command to profile when "
+                         "comparing rocprofv3's kernel durations with the roofline's")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="end with a plain 256 MiB device copy, the size reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc run")
@@ -309,6 +317,13 @@ def main():
         if ns_mode == B.BS_NS_MLP:
             plan.set_mlp(mlp, table)
         prm = plan.params()
+        if args.stage_pass:
+            st = stage_profile(torch, plan, fs, xyz, gamma, out, max(1, args.steps))
+            plan.status()
+            log(f"[bench] {name} stage pass, {max(1, args.steps)} evaluations (ms): "
+                + ", ".join(f"{k}={v:.4f}" for k, v in st.items()))
+            plan.close()
+            continue
         plan.set_filaments(fs.offsets, xyz, gamma)
         plan.velocity(out)
         plan.status()
@@ -325,6 +340,9 @@ def main():
         results[name] = dict(ms=ms_host, ms_events=ms_ev, err=err, errmax=errmax, stages=st,
                              prm=prm.as_dict(), plan=plan, ns_mode=ns_mode, tol=tol,
                              precision=prec, ns_pairs=npairs, ns_fallback=nfb)
+
+    if args.stage_pass:
+        return
 
     if args.pmc_calibrate:
         src_t = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -348,28 +366,38 @@ def main():
         if st.get(k, 0) > 0:
             roof_all[k] = dict(bound="hbm", achieved=b / (st[k] * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                                unit="GB/s", bytes=b, ms=st[k])
-    if st.get("pairs", 0) > 0 and N <= 300_000:
+    if st.get("pairs", 0) > 0:
         npairs = count_pairs(primary["plan"], fs, prm["Q"], prm["rcut"])
         peak = FP32_VECTOR_TFLOPS if fp32 else FP64_VECTOR_TFLOPS
         fl = npairs * PAIR_FLOP
         roof_all["pairs"] = dict(bound="alu", achieved=fl / (st["pairs"] * 1e-3) / 1e12,
                                  peak=peak, unit="TFLOP/s", flops=fl, pairs=npairs,
                                  ms=st["pairs"])
-    # dominant single-kernel stage (the stage events then time exactly one kernel)
-    dom = max((k for k in roof_all if k in SINGLE_KERNEL_STAGES), key=lambda k: roof_all[k]["ms"])
-    d = roof_all[dom]
-    srcname = SINGLE_KERNEL_STAGES[dom]
-    if dom == "spectral" and pruned_transforms(rp):
-        srcname = "fft.hip"         # the spectral operator runs inside the z transform
-    src = os.path.join(ROOT, "paper_2406_07366_amd", "csrc", srcname)
-    traffic = read_traffic(os.path.join(ROOT, "profiles",
-                                        f"pmc_{dom}_{fs.name}_{'mixed' if fp32 else 'fp64'}.txt"),
-                           src)
-    roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"],
-                "peak": d["peak"], "unit": d["unit"], "frac": d["achieved"] / d["peak"],
-                "traffic": traffic}
-    if "bytes" in d:
-        roofline["algorithmic_bytes"] = d["bytes"]
+    # dominant single-kernel stage of the plan's stream, the evaluation's
+    # critical path (the stage events then time exactly one kernel); the pair
+    # sum runs on the second stream beside it and is reported with it
+    def roof_entry(k):
+        d = roof_all[k]
+        srcname = SINGLE_KERNEL_STAGES[k]
+        if k == "spectral" and pruned_transforms(rp):
+            srcname = "fft.hip"         # the spectral operator runs inside the z transform
+        src = os.path.join(ROOT, "paper_2406_07366_amd", "csrc", srcname)
+        traffic = read_traffic(os.path.join(
+            ROOT, "profiles", f"pmc_{k}_{fs.name}_{'mixed' if fp32 else 'fp64'}.txt"), src)
+        e = {"kernel": k, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+             "unit": d["unit"], "frac": d["achieved"] / d["peak"], "traffic": traffic,
+             "ms": d["ms"]}
+        if "bytes" in d:
+            e["algorithmic_bytes"] = d["bytes"]
+        if "flops" in d:
+            e["algorithmic_flops"] = d["flops"]
+            e["pairs"] = d["pairs"]
+        return e
+
+    dom = max((k for k in roof_all if k in PLAN_STREAM_STAGES), key=lambda k: roof_all[k]["ms"])
+    roofline = roof_entry(dom)
+    if "pairs" in roof_all:
+        roofline["side_stream"] = roof_entry("pairs")
 
     cpu = None
     if not args.no_cpu_baseline:
