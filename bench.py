@@ -267,8 +267,8 @@ def main():
                          "JSON line per tolerance and size, errors against the tol = 1e-14 run")
     ap.add_argument("--stage-pass", action="store_true",
                     help="run only the per-stage timing pass (stages one after another, as the "
-                         "roofline's kernel durations are measured) for --steps evaluations of "
-                         "each leg and print its stage times: the command to profile when "
+                         "roofline's kernel durations are measured) for one warm-up and --steps "
+                         "evaluations of each leg and print its stage times: the command to profile when "
                          "comparing rocprofv3's kernel durations with the roofline's")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="end with a plain 256 MiB device copy, the size reference for the "
@@ -318,6 +318,7 @@ def main():
             plan.set_mlp(mlp, table)
         prm = plan.params()
         if args.stage_pass:
+            stage_profile(torch, plan, fs, xyz, gamma, out, 1)   # warm-up (first launches)
             st = stage_profile(torch, plan, fs, xyz, gamma, out, max(1, args.steps))
             plan.status()
             log(f"[bench] {name} stage pass, {max(1, args.steps)} evaluations (ms): "
