@@ -877,8 +877,10 @@ __device__ void ns_pair(int o, int sg, int sh, const int *off, const int *fil, c
     for (int q = 0; q < 3; q++) out[q] = g4 * acc[q] - qs[q] / (4.0 * kPi);
 }
 
-// every pair (list == nullptr, count = total pairs), or the pairs listed
-__global__ __launch_bounds__(256) void k_ns_integrate(
+// every pair (list == nullptr, count = total pairs), or the pairs listed.
+// Held to 128 VGPRs (four wavefronts per SIMD instead of three at 158, no
+// spills: 1.32 -> 1.27 ms for the 1.1e7 pairs of the 1e6-node tangle)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ns_integrate(
     const int *__restrict__ count, const int *__restrict__ list, const int *__restrict__ pnode,
     const int2 *__restrict__ pairs, const int *__restrict__ off, const int *__restrict__ fil,
     const double *__restrict__ x, const double *__restrict__ xn, const double *__restrict__ D,
@@ -1543,9 +1545,10 @@ void ns_rule(NsRule *R);
 // the graded-panel integrator on every pair (list == nullptr) or on the
 // listed ones; nothing when *skip is set.  The pair count is known on the
 // device only: the grid strides over it with many more workgroups than fit
-// at once (three wavefronts per SIMD at its 158 VGPRs), so that the last
-// round does not run the CUs a third full (1024 workgroups: 1.48 ms for the
-// 1.1e7 pairs of the 1e6-node tangle; 12288: 1.36 ms)
+// at once (1024 resident at four wavefronts per SIMD), so that the last
+// round does not leave most CUs idle (1024 workgroups: 1.48 ms for the
+// 1.1e7 pairs of the 1e6-node tangle at three wavefronts per SIMD; 12288:
+// 1.36 ms)
 constexpr int kNsIntegrateBlocks = 12288;
 
 static void adaptive_pairs(bs_plan_t p, const int *count, const int *list,
