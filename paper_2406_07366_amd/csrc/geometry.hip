@@ -510,10 +510,14 @@ __global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const d
 // Everything set_filaments derives per filament, in one workgroup per
 // filament: chord lengths (and the plan's copies of the nodes and of the
 // circulation), the spline solve, quadrature points, charges and segment
-// lengths, and the velocity's local term minus the long-range self
+// lengths, and (LOCAL) the velocity's local term minus the long-range self
 // correction (into vls, which the velocity sums start from).  The keys and
-// counts of the bin sorts that follow are formed here too.
-template <int ORDER>
+// counts of the bin sorts that follow are formed here too.  The local term
+// is what sets the kernel's registers (237 VGPRs with it, two wavefronts per
+// SIMD; 82 without, five), so large inputs leave it to k_local_self, one
+// thread per node (1e6 nodes: 0.40 -> 0.29 ms for both launches), and small
+// ones, bound by the host's launch rate, keep the single launch.
+template <int ORDER, bool LOCAL>
 __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restrict__ off, const double *xs,
                            double *xd, double *__restrict__ xn,
                            const double *__restrict__ shift,
@@ -564,9 +568,12 @@ __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restric
         }
         wave_add<false>(bk.cnt[2], k2, act);
     }
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        local_self_node<ORDER>(b0 + k, b0 + (k == 0 ? n - 1 : k - 1), b0 + (k + 1 == n ? 0 : k + 1),
-                               g, la, xd, xn, dtau, D, sdd, ell, qpos, qchg, vls);
+    if constexpr (LOCAL) {
+        for (int k = threadIdx.x; k < n; k += blockDim.x)
+            local_self_node<ORDER>(b0 + k, b0 + (k == 0 ? n - 1 : k - 1),
+                                   b0 + (k + 1 == n ? 0 : k + 1), g, la, xd, xn, dtau, D, sdd,
+                                   ell, qpos, qchg, vls);
+    }
 }
 
 // ------------------------------------------------------------------ launch
@@ -584,13 +591,18 @@ static LocalArgs local_args(bs_plan_t p, int mode, double sign) {
     return la;
 }
 
+// inputs from this many nodes take the local term in its own launch
+constexpr int64_t kFilamentSplitNodes = 16384;
+
 void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
     if (p->N == 0) return;
     GLRule r = gl_rule(p->Q);
     GLArgs g;
     for (int i = 0; i < kMaxQ; i++) { g.h[i] = r.h[i]; g.w[i] = r.w[i]; }
     const LocalArgs la = local_args(p, LS_VLOCAL | LS_VSELF | LS_ASSIGN, 1.0);
-    auto kern = p->order == 6 ? k_filament<6> : k_filament<4>;
+    const bool split = p->N >= kFilamentSplitNodes;
+    auto kern = p->order == 6 ? (split ? k_filament<6, false> : k_filament<6, true>)
+                              : (split ? k_filament<4, false> : k_filament<4, true>);
     hipLaunchKernelGGL(kern, dim3((unsigned)p->nfil), dim3(p->order == 6 ? 64 : 128), 0,
                        p->stream, (int)p->nfil, (const int *)p->d_off.p, xyz,
                        (double *)p->d_x.p, (double *)p->d_xn.p,
@@ -600,6 +612,7 @@ void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
                        (double *)p->d_qpos.p, (double *)p->d_qchg.p, (double *)p->d_ell.p,
                        (int *)p->d_status.p, (double *)p->spline_tmp.p, g, la,
                        (double *)p->d_vls.p, bin_keys(p));
+    if (split) launch_local_self(p, LS_VLOCAL | LS_VSELF | LS_ASSIGN, 1.0, (double *)p->d_vls.p);
 }
 
 void launch_spline_data(bs_plan_t p, const double *data, double *Dout, double *Sout) {
