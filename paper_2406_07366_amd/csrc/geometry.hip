@@ -514,9 +514,9 @@ __global__ __launch_bounds__(256) void k_local_self(int N, LocalArgs la, const d
 // correction (into vls, which the velocity sums start from).  The keys and
 // counts of the bin sorts that follow are formed here too.  The local term
 // is what sets the kernel's registers (237 VGPRs with it, two wavefronts per
-// SIMD; 82 without, five), so large inputs leave it to k_local_self, one
-// thread per node (1e6 nodes: 0.40 -> 0.29 ms for both launches), and small
-// ones, bound by the host's launch rate, keep the single launch.
+// SIMD; 82 without, five), so inputs that need more wavefronts than that
+// leave it to k_local_self, one thread per node (1e6 nodes in 1e4 filaments:
+// 0.40 -> 0.29 ms for both launches); the others keep the single launch.
 template <int ORDER, bool LOCAL>
 __global__ __launch_bounds__(128) void k_filament(int nfil, const int *__restrict__ off, const double *xs,
                            double *xd, double *__restrict__ xn,
@@ -591,8 +591,14 @@ static LocalArgs local_args(bs_plan_t p, int mode, double sign) {
     return la;
 }
 
-// inputs from this many nodes take the local term in its own launch
+// The local term takes its own launch on inputs of at least this many nodes
+// when the per-filament kernel is short of wavefronts: more filaments than
+// its registers let run at once (two wavefronts per SIMD: 1024 filaments of
+// two wavefronts), or filaments so long (over 1024 nodes on average) that
+// their workgroups loop over many nodes each.  Otherwise the extra launch
+// costs more than it saves (1e5 nodes in 1000 filaments: 44 -> 51 us).
 constexpr int64_t kFilamentSplitNodes = 16384;
+constexpr int64_t kFilamentSplitFils = 1024;
 
 void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
     if (p->N == 0) return;
@@ -600,7 +606,8 @@ void launch_filaments(bs_plan_t p, const double *xyz, const double *gamma) {
     GLArgs g;
     for (int i = 0; i < kMaxQ; i++) { g.h[i] = r.h[i]; g.w[i] = r.w[i]; }
     const LocalArgs la = local_args(p, LS_VLOCAL | LS_VSELF | LS_ASSIGN, 1.0);
-    const bool split = p->N >= kFilamentSplitNodes;
+    const bool split = p->N >= kFilamentSplitNodes &&
+                       (p->nfil > kFilamentSplitFils || p->N > kFilamentSplitFils * p->nfil);
     auto kern = p->order == 6 ? (split ? k_filament<6, false> : k_filament<6, true>)
                               : (split ? k_filament<4, false> : k_filament<4, true>);
     hipLaunchKernelGGL(kern, dim3((unsigned)p->nfil), dim3(p->order == 6 ? 64 : 128), 0,
