@@ -217,9 +217,13 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int64_t B, const int *__restr
     typedef typename Prec<F>::Op Op;
     __shared__ typename Prec<F>::W W[kWpad];
     __shared__ float b[kBpad];
+    if (Bdev) B = *Bdev;
+    // a workgroup without a tile returns before staging the weights (the
+    // launch is sized for the largest count; the device-side one is often
+    // far smaller, or zero)
+    if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= (B + 15) / 16) return;
     load_weights_lds(wg, bg, W, b);
     __syncthreads();
-    if (Bdev) B = *Bdev;
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int g = l >> 4;
     Op A1[4], A2[4][4], A3[4][4], A4[4];
